@@ -1,0 +1,275 @@
+"""CPU oracle for the mesh-intersection search and the stroboscopic map.
+
+TEST INFRASTRUCTURE ONLY: used by tests/, the smoke check and the CPU-baseline
+leg of the benchmark.  The product path never imports this package, and this
+package imports nothing from the product path.
+
+Python side of the plain C oracle in oracle.c (loaded through ctypes); see
+that file for the definitions and their sources in the paper.  exact.py holds
+the rational-arithmetic checks.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+HIT_DTYPE = np.dtype([
+    ("triA", np.int32), ("triB", np.int32), ("flags", np.uint32), ("pad", np.uint32),
+    ("u", np.float64), ("v", np.float64), ("a", np.float64), ("b", np.float64),
+    ("X", np.float64, (4,)),
+    ("thA", np.float64), ("sA", np.float64), ("thB", np.float64), ("sB", np.float64),
+    ("margin", np.float64),
+])
+assert HIT_DTYPE.itemsize == 120
+
+# pair_test status codes
+ST_AABB, ST_MOLLER, ST_DEGENERATE, ST_OUTSIDE, ST_HIT = range(5)
+
+
+class _Mesh(C.Structure):
+    _fields_ = [("V", C.c_void_p), ("n_theta_v", C.c_int32), ("n_s_v", C.c_int32),
+                ("periodic", C.c_int32), ("pad", C.c_int32),
+                ("theta", C.c_void_p), ("s", C.c_void_p)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("n_cand", C.c_int64), ("cand", C.POINTER(C.c_int64)),
+                ("n_hits", C.c_int64), ("hits", C.c_void_p),
+                ("counts", C.c_int64 * 8),
+                ("n_entries", C.c_int64), ("n_slots", C.c_int64), ("n_boxes", C.c_int64)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.ensure_built()
+        L = C.CDLL(path)
+        P, I64, I32, D = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+        L.orc_n_tris.argtypes = [C.POINTER(_Mesh)]; L.orc_n_tris.restype = I64
+        L.orc_tri_verts.argtypes = [C.POINTER(_Mesh), I64, P]; L.orc_tri_verts.restype = None
+        L.orc_tri_aabb.argtypes = [C.POINTER(_Mesh), I64, P, P]; L.orc_tri_aabb.restype = None
+        L.orc_pair.argtypes = [C.POINTER(_Mesh), I64, C.POINTER(_Mesh), I64, P]; L.orc_pair.restype = C.c_int
+        L.orc_solve4.argtypes = [P, P, P]; L.orc_solve4.restype = C.c_int
+        L.orc_moller_reject.argtypes = [P, P]; L.orc_moller_reject.restype = C.c_int
+        L.orc_bruteforce.argtypes = [C.POINTER(_Mesh), C.POINTER(_Mesh), C.c_int, C.POINTER(_Result), C.c_int]
+        L.orc_bruteforce.restype = C.c_int
+        L.orc_grid_search.argtypes = [C.POINTER(_Mesh), C.POINTER(_Mesh), P, D, P, C.POINTER(_Result), C.c_int]
+        L.orc_grid_search.restype = C.c_int
+        L.orc_grid_entries.argtypes = [C.POINTER(_Mesh), P, D, P]; L.orc_grid_entries.restype = I64
+        L.orc_result_free.argtypes = [C.POINTER(_Result)]; L.orc_result_free.restype = None
+        L.orc_rk8_tableau.argtypes = [P, P, P]; L.orc_rk8_tableau.restype = None
+        L.orc_rk8_map.argtypes = [P, P, I64, D, D, I32, I32, C.c_int]; L.orc_rk8_map.restype = C.c_int
+        L.orc_rk8_tangent.argtypes = [P, P, I32, I32, P, P, I64, D, D, I32, I32, C.c_int]
+        L.orc_rk8_tangent.restype = C.c_int
+        L.orc_jacobi.argtypes = [P, D]; L.orc_jacobi.restype = D
+        L.orc_energy_balance.argtypes = [P, D, D, I32, I32, P]; L.orc_energy_balance.restype = C.c_int
+        L.orc_mismatch.argtypes = [P, I64, P, P, D, D, I32, I32, I32, P, P, P, P, C.c_int]
+        L.orc_mismatch.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class OMesh:
+    """Holds numpy buffers alive for the C view of a mesh."""
+
+    def __init__(self, mesh):
+        self.V = np.ascontiguousarray(mesh.verts, dtype=np.float64)
+        self.theta = np.ascontiguousarray(mesh.theta, dtype=np.float64)
+        self.s = np.ascontiguousarray(mesh.s, dtype=np.float64)
+        assert self.V.shape == (len(self.s), len(self.theta), 4)
+        self.c = _Mesh(self.V.ctypes.data, len(self.theta), len(self.s), int(bool(mesh.periodic)), 0,
+                       self.theta.ctypes.data, self.s.ctypes.data)
+
+    @property
+    def ref(self):
+        return C.byref(self.c)
+
+
+def n_tris(mesh) -> int:
+    return int(lib().orc_n_tris(OMesh(mesh).ref))
+
+
+def tri_verts(mesh, t: int) -> np.ndarray:
+    om = OMesh(mesh)
+    out = np.empty((3, 4))
+    lib().orc_tri_verts(om.ref, int(t), _ptr(out))
+    return out
+
+
+def tri_aabb(mesh, t: int):
+    om = OMesh(mesh)
+    lo = np.empty(4); hi = np.empty(4)
+    lib().orc_tri_aabb(om.ref, int(t), _ptr(lo), _ptr(hi))
+    return lo, hi
+
+
+def pair(meshA, ta: int, meshB, tb: int):
+    """Status code of the predicate on one pair, and the hit record if any."""
+    a, b = OMesh(meshA), OMesh(meshB)
+    h = np.zeros(1, dtype=HIT_DTYPE)
+    st = lib().orc_pair(a.ref, int(ta), b.ref, int(tb), _ptr(h))
+    return int(st), (h[0] if st == ST_HIT else None)
+
+
+def solve4(p: np.ndarray, q: np.ndarray):
+    p = np.ascontiguousarray(p, dtype=np.float64); q = np.ascontiguousarray(q, dtype=np.float64)
+    z = np.zeros(4)
+    ok = lib().orc_solve4(_ptr(p), _ptr(q), _ptr(z))
+    return bool(ok), z
+
+
+def moller_reject(p: np.ndarray, q: np.ndarray) -> bool:
+    p = np.ascontiguousarray(p, dtype=np.float64); q = np.ascontiguousarray(q, dtype=np.float64)
+    return bool(lib().orc_moller_reject(_ptr(p), _ptr(q)))
+
+
+class SearchResult:
+    def __init__(self, res: _Result):
+        self.cand = np.ctypeslib.as_array(res.cand, shape=(res.n_cand,)).copy() if res.n_cand else np.zeros(0, np.int64)
+        if res.n_hits:
+            buf = (C.c_char * (res.n_hits * HIT_DTYPE.itemsize)).from_address(res.hits)
+            self.hits = np.frombuffer(bytes(buf), dtype=HIT_DTYPE).copy()
+        else:
+            self.hits = np.zeros(0, dtype=HIT_DTYPE)
+        c = list(res.counts)
+        self.counts = dict(examined=c[0], aabb_pass=c[1], moller_reject=c[2], degenerate=c[3],
+                           outside=c[4], hits=c[5], nonfinite_A=c[6], nonfinite_B=c[7])
+        self.n_entries = int(res.n_entries)
+        self.n_slots = int(res.n_slots)
+        self.n_boxes = int(res.n_boxes)
+
+    @property
+    def hit_pairs(self) -> np.ndarray:
+        return (self.hits["triA"].astype(np.int64) << 32) | self.hits["triB"].astype(np.int64)
+
+
+def bruteforce(meshA, meshB, forced: bool = False, nthreads: int = 0) -> SearchResult:
+    """All pairs: C = AABB-overlapping pairs, H = pairs satisfying P (sorted)."""
+    a, b = OMesh(meshA), OMesh(meshB)
+    res = _Result()
+    rc = lib().orc_bruteforce(a.ref, b.ref, int(forced), C.byref(res), int(nthreads))
+    if rc != 0:
+        raise RuntimeError(f"orc_bruteforce failed ({rc})")
+    out = SearchResult(res)
+    lib().orc_result_free(C.byref(res))
+    return out
+
+
+def grid_search(meshA, meshB, w_lo, inv_edge: float, n_cells, nthreads: int = 0) -> SearchResult:
+    """Uniform-grid search with per-box lists (paper Sec. 6.2.1), then the
+    AABB, Moller and narrow-phase tests; C and H are sorted and distinct."""
+    a, b = OMesh(meshA), OMesh(meshB)
+    wl = np.ascontiguousarray(w_lo, dtype=np.float64)
+    nc = np.ascontiguousarray(n_cells, dtype=np.int64)
+    res = _Result()
+    rc = lib().orc_grid_search(a.ref, b.ref, _ptr(wl), float(inv_edge), _ptr(nc), C.byref(res), int(nthreads))
+    if rc != 0:
+        raise RuntimeError(f"orc_grid_search failed ({rc})")
+    out = SearchResult(res)
+    lib().orc_result_free(C.byref(res))
+    return out
+
+
+def grid_entries(mesh, w_lo, inv_edge: float, n_cells) -> int:
+    om = OMesh(mesh)
+    wl = np.ascontiguousarray(w_lo, dtype=np.float64)
+    nc = np.ascontiguousarray(n_cells, dtype=np.int64)
+    return int(lib().orc_grid_entries(om.ref, _ptr(wl), float(inv_edge), _ptr(nc)))
+
+
+def rk8_tableau():
+    a = np.zeros((11, 11)); b = np.zeros(11); c = np.zeros(11)
+    lib().orc_rk8_tableau(_ptr(a), _ptr(b), _ptr(c))
+    return a, b, c
+
+
+def rk8_map(states: np.ndarray, mu: float, e: float, steps_per_period: int, n_periods: int,
+            nthreads: int = 0) -> np.ndarray:
+    x = np.ascontiguousarray(states, dtype=np.float64).reshape(-1, 4)
+    out = np.empty_like(x)
+    rc = lib().orc_rk8_map(_ptr(x), _ptr(out), x.shape[0], float(mu), float(e), int(steps_per_period),
+                           int(n_periods), int(nthreads))
+    if rc != 0:
+        raise RuntimeError("orc_rk8_map failed")
+    return out.reshape(np.shape(states))
+
+
+def rk8_tangent(states: np.ndarray, dirs: np.ndarray, e_col: int, mu: float, e: float,
+                steps_per_period: int, n_periods: int, nthreads: int = 0):
+    """states (n,4), dirs (n, nd, 4): returns (F^n(states), DF^n dirs [+ dF/de in column e_col])."""
+    x = np.ascontiguousarray(states, dtype=np.float64).reshape(-1, 4)
+    d = np.ascontiguousarray(dirs, dtype=np.float64).reshape(x.shape[0], -1, 4)
+    nd = d.shape[1]
+    out = np.empty_like(x); dout = np.empty_like(d)
+    rc = lib().orc_rk8_tangent(_ptr(x), _ptr(d), nd, int(e_col), _ptr(out), _ptr(dout), x.shape[0],
+                               float(mu), float(e), int(steps_per_period), int(n_periods), int(nthreads))
+    if rc != 0:
+        raise RuntimeError("orc_rk8_tangent failed")
+    return out, dout
+
+
+def jacobi(state, mu: float) -> float:
+    y = np.ascontiguousarray(state, dtype=np.float64)
+    return float(lib().orc_jacobi(_ptr(y), float(mu)))
+
+
+def energy_balance(state, mu: float, e: float, steps_per_period: int, n_periods: int) -> float:
+    y = np.ascontiguousarray(state, dtype=np.float64)
+    r = np.zeros(1)
+    lib().orc_energy_balance(_ptr(y), float(mu), float(e), int(steps_per_period), int(n_periods), _ptr(r))
+    return float(r[0])
+
+
+def mismatch(params: np.ndarray, patch_u, patch_s, mu: float, e: float, steps_per_period: int,
+             n_u: int, n_s: int, nthreads: int = 0):
+    """f, r, J, grad of f = F^{n_u}(x_u(th1,s1)) - F^{n_s}(x_s(th2,s2)) (n_s < 0)."""
+    p = np.ascontiguousarray(params, dtype=np.float64).reshape(-1, 4)
+    K = p.shape[0]
+    pu = np.ascontiguousarray(np.concatenate([patch_u.base, patch_u.d1, patch_u.d2]), dtype=np.float64)
+    ps = np.ascontiguousarray(np.concatenate([patch_s.base, patch_s.d1, patch_s.d2]), dtype=np.float64)
+    f = np.empty((K, 4)); r = np.empty(K); J = np.empty((K, 4, 5)); g = np.empty((K, 5))
+    rc = lib().orc_mismatch(_ptr(p), K, _ptr(pu), _ptr(ps), float(mu), float(e), int(steps_per_period),
+                            int(n_u), int(n_s), _ptr(f), _ptr(r), _ptr(J), _ptr(g), int(nthreads))
+    if rc != 0:
+        raise RuntimeError("orc_mismatch failed")
+    return f, r, J, g
+
+
+def default_grid(meshes, kappa: float):
+    """World = box of all finite vertices; edge = kappa x mean over both meshes
+    of the triangles' longest 4D edge; cells per axis = max(1, ceil(span x
+    inv_edge)).  Returns (w_lo, w_hi, inv_edge, n_cells).  Test helper."""
+    import math
+    lo = np.full(4, np.inf); hi = np.full(4, -np.inf)
+    tot, cnt = 0.0, 0
+    for m in meshes:
+        v = m.verts
+        fin = np.all(np.isfinite(v.reshape(-1, 4)), axis=1)
+        if fin.any():
+            vv = v.reshape(-1, 4)[fin]
+            lo = np.minimum(lo, vv.min(axis=0)); hi = np.maximum(hi, vv.max(axis=0))
+        if m.n_tris == 0:
+            continue
+        w = np.concatenate([v, v[:, :1]], axis=1) if m.periodic else v
+        a = w[:-1, :-1]; b = w[:-1, 1:]; c = w[1:, :-1]; d = w[1:, 1:]   # (i,k) (i+1,k) (i,k+1) (i+1,k+1)
+        nrm = lambda x: np.sqrt(np.sum(x * x, axis=-1))
+        e_diag = nrm(b - c)
+        t1 = np.maximum(np.maximum(nrm(b - a), nrm(c - a)), e_diag)
+        t2 = np.maximum(np.maximum(nrm(c - d), nrm(b - d)), e_diag)
+        allt = np.concatenate([t1.ravel(), t2.ravel()])
+        allt = allt[np.isfinite(allt)]
+        tot += float(allt.sum()); cnt += allt.size
+    edge = kappa * (tot / max(cnt, 1))
+    inv = 1.0 / edge
+    n = np.array([max(1, int(math.ceil((hi[d] - lo[d]) * inv))) for d in range(4)], dtype=np.int64)
+    return lo, hi, inv, n

@@ -1,0 +1,225 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the bench.
+
+This module holds no arithmetic of the search or of the map: it only draws
+random numbers and evaluates the closed-form test surfaces that stand in for
+the manifold meshes of the paper (whose Jupiter-Europa manifolds are not
+available).  Both the CPU oracle and the HIP path consume the exact bytes
+produced here.
+
+Mesh convention (paper Sec. 6.1): a mesh is a grid of vertices W(theta_i, s_k)
+stored as an (n_s_v, n_theta_v, 4) float64 array (theta index fastest, the
+four coordinates (x, y, p_x, p_y) contiguous), with the sample values
+theta[n_theta_v] and s[n_s_v].  A periodic mesh has n_theta_v = N samples
+theta_i = 2 pi i / N; quad (i, k) joins theta index i and (i+1) mod N.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+TWO_PI = 2.0 * math.pi
+
+
+@dataclasses.dataclass
+class Mesh:
+    verts: np.ndarray          # (n_s_v, n_theta_v, 4) float64, C-contiguous
+    theta: np.ndarray          # (n_theta_v,) float64
+    s: np.ndarray              # (n_s_v,) float64
+    periodic: bool
+
+    @property
+    def n_theta_v(self) -> int:
+        return int(self.verts.shape[1])
+
+    @property
+    def n_s_v(self) -> int:
+        return int(self.verts.shape[0])
+
+    @property
+    def n_quads_theta(self) -> int:
+        return self.n_theta_v if self.periodic else max(self.n_theta_v - 1, 0)
+
+    @property
+    def n_tris(self) -> int:
+        return 2 * self.n_quads_theta * max(self.n_s_v - 1, 0)
+
+
+# ---------------------------------------------------------------------------
+# Closed-form torus-like surfaces (plain search workloads)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class SurfaceCoeffs:
+    phi: float
+    psi: float
+    alpha: np.ndarray   # (4, 5) noise amplitudes in [-1, 1]
+    beta: np.ndarray    # (4, 5) noise phases in [0, 2 pi)
+    gamma: np.ndarray   # (4, 5) noise s-frequencies in [-pi, pi]
+    noise_amp: float = 1e-2
+
+
+def surface_coeffs(seed: int, noise_amp: float = 1e-2) -> SurfaceCoeffs:
+    """Draw (phi, psi, alpha, beta, gamma) in that order from default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    phi = float(rng.uniform(0.0, TWO_PI))
+    psi = float(rng.uniform(0.0, TWO_PI))
+    alpha = rng.uniform(-1.0, 1.0, size=(4, 5))
+    beta = rng.uniform(0.0, TWO_PI, size=(4, 5))
+    gamma = rng.uniform(-math.pi, math.pi, size=(4, 5))
+    return SurfaceCoeffs(phi, psi, alpha, beta, gamma, noise_amp)
+
+
+def eval_surface(c: SurfaceCoeffs, th: np.ndarray, s: np.ndarray) -> np.ndarray:
+    """K(theta, s) = ((1+0.3 s) cos th, (1+0.3 s) sin th, s cos(2 th + phi),
+    s sin(th + psi)) + sum_m (amp/5) alpha_{c,m} cos(m th + gamma_{c,m} s + beta_{c,m}).
+
+    th and s broadcast against each other; returns (..., 4)."""
+    th = np.asarray(th, dtype=np.float64)
+    s = np.asarray(s, dtype=np.float64)
+    th, s = np.broadcast_arrays(th, s)
+    r = 1.0 + 0.3 * s
+    out = np.empty(th.shape + (4,), dtype=np.float64)
+    out[..., 0] = r * np.cos(th)
+    out[..., 1] = r * np.sin(th)
+    out[..., 2] = s * np.cos(2.0 * th + c.phi)
+    out[..., 3] = s * np.sin(th + c.psi)
+    w = c.noise_amp / 5.0
+    for comp in range(4):
+        acc = np.zeros(th.shape, dtype=np.float64)
+        for m in range(5):
+            acc += c.alpha[comp, m] * np.cos((m + 1) * th + c.gamma[comp, m] * s + c.beta[comp, m])
+        out[..., comp] += w * acc
+    return out
+
+
+def torus_mesh(n_quads_theta: int, n_quads_s: int, coeffs: SurfaceCoeffs) -> Mesh:
+    """Periodic N x M-quad mesh over theta in [0, 2 pi) x s in [0, 1]:
+    theta_i = 2 pi i / N (N samples), s_k = k / M (M + 1 samples)."""
+    N, M = int(n_quads_theta), int(n_quads_s)
+    theta = TWO_PI * np.arange(N, dtype=np.float64) / N
+    s = np.arange(M + 1, dtype=np.float64) / M
+    verts = eval_surface(coeffs, theta[None, :], s[:, None])
+    return Mesh(np.ascontiguousarray(verts), theta, s, True)
+
+
+def plain_pair(n_quads_theta: int, n_quads_s: int, seed: int = 0,
+               noise_amp: float = 1e-2) -> tuple[Mesh, Mesh]:
+    """The plain-search workload: surface A from seed, surface B from seed+1."""
+    a = torus_mesh(n_quads_theta, n_quads_s, surface_coeffs(seed, noise_amp))
+    b = torus_mesh(n_quads_theta, n_quads_s, surface_coeffs(seed + 1, noise_amp))
+    return a, b
+
+
+def crop(mesh: Mesh, i0: int, ni: int, k0: int, nk: int) -> Mesh:
+    """Non-periodic crop of ni x nk quads starting at quad (i0, k0)."""
+    idx = (np.arange(i0, i0 + ni + 1) % mesh.n_theta_v)
+    v = mesh.verts[k0:k0 + nk + 1][:, idx]
+    th = mesh.theta[idx].copy()
+    # keep theta increasing across the periodic seam
+    for j in range(1, len(th)):
+        while th[j] <= th[j - 1]:
+            th[j] += TWO_PI
+    return Mesh(np.ascontiguousarray(v), th, mesh.s[k0:k0 + nk + 1].copy(), False)
+
+
+# ---------------------------------------------------------------------------
+# Batched continuation family
+# ---------------------------------------------------------------------------
+
+def family_sizes(n_pairs: int, seed: int) -> list[tuple[int, int, int, int]]:
+    """Per pair (N_A, M_A, N_B, M_B): N ~ logU[32, 1024], M ~ logU[16, 128],
+    independent per surface, rounded to the nearest integer."""
+    rng = np.random.default_rng(seed + 7919)
+    out = []
+    for _ in range(n_pairs):
+        row = []
+        for _surf in range(2):
+            n = int(round(math.exp(rng.uniform(math.log(32.0), math.log(1024.0)))))
+            m = int(round(math.exp(rng.uniform(math.log(16.0), math.log(128.0)))))
+            row += [n, m]
+        out.append(tuple(row))
+    return out
+
+
+def family(n_pairs: int = 256, seed: int = 0, drift: float = 1e-3,
+           sizes: list | None = None) -> list[tuple[Mesh, Mesh]]:
+    """A torus-family-like sequence of mesh pairs: member m uses
+    phi_m = phi_0 + drift m and psi_m = psi_0 + drift m, noise fixed."""
+    ca0 = surface_coeffs(seed)
+    cb0 = surface_coeffs(seed + 1)
+    if sizes is None:
+        sizes = family_sizes(n_pairs, seed)
+    pairs = []
+    for m, (na, ma, nb, mb) in enumerate(sizes):
+        ca = dataclasses.replace(ca0, phi=ca0.phi + drift * m, psi=ca0.psi + drift * m)
+        cb = dataclasses.replace(cb0, phi=cb0.phi + drift * m, psi=cb0.psi + drift * m)
+        pairs.append((torus_mesh(na, ma, ca), torus_mesh(nb, mb, cb)))
+    return pairs
+
+
+# ---------------------------------------------------------------------------
+# Affine and graph-surface plants (closed-form intersections)
+# ---------------------------------------------------------------------------
+
+def affine_mesh(p0, d_theta, d_s, theta, s) -> Mesh:
+    """Non-periodic mesh of the affine surface W(th, s) = p0 + th d_theta + s d_s
+    sampled at the given (increasing) theta and s values."""
+    theta = np.asarray(theta, dtype=np.float64)
+    s = np.asarray(s, dtype=np.float64)
+    p0 = np.asarray(p0, dtype=np.float64)
+    d1 = np.asarray(d_theta, dtype=np.float64)
+    d2 = np.asarray(d_s, dtype=np.float64)
+    v = p0[None, None, :] + theta[None, :, None] * d1[None, None, :] + s[:, None, None] * d2[None, None, :]
+    return Mesh(np.ascontiguousarray(v), theta.copy(), s.copy(), False)
+
+
+# ---------------------------------------------------------------------------
+# Propagated-mesh patches (stroboscopic map workloads)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Patch:
+    base: np.ndarray   # (4,)
+    d1: np.ndarray     # (4,) unit, theta-like direction
+    d2: np.ndarray     # (4,) unit, s-like direction, orthogonal to d1
+
+
+def patch_dirs(seed: int, base) -> Patch:
+    """Two seeded Gaussian directions in R^4, Gram-Schmidt orthonormalised."""
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal((2, 4))
+    d1 = g[0] / np.linalg.norm(g[0])
+    d2 = g[1] - np.dot(g[1], d1) * d1
+    d2 = d2 / np.linalg.norm(d2)
+    return Patch(np.asarray(base, dtype=np.float64), d1, d2)
+
+
+UNSTABLE_BASE = (0.92, 0.0, 0.0, 0.05)
+STABLE_BASE = (1.08, 0.0, 0.0, -0.05)
+
+
+def patch_vertices(p: Patch, n_theta_v: int, n_s_v: int, half_width: float = 1e-3) -> Mesh:
+    """Grid base + alpha_i d1 + beta_j d2, alpha in linspace(-w, w, n_theta_v),
+    beta in linspace(-w, w, n_s_v); non-periodic; (theta, s) = (alpha, beta)."""
+    al = np.linspace(-half_width, half_width, n_theta_v)
+    be = np.linspace(-half_width, half_width, n_s_v)
+    v = p.base[None, None, :] + al[None, :, None] * p.d1[None, None, :] + be[:, None, None] * p.d2[None, None, :]
+    return Mesh(np.ascontiguousarray(v), al, be, False)
+
+
+def propagated_patches(n_quads_theta: int = 2048, n_quads_s: int = 256, seed: int = 0):
+    """Unstable and stable seed patches before propagation: (Mesh, Patch) x 2."""
+    pu = patch_dirs(seed, UNSTABLE_BASE)
+    ps = patch_dirs(seed + 1, STABLE_BASE)
+    mu = patch_vertices(pu, n_quads_theta + 1, n_quads_s + 1)
+    ms = patch_vertices(ps, n_quads_theta + 1, n_quads_s + 1)
+    return (mu, pu), (ms, ps)
+
+
+def random_states(n: int, seed: int, center=UNSTABLE_BASE, spread: float = 1e-2) -> np.ndarray:
+    """n seeded phase-space points around `center` (uniform box of half-width spread)."""
+    rng = np.random.default_rng(seed)
+    c = np.asarray(center, dtype=np.float64)
+    return np.ascontiguousarray(c[None, :] + rng.uniform(-spread, spread, size=(n, 4)))
