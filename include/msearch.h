@@ -1,0 +1,230 @@
+/*
+ * msearch.h -- C ABI of the MI355X (gfx950) manifold-mesh intersection
+ * search and stroboscopic-map library (libmsearch.so).
+ *
+ * Method: Kumar, Anderson, de la Llave, "Rapid GPU-assisted search and
+ * parameterization-based refinement and continuation of connections between
+ * tori in periodically perturbed planar circular restricted 3-body problems",
+ * arXiv 2109.14814.  Section numbers below refer to that paper.
+ *
+ * Conventions for every entry point
+ *   - Return value: MS_OK (0) or a negative MS_E_* code.  After an error,
+ *     last_error() returns a thread-local description.  No C++ exception
+ *     crosses this boundary.
+ *   - Pointers named *_dev are device (HBM) pointers owned by the caller; the
+ *     library borrows them for the duration of the call (and, for vertices
+ *     passed to mesh_build, for the lifetime of the mesh handle).  Pointers
+ *     named *_host are host pointers.
+ *   - `stream` is a hipStream_t (passed as void* so that this header needs no
+ *     HIP include); NULL means the default stream.  All device work is queued
+ *     on that stream.  Unless stated otherwise a call returns once its work is
+ *     queued.
+ *   - FP64 throughout.  Floating-point expressions in the kernels are built
+ *     with contraction off, so each operation rounds once as written.
+ */
+#ifndef MSEARCH_H
+#define MSEARCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+enum {
+    MS_OK = 0,
+    MS_E_ARG = -1,        /* invalid argument (NULL, negative size, bad flag) */
+    MS_E_CAPACITY = -2,   /* an output buffer is too small; *needed says how large */
+    MS_E_HIP = -3,        /* a HIP runtime call failed (text in last_error) */
+    MS_E_NONFINITE = -4,  /* non-finite vertex with MS_SEARCH_STRICT */
+    MS_E_KEYBITS = -5,    /* grid too fine: cell index does not fit the sort key */
+    MS_E_WORKSPACE = -6   /* workspace too small for this search; query again */
+};
+
+/* Thread-local text of the last error (never NULL). */
+const char *last_error(void);
+
+/* ------------------------------------------------------------------ mesh */
+
+/* Opaque mesh handle: triangle table and per-triangle 4D boxes in HBM. */
+typedef struct ms_mesh ms_mesh;
+
+/* Vertex layouts accepted by mesh_build. */
+enum {
+    MS_LAYOUT_AOS = 0,    /* (n_s_v * n_theta_v) x 4 doubles, theta index fastest,
+                             (x, y, p_x, p_y) of one vertex contiguous (32 B).
+                             Borrowed: must outlive the handle. */
+    MS_LAYOUT_SOA = 1     /* four planes x[n_s_v][n_theta_v], y, p_x, p_y, back to
+                             back (the four N x M arrays of Sec. 6.1, stored with
+                             theta fastest).  Copied into an owned AoS buffer. */
+};
+
+/*
+ * mesh_build -- triangulate a vertex grid W(theta_i, s_k) (Sec. 6.1) and
+ * compute every triangle's 4D axis-aligned bounding box (Sec. 6.2.2).
+ *
+ * Quad (i, k) joins W(i,k), W(i+1,k), W(i,k+1), W(i+1,k+1); when periodic
+ * != 0, i+1 is taken mod n_theta_v (theta_N = theta_0 + 2 pi) so there are
+ * n_theta_v quads per s-row, otherwise n_theta_v - 1.  Quad q = i + k*Nq is
+ * split along W(i+1,k)-W(i,k+1) into triangles 2q (T1) and 2q+1 (T2), with
+ * the vertex order of the narrow phase (Sec. 6.2.4):
+ *   T1: p1 = W(i+1,k), p2 = W(i,k),     p3 = W(i,k+1)
+ *   T2: p1 = W(i,k+1), p2 = W(i+1,k+1), p3 = W(i+1,k)
+ * theta_host[n_theta_v] and s_host[n_s_v] are the sample values used for the
+ * (theta, s) estimates of hits; they are copied.  A triangle with a
+ * non-finite coordinate is flagged and takes no part in any search.
+ * Allocates the handle's device buffers (64 B per triangle); synchronises
+ * `stream` before returning.  A grid with fewer than 2 vertices along s (or
+ * along a non-periodic theta) has no triangles and is valid.
+ */
+int mesh_build(const double *verts_dev, int32_t n_theta_v, int32_t n_s_v, int32_t periodic,
+               int32_t layout, const double *theta_host, const double *s_host, void *stream,
+               ms_mesh **out);
+
+/* Release a handle and its device buffers (NULL is accepted). */
+int mesh_free(ms_mesh *mesh);
+
+typedef struct {
+    int64_t n_tris;        /* 2 * Nq * (n_s_v - 1) */
+    int64_t n_nonfinite;   /* triangles excluded for non-finite coordinates */
+    double lo[4], hi[4];   /* bounds of all finite vertices (+inf/-inf if none) */
+    double mean_diam;      /* mean over finite triangles of the longest 4D edge */
+} ms_mesh_info_t;
+
+int mesh_info(const ms_mesh *mesh, ms_mesh_info_t *out);
+
+/* --------------------------------------------------------------- search */
+
+/* Search flags. */
+enum {
+    MS_SEARCH_CANDIDATES = 1,   /* also write the candidate set C to cand_dev */
+    MS_SEARCH_STRICT = 2        /* fail with MS_E_NONFINITE if a mesh has non-finite triangles */
+};
+
+/*
+ * Uniform grid of Sec. 6.2.1 in the 0-based form: cell of coordinate x on
+ * axis d is clamp(floor((x - world_lo[d]) * inv_edge), 0, n_cells[d] - 1),
+ * evaluated in FP64.  The grid only decides which pairs are examined; the
+ * hit set does not depend on it (every box-overlapping pair shares the cell
+ * of the componentwise max of the two boxes' lower corners and is examined
+ * there exactly once).
+ */
+typedef struct {
+    double world_lo[4];
+    double inv_edge;        /* 1 / cell edge, > 0 and finite */
+    int64_t n_cells[4];     /* cells per axis, >= 1 */
+    int32_t flags;          /* MS_SEARCH_* */
+    int32_t pad;
+} search_params_t;
+
+/* World = box of both meshes' finite vertices, edge = kappa * mean triangle
+ * diameter of both meshes, n_cells[d] = max(1, ceil(span_d * inv_edge)). */
+int search_default_params(const ms_mesh *A, const ms_mesh *B, double kappa, search_params_t *out);
+
+/*
+ * Hit record (120 B).  (u, v) are the coordinates of the intersection point
+ * on A's triangle and (a, b) on B's, in the form of the narrow-phase system
+ * p2 + (p1 - p2) u + (p3 - p2) v = q2 + (q1 - q2) a + (q3 - q2) b
+ * (Sec. 6.2.4; the paper writes (a, b, c, d)).  X is the point
+ * (p2 + u (p1 - p2)) + v (p3 - p2); (thA, sA) and (thB, sB) the parameter
+ * estimates of Sec. 6.2.4; margin = min(u, v, a, b, 1-(u+v), 1-(a+b)).
+ */
+typedef struct {
+    int32_t triA, triB;
+    uint32_t flags, pad;
+    double u, v, a, b;
+    double X[4];
+    double thA, sA, thB, sB;
+    double margin;
+} hit_t;
+
+/* Counters written by a search (device memory, int64 each). */
+typedef struct {
+    int64_t n_entries;       /* (cell, triangle) entries after the both-sides cell filter */
+    int64_t n_entries_all;   /* entries before the filter */
+    int64_t n_cells;         /* distinct cells holding both meshes */
+    int64_t n_slots;         /* sum over those cells of nA * nB */
+    int64_t n_cand;          /* |C|: distinct box-overlapping pairs */
+    int64_t n_moller;        /* candidates rejected by the Moller test */
+    int64_t n_degenerate;    /* candidates with a singular 4x4 system */
+    int64_t n_outside;       /* solved, intersection outside a triangle */
+    int64_t n_hits;          /* |H| */
+    int64_t n_nonfinite;     /* triangles of A and B excluded */
+    int64_t overflow;        /* bit 0: entries > capacity, bit 1: cand, bit 2: hits */
+    int64_t reserved[5];
+} search_stats_t;
+
+/*
+ * search_workspace_size -- bytes of device workspace that search_intersections
+ * needs for this pair and grid, with room for cand_cap candidates and
+ * hits_cap hits.  Runs an entry-count kernel on `stream` and synchronises it.
+ * Returns MS_E_KEYBITS when the sort key [cell | side | triangle] needs more
+ * than 63 bits (prod(n_cells) too large for the triangle counts).
+ */
+int search_workspace_size(const ms_mesh *A, const ms_mesh *B, const search_params_t *params,
+                          int64_t cand_cap, int64_t hits_cap, void *stream, size_t *bytes);
+
+/*
+ * search_intersections -- H = { (A_i, B_j) : triangles intersect } (Sec. 6.2),
+ * by the GPU pipeline: entry keys per covered cell, LDS radix sort, per-cell
+ * pair enumeration with the box test (Sec. 6.2.2), Moller quick test
+ * (Sec. 6.2.3) and the 4x4 narrow phase (Sec. 6.2.4), hits sorted by
+ * (triA, triB).
+ *   ws_dev/ws_bytes: workspace from search_workspace_size (not shared with a
+ *     concurrent call); cand_cap and hits_cap must not exceed the values the
+ *     workspace was sized for.
+ *   hits_dev/hits_cap: output records, sorted by (triA, triB).
+ *   stats_dev: one search_stats_t in device memory, written by the search.
+ *   cand_dev/cand_cap: with MS_SEARCH_CANDIDATES, receives C as packed
+ *     (triA << 32 | triB), unordered; else ignored (may be NULL).
+ *   needed (host, may be NULL): on MS_E_CAPACITY / MS_E_WORKSPACE, needed[0] =
+ *     hits, needed[1] = candidates, needed[2] = workspace bytes required.
+ * Synchronises `stream` at the end to check capacities and returns
+ * MS_E_CAPACITY or MS_E_WORKSPACE when a buffer overflowed (outputs are then
+ * incomplete but every write stayed in bounds).
+ */
+int search_intersections(const ms_mesh *A, const ms_mesh *B, const search_params_t *params,
+                         void *ws_dev, size_t ws_bytes, hit_t *hits_dev, int64_t hits_cap,
+                         search_stats_t *stats_dev, int64_t *cand_dev, int64_t cand_cap,
+                         int64_t *needed, void *stream);
+
+/*
+ * narrow_allpairs -- the full pair test (Moller, 4x4 solve, inclusion) on every
+ * pair of A x B with no grid and no early exit (the box test is evaluated and
+ * folded into the decision): the "tri-pair tests/s" workload.  Hits are
+ * written unordered to hits_dev; *n_hits_dev (device int64) receives |H|;
+ * stats_dev (optional) receives the per-stage counters.  Asynchronous.
+ */
+int narrow_allpairs(const ms_mesh *A, const ms_mesh *B, hit_t *hits_dev, int64_t hits_cap,
+                    int64_t *n_hits_dev, search_stats_t *stats_dev, void *stream);
+
+/* ------------------------------------------------------------------ map */
+
+/* Planar elliptic restricted three-body problem in pulsating rotating
+ * coordinates with the true anomaly f as independent variable (the model
+ * family of Sec. 3.2-3.3):
+ *   x'' - 2 y' = w(f) dOmega/dx,  y'' + 2 x' = w(f) dOmega/dy,
+ *   w = 1 / (1 + e cos f), Omega = (x^2+y^2)/2 + (1-mu)/r1 + mu/r2.
+ * The stroboscopic map F advances f by 2 pi (Sec. 4.1). */
+typedef struct {
+    double mu, e;
+    int32_t steps_per_period;   /* fixed RK8 steps per 2 pi of f */
+    int32_t n_periods;          /* F^n_periods; negative = backwards */
+} map_params_t;
+
+/*
+ * propagate_vertices -- out = F^n(in) for n_vertices states (x, y, x', y'),
+ * AoS 4 doubles each, by the 11-stage order-8 explicit Runge-Kutta method of
+ * Cooper & Verner (1972) with fixed steps (the globalization maps
+ * F^{+-k} of Sec. 4.3).  in_dev may equal out_dev.  Asynchronous.
+ */
+int propagate_vertices(const double *in_dev, double *out_dev, int64_t n_vertices,
+                       const map_params_t *params, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSEARCH_H */

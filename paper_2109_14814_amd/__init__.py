@@ -1,0 +1,254 @@
+"""Python binding of libmsearch.so (the MI355X mesh-intersection search and
+stroboscopic-map library; C ABI in include/msearch.h).
+
+Argument marshalling only: every step of the search and of the map runs in
+the library's HIP kernels.  PyTorch provides device memory and the current
+HIP stream.  Importing this package does not need a GPU; calling into the
+library does, and fails loudly when the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmsearch.so")
+
+MS_OK, MS_E_ARG, MS_E_CAPACITY, MS_E_HIP, MS_E_NONFINITE, MS_E_KEYBITS, MS_E_WORKSPACE = 0, -1, -2, -3, -4, -5, -6
+MS_LAYOUT_AOS, MS_LAYOUT_SOA = 0, 1
+MS_SEARCH_CANDIDATES, MS_SEARCH_STRICT = 1, 2
+
+# Exported entry points (the C ABI of include/msearch.h).
+EXPORTS = ("last_error", "mesh_build", "mesh_free", "mesh_info", "search_default_params",
+           "search_workspace_size", "search_intersections", "narrow_allpairs", "propagate_vertices")
+
+HIT_DTYPE = np.dtype([
+    ("triA", np.int32), ("triB", np.int32), ("flags", np.uint32), ("pad", np.uint32),
+    ("u", np.float64), ("v", np.float64), ("a", np.float64), ("b", np.float64),
+    ("X", np.float64, (4,)),
+    ("thA", np.float64), ("sA", np.float64), ("thB", np.float64), ("sB", np.float64),
+    ("margin", np.float64),
+])
+STATS_FIELDS = ("n_entries", "n_entries_all", "n_cells", "n_slots", "n_cand", "n_moller", "n_degenerate",
+                "n_outside", "n_hits", "n_nonfinite", "overflow")
+
+
+class MSearchError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class SearchParams(C.Structure):
+    _fields_ = [("world_lo", C.c_double * 4), ("inv_edge", C.c_double), ("n_cells", C.c_int64 * 4),
+                ("flags", C.c_int32), ("pad", C.c_int32)]
+
+
+class MeshInfo(C.Structure):
+    _fields_ = [("n_tris", C.c_int64), ("n_nonfinite", C.c_int64), ("lo", C.c_double * 4),
+                ("hi", C.c_double * 4), ("mean_diam", C.c_double)]
+
+
+class MapParams(C.Structure):
+    _fields_ = [("mu", C.c_double), ("e", C.c_double), ("steps_per_period", C.c_int32), ("n_periods", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmsearch.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it first (python -m paper_2109_14814_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.last_error.argtypes = []; L.last_error.restype = C.c_char_p
+        L.mesh_build.argtypes = [P, I32, I32, I32, I32, P, P, P, C.POINTER(P)]; L.mesh_build.restype = C.c_int
+        L.mesh_free.argtypes = [P]; L.mesh_free.restype = C.c_int
+        L.mesh_info.argtypes = [P, C.POINTER(MeshInfo)]; L.mesh_info.restype = C.c_int
+        L.search_default_params.argtypes = [P, P, D, C.POINTER(SearchParams)]
+        L.search_default_params.restype = C.c_int
+        L.search_workspace_size.argtypes = [P, P, C.POINTER(SearchParams), I64, I64, P, C.POINTER(C.c_size_t)]
+        L.search_workspace_size.restype = C.c_int
+        L.search_intersections.argtypes = [P, P, C.POINTER(SearchParams), P, C.c_size_t, P, I64, P, P, I64, P, P]
+        L.search_intersections.restype = C.c_int
+        L.narrow_allpairs.argtypes = [P, P, P, I64, P, P, P]; L.narrow_allpairs.restype = C.c_int
+        L.propagate_vertices.argtypes = [P, P, I64, C.POINTER(MapParams), P]
+        L.propagate_vertices.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != MS_OK:
+        raise MSearchError(rc, lib().last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_bytes(n: int):
+    torch = _torch()
+    return torch.empty(max(int(n), 1), dtype=torch.uint8, device="cuda")
+
+
+class Mesh:
+    """A triangulated vertex grid resident in HBM (mesh_build).
+
+    verts: (n_s_v, n_theta_v, 4) float64 (numpy or torch); theta, s: sample values."""
+
+    def __init__(self, verts, theta, s, periodic: bool, layout: int = MS_LAYOUT_AOS):
+        torch = _torch()
+        v = torch.as_tensor(verts, dtype=torch.float64)
+        if layout == MS_LAYOUT_SOA:
+            v = v.permute(2, 0, 1)
+        self.verts = v.contiguous().to("cuda")
+        n_s_v, n_theta_v = (self.verts.shape[1], self.verts.shape[2]) if layout == MS_LAYOUT_SOA else \
+            (self.verts.shape[0], self.verts.shape[1])
+        self.theta = np.ascontiguousarray(theta, dtype=np.float64)
+        self.s = np.ascontiguousarray(s, dtype=np.float64)
+        assert len(self.theta) == n_theta_v and len(self.s) == n_s_v
+        h = C.c_void_p()
+        _check(lib().mesh_build(C.c_void_p(self.verts.data_ptr()), n_theta_v, n_s_v, int(bool(periodic)), layout,
+                                self.theta.ctypes.data_as(C.c_void_p), self.s.ctypes.data_as(C.c_void_p),
+                                _stream(), C.byref(h)))
+        self.handle = h
+        inf = MeshInfo()
+        _check(lib().mesh_info(h, C.byref(inf)))
+        self.n_tris = int(inf.n_tris)
+        self.n_nonfinite = int(inf.n_nonfinite)
+        self.lo = np.array(inf.lo[:]); self.hi = np.array(inf.hi[:])
+        self.mean_diam = float(inf.mean_diam)
+
+    @classmethod
+    def from_synth(cls, m, layout: int = MS_LAYOUT_AOS):
+        return cls(m.verts, m.theta, m.s, m.periodic, layout)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().mesh_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def default_params(A: Mesh, B: Mesh, kappa: float) -> SearchParams:
+    p = SearchParams()
+    _check(lib().search_default_params(A.handle, B.handle, float(kappa), C.byref(p)))
+    return p
+
+
+def make_params(w_lo, inv_edge: float, n_cells, flags: int = 0) -> SearchParams:
+    p = SearchParams()
+    for d in range(4):
+        p.world_lo[d] = float(w_lo[d])
+        p.n_cells[d] = int(n_cells[d])
+    p.inv_edge = float(inv_edge)
+    p.flags = int(flags)
+    return p
+
+
+def _stats_dict(buf) -> dict:
+    arr = buf.view(_torch().int64).cpu().numpy()
+    return {k: int(arr[i]) for i, k in enumerate(STATS_FIELDS)}
+
+
+class Searcher:
+    """Device buffers for repeated searches of one mesh pair."""
+
+    def __init__(self, A: Mesh, B: Mesh, params: SearchParams, hits_cap: int = 1 << 16,
+                 cand_cap: int = 1 << 20):
+        self.A, self.B, self.params = A, B, params
+        self.hits_cap, self.cand_cap = int(hits_cap), int(cand_cap)
+        self.stats = _dev_bytes(16 * 8)
+        self._alloc()
+
+    def _alloc(self):
+        nb = C.c_size_t()
+        _check(lib().search_workspace_size(self.A.handle, self.B.handle, C.byref(self.params), self.cand_cap,
+                                           self.hits_cap, _stream(), C.byref(nb)))
+        self.ws_bytes = int(nb.value)
+        self.ws = _dev_bytes(self.ws_bytes)
+        self.hits = _dev_bytes(self.hits_cap * HIT_DTYPE.itemsize)
+        want_cand = bool(self.params.flags & MS_SEARCH_CANDIDATES)
+        self.cand = _dev_bytes(self.cand_cap * 8) if want_cand else None
+
+    def _call(self, needed):
+        cand_ptr = C.c_void_p(self.cand.data_ptr()) if self.cand is not None else None
+        return lib().search_intersections(self.A.handle, self.B.handle, C.byref(self.params),
+                                          C.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+                                          C.c_void_p(self.hits.data_ptr()), self.hits_cap,
+                                          C.c_void_p(self.stats.data_ptr()), cand_ptr, self.cand_cap,
+                                          needed, _stream())
+
+    def run(self, retry: bool = True) -> None:
+        """One search.  On a capacity error, grow the buffers to the reported
+        needs and search once more (when retry is set)."""
+        needed = (C.c_int64 * 3)()
+        rc = self._call(needed)
+        if rc in (MS_E_CAPACITY, MS_E_WORKSPACE) and retry:
+            self.hits_cap = max(self.hits_cap, int(needed[0]))
+            self.cand_cap = max(self.cand_cap, int(needed[1]))
+            self._alloc()
+            rc = self._call(needed)
+        _check(rc)
+
+    def results(self):
+        """(hits structured array sorted by (triA, triB), stats dict, candidates or None)."""
+        st = _stats_dict(self.stats)
+        nh = min(st["n_hits"], self.hits_cap)
+        hits = np.frombuffer(self.hits[: nh * HIT_DTYPE.itemsize].cpu().numpy().tobytes(), dtype=HIT_DTYPE)
+        cand = None
+        if self.cand is not None:
+            nc = min(st["n_cand"], self.cand_cap)
+            cand = self.cand[: nc * 8].view(_torch().int64).cpu().numpy().copy()
+        return hits, st, cand
+
+
+def search(A: Mesh, B: Mesh, params: SearchParams, hits_cap: int = 1 << 16, cand_cap: int = 1 << 20):
+    s = Searcher(A, B, params, hits_cap, cand_cap)
+    s.run()
+    return s.results()
+
+
+def narrow_allpairs(A: Mesh, B: Mesh, hits_cap: int = 1 << 16):
+    """All pairs with the full test on every pair: (hits sorted by (triA, triB), stats)."""
+    torch = _torch()
+    hits = _dev_bytes(hits_cap * HIT_DTYPE.itemsize)
+    nh = torch.zeros(1, dtype=torch.int64, device="cuda")
+    stats = _dev_bytes(16 * 8)
+    _check(lib().narrow_allpairs(A.handle, B.handle, C.c_void_p(hits.data_ptr()), int(hits_cap),
+                                 C.c_void_p(nh.data_ptr()), C.c_void_p(stats.data_ptr()), _stream()))
+    st = _stats_dict(stats)
+    n = min(int(nh.item()), hits_cap)
+    h = np.frombuffer(hits[: n * HIT_DTYPE.itemsize].cpu().numpy().tobytes(), dtype=HIT_DTYPE)
+    order = np.lexsort((h["triB"], h["triA"]))
+    return h[order], st
+
+
+def propagate(states, mu: float, e: float, steps_per_period: int, n_periods: int, out=None):
+    """F^n_periods of (n, 4) states on the GPU (torch float64 cuda tensor in, tensor out)."""
+    torch = _torch()
+    x = torch.as_tensor(states, dtype=torch.float64).to("cuda").contiguous()
+    assert x.shape[-1] == 4
+    if out is None:
+        out = torch.empty_like(x)
+    p = MapParams(float(mu), float(e), int(steps_per_period), int(n_periods))
+    _check(lib().propagate_vertices(C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()), x.numel() // 4,
+                                    C.byref(p), _stream()))
+    return out

@@ -1,0 +1,188 @@
+// ms_internal.hpp -- internal definitions shared by the HIP sources of
+// libmsearch.so (never installed; the public ABI is include/msearch.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+
+#include "../../include/msearch.h"
+
+#define MS_HD __host__ __device__ __forceinline__
+#define MS_D __device__ __forceinline__
+
+namespace ms {
+
+constexpr int WAVE = 64;
+
+// ----------------------------------------------------------------- errors
+
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+#define MS_HIP(call)                                            \
+    do {                                                        \
+        hipError_t _e = (call);                                 \
+        if (_e != hipSuccess) return ::ms::hip_fail(_e, #call); \
+    } while (0)
+
+// -------------------------------------------------------------- mesh view
+
+// Device view of a triangulated vertex grid (see mesh_build in msearch.h).
+struct MeshView {
+    const double *V;       // AoS vertices, 4 doubles each, theta index fastest
+    const double *box;     // per triangle: lo[4], hi[4]; NaN-filled when non-finite
+    const double *theta;   // n_theta_v samples
+    const double *s;       // n_s_v samples
+    int32_t n_theta_v, n_s_v;
+    int32_t nq;            // quads per s-row
+    int32_t periodic;
+    int32_t n_tris;
+    int32_t pad;
+};
+
+// Vertex ids (in the AoS array) of triangle t in narrow-phase order.
+MS_HD void tri_vertex_ids(const MeshView &m, int32_t t, int32_t &v1, int32_t &v2, int32_t &v3)
+{
+    int32_t q = t >> 1;
+    int32_t h = t & 1;
+    int32_t k = q / m.nq;
+    int32_t i = q - k * m.nq;
+    int32_t i1 = i + 1;
+    if (i1 == m.n_theta_v) i1 = 0;   // periodic wrap (i1 == n_theta_v only when periodic)
+    int32_t r0 = k * m.n_theta_v, r1 = r0 + m.n_theta_v;
+    if (h == 0) { v1 = r0 + i1; v2 = r0 + i;  v3 = r1 + i; }
+    else        { v1 = r1 + i;  v2 = r1 + i1; v3 = r0 + i1; }
+}
+
+struct d4 { double x, y, z, w; };
+
+MS_D d4 load_d4(const double *p)
+{
+    const double2 *q = reinterpret_cast<const double2 *>(p);
+    double2 a = q[0], b = q[1];
+    return d4{a.x, a.y, b.x, b.y};
+}
+
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+// Streaming load (data read once): bypasses cache retention.
+MS_D d4 load_d4_nt(const double *p)
+{
+    const dvec2 *q = reinterpret_cast<const dvec2 *>(p);
+    dvec2 a = __builtin_nontemporal_load(q);
+    dvec2 b = __builtin_nontemporal_load(q + 1);
+    return d4{a.x, a.y, b.x, b.y};
+}
+
+// ------------------------------------------------------------ grid / keys
+
+struct GridView {
+    double wlo[4];
+    double inv;
+    int64_t n[4];
+};
+
+// Cell of coordinate x on one axis: clamp(floor((x - wlo) * inv), 0, n - 1),
+// FP64, one rounding per operation (the kernels are built with contraction off).
+MS_D int64_t cell_of(double x, double wlo, double inv, int64_t n)
+{
+    double t = (x - wlo) * inv;
+    double f = floor(t);
+    if (!(f >= 0.0)) return 0;
+    if (f >= (double)n) return n - 1;
+    int64_t c = (int64_t)f;
+    return c < n ? c : n - 1;
+}
+
+MS_D int64_t cell_linear(const int64_t c[4], const int64_t n[4])
+{
+    return ((c[0] * n[1] + c[1]) * n[2] + c[2]) * n[3] + c[3];
+}
+
+// ------------------------------------------------------------- wave utils
+
+MS_D uint64_t ballot(bool p) { return __ballot(p); }
+
+MS_D int lane_id() { return __lane_id(); }
+
+// Number of set bits of m below this lane.
+MS_D int mbcnt(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+}
+
+// Wave-aggregated slot reservation: every lane with `want` gets a distinct
+// index in [base, base + popcount); one atomic per wave.
+MS_D int64_t wave_reserve(bool want, unsigned long long *counter)
+{
+    uint64_t m = ballot(want);
+    if (m == 0) return -1;
+    int leader = __builtin_ctzll(m);
+    unsigned long long base = 0;
+    if (lane_id() == leader) base = atomicAdd(counter, (unsigned long long)__builtin_popcountll(m));
+    base = __shfl(base, leader);
+    return want ? (int64_t)(base + (unsigned long long)mbcnt(m)) : -1;
+}
+
+MS_D unsigned long long wave_sum_u64(unsigned long long v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// ------------------------------------------------------------ search stats
+
+enum StatIdx {
+    ST_ENTRIES = 0, ST_ENTRIES_ALL, ST_CELLS, ST_SLOTS, ST_CAND, ST_MOLLER, ST_DEGEN,
+    ST_OUTSIDE, ST_HITS, ST_NONFINITE, ST_OVERFLOW
+};
+
+MS_HD int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+inline int bits_for(uint64_t x)   // bits needed to store values 0..x
+{
+    int b = 0;
+    while (b < 64 && (x >> b) != 0) ++b;
+    return b;
+}
+
+// -------------------------------------------------- internal sort/scan API
+
+// Radix sort of 64-bit keys on bits [lo_bit, lo_bit + n_bits), stable.
+// n is read from device memory (*n_dev); cap bounds it on the host.  The
+// sorted keys end up in *result (either keys or alt).
+struct SortWs {
+    uint32_t *hist;          // passes * 256
+    uint32_t *status;        // tiles_cap * 256
+    uint32_t *tile_ctr;      // passes
+};
+size_t sort_ws_bytes(int64_t cap, int max_passes);
+void sort_ws_carve(void *base, int64_t cap, int max_passes, SortWs &ws);
+int radix_sort_u64(uint64_t *keys, uint64_t *alt, const int64_t *n_dev, int64_t cap, int lo_bit,
+                   int n_bits, const SortWs &ws, hipStream_t st, uint64_t **result);
+
+// Exclusive scan of n 32-bit counts into 64-bit offsets; out[n] = total.
+// n from the host; total also added to *total_dev if non-NULL.
+size_t scan_ws_bytes();
+int scan_u32_to_i64(const uint32_t *in, int64_t *out, int64_t n, int64_t *total_dev, void *ws, hipStream_t st);
+// Exclusive scan of a device-sized (*n_dev) array of int64, cap on host;
+// out[n] = total, also stored to *total_dev.
+int scan_i64_dev(const int64_t *in, int64_t *out, const int64_t *n_dev, int64_t cap, int64_t *total_dev,
+                 void *ws, hipStream_t st);
+
+int launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st);
+
+}  // namespace ms
+
+// The opaque handle of the public ABI.
+struct ms_mesh {
+    ms::MeshView view;
+    double *owned_V;          // AoS copy for MS_LAYOUT_SOA
+    double *box;              // device, 8 doubles per triangle
+    double *theta_dev, *s_dev;
+    int64_t *scratch;         // small device scratch (counters)
+    ms_mesh_info_t info;
+    int device;
+};

@@ -1,0 +1,210 @@
+// rk8.hip -- stroboscopic map of the planar elliptic restricted three-body
+// problem (pulsating rotating coordinates, true anomaly as time), fixed-step
+// explicit Runge-Kutta of order 8 (Cooper & Verner 1972, 11 stages).
+//
+// One thread per state; the tableau is a kernel argument (scalar loads) and
+// the stage weights w(f) = 1 / (1 + e cos f) are tabulated per step of one
+// period on the host (w is 2 pi periodic and even, so the same table serves
+// every period and both directions), read with uniform loads.
+#include <math.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "ms_internal.hpp"
+
+namespace ms {
+
+namespace {
+
+constexpr int S = 11;
+constexpr int RK_BLOCK = 128;
+
+struct Tableau {
+    double a[S][S];
+    double b[S];
+    double c[S];
+};
+
+// Non-zero pattern of the Cooper-Verner tableau (used to drop the zero terms
+// at compile time; the values themselves come from make_tableau).
+constexpr bool NZ[S][S] = {
+    {0}, {1}, {1, 1}, {1, 1, 1}, {1, 0, 1, 1}, {1, 0, 1, 1, 1}, {1, 0, 1, 1, 1, 1},
+    {1, 0, 0, 0, 1, 1, 1}, {1, 0, 0, 0, 1, 1, 1, 1}, {1, 0, 0, 0, 1, 1, 1, 1, 1}, {0, 0, 0, 0, 1, 1, 1, 1, 1, 1}};
+constexpr bool NZB[S] = {1, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1};
+
+// Cooper & Verner (1972), SIAM J. Numer. Anal. 9, order-8 method with 11
+// stages; coefficients in Q(sqrt 21), evaluated once in double precision.
+Tableau make_tableau()
+{
+    Tableau T;
+    memset(&T, 0, sizeof T);
+    const double q = sqrt(21.0);
+    double (*a)[S] = T.a;
+    a[1][0] = 0.5;
+    a[2][0] = 0.25; a[2][1] = 0.25;
+    a[3][0] = 1.0 / 7.0; a[3][1] = -(7.0 + 3.0 * q) / 98.0; a[3][2] = (21.0 + 5.0 * q) / 49.0;
+    a[4][0] = (11.0 + q) / 84.0; a[4][2] = (18.0 + 4.0 * q) / 63.0; a[4][3] = (21.0 - q) / 252.0;
+    a[5][0] = (5.0 + q) / 48.0; a[5][2] = (9.0 + q) / 36.0; a[5][3] = (14.0 * q - 231.0) / 360.0; a[5][4] = (63.0 - 7.0 * q) / 80.0;
+    a[6][0] = (10.0 - q) / 42.0; a[6][2] = (92.0 * q - 432.0) / 315.0; a[6][3] = (633.0 - 145.0 * q) / 90.0;
+    a[6][4] = (115.0 * q - 504.0) / 70.0; a[6][5] = (63.0 - 13.0 * q) / 35.0;
+    a[7][0] = 1.0 / 14.0; a[7][4] = (14.0 - 3.0 * q) / 126.0; a[7][5] = (13.0 - 3.0 * q) / 63.0; a[7][6] = 1.0 / 9.0;
+    a[8][0] = 1.0 / 32.0; a[8][4] = (91.0 - 21.0 * q) / 576.0; a[8][5] = 11.0 / 72.0;
+    a[8][6] = -(385.0 + 75.0 * q) / 1152.0; a[8][7] = (63.0 + 13.0 * q) / 128.0;
+    a[9][0] = 1.0 / 14.0; a[9][4] = 1.0 / 9.0; a[9][5] = -(733.0 + 147.0 * q) / 2205.0;
+    a[9][6] = (515.0 + 111.0 * q) / 504.0; a[9][7] = -(51.0 + 11.0 * q) / 56.0; a[9][8] = (132.0 + 28.0 * q) / 245.0;
+    a[10][4] = (7.0 * q - 42.0) / 18.0; a[10][5] = (28.0 * q - 18.0) / 45.0; a[10][6] = -(273.0 + 53.0 * q) / 72.0;
+    a[10][7] = (301.0 + 53.0 * q) / 72.0; a[10][8] = (28.0 - 28.0 * q) / 45.0; a[10][9] = (49.0 - 7.0 * q) / 18.0;
+    const double b[S] = {1.0 / 20.0, 0, 0, 0, 0, 0, 0, 49.0 / 180.0, 16.0 / 45.0, 49.0 / 180.0, 1.0 / 20.0};
+    const double c[S] = {0.0, 0.5, 0.5, (7.0 + q) / 14.0, (7.0 + q) / 14.0, 0.5, (7.0 - q) / 14.0, (7.0 - q) / 14.0,
+                         0.5, (7.0 + q) / 14.0, 1.0};
+    memcpy(T.b, b, sizeof b);
+    memcpy(T.c, c, sizeof c);
+    return T;
+}
+
+// The pattern must describe the values exactly (checked once on the host).
+bool pattern_matches(const Tableau &T)
+{
+    for (int i = 0; i < S; ++i) {
+        for (int j = 0; j < S; ++j)
+            if ((T.a[i][j] != 0.0) != (j < i && NZ[i][j])) return false;
+        if ((T.b[i] != 0.0) != NZB[i]) return false;
+    }
+    return true;
+}
+
+const Tableau &tableau()
+{
+    static const Tableau T = make_tableau();
+    return T;
+}
+
+// Stage-weight tables per (device, e, steps per period), kept for the life of
+// the process.
+std::mutex g_tab_mu;
+std::map<std::tuple<int, uint64_t, int>, double *> g_tabs;
+
+int omega_table(double e, int steps, double **out)
+{
+    int dev = 0;
+    MS_HIP(hipGetDevice(&dev));
+    uint64_t eb;
+    memcpy(&eb, &e, 8);
+    std::lock_guard<std::mutex> lk(g_tab_mu);
+    auto key = std::make_tuple(dev, eb, steps);
+    auto it = g_tabs.find(key);
+    if (it != g_tabs.end()) { *out = it->second; return MS_OK; }
+    const Tableau &T = tableau();
+    const double h = 6.283185307179586476925286766559 / (double)steps;
+    std::vector<double> w((size_t)steps * S);
+    for (int n = 0; n < steps; ++n)
+        for (int i = 0; i < S; ++i) w[(size_t)n * S + i] = 1.0 / (1.0 + e * cos((double)n * h + T.c[i] * h));
+    double *d = nullptr;
+    MS_HIP(hipMalloc(&d, w.size() * sizeof(double)));
+    hipError_t er = hipMemcpy(d, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (er != hipSuccess) { (void)hipFree(d); return hip_fail(er, "copy stage table"); }
+    g_tabs[key] = d;
+    *out = d;
+    return MS_OK;
+}
+
+struct Model {
+    double mu, one_minus_mu;
+};
+
+// Right-hand side at stage weight w: (x', y', w Omega_x + 2 y', w Omega_y - 2 x').
+MS_D void field(const Model &md, double w, const double y[4], double k[4])
+{
+#pragma clang fp contract(fast)
+    double x = y[0], yy = y[1];
+    double dx1 = x + md.mu, dx2 = x - md.one_minus_mu;
+    double yy2 = yy * yy;
+    double r1s = dx1 * dx1 + yy2, r2s = dx2 * dx2 + yy2;
+    double r1 = sqrt(r1s), r2 = sqrt(r2s);
+    double g1 = md.one_minus_mu / (r1s * r1), g2 = md.mu / (r2s * r2);
+    double Ox = x - g1 * dx1 - g2 * dx2;
+    double Oy = yy - (g1 + g2) * yy;
+    k[0] = y[2];
+    k[1] = y[3];
+    k[2] = 2.0 * y[3] + w * Ox;
+    k[3] = -2.0 * y[2] + w * Oy;
+}
+
+__global__ void __launch_bounds__(RK_BLOCK) k_rk8_map(const double *__restrict__ in, double *__restrict__ out,
+                                                      int64_t n, Model md, Tableau T, const double *__restrict__ wtab,
+                                                      int steps, int64_t nsteps, double h)
+{
+#pragma clang fp contract(fast)
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    d4 s = load_d4(in + 4 * v);
+    double y[4] = {s.x, s.y, s.z, s.w};
+    int n_in = 0;
+    for (int64_t st = 0; st < nsteps; ++st) {
+        const double *w = wtab + (size_t)n_in * S;
+        double k[S][4];
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            double ys[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < i; ++j)
+                    if (NZ[i][j]) acc += T.a[i][j] * k[j][c];
+                ys[c] = y[c] + h * acc;
+            }
+            field(md, w[i], ys, k[i]);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < S; ++i)
+                if (NZB[i]) acc += T.b[i] * k[i][c];
+            y[c] = y[c] + h * acc;
+        }
+        if (++n_in == steps) n_in = 0;
+    }
+    double2 *o = reinterpret_cast<double2 *>(out + 4 * v);
+    o[0] = make_double2(y[0], y[1]);
+    o[1] = make_double2(y[2], y[3]);
+}
+
+}  // namespace
+}  // namespace ms
+
+using namespace ms;
+
+extern "C" int propagate_vertices(const double *in_dev, double *out_dev, int64_t n_vertices, const map_params_t *p,
+                                  void *stream)
+{
+    if (!p || n_vertices < 0 || (n_vertices > 0 && (!in_dev || !out_dev)))
+        return fail(MS_E_ARG, "propagate_vertices: bad argument");
+    if (p->steps_per_period <= 0) return fail(MS_E_ARG, "propagate_vertices: steps_per_period must be > 0");
+    if (!(p->e >= 0.0 && p->e < 1.0) || !(p->mu >= 0.0 && p->mu <= 1.0))
+        return fail(MS_E_ARG, "propagate_vertices: need 0 <= e < 1 and 0 <= mu <= 1");
+    if (n_vertices == 0) return MS_OK;
+    if (!pattern_matches(tableau())) return fail(MS_E_ARG, "propagate_vertices: internal tableau pattern mismatch");
+    hipStream_t st = (hipStream_t)stream;
+    double *wtab = nullptr;
+    int rc = omega_table(p->e, p->steps_per_period, &wtab);
+    if (rc) return rc;
+    int np = p->n_periods < 0 ? -p->n_periods : p->n_periods;
+    int64_t nsteps = (int64_t)p->steps_per_period * np;
+    double h = (p->n_periods < 0 ? -6.283185307179586476925286766559 : 6.283185307179586476925286766559) /
+               (double)p->steps_per_period;
+    if (nsteps == 0) {
+        if (in_dev != out_dev) MS_HIP(hipMemcpyAsync(out_dev, in_dev, (size_t)n_vertices * 32, hipMemcpyDeviceToDevice, st));
+        return MS_OK;
+    }
+    Model md{p->mu, 1.0 - p->mu};
+    hipLaunchKernelGGL(k_rk8_map, dim3((unsigned)ceil_div(n_vertices, RK_BLOCK)), dim3(RK_BLOCK), 0, st, in_dev,
+                       out_dev, n_vertices, md, tableau(), wtab, p->steps_per_period, nsteps, h);
+    MS_HIP(hipGetLastError());
+    return MS_OK;
+}
