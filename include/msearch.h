@@ -89,11 +89,19 @@ int mesh_free(ms_mesh *mesh);
 typedef struct {
     int64_t n_tris;        /* 2 * Nq * (n_s_v - 1) */
     int64_t n_nonfinite;   /* triangles excluded for non-finite coordinates */
-    double lo[4], hi[4];   /* bounds of all finite vertices (+inf/-inf if none) */
+    double lo[4], hi[4];   /* bounds of the finite triangles (+inf/-inf if none) */
     double mean_diam;      /* mean over finite triangles of the longest 4D edge */
 } ms_mesh_info_t;
 
+/* Bounds, diameter and counts of a mesh (waits for a pending mesh_update). */
 int mesh_info(const ms_mesh *mesh, ms_mesh_info_t *out);
+
+/*
+ * mesh_update -- recompute the triangle boxes after the caller changed the
+ * vertex values in place (same grid, same buffer; e.g. after
+ * propagate_vertices).  Asynchronous on `stream`; allocates nothing.
+ */
+int mesh_update(ms_mesh *mesh, void *stream);
 
 /* --------------------------------------------------------------- search */
 
@@ -119,7 +127,7 @@ typedef struct {
     int32_t pad;
 } search_params_t;
 
-/* World = box of both meshes' finite vertices, edge = kappa * mean triangle
+/* World = box of both meshes' finite triangles, edge = kappa * mean triangle
  * diameter of both meshes, n_cells[d] = max(1, ceil(span_d * inv_edge)). */
 int search_default_params(const ms_mesh *A, const ms_mesh *B, double kappa, search_params_t *out);
 
@@ -199,6 +207,46 @@ int search_intersections(const ms_mesh *A, const ms_mesh *B, const search_params
  */
 int narrow_allpairs(const ms_mesh *A, const ms_mesh *B, hit_t *hits_dev, int64_t hits_cap,
                     int64_t *n_hits_dev, search_stats_t *stats_dev, void *stream);
+
+/*
+ * Batched search: many mesh pairs (e.g. the members of a torus family or the
+ * half-layer pairs of Sec. 5 / Sec. 6.4) searched together by one pass of
+ * the pipeline.  Each pair keeps its own grid; the cells of pair i are
+ * offset so that no two pairs share a cell.  Hits come out sorted by (pair,
+ * triA, triB); hit_t.flags holds the pair index.
+ *
+ * batch_create -- plan a batch: copies the pair descriptors (the meshes
+ *   must stay alive and unchanged in topology), counts entries (runs kernels
+ *   on `stream`, synchronises) and returns the workspace size for hits_cap
+ *   hits and cand_cap internal candidates.
+ * batch_search -- queue the search of every pair (asynchronous; no host
+ *   synchronisation).  pair_hit_offsets_dev receives n_pairs + 1 int64 offsets
+ *   into hits_dev.  With use_graph != 0 the kernel sequence is captured into a
+ *   HIP graph on the first call (and again whenever a buffer argument
+ *   changes) and later calls launch the graph.  Capacity overflow is
+ *   reported in stats_dev->overflow (check it after synchronising);
+ *   batch_needed then gives the sizes to re-plan with.
+ * batch_free -- release the plan and its graph.
+ */
+typedef struct ms_batch ms_batch;
+int batch_create(int32_t n_pairs, const ms_mesh *const *A, const ms_mesh *const *B, const search_params_t *params,
+                 int64_t hits_cap, int64_t cand_cap, void *stream, ms_batch **out, size_t *ws_bytes);
+int batch_search(ms_batch *batch, void *ws_dev, size_t ws_bytes, hit_t *hits_dev, int64_t hits_cap,
+                 int64_t *pair_hit_offsets_dev, search_stats_t *stats_dev, int32_t use_graph, void *stream);
+/* needed[0] hits, needed[1] candidates, needed[2] workspace bytes for the
+ * counts of a finished search (stats copied to the host). */
+int batch_needed(const ms_batch *batch, const search_stats_t *stats_host, int64_t *needed);
+int batch_free(ms_batch *batch);
+
+/*
+ * Kernel timing of search_intersections for benchmarks.  While enabled (per
+ * calling thread), each search records a HIP event on its stream before every
+ * kernel and at its end; search_profile_read returns the names (comma
+ * separated) and durations in ms of the kernels of the last search
+ * (waiting for its last event).  *n receives the number of kernels.
+ */
+int search_profile_enable(int on);
+int search_profile_read(char *names, size_t names_len, double *ms, int cap, int *n);
 
 /* ------------------------------------------------------------------ map */
 

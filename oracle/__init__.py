@@ -71,6 +71,7 @@ def lib():
         L.orc_energy_balance.argtypes = [P, D, D, I32, I32, P]; L.orc_energy_balance.restype = C.c_int
         L.orc_mismatch.argtypes = [P, I64, P, P, D, D, I32, I32, I32, P, P, P, P, C.c_int]
         L.orc_mismatch.restype = C.c_int
+        L.orc_max_threads.argtypes = []; L.orc_max_threads.restype = C.c_int
         _lib = L
     return _lib
 
@@ -185,6 +186,10 @@ def grid_entries(mesh, w_lo, inv_edge: float, n_cells) -> int:
     wl = np.ascontiguousarray(w_lo, dtype=np.float64)
     nc = np.ascontiguousarray(n_cells, dtype=np.int64)
     return int(lib().orc_grid_entries(om.ref, _ptr(wl), float(inv_edge), _ptr(nc)))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 
 
 def rk8_tableau():

@@ -942,3 +942,6 @@ ORC_API int orc_mismatch(const double *params, int64_t K, const double *pu, cons
     }
     return err ? -1 : 0;
 }
+
+/* Threads the OpenMP loops of this library use. */
+ORC_API int orc_max_threads(void) { return omp_get_max_threads(); }

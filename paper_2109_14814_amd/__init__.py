@@ -21,8 +21,10 @@ MS_LAYOUT_AOS, MS_LAYOUT_SOA = 0, 1
 MS_SEARCH_CANDIDATES, MS_SEARCH_STRICT = 1, 2
 
 # Exported entry points (the C ABI of include/msearch.h).
-EXPORTS = ("last_error", "mesh_build", "mesh_free", "mesh_info", "search_default_params",
-           "search_workspace_size", "search_intersections", "narrow_allpairs", "propagate_vertices")
+EXPORTS = ("last_error", "mesh_build", "mesh_free", "mesh_info", "mesh_update", "search_default_params",
+           "search_workspace_size", "search_intersections", "narrow_allpairs", "propagate_vertices",
+           "search_profile_enable", "search_profile_read", "batch_create", "batch_search", "batch_needed",
+           "batch_free")
 
 HIT_DTYPE = np.dtype([
     ("triA", np.int32), ("triB", np.int32), ("flags", np.uint32), ("pad", np.uint32),
@@ -79,6 +81,15 @@ def lib():
         L.narrow_allpairs.argtypes = [P, P, P, I64, P, P, P]; L.narrow_allpairs.restype = C.c_int
         L.propagate_vertices.argtypes = [P, P, I64, C.POINTER(MapParams), P]
         L.propagate_vertices.restype = C.c_int
+        L.mesh_update.argtypes = [P, P]; L.mesh_update.restype = C.c_int
+        L.batch_create.argtypes = [I32, P, P, P, I64, I64, P, C.POINTER(P), C.POINTER(C.c_size_t)]
+        L.batch_create.restype = C.c_int
+        L.batch_search.argtypes = [P, P, C.c_size_t, P, I64, P, P, I32, P]; L.batch_search.restype = C.c_int
+        L.batch_needed.argtypes = [P, P, P]; L.batch_needed.restype = C.c_int
+        L.batch_free.argtypes = [P]; L.batch_free.restype = C.c_int
+        L.search_profile_enable.argtypes = [C.c_int]; L.search_profile_enable.restype = C.c_int
+        L.search_profile_read.argtypes = [C.c_char_p, C.c_size_t, P, C.c_int, C.POINTER(C.c_int)]
+        L.search_profile_read.restype = C.c_int
         _lib = L
     return _lib
 
@@ -130,6 +141,10 @@ class Mesh:
         self.n_nonfinite = int(inf.n_nonfinite)
         self.lo = np.array(inf.lo[:]); self.hi = np.array(inf.hi[:])
         self.mean_diam = float(inf.mean_diam)
+
+    def update(self):
+        """Recompute the triangle boxes after self.verts changed in place."""
+        _check(lib().mesh_update(self.handle, _stream()))
 
     @classmethod
     def from_synth(cls, m, layout: int = MS_LAYOUT_AOS):
@@ -198,10 +213,13 @@ class Searcher:
 
     def run(self, retry: bool = True) -> None:
         """One search.  On a capacity error, grow the buffers to the reported
-        needs and search once more (when retry is set)."""
+        needs and search again (when retry is set).  A candidate overflow
+        only bounds the hit count from below, so a second growth may follow."""
         needed = (C.c_int64 * 3)()
         rc = self._call(needed)
-        if rc in (MS_E_CAPACITY, MS_E_WORKSPACE) and retry:
+        for _ in range(3 if retry else 0):
+            if rc not in (MS_E_CAPACITY, MS_E_WORKSPACE):
+                break
             self.hits_cap = max(self.hits_cap, int(needed[0]))
             self.cand_cap = max(self.cand_cap, int(needed[1]))
             self._alloc()
@@ -220,10 +238,99 @@ class Searcher:
         return hits, st, cand
 
 
+def profile_enable(on: bool = True):
+    _check(lib().search_profile_enable(int(bool(on))))
+
+
+def profile_read():
+    """[(kernel name, ms)] of the last search while profiling was enabled."""
+    cap = 256
+    names = C.create_string_buffer(8192)
+    arr = (C.c_double * cap)()
+    n = C.c_int()
+    _check(lib().search_profile_read(names, 8192, arr, cap, C.byref(n)))
+    nm = names.value.decode().split(",") if n.value else []
+    return list(zip(nm, arr[: n.value]))
+
+
 def search(A: Mesh, B: Mesh, params: SearchParams, hits_cap: int = 1 << 16, cand_cap: int = 1 << 20):
     s = Searcher(A, B, params, hits_cap, cand_cap)
     s.run()
     return s.results()
+
+
+class Batch:
+    """Many mesh pairs searched by one pass of the pipeline (batch_create /
+    batch_search); with use_graph the kernel sequence is a captured HIP graph."""
+
+    def __init__(self, pairs, params, hits_cap: int = 1 << 16, cand_cap: int = 1 << 20):
+        self.pairs = list(pairs)
+        self.params = list(params)
+        n = len(self.pairs)
+        self._A = (C.c_void_p * n)(*[a.handle for a, _ in self.pairs])
+        self._B = (C.c_void_p * n)(*[b.handle for _, b in self.pairs])
+        self._P = (SearchParams * n)(*self.params)
+        self.hits_cap, self.cand_cap = int(hits_cap), int(cand_cap)
+        self.handle = None
+        self.stats = _dev_bytes(16 * 8)
+        self.offsets = _torch().zeros(n + 1, dtype=_torch().int64, device="cuda")
+        self._create()
+
+    def _create(self):
+        if self.handle:
+            lib().batch_free(self.handle)
+        h = C.c_void_p()
+        nb = C.c_size_t()
+        _check(lib().batch_create(len(self.pairs), self._A, self._B, self._P, self.hits_cap, self.cand_cap,
+                                  _stream(), C.byref(h), C.byref(nb)))
+        self.handle = h
+        self.ws_bytes = int(nb.value)
+        self.ws = _dev_bytes(self.ws_bytes)
+        self.hits = _dev_bytes(self.hits_cap * HIT_DTYPE.itemsize)
+
+    def run(self, use_graph: bool = True) -> None:
+        """Queue one search of every pair (no host synchronisation)."""
+        _check(lib().batch_search(self.handle, C.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+                                  C.c_void_p(self.hits.data_ptr()), self.hits_cap,
+                                  C.c_void_p(self.offsets.data_ptr()), C.c_void_p(self.stats.data_ptr()),
+                                  int(bool(use_graph)), _stream()))
+
+    def run_checked(self, use_graph: bool = True) -> None:
+        """Search, and on a capacity overflow re-plan with the reported sizes and search again."""
+        for _ in range(3):
+            self.run(use_graph)
+            st = self.stats_dict()
+            if st["overflow"] == 0:
+                return
+            needed = (C.c_int64 * 3)()
+            sh = (C.c_int64 * 16)(*self.stats.view(_torch().int64).cpu().tolist())
+            _check(lib().batch_needed(self.handle, sh, needed))
+            self.hits_cap = max(self.hits_cap, int(needed[0]))
+            self.cand_cap = max(self.cand_cap, int(needed[1]))
+            self._create()
+        raise MSearchError(MS_E_CAPACITY, "batch: capacity still exceeded after re-planning")
+
+    def stats_dict(self) -> dict:
+        return _stats_dict(self.stats)
+
+    def results(self):
+        """(list of per-pair hit arrays sorted by (triA, triB), stats dict)."""
+        st = self.stats_dict()
+        nh = min(st["n_hits"], self.hits_cap)
+        hits = np.frombuffer(self.hits[: nh * HIT_DTYPE.itemsize].cpu().numpy().tobytes(), dtype=HIT_DTYPE)
+        off = self.offsets.cpu().numpy()
+        return [hits[off[i]:off[i + 1]] for i in range(len(self.pairs))], st
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def narrow_allpairs(A: Mesh, B: Mesh, hits_cap: int = 1 << 16):

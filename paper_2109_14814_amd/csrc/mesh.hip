@@ -49,7 +49,8 @@ __global__ void __launch_bounds__(MB_BLOCK) k_soa_to_aos(const double *soa, doub
 
 // Per-triangle box (exact min / max per axis); NaN-filled if any vertex
 // coordinate is not finite.  Also accumulates, per block, the longest-edge
-// sum and the count of finite triangles, and the finite-vertex bounds.
+// sum, the counts of finite and non-finite triangles and the bounds of the
+// finite triangles.
 struct Partial {
     double lo[4], hi[4];
     double diam_sum;
@@ -57,7 +58,7 @@ struct Partial {
     long long pad;
 };
 
-__global__ void __launch_bounds__(MB_BLOCK) k_tri_boxes(MeshView m, int64_t nv, double *box, Partial *part)
+__global__ void __launch_bounds__(MB_BLOCK) k_tri_boxes(MeshView m, double *box, Partial *part)
 {
     __shared__ double s_lo[4][MB_BLOCK / WAVE], s_hi[4][MB_BLOCK / WAVE], s_sum[MB_BLOCK / WAVE];
     __shared__ long long s_fin[MB_BLOCK / WAVE], s_bad[MB_BLOCK / WAVE];
@@ -66,16 +67,18 @@ __global__ void __launch_bounds__(MB_BLOCK) k_tri_boxes(MeshView m, int64_t nv, 
     double dsum = 0.0;
     long long nfin = 0, nbad = 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (int64_t t = g0; t < m.n_tris; t += stride) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m.n_tris; t += stride) {
         int32_t i1, i2, i3;
         tri_vertex_ids(m, (int32_t)t, i1, i2, i3);
         d4 p1 = load_d4(m.V + 4 * (int64_t)i1), p2 = load_d4(m.V + 4 * (int64_t)i2), p3 = load_d4(m.V + 4 * (int64_t)i3);
         double a[3][4] = {{p1.x, p1.y, p1.z, p1.w}, {p2.x, p2.y, p2.z, p2.w}, {p3.x, p3.y, p3.z, p3.w}};
         bool fin = true;
+#pragma unroll
         for (int j = 0; j < 3; ++j)
+#pragma unroll
             for (int d = 0; d < 4; ++d) fin = fin && isfinite(a[j][d]);
         double bl[4], bh[4];
+#pragma unroll
         for (int d = 0; d < 4; ++d) {
             double l = a[0][d], h = a[0][d];
             if (a[1][d] < l) l = a[1][d];
@@ -84,6 +87,7 @@ __global__ void __launch_bounds__(MB_BLOCK) k_tri_boxes(MeshView m, int64_t nv, 
             if (a[2][d] > h) h = a[2][d];
             bl[d] = fin ? l : NAN;
             bh[d] = fin ? h : NAN;
+            if (fin) { lo[d] = fmin(lo[d], l); hi[d] = fmax(hi[d], h); }
         }
         double2 *o = reinterpret_cast<double2 *>(box + 8 * t);
         o[0] = make_double2(bl[0], bl[1]);
@@ -92,11 +96,13 @@ __global__ void __launch_bounds__(MB_BLOCK) k_tri_boxes(MeshView m, int64_t nv, 
         o[3] = make_double2(bh[2], bh[3]);
         if (fin) {
             double e = 0.0;
+#pragma unroll
             for (int j = 0; j < 3; ++j) {
                 const double *x = a[j], *y = a[(j + 1) % 3];
-                double s = 0.0;
-                for (int d = 0; d < 4; ++d) s += (x[d] - y[d]) * (x[d] - y[d]);
-                e = fmax(e, s);
+                double sq = 0.0;
+#pragma unroll
+                for (int d = 0; d < 4; ++d) sq += (x[d] - y[d]) * (x[d] - y[d]);
+                e = fmax(e, sq);
             }
             dsum += sqrt(e);
             ++nfin;
@@ -104,15 +110,9 @@ __global__ void __launch_bounds__(MB_BLOCK) k_tri_boxes(MeshView m, int64_t nv, 
             ++nbad;
         }
     }
-    for (int64_t v = g0; v < nv; v += stride) {
-        d4 p = load_d4(m.V + 4 * v);
-        double c[4] = {p.x, p.y, p.z, p.w};
-        bool fin = isfinite(c[0]) && isfinite(c[1]) && isfinite(c[2]) && isfinite(c[3]);
-        if (fin)
-            for (int d = 0; d < 4; ++d) { lo[d] = fmin(lo[d], c[d]); hi[d] = fmax(hi[d], c[d]); }
-    }
     // wave then block reductions
     for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
         for (int d = 0; d < 4; ++d) {
             lo[d] = fmin(lo[d], __shfl_xor(lo[d], o));
             hi[d] = fmax(hi[d], __shfl_xor(hi[d], o));
@@ -137,6 +137,51 @@ __global__ void __launch_bounds__(MB_BLOCK) k_tri_boxes(MeshView m, int64_t nv, 
         for (int i = 0; i < MB_BLOCK / WAVE; ++i) { p.diam_sum += s_sum[i]; p.n_fin_tris += s_fin[i]; p.n_bad_tris += s_bad[i]; }
         part[blockIdx.x] = p;
     }
+}
+
+}  // namespace
+}  // namespace ms
+
+
+namespace ms {
+namespace {
+
+// Queue the box pass of mesh m on stream st (asynchronous).
+int launch_boxes(ms_mesh *m, hipStream_t st)
+{
+    const MeshView &mv = m->view;
+    int64_t g = ceil_div(mv.n_tris > 0 ? mv.n_tris : 1, MB_BLOCK);
+    if (g > MB_GRID) g = MB_GRID;
+    m->n_partials = (int)g;
+    hipLaunchKernelGGL(k_tri_boxes, dim3((unsigned)g), dim3(MB_BLOCK), 0, st, mv, m->box, (Partial *)m->scratch);
+    MS_HIP(hipGetLastError());
+    MS_HIP(hipEventRecord(m->boxes_done, st));
+    m->info_stale = 1;
+    return MS_OK;
+}
+
+// Wait for the last box pass and reduce its per-block partials on the host.
+int reduce_info(ms_mesh *m)
+{
+    if (!m->info_stale) return MS_OK;
+    MS_HIP(hipEventSynchronize(m->boxes_done));
+    std::vector<Partial> hp((size_t)m->n_partials);
+    MS_HIP(hipMemcpy(hp.data(), m->scratch, hp.size() * sizeof(Partial), hipMemcpyDeviceToHost));
+    ms_mesh_info_t &inf = m->info;
+    inf.n_tris = m->view.n_tris;
+    for (int d = 0; d < 4; ++d) { inf.lo[d] = INFINITY; inf.hi[d] = -INFINITY; }
+    double dsum = 0.0;
+    long long nfin = 0, nbad = 0;
+    for (const Partial &p : hp) {
+        for (int d = 0; d < 4; ++d) { inf.lo[d] = fmin(inf.lo[d], p.lo[d]); inf.hi[d] = fmax(inf.hi[d], p.hi[d]); }
+        dsum += p.diam_sum;
+        nfin += p.n_fin_tris;
+        nbad += p.n_bad_tris;
+    }
+    inf.n_nonfinite = nbad;
+    inf.mean_diam = nfin > 0 ? dsum / (double)nfin : 0.0;
+    m->info_stale = 0;
+    return MS_OK;
 }
 
 }  // namespace
@@ -186,8 +231,11 @@ extern "C" int mesh_build(const double *verts_dev, int32_t n_theta_v, int32_t n_
         return cleanup(hip_fail(e, "hipMalloc theta"));
     if ((e = hipMalloc(&m->s_dev, (size_t)(n_s_v > 0 ? n_s_v : 1) * 8)) != hipSuccess)
         return cleanup(hip_fail(e, "hipMalloc s"));
-    if ((e = hipMalloc(&m->scratch, (size_t)(MB_GRID * sizeof(Partial) + 256))) != hipSuccess)
+    if ((e = hipMalloc(&m->scratch, (size_t)(MB_GRID * sizeof(Partial) + MS_COUNT_PARTIALS * 8 + 256))) != hipSuccess)
         return cleanup(hip_fail(e, "hipMalloc scratch"));
+    m->counter = (int64_t *)((char *)m->scratch + MB_GRID * sizeof(Partial));
+    if ((e = hipEventCreateWithFlags(&m->boxes_done, hipEventDisableTiming)) != hipSuccess)
+        return cleanup(hip_fail(e, "hipEventCreate"));
     if (n_theta_v > 0 && (e = hipMemcpyAsync(m->theta_dev, theta_host, (size_t)n_theta_v * 8, hipMemcpyHostToDevice, st)) != hipSuccess)
         return cleanup(hip_fail(e, "copy theta"));
     if (n_s_v > 0 && (e = hipMemcpyAsync(m->s_dev, s_host, (size_t)n_s_v * 8, hipMemcpyHostToDevice, st)) != hipSuccess)
@@ -204,30 +252,9 @@ extern "C" int mesh_build(const double *verts_dev, int32_t n_theta_v, int32_t n_
     mv.periodic = periodic ? 1 : 0;
     mv.n_tris = (int32_t)ntri;
 
-    int64_t work = ntri > nv ? ntri : nv;
-    int64_t g = ceil_div(work > 0 ? work : 1, MB_BLOCK);
-    if (g > MB_GRID) g = MB_GRID;
-    Partial *part = (Partial *)m->scratch;
-    hipLaunchKernelGGL(k_tri_boxes, dim3((unsigned)g), dim3(MB_BLOCK), 0, st, mv, nv, m->box, part);
-    if ((e = hipGetLastError()) != hipSuccess) return cleanup(hip_fail(e, "k_tri_boxes launch"));
-    std::vector<Partial> hp((size_t)g);
-    if ((e = hipMemcpyAsync(hp.data(), part, (size_t)g * sizeof(Partial), hipMemcpyDeviceToHost, st)) != hipSuccess)
-        return cleanup(hip_fail(e, "copy partials"));
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return cleanup(hip_fail(e, "mesh_build sync"));
-
-    ms_mesh_info_t &inf = m->info;
-    inf.n_tris = ntri;
-    for (int d = 0; d < 4; ++d) { inf.lo[d] = INFINITY; inf.hi[d] = -INFINITY; }
-    double dsum = 0.0;
-    long long nfin = 0, nbad = 0;
-    for (int64_t b = 0; b < g; ++b) {
-        for (int d = 0; d < 4; ++d) { inf.lo[d] = fmin(inf.lo[d], hp[b].lo[d]); inf.hi[d] = fmax(inf.hi[d], hp[b].hi[d]); }
-        dsum += hp[b].diam_sum;
-        nfin += hp[b].n_fin_tris;
-        nbad += hp[b].n_bad_tris;
-    }
-    inf.n_nonfinite = nbad;
-    inf.mean_diam = nfin > 0 ? dsum / (double)nfin : 0.0;
+    int rc = launch_boxes(m, st);
+    if (rc) return cleanup(rc);
+    if ((rc = reduce_info(m))) return cleanup(rc);
     *out = m;
     return MS_OK;
 }
@@ -240,13 +267,22 @@ extern "C" int mesh_free(ms_mesh *m)
     if (m->theta_dev) (void)hipFree(m->theta_dev);
     if (m->s_dev) (void)hipFree(m->s_dev);
     if (m->scratch) (void)hipFree(m->scratch);
+    if (m->boxes_done) (void)hipEventDestroy(m->boxes_done);
     delete m;
     return MS_OK;
+}
+
+extern "C" int mesh_update(ms_mesh *m, void *stream)
+{
+    if (!m) return fail(MS_E_ARG, "mesh_update: NULL mesh");
+    return launch_boxes(m, (hipStream_t)stream);
 }
 
 extern "C" int mesh_info(const ms_mesh *m, ms_mesh_info_t *out)
 {
     if (!m || !out) return fail(MS_E_ARG, "mesh_info: NULL argument");
+    int rc = reduce_info(const_cast<ms_mesh *>(m));
+    if (rc) return rc;
     *out = m->info;
     return MS_OK;
 }
@@ -261,6 +297,8 @@ extern "C" int search_default_params(const ms_mesh *A, const ms_mesh *B, double 
         lo[d] = fmin(A->info.lo[d], B->info.lo[d]);
         hi[d] = fmax(A->info.hi[d], B->info.hi[d]);
     }
+    int rc;
+    if ((rc = reduce_info(const_cast<ms_mesh *>(A))) || (rc = reduce_info(const_cast<ms_mesh *>(B)))) return rc;
     int64_t na = A->info.n_tris - A->info.n_nonfinite, nb = B->info.n_tris - B->info.n_nonfinite;
     double diam = (na + nb) > 0 ? (A->info.mean_diam * (double)na + B->info.mean_diam * (double)nb) / (double)(na + nb) : 0.0;
     double edge = kappa * diam;

@@ -150,18 +150,35 @@ inline int bits_for(uint64_t x)   // bits needed to store values 0..x
 
 // -------------------------------------------------- internal sort/scan API
 
-// Radix sort of 64-bit keys on bits [lo_bit, lo_bit + n_bits), stable.
-// n is read from device memory (*n_dev); cap bounds it on the host.  The
-// sorted keys end up in *result (either keys or alt).
-struct SortWs {
-    uint32_t *hist;          // passes * 256
-    uint32_t *status;        // tiles_cap * 256
-    uint32_t *tile_ctr;      // passes
+// LSD radix sort of 64-bit keys on bits [lo_bit, lo_bit + n_bits), stable,
+// with RB-bit digits (RB in 8..10 chosen for the fewest passes).  Before the
+// first pass the caller must have: accumulated the digit histograms of every
+// pass into hist, cleared the tile counters, and cleared the pass-0
+// look-back words of the tiles in use; each pass clears the next pass's
+// words itself.
+constexpr int SORT_TILE_KEYS = 4096;
+
+struct RadixPlan {
+    int lo_bit, n_bits, passes, rb;
+    int64_t cap, tiles_cap;
+    uint32_t *hist;       // passes x 2^rb
+    uint32_t *status;     // passes x tiles_cap x 2^rb
+    uint32_t *tile_ctr;   // passes
 };
-size_t sort_ws_bytes(int64_t cap, int max_passes);
-void sort_ws_carve(void *base, int64_t cap, int max_passes, SortWs &ws);
-int radix_sort_u64(uint64_t *keys, uint64_t *alt, const int64_t *n_dev, int64_t cap, int lo_bit,
-                   int n_bits, const SortWs &ws, hipStream_t st, uint64_t **result);
+
+RadixPlan radix_plan(int lo_bit, int n_bits, int64_t cap);
+size_t radix_ws_bytes(const RadixPlan &p);
+void radix_ws_carve(RadixPlan &p, void *base);
+// Sorted keys end in *result (keys or alt).  In its last pass each block
+// also clears extra[tile * extra_per_tile ...] (a later kernel's words).
+int radix_sort(const RadixPlan &p, uint64_t *keys, uint64_t *alt, const int64_t *n_dev, uint64_t *extra,
+               int extra_per_tile, hipStream_t st, uint64_t **result);
+
+// Sort of distinct 64-bit keys in two kernels: chunks of 4096 sorted in LDS,
+// then every key placed by its rank in the other chunks (cost grows with
+// n^2 / 4096; meant for small n such as hit lists).  n from device memory.
+int sort_unique_small(const uint64_t *in, uint64_t *tmp, uint64_t *out, const int64_t *n_dev, int64_t cap,
+                      int lo_bit, int n_bits, hipStream_t st);   // n = min(*n_dev, cap)
 
 // Exclusive scan of n 32-bit counts into 64-bit offsets; out[n] = total.
 // n from the host; total also added to *total_dev if non-NULL.
@@ -174,7 +191,18 @@ int scan_i64_dev(const int64_t *in, int64_t *out, const int64_t *n_dev, int64_t 
 
 int launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st);
 
+// ------------------------------------------------------------- profiling
+
+// When enabled (search_profile_enable), the search records a HIP event on
+// its stream before every kernel and once at the end; search_profile_read
+// turns consecutive events into per-kernel durations.
+void prof_begin(hipStream_t st);
+void prof_mark(const char *name, hipStream_t st);
+void prof_end(hipStream_t st);
+
 }  // namespace ms
+
+constexpr int MS_COUNT_PARTIALS = 2048;
 
 // The opaque handle of the public ABI.
 struct ms_mesh {
@@ -182,7 +210,11 @@ struct ms_mesh {
     double *owned_V;          // AoS copy for MS_LAYOUT_SOA
     double *box;              // device, 8 doubles per triangle
     double *theta_dev, *s_dev;
-    int64_t *scratch;         // small device scratch (counters)
+    int64_t *scratch;         // small device scratch: per-block partials of the box pass
+    int64_t *counter;         // MS_COUNT_PARTIALS device words (entry counting of workspace queries)
+    hipEvent_t boxes_done;    // recorded after the box pass
+    int info_stale;           // bounds / diameter not reduced since the last box pass
     ms_mesh_info_t info;
     int device;
+    int n_partials;
 };

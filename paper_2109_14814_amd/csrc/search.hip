@@ -1,25 +1,35 @@
-// search.hip -- the mesh-intersection search of Sec. 6.2 on one GPU.
+// search.hip -- the mesh-intersection search of Sec. 6.2 on one GPU, for one
+// mesh pair or a batch of pairs searched together.
 //
-// Pipeline (one HIP stream, counts kept in device memory):
-//   k_mark      per triangle: overlapped cells (Sec. 6.2.1); per-side hashed
-//               occupancy bitmaps
-//   k_count     per triangle: cells also touched by the other mesh (a box that
-//               holds triangles of only one mesh cannot hold a pair, Sec. 6.3)
-//   scan        entry offsets
-//   k_emit      entries key = [cell | side | triangle]
-//   radix sort  groups entries by cell (A's before B's inside a cell)
-//   k_cells     per cell holding both meshes: start, nA, nB
-//   scan        pair-slot offsets (sum of nA * nB)
+// Every kernel reads its sizes from device memory, so one call queues a fixed
+// sequence of kernels with no host round trip (and can be captured in a HIP
+// graph):
+//   k_prepare   clear counters, occupancy flags and look-back words
+//   k_mark      per triangle: overlapped cells of its pair's grid (Sec. 6.2.1),
+//               one occupancy flag per (hashed) cell and side, compact range
+//   k_count     per triangle: cells that the other mesh also touches (a box
+//               with triangles of one mesh only cannot hold a pair)
+//   k_emit      keys [cell | side | triangle] at scanned offsets, digit
+//               histograms for the sort
+//   radix sort  onesweep passes, cells grouped (A's entries before B's)
+//   k_cells     per cell holding both meshes: start, nA, nB, pair; slot
+//               offsets sum(nA * nB) by a look-back scan
 //   k_enum      slot -> (cell, iA, iB); a pair is kept only in its home cell
-//               (cell of the componentwise max of the boxes' lower corners) and
-//               only if the closed boxes overlap (Sec. 6.2.2)
-//   k_narrow    Moller quick test (Sec. 6.2.3), 4x4 solve and inclusion test
+//               (cell of the componentwise max of the boxes' lower corners)
+//               and only if the closed boxes overlap (Sec. 6.2.2)
+//   k_narrow    Moller quick test (Sec. 6.2.3), 4x4 solve and inclusion
 //               (Sec. 6.2.4), hit records
-//   sort        hits by (triA, triB)
+//   sort        hits by (pair, triA, triB)
+// A batch keys its cells by a per-pair cell offset, so entries of different
+// pairs never share a cell.
 #include <math.h>
 #include <string.h>
 
+#include <string>
+#include <vector>
+
 #include "ms_internal.hpp"
+#include "predicate.hpp"
 
 namespace ms {
 
@@ -27,7 +37,17 @@ namespace {
 
 constexpr int BLOCK = 256;
 constexpr int MAX_GRID = 2048;
-constexpr double TWO_PI = 6.283185307179586476925286766559;
+static_assert(MAX_GRID <= MS_COUNT_PARTIALS, "count partials fit the mesh scratch");
+constexpr int KEYS_ITEMS = 2;                         // triangles per thread in k_count / k_emit
+constexpr int KEYS_TILE = BLOCK * KEYS_ITEMS;         // triangles per k_count / k_emit block
+constexpr int CELLS_ITEMS = 16;
+constexpr int CELLS_TILE = BLOCK * CELLS_ITEMS;       // = SORT_TILE_KEYS entries per k_cells block
+constexpr int MAX_PASSES = 7;
+constexpr uint64_t SFLAG_AGG = 1ull << 62;
+constexpr uint64_t SFLAG_PRE = 2ull << 62;
+constexpr uint64_t SVAL_MASK = (1ull << 62) - 1;
+
+static_assert(CELLS_TILE == SORT_TILE_KEYS, "k_cells tiles follow the sort tiles");
 
 inline unsigned grid_for(int64_t n, int64_t cap = MAX_GRID)
 {
@@ -41,28 +61,74 @@ struct KeyLayout {
     uint64_t tmask;
 };
 
-struct PairView {
+// One mesh pair with its grid.  Cells of this pair have global ids
+// cell_base + linear cell; its triangles have global indices tri_off +
+// [0, nA) (A) and tri_off + nA + [0, nB) (B).
+struct PairDesc {
     MeshView A, B;
     GridView g;
-    KeyLayout kl;
-    int32_t nA, nB;      // triangles (entries of B are indexed nA + t in the per-triangle arrays)
-    int32_t bm_log2;     // bitmap bits per side = 2^bm_log2
-    int32_t pad;
+    uint64_t cell_base;
+    int64_t tri_off;
+    int32_t nA, nB;
 };
+
+struct BatchView {
+    PairDesc p0;                 // the pair of a single search
+    const PairDesc *pairs;       // device array of a batch
+    const int64_t *tri_off;      // n_pairs + 1 (batch)
+    const uint64_t *cell_base;   // n_pairs + 1 (batch)
+    int64_t n_tri;
+    int32_t n_pairs;
+    int32_t bm_log2;             // occupancy flags per side: 2^bm_log2 bytes
+    int32_t packable;            // every grid has <= 4096 cells per axis
+    int32_t pb, tbA, tbB;        // bits of the pair, A- and B-triangle fields of hit keys
+    KeyLayout kl;
+};
+
+template <bool ONE>
+MS_D const PairDesc &pair_desc(const BatchView &bv, int p)
+{
+    if constexpr (ONE) return bv.p0;
+    else return bv.pairs[p];
+}
+
+// Last index i in [0, n) with a[i] <= x (a ascending, a[0] <= x).
+template <typename T>
+MS_D int64_t last_le(const T *a, int64_t n, T x)
+{
+    int64_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        int64_t mid = lo + ((hi - lo) >> 1);
+        if (a[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <bool ONE>
+MS_D int pair_of_tri(const BatchView &bv, int64_t gt)
+{
+    if constexpr (ONE) return 0;
+    else return (int)last_le<int64_t>(bv.tri_off, bv.n_pairs, gt);
+}
+
+template <bool ONE>
+MS_D int pair_of_cell(const BatchView &bv, uint64_t gcell)
+{
+    if constexpr (ONE) return 0;
+    else return (int)last_le<uint64_t>(bv.cell_base, bv.n_pairs, gcell);
+}
 
 MS_D uint32_t bm_hash(uint64_t cell, int log2)
 {
     return (uint32_t)((cell * 0x9E3779B97F4A7C15ull) >> (64 - log2));
 }
 
-MS_D bool bm_test(const uint64_t *bm, uint32_t h) { return (bm[h >> 6] >> (h & 63)) & 1ull; }
-
 struct CellRange {
     int64_t lo[4], hi[4];
 };
 
-// Overlapped cell range of a triangle's box, or false when the triangle is
-// flagged non-finite.
+// Overlapped cell range of a triangle's box, or false for a non-finite one.
 MS_D bool tri_cells(const double *box, const GridView &g, CellRange &r)
 {
     const double2 *b = reinterpret_cast<const double2 *>(box);
@@ -82,7 +148,7 @@ MS_D int64_t range_count(const CellRange &r)
     return (r.hi[0] - r.lo[0] + 1) * (r.hi[1] - r.lo[1] + 1) * (r.hi[2] - r.lo[2] + 1) * (r.hi[3] - r.lo[3] + 1);
 }
 
-// Visit every cell of a range in lexicographic order.
+// Visit every cell of a range in lexicographic order (linear cell ids).
 template <typename F>
 MS_D void for_cells(const CellRange &r, const int64_t n[4], F &&f)
 {
@@ -94,101 +160,346 @@ MS_D void for_cells(const CellRange &r, const int64_t n[4], F &&f)
             }
 }
 
-// Triangle gt of the concatenation [A's triangles, B's triangles]: side, local
-// index and box pointer.
-MS_D void tri_of(const PairView &pv, int64_t gt, int &side, int32_t &t, const double *&box)
+// Compact cell range: lo cell per axis in 12 bits (bits 0..47), extent per
+// axis in 4 bits (48..63).  Two values no range can take mark a non-finite
+// triangle and a range too large to pack (recomputed from the box).
+constexpr uint64_t RNG_NONFINITE = ~0ull;
+constexpr uint64_t RNG_FROM_BOX = ~0ull - 1;
+
+MS_D uint64_t pack_range(const CellRange &r, bool packable)
 {
-    side = gt >= pv.nA;
-    t = (int32_t)(side ? gt - pv.nA : gt);
-    box = (side ? pv.B.box : pv.A.box) + 8 * (int64_t)t;
+    if (!packable) return RNG_FROM_BOX;
+    uint64_t v = 0;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        int64_t e = r.hi[d] - r.lo[d];
+        if (e > 15) return RNG_FROM_BOX;
+        v |= (uint64_t)r.lo[d] << (12 * d);
+        v |= (uint64_t)e << (48 + 4 * d);
+    }
+    return v;
+}
+
+MS_D void unpack_range(uint64_t v, CellRange &r)
+{
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        r.lo[d] = (int64_t)((v >> (12 * d)) & 4095);
+        r.hi[d] = r.lo[d] + (int64_t)((v >> (48 + 4 * d)) & 15);
+    }
+}
+
+// Where triangle gt lives: pair, side, local index, box.
+struct TriLoc {
+    int p, side;
+    int32_t t;
+    const double *box;
+};
+
+template <bool ONE>
+MS_D TriLoc locate(const BatchView &bv, int64_t gt)
+{
+    TriLoc L;
+    L.p = pair_of_tri<ONE>(bv, gt);
+    const PairDesc &P = pair_desc<ONE>(bv, L.p);
+    int64_t local = gt - P.tri_off;
+    L.side = local >= P.nA;
+    L.t = (int32_t)(L.side ? local - P.nA : local);
+    L.box = (L.side ? P.B.box : P.A.box) + 8 * (int64_t)L.t;
+    return L;
+}
+
+// Cell range of triangle gt from its compact record (or its box).
+template <bool ONE>
+MS_D bool range_of(const BatchView &bv, const uint64_t *rng, int64_t gt, const TriLoc &L, CellRange &r)
+{
+    uint64_t v = rng[gt];
+    if (v == RNG_NONFINITE) return false;
+    if (v != RNG_FROM_BOX) {
+        unpack_range(v, r);
+        return true;
+    }
+    return tri_cells(L.box, pair_desc<ONE>(bv, L.p).g, r);
+}
+
+// Decoupled look-back over 64-bit status words [flag:2 | value:62] of the
+// tiles before `tile`, run by all 64 lanes of one wave: each round reads 64
+// predecessors at once, finds the nearest inclusive prefix with a ballot and
+// re-reads when a predecessor before it has not published yet.  Returns the
+// exclusive prefix in every lane.
+MS_D uint64_t wave_lookback(const uint64_t *status, int64_t tile)
+{
+    const int lane = lane_id();
+    uint64_t excl = 0;
+    int64_t t = tile - 1;
+    for (;;) {
+        const int64_t idx = t - lane;
+        const uint64_t v = idx >= 0 ? __hip_atomic_load(status + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                    : SFLAG_PRE;
+        const uint64_t fl = v & ~SVAL_MASK;
+        const uint64_t pre = ballot(fl == SFLAG_PRE);
+        const uint64_t zero = ballot(fl == 0);
+        const int k = pre ? __builtin_ctzll(pre) : 63;
+        const uint64_t upto = (2ull << k) - 1;     // lanes 0..k
+        if (zero & upto) continue;
+        excl += wave_sum_u64(lane <= k ? (v & SVAL_MASK) : 0ull);
+        if (pre) return excl;
+        t -= 64;
+    }
+}
+
+// The same over pairs of words (a, b) published together: a predecessor is
+// ready when both words carry the same non-zero flag.
+MS_D void wave_lookback2(const uint64_t *status, int64_t tile, uint64_t &ea, uint64_t &eb)
+{
+    const int lane = lane_id();
+    ea = eb = 0;
+    int64_t t = tile - 1;
+    for (;;) {
+        const int64_t idx = t - lane;
+        uint64_t va = SFLAG_PRE, vb = SFLAG_PRE;
+        if (idx >= 0) {
+            va = __hip_atomic_load(status + 2 * idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            vb = __hip_atomic_load(status + 2 * idx + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const uint64_t fa = va & ~SVAL_MASK, fb = vb & ~SVAL_MASK;
+        const bool ready = fa != 0 && fa == fb;
+        const uint64_t pre = ballot(ready && fa == SFLAG_PRE);
+        const uint64_t notready = ballot(!ready);
+        const int k = pre ? __builtin_ctzll(pre) : 63;
+        const uint64_t upto = (2ull << k) - 1;
+        if (notready & upto) continue;
+        ea += wave_sum_u64(lane <= k ? (va & SVAL_MASK) : 0ull);
+        eb += wave_sum_u64(lane <= k ? (vb & SVAL_MASK) : 0ull);
+        if (pre) return;
+        t -= 64;
+    }
+}
+
+MS_D void publish_u64(uint64_t *w, uint64_t flag, uint64_t v)
+{
+    __hip_atomic_store(w, flag | v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+MS_D T block_sum(T v, T *s_tmp)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    __syncthreads();
+    if (lane_id() == 0) s_tmp[threadIdx.x / WAVE] = v;
+    __syncthreads();
+    T t = 0;
+    for (int i = 0; i < BLOCK / WAVE; ++i) t += s_tmp[i];
+    return t;
+}
+
+// Exclusive scan of one value per thread over the block; *total = sum.
+template <typename T>
+MS_D T block_excl(T v, T *s_tmp, T *total)
+{
+    const int lane = lane_id(), w = threadIdx.x / WAVE;
+    T x = v;
+    for (int o = 1; o < WAVE; o <<= 1) {
+        T y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    __syncthreads();
+    if (lane == WAVE - 1) s_tmp[w] = x;
+    __syncthreads();
+    T add = 0, tot = 0;
+    for (int i = 0; i < BLOCK / WAVE; ++i) {
+        T t = s_tmp[i];
+        if (i < w) add += t;
+        tot += t;
+    }
+    *total = tot;
+    return add + x - v;
 }
 
 // ---------------------------------------------------------------- kernels
 
-__global__ void __launch_bounds__(BLOCK) k_init(search_stats_t *stats)
+struct ClearSpec {
+    search_stats_t *stats;
+    uint64_t *flags;   int64_t flag_words;
+    uint64_t *kstat;   int64_t kstat_words;      // look-back words
+    uint32_t *hist;    int64_t hist_words;       // sort histograms
+    uint32_t *ctrs;    int64_t ctr_words;        // tile counters
+};
+
+__global__ void __launch_bounds__(BLOCK) k_prepare(ClearSpec c)
 {
-    int64_t *s = (int64_t *)stats;
-    if (threadIdx.x < 16) s[threadIdx.x] = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c.stats && g0 < 16) ((int64_t *)c.stats)[g0] = 0;
+    for (int64_t i = g0; i < c.flag_words; i += stride) c.flags[i] = 0;
+    for (int64_t i = g0; i < c.kstat_words; i += stride) c.kstat[i] = 0;
+    for (int64_t i = g0; i < c.hist_words; i += stride) c.hist[i] = 0;
+    for (int64_t i = g0; i < c.ctr_words; i += stride) c.ctrs[i] = 0;
 }
 
-__global__ void __launch_bounds__(BLOCK) k_mark(PairView pv, uint64_t *bm, search_stats_t *stats)
+// Occupancy: one byte per hashed global cell and side, set with plain stores
+// (all writers store the same value).  Stores each triangle's compact cell
+// range and per-block entry / non-finite totals.
+template <bool ONE>
+__global__ void __launch_bounds__(BLOCK) k_mark(BatchView bv, uint8_t *flags, uint64_t *rng,
+                                                unsigned long long *partial)
 {
-    const int64_t ntot = (int64_t)pv.nA + pv.nB;
+    __shared__ unsigned long long s_tmp[BLOCK / WAVE];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     unsigned long long all = 0, bad = 0;
-    const size_t words = (size_t)1 << (pv.bm_log2 - 6);
-    for (int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gt < ntot; gt += stride) {
-        int side; int32_t t; const double *box;
-        tri_of(pv, gt, side, t, box);
+    const size_t side_bytes = (size_t)1 << bv.bm_log2;
+    for (int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gt < bv.n_tri; gt += stride) {
+        TriLoc L = locate<ONE>(bv, gt);
+        const PairDesc &P = pair_desc<ONE>(bv, L.p);
         CellRange r;
-        if (!tri_cells(box, pv.g, r)) { ++bad; continue; }
+        if (!tri_cells(L.box, P.g, r)) {
+            ++bad;
+            rng[gt] = RNG_NONFINITE;
+            continue;
+        }
+        rng[gt] = pack_range(r, bv.packable != 0);
         all += (unsigned long long)range_count(r);
-        uint64_t *mine = bm + (size_t)side * words;
-        for_cells(r, pv.g.n, [&](uint64_t c) {
-            uint32_t h = bm_hash(c, pv.bm_log2);
-            uint64_t bit = 1ull << (h & 63);
-            // bits only go from 0 to 1 during this kernel, so a (possibly
-            // stale) set bit is final and the atomic can be skipped
-            if (!(mine[h >> 6] & bit)) atomicOr((unsigned long long *)&mine[h >> 6], (unsigned long long)bit);
-        });
+        uint8_t *mine = flags + (size_t)L.side * side_bytes;
+        const uint64_t cb = P.cell_base;
+        for_cells(r, P.g.n, [&](uint64_t c) { mine[bm_hash(cb + c, bv.bm_log2)] = 1; });
     }
-    all = wave_sum_u64(all);
-    bad = wave_sum_u64(bad);
-    if (lane_id() == 0) {
-        if (all) atomicAdd((unsigned long long *)&stats->n_entries_all, all);
-        if (bad) atomicAdd((unsigned long long *)&stats->n_nonfinite, bad);
+    all = block_sum(all, s_tmp);
+    bad = block_sum(bad, s_tmp);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = all;
+        partial[2 * blockIdx.x + 1] = bad;
     }
 }
 
-__global__ void __launch_bounds__(BLOCK) k_count(PairView pv, const uint64_t *bm, uint32_t *cnt)
+struct KeysOut {
+    uint64_t *keys;
+    int64_t cap;
+    uint32_t *cnt;            // entries per triangle
+    uint64_t *btot;           // entries per k_count block
+    uint32_t *hist;           // passes x radix digit counts of the sort
+    uint32_t *sort_status0;   // the sort's pass-0 look-back words (radix per tile)
+    int passes, rb, lo_bit;
+    int64_t *n_eff;           // keys to sort (0 on overflow)
+    search_stats_t *stats;
+    const unsigned long long *mark_partial;
+    int n_mark_partial;
+};
+
+// Entries of each triangle (cells the other mesh also occupies) and the
+// total of each block of KEYS_TILE triangles.
+template <bool ONE>
+__global__ void __launch_bounds__(BLOCK) k_count(BatchView bv, const uint8_t *flags, const uint64_t *rng, KeysOut o)
 {
-    const int64_t ntot = (int64_t)pv.nA + pv.nB;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const size_t words = (size_t)1 << (pv.bm_log2 - 6);
-    for (int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gt < ntot; gt += stride) {
-        int side; int32_t t; const double *box;
-        tri_of(pv, gt, side, t, box);
+    __shared__ uint64_t s_tmp[BLOCK / WAVE];
+    const int64_t base = (int64_t)blockIdx.x * KEYS_TILE;
+    const size_t side_bytes = (size_t)1 << bv.bm_log2;
+    uint64_t mine = 0;
+#pragma unroll
+    for (int i = 0; i < KEYS_ITEMS; ++i) {
+        const int64_t gt = base + i * BLOCK + threadIdx.x;
+        if (gt >= bv.n_tri) break;
+        TriLoc L = locate<ONE>(bv, gt);
         CellRange r;
         uint32_t c = 0;
-        if (tri_cells(box, pv.g, r)) {
-            const uint64_t *other = bm + (size_t)(1 - side) * words;
-            for_cells(r, pv.g.n, [&](uint64_t cell) { c += bm_test(other, bm_hash(cell, pv.bm_log2)); });
+        if (range_of<ONE>(bv, rng, gt, L, r)) {
+            const uint8_t *other = flags + (size_t)(1 - L.side) * side_bytes;
+            const uint64_t cb = pair_desc<ONE>(bv, L.p).cell_base;
+            for_cells(r, pair_desc<ONE>(bv, L.p).g.n,
+                      [&](uint64_t cell) { c += other[bm_hash(cb + cell, bv.bm_log2)] != 0; });
         }
-        cnt[gt] = c;
+        o.cnt[gt] = c;
+        mine += c;
     }
+    const uint64_t t = block_sum(mine, s_tmp);
+    if (threadIdx.x == 0) o.btot[blockIdx.x] = t;
 }
 
-// Entries of every triangle at its scanned offset.  When the total exceeds
-// the capacity nothing is written and the overflow flag is raised; the
-// number of keys to sort (n_eff) is then 0.
-__global__ void __launch_bounds__(BLOCK) k_emit(PairView pv, const uint64_t *bm, const int64_t *off, int64_t cap,
-                                                uint64_t *keys, int64_t *n_eff, search_stats_t *stats)
+// Emit the keys [cell | side | triangle] of every triangle: the block's
+// offset is the sum of the totals of the blocks before it (read in
+// parallel), the threads' offsets a block scan.  Also accumulates the digit
+// histograms of the sort, clears the sort's pass-0 look-back words of the
+// tiles the block writes, and (last block) publishes the totals.
+template <bool ONE>
+__global__ void __launch_bounds__(BLOCK) k_emit(BatchView bv, const uint8_t *flags, const uint64_t *rng, KeysOut o)
 {
-    const int64_t ntot = (int64_t)pv.nA + pv.nB;
-    const int64_t E = off[ntot];
-    const bool fits = E <= cap;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        *n_eff = fits ? E : 0;
-        if (!fits) atomicOr((unsigned long long *)&stats->overflow, 1ull);
+    __shared__ uint32_t s_hist[MAX_PASSES * 1024];
+    __shared__ uint64_t s_tmp[BLOCK / WAVE];
+    const int64_t b = blockIdx.x;
+    const int64_t base = b * KEYS_TILE;
+    const size_t side_bytes = (size_t)1 << bv.bm_log2;
+    const int R = 1 << o.rb;
+    for (int i = threadIdx.x; i < o.passes * R; i += BLOCK) s_hist[i] = 0;
+    // block offset: sum of the earlier blocks' totals
+    uint64_t pre = 0;
+    for (int64_t j = threadIdx.x; j < b; j += BLOCK) pre += o.btot[j];
+    const uint64_t blk0 = block_sum(pre, s_tmp);
+    uint32_t cnt[KEYS_ITEMS];
+    uint64_t mine = 0;
+#pragma unroll
+    for (int i = 0; i < KEYS_ITEMS; ++i) {
+        const int64_t gt = base + i * BLOCK + threadIdx.x;
+        cnt[i] = gt < bv.n_tri ? o.cnt[gt] : 0u;
+        mine += cnt[i];
     }
-    if (!fits) return;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const size_t words = (size_t)1 << (pv.bm_log2 - 6);
-    for (int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gt < ntot; gt += stride) {
-        int side; int32_t t; const double *box;
-        tri_of(pv, gt, side, t, box);
+    uint64_t btotal;
+    const uint64_t texcl = block_excl(mine, s_tmp, &btotal);
+    if (b == gridDim.x - 1) {
+        // the last block publishes the totals (mark partials summed by the whole block)
+        unsigned long long all = 0, bad = 0;
+        for (int i = threadIdx.x; i < o.n_mark_partial; i += BLOCK) { all += o.mark_partial[2 * i]; bad += o.mark_partial[2 * i + 1]; }
+        all = block_sum(all, (unsigned long long *)s_tmp);
+        bad = block_sum(bad, (unsigned long long *)s_tmp);
+        if (threadIdx.x == 0) {
+            const int64_t E = (int64_t)(blk0 + btotal);
+            o.stats->n_entries = E;
+            o.stats->n_entries_all = (int64_t)all;
+            o.stats->n_nonfinite = (int64_t)bad;
+            *o.n_eff = E <= o.cap ? E : 0;
+            if (E > o.cap) atomicOr((unsigned long long *)&o.stats->overflow, 1ull);
+        }
+    }
+    if (btotal > 0 && (int64_t)(blk0 + btotal) <= o.cap) {
+        const int64_t t0 = (int64_t)blk0 / SORT_TILE_KEYS, t1 = (int64_t)(blk0 + btotal - 1) / SORT_TILE_KEYS;
+        for (int64_t w = threadIdx.x; w < (t1 - t0 + 1) * R; w += BLOCK) o.sort_status0[t0 * R + w] = 0;
+    }
+    __syncthreads();
+    int64_t pos = (int64_t)(blk0 + texcl);
+#pragma unroll
+    for (int i = 0; i < KEYS_ITEMS; ++i) {
+        if (cnt[i] == 0) continue;
+        const int64_t gt = base + i * BLOCK + threadIdx.x;
+        TriLoc L = locate<ONE>(bv, gt);
         CellRange r;
-        if (!tri_cells(box, pv.g, r)) continue;
-        const uint64_t *other = bm + (size_t)(1 - side) * words;
-        int64_t o = off[gt];
-        const uint64_t low = ((uint64_t)side << pv.kl.tb) | (uint64_t)t;
-        for_cells(r, pv.g.n, [&](uint64_t cell) {
-            if (bm_test(other, bm_hash(cell, pv.bm_log2))) keys[o++] = (cell << pv.kl.cell_shift) | low;
+        range_of<ONE>(bv, rng, gt, L, r);
+        const uint8_t *other = flags + (size_t)(1 - L.side) * side_bytes;
+        const uint64_t cb = pair_desc<ONE>(bv, L.p).cell_base;
+        const uint64_t low = ((uint64_t)L.side << bv.kl.tb) | (uint64_t)L.t;
+        for_cells(r, pair_desc<ONE>(bv, L.p).g.n, [&](uint64_t cell) {
+            const uint64_t gc = cb + cell;
+            if (other[bm_hash(gc, bv.bm_log2)]) {
+                const uint64_t key = (gc << bv.kl.cell_shift) | low;
+                if (pos < o.cap) {
+                    o.keys[pos] = key;
+                    for (int q = 0; q < o.passes; ++q)
+                        atomicAdd(&s_hist[q * R + (int)((key >> (o.lo_bit + o.rb * q)) & (uint64_t)(R - 1))], 1u);
+                }
+                ++pos;
+            }
         });
     }
+    __syncthreads();
+    if (btotal > 0)
+        for (int i = threadIdx.x; i < o.passes * R; i += BLOCK)
+            if (s_hist[i]) atomicAdd(&o.hist[i], s_hist[i]);
 }
 
-// First index in [lo, hi) whose key is >= k (keys sorted ascending).
+struct CellRec {
+    int64_t start;
+    int32_t nA, nB;
+    int32_t pair, pad;
+};
+
+// First index in [lo, hi) whose key is >= k (keys ascending).
 MS_D int64_t lower_bound_u64(const uint64_t *a, int64_t lo, int64_t hi, uint64_t k)
 {
     while (lo < hi) {
@@ -199,52 +510,134 @@ MS_D int64_t lower_bound_u64(const uint64_t *a, int64_t lo, int64_t hi, uint64_t
     return lo;
 }
 
-struct CellRec {
-    int64_t start;
-    int32_t nA, nB;
-};
-
-__global__ void __launch_bounds__(BLOCK) k_cells(const uint64_t *keys, const int64_t *n_dev, KeyLayout kl,
-                                                 CellRec *cells, int64_t *pairs, search_stats_t *stats)
+// The same, galloping from lo (cheap when the answer is close to lo).
+MS_D int64_t gallop_u64(const uint64_t *a, int64_t lo, int64_t hi, uint64_t k)
 {
-    const int64_t n = *n_dev;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t iters = ceil_div(n, stride);
-    for (int64_t it = 0; it < iters; ++it) {
-        int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + it * stride;
-        bool start = false;
-        int64_t nA = 0, nB = 0;
-        if (e < n) {
-            uint64_t k = keys[e];
-            uint64_t cell = k >> kl.cell_shift;
-            start = (e == 0) || ((keys[e - 1] >> kl.cell_shift) != cell);
-            if (start) {
-                uint64_t next = (cell + 1) << kl.cell_shift;
-                int64_t end = lower_bound_u64(keys, e + 1, n, next);
-                int64_t fb = lower_bound_u64(keys, e, end, (cell << kl.cell_shift) | (1ull << kl.tb));
-                nA = fb - e;
-                nB = end - fb;
-                start = nA > 0 && nB > 0;
-            }
-        }
-        int64_t slot = wave_reserve(start, (unsigned long long *)&stats->n_cells);
-        if (start) {
-            cells[slot] = CellRec{e, (int32_t)nA, (int32_t)nB};
-            pairs[slot] = nA * nB;
-        }
+    int64_t step = 1, prev = lo;
+    while (lo < hi && a[lo] < k) {
+        prev = lo + 1;
+        lo += step;
+        step <<= 1;
     }
+    if (lo > hi) lo = hi;
+    return lower_bound_u64(a, prev, lo, k);
 }
 
-// Last index c in [0, n) with pre[c] <= x (pre ascending, pre[0] = 0).
-MS_D int64_t upper_bound_m1(const int64_t *pre, int64_t n, int64_t x)
+struct CellsOut {
+    CellRec *cells;
+    int64_t *pstart;          // n_cells + 1
+    uint64_t *cstat;          // 2 look-back words per tile (count, slots)
+    uint32_t *tile_ctr;
+    search_stats_t *stats;
+};
+
+// Cells holding both meshes, in key order, with their slot offsets: a block
+// per sorted tile; a cell belongs to the tile holding its first entry.
+template <bool ONE>
+__global__ void __launch_bounds__(BLOCK) k_cells(BatchView bv, const uint64_t *keys, const int64_t *n_dev, CellsOut o)
 {
-    int64_t lo = 0, hi = n;   // invariant: pre[lo] <= x < pre[hi] (pre[n] = total)
-    while (hi - lo > 1) {
-        int64_t mid = lo + ((hi - lo) >> 1);
-        if (pre[mid] <= x) lo = mid;
-        else hi = mid;
+    __shared__ uint32_t s_tmp32[BLOCK / WAVE];
+    __shared__ uint64_t s_tmp64[BLOCK / WAVE];
+    __shared__ uint64_t s_cbase, s_pbase;
+    __shared__ uint32_t s_tile;
+    const int64_t n = *n_dev;
+    const int64_t ntiles = (n + CELLS_TILE - 1) / CELLS_TILE;
+    const int sh = bv.kl.cell_shift;
+    if (n == 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            o.stats->n_cells = 0;
+            o.stats->n_slots = 0;
+            o.pstart[0] = 0;
+        }
+        return;
     }
-    return lo;
+    if ((int64_t)blockIdx.x >= ntiles) return;   // no tile for this block: leave the counter alone
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(o.tile_ctr, 1u);
+        __syncthreads();
+        const int64_t tile = s_tile;
+        __syncthreads();
+        if (tile >= ntiles) break;
+        // each thread owns CELLS_ITEMS consecutive entries
+        const int64_t e0 = tile * CELLS_TILE + (int64_t)threadIdx.x * CELLS_ITEMS;
+        int64_t st[CELLS_ITEMS];
+        int32_t na[CELLS_ITEMS], nb[CELLS_ITEMS];
+        uint32_t ccount = 0;
+        uint64_t pcount = 0;
+#pragma unroll
+        for (int i = 0; i < CELLS_ITEMS; ++i) {
+            const int64_t e = e0 + i;
+            st[i] = -1;
+            na[i] = nb[i] = 0;
+            if (e < n) {
+                const uint64_t cell = keys[e] >> sh;
+                if (e == 0 || (keys[e - 1] >> sh) != cell) {
+                    const int64_t end = gallop_u64(keys, e + 1, n, (cell + 1) << sh);
+                    const int64_t fb = gallop_u64(keys, e, end, (cell << sh) | (1ull << bv.kl.tb));
+                    if (fb > e && end > fb) {
+                        st[i] = e;
+                        na[i] = (int32_t)(fb - e);
+                        nb[i] = (int32_t)(end - fb);
+                        ++ccount;
+                        pcount += (uint64_t)(fb - e) * (uint64_t)(end - fb);
+                    }
+                }
+            }
+        }
+        uint32_t ctot;
+        uint64_t ptot;
+        const uint32_t cex = block_excl(ccount, s_tmp32, &ctot);
+        const uint64_t pex = block_excl(pcount, s_tmp64, &ptot);
+        if (threadIdx.x < WAVE) {
+            uint64_t cb = 0, pb = 0;
+            uint64_t *sc = o.cstat + 2 * tile, *sp = sc + 1;
+            if (tile == 0) {
+                if (threadIdx.x == 0) {
+                    publish_u64(sp, SFLAG_PRE, ptot);
+                    publish_u64(sc, SFLAG_PRE, ctot);
+                }
+            } else {
+                if (threadIdx.x == 0) {
+                    publish_u64(sp, SFLAG_AGG, ptot);
+                    publish_u64(sc, SFLAG_AGG, ctot);
+                }
+                wave_lookback2(o.cstat, tile, cb, pb);
+                if (threadIdx.x == 0) {
+                    publish_u64(sp, SFLAG_PRE, pb + ptot);
+                    publish_u64(sc, SFLAG_PRE, cb + ctot);
+                }
+            }
+            if (threadIdx.x == 0) {
+                s_cbase = cb;
+                s_pbase = pb;
+                if (tile == ntiles - 1) {
+                    const int64_t nc = (int64_t)(cb + ctot), P = (int64_t)(pb + ptot);
+                    o.stats->n_cells = nc;
+                    o.stats->n_slots = P;
+                    o.pstart[nc] = P;
+                }
+            }
+        }
+        __syncthreads();
+        int64_t ci = (int64_t)s_cbase + cex;
+        uint64_t ps = s_pbase + pex;
+#pragma unroll
+        for (int i = 0; i < CELLS_ITEMS; ++i) {
+            if (st[i] < 0) continue;
+            const uint64_t gcell = keys[st[i]] >> sh;
+            CellRec cr;
+            cr.start = st[i];
+            cr.nA = na[i];
+            cr.nB = nb[i];
+            cr.pair = pair_of_cell<ONE>(bv, gcell);
+            cr.pad = 0;
+            o.cells[ci] = cr;
+            o.pstart[ci] = (int64_t)ps;
+            ps += (uint64_t)na[i] * (uint64_t)nb[i];
+            ++ci;
+        }
+        __syncthreads();
+    }
 }
 
 struct Box { double lo[4], hi[4]; };
@@ -256,183 +649,81 @@ MS_D Box load_box(const double *p)
     return Box{{l01.x, l01.y, l23.x, l23.y}, {h01.x, h01.y, h23.x, h23.y}};
 }
 
-__global__ void __launch_bounds__(BLOCK) k_enum(PairView pv, const uint64_t *keys, const CellRec *cells,
-                                                const int64_t *pstart, search_stats_t *stats, int64_t *cand,
-                                                int64_t cand_cap)
+MS_D int64_t uniform_i64(int64_t v)
 {
+    return ((int64_t)__builtin_amdgcn_readfirstlane((int)(v >> 32)) << 32) |
+           (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+}
+
+constexpr int ENUM_LDS_CELLS = 4096;
+
+template <bool ONE>
+__global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *keys, const CellRec *cells,
+                                                const int64_t *pstart_g, search_stats_t *stats, uint64_t *cand,
+                                                int32_t *cand_pair, int64_t cand_cap)
+{
+    __shared__ int64_t s_pstart[ENUM_LDS_CELLS + 1];
     const int64_t ncells = stats->n_cells;
-    const int64_t P = pstart[ncells];
+    const int64_t P = stats->n_slots;
+    // small cell lists are searched in LDS, large ones in global memory
+    const bool in_lds = ncells <= ENUM_LDS_CELLS;
+    if (in_lds) {
+        for (int64_t i = threadIdx.x; i <= ncells; i += BLOCK) s_pstart[i] = pstart_g[i];
+        __syncthreads();
+    }
+    const int64_t *pstart = in_lds ? s_pstart : pstart_g;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t iters = ceil_div(P, stride);
+    const int lane = lane_id();
     for (int64_t it = 0; it < iters; ++it) {
-        int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + it * stride;
+        const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + it * stride;
+        // one scalar binary search per wave for its first slot; each lane
+        // then steps over the (few) cells its own slot passes
+        const int64_t s0 = uniform_i64(slot - lane);
         bool keep = false;
         uint64_t packed = 0;
-        if (slot < P) {
-            int64_t c = upper_bound_m1(pstart, ncells, slot);
-            CellRec cr = cells[c];
-            int64_t local = slot - pstart[c];
-            int64_t iA = local % cr.nA, iB = local / cr.nA;
-            uint64_t kA = keys[cr.start + iA];
-            uint64_t kB = keys[cr.start + cr.nA + iB];
-            uint64_t cell = kA >> pv.kl.cell_shift;
-            int32_t ta = (int32_t)(kA & pv.kl.tmask), tb = (int32_t)(kB & pv.kl.tmask);
-            Box a = load_box(pv.A.box + 8 * (int64_t)ta);
-            Box b = load_box(pv.B.box + 8 * (int64_t)tb);
-            bool ov = true;
-            int64_t h[4];
+        int32_t pr = 0;
+        if (s0 < P) {
+            const int64_t c0 = last_le<int64_t>(pstart, ncells, s0);
+            if (slot < P) {
+                int64_t c = c0;
+                while (pstart[c + 1] <= slot) ++c;
+                const CellRec cr = cells[c];
+                const uint64_t local = (uint64_t)(slot - pstart[c]);
+                uint64_t iB;
+                if (local < 0xffffffffull) iB = (uint32_t)local / (uint32_t)cr.nA;
+                else iB = local / (uint64_t)cr.nA;
+                const uint64_t iA = local - iB * (uint64_t)cr.nA;
+                const uint64_t kA = keys[cr.start + (int64_t)iA];
+                const uint64_t kB = keys[cr.start + cr.nA + (int64_t)iB];
+                const PairDesc &Pd = pair_desc<ONE>(bv, cr.pair);
+                const uint64_t cell = (kA >> bv.kl.cell_shift) - Pd.cell_base;
+                const int32_t ta = (int32_t)(kA & bv.kl.tmask), tb = (int32_t)(kB & bv.kl.tmask);
+                const Box a = load_box(Pd.A.box + 8 * (int64_t)ta);
+                const Box b = load_box(Pd.B.box + 8 * (int64_t)tb);
+                bool ov = true;
+                int64_t h[4];
 #pragma unroll
-            for (int d = 0; d < 4; ++d) {
-                ov = ov && (a.lo[d] <= b.hi[d]) && (b.lo[d] <= a.hi[d]);
-                double m = a.lo[d] > b.lo[d] ? a.lo[d] : b.lo[d];
-                h[d] = cell_of(m, pv.g.wlo[d], pv.g.inv, pv.g.n[d]);
+                for (int d = 0; d < 4; ++d) {
+                    ov = ov && (a.lo[d] <= b.hi[d]) && (b.lo[d] <= a.hi[d]);
+                    double m = a.lo[d] > b.lo[d] ? a.lo[d] : b.lo[d];
+                    h[d] = cell_of(m, Pd.g.wlo[d], Pd.g.inv, Pd.g.n[d]);
+                }
+                keep = ov && ((uint64_t)cell_linear(h, Pd.g.n) == cell);
+                packed = ((uint64_t)(uint32_t)ta << 32) | (uint32_t)tb;
+                pr = cr.pair;
             }
-            keep = ov && ((uint64_t)cell_linear(h, pv.g.n) == cell);
-            packed = ((uint64_t)(uint32_t)ta << 32) | (uint32_t)tb;
         }
-        int64_t idx = wave_reserve(keep, (unsigned long long *)&stats->n_cand);
+        const int64_t idx = wave_reserve(keep, (unsigned long long *)&stats->n_cand);
         if (keep) {
-            if (idx < cand_cap) cand[idx] = (int64_t)packed;
-            else atomicOr((unsigned long long *)&stats->overflow, 2ull);
-        }
-    }
-}
-
-// ------------------------------------------------------- the pair predicate
-
-struct Tri { double p[3][4]; };
-
-MS_D Tri load_tri(const MeshView &m, int32_t t)
-{
-    int32_t i1, i2, i3;
-    tri_vertex_ids(m, t, i1, i2, i3);
-    d4 a = load_d4(m.V + 4 * (int64_t)i1), b = load_d4(m.V + 4 * (int64_t)i2), c = load_d4(m.V + 4 * (int64_t)i3);
-    return Tri{{{a.x, a.y, a.z, a.w}, {b.x, b.y, b.z, b.w}, {c.x, c.y, c.z, c.w}}};
-}
-
-// Same-side test of Sec. 6.2.3 on the (x, y, p_x) projection: with
-// n = (p1 - p2) x (p3 - p2), reject when n.(q_j - p2) is > 0 for all j or < 0
-// for all j.
-MS_D bool same_side(const Tri &P, const Tri &Q)
-{
-    const double *p1 = P.p[0], *p2 = P.p[1], *p3 = P.p[2];
-    double e1x = p1[0] - p2[0], e1y = p1[1] - p2[1], e1z = p1[2] - p2[2];
-    double e2x = p3[0] - p2[0], e2y = p3[1] - p2[1], e2z = p3[2] - p2[2];
-    double nx = e1y * e2z - e1z * e2y;
-    double ny = e1z * e2x - e1x * e2z;
-    double nz = e1x * e2y - e1y * e2x;
-    double f[3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const double *q = Q.p[j];
-        f[j] = (nx * (q[0] - p2[0]) + ny * (q[1] - p2[1])) + nz * (q[2] - p2[2]);
-    }
-    bool pos = (f[0] > 0.0) && (f[1] > 0.0) && (f[2] > 0.0);
-    bool neg = (f[0] < 0.0) && (f[1] < 0.0) && (f[2] < 0.0);
-    return pos || neg;
-}
-
-// 4x4 system of Sec. 6.2.4, Gaussian elimination with partial pivoting
-// (first row of largest magnitude; exact zero pivot = singular).  Row swaps
-// are selects on fully unrolled loops, so the matrix stays in registers.
-MS_D bool solve_pair(const Tri &P, const Tri &Q, double z[4])
-{
-    double M[4][4], r[4];
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        M[d][0] = P.p[0][d] - P.p[1][d];
-        M[d][1] = P.p[2][d] - P.p[1][d];
-        M[d][2] = Q.p[1][d] - Q.p[0][d];
-        M[d][3] = Q.p[1][d] - Q.p[2][d];
-        r[d] = Q.p[1][d] - P.p[1][d];
-    }
-    bool ok = true;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        int piv = k;
-        double best = fabs(M[k][k]);
-#pragma unroll
-        for (int i = k + 1; i < 4; ++i) {
-            double a = fabs(M[i][k]);
-            if (a > best) { best = a; piv = i; }
-        }
-#pragma unroll
-        for (int i = k + 1; i < 4; ++i) {
-            bool s = piv == i;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                double x = M[k][j], y = M[i][j];
-                M[k][j] = s ? y : x;
-                M[i][j] = s ? x : y;
+            if (idx < cand_cap) {
+                cand[idx] = packed;
+                cand_pair[idx] = pr;
+            } else {
+                atomicOr((unsigned long long *)&stats->overflow, 2ull);
             }
-            double x = r[k], y = r[i];
-            r[k] = s ? y : x;
-            r[i] = s ? x : y;
-        }
-        ok = ok && (M[k][k] != 0.0);
-#pragma unroll
-        for (int i = k + 1; i < 4; ++i) {
-            double l = M[i][k] / M[k][k];
-#pragma unroll
-            for (int j = k + 1; j < 4; ++j) M[i][j] = M[i][j] - l * M[k][j];
-            r[i] = r[i] - l * r[k];
         }
     }
-#pragma unroll
-    for (int k = 3; k >= 0; --k) {
-        double acc = 0.0;
-#pragma unroll
-        for (int j = k + 1; j < 4; ++j) acc = acc + M[k][j] * z[j];
-        z[k] = (r[k] - acc) / M[k][k];
-    }
-    return ok;
-}
-
-// (theta, s) estimate on triangle t from its barycentrics (Sec. 6.2.4).
-MS_D void tri_param(const MeshView &m, int32_t t, double u, double v, double &th, double &s)
-{
-    int32_t q = t >> 1, h = t & 1;
-    int32_t k = q / m.nq, i = q - k * m.nq;
-    double th0 = m.theta[i];
-    double th1 = (i + 1 < m.n_theta_v) ? m.theta[i + 1] : m.theta[0] + TWO_PI;
-    double s0 = m.s[k], s1 = m.s[k + 1];
-    if (h == 0) {
-        th = (1.0 - u) * th0 + u * th1;
-        s = (1.0 - v) * s0 + v * s1;
-    } else {
-        th = u * th0 + (1.0 - u) * th1;
-        s = v * s0 + (1.0 - v) * s1;
-    }
-    if (m.periodic && th >= TWO_PI) th = th - TWO_PI;
-}
-
-enum { PS_AABB = 0, PS_MOLLER = 1, PS_DEGEN = 2, PS_OUTSIDE = 3, PS_HIT = 4 };
-
-// The full pair test without early exits: every stage is evaluated and the
-// status is decided at the end (box, Moller, singular, inclusion).
-MS_D int pair_status(const Tri &P, const Tri &Q, bool box_ok, double z[4])
-{
-    bool sep = same_side(P, Q) || same_side(Q, P);
-    bool ok = solve_pair(P, Q, z);
-    double uv = z[0] + z[1], ab = z[2] + z[3];
-    bool in = (z[0] >= 0.0) && (z[1] >= 0.0) && (z[2] >= 0.0) && (z[3] >= 0.0) && (uv <= 1.0) && (ab <= 1.0);
-    return !box_ok ? PS_AABB : sep ? PS_MOLLER : !ok ? PS_DEGEN : !in ? PS_OUTSIDE : PS_HIT;
-}
-
-MS_D void make_hit(const PairView &pv, const MeshView &A, const MeshView &B, int32_t ta, int32_t tb, const Tri &P,
-                   const double z[4], hit_t &h)
-{
-    double u = z[0], v = z[1], a = z[2], b = z[3];
-    h.triA = ta; h.triB = tb; h.flags = 0; h.pad = 0;
-    h.u = u; h.v = v; h.a = a; h.b = b;
-#pragma unroll
-    for (int d = 0; d < 4; ++d) h.X[d] = (P.p[1][d] + u * (P.p[0][d] - P.p[1][d])) + v * (P.p[2][d] - P.p[1][d]);
-    tri_param(A, ta, u, v, h.thA, h.sA);
-    tri_param(B, tb, a, b, h.thB, h.sB);
-    double mg = u;
-    mg = fmin(mg, v); mg = fmin(mg, a); mg = fmin(mg, b);
-    mg = fmin(mg, 1.0 - (u + v)); mg = fmin(mg, 1.0 - (a + b));
-    h.margin = mg;
 }
 
 MS_D void wave_count(bool p, int64_t *ctr)
@@ -455,8 +746,9 @@ MS_D void emit_hit(bool hit, const hit_t &h, uint64_t key, hit_t *hits, uint64_t
     }
 }
 
-__global__ void __launch_bounds__(BLOCK) k_narrow(PairView pv, const int64_t *cand, int64_t cand_cap,
-                                                  hit_t *hits, uint64_t *hkeys, int64_t hits_cap, int tbB,
+template <bool ONE>
+__global__ void __launch_bounds__(BLOCK) k_narrow(BatchView bv, const uint64_t *cand, const int32_t *cand_pair,
+                                                  int64_t cand_cap, hit_t *hits, uint64_t *hkeys, int64_t hits_cap,
                                                   search_stats_t *stats)
 {
     int64_t n = stats->n_cand;
@@ -464,215 +756,439 @@ __global__ void __launch_bounds__(BLOCK) k_narrow(PairView pv, const int64_t *ca
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t iters = ceil_div(n, stride);
     for (int64_t it = 0; it < iters; ++it) {
-        int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + it * stride;
+        const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + it * stride;
         int st = PS_AABB;
-        int32_t ta = 0, tb = 0;
+        int32_t ta = 0, tb = 0, p = 0;
         double z[4] = {0, 0, 0, 0};
-        Tri P;
+        Tri Pt;
         if (c < n) {
-            uint64_t pk = (uint64_t)cand[c];
+            const uint64_t pk = cand[c];
             ta = (int32_t)(pk >> 32);
             tb = (int32_t)(pk & 0xffffffffu);
-            P = load_tri(pv.A, ta);
-            Tri Q = load_tri(pv.B, tb);
-            bool sep = same_side(P, Q) || same_side(Q, P);
-            if (sep) {
+            p = ONE ? 0 : cand_pair[c];
+            const PairDesc &Pd = pair_desc<ONE>(bv, p);
+            Pt = load_tri(Pd.A, ta);
+            const Tri Q = load_tri(Pd.B, tb);
+            if (same_side(Pt, Q) || same_side(Q, Pt)) {
                 st = PS_MOLLER;
             } else {
-                bool ok = solve_pair(P, Q, z);
-                double uv = z[0] + z[1], ab = z[2] + z[3];
-                bool in = (z[0] >= 0.0) && (z[1] >= 0.0) && (z[2] >= 0.0) && (z[3] >= 0.0) && (uv <= 1.0) && (ab <= 1.0);
-                st = !ok ? PS_DEGEN : !in ? PS_OUTSIDE : PS_HIT;
+                bool ok = solve_pair(Pt, Q, z);
+                st = !ok ? PS_DEGEN : !inside(z) ? PS_OUTSIDE : PS_HIT;
             }
         }
         wave_count(st == PS_MOLLER, &stats->n_moller);
         wave_count(st == PS_DEGEN, &stats->n_degenerate);
         wave_count(st == PS_OUTSIDE, &stats->n_outside);
         hit_t h;
-        if (st == PS_HIT) make_hit(pv, pv.A, pv.B, ta, tb, P, z, h);
-        emit_hit(st == PS_HIT, h, ((uint64_t)ta << tbB) | (uint64_t)tb, hits, hkeys, hits_cap, stats);
+        uint64_t key = 0;
+        if (st == PS_HIT) {
+            const PairDesc &Pd = pair_desc<ONE>(bv, p);
+            make_hit(Pd.A, Pd.B, ta, tb, (uint32_t)p, Pt, z, h);
+            key = ((uint64_t)p << (bv.tbA + bv.tbB)) | ((uint64_t)(uint32_t)ta << bv.tbB) | (uint32_t)tb;
+        }
+        emit_hit(st == PS_HIT, h, key, hits, hkeys, hits_cap, stats);
     }
+}
+
+__global__ void __launch_bounds__(BLOCK) k_hits_place(const hit_t *tmp, const uint64_t *sorted, const int64_t *n_dev,
+                                                      int64_t cap, int tbA, int tbB, hit_t *out)
+{
+    const int64_t n = *n_dev < cap ? *n_dev : cap;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const hit_t &h = tmp[i];
+        const uint64_t key = ((uint64_t)h.flags << (tbA + tbB)) | ((uint64_t)(uint32_t)h.triA << tbB) | (uint32_t)h.triB;
+        out[lower_bound_u64(sorted, 0, n, key)] = h;
+    }
+}
+
+// Per-pair hit offsets of a batch from the sorted hit keys.
+__global__ void __launch_bounds__(BLOCK) k_pair_offsets(const uint64_t *sorted, const int64_t *n_dev, int64_t cap,
+                                                        int n_pairs, int shift, int64_t *offs)
+{
+    const int64_t n = *n_dev < cap ? *n_dev : cap;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p <= n_pairs; p += gridDim.x * blockDim.x)
+        offs[p] = p == n_pairs ? n : lower_bound_u64(sorted, 0, n, (uint64_t)p << shift);
 }
 
 // All pairs, tiled: each thread holds one triangle of A, tiles of B are
 // staged in LDS; every stage of the test runs on every pair.
 constexpr int AP_TILE = 128;
 
-__global__ void __launch_bounds__(BLOCK) k_allpairs(PairView pv, hit_t *hits, int64_t hits_cap,
-                                                    search_stats_t *stats)
+__global__ void __launch_bounds__(BLOCK) k_allpairs(PairDesc pd, hit_t *hits, int64_t hits_cap, search_stats_t *stats)
 {
     __shared__ double s_tri[AP_TILE][12];
     __shared__ double s_box[AP_TILE][8];
-    const int64_t a_tiles = ceil_div(pv.nA, BLOCK);
-    const int64_t b_tiles = ceil_div(pv.nB, AP_TILE);
+    const int64_t a_tiles = ceil_div(pd.nA, BLOCK);
+    const int64_t b_tiles = ceil_div(pd.nB, AP_TILE);
     const int64_t n_work = a_tiles * b_tiles;
     for (int64_t w = blockIdx.x; w < n_work; w += gridDim.x) {
         const int64_t at = w % a_tiles, bt = w / a_tiles;
         const int32_t ta = (int32_t)(at * BLOCK + threadIdx.x);
-        const bool a_ok = ta < pv.nA;
-        Tri P = a_ok ? load_tri(pv.A, ta) : Tri{};
-        Box ba = a_ok ? load_box(pv.A.box + 8 * (int64_t)ta) : Box{};
-        bool a_fin = a_ok && (ba.lo[0] == ba.lo[0]);
+        const bool a_ok = ta < pd.nA;
+        Tri P = a_ok ? load_tri(pd.A, ta) : Tri{};
+        Box ba = a_ok ? load_box(pd.A.box + 8 * (int64_t)ta) : Box{};
+        const bool a_fin = a_ok && (ba.lo[0] == ba.lo[0]);
         const int32_t tb0 = (int32_t)(bt * AP_TILE);
         __syncthreads();
         if (threadIdx.x < AP_TILE) {
             int32_t tb = tb0 + threadIdx.x;
-            if (tb < pv.nB) {
-                Tri Q = load_tri(pv.B, tb);
-                Box bb = load_box(pv.B.box + 8 * (int64_t)tb);
+            if (tb < pd.nB) {
+                Tri Q = load_tri(pd.B, tb);
+                Box bb = load_box(pd.B.box + 8 * (int64_t)tb);
                 for (int j = 0; j < 3; ++j)
                     for (int d = 0; d < 4; ++d) s_tri[threadIdx.x][4 * j + d] = Q.p[j][d];
                 for (int d = 0; d < 4; ++d) { s_box[threadIdx.x][d] = bb.lo[d]; s_box[threadIdx.x][4 + d] = bb.hi[d]; }
             }
         }
         __syncthreads();
-        const int nb = (int)((pv.nB - tb0) < AP_TILE ? (pv.nB - tb0) : AP_TILE);
+        const int nb = (int)((pd.nB - tb0) < AP_TILE ? (pd.nB - tb0) : AP_TILE);
         for (int j = 0; j < nb; ++j) {
             Tri Q;
 #pragma unroll
             for (int v = 0; v < 3; ++v)
 #pragma unroll
                 for (int d = 0; d < 4; ++d) Q.p[v][d] = s_tri[j][4 * v + d];
-            bool b_fin = s_box[j][0] == s_box[j][0];
+            const bool b_fin = s_box[j][0] == s_box[j][0];
             bool box = true;
 #pragma unroll
             for (int d = 0; d < 4; ++d) box = box && (ba.lo[d] <= s_box[j][4 + d]) && (s_box[j][d] <= ba.hi[d]);
             double z[4];
-            int st = pair_status(P, Q, box, z);
-            bool live = a_fin && b_fin;
+            int st = pair_status_forced(P, Q, box, z);
+            const bool live = a_fin && b_fin;
             if (!live) st = PS_AABB;
             wave_count(live && st != PS_AABB, &stats->n_cand);
             wave_count(st == PS_MOLLER, &stats->n_moller);
             wave_count(st == PS_DEGEN, &stats->n_degenerate);
             wave_count(st == PS_OUTSIDE, &stats->n_outside);
             hit_t h;
-            if (st == PS_HIT) make_hit(pv, pv.A, pv.B, ta, tb0 + j, P, z, h);
+            if (st == PS_HIT) make_hit(pd.A, pd.B, ta, tb0 + j, 0u, P, z, h);
             emit_hit(st == PS_HIT, h, 0, hits, nullptr, hits_cap, stats);
         }
     }
 }
 
-__global__ void k_min_i64(const int64_t *a, int64_t cap, int64_t *out)
-{
-    int64_t v = *a;
-    *out = v < cap ? v : cap;
-}
+__global__ void k_copy_i64(const int64_t *a, int64_t *out) { *out = *a; }
 
-__global__ void __launch_bounds__(BLOCK) k_hits_place(const hit_t *tmp, const uint64_t *sorted, const int64_t *n_dev,
-                                                      int tbB, hit_t *out)
+// Entry count of one pair's grid (workspace sizing): per-block partials.
+__global__ void __launch_bounds__(BLOCK) k_count_all(PairDesc pd, unsigned long long *partial)
 {
-    const int64_t n = *n_dev;
+    __shared__ unsigned long long s_tmp[BLOCK / WAVE];
+    const int64_t ntot = (int64_t)pd.nA + pd.nB;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const hit_t &h = tmp[i];
-        uint64_t key = ((uint64_t)(uint32_t)h.triA << tbB) | (uint32_t)h.triB;
-        int64_t pos = lower_bound_u64(sorted, 0, n, key);
-        out[pos] = h;
+    unsigned long long all = 0;
+    for (int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gt < ntot; gt += stride) {
+        const bool side = gt >= pd.nA;
+        const int64_t t = side ? gt - pd.nA : gt;
+        CellRange r;
+        if (tri_cells((side ? pd.B.box : pd.A.box) + 8 * t, pd.g, r)) all += (unsigned long long)range_count(r);
     }
+    all = block_sum(all, s_tmp);
+    if (threadIdx.x == 0) partial[blockIdx.x] = all;
 }
 
 // ------------------------------------------------------------- host side
 
-struct Plan {
-    int64_t nA, nB, ntot;
-    int tb, tbA, tbB;
+struct Geometry {
+    int64_t n_pairs, n_tri, max_nA, max_nB;
+    int tb, tbA, tbB, pb;
     int cell_bits;
     int bm_log2;
+    int packable;
+    uint64_t total_cells;
+};
+
+struct Layout {
     int64_t ent_cap, cand_cap, hits_cap;
-    // byte offsets into the workspace
-    size_t o_bm, o_cnt, o_off, o_keys, o_alt, o_sort, o_scan, o_cells, o_pairs, o_pstart, o_cand, o_htmp,
-        o_hkeys, o_halt, o_hsort, o_misc, total;
+    RadixPlan rp;
+    size_t o_flags, o_part, o_rng, o_cnt, o_btot, o_keys, o_alt, o_sort, o_cstat, o_ctrs, o_cells, o_pstart, o_cand,
+        o_cpair, o_htmp, o_hkeys, o_halt, o_misc, o_desc, o_toff, o_cbase, total;
+    int64_t n_kblocks, cell_cap;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-int key_layout(const ms_mesh *A, const ms_mesh *B, const search_params_t *p, Plan &pl)
+int pair_cells(const search_params_t *p, uint64_t &cells)
 {
-    pl.nA = A->info.n_tris;
-    pl.nB = B->info.n_tris;
-    pl.ntot = pl.nA + pl.nB;
-    int64_t mx = pl.nA > pl.nB ? pl.nA : pl.nB;
-    pl.tb = bits_for(mx > 0 ? (uint64_t)(mx - 1) : 0);
-    if (pl.tb == 0) pl.tb = 1;
-    pl.tbA = bits_for(pl.nA > 0 ? (uint64_t)(pl.nA - 1) : 0);
-    pl.tbB = bits_for(pl.nB > 0 ? (uint64_t)(pl.nB - 1) : 0);
-    if (pl.tbB == 0) pl.tbB = 1;
-    // total cells, with overflow detection
-    unsigned __int128 cells = 1;
+    unsigned __int128 c = 1;
     for (int d = 0; d < 4; ++d) {
         if (p->n_cells[d] < 1) return fail(MS_E_ARG, "search: n_cells must be >= 1");
-        cells *= (unsigned __int128)p->n_cells[d];
-        if (cells > ((unsigned __int128)1 << 64)) return fail(MS_E_KEYBITS, "search: grid has more than 2^64 cells");
+        c *= (unsigned __int128)p->n_cells[d];
+        if (c > ((unsigned __int128)1 << 62)) return fail(MS_E_KEYBITS, "search: grid has more than 2^62 cells");
     }
-    pl.cell_bits = bits_for((uint64_t)(cells - 1));
-    if (pl.cell_bits + 1 + pl.tb > 63)
-        return fail(MS_E_KEYBITS, "search: cell index + side + triangle needs more than 63 key bits; coarsen the grid");
     if (!(p->inv_edge > 0.0) || !isfinite(p->inv_edge)) return fail(MS_E_ARG, "search: inv_edge must be > 0 and finite");
     for (int d = 0; d < 4; ++d)
         if (!isfinite(p->world_lo[d])) return fail(MS_E_ARG, "search: world_lo must be finite");
-    int lg = bits_for((uint64_t)(pl.ntot > 0 ? pl.ntot : 1)) + 4;
-    pl.bm_log2 = lg < 12 ? 12 : (lg > 26 ? 26 : lg);
+    cells = (uint64_t)c;
     return MS_OK;
 }
 
-void layout_ws(Plan &pl)
+int geometry(int64_t n_pairs, const ms_mesh *const *A, const ms_mesh *const *B, const search_params_t *prm,
+             Geometry &G)
+{
+    memset(&G, 0, sizeof G);
+    G.n_pairs = n_pairs;
+    G.packable = 1;
+    unsigned __int128 total = 0;
+    for (int64_t i = 0; i < n_pairs; ++i) {
+        if (!A[i] || !B[i]) return fail(MS_E_ARG, "search: NULL mesh");
+        uint64_t c = 0;
+        int rc = pair_cells(&prm[i], c);
+        if (rc) return rc;
+        total += c;
+        G.n_tri += (int64_t)A[i]->view.n_tris + B[i]->view.n_tris;
+        if (A[i]->view.n_tris > G.max_nA) G.max_nA = A[i]->view.n_tris;
+        if (B[i]->view.n_tris > G.max_nB) G.max_nB = B[i]->view.n_tris;
+        for (int d = 0; d < 4; ++d)
+            if (prm[i].n_cells[d] > 4096) G.packable = 0;
+    }
+    if (total > ((unsigned __int128)1 << 62)) return fail(MS_E_KEYBITS, "search: the grids have more than 2^62 cells");
+    G.total_cells = (uint64_t)total;
+    int64_t mx = G.max_nA > G.max_nB ? G.max_nA : G.max_nB;
+    G.tb = bits_for(mx > 0 ? (uint64_t)(mx - 1) : 0);
+    if (G.tb == 0) G.tb = 1;
+    G.tbA = bits_for(G.max_nA > 0 ? (uint64_t)(G.max_nA - 1) : 0);
+    G.tbB = bits_for(G.max_nB > 0 ? (uint64_t)(G.max_nB - 1) : 0);
+    if (G.tbB == 0) G.tbB = 1;
+    G.pb = bits_for(n_pairs > 1 ? (uint64_t)(n_pairs - 1) : 0);
+    G.cell_bits = bits_for(G.total_cells > 0 ? G.total_cells - 1 : 0);
+    if (G.cell_bits + 1 + G.tb > 63)
+        return fail(MS_E_KEYBITS, "search: cell index + side + triangle needs more than 63 key bits; coarsen the grid");
+    if (G.pb + G.tbA + G.tbB > 64) return fail(MS_E_KEYBITS, "search: pair + triangle indices exceed 64 bits");
+    int lg = bits_for((uint64_t)(G.n_tri > 0 ? G.n_tri : 1)) + 3;
+    G.bm_log2 = lg < 12 ? 12 : (lg > 23 ? 23 : lg);
+    return MS_OK;
+}
+
+void layout(const Geometry &G, Layout &L)
 {
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
-    int passes = (pl.cell_bits + 1 + 7) / 8;
-    int hpasses = (pl.tbA + pl.tbB + 7) / 8;
-    int max_passes = passes > hpasses ? passes : hpasses;
-    if (max_passes < 1) max_passes = 1;
-    int64_t cell_cap = pl.ent_cap / 2 + 1;
-    pl.o_bm = take(((size_t)2 << pl.bm_log2) / 8);
-    pl.o_cnt = take((size_t)(pl.ntot + 1) * 4);
-    pl.o_off = take((size_t)(pl.ntot + 1) * 8);
-    pl.o_keys = take((size_t)(pl.ent_cap + 1) * 8);
-    pl.o_alt = take((size_t)(pl.ent_cap + 1) * 8);
-    pl.o_sort = take(sort_ws_bytes(pl.ent_cap > pl.hits_cap ? pl.ent_cap : pl.hits_cap, max_passes));
-    pl.o_scan = take(scan_ws_bytes());
-    pl.o_cells = take((size_t)cell_cap * sizeof(CellRec));
-    pl.o_pairs = take((size_t)cell_cap * 8);
-    pl.o_pstart = take((size_t)(cell_cap + 1) * 8);
-    pl.o_cand = take((size_t)(pl.cand_cap > 0 ? pl.cand_cap : 1) * 8);
-    pl.o_htmp = take((size_t)(pl.hits_cap > 0 ? pl.hits_cap : 1) * sizeof(hit_t));
-    pl.o_hkeys = take((size_t)(pl.hits_cap + 1) * 8);
-    pl.o_halt = take((size_t)(pl.hits_cap + 1) * 8);
-    pl.o_hsort = pl.o_sort;   // the hit sort reuses the entry sort's scratch (the entry sort is done by then)
-    pl.o_misc = take(64);
-    pl.total = o;
+    L.rp = radix_plan(G.tb, G.cell_bits + 1, L.ent_cap);
+    L.n_kblocks = ceil_div(G.n_tri > 0 ? G.n_tri : 1, KEYS_TILE);
+    L.cell_cap = L.ent_cap / 2 + 1;
+    const int64_t tiles = L.rp.tiles_cap;
+    L.o_flags = take((size_t)2 << G.bm_log2);
+    L.o_part = take((size_t)MAX_GRID * 16);
+    L.o_rng = take((size_t)(G.n_tri + 1) * 8);
+    L.o_cnt = take((size_t)(G.n_tri + 1) * 4);
+    L.o_btot = take((size_t)L.n_kblocks * 8);
+    L.o_keys = take((size_t)(L.ent_cap + 1) * 8);
+    L.o_alt = take((size_t)(L.ent_cap + 1) * 8);
+    L.o_sort = take(radix_ws_bytes(L.rp));
+    L.o_cstat = take((size_t)tiles * 16);
+    L.o_ctrs = take(64);
+    L.o_cells = take((size_t)L.cell_cap * sizeof(CellRec));
+    L.o_pstart = take((size_t)(L.cell_cap + 1) * 8);
+    L.o_cand = take((size_t)(L.cand_cap > 0 ? L.cand_cap : 1) * 8);
+    L.o_cpair = take((size_t)(L.cand_cap > 0 ? L.cand_cap : 1) * 4);
+    L.o_htmp = take((size_t)(L.hits_cap > 0 ? L.hits_cap : 1) * sizeof(hit_t));
+    L.o_hkeys = take((size_t)(L.hits_cap + 1) * 8);
+    L.o_halt = take((size_t)(L.hits_cap + 1) * 8);
+    L.o_misc = take(64);
+    L.o_desc = take((size_t)(G.n_pairs > 1 ? G.n_pairs : 1) * sizeof(PairDesc));
+    L.o_toff = take((size_t)(G.n_pairs + 1) * 8);
+    L.o_cbase = take((size_t)(G.n_pairs + 1) * 8);
+    L.total = o;
 }
 
-__global__ void __launch_bounds__(BLOCK) k_count_all(PairView pv, unsigned long long *total)
+// Largest entry capacity whose layout fits ws_bytes (other capacities fixed).
+bool fit_entries(const Geometry &G, Layout &L, size_t ws_bytes)
 {
-    const int64_t ntot = (int64_t)pv.nA + pv.nB;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    unsigned long long all = 0;
-    for (int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gt < ntot; gt += stride) {
-        int side; int32_t t; const double *box;
-        tri_of(pv, gt, side, t, box);
-        CellRange r;
-        if (tri_cells(box, pv.g, r)) all += (unsigned long long)range_count(r);
+    L.ent_cap = 0;
+    layout(G, L);
+    if (L.total > ws_bytes) return false;
+    int64_t lo = 0, hi = (int64_t)(ws_bytes / 16) + 1;
+    while (hi - lo > 1) {
+        int64_t mid = lo + (hi - lo) / 2;
+        Layout t = L;
+        t.ent_cap = mid;
+        layout(G, t);
+        if (t.total <= ws_bytes) lo = mid; else hi = mid;
     }
-    all = wave_sum_u64(all);
-    if (lane_id() == 0 && all) atomicAdd(total, all);
+    L.ent_cap = lo < ((int64_t)1 << 30) - 2 ? lo : ((int64_t)1 << 30) - 2;
+    layout(G, L);
+    return true;
 }
 
-PairView make_pair_view(const ms_mesh *A, const ms_mesh *B, const search_params_t *p, const Plan &pl)
+PairDesc make_desc(const ms_mesh *A, const ms_mesh *B, const search_params_t *p, uint64_t cell_base, int64_t tri_off)
 {
-    PairView pv;
-    memset(&pv, 0, sizeof pv);
-    pv.A = A->view;
-    pv.B = B->view;
-    for (int d = 0; d < 4; ++d) { pv.g.wlo[d] = p->world_lo[d]; pv.g.n[d] = p->n_cells[d]; }
-    pv.g.inv = p->inv_edge;
-    pv.kl.tb = pl.tb;
-    pv.kl.cell_shift = pl.tb + 1;
-    pv.kl.tmask = (1ull << pl.tb) - 1;
-    pv.nA = (int32_t)pl.nA;
-    pv.nB = (int32_t)pl.nB;
-    pv.bm_log2 = pl.bm_log2;
-    return pv;
+    PairDesc d;
+    memset(&d, 0, sizeof d);
+    d.A = A->view;
+    d.B = B->view;
+    for (int k = 0; k < 4; ++k) { d.g.wlo[k] = p->world_lo[k]; d.g.n[k] = p->n_cells[k]; }
+    d.g.inv = p->inv_edge;
+    d.cell_base = cell_base;
+    d.tri_off = tri_off;
+    d.nA = A->view.n_tris;
+    d.nB = B->view.n_tris;
+    return d;
+}
+
+BatchView make_view(const Geometry &G, const PairDesc &p0, char *ws, const Layout &L)
+{
+    BatchView bv;
+    memset(&bv, 0, sizeof bv);
+    bv.p0 = p0;
+    bv.pairs = (const PairDesc *)(ws + L.o_desc);
+    bv.tri_off = (const int64_t *)(ws + L.o_toff);
+    bv.cell_base = (const uint64_t *)(ws + L.o_cbase);
+    bv.n_tri = G.n_tri;
+    bv.n_pairs = (int32_t)G.n_pairs;
+    bv.bm_log2 = G.bm_log2;
+    bv.packable = G.packable;
+    bv.pb = G.pb;
+    bv.tbA = G.tbA;
+    bv.tbB = G.tbB;
+    bv.kl.tb = G.tb;
+    bv.kl.cell_shift = G.tb + 1;
+    bv.kl.tmask = (1ull << G.tb) - 1;
+    return bv;
+}
+
+// Queue the whole pipeline (no host synchronisation).
+template <bool ONE>
+int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, hit_t *hits_dev, int64_t hits_cap,
+            search_stats_t *stats, uint64_t *cand_user, int64_t cand_cap, int64_t *pair_offs, hipStream_t st)
+{
+    int rc;
+    uint8_t *flags = (uint8_t *)(ws + L.o_flags);
+    unsigned long long *mpart = (unsigned long long *)(ws + L.o_part);
+    uint64_t *rng = (uint64_t *)(ws + L.o_rng);
+    uint32_t *cnt = (uint32_t *)(ws + L.o_cnt);
+    uint64_t *btot = (uint64_t *)(ws + L.o_btot);
+    uint64_t *keys = (uint64_t *)(ws + L.o_keys);
+    uint64_t *alt = (uint64_t *)(ws + L.o_alt);
+    uint64_t *cstat = (uint64_t *)(ws + L.o_cstat);
+    uint32_t *ctrs = (uint32_t *)(ws + L.o_ctrs);     // [0]: k_cells tile counter
+    CellRec *cells = (CellRec *)(ws + L.o_cells);
+    int64_t *pstart = (int64_t *)(ws + L.o_pstart);
+    uint64_t *cand = cand_user ? cand_user : (uint64_t *)(ws + L.o_cand);
+    int32_t *cpair = (int32_t *)(ws + L.o_cpair);
+    hit_t *htmp = (hit_t *)(ws + L.o_htmp);
+    uint64_t *hkeys = (uint64_t *)(ws + L.o_hkeys);
+    uint64_t *halt = (uint64_t *)(ws + L.o_halt);
+    int64_t *misc = (int64_t *)(ws + L.o_misc);       // [0] keys to sort
+    RadixPlan rp = L.rp;
+    radix_ws_carve(rp, ws + L.o_sort);
+    const int R = 1 << rp.rb;
+
+    prof_begin(st);
+    // 1. clear: counters, flags, sort histograms and tile counters, k_cells
+    //    counter (and, with no sort pass, k_cells' words)
+    ClearSpec cs;
+    cs.stats = stats;
+    cs.flags = (uint64_t *)flags;
+    cs.flag_words = (int64_t)(((size_t)2 << G.bm_log2) / 8);
+    cs.kstat = nullptr;
+    cs.kstat_words = 0;
+    cs.hist = rp.hist;
+    cs.hist_words = (int64_t)rp.passes * R;
+    cs.ctrs = rp.tile_ctr;
+    cs.ctr_words = rp.passes;
+    prof_mark("k_prepare", st);
+    hipLaunchKernelGGL(k_prepare, dim3(grid_for(cs.flag_words, 1024)), dim3(BLOCK), 0, st, cs);
+    ClearSpec cs2;
+    memset(&cs2, 0, sizeof cs2);
+    cs2.ctrs = ctrs;
+    cs2.ctr_words = 16;
+    if (rp.passes == 0) {
+        cs2.kstat = cstat;
+        cs2.kstat_words = 2 * rp.tiles_cap;
+    }
+    hipLaunchKernelGGL(k_prepare, dim3(grid_for(cs2.kstat_words + 16, 256)), dim3(BLOCK), 0, st, cs2);
+    const unsigned g_tri = grid_for(G.n_tri);
+    prof_mark("k_mark", st);
+    hipLaunchKernelGGL(k_mark<ONE>, dim3(g_tri), dim3(BLOCK), 0, st, bv, flags, rng, mpart);
+    KeysOut ko;
+    ko.keys = keys;
+    ko.cap = L.ent_cap;
+    ko.cnt = cnt;
+    ko.btot = btot;
+    ko.hist = rp.hist;
+    ko.sort_status0 = rp.status;
+    ko.passes = rp.passes;
+    ko.rb = rp.rb;
+    ko.lo_bit = rp.lo_bit;
+    ko.n_eff = misc;
+    ko.stats = stats;
+    ko.mark_partial = mpart;
+    ko.n_mark_partial = (int)g_tri;
+    prof_mark("k_count", st);
+    hipLaunchKernelGGL(k_count<ONE>, dim3((unsigned)L.n_kblocks), dim3(BLOCK), 0, st, bv, flags, rng, ko);
+    prof_mark("k_emit", st);
+    hipLaunchKernelGGL(k_emit<ONE>, dim3((unsigned)L.n_kblocks), dim3(BLOCK), 0, st, bv, flags, rng, ko);
+    MS_HIP(hipGetLastError());
+    uint64_t *sorted = keys;
+    if ((rc = radix_sort(rp, keys, alt, misc, cstat, 2, st, &sorted))) return rc;
+    CellsOut co;
+    co.cells = cells;
+    co.pstart = pstart;
+    co.cstat = cstat;
+    co.tile_ctr = ctrs;
+    co.stats = stats;
+    prof_mark("k_cells", st);
+    {
+        int64_t g = rp.tiles_cap < 1024 ? rp.tiles_cap : 1024;
+        hipLaunchKernelGGL(k_cells<ONE>, dim3((unsigned)g), dim3(BLOCK), 0, st, bv, sorted, misc, co);
+    }
+    prof_mark("k_enum", st);
+    hipLaunchKernelGGL(k_enum<ONE>, dim3(MAX_GRID), dim3(BLOCK), 0, st, bv, sorted, cells, pstart, stats, cand, cpair,
+                       cand_cap);
+    prof_mark("k_narrow", st);
+    hipLaunchKernelGGL(k_narrow<ONE>, dim3(MAX_GRID), dim3(BLOCK), 0, st, bv, cand, cpair, cand_cap, htmp, hkeys,
+                       hits_cap, stats);
+    MS_HIP(hipGetLastError());
+    if (hits_cap > 0) {
+        if ((rc = sort_unique_small(hkeys, halt, hkeys, &stats->n_hits, hits_cap, 0, G.pb + G.tbA + G.tbB, st))) return rc;
+        prof_mark("k_hits_place", st);
+        hipLaunchKernelGGL(k_hits_place, dim3(grid_for(hits_cap, 256)), dim3(BLOCK), 0, st, htmp, hkeys, &stats->n_hits,
+                           hits_cap, G.tbA, G.tbB, hits_dev);
+        if (pair_offs)
+            hipLaunchKernelGGL(k_pair_offsets, dim3(grid_for(G.n_pairs + 1, 64)), dim3(BLOCK), 0, st, hkeys,
+                               &stats->n_hits, hits_cap, (int)G.n_pairs, G.tbA + G.tbB, pair_offs);
+        MS_HIP(hipGetLastError());
+    }
+    prof_end(st);
+    return MS_OK;
+}
+
+int check_status(const search_stats_t &hs, const Geometry &G, const Layout &L, int64_t hits_cap, int64_t cand_cap,
+                 bool want_cand, int64_t *needed)
+{
+    if (!hs.overflow) return MS_OK;
+    if (needed) {
+        needed[0] = hs.n_hits;
+        needed[1] = hs.n_cand;
+        Layout t = L;
+        t.ent_cap = hs.n_entries;
+        t.hits_cap = hs.n_hits > hits_cap ? hs.n_hits : hits_cap;
+        t.cand_cap = want_cand ? 0 : (hs.n_cand > cand_cap ? hs.n_cand : cand_cap);
+        layout(G, t);
+        needed[2] = (int64_t)t.total;
+    }
+    if (hs.overflow & 1) return fail(MS_E_WORKSPACE, "search: entries exceed the workspace");
+    return fail(MS_E_CAPACITY, "search: candidate or hit capacity exceeded");
+}
+
+// Entries of all pairs before filtering (workspace sizing); synchronises.
+int count_entries(int64_t n_pairs, const ms_mesh *const *A, const ms_mesh *const *B, const search_params_t *prm,
+                  unsigned long long *dev_partial, hipStream_t st, int64_t &total)
+{
+    total = 0;
+    std::vector<unsigned long long> host(MAX_GRID);
+    for (int64_t i = 0; i < n_pairs; ++i) {
+        PairDesc pd = make_desc(A[i], B[i], &prm[i], 0, 0);
+        const int64_t nt = (int64_t)pd.nA + pd.nB;
+        const unsigned g = grid_for(nt);
+        hipLaunchKernelGGL(k_count_all, dim3(g), dim3(BLOCK), 0, st, pd, dev_partial);
+        MS_HIP(hipGetLastError());
+        MS_HIP(hipMemcpyAsync(host.data(), dev_partial, (size_t)g * 8, hipMemcpyDeviceToHost, st));
+        MS_HIP(hipStreamSynchronize(st));
+        for (unsigned b = 0; b < g; ++b) total += (int64_t)host[b];
+    }
+    return MS_OK;
 }
 
 }  // namespace
@@ -680,29 +1196,25 @@ PairView make_pair_view(const ms_mesh *A, const ms_mesh *B, const search_params_
 
 using namespace ms;
 
+// ------------------------------------------------------------ single pair
+
 extern "C" int search_workspace_size(const ms_mesh *A, const ms_mesh *B, const search_params_t *params,
                                      int64_t cand_cap, int64_t hits_cap, void *stream, size_t *bytes)
 {
     if (!A || !B || !params || !bytes) return fail(MS_E_ARG, "search_workspace_size: NULL argument");
     if (cand_cap < 0 || hits_cap < 0) return fail(MS_E_ARG, "search_workspace_size: negative capacity");
-    Plan pl;
-    memset(&pl, 0, sizeof pl);
-    int rc = key_layout(A, B, params, pl);
+    Geometry G;
+    int rc = geometry(1, &A, &B, params, G);
     if (rc) return rc;
-    hipStream_t st = (hipStream_t)stream;
-    PairView pv = make_pair_view(A, B, params, pl);
-    unsigned long long *ctr = (unsigned long long *)(A->scratch);
-    if ((rc = launch_fill_u64((uint64_t *)ctr, 0, 1, st))) return rc;
-    hipLaunchKernelGGL(k_count_all, dim3(grid_for(pl.ntot)), dim3(BLOCK), 0, st, pv, ctr);
-    MS_HIP(hipGetLastError());
-    unsigned long long E = 0;
-    MS_HIP(hipMemcpyAsync(&E, ctr, 8, hipMemcpyDeviceToHost, st));
-    MS_HIP(hipStreamSynchronize(st));
-    pl.ent_cap = (int64_t)E;
-    pl.cand_cap = cand_cap;
-    pl.hits_cap = hits_cap;
-    layout_ws(pl);
-    *bytes = pl.total;
+    int64_t E = 0;
+    if ((rc = count_entries(1, &A, &B, params, (unsigned long long *)A->counter, (hipStream_t)stream, E))) return rc;
+    Layout L;
+    memset(&L, 0, sizeof L);
+    L.ent_cap = E;
+    L.cand_cap = cand_cap;
+    L.hits_cap = hits_cap;
+    layout(G, L);
+    *bytes = L.total;
     return MS_OK;
 }
 
@@ -715,109 +1227,36 @@ extern "C" int search_intersections(const ms_mesh *A, const ms_mesh *B, const se
     if (hits_cap > 0 && !hits_dev) return fail(MS_E_ARG, "search_intersections: hits_dev is NULL");
     const bool want_cand = (params->flags & MS_SEARCH_CANDIDATES) != 0;
     if (want_cand && cand_cap > 0 && !cand_dev) return fail(MS_E_ARG, "search_intersections: cand_dev is NULL");
-    if ((params->flags & MS_SEARCH_STRICT) && (A->info.n_nonfinite || B->info.n_nonfinite))
-        return fail(MS_E_NONFINITE, "search_intersections: non-finite triangles with MS_SEARCH_STRICT");
-    Plan pl;
-    memset(&pl, 0, sizeof pl);
-    int rc = key_layout(A, B, params, pl);
+    if (params->flags & MS_SEARCH_STRICT) {
+        ms_mesh_info_t ia, ib;
+        int r0 = mesh_info(A, &ia);
+        if (r0) return r0;
+        if ((r0 = mesh_info(B, &ib))) return r0;
+        if (ia.n_nonfinite || ib.n_nonfinite)
+            return fail(MS_E_NONFINITE, "search_intersections: non-finite triangles with MS_SEARCH_STRICT");
+    }
+    Geometry G;
+    int rc = geometry(1, &A, &B, params, G);
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
-
-    // Largest entry capacity that fits the workspace for these capacities.
-    pl.cand_cap = want_cand ? 0 : cand_cap;
-    pl.hits_cap = hits_cap;
-    pl.ent_cap = 0;
-    layout_ws(pl);
-    if (pl.total > ws_bytes) {
-        if (needed) { needed[0] = hits_cap; needed[1] = cand_cap; needed[2] = (int64_t)pl.total; }
+    Layout L;
+    memset(&L, 0, sizeof L);
+    L.cand_cap = want_cand ? 0 : cand_cap;
+    L.hits_cap = hits_cap;
+    if (!fit_entries(G, L, ws_bytes)) {
+        if (needed) { needed[0] = hits_cap; needed[1] = cand_cap; needed[2] = (int64_t)L.total; }
         return fail(MS_E_WORKSPACE, "search_intersections: workspace smaller than the fixed part");
     }
-    {
-        // each entry costs 16 B of keys + 8 B cells/pairs + look-back words; grow ent_cap to fit
-        int64_t lo = 0, hi = (int64_t)(ws_bytes / 16) + 1;
-        while (hi - lo > 1) {
-            int64_t mid = lo + (hi - lo) / 2;
-            Plan t = pl;
-            t.ent_cap = mid;
-            layout_ws(t);
-            if (t.total <= ws_bytes) lo = mid; else hi = mid;
-        }
-        pl.ent_cap = lo;
-        if (pl.ent_cap > ((int64_t)1 << 30) - 2) pl.ent_cap = ((int64_t)1 << 30) - 2;
-        layout_ws(pl);
-    }
     char *ws = (char *)ws_dev;
-    uint64_t *bm = (uint64_t *)(ws + pl.o_bm);
-    uint32_t *cnt = (uint32_t *)(ws + pl.o_cnt);
-    int64_t *off = (int64_t *)(ws + pl.o_off);
-    uint64_t *keys = (uint64_t *)(ws + pl.o_keys);
-    uint64_t *alt = (uint64_t *)(ws + pl.o_alt);
-    int max_passes = (pl.cell_bits + 1 + 7) / 8;
-    int hpasses = (pl.tbA + pl.tbB + 7) / 8;
-    if (hpasses > max_passes) max_passes = hpasses;
-    if (max_passes < 1) max_passes = 1;
-    SortWs sws;
-    sort_ws_carve(ws + pl.o_sort, pl.ent_cap > pl.hits_cap ? pl.ent_cap : pl.hits_cap, max_passes, sws);
-    void *scan_ws = ws + pl.o_scan;
-    CellRec *cells = (CellRec *)(ws + pl.o_cells);
-    int64_t *pairs = (int64_t *)(ws + pl.o_pairs);
-    int64_t *pstart = (int64_t *)(ws + pl.o_pstart);
-    int64_t *cand = want_cand ? cand_dev : (int64_t *)(ws + pl.o_cand);
-    int64_t ccap = cand_cap;
-    hit_t *htmp = (hit_t *)(ws + pl.o_htmp);
-    uint64_t *hkeys = (uint64_t *)(ws + pl.o_hkeys);
-    uint64_t *halt = (uint64_t *)(ws + pl.o_halt);
-    int64_t *misc = (int64_t *)(ws + pl.o_misc);   // [0] n_eff entries, [1] n_eff hits
-    int64_t cell_cap = pl.ent_cap / 2 + 1;
-
-    PairView pv = make_pair_view(A, B, params, pl);
-    hipLaunchKernelGGL(k_init, dim3(1), dim3(BLOCK), 0, st, stats_dev);
-    if ((rc = launch_fill_u64(bm, 0, (int64_t)(((size_t)2 << pl.bm_log2) / 64), st))) return rc;
-    hipLaunchKernelGGL(k_mark, dim3(grid_for(pl.ntot)), dim3(BLOCK), 0, st, pv, bm, stats_dev);
-    hipLaunchKernelGGL(k_count, dim3(grid_for(pl.ntot)), dim3(BLOCK), 0, st, pv, bm, cnt);
-    MS_HIP(hipGetLastError());
-    if ((rc = scan_u32_to_i64(cnt, off, pl.ntot, &stats_dev->n_entries, scan_ws, st))) return rc;
-    hipLaunchKernelGGL(k_emit, dim3(grid_for(pl.ntot)), dim3(BLOCK), 0, st, pv, bm, off, pl.ent_cap, keys, misc,
-                       stats_dev);
-    MS_HIP(hipGetLastError());
-    uint64_t *sorted = keys;
-    if ((rc = radix_sort_u64(keys, alt, misc, pl.ent_cap, pl.tb, pl.cell_bits + 1, sws, st, &sorted))) return rc;
-    hipLaunchKernelGGL(k_cells, dim3(grid_for(pl.ent_cap)), dim3(BLOCK), 0, st, sorted, misc, pv.kl, cells, pairs,
-                       stats_dev);
-    MS_HIP(hipGetLastError());
-    if ((rc = scan_i64_dev(pairs, pstart, &stats_dev->n_cells, cell_cap, &stats_dev->n_slots, scan_ws, st))) return rc;
-    hipLaunchKernelGGL(k_enum, dim3(MAX_GRID), dim3(BLOCK), 0, st, pv, sorted, cells, pstart, stats_dev, cand, ccap);
-    MS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_narrow, dim3(MAX_GRID), dim3(BLOCK), 0, st, pv, cand, ccap, htmp, hkeys, hits_cap, pl.tbB,
-                       stats_dev);
-    hipLaunchKernelGGL(k_min_i64, dim3(1), dim3(1), 0, st, &stats_dev->n_hits, hits_cap, misc + 1);
-    MS_HIP(hipGetLastError());
-    uint64_t *hsorted = hkeys;
-    if (hits_cap > 0) {
-        if ((rc = radix_sort_u64(hkeys, halt, misc + 1, hits_cap, 0, pl.tbA + pl.tbB, sws, st, &hsorted))) return rc;
-        hipLaunchKernelGGL(k_hits_place, dim3(grid_for(hits_cap, 256)), dim3(BLOCK), 0, st, htmp, hsorted, misc + 1,
-                           pl.tbB, hits_dev);
-        MS_HIP(hipGetLastError());
-    }
-    // status: read the counters back
+    const PairDesc p0 = make_desc(A, B, params, 0, 0);
+    const BatchView bv = make_view(G, p0, ws, L);
+    if ((rc = enqueue<true>(G, L, bv, ws, hits_dev, hits_cap, stats_dev, want_cand ? (uint64_t *)cand_dev : nullptr,
+                            cand_cap, nullptr, st)))
+        return rc;
     search_stats_t hs;
     MS_HIP(hipMemcpyAsync(&hs, stats_dev, sizeof hs, hipMemcpyDeviceToHost, st));
     MS_HIP(hipStreamSynchronize(st));
-    if (hs.overflow) {
-        if (needed) {
-            needed[0] = hs.n_hits;
-            needed[1] = hs.n_cand;
-            Plan t = pl;
-            t.ent_cap = hs.n_entries;
-            t.hits_cap = hs.n_hits > hits_cap ? hs.n_hits : hits_cap;
-            t.cand_cap = want_cand ? 0 : (hs.n_cand > cand_cap ? hs.n_cand : cand_cap);
-            layout_ws(t);
-            needed[2] = (int64_t)t.total;
-        }
-        if (hs.overflow & 1) return fail(MS_E_WORKSPACE, "search_intersections: entries exceed the workspace");
-        return fail(MS_E_CAPACITY, "search_intersections: candidate or hit capacity exceeded");
-    }
-    return MS_OK;
+    return check_status(hs, G, L, hits_cap, cand_cap, want_cand, needed);
 }
 
 extern "C" int narrow_allpairs(const ms_mesh *A, const ms_mesh *B, hit_t *hits_dev, int64_t hits_cap,
@@ -826,23 +1265,276 @@ extern "C" int narrow_allpairs(const ms_mesh *A, const ms_mesh *B, hit_t *hits_d
     if (!A || !B || !n_hits_dev || !stats_dev) return fail(MS_E_ARG, "narrow_allpairs: NULL argument");
     if (hits_cap < 0 || (hits_cap > 0 && !hits_dev)) return fail(MS_E_ARG, "narrow_allpairs: bad hits buffer");
     hipStream_t st = (hipStream_t)stream;
-    Plan pl;
-    memset(&pl, 0, sizeof pl);
-    pl.nA = A->info.n_tris;
-    pl.nB = B->info.n_tris;
-    PairView pv;
-    memset(&pv, 0, sizeof pv);
-    pv.A = A->view;
-    pv.B = B->view;
-    pv.nA = (int32_t)pl.nA;
-    pv.nB = (int32_t)pl.nB;
-    hipLaunchKernelGGL(k_init, dim3(1), dim3(BLOCK), 0, st, stats_dev);
-    int64_t work = ceil_div(pl.nA, BLOCK) * ceil_div(pl.nB, AP_TILE);
+    search_params_t p;
+    memset(&p, 0, sizeof p);
+    p.inv_edge = 1.0;
+    for (int d = 0; d < 4; ++d) p.n_cells[d] = 1;
+    PairDesc pd = make_desc(A, B, &p, 0, 0);
+    ClearSpec cs;
+    memset(&cs, 0, sizeof cs);
+    cs.stats = stats_dev;
+    hipLaunchKernelGGL(k_prepare, dim3(1), dim3(64), 0, st, cs);
+    int64_t work = ceil_div(pd.nA, BLOCK) * ceil_div(pd.nB, AP_TILE);
     if (work > 0) {
         int64_t g = work < 8192 ? work : 8192;
-        hipLaunchKernelGGL(k_allpairs, dim3((unsigned)g), dim3(BLOCK), 0, st, pv, hits_dev, hits_cap, stats_dev);
+        hipLaunchKernelGGL(k_allpairs, dim3((unsigned)g), dim3(BLOCK), 0, st, pd, hits_dev, hits_cap, stats_dev);
     }
-    hipLaunchKernelGGL(k_min_i64, dim3(1), dim3(1), 0, st, &stats_dev->n_hits, (int64_t)INT64_MAX, n_hits_dev);
+    hipLaunchKernelGGL(k_copy_i64, dim3(1), dim3(1), 0, st, &stats_dev->n_hits, n_hits_dev);
     MS_HIP(hipGetLastError());
+    return MS_OK;
+}
+
+// ------------------------------------------------------------------ batch
+
+struct ms_batch {
+    ms::Geometry G;
+    std::vector<ms::PairDesc> desc;
+    std::vector<int64_t> tri_off;
+    std::vector<uint64_t> cell_base;
+    int64_t ent_all;             // entries before filtering (workspace sizing)
+    int64_t hits_cap, cand_cap;
+    // captured graph and the buffers it was captured with; capture runs on a
+    // stream of the batch's own (the caller's may be the legacy default
+    // stream, which cannot be captured); the graph is launched on the
+    // caller's stream
+    hipStream_t cap_stream;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    void *g_ws;
+    size_t g_ws_bytes;
+    void *g_hits, *g_offs, *g_stats;
+    int64_t g_hits_cap;
+};
+
+namespace ms {
+namespace {
+
+int batch_upload(ms_batch *b, char *ws, const Layout &L, hipStream_t st)
+{
+    const int64_t np = b->G.n_pairs;
+    MS_HIP(hipMemcpyAsync(ws + L.o_desc, b->desc.data(), (size_t)np * sizeof(PairDesc), hipMemcpyHostToDevice, st));
+    MS_HIP(hipMemcpyAsync(ws + L.o_toff, b->tri_off.data(), (size_t)(np + 1) * 8, hipMemcpyHostToDevice, st));
+    MS_HIP(hipMemcpyAsync(ws + L.o_cbase, b->cell_base.data(), (size_t)(np + 1) * 8, hipMemcpyHostToDevice, st));
+    return MS_OK;
+}
+
+}  // namespace
+}  // namespace ms
+
+extern "C" int batch_create(int32_t n_pairs, const ms_mesh *const *A, const ms_mesh *const *B,
+                            const search_params_t *params, int64_t hits_cap, int64_t cand_cap, void *stream,
+                            ms_batch **out, size_t *ws_bytes)
+{
+    if (!out || !ws_bytes || n_pairs < 1 || !A || !B || !params || hits_cap < 0 || cand_cap < 0)
+        return fail(MS_E_ARG, "batch_create: bad argument");
+    *out = nullptr;
+    ms_batch *b = new ms_batch();
+    b->graph = nullptr;
+    b->exec = nullptr;
+    b->g_ws = nullptr;
+    b->cap_stream = nullptr;
+    int rc = geometry(n_pairs, A, B, params, b->G);
+    if (rc) { delete b; return rc; }
+    {
+        hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) { delete b; return hip_fail(e, "hipStreamCreate"); }
+    }
+    b->desc.resize((size_t)n_pairs);
+    b->tri_off.resize((size_t)n_pairs + 1);
+    b->cell_base.resize((size_t)n_pairs + 1);
+    uint64_t cb = 0;
+    int64_t to = 0;
+    for (int32_t i = 0; i < n_pairs; ++i) {
+        uint64_t c = 0;
+        pair_cells(&params[i], c);
+        b->desc[(size_t)i] = make_desc(A[i], B[i], &params[i], cb, to);
+        b->cell_base[(size_t)i] = cb;
+        b->tri_off[(size_t)i] = to;
+        cb += c;
+        to += (int64_t)A[i]->view.n_tris + B[i]->view.n_tris;
+    }
+    b->cell_base[(size_t)n_pairs] = cb;
+    b->tri_off[(size_t)n_pairs] = to;
+    int64_t E = 0;
+    if ((rc = count_entries(n_pairs, A, B, params, (unsigned long long *)A[0]->counter, (hipStream_t)stream, E))) {
+        batch_free(b);
+        return rc;
+    }
+    b->ent_all = E;
+    b->hits_cap = hits_cap;
+    b->cand_cap = cand_cap;
+    Layout L;
+    memset(&L, 0, sizeof L);
+    L.ent_cap = E;
+    L.cand_cap = cand_cap;
+    L.hits_cap = hits_cap;
+    layout(b->G, L);
+    *ws_bytes = L.total;
+    *out = b;
+    return MS_OK;
+}
+
+extern "C" int batch_free(ms_batch *b)
+{
+    if (!b) return MS_OK;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    delete b;
+    return MS_OK;
+}
+
+extern "C" int batch_search(ms_batch *b, void *ws_dev, size_t ws_bytes, hit_t *hits_dev, int64_t hits_cap,
+                            int64_t *pair_hit_offsets_dev, search_stats_t *stats_dev, int32_t use_graph, void *stream)
+{
+    if (!b || !ws_dev || !stats_dev || !pair_hit_offsets_dev || hits_cap < 0 || (hits_cap > 0 && !hits_dev))
+        return fail(MS_E_ARG, "batch_search: bad argument");
+    if (hits_cap > b->hits_cap) return fail(MS_E_ARG, "batch_search: hits_cap above the value the batch was sized for");
+    hipStream_t st = (hipStream_t)stream;
+    Layout L;
+    memset(&L, 0, sizeof L);
+    L.cand_cap = b->cand_cap;
+    L.hits_cap = hits_cap;
+    if (!fit_entries(b->G, L, ws_bytes)) return fail(MS_E_WORKSPACE, "batch_search: workspace smaller than the fixed part");
+    char *ws = (char *)ws_dev;
+    const BatchView bv = make_view(b->G, b->desc[0], ws, L);
+    int rc;
+    if (!use_graph) {
+        if ((rc = batch_upload(b, ws, L, st))) return rc;
+        return enqueue<false>(b->G, L, bv, ws, hits_dev, hits_cap, stats_dev, nullptr, L.cand_cap,
+                              pair_hit_offsets_dev, st);
+    }
+    const bool same = b->exec && b->g_ws == ws_dev && b->g_ws_bytes == ws_bytes && b->g_hits == (void *)hits_dev &&
+                      b->g_offs == (void *)pair_hit_offsets_dev && b->g_stats == (void *)stats_dev &&
+                      b->g_hits_cap == hits_cap;
+    if (!same) {
+        if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+        if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+        // the descriptors go to the workspace once, outside the graph
+        if ((rc = batch_upload(b, ws, L, st))) return rc;
+        MS_HIP(hipStreamSynchronize(st));
+        hipStream_t cs = b->cap_stream;
+        MS_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        rc = enqueue<false>(b->G, L, bv, ws, hits_dev, hits_cap, stats_dev, nullptr, L.cand_cap, pair_hit_offsets_dev,
+                            cs);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(cs, &g);
+        if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        hipGraphExec_t x = nullptr;
+        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) { (void)hipGraphDestroy(g); return hip_fail(e, "hipGraphInstantiate"); }
+        b->graph = g;
+        b->exec = x;
+        b->g_ws = ws_dev;
+        b->g_ws_bytes = ws_bytes;
+        b->g_hits = hits_dev;
+        b->g_offs = pair_hit_offsets_dev;
+        b->g_stats = stats_dev;
+        b->g_hits_cap = hits_cap;
+    }
+    MS_HIP(hipGraphLaunch(b->exec, st));
+    return MS_OK;
+}
+
+extern "C" int batch_needed(const ms_batch *b, const search_stats_t *stats_host, int64_t *needed)
+{
+    if (!b || !stats_host || !needed) return fail(MS_E_ARG, "batch_needed: NULL argument");
+    Layout L;
+    memset(&L, 0, sizeof L);
+    L.ent_cap = stats_host->n_entries > b->ent_all ? stats_host->n_entries : b->ent_all;
+    L.hits_cap = stats_host->n_hits > b->hits_cap ? stats_host->n_hits : b->hits_cap;
+    L.cand_cap = stats_host->n_cand > b->cand_cap ? stats_host->n_cand : b->cand_cap;
+    layout(b->G, L);
+    needed[0] = L.hits_cap;
+    needed[1] = L.cand_cap;
+    needed[2] = (int64_t)L.total;
+    return MS_OK;
+}
+
+// ---------------------------------------------------------------- profiling
+
+namespace ms {
+namespace {
+
+struct Profiler {
+    bool on = false;
+    bool open = false;
+    std::vector<const char *> names;
+    std::vector<hipEvent_t> events;   // pool, grows on demand
+    size_t used = 0;
+};
+
+thread_local Profiler g_prof;
+
+void prof_record(const char *name, hipStream_t st)
+{
+    Profiler &P = g_prof;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return;
+    if (P.used == P.events.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) { P.on = false; return; }
+        P.events.push_back(e);
+    }
+    if (P.names.size() < P.used + 1) P.names.resize(P.used + 1);
+    P.names[P.used] = name;
+    (void)hipEventRecord(P.events[P.used], st);
+    ++P.used;
+}
+
+}  // namespace
+
+void prof_begin(hipStream_t)
+{
+    if (!g_prof.on) return;
+    g_prof.used = 0;
+    g_prof.open = true;
+}
+
+void prof_mark(const char *name, hipStream_t st)
+{
+    if (g_prof.on && g_prof.open) prof_record(name, st);
+}
+
+void prof_end(hipStream_t st)
+{
+    if (g_prof.on && g_prof.open) {
+        prof_record("end", st);
+        g_prof.open = false;
+    }
+}
+
+}  // namespace ms
+
+extern "C" int search_profile_enable(int on)
+{
+    ms::g_prof.on = on != 0;
+    ms::g_prof.open = false;
+    ms::g_prof.used = 0;
+    return MS_OK;
+}
+
+extern "C" int search_profile_read(char *names, size_t names_len, double *ms_out, int cap, int *n_out)
+{
+    if (!n_out || (cap > 0 && !ms_out)) return ms::fail(MS_E_ARG, "search_profile_read: NULL argument");
+    ms::Profiler &P = ms::g_prof;
+    int n = P.used > 0 ? (int)P.used - 1 : 0;
+    *n_out = n;
+    if (n == 0) return MS_OK;
+    MS_HIP(hipEventSynchronize(P.events[P.used - 1]));
+    std::string csv;
+    for (int i = 0; i < n && i < cap; ++i) {
+        float t = 0.f;
+        MS_HIP(hipEventElapsedTime(&t, P.events[i], P.events[i + 1]));
+        ms_out[i] = t;
+        if (i) csv += ",";
+        csv += P.names[i];
+    }
+    if (names && names_len) {
+        size_t k = csv.size() < names_len - 1 ? csv.size() : names_len - 1;
+        memcpy(names, csv.data(), k);
+        names[k] = 0;
+    }
     return MS_OK;
 }

@@ -6,6 +6,8 @@
 //     consecutive addresses;
 //   * exclusive scans (reduce / scan partials / rescan) with host- or
 //     device-side element counts, so they can run inside captured graphs.
+#include <string.h>
+
 #include "ms_internal.hpp"
 
 namespace ms {
@@ -19,11 +21,11 @@ constexpr int SORT_WAVES = SORT_BLOCK / WAVE;
 constexpr int SORT_ITEMS = 16;
 constexpr int SORT_TILE = SORT_BLOCK * SORT_ITEMS;      // 4096 keys
 constexpr int WAVE_TILE = WAVE * SORT_ITEMS;            // 1024 keys per wave
-constexpr int MAX_PASSES = 8;
 constexpr uint32_t FLAG_AGG = 1u << 30;
 constexpr uint32_t FLAG_PRE = 2u << 30;
 constexpr uint32_t VAL_MASK = (1u << 30) - 1;
 constexpr int MAX_SORT_GRID = 1024;
+constexpr int LB_W = 16;            // look-back window (statuses read per round trip)
 
 __device__ __forceinline__ uint32_t digit_of(uint64_t k, int shift) { return (uint32_t)(k >> shift) & (RADIX - 1); }
 
@@ -55,57 +57,61 @@ __global__ void __launch_bounds__(256) k_fill_u64(uint64_t *p, uint64_t v, int64
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
-// Digit histograms of every pass in one read of the keys.
-__global__ void __launch_bounds__(SORT_BLOCK) k_radix_hist(const uint64_t *keys, const int64_t *n_dev, int lo_bit,
-                                                           int passes, uint32_t *hist)
-{
-    __shared__ uint32_t s_h[MAX_PASSES * RADIX];
-    for (int i = threadIdx.x; i < passes * RADIX; i += SORT_BLOCK) s_h[i] = 0;
-    __syncthreads();
-    int64_t n = *n_dev;
-    int64_t stride = (int64_t)gridDim.x * SORT_BLOCK;
-    for (int64_t i = (int64_t)blockIdx.x * SORT_BLOCK + threadIdx.x; i < n; i += stride) {
-        uint64_t k = __builtin_nontemporal_load(keys + i);
-        for (int p = 0; p < passes; ++p) atomicAdd(&s_h[p * RADIX + digit_of(k, lo_bit + RB * p)], 1u);
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < passes * RADIX; i += SORT_BLOCK)
-        if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
-}
-
-// One stable counting pass on digit (shift .. shift+7) from `in` to `out`.
+// One stable counting pass on RB-bit digit `shift` from `in` to `out`
+// (RB = 8, 9 or 10; each of the 256 threads owns RADIX / 256 digits).
+// Besides its own look-back words, each block clears, for the tile it
+// processes, the look-back words of the next pass (status_next) and
+// `extra_per_tile` words of `extra` (a later kernel's look-back words), so
+// no separate clearing kernel is needed.
+template <int RBT>
 __global__ void __launch_bounds__(SORT_BLOCK) k_radix_onesweep(const uint64_t *__restrict__ in,
                                                                uint64_t *__restrict__ out, const int64_t *n_dev,
                                                                int shift, const uint32_t *__restrict__ hist_pass,
-                                                               uint32_t *status, uint32_t *tile_ctr)
+                                                               uint32_t *status, uint32_t *status_next,
+                                                               uint32_t *tile_ctr, uint64_t *extra,
+                                                               int extra_per_tile)
 {
+    constexpr int R = 1 << RBT;
+    constexpr int DPT = R / SORT_BLOCK;
     __shared__ uint64_t s_keys[SORT_TILE];
-    __shared__ uint32_t s_wcnt[SORT_WAVES][RADIX];
-    __shared__ uint32_t s_tstart[RADIX];
-    __shared__ int64_t s_gbase[RADIX];
-    __shared__ int64_t s_dbase[RADIX];
+    __shared__ uint32_t s_wcnt[SORT_WAVES][R];
+    __shared__ uint32_t s_tstart[R];
+    __shared__ uint32_t s_gbase[R];
+    __shared__ uint32_t s_dbase[R];
     __shared__ uint32_t s_tmp[SORT_WAVES];
     __shared__ uint32_t s_tile;
 
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
     const int64_t n = *n_dev;
     const int64_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
+    if ((int64_t)blockIdx.x >= ntiles) return;   // no tile for this block: leave the counter alone
 
-    // global exclusive offsets of each digit (same for every tile)
+    // global exclusive offsets of the digits (the same for every tile)
     {
-        uint32_t c = hist_pass[tid];
-        uint32_t ex = block_excl_scan_256(c, s_tmp, nullptr);
-        s_dbase[tid] = ex;
+        uint32_t v[DPT], sum = 0;
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) { v[j] = hist_pass[tid * DPT + j]; sum += v[j]; }
+        uint32_t ex = block_excl_scan_256(sum, s_tmp, nullptr);
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) { s_dbase[tid * DPT + j] = ex; ex += v[j]; }
     }
 
     for (;;) {
         if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
-        s_wcnt[0][tid] = 0; s_wcnt[1][tid] = 0; s_wcnt[2][tid] = 0; s_wcnt[3][tid] = 0;
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) {
+            s_wcnt[0][tid * DPT + j] = 0; s_wcnt[1][tid * DPT + j] = 0;
+            s_wcnt[2][tid * DPT + j] = 0; s_wcnt[3][tid * DPT + j] = 0;
+        }
         __syncthreads();
         const int64_t tile = s_tile;
         if (tile >= ntiles) break;
         const int64_t base = tile * SORT_TILE;
         const int64_t wbase = base + (int64_t)w * WAVE_TILE;
+        if (status_next)
+            for (int j = tid; j < R; j += SORT_BLOCK) status_next[tile * R + j] = 0;
+        if (extra)
+            for (int j = tid; j < extra_per_tile; j += SORT_BLOCK) extra[tile * extra_per_tile + j] = 0;
 
         uint64_t key[SORT_ITEMS];
         uint32_t rank[SORT_ITEMS];
@@ -114,60 +120,93 @@ __global__ void __launch_bounds__(SORT_BLOCK) k_radix_onesweep(const uint64_t *_
             int64_t idx = wbase + i * WAVE + lane;
             key[i] = idx < n ? __builtin_nontemporal_load(in + idx) : ~0ull;
         }
-        // wave-level stable ranking: for each item, the lanes holding the
-        // same digit are found with 8 ballots; the lowest of them bumps the
-        // wave's counter for that digit
+        // wave-level stable ranking: the lanes holding the same digit are
+        // found with RB ballots; the lowest of them bumps the wave's counter
 #pragma unroll
         for (int i = 0; i < SORT_ITEMS; ++i) {
             int64_t idx = wbase + i * WAVE + lane;
             bool valid = idx < n;
-            uint32_t d = digit_of(key[i], shift);
+            uint32_t d = (uint32_t)(key[i] >> shift) & (R - 1);
             uint64_t peers = ballot(valid);
 #pragma unroll
-            for (int b = 0; b < RB; ++b) {
+            for (int b = 0; b < RBT; ++b) {
                 uint64_t m = ballot((d >> b) & 1u);
                 peers &= ((d >> b) & 1u) ? m : ~m;
             }
-            uint32_t before = (uint32_t)mbcnt(peers);
             uint32_t prev = valid ? s_wcnt[w][d] : 0u;
-            rank[i] = prev + before;
+            rank[i] = prev + (uint32_t)mbcnt(peers);
             bool leader = valid && (peers != 0) && (lane == __builtin_ctzll(peers));
             if (leader) s_wcnt[w][d] = prev + (uint32_t)__builtin_popcountll(peers);
         }
         __syncthreads();
-        // per digit: waves' exclusive offsets, tile count, tile-local start
-        uint32_t c0 = s_wcnt[0][tid], c1 = s_wcnt[1][tid], c2 = s_wcnt[2][tid], c3 = s_wcnt[3][tid];
-        uint32_t tcount = c0 + c1 + c2 + c3;
-        uint32_t tstart = block_excl_scan_256(tcount, s_tmp, nullptr);
-        s_wcnt[0][tid] = 0; s_wcnt[1][tid] = c0; s_wcnt[2][tid] = c0 + c1; s_wcnt[3][tid] = c0 + c1 + c2;
-        s_tstart[tid] = tstart;
-        // decoupled look-back for this digit
-        uint32_t *my = status + tile * RADIX + tid;
-        if (tile == 0) {
-            __hip_atomic_store(my, FLAG_PRE | tcount, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_gbase[tid] = s_dbase[tid];
-        } else {
-            __hip_atomic_store(my, FLAG_AGG | tcount, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            uint32_t excl = 0;
-            int64_t t = tile - 1;
-            for (;;) {
-                uint32_t sv = __hip_atomic_load(status + t * RADIX + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                uint32_t fl = sv & ~VAL_MASK;
-                if (fl == 0) continue;            // predecessor not published yet (it is running)
-                excl += sv & VAL_MASK;
-                if (fl == FLAG_PRE) break;
-                --t;
+        // per digit: the waves' exclusive offsets, the tile count and start
+        uint32_t tcount[DPT], tsum = 0;
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) {
+            const int d = tid * DPT + j;
+            uint32_t c0 = s_wcnt[0][d], c1 = s_wcnt[1][d], c2 = s_wcnt[2][d], c3 = s_wcnt[3][d];
+            tcount[j] = c0 + c1 + c2 + c3;
+            tsum += tcount[j];
+            s_wcnt[0][d] = 0; s_wcnt[1][d] = c0; s_wcnt[2][d] = c0 + c1; s_wcnt[3][d] = c0 + c1 + c2;
+        }
+        uint32_t tstart = block_excl_scan_256(tsum, s_tmp, nullptr);
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) { s_tstart[tid * DPT + j] = tstart; tstart += tcount[j]; }
+        // decoupled look-back, one chain per digit
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) {
+            const int d = tid * DPT + j;
+            uint32_t *my = status + tile * R + d;
+            if (tile == 0) {
+                __hip_atomic_store(my, FLAG_PRE | tcount[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_gbase[d] = s_dbase[d];
+            } else {
+                __hip_atomic_store(my, FLAG_AGG | tcount[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            __hip_atomic_store(my, FLAG_PRE | (excl + tcount), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_gbase[tid] = s_dbase[tid] + excl;
+        }
+        if (tile > 0) {
+#pragma unroll
+            for (int j = 0; j < DPT; ++j) {
+                const int d = tid * DPT + j;
+                // read LB_W predecessors per round trip; stop at the first
+                // inclusive prefix; re-read from a predecessor not yet published
+                uint32_t excl = 0;
+                int64_t t = tile - 1;
+                for (;;) {
+                    uint32_t sv[LB_W];
+#pragma unroll
+                    for (int k = 0; k < LB_W; ++k)
+                        sv[k] = (t - k >= 0) ? __hip_atomic_load(status + (t - k) * R + d, __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT)
+                                             : FLAG_PRE;
+                    bool done = false;
+                    int used = 0;
+#pragma unroll
+                    for (int k = 0; k < LB_W; ++k) {
+                        if (!done && used == k) {
+                            uint32_t fl = sv[k] & ~VAL_MASK;
+                            if (fl != 0) {
+                                excl += sv[k] & VAL_MASK;
+                                if (fl == FLAG_PRE) done = true;
+                                else used = k + 1;
+                            }
+                        }
+                    }
+                    if (done) break;
+                    t -= used;
+                }
+                __hip_atomic_store(status + tile * R + d, FLAG_PRE | (excl + tcount[j]), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                s_gbase[d] = s_dbase[d] + excl;
+            }
         }
         __syncthreads();
-        // stage the tile in LDS in digit order
+        // stage the tile in LDS in digit order, then write runs out
 #pragma unroll
         for (int i = 0; i < SORT_ITEMS; ++i) {
             int64_t idx = wbase + i * WAVE + lane;
             if (idx < n) {
-                uint32_t d = digit_of(key[i], shift);
+                uint32_t d = (uint32_t)(key[i] >> shift) & (R - 1);
                 s_keys[s_tstart[d] + s_wcnt[w][d] + rank[i]] = key[i];
             }
         }
@@ -175,10 +214,128 @@ __global__ void __launch_bounds__(SORT_BLOCK) k_radix_onesweep(const uint64_t *_
         const int valid_in_tile = (int)((n - base) < SORT_TILE ? (n - base) : SORT_TILE);
         for (int j = tid; j < valid_in_tile; j += SORT_BLOCK) {
             uint64_t k = s_keys[j];
-            uint32_t d = digit_of(k, shift);
-            out[s_gbase[d] + (j - (int64_t)s_tstart[d])] = k;
+            uint32_t d = (uint32_t)(k >> shift) & (R - 1);
+            out[(int64_t)s_gbase[d] + (j - (int64_t)s_tstart[d])] = k;
         }
         __syncthreads();
+    }
+}
+
+// ----------------------------------------------- small sorts of unique keys
+
+// Each block sorts one chunk of SORT_TILE keys completely in LDS (stable
+// LSD passes with the same wave-ballot ranking as the onesweep kernel).
+constexpr int TINY_SORT = 1024;
+
+__global__ void __launch_bounds__(SORT_BLOCK) k_sort_chunks(const uint64_t *__restrict__ in, uint64_t *__restrict__ out,
+                                                            uint64_t *__restrict__ final_out, const int64_t *n_dev,
+                                                            int64_t cap, int lo_bit, int passes)
+{
+    __shared__ uint64_t s_buf[2][SORT_TILE];
+    __shared__ uint32_t s_wcnt[SORT_WAVES][RADIX];
+    __shared__ uint32_t s_tstart[RADIX];
+    __shared__ uint32_t s_tmp[SORT_WAVES];
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
+    const int64_t n = *n_dev < cap ? *n_dev : cap;
+    if (n <= TINY_SORT) {
+        // few keys: block 0 ranks each key by counting the smaller ones
+        if (blockIdx.x != 0) return;
+        for (int i = tid; i < n; i += SORT_BLOCK) s_buf[0][i] = in[i];
+        __syncthreads();
+        for (int i = tid; i < n; i += SORT_BLOCK) {
+            const uint64_t k = s_buf[0][i];
+            int r = 0;
+            for (int j = 0; j < n; ++j) r += s_buf[0][j] < k;
+            final_out[r] = k;
+        }
+        return;
+    }
+    const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
+    if (base >= n) return;
+    const int cnt = (int)((n - base) < SORT_TILE ? (n - base) : SORT_TILE);
+    uint64_t key[SORT_ITEMS];
+#pragma unroll
+    for (int i = 0; i < SORT_ITEMS; ++i) {
+        int idx = w * WAVE_TILE + i * WAVE + lane;
+        key[i] = idx < cnt ? in[base + idx] : ~0ull;
+    }
+    int cur = 0;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = lo_bit + RB * p;
+        s_wcnt[0][tid] = 0; s_wcnt[1][tid] = 0; s_wcnt[2][tid] = 0; s_wcnt[3][tid] = 0;
+        __syncthreads();
+        uint32_t rank[SORT_ITEMS];
+#pragma unroll
+        for (int i = 0; i < SORT_ITEMS; ++i) {
+            int idx = w * WAVE_TILE + i * WAVE + lane;
+            bool valid = idx < cnt;
+            uint32_t d = digit_of(key[i], shift);
+            uint64_t peers = ballot(valid);
+#pragma unroll
+            for (int b = 0; b < RB; ++b) {
+                uint64_t m = ballot((d >> b) & 1u);
+                peers &= ((d >> b) & 1u) ? m : ~m;
+            }
+            uint32_t prev = valid ? s_wcnt[w][d] : 0u;
+            rank[i] = prev + (uint32_t)mbcnt(peers);
+            bool leader = valid && (peers != 0) && (lane == __builtin_ctzll(peers));
+            if (leader) s_wcnt[w][d] = prev + (uint32_t)__builtin_popcountll(peers);
+        }
+        __syncthreads();
+        uint32_t c0 = s_wcnt[0][tid], c1 = s_wcnt[1][tid], c2 = s_wcnt[2][tid], c3 = s_wcnt[3][tid];
+        uint32_t tstart = block_excl_scan_256(c0 + c1 + c2 + c3, s_tmp, nullptr);
+        s_wcnt[0][tid] = 0; s_wcnt[1][tid] = c0; s_wcnt[2][tid] = c0 + c1; s_wcnt[3][tid] = c0 + c1 + c2;
+        s_tstart[tid] = tstart;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < SORT_ITEMS; ++i) {
+            int idx = w * WAVE_TILE + i * WAVE + lane;
+            if (idx < cnt) {
+                uint32_t d = digit_of(key[i], shift);
+                s_buf[cur][s_tstart[d] + s_wcnt[w][d] + rank[i]] = key[i];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < SORT_ITEMS; ++i) {
+            int idx = w * WAVE_TILE + i * WAVE + lane;
+            key[i] = idx < cnt ? s_buf[cur][idx] : ~0ull;
+        }
+        cur ^= 1;
+    }
+#pragma unroll
+    for (int i = 0; i < SORT_ITEMS; ++i) {
+        int idx = w * WAVE_TILE + i * WAVE + lane;
+        if (idx < cnt) out[base + idx] = key[i];
+    }
+}
+
+// Final position of each key of the sorted chunks: its index in its own chunk
+// plus, for every other chunk, the number of keys there that are smaller
+// (keys are distinct).
+__global__ void __launch_bounds__(SORT_BLOCK) k_merge_rank(const uint64_t *__restrict__ chunks,
+                                                           uint64_t *__restrict__ out, const int64_t *n_dev, int64_t cap)
+{
+    const int64_t n = *n_dev < cap ? *n_dev : cap;
+    if (n <= TINY_SORT) return;   // already placed by k_sort_chunks
+    const int64_t nch = (n + SORT_TILE - 1) / SORT_TILE;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint64_t k = chunks[i];
+        const int64_t c = i / SORT_TILE;
+        int64_t pos = i - c * SORT_TILE;
+        for (int64_t o = 0; o < nch; ++o) {
+            if (o == c) continue;
+            int64_t lo = o * SORT_TILE, hi = lo + SORT_TILE < n ? lo + SORT_TILE : n;
+            const int64_t b = lo;
+            while (lo < hi) {
+                int64_t mid = lo + ((hi - lo) >> 1);
+                if (chunks[mid] < k) lo = mid + 1;
+                else hi = mid;
+            }
+            pos += lo - b;
+        }
+        out[pos] = k;
     }
 }
 
@@ -305,58 +462,82 @@ int launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st)
     return MS_OK;
 }
 
-size_t sort_ws_bytes(int64_t cap, int max_passes)
+RadixPlan radix_plan(int lo_bit, int n_bits, int64_t cap)
 {
-    int64_t tiles = ceil_div(cap > 0 ? cap : 1, SORT_TILE);
-    size_t words = (size_t)max_passes * RADIX + (size_t)max_passes * tiles * RADIX + (size_t)max_passes;
-    words = (words + 1) & ~(size_t)1;   // even count of u32 -> 8-byte multiple
-    return words * sizeof(uint32_t);
+    RadixPlan p;
+    memset(&p, 0, sizeof p);
+    p.lo_bit = lo_bit;
+    p.n_bits = n_bits < 0 ? 0 : n_bits;
+    p.cap = cap > 0 ? cap : 0;
+    p.tiles_cap = ceil_div(p.cap > 0 ? p.cap : 1, SORT_TILE);
+    if (p.n_bits == 0) { p.passes = 0; p.rb = 8; return p; }
+    p.passes = (p.n_bits + 9) / 10;
+    int rb = (p.n_bits + p.passes - 1) / p.passes;
+    p.rb = rb < 8 ? 8 : rb;
+    return p;
 }
 
-void sort_ws_carve(void *base, int64_t cap, int max_passes, SortWs &ws)
+size_t radix_ws_bytes(const RadixPlan &p)
 {
-    int64_t tiles = ceil_div(cap > 0 ? cap : 1, SORT_TILE);
-    uint32_t *p = (uint32_t *)base;
-    ws.hist = p;
-    ws.status = p + (size_t)max_passes * RADIX;
-    ws.tile_ctr = ws.status + (size_t)max_passes * tiles * RADIX;
+    size_t r = (size_t)1 << p.rb;
+    size_t words = (size_t)p.passes * r + (size_t)p.passes * p.tiles_cap * r + (size_t)p.passes + 2;
+    return (words * sizeof(uint32_t) + 255) & ~(size_t)255;
 }
 
-int radix_sort_u64(uint64_t *keys, uint64_t *alt, const int64_t *n_dev, int64_t cap, int lo_bit, int n_bits,
-                   const SortWs &ws, hipStream_t st, uint64_t **result)
+void radix_ws_carve(RadixPlan &p, void *base)
+{
+    size_t r = (size_t)1 << p.rb;
+    uint32_t *w = (uint32_t *)base;
+    p.hist = w;
+    p.status = w + (size_t)p.passes * r;
+    p.tile_ctr = p.status + (size_t)p.passes * p.tiles_cap * r;
+}
+
+int radix_sort(const RadixPlan &p, uint64_t *keys, uint64_t *alt, const int64_t *n_dev, uint64_t *extra,
+               int extra_per_tile, hipStream_t st, uint64_t **result)
 {
     *result = keys;
-    if (cap <= 0 || n_bits <= 0) return MS_OK;
-    if (cap >= (int64_t)VAL_MASK) return fail(MS_E_CAPACITY, "radix sort: more than 2^30 keys");
-    int passes = (n_bits + RB - 1) / RB;
-    if (passes > MAX_PASSES) return fail(MS_E_KEYBITS, "radix sort: more than 64 key bits");
-    int64_t tiles = ceil_div(cap, SORT_TILE);
-    // clear histograms, look-back status words and tile counters of every pass
-    size_t words = (size_t)passes * RADIX + (size_t)passes * tiles * RADIX + (size_t)passes;
-    // status and counters follow the histograms contiguously only when the
-    // workspace was carved for exactly `passes`; clear each region instead
-    int rc;
-    if ((rc = launch_fill_u64((uint64_t *)ws.hist, 0, (int64_t)((size_t)passes * RADIX / 2), st))) return rc;
-    if ((rc = launch_fill_u64((uint64_t *)ws.status, 0, (int64_t)((size_t)passes * tiles * RADIX / 2), st))) return rc;
-    (void)words;
-    {
-        int64_t g = tiles < MAX_SORT_GRID ? tiles : MAX_SORT_GRID;
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)g), dim3(SORT_BLOCK), 0, st, keys, n_dev, lo_bit, passes,
-                           ws.hist);
-        MS_HIP(hipGetLastError());
-    }
-    // tile counters: one u32 per pass, cleared with a tiny fill (2 per u64)
-    if ((rc = launch_fill_u64((uint64_t *)ws.tile_ctr, 0, (passes + 1) / 2, st))) return rc;
+    if (p.passes == 0 || p.cap == 0) return MS_OK;
+    if (p.cap >= (int64_t)VAL_MASK) return fail(MS_E_CAPACITY, "radix sort: more than 2^30 keys");
+    const size_t r = (size_t)1 << p.rb;
+    int64_t g = p.tiles_cap < MAX_SORT_GRID ? p.tiles_cap : MAX_SORT_GRID;
     uint64_t *src = keys, *dst = alt;
-    int64_t g = tiles < MAX_SORT_GRID ? tiles : MAX_SORT_GRID;
-    for (int p = 0; p < passes; ++p) {
-        hipLaunchKernelGGL(k_radix_onesweep, dim3((unsigned)g), dim3(SORT_BLOCK), 0, st, src, dst, n_dev,
-                           lo_bit + RB * p, ws.hist + p * RADIX, ws.status + (size_t)p * tiles * RADIX,
-                           ws.tile_ctr + p);
+    for (int q = 0; q < p.passes; ++q) {
+        uint32_t *stat = p.status + (size_t)q * p.tiles_cap * r;
+        uint32_t *next = q + 1 < p.passes ? stat + (size_t)p.tiles_cap * r : nullptr;
+        uint64_t *ex = q + 1 == p.passes ? extra : nullptr;
+        int shift = p.lo_bit + p.rb * q;
+        prof_mark("k_radix_onesweep", st);
+        if (p.rb == 8)
+            hipLaunchKernelGGL(k_radix_onesweep<8>, dim3((unsigned)g), dim3(SORT_BLOCK), 0, st, src, dst, n_dev, shift,
+                               p.hist + q * r, stat, next, p.tile_ctr + q, ex, extra_per_tile);
+        else if (p.rb == 9)
+            hipLaunchKernelGGL(k_radix_onesweep<9>, dim3((unsigned)g), dim3(SORT_BLOCK), 0, st, src, dst, n_dev, shift,
+                               p.hist + q * r, stat, next, p.tile_ctr + q, ex, extra_per_tile);
+        else
+            hipLaunchKernelGGL(k_radix_onesweep<10>, dim3((unsigned)g), dim3(SORT_BLOCK), 0, st, src, dst, n_dev,
+                               shift, p.hist + q * r, stat, next, p.tile_ctr + q, ex, extra_per_tile);
         MS_HIP(hipGetLastError());
         uint64_t *t = src; src = dst; dst = t;
     }
     *result = src;
+    return MS_OK;
+}
+
+int sort_unique_small(const uint64_t *in, uint64_t *tmp, uint64_t *out, const int64_t *n_dev, int64_t cap,
+                      int lo_bit, int n_bits, hipStream_t st)
+{
+    if (cap <= 0) return MS_OK;
+    int passes = n_bits <= 0 ? 0 : (n_bits + RB - 1) / RB;
+    int64_t chunks = ceil_div(cap, SORT_TILE);
+    prof_mark("k_sort_chunks", st);
+    hipLaunchKernelGGL(k_sort_chunks, dim3((unsigned)chunks), dim3(SORT_BLOCK), 0, st, in, tmp, out, n_dev, cap, lo_bit,
+                       passes);
+    int64_t g = ceil_div(cap, SORT_BLOCK);
+    if (g > 1024) g = 1024;
+    prof_mark("k_merge_rank", st);
+    hipLaunchKernelGGL(k_merge_rank, dim3((unsigned)g), dim3(SORT_BLOCK), 0, st, tmp, out, n_dev, cap);
+    MS_HIP(hipGetLastError());
     return MS_OK;
 }
 

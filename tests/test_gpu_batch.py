@@ -1,0 +1,142 @@
+"""GPU parity of the batched search (many mesh pairs in one pass, optionally
+one captured HIP graph): per pair, identical to the plain search and to the
+oracle; graph replays identical to the eager run."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+FLOAT_FIELDS = ("u", "v", "a", "b", "thA", "sA", "thB", "sB", "margin")
+
+
+@pytest.fixture(scope="module")
+def ms():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2109_14814_amd as ms
+    ms.lib()
+    return ms
+
+
+def _pairs(h):
+    return (h["triA"].astype(np.int64) << 32) | h["triB"].astype(np.int64)
+
+
+def assert_same_hits(got, want, exact=False):
+    assert np.array_equal(_pairs(got), _pairs(want)), (len(got), len(want))
+    for f in FLOAT_FIELDS:
+        if len(got):
+            d = np.max(np.abs(got[f] - want[f]))
+            assert d <= (0.0 if exact else 1e-10), (f, d)
+    if len(got):
+        assert np.max(np.abs(got["X"] - want["X"])) <= (0.0 if exact else 1e-10)
+
+
+def small_family(n_pairs, seed):
+    rng = np.random.default_rng(seed)
+    sizes = []
+    for _ in range(n_pairs):
+        row = []
+        for _s in range(2):
+            row += [int(round(np.exp(rng.uniform(np.log(8), np.log(96))))),
+                    int(round(np.exp(rng.uniform(np.log(4), np.log(24)))))]
+        sizes.append(tuple(row))
+    return synth.family(n_pairs, seed, sizes=sizes)
+
+
+def grids_for(fam, kappa):
+    return [oracle.default_grid([a, b], kappa) for a, b in fam]
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_matches_oracle_per_pair(ms, use_graph):
+    fam = small_family(24, 3)
+    grids = grids_for(fam, 1.5)
+    gp = [(ms.Mesh.from_synth(a), ms.Mesh.from_synth(b)) for a, b in fam]
+    params = [ms.make_params(g[0], g[2], g[3]) for g in grids]
+    bt = ms.Batch(gp, params, hits_cap=1 << 12, cand_cap=1 << 16)
+    bt.run_checked(use_graph)
+    per_pair, st = bt.results()
+    assert st["overflow"] == 0
+    tot_c = tot_h = 0
+    for (a, b), hits in zip(fam, per_pair):
+        ref = oracle.bruteforce(a, b)
+        assert_same_hits(hits, ref.hits)
+        assert np.all(hits["flags"] == hits["flags"][0]) if len(hits) else True
+        tot_c += len(ref.cand)
+        tot_h += len(ref.hits)
+    assert st["n_cand"] == tot_c and st["n_hits"] == tot_h
+    assert tot_h > 0
+
+
+def test_batch_equals_plain_on_the_full_family(ms):
+    """The 256-pair continuation family at its full sizes: the batched search
+    (one graph launch) reproduces the 256 plain searches bit for bit."""
+    import torch
+    fam = synth.family(256, 0)
+    gp = [(ms.Mesh.from_synth(a), ms.Mesh.from_synth(b)) for a, b in fam]
+    grids = grids_for(fam, 2.0)
+    params = [ms.make_params(g[0], g[2], g[3]) for g in grids]
+    plain = []
+    for (a, b), p in zip(gp, params):
+        hits, st, _ = ms.search(a, b, p, hits_cap=1 << 12, cand_cap=1 << 18)
+        plain.append((hits, st))
+    bt = ms.Batch(gp, params, hits_cap=1 << 16, cand_cap=1 << 22)
+    bt.run_checked(True)
+    per_pair, st = bt.results()
+    for i, hits in enumerate(per_pair):
+        assert_same_hits(hits, plain[i][0], exact=True)
+        assert np.all(hits["flags"] == i)
+    assert st["n_cand"] == sum(p[1]["n_cand"] for p in plain)
+    assert st["n_slots"] == sum(p[1]["n_slots"] for p in plain)
+    assert st["n_cells"] == sum(p[1]["n_cells"] for p in plain)
+    # a sample of pairs against the oracle's grid search with the same grids
+    for i in (0, 17, 101, 255):
+        a, b = fam[i]
+        g = grids[i]
+        ref = oracle.grid_search(a, b, g[0], g[2], g[3])
+        assert_same_hits(per_pair[i], ref.hits)
+        assert plain[i][1]["n_cand"] == len(ref.cand)
+
+
+def test_graph_replays_are_identical(ms):
+    """Replay the captured graph several times, with eager device work and
+    synchronisations in between; every replay gives the eager result."""
+    import torch
+    fam = small_family(16, 5)
+    gp = [(ms.Mesh.from_synth(a), ms.Mesh.from_synth(b)) for a, b in fam]
+    params = [ms.default_params(a, b, 1.0) for a, b in gp]
+    eager = ms.Batch(gp, params, hits_cap=1 << 12, cand_cap=1 << 16)
+    eager.run_checked(False)
+    ref, st_ref = eager.results()
+    bt = ms.Batch(gp, params, hits_cap=1 << 12, cand_cap=1 << 16)
+    junk = torch.zeros(1 << 20, device="cuda")
+    for rep in range(4):
+        bt.run(True)
+        torch.cuda.synchronize()
+        got, st = bt.results()
+        assert st == st_ref, rep
+        for g, r in zip(got, ref):
+            assert_same_hits(g, r, exact=True)
+        junk.add_(1.0)            # unrelated eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_batch_overflow_is_reported_and_replanned(ms):
+    fam = small_family(8, 9)
+    gp = [(ms.Mesh.from_synth(a), ms.Mesh.from_synth(b)) for a, b in fam]
+    params = [ms.default_params(a, b, 1.0) for a, b in gp]
+    bt = ms.Batch(gp, params, hits_cap=1, cand_cap=2)
+    bt.run(True)
+    import torch
+    torch.cuda.synchronize()
+    assert bt.stats_dict()["overflow"] != 0
+    bt.run_checked(True)
+    per_pair, st = bt.results()
+    assert st["overflow"] == 0
+    for (a, b), hits in zip(fam, per_pair):
+        assert_same_hits(hits, oracle.bruteforce(a, b).hits)
