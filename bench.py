@@ -6,10 +6,15 @@ both meshes' triangle boxes from the HBM-resident vertices, then the full
 keyed-grid search (entry keys, radix sort, cell pairs, box test, Moller
 test, 4x4 narrow phase, sorted hits).  Prints one JSON line.
 
+The cell edge is picked by the package's autotuner unless --kappa is given.
+
 Side legs (reported in the same line): the all-pairs forced test rate on the
 64 x 64 workload, the 256-pair continuation family searched pair by pair
-(plain) and in one captured graph (batched), and the RK8 map rate; the CPU
-oracle is timed on a bounded sample as the baseline.
+(plain) and in one captured graph (batched), the RK8 map rate, the
+refinement kernels (residual, tangent, discrete adjoint, damped Newton) on
+128 planted problems, and a plain 1 GiB device copy (the HBM reference that
+also scales the hardware counters); the CPU oracle is timed on a bounded
+sample as the baseline.
 """
 from __future__ import annotations
 
@@ -32,33 +37,82 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kernel: str, st: dict, ntot: int) -> float | None:
-    """Bytes a kernel must move per launch (counted once, no re-reads)."""
-    E, Eall, nc, P, C, H = (st["n_entries"], st["n_entries_all"], st["n_cells"], st["n_slots"],
-                            st["n_cand"], st["n_hits"])
+def algorithmic_bytes(kernel: str, st: dict, mesh_sizes) -> float | None:
+    """Bytes a kernel must move per launch, each byte counted once (no
+    re-reads): the per-unit figures times the units of one launch."""
+    E, nc, C, H = st["n_entries"], st["n_cells"], st["n_cand"], st["n_hits"]
+    ntot = sum(nt for nt, _ in mesh_sizes)
+    nt1, nv1 = mesh_sizes[0]
     table = {
+        "k_tri_boxes": 32.0 * nv1 + 64.0 * nt1,      # one mesh: vertices read once, boxes written
         "k_mark": 72.0 * ntot,                       # triangle boxes read, compact cell ranges written
         "k_count": 12.0 * ntot,                      # cell ranges read, counts written
         "k_emit": 12.0 * ntot + 8.0 * E,             # counts + cell ranges read, keys written
         "k_radix_onesweep": 16.0 * E,                # keys read + written
-        "k_cells": 8.0 * E + 32.0 * nc,              # keys read, cell records + slot offsets written
-        "k_enum": 8.0 * E + 32.0 * nc + 64.0 * E + 12.0 * C,   # keys, cells, boxes once, candidates
+        "k_cells": 8.0 * E + 40.0 * nc,              # keys read, cell records + slot offsets written
+        "k_enum": 8.0 * E + 40.0 * nc + 64.0 * E + 12.0 * C,   # keys, cells, boxes once, candidates
         "k_narrow": C * (12.0 + 192.0) + 120.0 * H,  # candidates, 6 vertices, hit records
     }
     return table.get(kernel)
 
 
+SEARCH_SOURCES = ("mesh.hip", "sort_scan.hip", "search.hip", "predicate.hpp", "ms_internal.hpp")
+
+
+def source_digest() -> str:
+    """Digest of the sources of the search kernels (the hardware counters in
+    profiles/ are valid only for the sources they were taken on)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2109_14814_amd", "csrc")
+    files = [os.path.join(csrc, f) for f in SEARCH_SOURCES]
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "search_512x512_traffic.txt")
+
+
+def measured_traffic(kernel: str) -> float | None:
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, KiB per dispatch, each scaled by the
+    same counter's reading on a plain copy of known size), or None when the
+    summary is missing or was taken on other sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    digest, rows = None, {}
+    for line in open(TRAFFIC_FILE):
+        f = line.split()
+        if len(f) >= 2 and f[0] == "source_digest":
+            digest = f[1]
+        elif len(f) == 7 and f[0].startswith("k_"):
+            try:
+                rows[f[0]] = float(f[6])
+            except ValueError:
+                pass
+    if digest != source_digest():
+        return None
+    return rows.get(kernel)
+
+
 def time_search(ms, A, B, searcher, steps, warmup, profile=False):
+    """ms per step (mesh_update x 2 + one queued search); with profile, also
+    the per-dispatch kernel durations of every step."""
     import torch
     for _ in range(warmup):
-        A.update(); B.update(); searcher.run()
+        A.update(); B.update(); searcher.run_async()
     torch.cuda.synchronize()
+    searcher.check_overflow()
     kern = {}
     if profile:
         ms.profile_enable(True)
     t0 = time.perf_counter()
     for _ in range(steps):
-        A.update(); B.update(); searcher.run()
+        A.update(); B.update(); searcher.run_async()
         if profile:
             for name, t in ms.profile_read():
                 kern.setdefault(name, []).append(t)
@@ -66,6 +120,7 @@ def time_search(ms, A, B, searcher, steps, warmup, profile=False):
     t1 = time.perf_counter()
     if profile:
         ms.profile_enable(False)
+    searcher.check_overflow()
     return (t1 - t0) / steps * 1e3, kern
 
 
@@ -76,8 +131,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=512, help="quads per axis of each surface")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--kappa", type=float, default=0.0, help="cell edge / mean triangle diameter (0 = sweep)")
-    ap.add_argument("--legs", default="search,allpairs,family,rk8,cpu")
+    ap.add_argument("--kappa", type=float, default=0.0, help="cell edge / mean triangle diameter (0 = autotune)")
+    ap.add_argument("--legs", default="search,allpairs,family,rk8,refine,copy,cpu")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -97,38 +152,35 @@ def main():
     # ------------------------------------------------ main leg: 512^2 search
     Am, Bm = synth.plain_pair(args.n, args.n, args.seed)
     A, B = ms.Mesh.from_synth(Am), ms.Mesh.from_synth(Bm)
-    ntot = A.n_tris + B.n_tris
+    mesh_sizes = [(A.n_tris, Am.verts.shape[0] * Am.verts.shape[1]), (B.n_tris, Bm.verts.shape[0] * Bm.verts.shape[1])]
     logical_pairs = A.n_tris * B.n_tris
-    kappas = [args.kappa] if args.kappa > 0 else [0.75, 1.0, 1.5, 2.0, 3.0, 4.0]
-    sweep = {}
-    best = None
-    for k in kappas:
-        p = ms.default_params(A, B, k)
-        s = ms.Searcher(A, B, p, hits_cap=1 << 14, cand_cap=1 << 20)
-        t, _ = time_search(ms, A, B, s, steps=max(5, args.steps // 10), warmup=3)
-        sweep[k] = round(t, 5)
-        log(f"kappa {k}: {t:.4f} ms/search")
-        if best is None or t < best[0]:
-            best = (t, k, p, s)
-    _, kappa, params, searcher = best
-    ms_step, kern = time_search(ms, A, B, searcher, args.steps, args.warmup, profile=True)
+    if args.kappa > 0:
+        kappa, params, sweep = args.kappa, ms.default_params(A, B, args.kappa), {}
+    else:
+        kappa, params, sweep = ms.autotune_kappa(A, B)
+        sweep = {k: round(v, 5) for k, v in sweep.items()}
+        log(f"autotuned kappa {kappa}: " + ", ".join(f"{k}: {v:.4f} ms" for k, v in sweep.items()))
+    searcher = ms.Searcher(A, B, params, hits_cap=1 << 14, cand_cap=1 << 20)
+    searcher.run()
+    ms_step_prof, kern = time_search(ms, A, B, searcher, args.steps, args.warmup, profile=True)
     hits, st, _ = searcher.results()
-    log(f"search: {ms_step:.4f} ms/step (profiled), kappa={kappa}, stats={st}")
-    ms_step_np, _ = time_search(ms, A, B, searcher, args.steps, args.warmup, profile=False)
-    log(f"search: {ms_step_np:.4f} ms/step (unprofiled)")
+    log(f"search: {ms_step_prof:.4f} ms/step with per-kernel events, kappa={kappa}, stats={st}")
+    ms_step, _ = time_search(ms, A, B, searcher, args.steps, args.warmup, profile=False)
+    log(f"search: {ms_step:.4f} ms/step (timed region, no events)")
     value = logical_pairs / (ms_step * 1e-3)
 
     kern_avg = {k: sum(v) / len(v) for k, v in kern.items()}
     kern_launches = {k: len(v) / args.steps for k, v in kern.items()}
     kern_total = {k: sum(v) / args.steps for k, v in kern.items()}
-    dominant = max((k for k in kern_total if algorithmic_bytes(k, st, ntot) is not None),
+    dominant = max((k for k in kern_total if algorithmic_bytes(k, st, mesh_sizes) is not None),
                    key=lambda k: kern_total[k])
     dom_ms = kern_avg[dominant]
-    dom_bytes = algorithmic_bytes(dominant, st, ntot)
+    dom_bytes = algorithmic_bytes(dominant, st, mesh_sizes)
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     roofline = {"kernel": dominant, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                "avg_launch_ms": round(dom_ms, 6), "bytes_per_launch": dom_bytes}
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(dominant),
+                "avg_launch_ms": round(dom_ms, 6), "bytes_per_launch": dom_bytes,
+                "source_digest": source_digest()}
 
     out = {
         "metric": METRIC,
@@ -141,10 +193,11 @@ def main():
         "config": {"workload": f"plain search, two seeded torus surfaces of {args.n}x{args.n} quads "
                                f"({A.n_tris} triangles each), FP64, seed {args.seed}",
                    "kappa": kappa, "world_cells": list(params.n_cells)},
-        "ms_per_search_unprofiled": ms_step_np,
-        "kappa_sweep_ms": sweep,
+        "ms_per_step_with_kernel_events": ms_step_prof,
+        "kappa_autotune_ms": sweep,
         "search_stats": st,
         "kernels_ms_avg": {k: round(v, 6) for k, v in kern_avg.items()},
+        "kernels_ms_per_step": {k: round(v, 6) for k, v in kern_total.items()},
         "kernels_launches_per_step": kern_launches,
         "roofline": roofline,
     }
@@ -170,10 +223,9 @@ def main():
     if "family" in legs:
         fam = synth.family(256, args.seed)
         gp = [(ms.Mesh.from_synth(a), ms.Mesh.from_synth(b)) for a, b in fam]
-        srch = []
-        for ga, gb in gp:
-            p = ms.default_params(ga, gb, kappa)
-            srch.append(ms.Searcher(ga, gb, p, hits_cap=1 << 12, cand_cap=1 << 18))
+        fkappa, fparams, fsweep = ms.autotune_batch_kappa(gp)
+        log(f"family: autotuned kappa {fkappa}: " + ", ".join(f"{k}: {v:.3f} ms" for k, v in fsweep.items()))
+        srch = [ms.Searcher(ga, gb, p, hits_cap=1 << 12, cand_cap=1 << 18) for (ga, gb), p in zip(gp, fparams)]
         for s in srch:
             s.run()
         torch.cuda.synchronize()
@@ -183,7 +235,7 @@ def main():
         torch.cuda.synchronize()
         t_f = time.perf_counter() - t0
         plain_stats = [s.results()[1] for s in srch]
-        bt = ms.Batch(gp, [s.params for s in srch], hits_cap=1 << 16, cand_cap=1 << 22)
+        bt = ms.Batch(gp, fparams, hits_cap=1 << 16, cand_cap=1 << 22)
         bt.run_checked(True)
         torch.cuda.synchronize()
         reps = 10
@@ -193,7 +245,9 @@ def main():
         torch.cuda.synchronize()
         t_b = (time.perf_counter() - t0) / reps
         bst = bt.stats_dict()
-        same = all(bst[k] == sum(p[k] for p in plain_stats) for k in ("n_cand", "n_hits", "n_cells", "n_slots"))
+        same = bst["overflow"] == 0 and all(bst[k] == sum(p[k] for p in plain_stats)
+                                            for k in ("n_cand", "n_hits", "n_cells", "n_slots"))
+        out["family_kappa"] = fkappa
         out["family_plain_meshes_per_s"] = len(srch) / t_f
         out["family_plain_ms_total"] = t_f * 1e3
         out["family_batched_meshes_per_s"] = len(srch) / t_b
@@ -202,6 +256,7 @@ def main():
         out["family_batched_counts_equal_plain"] = bool(same)
         out["family_tris_total"] = int(sum(ga.n_tris + gb.n_tris for ga, gb in gp))
         log(f"family: 256 plain searches in {t_f * 1e3:.2f} ms, batched graph {t_b * 1e3:.2f} ms, counts equal={same}")
+        del bt, srch, gp
 
     # ------------------------------------------------------------ RK8 rate
     if "rk8" in legs:
@@ -218,6 +273,61 @@ def main():
         out["rk8_vertex_steps_per_s"] = vsteps / t_rk
         out["rk8_ms_F3_patch"] = t_rk * 1e3
         log(f"rk8: F^3 of {V.shape[0]} vertices in {t_rk * 1e3:.1f} ms")
+
+    # ------------------------- plain device copy (HBM reference, counter scale)
+    if "copy" in legs:
+        nbytes = 1 << 30
+        src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        reps = 10
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        t_c = e0.elapsed_time(e1) / reps * 1e-3
+        out["copy_bytes"] = 2 * nbytes
+        out["copy_GBps"] = 2 * nbytes / t_c / 1e9
+        log(f"copy: {nbytes >> 20} MiB in {t_c * 1e3:.3f} ms -> {2 * nbytes / t_c / 1e9:.1f} GB/s (read+write)")
+        del src, dst
+
+    # ------------------------------- refinement: tangent, adjoint, Newton
+    if "refine" in legs:
+        MU, ECC, STEPS, K = 2.528e-5, 0.0094, 4000, 128
+
+        def gpu_map(x, n):
+            return ms.propagate(torch.tensor(x, device="cuda"), MU, ECC, STEPS, n).cpu().numpy()
+
+        pr = synth.planted_refinement(K, args.seed, gpu_map)
+        U = np.repeat(ms.patch_row(pr.patch_u)[None, :], K, axis=0)
+        S = np.stack([ms.patch_row(p) for p in pr.patches_s])
+        rng = np.random.default_rng(args.seed + 1)
+        x0 = pr.roots + rng.uniform(-1e-4, 1e-4, size=pr.roots.shape)
+        fwd, bwd = ms.MapParams(MU, ECC, STEPS, 3), ms.MapParams(MU, ECC, STEPS, -3)
+        res = {}
+        for name, fn in (("residual", lambda: ms.refine_grad(x0, U, S, fwd, bwd, ms.MS_REFINE_RESIDUAL)),
+                         ("tangent", lambda: ms.refine_grad(x0, U, S, fwd, bwd, ms.MS_REFINE_TANGENT)),
+                         ("adjoint", lambda: ms.refine_grad(x0, U, S, fwd, bwd, ms.MS_REFINE_ADJOINT, 100)),
+                         ("newton", lambda: ms.refine_newton(x0, U, S, fwd, bwd, max_trials=30))):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            res[name] = (time.perf_counter() - t0) * 1e3
+            if name == "newton":
+                xg, _, rg, sg, tg = (t.cpu().numpy() for t in r)
+        out["refine_hits"] = K
+        out["refine_ms"] = {k: round(v, 3) for k, v in res.items()}
+        out["refine_adjoint_grads_per_s"] = K / (res["adjoint"] * 1e-3)
+        out["refine_newton_converged"] = int(np.sum(sg == 0))
+        out["refine_newton_max_trials_used"] = int(tg.max())
+        out["refine_newton_max_root_error"] = float(np.max(np.abs(xg - pr.roots)))
+        log(f"refine: K={K} residual {res['residual']:.1f} ms, tangent {res['tangent']:.1f} ms, adjoint "
+            f"{res['adjoint']:.1f} ms, newton {res['newton']:.1f} ms ({int(np.sum(sg == 0))} converged)")
 
     # ------------------------------------------- CPU oracle baseline (bounded)
     if "cpu" in legs:

@@ -199,6 +199,18 @@ int search_intersections(const ms_mesh *A, const ms_mesh *B, const search_params
                          int64_t *needed, void *stream);
 
 /*
+ * search_intersections_async -- the same search without the final
+ * synchronisation: returns once the kernels are queued on `stream`.  A buffer
+ * overflow is reported only in stats_dev->overflow (bit 0 entries, bit 1
+ * candidates, bit 2 hits); read it after the stream has completed and, if
+ * set, call search_intersections to learn the sizes needed.  For loops that
+ * search repeatedly without host round trips.
+ */
+int search_intersections_async(const ms_mesh *A, const ms_mesh *B, const search_params_t *params, void *ws_dev,
+                               size_t ws_bytes, hit_t *hits_dev, int64_t hits_cap, search_stats_t *stats_dev,
+                               int64_t *cand_dev, int64_t cand_cap, void *stream);
+
+/*
  * narrow_allpairs -- the full pair test (Moller, 4x4 solve, inclusion) on every
  * pair of A x B with no grid and no early exit (the box test is evaluated and
  * folded into the decision): the "tri-pair tests/s" workload.  Hits are
@@ -239,11 +251,13 @@ int batch_needed(const ms_batch *batch, const search_stats_t *stats_host, int64_
 int batch_free(ms_batch *batch);
 
 /*
- * Kernel timing of search_intersections for benchmarks.  While enabled (per
- * calling thread), each search records a HIP event on its stream before every
- * kernel and at its end; search_profile_read returns the names (comma
- * separated) and durations in ms of the kernels of the last search
- * (waiting for its last event).  *n receives the number of kernels.
+ * Kernel timing for benchmarks.  While enabled (per calling thread), every
+ * kernel that mesh_update and the searches queue on an uncaptured stream is
+ * launched with a start and a stop event that take that dispatch's own begin
+ * and end timestamps.  search_profile_read waits for the last of them and
+ * returns the names (comma separated) and durations in ms of the kernels
+ * launched since the previous read (at most cap of them; *n receives the
+ * number), then starts a new record.
  */
 int search_profile_enable(int on);
 int search_profile_read(char *names, size_t names_len, double *ms, int cap, int *n);
@@ -270,6 +284,89 @@ typedef struct {
  */
 int propagate_vertices(const double *in_dev, double *out_dev, int64_t n_vertices,
                        const map_params_t *params, void *stream);
+
+/* ------------------------------------------------------------ refinement */
+
+/*
+ * The refinement problem of Sec. 7.  A hit of the search gives approximate
+ * parameters x = (th1, s1, th2, s2) of a point where the unstable and stable
+ * manifold meshes meet.  With the manifolds represented near the hit by
+ * patches
+ *   x_u(th, s) = U.base + th U.d1 + s U.d2,   x_s(th, s) = S.base + th S.d1 + s S.d2
+ * and pushed by the stroboscopic map (F^{fwd.n_periods} on the unstable side,
+ * F^{bwd.n_periods} on the stable side, usually +3 and -3; the
+ * globalisations of Sec. 4.3), the mismatch is
+ *   f(x) = F^{fwd.n_periods}(x_u(th1, s1)) - F^{bwd.n_periods}(x_s(th2, s2)),
+ * r = |f|^2, and Df = [df/dth1 df/ds1 df/dth2 df/ds2] (Sec. 7).  The
+ * derivative with respect to the eccentricity e (shared by both maps, which
+ * must have the same mu and e) is the fifth column.
+ *
+ * patch_t arrays are device arrays: one patch per hit (patch_stride = 1) or
+ * one patch shared by all hits (patch_stride = 0).
+ */
+typedef struct {
+    double base[4], d1[4], d2[4];
+} patch_t;
+
+enum {
+    MS_REFINE_RESIDUAL = 0,   /* f, r */
+    MS_REFINE_ADJOINT = 1,    /* f, r, grad = dr/d(th1, s1, th2, s2, e) by the discrete adjoint */
+    MS_REFINE_TANGENT = 2,    /* f, r, J = df/d(th1, s1, th2, s2, e) by the variational
+                                 equations, grad = 2 J^T f */
+    MS_REFINE_NEWTON = 3      /* (workspace sizing of refine_newton only) */
+};
+
+/* Workspace bytes of refine_grad (mode 0-2) or refine_newton (mode 3) for K
+ * hits; the adjoint's share grows with K x (steps / ckpt_every + ckpt_every). */
+int refine_workspace_size(int64_t K, const map_params_t *fwd, const map_params_t *bwd, int32_t ckpt_every,
+                          int32_t mode, size_t *bytes);
+
+/*
+ * refine_grad -- mismatch and derivatives for K parameter vectors.
+ *   params_dev  K x 4 doubles (th1, s1, th2, s2).
+ *   f_dev       K x 4 (required for MS_REFINE_ADJOINT, else optional);
+ *   r_dev       K (optional);
+ *   grad_dev    K x 5: dr/d(th1, s1, th2, s2, e) (adjoint and tangent modes);
+ *   J_dev       K x 4 x 5, row-major (tangent mode, optional).
+ * The adjoint runs the map forwards keeping the state every ckpt_every steps,
+ * then backwards through the transpose of every Runge-Kutta step, recomputing
+ * each segment from its checkpoint; the result does not depend on
+ * ckpt_every (bit for bit).  The tangent integrates the variational
+ * equations with the same method, so both give the derivative of the
+ * discrete map.  ws: refine_workspace_size bytes.  Asynchronous on `stream`.
+ */
+int refine_grad(const double *params_dev, int64_t K, const patch_t *U_dev, const patch_t *S_dev,
+                int32_t patch_stride, const map_params_t *fwd, const map_params_t *bwd, int32_t ckpt_every,
+                int32_t mode, double *f_dev, double *r_dev, double *grad_dev, double *J_dev, void *ws,
+                size_t ws_bytes, void *stream);
+
+/*
+ * refine_newton -- damped Newton iteration of Sec. 7,
+ *   x <- x - alpha Df(x)^{-1} f(x),
+ * per hit, from params_in_dev (K x 4) to params_out_dev (K x 4).  alpha
+ * starts at alpha0 after every accepted step and is halved after every trial
+ * point whose r is not below the current one (the current point is kept).
+ * Df is solved by Gaussian elimination with partial pivoting (first row of
+ * largest magnitude).  Per hit the iteration stops with status
+ *   0 converged (|f|^2 <= tol^2), 1 max_trials trial points evaluated,
+ *   2 alpha < alpha_min, 3 Df singular (exact zero pivot),
+ *   4 non-finite mismatch at the start point.
+ * Outputs: the final point, its f (K x 4) and r (K), status and the number of
+ * trial points (K int32 each; f_dev, r_dev, status_dev, trials_dev optional).
+ * Every trial evaluates f and Df at once (tangent pass); the whole iteration
+ * is queued without host synchronisation (max_trials + 1 passes).
+ */
+typedef struct {
+    int32_t max_trials;
+    double tol;
+    double alpha0;
+    double alpha_min;
+} newton_params_t;
+
+int refine_newton(const double *params_in_dev, double *params_out_dev, int64_t K, const patch_t *U_dev,
+                  const patch_t *S_dev, int32_t patch_stride, const map_params_t *fwd, const map_params_t *bwd,
+                  const newton_params_t *np, double *f_dev, double *r_dev, int32_t *status_dev,
+                  int32_t *trials_dev, void *ws, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

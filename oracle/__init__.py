@@ -250,6 +250,106 @@ def mismatch(params: np.ndarray, patch_u, patch_s, mu: float, e: float, steps_pe
     return f, r, J, g
 
 
+def gepp4(M, rhs):
+    """Solve M z = rhs for a 4 x 4 system by Gaussian elimination with partial
+    pivoting, in plain double arithmetic: the pivot of column k is the first
+    row (from k down) of largest magnitude; an exact zero pivot means the
+    system is singular.  Returns (ok, z) with z None when singular."""
+    A = [[float(M[i][j]) for j in range(4)] for i in range(4)]
+    r = [float(x) for x in rhs]
+    for k in range(4):
+        piv, best = k, abs(A[k][k])
+        for i in range(k + 1, 4):
+            if abs(A[i][k]) > best:
+                piv, best = i, abs(A[i][k])
+        if piv != k:
+            A[k], A[piv] = A[piv], A[k]
+            r[k], r[piv] = r[piv], r[k]
+        if A[k][k] == 0.0:
+            return False, None
+        for i in range(k + 1, 4):
+            l = A[i][k] / A[k][k]
+            for j in range(k + 1, 4):
+                A[i][j] = A[i][j] - l * A[k][j]
+            r[i] = r[i] - l * r[k]
+    z = [0.0] * 4
+    for k in range(3, -1, -1):
+        acc = 0.0
+        for j in range(k + 1, 4):
+            acc = acc + A[k][j] * z[j]
+        z[k] = (r[k] - acc) / A[k][k]
+    return True, np.array(z)
+
+
+NEWTON_CONVERGED, NEWTON_LIMIT, NEWTON_STALLED, NEWTON_SINGULAR, NEWTON_NONFINITE = 0, 1, 2, 3, 4
+
+
+def damped_newton(params, patch_u, patch_s, mu: float, e: float, steps_per_period: int, n_u: int, n_s: int,
+                  max_trials: int = 40, tol: float = 1e-12, alpha0: float = 1.0, alpha_min: float = 2.0 ** -30,
+                  history: bool = False):
+    """Damped Newton refinement of mesh hits (paper Sec. 7):
+        x <- x - alpha Df(x)^{-1} f(x),
+    with f the mismatch of `mismatch` and Df its first four Jacobian columns.
+    The paper picks alpha by trial and error; here alpha starts at alpha0
+    after every accepted point and is halved after every trial point whose
+    r = |f|^2 is not below the current r (the current point is kept).  Per
+    row: stop when r <= tol^2 (converged), after max_trials trial points,
+    when alpha < alpha_min, on a singular Df, or on a non-finite f at the
+    start.  patch_u / patch_s: one patch for all rows, or a list with one
+    per row.  Returns (x, f, r, status, trials[, accepted r sequences])."""
+    P = np.ascontiguousarray(params, dtype=np.float64).reshape(-1, 4)
+    K = P.shape[0]
+    xo = np.empty_like(P); fo = np.full((K, 4), np.nan); ro = np.full(K, np.nan)
+    status = np.empty(K, np.int32); trials = np.zeros(K, np.int32)
+    hist = []
+    tol2 = tol * tol
+    for k in range(K):
+        q = P[k].copy()
+        based, st, tr = False, -1, 0
+        p = fp = delta = None
+        rp = alpha = 0.0
+        seq = []
+        pu_k = patch_u[k] if isinstance(patch_u, (list, tuple)) else patch_u
+        ps_k = patch_s[k] if isinstance(patch_s, (list, tuple)) else patch_s
+        while True:
+            f, r, J, _ = mismatch(q[None, :], pu_k, ps_k, mu, e, steps_per_period, n_u, n_s, nthreads=1)
+            f, r, J = f[0], float(r[0]), J[0]
+            if not based:
+                accept = True
+                if not np.isfinite(r):
+                    st = NEWTON_NONFINITE
+            else:
+                tr += 1
+                accept = r < rp
+            if accept and st == -1:
+                p, fp, rp, alpha, based = q.copy(), f.copy(), r, alpha0, True
+                seq.append(r)
+                if r <= tol2:
+                    st = NEWTON_CONVERGED
+                else:
+                    ok, z = gepp4(J[:, :4], -f)
+                    if not ok:
+                        st = NEWTON_SINGULAR
+                    else:
+                        delta = z
+            elif st == -1:
+                alpha = alpha * 0.5
+                if alpha < alpha_min:
+                    st = NEWTON_STALLED
+            if st == -1 and tr >= max_trials:
+                st = NEWTON_LIMIT
+            if st != -1:
+                break
+            q = np.array([p[c] + alpha * delta[c] for c in range(4)])
+        xo[k] = p if based else q
+        if based:
+            fo[k] = fp; ro[k] = rp
+        status[k] = st; trials[k] = tr
+        hist.append(seq)
+    out = (xo, fo, ro, status, trials)
+    return out + (hist,) if history else out
+
+
 def default_grid(meshes, kappa: float):
     """World = box of all finite vertices; edge = kappa x mean over both meshes
     of the triangles' longest 4D edge; cells per axis = max(1, ceil(span x

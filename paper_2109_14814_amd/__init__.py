@@ -22,9 +22,12 @@ MS_SEARCH_CANDIDATES, MS_SEARCH_STRICT = 1, 2
 
 # Exported entry points (the C ABI of include/msearch.h).
 EXPORTS = ("last_error", "mesh_build", "mesh_free", "mesh_info", "mesh_update", "search_default_params",
-           "search_workspace_size", "search_intersections", "narrow_allpairs", "propagate_vertices",
+           "search_workspace_size", "search_intersections", "search_intersections_async", "narrow_allpairs", "propagate_vertices",
            "search_profile_enable", "search_profile_read", "batch_create", "batch_search", "batch_needed",
-           "batch_free")
+           "batch_free", "refine_workspace_size", "refine_grad", "refine_newton")
+
+MS_REFINE_RESIDUAL, MS_REFINE_ADJOINT, MS_REFINE_TANGENT, MS_REFINE_NEWTON = 0, 1, 2, 3
+NEWTON_STATUS = {0: "converged", 1: "trial limit", 2: "step too small", 3: "singular", 4: "non-finite"}
 
 HIT_DTYPE = np.dtype([
     ("triA", np.int32), ("triB", np.int32), ("flags", np.uint32), ("pad", np.uint32),
@@ -57,6 +60,10 @@ class MapParams(C.Structure):
     _fields_ = [("mu", C.c_double), ("e", C.c_double), ("steps_per_period", C.c_int32), ("n_periods", C.c_int32)]
 
 
+class NewtonParams(C.Structure):
+    _fields_ = [("max_trials", C.c_int32), ("tol", C.c_double), ("alpha0", C.c_double), ("alpha_min", C.c_double)]
+
+
 _lib = None
 
 
@@ -78,6 +85,8 @@ def lib():
         L.search_workspace_size.restype = C.c_int
         L.search_intersections.argtypes = [P, P, C.POINTER(SearchParams), P, C.c_size_t, P, I64, P, P, I64, P, P]
         L.search_intersections.restype = C.c_int
+        L.search_intersections_async.argtypes = [P, P, C.POINTER(SearchParams), P, C.c_size_t, P, I64, P, P, I64, P]
+        L.search_intersections_async.restype = C.c_int
         L.narrow_allpairs.argtypes = [P, P, P, I64, P, P, P]; L.narrow_allpairs.restype = C.c_int
         L.propagate_vertices.argtypes = [P, P, I64, C.POINTER(MapParams), P]
         L.propagate_vertices.restype = C.c_int
@@ -90,6 +99,14 @@ def lib():
         L.search_profile_enable.argtypes = [C.c_int]; L.search_profile_enable.restype = C.c_int
         L.search_profile_read.argtypes = [C.c_char_p, C.c_size_t, P, C.c_int, C.POINTER(C.c_int)]
         L.search_profile_read.restype = C.c_int
+        MP = C.POINTER(MapParams)
+        L.refine_workspace_size.argtypes = [I64, MP, MP, I32, I32, C.POINTER(C.c_size_t)]
+        L.refine_workspace_size.restype = C.c_int
+        L.refine_grad.argtypes = [P, I64, P, P, I32, MP, MP, I32, I32, P, P, P, P, P, C.c_size_t, P]
+        L.refine_grad.restype = C.c_int
+        L.refine_newton.argtypes = [P, P, I64, P, P, I32, MP, MP, C.POINTER(NewtonParams), P, P, P, P, P,
+                                    C.c_size_t, P]
+        L.refine_newton.restype = C.c_int
         _lib = L
     return _lib
 
@@ -226,6 +243,22 @@ class Searcher:
             rc = self._call(needed)
         _check(rc)
 
+    def run_async(self) -> None:
+        """Queue one search without waiting (overflow only in the stats;
+        check_overflow() after synchronising)."""
+        cand_ptr = C.c_void_p(self.cand.data_ptr()) if self.cand is not None else None
+        _check(lib().search_intersections_async(self.A.handle, self.B.handle, C.byref(self.params),
+                                                C.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+                                                C.c_void_p(self.hits.data_ptr()), self.hits_cap,
+                                                C.c_void_p(self.stats.data_ptr()), cand_ptr, self.cand_cap, _stream()))
+
+    def check_overflow(self) -> None:
+        """Raise if the last search overflowed a buffer."""
+        st = _stats_dict(self.stats)
+        if st["overflow"]:
+            raise MSearchError(MS_E_CAPACITY, f"search overflowed its buffers (flags {st['overflow']}); "
+                                              "run() grows them")
+
     def results(self):
         """(hits structured array sorted by (triA, triB), stats dict, candidates or None)."""
         st = _stats_dict(self.stats)
@@ -238,12 +271,63 @@ class Searcher:
         return hits, st, cand
 
 
+KAPPAS = (0.5, 0.75, 1.0, 1.5, 2.0, 3.0, 4.0)
+
+
+def _time_ms(fn, reps: int) -> float:
+    torch = _torch()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def autotune_kappa(A: Mesh, B: Mesh, kappas=KAPPAS, reps: int = 10, tie: float = 0.03,
+                   hits_cap: int = 1 << 14, cand_cap: int = 1 << 20):
+    """Cell-edge autotuner for one mesh pair.  The grid of Sec. 6.2.1 only
+    needs cells larger than the triangles; the edge is kappa x the mean
+    triangle diameter, and the result set does not depend on it.  Times the
+    search at every kappa and returns the smallest kappa within `tie` of the
+    fastest (so that near-ties resolve the same way every run), its
+    parameters and the timings {kappa: ms}."""
+    times = {}
+    for k in kappas:
+        s = Searcher(A, B, default_params(A, B, k), hits_cap, cand_cap)
+        s.run()
+        times[k] = _time_ms(s.run_async, reps)
+        s.check_overflow()
+    fastest = min(times.values())
+    kappa = min(k for k in kappas if times[k] <= fastest * (1.0 + tie))
+    return kappa, default_params(A, B, kappa), times
+
+
+def autotune_batch_kappa(pairs, kappas=(1.0, 1.5, 2.0, 3.0), reps: int = 3, tie: float = 0.03,
+                         hits_cap: int = 1 << 16, cand_cap: int = 1 << 22):
+    """The same for a batch of mesh pairs searched together (one kappa for
+    every pair, one captured graph per trial).  Returns (kappa, per-pair
+    parameters, timings)."""
+    times = {}
+    for k in kappas:
+        params = [default_params(a, b, k) for a, b in pairs]
+        bt = Batch(pairs, params, hits_cap=hits_cap, cand_cap=cand_cap)
+        bt.run_checked(True)
+        times[k] = _time_ms(lambda: bt.run(True), reps)
+        del bt
+    fastest = min(times.values())
+    kappa = min(k for k in kappas if times[k] <= fastest * (1.0 + tie))
+    return kappa, [default_params(a, b, kappa) for a, b in pairs], times
+
+
 def profile_enable(on: bool = True):
     _check(lib().search_profile_enable(int(bool(on))))
 
 
 def profile_read():
-    """[(kernel name, ms)] of the last search while profiling was enabled."""
+    """[(kernel name, ms)] of every kernel launched by mesh updates and searches
+    since the previous read, while profiling is enabled (dispatch timestamps)."""
     cap = 256
     names = C.create_string_buffer(8192)
     arr = (C.c_double * cap)()
@@ -334,7 +418,8 @@ class Batch:
 
 
 def narrow_allpairs(A: Mesh, B: Mesh, hits_cap: int = 1 << 16):
-    """All pairs with the full test on every pair: (hits sorted by (triA, triB), stats)."""
+    """All pairs with the full test on every pair: (hits in the order the
+    kernel wrote them, stats)."""
     torch = _torch()
     hits = _dev_bytes(hits_cap * HIT_DTYPE.itemsize)
     nh = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -344,8 +429,7 @@ def narrow_allpairs(A: Mesh, B: Mesh, hits_cap: int = 1 << 16):
     st = _stats_dict(stats)
     n = min(int(nh.item()), hits_cap)
     h = np.frombuffer(hits[: n * HIT_DTYPE.itemsize].cpu().numpy().tobytes(), dtype=HIT_DTYPE)
-    order = np.lexsort((h["triB"], h["triA"]))
-    return h[order], st
+    return h, st
 
 
 def propagate(states, mu: float, e: float, steps_per_period: int, n_periods: int, out=None):
@@ -359,3 +443,119 @@ def propagate(states, mu: float, e: float, steps_per_period: int, n_periods: int
     _check(lib().propagate_vertices(C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()), x.numel() // 4,
                                     C.byref(p), _stream()))
     return out
+
+
+# ------------------------------------------------------------- refinement
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p()
+
+
+def _patches(P):
+    """(12,) or (n, 12) patch rows (base, d1, d2) -> (cuda float64 tensor, stride)."""
+    torch = _torch()
+    t = torch.as_tensor(P, dtype=torch.float64).reshape(-1, 12).to("cuda").contiguous()
+    return t, (0 if t.shape[0] == 1 else 1)
+
+
+def patch_row(patch) -> np.ndarray:
+    """Row (base, d1, d2) of an object with base, d1, d2 attributes."""
+    return np.concatenate([np.asarray(patch.base, np.float64), np.asarray(patch.d1, np.float64),
+                           np.asarray(patch.d2, np.float64)])
+
+
+def refine_grad(params, U, S, fwd: MapParams, bwd: MapParams, mode: int, ckpt_every: int = 100):
+    """Mismatch f, r and (mode) its gradient / Jacobian for K parameter rows
+    (th1, s1, th2, s2): refine_grad of the C ABI.  Returns a dict of cuda
+    tensors: f (K,4), r (K,), grad (K,5) in adjoint and tangent modes, J
+    (K,4,5) in tangent mode."""
+    torch = _torch()
+    x = torch.as_tensor(params, dtype=torch.float64).reshape(-1, 4).to("cuda").contiguous()
+    K = x.shape[0]
+    u, su = _patches(U)
+    v, sv = _patches(S)
+    if su != sv or (su == 1 and (u.shape[0] != K or v.shape[0] != K)):
+        raise ValueError("patches: one shared row each, or one row per hit on both sides")
+    ck = int(ckpt_every) if mode == MS_REFINE_ADJOINT else 1
+    nb = C.c_size_t()
+    _check(lib().refine_workspace_size(K, C.byref(fwd), C.byref(bwd), ck, int(mode), C.byref(nb)))
+    ws = _dev_bytes(nb.value)
+    out = {"f": torch.empty((K, 4), dtype=torch.float64, device="cuda"),
+           "r": torch.empty((K,), dtype=torch.float64, device="cuda")}
+    if mode in (MS_REFINE_ADJOINT, MS_REFINE_TANGENT):
+        out["grad"] = torch.empty((K, 5), dtype=torch.float64, device="cuda")
+    if mode == MS_REFINE_TANGENT:
+        out["J"] = torch.empty((K, 4, 5), dtype=torch.float64, device="cuda")
+    _check(lib().refine_grad(_ptr(x), K, _ptr(u), _ptr(v), su, C.byref(fwd), C.byref(bwd), ck, int(mode),
+                             _ptr(out["f"]), _ptr(out["r"]), _ptr(out.get("grad")), _ptr(out.get("J")),
+                             _ptr(ws), nb.value, _stream()))
+    return out
+
+
+def refine_newton(params, U, S, fwd: MapParams, bwd: MapParams, max_trials: int = 40, tol: float = 1e-12,
+                  alpha0: float = 1.0, alpha_min: float = 2.0 ** -30):
+    """Damped Newton refinement of K parameter rows (refine_newton of the C
+    ABI).  Returns (x, f, r, status, trials) as cuda tensors."""
+    torch = _torch()
+    x = torch.as_tensor(params, dtype=torch.float64).reshape(-1, 4).to("cuda").contiguous()
+    K = x.shape[0]
+    u, su = _patches(U)
+    v, sv = _patches(S)
+    if su != sv or (su == 1 and (u.shape[0] != K or v.shape[0] != K)):
+        raise ValueError("patches: one shared row each, or one row per hit on both sides")
+    nb = C.c_size_t()
+    _check(lib().refine_workspace_size(K, C.byref(fwd), C.byref(bwd), 1, MS_REFINE_NEWTON, C.byref(nb)))
+    ws = _dev_bytes(nb.value)
+    xo = torch.empty_like(x)
+    f = torch.empty((K, 4), dtype=torch.float64, device="cuda")
+    r = torch.empty((K,), dtype=torch.float64, device="cuda")
+    st = torch.empty((K,), dtype=torch.int32, device="cuda")
+    tr = torch.empty((K,), dtype=torch.int32, device="cuda")
+    npar = NewtonParams(int(max_trials), float(tol), float(alpha0), float(alpha_min))
+    _check(lib().refine_newton(_ptr(x), _ptr(xo), K, _ptr(u), _ptr(v), su, C.byref(fwd), C.byref(bwd),
+                               C.byref(npar), _ptr(f), _ptr(r), _ptr(st), _ptr(tr), _ptr(ws), nb.value, _stream()))
+    return xo, f, r, st, tr
+
+
+def _mismatch_fn():
+    torch = _torch()
+
+    class MismatchFn(torch.autograd.Function):
+        """r = |F^{n_u}(x_u(th1, s1)) - F^{n_s}(x_s(th2, s2))|^2 per row of
+        params, as a differentiable function of params (K, 4) and the
+        eccentricity e (0-dim tensor).  forward: refine_grad residual mode;
+        backward: the discrete adjoint (refine_grad adjoint mode)."""
+
+        @staticmethod
+        def forward(ctx, params, e, U, S, mu, steps_per_period, n_u, n_s, ckpt_every):
+            ev = float(e.detach().cpu())
+            fwd = MapParams(float(mu), ev, int(steps_per_period), int(n_u))
+            bwd = MapParams(float(mu), ev, int(steps_per_period), int(n_s))
+            out = refine_grad(params.detach(), U, S, fwd, bwd, MS_REFINE_RESIDUAL)
+            ctx.save_for_backward(params.detach())
+            ctx.maps = (fwd, bwd, U, S, int(ckpt_every))
+            ctx.e_shape = e.shape
+            return out["r"]
+
+        @staticmethod
+        def backward(ctx, grad_r):
+            (params,) = ctx.saved_tensors
+            fwd, bwd, U, S, ck = ctx.maps
+            g = refine_grad(params, U, S, fwd, bwd, MS_REFINE_ADJOINT, ck)["grad"]
+            gr = grad_r.to(g.dtype)
+            g_params = gr[:, None] * g[:, :4]
+            g_e = (gr * g[:, 4]).sum().reshape(ctx.e_shape)
+            return g_params, g_e, None, None, None, None, None, None, None
+
+    return MismatchFn
+
+
+_MISMATCH = None
+
+
+def mismatch_r(params, e, U, S, mu: float, steps_per_period: int, n_u: int, n_s: int, ckpt_every: int = 100):
+    """Differentiable r (K,) through MismatchFn (adjoint backward)."""
+    global _MISMATCH
+    if _MISMATCH is None:
+        _MISMATCH = _mismatch_fn()
+    return _MISMATCH.apply(params, e, U, S, mu, steps_per_period, n_u, n_s, ckpt_every)

@@ -153,7 +153,7 @@ int launch_boxes(ms_mesh *m, hipStream_t st)
     int64_t g = ceil_div(mv.n_tris > 0 ? mv.n_tris : 1, MB_BLOCK);
     if (g > MB_GRID) g = MB_GRID;
     m->n_partials = (int)g;
-    hipLaunchKernelGGL(k_tri_boxes, dim3((unsigned)g), dim3(MB_BLOCK), 0, st, mv, m->box, (Partial *)m->scratch);
+    MS_LAUNCH("k_tri_boxes", k_tri_boxes, dim3((unsigned)g), dim3(MB_BLOCK), 0, st, mv, m->box, (Partial *)m->scratch);
     MS_HIP(hipGetLastError());
     MS_HIP(hipEventRecord(m->boxes_done, st));
     m->info_stale = 1;

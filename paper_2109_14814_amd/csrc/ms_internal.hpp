@@ -2,6 +2,7 @@
 // libmsearch.so (never installed; the public ABI is include/msearch.h).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string>
@@ -193,12 +194,21 @@ int launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st);
 
 // ------------------------------------------------------------- profiling
 
-// When enabled (search_profile_enable), the search records a HIP event on
-// its stream before every kernel and once at the end; search_profile_read
-// turns consecutive events into per-kernel durations.
-void prof_begin(hipStream_t st);
-void prof_mark(const char *name, hipStream_t st);
-void prof_end(hipStream_t st);
+// Kernel timing for benchmarks.  While enabled (search_profile_enable),
+// prof_pair hands out a start / stop event pair for the next kernel of an
+// uncaptured stream; MS_LAUNCH then launches that kernel with
+// hipExtLaunchKernelGGL, so the two events carry the dispatch's own start and
+// end timestamps.  Otherwise MS_LAUNCH is a plain launch.
+bool prof_pair(const char *name, hipStream_t st, hipEvent_t *start, hipEvent_t *stop);
+
+#define MS_LAUNCH(NAME, KERNEL, GRID, BLOCKDIM, SHMEM, STREAM, ...)                                          \
+    do {                                                                                                     \
+        hipEvent_t ms_e0_, ms_e1_;                                                                           \
+        if (::ms::prof_pair(NAME, STREAM, &ms_e0_, &ms_e1_))                                                 \
+            hipExtLaunchKernelGGL(KERNEL, GRID, BLOCKDIM, SHMEM, STREAM, ms_e0_, ms_e1_, 0, __VA_ARGS__);     \
+        else                                                                                                 \
+            hipLaunchKernelGGL(KERNEL, GRID, BLOCKDIM, SHMEM, STREAM, __VA_ARGS__);                          \
+    } while (0)
 
 }  // namespace ms
 

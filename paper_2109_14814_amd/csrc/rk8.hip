@@ -14,27 +14,14 @@
 #include <tuple>
 #include <vector>
 
-#include "ms_internal.hpp"
+#include "rk8_core.hpp"
 
 namespace ms {
 
 namespace {
 
-constexpr int S = 11;
+constexpr int S = RK_S;
 constexpr int RK_BLOCK = 128;
-
-struct Tableau {
-    double a[S][S];
-    double b[S];
-    double c[S];
-};
-
-// Non-zero pattern of the Cooper-Verner tableau (used to drop the zero terms
-// at compile time; the values themselves come from make_tableau).
-constexpr bool NZ[S][S] = {
-    {0}, {1}, {1, 1}, {1, 1, 1}, {1, 0, 1, 1}, {1, 0, 1, 1, 1}, {1, 0, 1, 1, 1, 1},
-    {1, 0, 0, 0, 1, 1, 1}, {1, 0, 0, 0, 1, 1, 1, 1}, {1, 0, 0, 0, 1, 1, 1, 1, 1}, {0, 0, 0, 0, 1, 1, 1, 1, 1, 1}};
-constexpr bool NZB[S] = {1, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1};
 
 // Cooper & Verner (1972), SIAM J. Numer. Anal. 9, order-8 method with 11
 // stages; coefficients in Q(sqrt 21), evaluated once in double precision.
@@ -66,43 +53,49 @@ Tableau make_tableau()
     return T;
 }
 
-// The pattern must describe the values exactly (checked once on the host).
-bool pattern_matches(const Tableau &T)
-{
-    for (int i = 0; i < S; ++i) {
-        for (int j = 0; j < S; ++j)
-            if ((T.a[i][j] != 0.0) != (j < i && NZ[i][j])) return false;
-        if ((T.b[i] != 0.0) != NZB[i]) return false;
-    }
-    return true;
-}
+// Stage tables per (device, e, steps per period, kind), kept for the life of
+// the process.
+std::mutex g_tab_mu;
+std::map<std::tuple<int, uint64_t, int, int>, double *> g_tabs;
 
-const Tableau &tableau()
+}  // namespace
+
+const Tableau &cv_tableau()
 {
     static const Tableau T = make_tableau();
     return T;
 }
 
-// Stage-weight tables per (device, e, steps per period), kept for the life of
-// the process.
-std::mutex g_tab_mu;
-std::map<std::tuple<int, uint64_t, int>, double *> g_tabs;
+bool cv_pattern_ok()
+{
+    const Tableau &T = cv_tableau();
+    for (int i = 0; i < S; ++i) {
+        for (int j = 0; j < S; ++j)
+            if ((T.a[i][j] != 0.0) != (j < i && RK_NZ[i][j])) return false;
+        if ((T.b[i] != 0.0) != RK_NZB[i]) return false;
+    }
+    return true;
+}
 
-int omega_table(double e, int steps, double **out)
+int stage_table(double e, int steps, int kind, double **out)
 {
     int dev = 0;
     MS_HIP(hipGetDevice(&dev));
     uint64_t eb;
     memcpy(&eb, &e, 8);
     std::lock_guard<std::mutex> lk(g_tab_mu);
-    auto key = std::make_tuple(dev, eb, steps);
+    auto key = std::make_tuple(dev, eb, steps, kind);
     auto it = g_tabs.find(key);
     if (it != g_tabs.end()) { *out = it->second; return MS_OK; }
-    const Tableau &T = tableau();
-    const double h = 6.283185307179586476925286766559 / (double)steps;
+    const Tableau &T = cv_tableau();
+    const double h = RK_TWO_PI / (double)steps;
     std::vector<double> w((size_t)steps * S);
     for (int n = 0; n < steps; ++n)
-        for (int i = 0; i < S; ++i) w[(size_t)n * S + i] = 1.0 / (1.0 + e * cos((double)n * h + T.c[i] * h));
+        for (int i = 0; i < S; ++i) {
+            double cf = cos((double)n * h + T.c[i] * h);
+            double om = 1.0 / (1.0 + e * cf);
+            w[(size_t)n * S + i] = kind == STAGE_W ? om : -cf * om * om;
+        }
     double *d = nullptr;
     MS_HIP(hipMalloc(&d, w.size() * sizeof(double)));
     hipError_t er = hipMemcpy(d, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice);
@@ -112,27 +105,7 @@ int omega_table(double e, int steps, double **out)
     return MS_OK;
 }
 
-struct Model {
-    double mu, one_minus_mu;
-};
-
-// Right-hand side at stage weight w: (x', y', w Omega_x + 2 y', w Omega_y - 2 x').
-MS_D void field(const Model &md, double w, const double y[4], double k[4])
-{
-#pragma clang fp contract(fast)
-    double x = y[0], yy = y[1];
-    double dx1 = x + md.mu, dx2 = x - md.one_minus_mu;
-    double yy2 = yy * yy;
-    double r1s = dx1 * dx1 + yy2, r2s = dx2 * dx2 + yy2;
-    double r1 = sqrt(r1s), r2 = sqrt(r2s);
-    double g1 = md.one_minus_mu / (r1s * r1), g2 = md.mu / (r2s * r2);
-    double Ox = x - g1 * dx1 - g2 * dx2;
-    double Oy = yy - (g1 + g2) * yy;
-    k[0] = y[2];
-    k[1] = y[3];
-    k[2] = 2.0 * y[3] + w * Ox;
-    k[3] = -2.0 * y[2] + w * Oy;
-}
+namespace {
 
 __global__ void __launch_bounds__(RK_BLOCK) k_rk8_map(const double *__restrict__ in, double *__restrict__ out,
                                                       int64_t n, Model md, Tableau T, const double *__restrict__ wtab,
@@ -155,17 +128,17 @@ __global__ void __launch_bounds__(RK_BLOCK) k_rk8_map(const double *__restrict__
                 double acc = 0.0;
 #pragma unroll
                 for (int j = 0; j < i; ++j)
-                    if (NZ[i][j]) acc += T.a[i][j] * k[j][c];
+                    if (RK_NZ[i][j]) acc += T.a[i][j] * k[j][c];
                 ys[c] = y[c] + h * acc;
             }
-            field(md, w[i], ys, k[i]);
+            rk_field(md, w[i], ys, k[i]);
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             double acc = 0.0;
 #pragma unroll
             for (int i = 0; i < S; ++i)
-                if (NZB[i]) acc += T.b[i] * k[i][c];
+                if (RK_NZB[i]) acc += T.b[i] * k[i][c];
             y[c] = y[c] + h * acc;
         }
         if (++n_in == steps) n_in = 0;
@@ -189,10 +162,10 @@ extern "C" int propagate_vertices(const double *in_dev, double *out_dev, int64_t
     if (!(p->e >= 0.0 && p->e < 1.0) || !(p->mu >= 0.0 && p->mu <= 1.0))
         return fail(MS_E_ARG, "propagate_vertices: need 0 <= e < 1 and 0 <= mu <= 1");
     if (n_vertices == 0) return MS_OK;
-    if (!pattern_matches(tableau())) return fail(MS_E_ARG, "propagate_vertices: internal tableau pattern mismatch");
+    if (!cv_pattern_ok()) return fail(MS_E_ARG, "propagate_vertices: internal tableau pattern mismatch");
     hipStream_t st = (hipStream_t)stream;
     double *wtab = nullptr;
-    int rc = omega_table(p->e, p->steps_per_period, &wtab);
+    int rc = stage_table(p->e, p->steps_per_period, STAGE_W, &wtab);
     if (rc) return rc;
     int np = p->n_periods < 0 ? -p->n_periods : p->n_periods;
     int64_t nsteps = (int64_t)p->steps_per_period * np;
@@ -204,7 +177,7 @@ extern "C" int propagate_vertices(const double *in_dev, double *out_dev, int64_t
     }
     Model md{p->mu, 1.0 - p->mu};
     hipLaunchKernelGGL(k_rk8_map, dim3((unsigned)ceil_div(n_vertices, RK_BLOCK)), dim3(RK_BLOCK), 0, st, in_dev,
-                       out_dev, n_vertices, md, tableau(), wtab, p->steps_per_period, nsteps, h);
+                       out_dev, n_vertices, md, cv_tableau(), wtab, p->steps_per_period, nsteps, h);
     MS_HIP(hipGetLastError());
     return MS_OK;
 }

@@ -1074,7 +1074,6 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
     radix_ws_carve(rp, ws + L.o_sort);
     const int R = 1 << rp.rb;
 
-    prof_begin(st);
     // 1. clear: counters, flags, sort histograms and tile counters, k_cells
     //    counter (and, with no sort pass, k_cells' words)
     ClearSpec cs;
@@ -1087,8 +1086,7 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
     cs.hist_words = (int64_t)rp.passes * R;
     cs.ctrs = rp.tile_ctr;
     cs.ctr_words = rp.passes;
-    prof_mark("k_prepare", st);
-    hipLaunchKernelGGL(k_prepare, dim3(grid_for(cs.flag_words, 1024)), dim3(BLOCK), 0, st, cs);
+    MS_LAUNCH("k_prepare", k_prepare, dim3(grid_for(cs.flag_words, 1024)), dim3(BLOCK), 0, st, cs);
     ClearSpec cs2;
     memset(&cs2, 0, sizeof cs2);
     cs2.ctrs = ctrs;
@@ -1097,10 +1095,9 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
         cs2.kstat = cstat;
         cs2.kstat_words = 2 * rp.tiles_cap;
     }
-    hipLaunchKernelGGL(k_prepare, dim3(grid_for(cs2.kstat_words + 16, 256)), dim3(BLOCK), 0, st, cs2);
+    MS_LAUNCH("k_prepare", k_prepare, dim3(grid_for(cs2.kstat_words + 16, 256)), dim3(BLOCK), 0, st, cs2);
     const unsigned g_tri = grid_for(G.n_tri);
-    prof_mark("k_mark", st);
-    hipLaunchKernelGGL(k_mark<ONE>, dim3(g_tri), dim3(BLOCK), 0, st, bv, flags, rng, mpart);
+    MS_LAUNCH("k_mark", k_mark<ONE>, dim3(g_tri), dim3(BLOCK), 0, st, bv, flags, rng, mpart);
     KeysOut ko;
     ko.keys = keys;
     ko.cap = L.ent_cap;
@@ -1115,10 +1112,8 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
     ko.stats = stats;
     ko.mark_partial = mpart;
     ko.n_mark_partial = (int)g_tri;
-    prof_mark("k_count", st);
-    hipLaunchKernelGGL(k_count<ONE>, dim3((unsigned)L.n_kblocks), dim3(BLOCK), 0, st, bv, flags, rng, ko);
-    prof_mark("k_emit", st);
-    hipLaunchKernelGGL(k_emit<ONE>, dim3((unsigned)L.n_kblocks), dim3(BLOCK), 0, st, bv, flags, rng, ko);
+    MS_LAUNCH("k_count", k_count<ONE>, dim3((unsigned)L.n_kblocks), dim3(BLOCK), 0, st, bv, flags, rng, ko);
+    MS_LAUNCH("k_emit", k_emit<ONE>, dim3((unsigned)L.n_kblocks), dim3(BLOCK), 0, st, bv, flags, rng, ko);
     MS_HIP(hipGetLastError());
     uint64_t *sorted = keys;
     if ((rc = radix_sort(rp, keys, alt, misc, cstat, 2, st, &sorted))) return rc;
@@ -1128,29 +1123,24 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
     co.cstat = cstat;
     co.tile_ctr = ctrs;
     co.stats = stats;
-    prof_mark("k_cells", st);
     {
         int64_t g = rp.tiles_cap < 1024 ? rp.tiles_cap : 1024;
-        hipLaunchKernelGGL(k_cells<ONE>, dim3((unsigned)g), dim3(BLOCK), 0, st, bv, sorted, misc, co);
+        MS_LAUNCH("k_cells", k_cells<ONE>, dim3((unsigned)g), dim3(BLOCK), 0, st, bv, sorted, misc, co);
     }
-    prof_mark("k_enum", st);
-    hipLaunchKernelGGL(k_enum<ONE>, dim3(MAX_GRID), dim3(BLOCK), 0, st, bv, sorted, cells, pstart, stats, cand, cpair,
+    MS_LAUNCH("k_enum", k_enum<ONE>, dim3(MAX_GRID), dim3(BLOCK), 0, st, bv, sorted, cells, pstart, stats, cand, cpair,
                        cand_cap);
-    prof_mark("k_narrow", st);
-    hipLaunchKernelGGL(k_narrow<ONE>, dim3(MAX_GRID), dim3(BLOCK), 0, st, bv, cand, cpair, cand_cap, htmp, hkeys,
+    MS_LAUNCH("k_narrow", k_narrow<ONE>, dim3(MAX_GRID), dim3(BLOCK), 0, st, bv, cand, cpair, cand_cap, htmp, hkeys,
                        hits_cap, stats);
     MS_HIP(hipGetLastError());
     if (hits_cap > 0) {
         if ((rc = sort_unique_small(hkeys, halt, hkeys, &stats->n_hits, hits_cap, 0, G.pb + G.tbA + G.tbB, st))) return rc;
-        prof_mark("k_hits_place", st);
-        hipLaunchKernelGGL(k_hits_place, dim3(grid_for(hits_cap, 256)), dim3(BLOCK), 0, st, htmp, hkeys, &stats->n_hits,
+        MS_LAUNCH("k_hits_place", k_hits_place, dim3(grid_for(hits_cap, 256)), dim3(BLOCK), 0, st, htmp, hkeys, &stats->n_hits,
                            hits_cap, G.tbA, G.tbB, hits_dev);
         if (pair_offs)
-            hipLaunchKernelGGL(k_pair_offsets, dim3(grid_for(G.n_pairs + 1, 64)), dim3(BLOCK), 0, st, hkeys,
+            MS_LAUNCH("k_pair_offsets", k_pair_offsets, dim3(grid_for(G.n_pairs + 1, 64)), dim3(BLOCK), 0, st, hkeys,
                                &stats->n_hits, hits_cap, (int)G.n_pairs, G.tbA + G.tbB, pair_offs);
         MS_HIP(hipGetLastError());
     }
-    prof_end(st);
     return MS_OK;
 }
 
@@ -1218,14 +1208,19 @@ extern "C" int search_workspace_size(const ms_mesh *A, const ms_mesh *B, const s
     return MS_OK;
 }
 
-extern "C" int search_intersections(const ms_mesh *A, const ms_mesh *B, const search_params_t *params, void *ws_dev,
-                                    size_t ws_bytes, hit_t *hits_dev, int64_t hits_cap, search_stats_t *stats_dev,
-                                    int64_t *cand_dev, int64_t cand_cap, int64_t *needed, void *stream)
+namespace ms {
+namespace {
+
+// Checks the arguments and queues one plain search (shared by the
+// synchronous and the asynchronous entry points).
+int search_queue(const ms_mesh *A, const ms_mesh *B, const search_params_t *params, void *ws_dev, size_t ws_bytes,
+                 hit_t *hits_dev, int64_t hits_cap, search_stats_t *stats_dev, int64_t *cand_dev, int64_t cand_cap,
+                 int64_t *needed, void *stream, Geometry &G, Layout &L, bool &want_cand)
 {
     if (!A || !B || !params || !stats_dev || (!ws_dev && ws_bytes)) return fail(MS_E_ARG, "search_intersections: NULL argument");
     if (hits_cap < 0 || cand_cap < 0) return fail(MS_E_ARG, "search_intersections: negative capacity");
     if (hits_cap > 0 && !hits_dev) return fail(MS_E_ARG, "search_intersections: hits_dev is NULL");
-    const bool want_cand = (params->flags & MS_SEARCH_CANDIDATES) != 0;
+    want_cand = (params->flags & MS_SEARCH_CANDIDATES) != 0;
     if (want_cand && cand_cap > 0 && !cand_dev) return fail(MS_E_ARG, "search_intersections: cand_dev is NULL");
     if (params->flags & MS_SEARCH_STRICT) {
         ms_mesh_info_t ia, ib;
@@ -1235,11 +1230,9 @@ extern "C" int search_intersections(const ms_mesh *A, const ms_mesh *B, const se
         if (ia.n_nonfinite || ib.n_nonfinite)
             return fail(MS_E_NONFINITE, "search_intersections: non-finite triangles with MS_SEARCH_STRICT");
     }
-    Geometry G;
     int rc = geometry(1, &A, &B, params, G);
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
-    Layout L;
     memset(&L, 0, sizeof L);
     L.cand_cap = want_cand ? 0 : cand_cap;
     L.hits_cap = hits_cap;
@@ -1250,13 +1243,39 @@ extern "C" int search_intersections(const ms_mesh *A, const ms_mesh *B, const se
     char *ws = (char *)ws_dev;
     const PairDesc p0 = make_desc(A, B, params, 0, 0);
     const BatchView bv = make_view(G, p0, ws, L);
-    if ((rc = enqueue<true>(G, L, bv, ws, hits_dev, hits_cap, stats_dev, want_cand ? (uint64_t *)cand_dev : nullptr,
-                            cand_cap, nullptr, st)))
-        return rc;
+    return enqueue<true>(G, L, bv, ws, hits_dev, hits_cap, stats_dev, want_cand ? (uint64_t *)cand_dev : nullptr,
+                         cand_cap, nullptr, st);
+}
+
+}  // namespace
+}  // namespace ms
+
+extern "C" int search_intersections(const ms_mesh *A, const ms_mesh *B, const search_params_t *params, void *ws_dev,
+                                    size_t ws_bytes, hit_t *hits_dev, int64_t hits_cap, search_stats_t *stats_dev,
+                                    int64_t *cand_dev, int64_t cand_cap, int64_t *needed, void *stream)
+{
+    Geometry G;
+    Layout L;
+    bool want_cand = false;
+    int rc = search_queue(A, B, params, ws_dev, ws_bytes, hits_dev, hits_cap, stats_dev, cand_dev, cand_cap, needed,
+                          stream, G, L, want_cand);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
     search_stats_t hs;
     MS_HIP(hipMemcpyAsync(&hs, stats_dev, sizeof hs, hipMemcpyDeviceToHost, st));
     MS_HIP(hipStreamSynchronize(st));
     return check_status(hs, G, L, hits_cap, cand_cap, want_cand, needed);
+}
+
+extern "C" int search_intersections_async(const ms_mesh *A, const ms_mesh *B, const search_params_t *params,
+                                          void *ws_dev, size_t ws_bytes, hit_t *hits_dev, int64_t hits_cap,
+                                          search_stats_t *stats_dev, int64_t *cand_dev, int64_t cand_cap, void *stream)
+{
+    Geometry G;
+    Layout L;
+    bool want_cand = false;
+    return search_queue(A, B, params, ws_dev, ws_bytes, hits_dev, hits_cap, stats_dev, cand_dev, cand_cap, nullptr,
+                        stream, G, L, want_cand);
 }
 
 extern "C" int narrow_allpairs(const ms_mesh *A, const ms_mesh *B, hit_t *hits_dev, int64_t hits_cap,
@@ -1459,50 +1478,32 @@ namespace {
 
 struct Profiler {
     bool on = false;
-    bool open = false;
     std::vector<const char *> names;
-    std::vector<hipEvent_t> events;   // pool, grows on demand
-    size_t used = 0;
+    std::vector<hipEvent_t> events;   // start / stop pairs, grows on demand
+    size_t used = 0;                  // pairs handed out since the last read
 };
 
 thread_local Profiler g_prof;
 
-void prof_record(const char *name, hipStream_t st)
+}  // namespace
+
+bool prof_pair(const char *name, hipStream_t st, hipEvent_t *start, hipEvent_t *stop)
 {
     Profiler &P = g_prof;
+    if (!P.on) return false;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return;
-    if (P.used == P.events.size()) {
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return false;
+    while (P.events.size() < 2 * (P.used + 1)) {
         hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) { P.on = false; return; }
+        if (hipEventCreate(&e) != hipSuccess) { P.on = false; return false; }
         P.events.push_back(e);
     }
     if (P.names.size() < P.used + 1) P.names.resize(P.used + 1);
     P.names[P.used] = name;
-    (void)hipEventRecord(P.events[P.used], st);
+    *start = P.events[2 * P.used];
+    *stop = P.events[2 * P.used + 1];
     ++P.used;
-}
-
-}  // namespace
-
-void prof_begin(hipStream_t)
-{
-    if (!g_prof.on) return;
-    g_prof.used = 0;
-    g_prof.open = true;
-}
-
-void prof_mark(const char *name, hipStream_t st)
-{
-    if (g_prof.on && g_prof.open) prof_record(name, st);
-}
-
-void prof_end(hipStream_t st)
-{
-    if (g_prof.on && g_prof.open) {
-        prof_record("end", st);
-        g_prof.open = false;
-    }
+    return true;
 }
 
 }  // namespace ms
@@ -1510,7 +1511,6 @@ void prof_end(hipStream_t st)
 extern "C" int search_profile_enable(int on)
 {
     ms::g_prof.on = on != 0;
-    ms::g_prof.open = false;
     ms::g_prof.used = 0;
     return MS_OK;
 }
@@ -1519,18 +1519,19 @@ extern "C" int search_profile_read(char *names, size_t names_len, double *ms_out
 {
     if (!n_out || (cap > 0 && !ms_out)) return ms::fail(MS_E_ARG, "search_profile_read: NULL argument");
     ms::Profiler &P = ms::g_prof;
-    int n = P.used > 0 ? (int)P.used - 1 : 0;
+    int n = (int)P.used;
     *n_out = n;
     if (n == 0) return MS_OK;
-    MS_HIP(hipEventSynchronize(P.events[P.used - 1]));
+    MS_HIP(hipEventSynchronize(P.events[2 * (P.used - 1) + 1]));
     std::string csv;
     for (int i = 0; i < n && i < cap; ++i) {
         float t = 0.f;
-        MS_HIP(hipEventElapsedTime(&t, P.events[i], P.events[i + 1]));
+        MS_HIP(hipEventElapsedTime(&t, P.events[2 * i], P.events[2 * i + 1]));
         ms_out[i] = t;
         if (i) csv += ",";
         csv += P.names[i];
     }
+    P.used = 0;
     if (names && names_len) {
         size_t k = csv.size() < names_len - 1 ? csv.size() : names_len - 1;
         memcpy(names, csv.data(), k);

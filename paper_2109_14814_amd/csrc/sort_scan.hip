@@ -507,15 +507,14 @@ int radix_sort(const RadixPlan &p, uint64_t *keys, uint64_t *alt, const int64_t 
         uint32_t *next = q + 1 < p.passes ? stat + (size_t)p.tiles_cap * r : nullptr;
         uint64_t *ex = q + 1 == p.passes ? extra : nullptr;
         int shift = p.lo_bit + p.rb * q;
-        prof_mark("k_radix_onesweep", st);
         if (p.rb == 8)
-            hipLaunchKernelGGL(k_radix_onesweep<8>, dim3((unsigned)g), dim3(SORT_BLOCK), 0, st, src, dst, n_dev, shift,
+            MS_LAUNCH("k_radix_onesweep", k_radix_onesweep<8>, dim3((unsigned)g), dim3(SORT_BLOCK), 0, st, src, dst, n_dev, shift,
                                p.hist + q * r, stat, next, p.tile_ctr + q, ex, extra_per_tile);
         else if (p.rb == 9)
-            hipLaunchKernelGGL(k_radix_onesweep<9>, dim3((unsigned)g), dim3(SORT_BLOCK), 0, st, src, dst, n_dev, shift,
+            MS_LAUNCH("k_radix_onesweep", k_radix_onesweep<9>, dim3((unsigned)g), dim3(SORT_BLOCK), 0, st, src, dst, n_dev, shift,
                                p.hist + q * r, stat, next, p.tile_ctr + q, ex, extra_per_tile);
         else
-            hipLaunchKernelGGL(k_radix_onesweep<10>, dim3((unsigned)g), dim3(SORT_BLOCK), 0, st, src, dst, n_dev,
+            MS_LAUNCH("k_radix_onesweep", k_radix_onesweep<10>, dim3((unsigned)g), dim3(SORT_BLOCK), 0, st, src, dst, n_dev,
                                shift, p.hist + q * r, stat, next, p.tile_ctr + q, ex, extra_per_tile);
         MS_HIP(hipGetLastError());
         uint64_t *t = src; src = dst; dst = t;
@@ -530,13 +529,11 @@ int sort_unique_small(const uint64_t *in, uint64_t *tmp, uint64_t *out, const in
     if (cap <= 0) return MS_OK;
     int passes = n_bits <= 0 ? 0 : (n_bits + RB - 1) / RB;
     int64_t chunks = ceil_div(cap, SORT_TILE);
-    prof_mark("k_sort_chunks", st);
-    hipLaunchKernelGGL(k_sort_chunks, dim3((unsigned)chunks), dim3(SORT_BLOCK), 0, st, in, tmp, out, n_dev, cap, lo_bit,
+    MS_LAUNCH("k_sort_chunks", k_sort_chunks, dim3((unsigned)chunks), dim3(SORT_BLOCK), 0, st, in, tmp, out, n_dev, cap, lo_bit,
                        passes);
     int64_t g = ceil_div(cap, SORT_BLOCK);
     if (g > 1024) g = 1024;
-    prof_mark("k_merge_rank", st);
-    hipLaunchKernelGGL(k_merge_rank, dim3((unsigned)g), dim3(SORT_BLOCK), 0, st, tmp, out, n_dev, cap);
+    MS_LAUNCH("k_merge_rank", k_merge_rank, dim3((unsigned)g), dim3(SORT_BLOCK), 0, st, tmp, out, n_dev, cap);
     MS_HIP(hipGetLastError());
     return MS_OK;
 }

@@ -223,3 +223,31 @@ def random_states(n: int, seed: int, center=UNSTABLE_BASE, spread: float = 1e-2)
     rng = np.random.default_rng(seed)
     c = np.asarray(center, dtype=np.float64)
     return np.ascontiguousarray(c[None, :] + rng.uniform(-spread, spread, size=(n, 4)))
+
+
+# ---------------------------------------------------------------------------
+# Planted refinement problems (known roots of the mismatch)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class PlantedRefinement:
+    patch_u: Patch            # shared unstable-side patch
+    patches_s: list           # one stable-side patch per root
+    roots: np.ndarray         # (K, 4) parameters (th1, s1, th2, s2) of the planted roots
+    n_periods: int            # the roots solve F^n(x_u) = F^-n(x_s)
+
+
+def planted_refinement(K: int, seed: int, map_forward, n_periods: int = 3, spread: float = 5e-4):
+    """K refinement problems with known roots: points p_k = x_u(th1_k, s1_k)
+    of the unstable patch are drawn; the k-th stable patch is centred at
+    F^{2n}(p_k), so that F^n(x_u(th1_k, s1_k)) = F^-n(x_s(0, 0)) up to the
+    integration error.  `map_forward(states, n_periods)` evaluates F^n on an
+    (m, 4) array (the caller supplies it; this module draws numbers only)."""
+    (_, pu), (_, ps) = propagated_patches(2, 2, seed)
+    rng = np.random.default_rng(seed + 100)
+    stars = rng.uniform(-spread, spread, size=(K, 2))
+    xu = pu.base[None, :] + stars[:, :1] * pu.d1[None, :] + stars[:, 1:2] * pu.d2[None, :]
+    y = np.asarray(map_forward(xu, 2 * n_periods), dtype=np.float64).reshape(K, 4)
+    patches = [Patch(y[k].copy(), ps.d1.copy(), ps.d2.copy()) for k in range(K)]
+    roots = np.concatenate([stars, np.zeros((K, 2))], axis=1)
+    return PlantedRefinement(pu, patches, roots, n_periods)
