@@ -258,21 +258,47 @@ def main():
         log(f"family: 256 plain searches in {t_f * 1e3:.2f} ms, batched graph {t_b * 1e3:.2f} ms, counts equal={same}")
         del bt, srch, gp
 
-    # ------------------------------------------------------------ RK8 rate
+    # ---------------- propagated patches: F^+-3, boxes, search, refinement
     if "rk8" in legs:
-        (mu_mesh, _), _ = synth.propagated_patches(2048, 256, args.seed)
-        V = torch.as_tensor(mu_mesh.verts.reshape(-1, 4)).cuda()
-        out_t = torch.empty_like(V)
-        ms.propagate(V[:1024], 2.528e-5, 0.0094, 4000, 1, out=out_t[:1024])
+        MU, ECC, STEPS = 2.528e-5, 0.0094, 4000
+        gmap = lambda x, n: ms.propagate(torch.tensor(np.ascontiguousarray(x)).cuda(), MU, ECC, STEPS, n)
+        pr = synth.planted_refinement(1, args.seed, lambda x, n: gmap(x, n).cpu().numpy())
+        mu_mesh = synth.patch_vertices(pr.patch_u, 2049, 257)
+        ms_mesh = synth.patch_vertices(pr.patches_s[0], 2049, 257)
+        gu, gs = ms.Mesh.from_synth(mu_mesh), ms.Mesh.from_synth(ms_mesh)
+        base_u, base_s = gu.verts.clone(), gs.verts.clone()
+        ms.propagate(base_u.view(-1, 4)[:1024], MU, ECC, STEPS, 1)    # stage table, warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ms.propagate(V, 2.528e-5, 0.0094, 4000, 3, out=out_t)
+        ms.propagate(base_u.view(-1, 4), MU, ECC, STEPS, 3, out=gu.verts.view(-1, 4))
+        ms.propagate(base_s.view(-1, 4), MU, ECC, STEPS, -3, out=gs.verts.view(-1, 4))
         torch.cuda.synchronize()
         t_rk = time.perf_counter() - t0
-        vsteps = V.shape[0] * 4000 * 3
+        t0 = time.perf_counter()
+        gu.update(); gs.update()
+        pp = ms.default_params(gu, gs, kappa)
+        sp = ms.Searcher(gu, gs, pp, hits_cap=1 << 14, cand_cap=1 << 22)
+        sp.run()
+        hp, stp, _ = sp.results()
+        t_s = time.perf_counter() - t0
+        x0 = np.stack([hp["thA"], hp["sA"], hp["thB"], hp["sB"]], axis=1)
+        t0 = time.perf_counter()
+        xr, _, rr, sr, tr = ms.refine_newton(x0, ms.patch_row(pr.patch_u), ms.patch_row(pr.patches_s[0]),
+                                             ms.MapParams(MU, ECC, STEPS, 3), ms.MapParams(MU, ECC, STEPS, -3),
+                                             max_trials=30)
+        sr = sr.cpu().numpy()
+        t_r = time.perf_counter() - t0
+        vsteps = 2 * base_u.numel() // 4 * STEPS * 3
         out["rk8_vertex_steps_per_s"] = vsteps / t_rk
-        out["rk8_ms_F3_patch"] = t_rk * 1e3
-        log(f"rk8: F^3 of {V.shape[0]} vertices in {t_rk * 1e3:.1f} ms")
+        out["rk8_ms_F3_and_Fm3_two_patches"] = t_rk * 1e3
+        out["propagated_search_ms_incl_setup"] = t_s * 1e3
+        out["propagated_hits"] = int(len(hp))
+        out["propagated_refine_ms"] = t_r * 1e3
+        out["propagated_refined_converged"] = int(np.sum(sr == 0))
+        out["propagated_root_error"] = float(np.max(np.abs(xr.cpu().numpy() - pr.roots[0]))) if len(hp) else None
+        log(f"propagated: F^3 + F^-3 of 2 x {base_u.numel() // 4} vertices in {t_rk * 1e3:.1f} ms, search "
+            f"{t_s * 1e3:.2f} ms ({len(hp)} hits), refine {t_r * 1e3:.1f} ms ({int(np.sum(sr == 0))} converged)")
+        del gu, gs, base_u, base_s, sp
 
     # ------------------------- plain device copy (HBM reference, counter scale)
     if "copy" in legs:

@@ -163,6 +163,17 @@ class Mesh:
         """Recompute the triangle boxes after self.verts changed in place."""
         _check(lib().mesh_update(self.handle, _stream()))
 
+    def info(self) -> dict:
+        """Counts, bounds and mean triangle diameter (mesh_info; waits for a
+        pending update)."""
+        inf = MeshInfo()
+        _check(lib().mesh_info(self.handle, C.byref(inf)))
+        self.lo = np.array(inf.lo[:]); self.hi = np.array(inf.hi[:])
+        self.mean_diam = float(inf.mean_diam)
+        self.n_nonfinite = int(inf.n_nonfinite)
+        return {"n_tris": int(inf.n_tris), "n_nonfinite": self.n_nonfinite, "lo": self.lo, "hi": self.hi,
+                "mean_diam": self.mean_diam}
+
     @classmethod
     def from_synth(cls, m, layout: int = MS_LAYOUT_AOS):
         return cls(m.verts, m.theta, m.s, m.periodic, layout)

@@ -1,0 +1,110 @@
+"""The propagated-mesh path (Sec. 4.3 feeding Sec. 6.2 and Sec. 7) on the GPU.
+
+Small patches: the unstable patch pushed by F^3 and a planted stable patch
+pulled back by F^-3, both propagated by the oracle, are searched by the GPU
+and by the oracle on the same vertex bytes (index sets bit-exact).  Full-size
+patches (2049 x 257 vertices each): the GPU propagates, updates the boxes,
+searches and refines; results are checked by properties that hold at any
+size (independence of the cell edge, A/B transposition, hits next to the
+planted point, Newton converging to the planted root)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+MU, ECC = 2.528e-5, 0.0094
+
+
+@pytest.fixture(scope="module")
+def ms():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2109_14814_amd as ms
+    ms.lib()
+    return ms
+
+
+def _pairs(h):
+    return (h["triA"].astype(np.int64) << 32) | h["triB"].astype(np.int64)
+
+
+def propagated(mesh, mapper, n):
+    v = mapper(mesh.verts.reshape(-1, 4), n).reshape(mesh.verts.shape)
+    return synth.Mesh(np.ascontiguousarray(v), mesh.theta.copy(), mesh.s.copy(), False)
+
+
+def oracle_pair(nq_t, nq_s, seed, steps):
+    mapper = lambda x, n: oracle.rk8_map(x, MU, ECC, steps, n)
+    pr = synth.planted_refinement(1, seed, mapper)
+    U = synth.patch_vertices(pr.patch_u, nq_t + 1, nq_s + 1)
+    S = synth.patch_vertices(pr.patches_s[0], nq_t + 1, nq_s + 1)
+    return propagated(U, mapper, 3), propagated(S, mapper, -3), pr
+
+
+@pytest.mark.parametrize("nq,kappa", [((96, 24), 1.0), ((160, 40), 2.0)])
+def test_small_propagated_patches_match_oracle(ms, nq, kappa):
+    A, B, pr = oracle_pair(nq[0], nq[1], 3, 4000)
+    grid = oracle.default_grid([A, B], kappa)
+    ref = oracle.grid_search(A, B, grid[0], grid[2], grid[3])
+    brute = oracle.bruteforce(A, B)
+    assert np.array_equal(ref.cand, brute.cand) and np.array_equal(ref.hit_pairs, brute.hit_pairs)
+    ga, gb = ms.Mesh.from_synth(A), ms.Mesh.from_synth(B)
+    s = ms.Searcher(ga, gb, ms.make_params(grid[0], grid[2], grid[3], ms.MS_SEARCH_CANDIDATES))
+    s.run()
+    hits, st, cand = s.results()
+    assert np.array_equal(np.sort(cand), ref.cand)
+    assert np.array_equal(_pairs(hits), ref.hit_pairs)
+    for f in ("u", "v", "a", "b", "thA", "sA", "thB", "sB", "margin"):
+        assert np.max(np.abs(hits[f] - ref.hits[f])) <= 1e-10
+    assert len(hits) > 0
+    # the hits sit next to the planted point: (th1*, s1*) on A, (0, 0) on B
+    star = pr.roots[0]
+    assert np.max(np.abs(hits["thA"] - star[0])) < 4 * 2e-3 / nq[0] + 1e-6
+    assert np.max(np.abs(hits["sA"] - star[1])) < 4 * 2e-3 / nq[1] + 1e-6
+
+
+def test_full_size_propagated_search_and_refinement(ms):
+    """The propagated-patch workload at full size: 2049 x 257 vertices per
+    patch (2^20 triangles each), F^3 and F^-3 on the GPU at 4000 steps per
+    period, boxes updated in place, searched at two cell edges and both
+    orders, and the hits refined by damped Newton."""
+    import torch
+    steps = 4000
+    gmap = lambda x, n: ms.propagate(torch.as_tensor(np.ascontiguousarray(x)).cuda(), MU, ECC, steps, n)
+    pr = synth.planted_refinement(1, 4, lambda x, n: gmap(x, n).cpu().numpy())
+    U = synth.patch_vertices(pr.patch_u, 2049, 257)
+    S = synth.patch_vertices(pr.patches_s[0], 2049, 257)
+    ga, gb = ms.Mesh.from_synth(U), ms.Mesh.from_synth(S)
+    for g, n in ((ga, 3), (gb, -3)):
+        flat = g.verts.view(-1, 4)
+        ms.propagate(flat, MU, ECC, steps, n, out=flat)
+        g.update()
+    assert ga.info()["n_tris"] == 2048 * 256 * 2
+    results = []
+    for kappa in (1.0, 3.0):
+        s = ms.Searcher(ga, gb, ms.default_params(ga, gb, kappa), hits_cap=1 << 14, cand_cap=1 << 22)
+        s.run()
+        hits, st, _ = s.results()
+        results.append((hits, st))
+    (h1, s1), (h2, s2) = results
+    assert np.array_equal(_pairs(h1), _pairs(h2)) and s1["n_cand"] == s2["n_cand"]
+    assert len(h1) > 0
+    sw = ms.Searcher(gb, ga, ms.default_params(gb, ga, 1.0), hits_cap=1 << 14, cand_cap=1 << 22)
+    sw.run()
+    hb, stb, _ = sw.results()
+    t = np.sort((hb["triB"].astype(np.int64) << 32) | hb["triA"].astype(np.int64))
+    assert np.array_equal(t, _pairs(h1)) and stb["n_cand"] == s1["n_cand"]
+    # the mesh hits seed the refinement, which lands on the planted root
+    x0 = np.stack([h1["thA"], h1["sA"], h1["thB"], h1["sB"]], axis=1)
+    star = pr.roots[0]
+    assert np.max(np.abs(x0 - star), axis=0).max() < 1e-4
+    fwd, bwd = ms.MapParams(MU, ECC, steps, 3), ms.MapParams(MU, ECC, steps, -3)
+    xr, fr, rr, sr, tr = ms.refine_newton(x0, ms.patch_row(pr.patch_u), ms.patch_row(pr.patches_s[0]), fwd, bwd,
+                                          max_trials=30)
+    sr, xr = sr.cpu().numpy(), xr.cpu().numpy()
+    assert np.all(sr == 0)
+    assert np.max(np.abs(xr - star)) < 1e-10
