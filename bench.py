@@ -41,17 +41,17 @@ def algorithmic_bytes(kernel: str, st: dict, mesh_sizes) -> float | None:
     """Bytes a kernel must move per launch, each byte counted once (no
     re-reads): the per-unit figures times the units of one launch."""
     E, nc, C, H = st["n_entries"], st["n_cells"], st["n_cand"], st["n_hits"]
+    nall = st.get("n_cells_all", nc)
     ntot = sum(nt for nt, _ in mesh_sizes)
-    nt1, nv1 = mesh_sizes[0]
+    nvtot = sum(nv for _, nv in mesh_sizes)
     table = {
-        "k_tri_boxes": 32.0 * nv1 + 64.0 * nt1,      # one mesh: vertices read once, boxes written
-        "k_mark": 72.0 * ntot,                       # triangle boxes read, compact cell ranges written
-        "k_count": 12.0 * ntot,                      # cell ranges read, counts written
-        "k_emit": 12.0 * ntot + 8.0 * E,             # counts + cell ranges read, keys written
-        "k_radix_onesweep": 16.0 * E,                # keys read + written
-        "k_cells": 8.0 * E + 40.0 * nc,              # keys read, cell records + slot offsets written
-        "k_enum": 8.0 * E + 40.0 * nc + 64.0 * E + 12.0 * C,   # keys, cells, boxes once, candidates
-        "k_narrow": C * (12.0 + 192.0) + 120.0 * H,  # candidates, 6 vertices, hit records
+        "k_mark": 32.0 * nvtot + 8.0 * ntot,          # vertices read once, compact cell ranges written
+        "k_keys": 8.0 * ntot + 8.0 * E,               # cell ranges read, keys written
+        "k_radix_onesweep": 16.0 * E,                 # keys read + written
+        "k_cells_scan": 8.0 * E + 8.0 * nall,         # keys read, cell bounds written
+        "k_cells_keep": 8.0 * nall + 40.0 * nc,       # cell bounds read, cell records + slot offsets written
+        "k_enum": 16.0 * E + 40.0 * nc + 12.0 * C,    # keys and ranges of the entries, cells, candidates
+        "k_narrow": C * (12.0 + 192.0) + 120.0 * H,   # candidates, 6 vertices, hit records
     }
     return table.get(kernel)
 

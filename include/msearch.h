@@ -62,8 +62,7 @@ enum {
 };
 
 /*
- * mesh_build -- triangulate a vertex grid W(theta_i, s_k) (Sec. 6.1) and
- * compute every triangle's 4D axis-aligned bounding box (Sec. 6.2.2).
+ * mesh_build -- triangulate a vertex grid W(theta_i, s_k) (Sec. 6.1).
  *
  * Quad (i, k) joins W(i,k), W(i+1,k), W(i,k+1), W(i+1,k+1); when periodic
  * != 0, i+1 is taken mod n_theta_v (theta_N = theta_0 + 2 pi) so there are
@@ -74,10 +73,11 @@ enum {
  *   T2: p1 = W(i,k+1), p2 = W(i+1,k+1), p3 = W(i+1,k)
  * theta_host[n_theta_v] and s_host[n_s_v] are the sample values used for the
  * (theta, s) estimates of hits; they are copied.  A triangle with a
- * non-finite coordinate is flagged and takes no part in any search.
- * Allocates the handle's device buffers (64 B per triangle); synchronises
- * `stream` before returning.  A grid with fewer than 2 vertices along s (or
- * along a non-periodic theta) has no triangles and is valid.
+ * non-finite coordinate takes no part in any search.  The triangles' 4D
+ * boxes (Sec. 6.2.2) are not stored: every kernel that needs one computes it
+ * from the three vertices.  Runs the statistics pass of mesh_info and
+ * synchronises `stream` before returning.  A grid with fewer than 2 vertices
+ * along s (or along a non-periodic theta) has no triangles and is valid.
  */
 int mesh_build(const double *verts_dev, int32_t n_theta_v, int32_t n_s_v, int32_t periodic,
                int32_t layout, const double *theta_host, const double *s_host, void *stream,
@@ -93,13 +93,16 @@ typedef struct {
     double mean_diam;      /* mean over finite triangles of the longest 4D edge */
 } ms_mesh_info_t;
 
-/* Bounds, diameter and counts of a mesh (waits for a pending mesh_update). */
+/* Bounds, diameter and counts of a mesh.  After mesh_update this runs the
+ * statistics pass on the stream given there and synchronises it. */
 int mesh_info(const ms_mesh *mesh, ms_mesh_info_t *out);
 
 /*
- * mesh_update -- recompute the triangle boxes after the caller changed the
- * vertex values in place (same grid, same buffer; e.g. after
- * propagate_vertices).  Asynchronous on `stream`; allocates nothing.
+ * mesh_update -- tell the handle that the caller changed the vertex values
+ * in place (same grid, same buffer; e.g. after propagate_vertices on
+ * `stream`).  Searches read the current vertices anyway; this only marks the
+ * statistics of mesh_info (and so search_default_params) for recomputation on
+ * `stream`.  Queues nothing and allocates nothing.
  */
 int mesh_update(ms_mesh *mesh, void *stream);
 
@@ -161,7 +164,8 @@ typedef struct {
     int64_t n_hits;          /* |H| */
     int64_t n_nonfinite;     /* triangles of A and B excluded */
     int64_t overflow;        /* bit 0: entries > capacity, bit 1: cand, bit 2: hits */
-    int64_t reserved[5];
+    int64_t n_cells_all;     /* distinct cells of the filtered entries (one-mesh cells included) */
+    int64_t reserved[4];     /* zero */
 } search_stats_t;
 
 /*
@@ -252,7 +256,7 @@ int batch_free(ms_batch *batch);
 
 /*
  * Kernel timing for benchmarks.  While enabled (per calling thread), every
- * kernel that mesh_update and the searches queue on an uncaptured stream is
+ * kernel that mesh_info and the searches queue on an uncaptured stream is
  * launched with a start and a stop event that take that dispatch's own begin
  * and end timestamps.  search_profile_read waits for the last of them and
  * returns the names (comma separated) and durations in ms of the kernels

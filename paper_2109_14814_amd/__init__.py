@@ -37,7 +37,7 @@ HIT_DTYPE = np.dtype([
     ("margin", np.float64),
 ])
 STATS_FIELDS = ("n_entries", "n_entries_all", "n_cells", "n_slots", "n_cand", "n_moller", "n_degenerate",
-                "n_outside", "n_hits", "n_nonfinite", "overflow")
+                "n_outside", "n_hits", "n_nonfinite", "overflow", "n_cells_all")
 
 
 class MSearchError(RuntimeError):

@@ -1,5 +1,6 @@
-// mesh.hip -- mesh handles: triangulation of a vertex grid (Sec. 6.1) and
-// per-triangle 4D bounding boxes (Sec. 6.2.2); error reporting of the ABI.
+// mesh.hip -- mesh handles: triangulation of a vertex grid (Sec. 6.1), the
+// mesh statistics used to plan a grid (bounds, mean triangle diameter), and
+// error reporting of the ABI.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -47,10 +48,10 @@ __global__ void __launch_bounds__(MB_BLOCK) k_soa_to_aos(const double *soa, doub
     }
 }
 
-// Per-triangle box (exact min / max per axis); NaN-filled if any vertex
-// coordinate is not finite.  Also accumulates, per block, the longest-edge
-// sum, the counts of finite and non-finite triangles and the bounds of the
-// finite triangles.
+// Statistics of a mesh for grid planning: bounds of the finite triangles'
+// vertices, the sum of their longest 4D edges and the counts of finite and
+// non-finite triangles, as per-block partials.  (The boxes themselves are
+// never stored: the search recomputes them from the vertices.)
 struct Partial {
     double lo[4], hi[4];
     double diam_sum;
@@ -58,7 +59,7 @@ struct Partial {
     long long pad;
 };
 
-__global__ void __launch_bounds__(MB_BLOCK) k_tri_boxes(MeshView m, double *box, Partial *part)
+__global__ void __launch_bounds__(MB_BLOCK) k_mesh_stats(MeshView m, Partial *part)
 {
     __shared__ double s_lo[4][MB_BLOCK / WAVE], s_hi[4][MB_BLOCK / WAVE], s_sum[MB_BLOCK / WAVE];
     __shared__ long long s_fin[MB_BLOCK / WAVE], s_bad[MB_BLOCK / WAVE];
@@ -77,24 +78,17 @@ __global__ void __launch_bounds__(MB_BLOCK) k_tri_boxes(MeshView m, double *box,
         for (int j = 0; j < 3; ++j)
 #pragma unroll
             for (int d = 0; d < 4; ++d) fin = fin && isfinite(a[j][d]);
-        double bl[4], bh[4];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-            double l = a[0][d], h = a[0][d];
-            if (a[1][d] < l) l = a[1][d];
-            if (a[2][d] < l) l = a[2][d];
-            if (a[1][d] > h) h = a[1][d];
-            if (a[2][d] > h) h = a[2][d];
-            bl[d] = fin ? l : NAN;
-            bh[d] = fin ? h : NAN;
-            if (fin) { lo[d] = fmin(lo[d], l); hi[d] = fmax(hi[d], h); }
-        }
-        double2 *o = reinterpret_cast<double2 *>(box + 8 * t);
-        o[0] = make_double2(bl[0], bl[1]);
-        o[1] = make_double2(bl[2], bl[3]);
-        o[2] = make_double2(bh[0], bh[1]);
-        o[3] = make_double2(bh[2], bh[3]);
         if (fin) {
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                double l = a[0][d], h = a[0][d];
+                if (a[1][d] < l) l = a[1][d];
+                if (a[2][d] < l) l = a[2][d];
+                if (a[1][d] > h) h = a[1][d];
+                if (a[2][d] > h) h = a[2][d];
+                lo[d] = fmin(lo[d], l);
+                hi[d] = fmax(hi[d], h);
+            }
             double e = 0.0;
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
@@ -146,27 +140,20 @@ __global__ void __launch_bounds__(MB_BLOCK) k_tri_boxes(MeshView m, double *box,
 namespace ms {
 namespace {
 
-// Queue the box pass of mesh m on stream st (asynchronous).
-int launch_boxes(ms_mesh *m, hipStream_t st)
-{
-    const MeshView &mv = m->view;
-    int64_t g = ceil_div(mv.n_tris > 0 ? mv.n_tris : 1, MB_BLOCK);
-    if (g > MB_GRID) g = MB_GRID;
-    m->n_partials = (int)g;
-    MS_LAUNCH("k_tri_boxes", k_tri_boxes, dim3((unsigned)g), dim3(MB_BLOCK), 0, st, mv, m->box, (Partial *)m->scratch);
-    MS_HIP(hipGetLastError());
-    MS_HIP(hipEventRecord(m->boxes_done, st));
-    m->info_stale = 1;
-    return MS_OK;
-}
-
-// Wait for the last box pass and reduce its per-block partials on the host.
+// Statistics pass of mesh m on stream st, then the host reduction of its
+// per-block partials (synchronises st).
 int reduce_info(ms_mesh *m)
 {
     if (!m->info_stale) return MS_OK;
-    MS_HIP(hipEventSynchronize(m->boxes_done));
-    std::vector<Partial> hp((size_t)m->n_partials);
-    MS_HIP(hipMemcpy(hp.data(), m->scratch, hp.size() * sizeof(Partial), hipMemcpyDeviceToHost));
+    const MeshView &mv = m->view;
+    hipStream_t st = m->upd_stream;
+    int64_t g = ceil_div(mv.n_tris > 0 ? mv.n_tris : 1, MB_BLOCK);
+    if (g > MB_GRID) g = MB_GRID;
+    MS_LAUNCH("k_mesh_stats", k_mesh_stats, dim3((unsigned)g), dim3(MB_BLOCK), 0, st, mv, (Partial *)m->scratch);
+    MS_HIP(hipGetLastError());
+    std::vector<Partial> hp((size_t)g);
+    MS_HIP(hipMemcpyAsync(hp.data(), m->scratch, hp.size() * sizeof(Partial), hipMemcpyDeviceToHost, st));
+    MS_HIP(hipStreamSynchronize(st));
     ms_mesh_info_t &inf = m->info;
     inf.n_tris = m->view.n_tris;
     for (int d = 0; d < 4; ++d) { inf.lo[d] = INFINITY; inf.hi[d] = -INFINITY; }
@@ -225,8 +212,6 @@ extern "C" int mesh_build(const double *verts_dev, int32_t n_theta_v, int32_t n_
         hipLaunchKernelGGL(k_soa_to_aos, dim3((unsigned)g), dim3(MB_BLOCK), 0, st, verts_dev, m->owned_V, nv);
         V = m->owned_V;
     }
-    size_t box_bytes = (size_t)(ntri > 0 ? ntri : 1) * 64;
-    if ((e = hipMalloc(&m->box, box_bytes)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc boxes"));
     if ((e = hipMalloc(&m->theta_dev, (size_t)(n_theta_v > 0 ? n_theta_v : 1) * 8)) != hipSuccess)
         return cleanup(hip_fail(e, "hipMalloc theta"));
     if ((e = hipMalloc(&m->s_dev, (size_t)(n_s_v > 0 ? n_s_v : 1) * 8)) != hipSuccess)
@@ -234,8 +219,6 @@ extern "C" int mesh_build(const double *verts_dev, int32_t n_theta_v, int32_t n_
     if ((e = hipMalloc(&m->scratch, (size_t)(MB_GRID * sizeof(Partial) + MS_COUNT_PARTIALS * 8 + 256))) != hipSuccess)
         return cleanup(hip_fail(e, "hipMalloc scratch"));
     m->counter = (int64_t *)((char *)m->scratch + MB_GRID * sizeof(Partial));
-    if ((e = hipEventCreateWithFlags(&m->boxes_done, hipEventDisableTiming)) != hipSuccess)
-        return cleanup(hip_fail(e, "hipEventCreate"));
     if (n_theta_v > 0 && (e = hipMemcpyAsync(m->theta_dev, theta_host, (size_t)n_theta_v * 8, hipMemcpyHostToDevice, st)) != hipSuccess)
         return cleanup(hip_fail(e, "copy theta"));
     if (n_s_v > 0 && (e = hipMemcpyAsync(m->s_dev, s_host, (size_t)n_s_v * 8, hipMemcpyHostToDevice, st)) != hipSuccess)
@@ -243,7 +226,6 @@ extern "C" int mesh_build(const double *verts_dev, int32_t n_theta_v, int32_t n_
 
     MeshView &mv = m->view;
     mv.V = V;
-    mv.box = m->box;
     mv.theta = m->theta_dev;
     mv.s = m->s_dev;
     mv.n_theta_v = n_theta_v;
@@ -252,9 +234,10 @@ extern "C" int mesh_build(const double *verts_dev, int32_t n_theta_v, int32_t n_
     mv.periodic = periodic ? 1 : 0;
     mv.n_tris = (int32_t)ntri;
 
-    int rc = launch_boxes(m, st);
+    m->upd_stream = st;
+    m->info_stale = 1;
+    int rc = reduce_info(m);
     if (rc) return cleanup(rc);
-    if ((rc = reduce_info(m))) return cleanup(rc);
     *out = m;
     return MS_OK;
 }
@@ -263,11 +246,9 @@ extern "C" int mesh_free(ms_mesh *m)
 {
     if (!m) return MS_OK;
     if (m->owned_V) (void)hipFree(m->owned_V);
-    if (m->box) (void)hipFree(m->box);
     if (m->theta_dev) (void)hipFree(m->theta_dev);
     if (m->s_dev) (void)hipFree(m->s_dev);
     if (m->scratch) (void)hipFree(m->scratch);
-    if (m->boxes_done) (void)hipEventDestroy(m->boxes_done);
     delete m;
     return MS_OK;
 }
@@ -275,7 +256,9 @@ extern "C" int mesh_free(ms_mesh *m)
 extern "C" int mesh_update(ms_mesh *m, void *stream)
 {
     if (!m) return fail(MS_E_ARG, "mesh_update: NULL mesh");
-    return launch_boxes(m, (hipStream_t)stream);
+    m->upd_stream = (hipStream_t)stream;
+    m->info_stale = 1;
+    return MS_OK;
 }
 
 extern "C" int mesh_info(const ms_mesh *m, ms_mesh_info_t *out)
@@ -292,13 +275,13 @@ extern "C" int search_default_params(const ms_mesh *A, const ms_mesh *B, double 
     if (!A || !B || !out) return fail(MS_E_ARG, "search_default_params: NULL argument");
     if (!(kappa > 0.0) || !isfinite(kappa)) return fail(MS_E_ARG, "search_default_params: kappa must be > 0");
     memset(out, 0, sizeof *out);
+    int rc;
+    if ((rc = reduce_info(const_cast<ms_mesh *>(A))) || (rc = reduce_info(const_cast<ms_mesh *>(B)))) return rc;
     double lo[4], hi[4];
     for (int d = 0; d < 4; ++d) {
         lo[d] = fmin(A->info.lo[d], B->info.lo[d]);
         hi[d] = fmax(A->info.hi[d], B->info.hi[d]);
     }
-    int rc;
-    if ((rc = reduce_info(const_cast<ms_mesh *>(A))) || (rc = reduce_info(const_cast<ms_mesh *>(B)))) return rc;
     int64_t na = A->info.n_tris - A->info.n_nonfinite, nb = B->info.n_tris - B->info.n_nonfinite;
     double diam = (na + nb) > 0 ? (A->info.mean_diam * (double)na + B->info.mean_diam * (double)nb) / (double)(na + nb) : 0.0;
     double edge = kappa * diam;

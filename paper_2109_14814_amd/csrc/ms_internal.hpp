@@ -33,7 +33,6 @@ int hip_fail(hipError_t e, const char *what);
 // Device view of a triangulated vertex grid (see mesh_build in msearch.h).
 struct MeshView {
     const double *V;       // AoS vertices, 4 doubles each, theta index fastest
-    const double *box;     // per triangle: lo[4], hi[4]; NaN-filled when non-finite
     const double *theta;   // n_theta_v samples
     const double *s;       // n_s_v samples
     int32_t n_theta_v, n_s_v;
@@ -64,6 +63,31 @@ MS_D d4 load_d4(const double *p)
     const double2 *q = reinterpret_cast<const double2 *>(p);
     double2 a = q[0], b = q[1];
     return d4{a.x, a.y, b.x, b.y};
+}
+
+// 4D box of triangle t (exact min / max per axis of its three vertices,
+// Sec. 6.2.2), computed from the vertices wherever it is needed; false when a
+// coordinate is not finite (such a triangle takes no part in a search).
+MS_D bool tri_box(const MeshView &m, int32_t t, double lo[4], double hi[4])
+{
+    int32_t i1, i2, i3;
+    tri_vertex_ids(m, t, i1, i2, i3);
+    const d4 a = load_d4(m.V + 4 * (int64_t)i1), b = load_d4(m.V + 4 * (int64_t)i2),
+             c = load_d4(m.V + 4 * (int64_t)i3);
+    const double va[4] = {a.x, a.y, a.z, a.w}, vb[4] = {b.x, b.y, b.z, b.w}, vc[4] = {c.x, c.y, c.z, c.w};
+    bool fin = true;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        double l = va[d], h = va[d];
+        if (vb[d] < l) l = vb[d];
+        if (vc[d] < l) l = vc[d];
+        if (vb[d] > h) h = vb[d];
+        if (vc[d] > h) h = vc[d];
+        lo[d] = l;
+        hi[d] = h;
+        fin = fin && isfinite(va[d]) && isfinite(vb[d]) && isfinite(vc[d]);
+    }
+    return fin;
 }
 
 typedef double dvec2 __attribute__((ext_vector_type(2)));
@@ -218,12 +242,11 @@ constexpr int MS_COUNT_PARTIALS = 2048;
 struct ms_mesh {
     ms::MeshView view;
     double *owned_V;          // AoS copy for MS_LAYOUT_SOA
-    double *box;              // device, 8 doubles per triangle
     double *theta_dev, *s_dev;
-    int64_t *scratch;         // small device scratch: per-block partials of the box pass
+    int64_t *scratch;         // small device scratch: per-block partials of the statistics pass
     int64_t *counter;         // MS_COUNT_PARTIALS device words (entry counting of workspace queries)
-    hipEvent_t boxes_done;    // recorded after the box pass
-    int info_stale;           // bounds / diameter not reduced since the last box pass
+    hipStream_t upd_stream;   // stream of the last mesh_update (vertex values changed there)
+    int info_stale;           // bounds / diameter not reduced since the vertices last changed
     ms_mesh_info_t info;
     int device;
     int n_partials;

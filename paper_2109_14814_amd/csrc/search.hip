@@ -4,22 +4,24 @@
 // Every kernel reads its sizes from device memory, so one call queues a fixed
 // sequence of kernels with no host round trip (and can be captured in a HIP
 // graph):
-//   k_prepare   clear counters, occupancy flags and look-back words
-//   k_mark      per triangle: overlapped cells of its pair's grid (Sec. 6.2.1),
-//               one occupancy flag per (hashed) cell and side, compact range
-//   k_count     per triangle: cells that the other mesh also touches (a box
-//               with triangles of one mesh only cannot hold a pair)
-//   k_emit      keys [cell | side | triangle] at scanned offsets, digit
-//               histograms for the sort
-//   radix sort  onesweep passes, cells grouped (A's entries before B's)
-//   k_cells     per cell holding both meshes: start, nA, nB, pair; slot
-//               offsets sum(nA * nB) by a look-back scan
-//   k_enum      slot -> (cell, iA, iB); a pair is kept only in its home cell
-//               (cell of the componentwise max of the boxes' lower corners)
-//               and only if the closed boxes overlap (Sec. 6.2.2)
-//   k_narrow    Moller quick test (Sec. 6.2.3), 4x4 solve and inclusion
-//               (Sec. 6.2.4), hit records
-//   sort        hits by (pair, triA, triB)
+//   k_prepare     clear counters, occupancy flags and look-back words
+//   k_mark        per triangle: its box from the vertices (Sec. 6.2.2), the
+//                 overlapped cells of its pair's grid (Sec. 6.2.1), one
+//                 occupancy flag per (hashed) cell and side, compact range
+//   k_keys        per triangle: the cells that the other mesh also touches
+//                 (a box with triangles of one mesh only cannot hold a pair);
+//                 keys [cell | side | triangle] at offsets from a one-pass
+//                 scan; digit histograms for the sort
+//   radix sort    onesweep passes, cells grouped (A's entries before B's)
+//   k_cells_scan  cell starts and A counts of the sorted keys (scan)
+//   k_cells_keep  cells holding both meshes: start, nA, nB, pair; slot
+//                 offsets sum(nA * nB) (scan)
+//   k_enum        slot -> (cell, iA, iB); a pair is kept only in its home cell
+//                 (cell of the componentwise max of the boxes' lower corners)
+//                 and only if the closed boxes overlap (Sec. 6.2.2)
+//   k_narrow      Moller quick test (Sec. 6.2.3), 4x4 solve and inclusion
+//                 (Sec. 6.2.4), hit records
+//   sort          hits by (pair, triA, triB)
 // A batch keys its cells by a per-pair cell offset, so entries of different
 // pairs never share a cell.
 #include <math.h>
@@ -38,8 +40,8 @@ namespace {
 constexpr int BLOCK = 256;
 constexpr int MAX_GRID = 2048;
 static_assert(MAX_GRID <= MS_COUNT_PARTIALS, "count partials fit the mesh scratch");
-constexpr int KEYS_ITEMS = 2;                         // triangles per thread in k_count / k_emit
-constexpr int KEYS_TILE = BLOCK * KEYS_ITEMS;         // triangles per k_count / k_emit block
+constexpr int KEYS_ITEMS = 4;                         // triangles per thread in k_keys
+constexpr int KEYS_TILE = BLOCK * KEYS_ITEMS;         // triangles per k_keys block
 constexpr int CELLS_ITEMS = 16;
 constexpr int CELLS_TILE = BLOCK * CELLS_ITEMS;       // = SORT_TILE_KEYS entries per k_cells block
 constexpr int MAX_PASSES = 7;
@@ -48,6 +50,7 @@ constexpr uint64_t SFLAG_PRE = 2ull << 62;
 constexpr uint64_t SVAL_MASK = (1ull << 62) - 1;
 
 static_assert(CELLS_TILE == SORT_TILE_KEYS, "k_cells tiles follow the sort tiles");
+static_assert(sizeof(search_stats_t) == 16 * 8, "search_stats_t is 16 int64 words");
 
 inline unsigned grid_for(int64_t n, int64_t cap = MAX_GRID)
 {
@@ -128,13 +131,12 @@ struct CellRange {
     int64_t lo[4], hi[4];
 };
 
-// Overlapped cell range of a triangle's box, or false for a non-finite one.
-MS_D bool tri_cells(const double *box, const GridView &g, CellRange &r)
+// Overlapped cell range of triangle t of mesh m (its box from the vertices),
+// or false for a non-finite triangle.
+MS_D bool tri_cells(const MeshView &m, int32_t t, const GridView &g, CellRange &r)
 {
-    const double2 *b = reinterpret_cast<const double2 *>(box);
-    double2 l01 = b[0], l23 = b[1], h01 = b[2], h23 = b[3];
-    double lo[4] = {l01.x, l01.y, l23.x, l23.y}, hi[4] = {h01.x, h01.y, h23.x, h23.y};
-    if (!(lo[0] == lo[0])) return false;
+    double lo[4], hi[4];
+    if (!tri_box(m, t, lo, hi)) return false;
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
         r.lo[d] = cell_of(lo[d], g.wlo[d], g.inv, g.n[d]);
@@ -158,6 +160,52 @@ MS_D void for_cells(const CellRange &r, const int64_t n[4], F &&f)
                 int64_t base = ((c0 * n[1] + c1) * n[2] + c2) * n[3];
                 for (int64_t c3 = r.lo[3]; c3 <= r.hi[3]; ++c3) f((uint64_t)(base + c3));
             }
+}
+
+// Occupancy flags of the cells of a range held by `other`, as a bit mask in
+// lexicographic order of the cells.  Ranges of up to 8 cells compute the j-th
+// cell from the mixed-radix digits of j, so that all their flag loads are in
+// flight together (the table is far larger than the caches); *big is set for
+// larger ranges, which the caller walks with for_cells.
+constexpr int MLP_CELLS = 8;
+
+MS_D uint32_t flag_mask(const CellRange &r, const int64_t n[4], uint64_t cb, const uint8_t *other, int log2,
+                        bool *big)
+{
+    const int64_t cnt = range_count(r);
+    *big = cnt > MLP_CELLS;
+    if (*big) return 0;
+    const uint32_t e1 = (uint32_t)(r.hi[1] - r.lo[1] + 1), e2 = (uint32_t)(r.hi[2] - r.lo[2] + 1),
+                   e3 = (uint32_t)(r.hi[3] - r.lo[3] + 1);
+    uint8_t v[MLP_CELLS];
+#pragma unroll
+    for (int j = 0; j < MLP_CELLS; ++j) {
+        v[j] = 0;
+        if (j < cnt) {
+            uint32_t q = (uint32_t)j;
+            const uint32_t d3 = q % e3; q /= e3;
+            const uint32_t d2 = q % e2; q /= e2;
+            const uint32_t d1 = q % e1; q /= e1;
+            const int64_t cell = (((r.lo[0] + q) * n[1] + r.lo[1] + d1) * n[2] + r.lo[2] + d2) * n[3] + r.lo[3] + d3;
+            v[j] = other[bm_hash(cb + (uint64_t)cell, log2)];
+        }
+    }
+    uint32_t m = 0;
+#pragma unroll
+    for (int j = 0; j < MLP_CELLS; ++j) m |= (uint32_t)(v[j] != 0) << j;
+    return m;
+}
+
+// The j-th cell of a range (lexicographic order).
+MS_D uint64_t range_cell(const CellRange &r, const int64_t n[4], int j)
+{
+    const uint32_t e1 = (uint32_t)(r.hi[1] - r.lo[1] + 1), e2 = (uint32_t)(r.hi[2] - r.lo[2] + 1),
+                   e3 = (uint32_t)(r.hi[3] - r.lo[3] + 1);
+    uint32_t q = (uint32_t)j;
+    const uint32_t d3 = q % e3; q /= e3;
+    const uint32_t d2 = q % e2; q /= e2;
+    const uint32_t d1 = q % e1; q /= e1;
+    return (uint64_t)((((r.lo[0] + q) * n[1] + r.lo[1] + d1) * n[2] + r.lo[2] + d2) * n[3] + r.lo[3] + d3);
 }
 
 // Compact cell range: lo cell per axis in 12 bits (bits 0..47), extent per
@@ -189,11 +237,10 @@ MS_D void unpack_range(uint64_t v, CellRange &r)
     }
 }
 
-// Where triangle gt lives: pair, side, local index, box.
+// Where triangle gt lives: pair, side, local index.
 struct TriLoc {
     int p, side;
     int32_t t;
-    const double *box;
 };
 
 template <bool ONE>
@@ -205,13 +252,14 @@ MS_D TriLoc locate(const BatchView &bv, int64_t gt)
     int64_t local = gt - P.tri_off;
     L.side = local >= P.nA;
     L.t = (int32_t)(L.side ? local - P.nA : local);
-    L.box = (L.side ? P.B.box : P.A.box) + 8 * (int64_t)L.t;
     return L;
 }
 
-// Cell range of triangle gt from its compact record (or its box).
-template <bool ONE>
-MS_D bool range_of(const BatchView &bv, const uint64_t *rng, int64_t gt, const TriLoc &L, CellRange &r)
+MS_D const MeshView &side_mesh(const PairDesc &P, int side) { return side ? P.B : P.A; }
+
+// Cell range of triangle t (global index gt) from its compact record, or from
+// its vertices when the range did not pack.
+MS_D bool range_at(const uint64_t *rng, int64_t gt, const MeshView &m, int32_t t, const GridView &g, CellRange &r)
 {
     uint64_t v = rng[gt];
     if (v == RNG_NONFINITE) return false;
@@ -219,22 +267,30 @@ MS_D bool range_of(const BatchView &bv, const uint64_t *rng, int64_t gt, const T
         unpack_range(v, r);
         return true;
     }
-    return tri_cells(L.box, pair_desc<ONE>(bv, L.p).g, r);
+    return tri_cells(m, t, g, r);
+}
+
+template <bool ONE>
+MS_D bool range_of(const BatchView &bv, const uint64_t *rng, int64_t gt, const TriLoc &L, CellRange &r)
+{
+    const PairDesc &P = pair_desc<ONE>(bv, L.p);
+    return range_at(rng, gt, side_mesh(P, L.side), L.t, P.g, r);
 }
 
 // Decoupled look-back over 64-bit status words [flag:2 | value:62] of the
-// tiles before `tile`, run by all 64 lanes of one wave: each round reads 64
-// predecessors at once, finds the nearest inclusive prefix with a ballot and
-// re-reads when a predecessor before it has not published yet.  Returns the
-// exclusive prefix in every lane.
-MS_D uint64_t wave_lookback(const uint64_t *status, int64_t tile)
+// tiles before `tile` (word of tile i at status[i * stride]), run by all 64
+// lanes of one wave: each round reads 64 predecessors at once, finds the
+// nearest inclusive prefix with a ballot and re-reads when a predecessor
+// before it has not published yet.  Returns the exclusive prefix in every
+// lane.
+MS_D uint64_t wave_lookback_s(const uint64_t *status, int64_t stride, int64_t tile)
 {
     const int lane = lane_id();
     uint64_t excl = 0;
     int64_t t = tile - 1;
     for (;;) {
         const int64_t idx = t - lane;
-        const uint64_t v = idx >= 0 ? __hip_atomic_load(status + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+        const uint64_t v = idx >= 0 ? __hip_atomic_load(status + idx * stride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                                     : SFLAG_PRE;
         const uint64_t fl = v & ~SVAL_MASK;
         const uint64_t pre = ballot(fl == SFLAG_PRE);
@@ -248,9 +304,13 @@ MS_D uint64_t wave_lookback(const uint64_t *status, int64_t tile)
     }
 }
 
-// The same over pairs of words (a, b) published together: a predecessor is
-// ready when both words carry the same non-zero flag.
-MS_D void wave_lookback2(const uint64_t *status, int64_t tile, uint64_t &ea, uint64_t &eb)
+MS_D uint64_t wave_lookback(const uint64_t *status, int64_t tile) { return wave_lookback_s(status, 1, tile); }
+MS_D uint64_t wave_lookback3(const uint64_t *status, int64_t tile) { return wave_lookback_s(status, 3, tile); }
+
+// The same over pairs of words (a, b) published together (tile i's pair at
+// status[i * stride], status[i * stride + 1]): a predecessor is ready when
+// both words carry the same non-zero flag.
+MS_D void wave_lookback2(const uint64_t *status, int64_t stride, int64_t tile, uint64_t &ea, uint64_t &eb)
 {
     const int lane = lane_id();
     ea = eb = 0;
@@ -259,8 +319,8 @@ MS_D void wave_lookback2(const uint64_t *status, int64_t tile, uint64_t &ea, uin
         const int64_t idx = t - lane;
         uint64_t va = SFLAG_PRE, vb = SFLAG_PRE;
         if (idx >= 0) {
-            va = __hip_atomic_load(status + 2 * idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            vb = __hip_atomic_load(status + 2 * idx + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            va = __hip_atomic_load(status + stride * idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            vb = __hip_atomic_load(status + stride * idx + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         const uint64_t fa = va & ~SVAL_MASK, fb = vb & ~SVAL_MASK;
         const bool ready = fa != 0 && fa == fb;
@@ -330,7 +390,7 @@ __global__ void __launch_bounds__(BLOCK) k_prepare(ClearSpec c)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c.stats && g0 < 16) ((int64_t *)c.stats)[g0] = 0;
+    if (c.stats && g0 < (int64_t)(sizeof(search_stats_t) / 8)) ((int64_t *)c.stats)[g0] = 0;
     for (int64_t i = g0; i < c.flag_words; i += stride) c.flags[i] = 0;
     for (int64_t i = g0; i < c.kstat_words; i += stride) c.kstat[i] = 0;
     for (int64_t i = g0; i < c.hist_words; i += stride) c.hist[i] = 0;
@@ -352,7 +412,7 @@ __global__ void __launch_bounds__(BLOCK) k_mark(BatchView bv, uint8_t *flags, ui
         TriLoc L = locate<ONE>(bv, gt);
         const PairDesc &P = pair_desc<ONE>(bv, L.p);
         CellRange r;
-        if (!tri_cells(L.box, P.g, r)) {
+        if (!tri_cells(side_mesh(P, L.side), L.t, P.g, r)) {
             ++bad;
             rng[gt] = RNG_NONFINITE;
             continue;
@@ -374,8 +434,7 @@ __global__ void __launch_bounds__(BLOCK) k_mark(BatchView bv, uint8_t *flags, ui
 struct KeysOut {
     uint64_t *keys;
     int64_t cap;
-    uint32_t *cnt;            // entries per triangle
-    uint64_t *btot;           // entries per k_count block
+    unsigned long long *ctr;  // [0] entries reserved, [1] blocks done (cleared)
     uint32_t *hist;           // passes x radix digit counts of the sort
     uint32_t *sort_status0;   // the sort's pass-0 look-back words (radix per tile)
     int passes, rb, lo_bit;
@@ -385,72 +444,64 @@ struct KeysOut {
     int n_mark_partial;
 };
 
-// Entries of each triangle (cells the other mesh also occupies) and the
-// total of each block of KEYS_TILE triangles.
+// Entries of each triangle: the cells of its range that the other mesh also
+// occupies (a cell holding one mesh only cannot hold a pair).  Each block
+// counts the entries of its KEYS_TILE triangles, reserves that many output
+// slots with one atomic add and writes the keys [cell | side | triangle].
+// The blocks' output ranges come out in any order, which the sort makes
+// irrelevant (the keys are distinct).  Also accumulates the digit histograms
+// of every sort pass, clears the sort's pass-0 look-back words of the tiles
+// it writes, and the last block to finish publishes the totals.
 template <bool ONE>
-__global__ void __launch_bounds__(BLOCK) k_count(BatchView bv, const uint8_t *flags, const uint64_t *rng, KeysOut o)
-{
-    __shared__ uint64_t s_tmp[BLOCK / WAVE];
-    const int64_t base = (int64_t)blockIdx.x * KEYS_TILE;
-    const size_t side_bytes = (size_t)1 << bv.bm_log2;
-    uint64_t mine = 0;
-#pragma unroll
-    for (int i = 0; i < KEYS_ITEMS; ++i) {
-        const int64_t gt = base + i * BLOCK + threadIdx.x;
-        if (gt >= bv.n_tri) break;
-        TriLoc L = locate<ONE>(bv, gt);
-        CellRange r;
-        uint32_t c = 0;
-        if (range_of<ONE>(bv, rng, gt, L, r)) {
-            const uint8_t *other = flags + (size_t)(1 - L.side) * side_bytes;
-            const uint64_t cb = pair_desc<ONE>(bv, L.p).cell_base;
-            for_cells(r, pair_desc<ONE>(bv, L.p).g.n,
-                      [&](uint64_t cell) { c += other[bm_hash(cb + cell, bv.bm_log2)] != 0; });
-        }
-        o.cnt[gt] = c;
-        mine += c;
-    }
-    const uint64_t t = block_sum(mine, s_tmp);
-    if (threadIdx.x == 0) o.btot[blockIdx.x] = t;
-}
-
-// Emit the keys [cell | side | triangle] of every triangle: the block's
-// offset is the sum of the totals of the blocks before it (read in
-// parallel), the threads' offsets a block scan.  Also accumulates the digit
-// histograms of the sort, clears the sort's pass-0 look-back words of the
-// tiles the block writes, and (last block) publishes the totals.
-template <bool ONE>
-__global__ void __launch_bounds__(BLOCK) k_emit(BatchView bv, const uint8_t *flags, const uint64_t *rng, KeysOut o)
+__global__ void __launch_bounds__(BLOCK) k_keys(BatchView bv, const uint8_t *flags, const uint64_t *rng, KeysOut o)
 {
     __shared__ uint32_t s_hist[MAX_PASSES * 1024];
     __shared__ uint64_t s_tmp[BLOCK / WAVE];
-    const int64_t b = blockIdx.x;
-    const int64_t base = b * KEYS_TILE;
+    __shared__ unsigned long long s_blk0;
+    __shared__ int s_last;
     const size_t side_bytes = (size_t)1 << bv.bm_log2;
     const int R = 1 << o.rb;
     for (int i = threadIdx.x; i < o.passes * R; i += BLOCK) s_hist[i] = 0;
-    // block offset: sum of the earlier blocks' totals
-    uint64_t pre = 0;
-    for (int64_t j = threadIdx.x; j < b; j += BLOCK) pre += o.btot[j];
-    const uint64_t blk0 = block_sum(pre, s_tmp);
+    const int64_t base = (int64_t)blockIdx.x * KEYS_TILE;
     uint32_t cnt[KEYS_ITEMS];
     uint64_t mine = 0;
 #pragma unroll
     for (int i = 0; i < KEYS_ITEMS; ++i) {
         const int64_t gt = base + i * BLOCK + threadIdx.x;
-        cnt[i] = gt < bv.n_tri ? o.cnt[gt] : 0u;
-        mine += cnt[i];
+        uint32_t c = 0;
+        if (gt < bv.n_tri) {
+            TriLoc L = locate<ONE>(bv, gt);
+            CellRange r;
+            if (range_of<ONE>(bv, rng, gt, L, r)) {
+                const uint8_t *other = flags + (size_t)(1 - L.side) * side_bytes;
+                const PairDesc &P = pair_desc<ONE>(bv, L.p);
+                bool big;
+                const uint32_t m = flag_mask(r, P.g.n, P.cell_base, other, bv.bm_log2, &big);
+                if (!big) c = (uint32_t)__builtin_popcount(m);
+                else for_cells(r, P.g.n, [&](uint64_t cell) { c += other[bm_hash(P.cell_base + cell, bv.bm_log2)] != 0; });
+            }
+        }
+        cnt[i] = c;
+        mine += c;
     }
     uint64_t btotal;
     const uint64_t texcl = block_excl(mine, s_tmp, &btotal);
-    if (b == gridDim.x - 1) {
+    if (threadIdx.x == 0) {
+        s_blk0 = btotal ? atomicAdd(&o.ctr[0], (unsigned long long)btotal) : 0ull;
+        __threadfence();
+        s_last = atomicAdd(&o.ctr[1], 1ull) == (unsigned long long)(gridDim.x - 1);
+    }
+    __syncthreads();
+    const uint64_t blk0 = s_blk0;
+    if (s_last) {
         // the last block publishes the totals (mark partials summed by the whole block)
+        __threadfence();
         unsigned long long all = 0, bad = 0;
         for (int i = threadIdx.x; i < o.n_mark_partial; i += BLOCK) { all += o.mark_partial[2 * i]; bad += o.mark_partial[2 * i + 1]; }
         all = block_sum(all, (unsigned long long *)s_tmp);
         bad = block_sum(bad, (unsigned long long *)s_tmp);
         if (threadIdx.x == 0) {
-            const int64_t E = (int64_t)(blk0 + btotal);
+            const int64_t E = (int64_t)__hip_atomic_load(&o.ctr[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             o.stats->n_entries = E;
             o.stats->n_entries_all = (int64_t)all;
             o.stats->n_nonfinite = (int64_t)bad;
@@ -462,7 +513,6 @@ __global__ void __launch_bounds__(BLOCK) k_emit(BatchView bv, const uint8_t *fla
         const int64_t t0 = (int64_t)blk0 / SORT_TILE_KEYS, t1 = (int64_t)(blk0 + btotal - 1) / SORT_TILE_KEYS;
         for (int64_t w = threadIdx.x; w < (t1 - t0 + 1) * R; w += BLOCK) o.sort_status0[t0 * R + w] = 0;
     }
-    __syncthreads();
     int64_t pos = (int64_t)(blk0 + texcl);
 #pragma unroll
     for (int i = 0; i < KEYS_ITEMS; ++i) {
@@ -472,20 +522,31 @@ __global__ void __launch_bounds__(BLOCK) k_emit(BatchView bv, const uint8_t *fla
         CellRange r;
         range_of<ONE>(bv, rng, gt, L, r);
         const uint8_t *other = flags + (size_t)(1 - L.side) * side_bytes;
-        const uint64_t cb = pair_desc<ONE>(bv, L.p).cell_base;
+        const PairDesc &P = pair_desc<ONE>(bv, L.p);
+        const uint64_t cb = P.cell_base;
         const uint64_t low = ((uint64_t)L.side << bv.kl.tb) | (uint64_t)L.t;
-        for_cells(r, pair_desc<ONE>(bv, L.p).g.n, [&](uint64_t cell) {
-            const uint64_t gc = cb + cell;
-            if (other[bm_hash(gc, bv.bm_log2)]) {
-                const uint64_t key = (gc << bv.kl.cell_shift) | low;
-                if (pos < o.cap) {
-                    o.keys[pos] = key;
-                    for (int q = 0; q < o.passes; ++q)
-                        atomicAdd(&s_hist[q * R + (int)((key >> (o.lo_bit + o.rb * q)) & (uint64_t)(R - 1))], 1u);
-                }
-                ++pos;
+        auto put = [&](uint64_t gc) {
+            const uint64_t key = (gc << bv.kl.cell_shift) | low;
+            if (pos < o.cap) {
+                o.keys[pos] = key;
+                for (int q = 0; q < o.passes; ++q)
+                    atomicAdd(&s_hist[q * R + (int)((key >> (o.lo_bit + o.rb * q)) & (uint64_t)(R - 1))], 1u);
             }
-        });
+            ++pos;
+        };
+        bool big;
+        uint32_t m = flag_mask(r, P.g.n, cb, other, bv.bm_log2, &big);
+        if (!big) {
+            while (m) {
+                const int j = __builtin_ctz(m);
+                m &= m - 1;
+                put(cb + range_cell(r, P.g.n, j));
+            }
+        } else {
+            for_cells(r, P.g.n, [&](uint64_t cell) {
+                if (other[bm_hash(cb + cell, bv.bm_log2)]) put(cb + cell);
+            });
+        }
     }
     __syncthreads();
     if (btotal > 0)
@@ -523,31 +584,39 @@ MS_D int64_t gallop_u64(const uint64_t *a, int64_t lo, int64_t hi, uint64_t k)
     return lower_bound_u64(a, prev, lo, k);
 }
 
-struct CellsOut {
-    CellRec *cells;
-    int64_t *pstart;          // n_cells + 1
-    uint64_t *cstat;          // 2 look-back words per tile (count, slots)
-    uint32_t *tile_ctr;
+// Cell boundaries of the sorted keys, as two fully parallel scans (no
+// searching through the key array):
+//   k_cells_scan  per sorted tile: the entries that start a cell and the
+//                 entries of mesh A, each counted by a block scan and a
+//                 decoupled look-back; every cell start e writes
+//                 bounds[ci] = (e << 32) | (A entries before e);
+//   k_cells_keep  per cell: nA, nB from consecutive bounds (A entries sort
+//                 before B entries inside a cell); cells holding both meshes
+//                 are kept, with their slot offsets sum(nA * nB), by a second
+//                 scan and look-back.
+struct CellsScanOut {
+    uint64_t *bounds;         // n_all + 1
+    int64_t *n_all;           // cells (including one-mesh cells)
     search_stats_t *stats;
+    uint64_t *stat;           // 3 look-back words per tile: [0] here, [1..2] k_cells_keep
+    uint32_t *tile_ctr;
 };
 
-// Cells holding both meshes, in key order, with their slot offsets: a block
-// per sorted tile; a cell belongs to the tile holding its first entry.
 template <bool ONE>
-__global__ void __launch_bounds__(BLOCK) k_cells(BatchView bv, const uint64_t *keys, const int64_t *n_dev, CellsOut o)
+__global__ void __launch_bounds__(BLOCK) k_cells_scan(BatchView bv, const uint64_t *keys, const int64_t *n_dev,
+                                                      CellsScanOut o)
 {
-    __shared__ uint32_t s_tmp32[BLOCK / WAVE];
     __shared__ uint64_t s_tmp64[BLOCK / WAVE];
-    __shared__ uint64_t s_cbase, s_pbase;
+    __shared__ uint64_t s_base;
     __shared__ uint32_t s_tile;
     const int64_t n = *n_dev;
     const int64_t ntiles = (n + CELLS_TILE - 1) / CELLS_TILE;
-    const int sh = bv.kl.cell_shift;
+    const int sh = bv.kl.cell_shift, tb = bv.kl.tb;
     if (n == 0) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
-            o.stats->n_cells = 0;
-            o.stats->n_slots = 0;
-            o.pstart[0] = 0;
+            *o.n_all = 0;
+            o.stats->n_cells_all = 0;
+            o.bounds[0] = 0;
         }
         return;
     }
@@ -560,27 +629,114 @@ __global__ void __launch_bounds__(BLOCK) k_cells(BatchView bv, const uint64_t *k
         if (tile >= ntiles) break;
         // each thread owns CELLS_ITEMS consecutive entries
         const int64_t e0 = tile * CELLS_TILE + (int64_t)threadIdx.x * CELLS_ITEMS;
-        int64_t st[CELLS_ITEMS];
-        int32_t na[CELLS_ITEMS], nb[CELLS_ITEMS];
-        uint32_t ccount = 0;
-        uint64_t pcount = 0;
+        uint64_t prev = (e0 > 0 && e0 < n) ? (keys[e0 - 1] >> sh) : ~0ull;
+        uint32_t startm = 0, am = 0;
+        uint64_t cnt = 0;   // (starts << 32) | A entries
 #pragma unroll
         for (int i = 0; i < CELLS_ITEMS; ++i) {
             const int64_t e = e0 + i;
-            st[i] = -1;
-            na[i] = nb[i] = 0;
             if (e < n) {
-                const uint64_t cell = keys[e] >> sh;
-                if (e == 0 || (keys[e - 1] >> sh) != cell) {
-                    const int64_t end = gallop_u64(keys, e + 1, n, (cell + 1) << sh);
-                    const int64_t fb = gallop_u64(keys, e, end, (cell << sh) | (1ull << bv.kl.tb));
-                    if (fb > e && end > fb) {
-                        st[i] = e;
-                        na[i] = (int32_t)(fb - e);
-                        nb[i] = (int32_t)(end - fb);
-                        ++ccount;
-                        pcount += (uint64_t)(fb - e) * (uint64_t)(end - fb);
-                    }
+                const uint64_t k = keys[e];
+                const uint64_t cell = k >> sh;
+                const bool st = e == 0 || cell != prev;
+                const bool isA = ((k >> tb) & 1) == 0;
+                startm |= (uint32_t)st << i;
+                am |= (uint32_t)isA << i;
+                cnt += ((uint64_t)st << 32) + (uint64_t)isA;
+                prev = cell;
+            }
+        }
+        uint64_t tot;
+        const uint64_t tex = block_excl(cnt, s_tmp64, &tot);
+        if (threadIdx.x < WAVE) {
+            uint64_t ex = 0;
+            uint64_t *w = o.stat + 3 * tile;
+            if (tile == 0) {
+                if (threadIdx.x == 0) publish_u64(w, SFLAG_PRE, tot);
+            } else {
+                if (threadIdx.x == 0) publish_u64(w, SFLAG_AGG, tot);
+                ex = wave_lookback3(o.stat, tile);
+                if (threadIdx.x == 0) publish_u64(w, SFLAG_PRE, ex + tot);
+            }
+            if (threadIdx.x == 0) {
+                s_base = ex;
+                if (tile == ntiles - 1) {
+                    const uint64_t all = ex + tot;
+                    *o.n_all = (int64_t)(all >> 32);
+                    o.stats->n_cells_all = (int64_t)(all >> 32);
+                    o.bounds[all >> 32] = ((uint64_t)n << 32) | (all & 0xffffffffull);
+                }
+            }
+        }
+        __syncthreads();
+        uint64_t run = s_base + tex;
+#pragma unroll
+        for (int i = 0; i < CELLS_ITEMS; ++i) {
+            if (startm >> i & 1) o.bounds[run >> 32] = ((uint64_t)(e0 + i) << 32) | (run & 0xffffffffull);
+            run += ((uint64_t)(startm >> i & 1) << 32) + (uint64_t)(am >> i & 1);
+        }
+        __syncthreads();
+    }
+}
+
+struct CellsOut {
+    CellRec *cells;
+    int64_t *pstart;          // n_cells + 1
+    uint64_t *stat;           // the same 3 words per tile as k_cells_scan
+    uint32_t *tile_ctr;
+    search_stats_t *stats;
+};
+
+template <bool ONE>
+__global__ void __launch_bounds__(BLOCK) k_cells_keep(BatchView bv, const uint64_t *keys, const uint64_t *bounds,
+                                                      const int64_t *n_all_dev, CellsOut o)
+{
+    __shared__ uint32_t s_tmp32[BLOCK / WAVE];
+    __shared__ uint64_t s_tmp64[BLOCK / WAVE];
+    __shared__ uint64_t s_cbase, s_pbase;
+    __shared__ uint32_t s_tile;
+    const int64_t nall = *n_all_dev;
+    const int64_t ntiles = (nall + CELLS_TILE - 1) / CELLS_TILE;
+    const int sh = bv.kl.cell_shift;
+    if (nall == 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            o.stats->n_cells = 0;
+            o.stats->n_slots = 0;
+            o.pstart[0] = 0;
+        }
+        return;
+    }
+    if ((int64_t)blockIdx.x >= ntiles) return;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(o.tile_ctr, 1u);
+        __syncthreads();
+        const int64_t tile = s_tile;
+        __syncthreads();
+        if (tile >= ntiles) break;
+        const int64_t c0 = tile * CELLS_TILE + (int64_t)threadIdx.x * CELLS_ITEMS;
+        uint32_t keepm = 0, ccount = 0;
+        uint64_t pcount = 0;
+        int32_t na[CELLS_ITEMS], nb[CELLS_ITEMS];
+        int64_t st[CELLS_ITEMS];
+        uint64_t v1 = c0 < nall ? bounds[c0] : 0;
+#pragma unroll
+        for (int i = 0; i < CELLS_ITEMS; ++i) {
+            const int64_t c = c0 + i;
+            na[i] = nb[i] = 0;
+            st[i] = 0;
+            if (c < nall) {
+                const uint64_t v0 = v1;
+                v1 = bounds[c + 1];
+                const int64_t s0 = (int64_t)(v0 >> 32), s1 = (int64_t)(v1 >> 32);
+                const int64_t a = (int64_t)((v1 & 0xffffffffull) - (v0 & 0xffffffffull));
+                const int64_t b = (s1 - s0) - a;
+                if (a > 0 && b > 0) {
+                    keepm |= 1u << i;
+                    st[i] = s0;
+                    na[i] = (int32_t)a;
+                    nb[i] = (int32_t)b;
+                    ++ccount;
+                    pcount += (uint64_t)a * (uint64_t)b;
                 }
             }
         }
@@ -590,7 +746,7 @@ __global__ void __launch_bounds__(BLOCK) k_cells(BatchView bv, const uint64_t *k
         const uint64_t pex = block_excl(pcount, s_tmp64, &ptot);
         if (threadIdx.x < WAVE) {
             uint64_t cb = 0, pb = 0;
-            uint64_t *sc = o.cstat + 2 * tile, *sp = sc + 1;
+            uint64_t *sc = o.stat + 3 * tile + 1, *sp = sc + 1;
             if (tile == 0) {
                 if (threadIdx.x == 0) {
                     publish_u64(sp, SFLAG_PRE, ptot);
@@ -601,7 +757,7 @@ __global__ void __launch_bounds__(BLOCK) k_cells(BatchView bv, const uint64_t *k
                     publish_u64(sp, SFLAG_AGG, ptot);
                     publish_u64(sc, SFLAG_AGG, ctot);
                 }
-                wave_lookback2(o.cstat, tile, cb, pb);
+                wave_lookback2(o.stat + 1, 3, tile, cb, pb);
                 if (threadIdx.x == 0) {
                     publish_u64(sp, SFLAG_PRE, pb + ptot);
                     publish_u64(sc, SFLAG_PRE, cb + ctot);
@@ -623,13 +779,12 @@ __global__ void __launch_bounds__(BLOCK) k_cells(BatchView bv, const uint64_t *k
         uint64_t ps = s_pbase + pex;
 #pragma unroll
         for (int i = 0; i < CELLS_ITEMS; ++i) {
-            if (st[i] < 0) continue;
-            const uint64_t gcell = keys[st[i]] >> sh;
+            if (!(keepm >> i & 1)) continue;
             CellRec cr;
             cr.start = st[i];
             cr.nA = na[i];
             cr.nB = nb[i];
-            cr.pair = pair_of_cell<ONE>(bv, gcell);
+            cr.pair = ONE ? 0 : pair_of_cell<ONE>(bv, keys[st[i]] >> sh);
             cr.pad = 0;
             o.cells[ci] = cr;
             o.pstart[ci] = (int64_t)ps;
@@ -640,89 +795,183 @@ __global__ void __launch_bounds__(BLOCK) k_cells(BatchView bv, const uint64_t *k
     }
 }
 
-struct Box { double lo[4], hi[4]; };
-
-MS_D Box load_box(const double *p)
-{
-    const double2 *b = reinterpret_cast<const double2 *>(p);
-    double2 l01 = b[0], l23 = b[1], h01 = b[2], h23 = b[3];
-    return Box{{l01.x, l01.y, l23.x, l23.y}, {h01.x, h01.y, h23.x, h23.y}};
-}
-
 MS_D int64_t uniform_i64(int64_t v)
 {
     return ((int64_t)__builtin_amdgcn_readfirstlane((int)(v >> 32)) << 32) |
            (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
 }
 
-constexpr int ENUM_LDS_CELLS = 4096;
+
+// Slot -> (cell, iA, iB), iA = slot mod nA, iB = slot / nA (Alg. 1).  A pair
+// is kept only in its home cell, the cell of the componentwise max of the two
+// boxes' lower corners (the one cell of both ranges that every overlapping
+// pair has, by monotonicity of the cell map), and only if the closed boxes
+// overlap (Sec. 6.2.2).
+//
+// Each block takes ENUM_SLOTS consecutive slots.  When the cells they fall in
+// have at most ENUM_STAGE entries in all, the block first stages those
+// entries (triangle index and box, computed once from the vertices) and the
+// cell records in LDS, so that every slot reads LDS only; otherwise (very
+// full cells) each slot gathers its two triangles from global memory.
+constexpr int ENUM_ITEMS = 16;
+constexpr int ENUM_SLOTS = BLOCK * ENUM_ITEMS;
+constexpr int ENUM_STAGE = 512;
+constexpr int ENUM_CELLS = 256;
+
+template <bool ONE>
+MS_D bool enum_pair(const PairDesc &Pd, uint64_t cell, const double alo[4], const double ahi[4], const double blo[4],
+                    const double bhi[4])
+{
+    bool ov = true;
+    int64_t h[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        ov = ov && (alo[d] <= bhi[d]) && (blo[d] <= ahi[d]);
+        const double m = alo[d] > blo[d] ? alo[d] : blo[d];
+        h[d] = cell_of(m, Pd.g.wlo[d], Pd.g.inv, Pd.g.n[d]);
+    }
+    return ov && (uint64_t)cell_linear(h, Pd.g.n) == cell;
+}
+
+constexpr int ENUM_PSTART = 4096;   // slot offsets kept in LDS when the cells are this few
 
 template <bool ONE>
 __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *keys, const CellRec *cells,
                                                 const int64_t *pstart_g, search_stats_t *stats, uint64_t *cand,
                                                 int32_t *cand_pair, int64_t cand_cap)
 {
-    __shared__ int64_t s_pstart[ENUM_LDS_CELLS + 1];
+    __shared__ int64_t s_pstart[ENUM_PSTART + 1];
+    __shared__ double s_box[ENUM_STAGE][8];
+    __shared__ int32_t s_t[ENUM_STAGE];
+    __shared__ int64_t s_pre[ENUM_CELLS + 1];
+    __shared__ int32_t s_first[ENUM_CELLS + 1], s_end[ENUM_CELLS], s_nA[ENUM_CELLS], s_pair[ENUM_CELLS];
+    __shared__ uint64_t s_cell[ENUM_CELLS];
+    __shared__ int64_t s_c0, s_c1, s_e0;
+    __shared__ int s_staged;
     const int64_t ncells = stats->n_cells;
     const int64_t P = stats->n_slots;
-    // small cell lists are searched in LDS, large ones in global memory
-    const bool in_lds = ncells <= ENUM_LDS_CELLS;
-    if (in_lds) {
+    const int64_t nchunks = ceil_div(P, ENUM_SLOTS);
+    if ((int64_t)blockIdx.x >= nchunks) return;
+    const bool lds_pre = ncells <= ENUM_PSTART;
+    if (lds_pre) {
         for (int64_t i = threadIdx.x; i <= ncells; i += BLOCK) s_pstart[i] = pstart_g[i];
         __syncthreads();
     }
-    const int64_t *pstart = in_lds ? s_pstart : pstart_g;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t iters = ceil_div(P, stride);
-    const int lane = lane_id();
-    for (int64_t it = 0; it < iters; ++it) {
-        const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + it * stride;
-        // one scalar binary search per wave for its first slot; each lane
-        // then steps over the (few) cells its own slot passes
-        const int64_t s0 = uniform_i64(slot - lane);
-        bool keep = false;
-        uint64_t packed = 0;
-        int32_t pr = 0;
-        if (s0 < P) {
-            const int64_t c0 = last_le<int64_t>(pstart, ncells, s0);
-            if (slot < P) {
-                int64_t c = c0;
-                while (pstart[c + 1] <= slot) ++c;
-                const CellRec cr = cells[c];
-                const uint64_t local = (uint64_t)(slot - pstart[c]);
-                uint64_t iB;
-                if (local < 0xffffffffull) iB = (uint32_t)local / (uint32_t)cr.nA;
-                else iB = local / (uint64_t)cr.nA;
-                const uint64_t iA = local - iB * (uint64_t)cr.nA;
-                const uint64_t kA = keys[cr.start + (int64_t)iA];
-                const uint64_t kB = keys[cr.start + cr.nA + (int64_t)iB];
+    const int64_t *pstart = lds_pre ? s_pstart : pstart_g;
+    for (int64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
+        const int64_t S0 = chunk * ENUM_SLOTS;
+        const int64_t S1 = S0 + ENUM_SLOTS < P ? S0 + ENUM_SLOTS : P;
+        if (threadIdx.x == 0) {
+            const int64_t c0 = last_le<int64_t>(pstart, ncells, S0);
+            const int64_t c1 = last_le<int64_t>(pstart, ncells, S1 - 1);
+            const CellRec a = cells[c0], b = cells[c1];
+            const int64_t e0 = a.start, e1 = b.start + b.nA + b.nB;
+            s_c0 = c0;
+            s_c1 = c1;
+            s_e0 = e0;
+            s_staged = (c1 - c0 + 1) <= ENUM_CELLS && (e1 - e0) <= ENUM_STAGE;
+        }
+        __syncthreads();
+        const int64_t c0 = s_c0, nc = s_c1 - s_c0 + 1, e0 = s_e0;
+        const bool staged = s_staged != 0;
+        if (staged) {
+            for (int64_t i = threadIdx.x; i < nc; i += BLOCK) {
+                const CellRec cr = cells[c0 + i];
                 const PairDesc &Pd = pair_desc<ONE>(bv, cr.pair);
-                const uint64_t cell = (kA >> bv.kl.cell_shift) - Pd.cell_base;
-                const int32_t ta = (int32_t)(kA & bv.kl.tmask), tb = (int32_t)(kB & bv.kl.tmask);
-                const Box a = load_box(Pd.A.box + 8 * (int64_t)ta);
-                const Box b = load_box(Pd.B.box + 8 * (int64_t)tb);
-                bool ov = true;
-                int64_t h[4];
-#pragma unroll
-                for (int d = 0; d < 4; ++d) {
-                    ov = ov && (a.lo[d] <= b.hi[d]) && (b.lo[d] <= a.hi[d]);
-                    double m = a.lo[d] > b.lo[d] ? a.lo[d] : b.lo[d];
-                    h[d] = cell_of(m, Pd.g.wlo[d], Pd.g.inv, Pd.g.n[d]);
+                s_pre[i] = pstart[c0 + i];
+                s_first[i] = (int32_t)(cr.start - e0);
+                s_end[i] = (int32_t)(cr.start + cr.nA + cr.nB - e0);
+                s_nA[i] = cr.nA;
+                s_pair[i] = cr.pair;
+                s_cell[i] = (keys[cr.start] >> bv.kl.cell_shift) - Pd.cell_base;
+                if (i == nc - 1) {
+                    s_pre[nc] = pstart[c0 + nc];
+                    s_first[nc] = (int32_t)(cr.start + cr.nA + cr.nB - e0);
                 }
-                keep = ov && ((uint64_t)cell_linear(h, Pd.g.n) == cell);
-                packed = ((uint64_t)(uint32_t)ta << 32) | (uint32_t)tb;
-                pr = cr.pair;
+            }
+            __syncthreads();
+            const int ne = s_first[nc];
+            for (int i = threadIdx.x; i < ne; i += BLOCK) {
+                int lo = 0, hi = (int)nc;             // the last kept cell starting at or before entry i
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_first[mid] <= i) lo = mid;
+                    else hi = mid;
+                }
+                // entries between kept cells belong to one-mesh cells, possibly
+                // of another mesh pair; no slot refers to them
+                if (i >= s_end[lo]) continue;
+                const uint64_t k = keys[e0 + i];
+                const int side = (int)((k >> bv.kl.tb) & 1);
+                const int32_t t = (int32_t)(k & bv.kl.tmask);
+                const PairDesc &Pd = pair_desc<ONE>(bv, s_pair[lo]);
+                double blo[4], bhi[4];
+                tri_box(side_mesh(Pd, side), t, blo, bhi);
+#pragma unroll
+                for (int d = 0; d < 4; ++d) { s_box[i][d] = blo[d]; s_box[i][4 + d] = bhi[d]; }
+                s_t[i] = t;
+            }
+            __syncthreads();
+        }
+        int64_t cg = c0;   // cell of this thread's last slot (unstaged path)
+#pragma unroll 1
+        for (int j = 0; j < ENUM_ITEMS; ++j) {
+            const int64_t slot = S0 + (int64_t)j * BLOCK + threadIdx.x;
+            bool keep = false;
+            uint64_t packed = 0;
+            int32_t pr = 0;
+            if (slot < S1) {
+                if (staged) {
+                    int lo = 0, hi = (int)nc;          // last staged cell with s_pre <= slot
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_pre[mid] <= slot) lo = mid;
+                        else hi = mid;
+                    }
+                    const int c = lo;
+                    const int32_t nA = s_nA[c];
+                    const uint32_t local = (uint32_t)(slot - s_pre[c]);
+                    const uint32_t iB = local / (uint32_t)nA, iA = local - iB * (uint32_t)nA;
+                    const int ia = s_first[c] + (int)iA, ib = s_first[c] + nA + (int)iB;
+                    pr = s_pair[c];
+                    const PairDesc &Pd = pair_desc<ONE>(bv, pr);
+                    double alo[4], ahi[4], blo[4], bhi[4];
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) {
+                        alo[d] = s_box[ia][d]; ahi[d] = s_box[ia][4 + d];
+                        blo[d] = s_box[ib][d]; bhi[d] = s_box[ib][4 + d];
+                    }
+                    keep = enum_pair<ONE>(Pd, s_cell[c], alo, ahi, blo, bhi);
+                    packed = ((uint64_t)(uint32_t)s_t[ia] << 32) | (uint32_t)s_t[ib];
+                } else {
+                    while (pstart[cg + 1] <= slot) ++cg;
+                    const CellRec cr = cells[cg];
+                    const uint64_t local = (uint64_t)(slot - pstart[cg]);
+                    const uint64_t iB = local / (uint64_t)cr.nA;
+                    const uint64_t iA = local - iB * (uint64_t)cr.nA;
+                    const uint64_t kA = keys[cr.start + (int64_t)iA];
+                    const uint64_t kB = keys[cr.start + cr.nA + (int64_t)iB];
+                    pr = cr.pair;
+                    const PairDesc &Pd = pair_desc<ONE>(bv, pr);
+                    const int32_t ta = (int32_t)(kA & bv.kl.tmask), tb = (int32_t)(kB & bv.kl.tmask);
+                    double alo[4], ahi[4], blo[4], bhi[4];
+                    tri_box(Pd.A, ta, alo, ahi);
+                    tri_box(Pd.B, tb, blo, bhi);
+                    keep = enum_pair<ONE>(Pd, (kA >> bv.kl.cell_shift) - Pd.cell_base, alo, ahi, blo, bhi);
+                    packed = ((uint64_t)(uint32_t)ta << 32) | (uint32_t)tb;
+                }
+            }
+            const int64_t idx = wave_reserve(keep, (unsigned long long *)&stats->n_cand);
+            if (keep) {
+                if (idx < cand_cap) {
+                    cand[idx] = packed;
+                    cand_pair[idx] = pr;
+                } else {
+                    atomicOr((unsigned long long *)&stats->overflow, 2ull);
+                }
             }
         }
-        const int64_t idx = wave_reserve(keep, (unsigned long long *)&stats->n_cand);
-        if (keep) {
-            if (idx < cand_cap) {
-                cand[idx] = packed;
-                cand_pair[idx] = pr;
-            } else {
-                atomicOr((unsigned long long *)&stats->overflow, 2ull);
-            }
-        }
+        __syncthreads();
     }
 }
 
@@ -819,6 +1068,7 @@ __global__ void __launch_bounds__(BLOCK) k_allpairs(PairDesc pd, hit_t *hits, in
 {
     __shared__ double s_tri[AP_TILE][12];
     __shared__ double s_box[AP_TILE][8];
+    __shared__ int s_fin[AP_TILE];
     const int64_t a_tiles = ceil_div(pd.nA, BLOCK);
     const int64_t b_tiles = ceil_div(pd.nB, AP_TILE);
     const int64_t n_work = a_tiles * b_tiles;
@@ -827,18 +1077,19 @@ __global__ void __launch_bounds__(BLOCK) k_allpairs(PairDesc pd, hit_t *hits, in
         const int32_t ta = (int32_t)(at * BLOCK + threadIdx.x);
         const bool a_ok = ta < pd.nA;
         Tri P = a_ok ? load_tri(pd.A, ta) : Tri{};
-        Box ba = a_ok ? load_box(pd.A.box + 8 * (int64_t)ta) : Box{};
-        const bool a_fin = a_ok && (ba.lo[0] == ba.lo[0]);
+        double alo[4] = {0, 0, 0, 0}, ahi[4] = {0, 0, 0, 0};
+        const bool a_fin = a_ok && tri_box(pd.A, ta, alo, ahi);
         const int32_t tb0 = (int32_t)(bt * AP_TILE);
         __syncthreads();
         if (threadIdx.x < AP_TILE) {
             int32_t tb = tb0 + threadIdx.x;
             if (tb < pd.nB) {
                 Tri Q = load_tri(pd.B, tb);
-                Box bb = load_box(pd.B.box + 8 * (int64_t)tb);
+                double blo[4], bhi[4];
+                s_fin[threadIdx.x] = tri_box(pd.B, tb, blo, bhi) ? 1 : 0;
                 for (int j = 0; j < 3; ++j)
                     for (int d = 0; d < 4; ++d) s_tri[threadIdx.x][4 * j + d] = Q.p[j][d];
-                for (int d = 0; d < 4; ++d) { s_box[threadIdx.x][d] = bb.lo[d]; s_box[threadIdx.x][4 + d] = bb.hi[d]; }
+                for (int d = 0; d < 4; ++d) { s_box[threadIdx.x][d] = blo[d]; s_box[threadIdx.x][4 + d] = bhi[d]; }
             }
         }
         __syncthreads();
@@ -849,10 +1100,10 @@ __global__ void __launch_bounds__(BLOCK) k_allpairs(PairDesc pd, hit_t *hits, in
             for (int v = 0; v < 3; ++v)
 #pragma unroll
                 for (int d = 0; d < 4; ++d) Q.p[v][d] = s_tri[j][4 * v + d];
-            const bool b_fin = s_box[j][0] == s_box[j][0];
+            const bool b_fin = s_fin[j] != 0;
             bool box = true;
 #pragma unroll
-            for (int d = 0; d < 4; ++d) box = box && (ba.lo[d] <= s_box[j][4 + d]) && (s_box[j][d] <= ba.hi[d]);
+            for (int d = 0; d < 4; ++d) box = box && (alo[d] <= s_box[j][4 + d]) && (s_box[j][d] <= ahi[d]);
             double z[4];
             int st = pair_status_forced(P, Q, box, z);
             const bool live = a_fin && b_fin;
@@ -881,7 +1132,7 @@ __global__ void __launch_bounds__(BLOCK) k_count_all(PairDesc pd, unsigned long 
         const bool side = gt >= pd.nA;
         const int64_t t = side ? gt - pd.nA : gt;
         CellRange r;
-        if (tri_cells((side ? pd.B.box : pd.A.box) + 8 * t, pd.g, r)) all += (unsigned long long)range_count(r);
+        if (tri_cells(side ? pd.B : pd.A, (int32_t)t, pd.g, r)) all += (unsigned long long)range_count(r);
     }
     all = block_sum(all, s_tmp);
     if (threadIdx.x == 0) partial[blockIdx.x] = all;
@@ -901,8 +1152,8 @@ struct Geometry {
 struct Layout {
     int64_t ent_cap, cand_cap, hits_cap;
     RadixPlan rp;
-    size_t o_flags, o_part, o_rng, o_cnt, o_btot, o_keys, o_alt, o_sort, o_cstat, o_ctrs, o_cells, o_pstart, o_cand,
-        o_cpair, o_htmp, o_hkeys, o_halt, o_misc, o_desc, o_toff, o_cbase, total;
+    size_t o_flags, o_part, o_rng, o_keys, o_alt, o_sort, o_cstat, o_ctrs, o_bounds, o_cells, o_pstart,
+        o_cand, o_cpair, o_htmp, o_hkeys, o_halt, o_misc, o_desc, o_toff, o_cbase, total;
     int64_t n_kblocks, cell_cap;
 };
 
@@ -971,13 +1222,12 @@ void layout(const Geometry &G, Layout &L)
     L.o_flags = take((size_t)2 << G.bm_log2);
     L.o_part = take((size_t)MAX_GRID * 16);
     L.o_rng = take((size_t)(G.n_tri + 1) * 8);
-    L.o_cnt = take((size_t)(G.n_tri + 1) * 4);
-    L.o_btot = take((size_t)L.n_kblocks * 8);
     L.o_keys = take((size_t)(L.ent_cap + 1) * 8);
     L.o_alt = take((size_t)(L.ent_cap + 1) * 8);
     L.o_sort = take(radix_ws_bytes(L.rp));
-    L.o_cstat = take((size_t)tiles * 16);
+    L.o_cstat = take((size_t)tiles * 24);
     L.o_ctrs = take(64);
+    L.o_bounds = take((size_t)(L.ent_cap + 2) * 8);
     L.o_cells = take((size_t)L.cell_cap * sizeof(CellRec));
     L.o_pstart = take((size_t)(L.cell_cap + 1) * 8);
     L.o_cand = take((size_t)(L.cand_cap > 0 ? L.cand_cap : 1) * 8);
@@ -1056,12 +1306,12 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
     uint8_t *flags = (uint8_t *)(ws + L.o_flags);
     unsigned long long *mpart = (unsigned long long *)(ws + L.o_part);
     uint64_t *rng = (uint64_t *)(ws + L.o_rng);
-    uint32_t *cnt = (uint32_t *)(ws + L.o_cnt);
-    uint64_t *btot = (uint64_t *)(ws + L.o_btot);
     uint64_t *keys = (uint64_t *)(ws + L.o_keys);
     uint64_t *alt = (uint64_t *)(ws + L.o_alt);
     uint64_t *cstat = (uint64_t *)(ws + L.o_cstat);
-    uint32_t *ctrs = (uint32_t *)(ws + L.o_ctrs);     // [0]: k_cells tile counter
+    uint32_t *ctrs = (uint32_t *)(ws + L.o_ctrs);     // [0] k_cells_scan, [1] k_cells_keep tile counters;
+                                                      // [4..7] k_keys entry and block counters (2 x u64)
+    uint64_t *bounds = (uint64_t *)(ws + L.o_bounds);
     CellRec *cells = (CellRec *)(ws + L.o_cells);
     int64_t *pstart = (int64_t *)(ws + L.o_pstart);
     uint64_t *cand = cand_user ? cand_user : (uint64_t *)(ws + L.o_cand);
@@ -1069,13 +1319,14 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
     hit_t *htmp = (hit_t *)(ws + L.o_htmp);
     uint64_t *hkeys = (uint64_t *)(ws + L.o_hkeys);
     uint64_t *halt = (uint64_t *)(ws + L.o_halt);
-    int64_t *misc = (int64_t *)(ws + L.o_misc);       // [0] keys to sort
+    int64_t *misc = (int64_t *)(ws + L.o_misc);       // [0] keys to sort, [1] cells (all)
     RadixPlan rp = L.rp;
     radix_ws_carve(rp, ws + L.o_sort);
     const int R = 1 << rp.rb;
 
-    // 1. clear: counters, flags, sort histograms and tile counters, k_cells
-    //    counter (and, with no sort pass, k_cells' words)
+    // 1. clear: counters, flags, the keys' look-back words, sort histograms
+    //    and tile counters, the other tile counters (and, with no sort pass,
+    //    the cell scans' words)
     ClearSpec cs;
     cs.stats = stats;
     cs.flags = (uint64_t *)flags;
@@ -1093,7 +1344,7 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
     cs2.ctr_words = 16;
     if (rp.passes == 0) {
         cs2.kstat = cstat;
-        cs2.kstat_words = 2 * rp.tiles_cap;
+        cs2.kstat_words = 3 * rp.tiles_cap;
     }
     MS_LAUNCH("k_prepare", k_prepare, dim3(grid_for(cs2.kstat_words + 16, 256)), dim3(BLOCK), 0, st, cs2);
     const unsigned g_tri = grid_for(G.n_tri);
@@ -1101,8 +1352,7 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
     KeysOut ko;
     ko.keys = keys;
     ko.cap = L.ent_cap;
-    ko.cnt = cnt;
-    ko.btot = btot;
+    ko.ctr = (unsigned long long *)(ctrs + 4);
     ko.hist = rp.hist;
     ko.sort_status0 = rp.status;
     ko.passes = rp.passes;
@@ -1112,23 +1362,30 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
     ko.stats = stats;
     ko.mark_partial = mpart;
     ko.n_mark_partial = (int)g_tri;
-    MS_LAUNCH("k_count", k_count<ONE>, dim3((unsigned)L.n_kblocks), dim3(BLOCK), 0, st, bv, flags, rng, ko);
-    MS_LAUNCH("k_emit", k_emit<ONE>, dim3((unsigned)L.n_kblocks), dim3(BLOCK), 0, st, bv, flags, rng, ko);
+    MS_LAUNCH("k_keys", k_keys<ONE>, dim3((unsigned)L.n_kblocks), dim3(BLOCK), 0, st, bv, flags, rng, ko);
     MS_HIP(hipGetLastError());
     uint64_t *sorted = keys;
-    if ((rc = radix_sort(rp, keys, alt, misc, cstat, 2, st, &sorted))) return rc;
-    CellsOut co;
-    co.cells = cells;
-    co.pstart = pstart;
-    co.cstat = cstat;
-    co.tile_ctr = ctrs;
-    co.stats = stats;
+    if ((rc = radix_sort(rp, keys, alt, misc, cstat, 3, st, &sorted))) return rc;
     {
-        int64_t g = rp.tiles_cap < 1024 ? rp.tiles_cap : 1024;
-        MS_LAUNCH("k_cells", k_cells<ONE>, dim3((unsigned)g), dim3(BLOCK), 0, st, bv, sorted, misc, co);
+        const int64_t g = rp.tiles_cap < 1024 ? rp.tiles_cap : 1024;
+        CellsScanOut so;
+        so.bounds = bounds;
+        so.n_all = misc + 1;
+        so.stat = cstat;
+        so.tile_ctr = ctrs;
+        so.stats = stats;
+        MS_LAUNCH("k_cells_scan", k_cells_scan<ONE>, dim3((unsigned)g), dim3(BLOCK), 0, st, bv, sorted, misc, so);
+        CellsOut co;
+        co.cells = cells;
+        co.pstart = pstart;
+        co.stat = cstat;
+        co.tile_ctr = ctrs + 1;
+        co.stats = stats;
+        MS_LAUNCH("k_cells_keep", k_cells_keep<ONE>, dim3((unsigned)g), dim3(BLOCK), 0, st, bv, sorted, bounds,
+                  misc + 1, co);
     }
     MS_LAUNCH("k_enum", k_enum<ONE>, dim3(MAX_GRID), dim3(BLOCK), 0, st, bv, sorted, cells, pstart, stats, cand, cpair,
-                       cand_cap);
+              cand_cap);
     MS_LAUNCH("k_narrow", k_narrow<ONE>, dim3(MAX_GRID), dim3(BLOCK), 0, st, bv, cand, cpair, cand_cap, htmp, hkeys,
                        hits_cap, stats);
     MS_HIP(hipGetLastError());
