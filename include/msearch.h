@@ -321,7 +321,9 @@ enum {
 };
 
 /* Workspace bytes of refine_grad (mode 0-2) or refine_newton (mode 3) for K
- * hits; the adjoint's share grows with K x (steps / ckpt_every + ckpt_every). */
+ * hits.  The adjoint needs K x 2 x (steps / ckpt_every) x 32 B of checkpoints
+ * plus a window of recomputed states and step Jacobians (at most 256 MiB, at
+ * least one checkpoint segment). */
 int refine_workspace_size(int64_t K, const map_params_t *fwd, const map_params_t *bwd, int32_t ckpt_every,
                           int32_t mode, size_t *bytes);
 
@@ -333,11 +335,14 @@ int refine_workspace_size(int64_t K, const map_params_t *fwd, const map_params_t
  *   grad_dev    K x 5: dr/d(th1, s1, th2, s2, e) (adjoint and tangent modes);
  *   J_dev       K x 4 x 5, row-major (tangent mode, optional).
  * The adjoint runs the map forwards keeping the state every ckpt_every steps,
- * then backwards through the transpose of every Runge-Kutta step, recomputing
- * each segment from its checkpoint; the result does not depend on
- * ckpt_every (bit for bit).  The tangent integrates the variational
- * equations with the same method, so both give the derivative of the
- * discrete map.  ws: refine_workspace_size bytes.  Asynchronous on `stream`.
+ * then goes backwards over windows of whole checkpoint segments: the states of
+ * a window are recomputed from their checkpoints, the Jacobian of every step
+ * of the window (and its derivative with respect to e) is formed in parallel,
+ * and the cotangent is carried back through the transposed steps; the result
+ * does not depend on ckpt_every (bit for bit).  The tangent integrates the
+ * variational equations with the same method, so both give the derivative of
+ * the discrete map.  ws: refine_workspace_size bytes.  Asynchronous on
+ * `stream`.
  */
 int refine_grad(const double *params_dev, int64_t K, const patch_t *U_dev, const patch_t *S_dev,
                 int32_t patch_stride, const map_params_t *fwd, const map_params_t *bwd, int32_t ckpt_every,

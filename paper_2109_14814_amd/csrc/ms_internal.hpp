@@ -194,7 +194,8 @@ struct RadixPlan {
 RadixPlan radix_plan(int lo_bit, int n_bits, int64_t cap);
 size_t radix_ws_bytes(const RadixPlan &p);
 void radix_ws_carve(RadixPlan &p, void *base);
-// Sorted keys end in *result (keys or alt).  In its last pass each block
+// The key count is min(*n_dev, p.cap).  Sorted keys end in *result (keys or
+// alt).  In its last pass each block
 // also clears extra[tile * extra_per_tile ...] (a later kernel's words).
 int radix_sort(const RadixPlan &p, uint64_t *keys, uint64_t *alt, const int64_t *n_dev, uint64_t *extra,
                int extra_per_tile, hipStream_t st, uint64_t **result);

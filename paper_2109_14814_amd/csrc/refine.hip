@@ -11,15 +11,15 @@
 //     derivative of the discrete map; e enters through w(f) = 1/(1 + e cos f);
 //   * adjoint: the gradient of r by the discrete adjoint (transpose) of every
 //     Runge-Kutta step, run backwards from the seed dr/dF = +-2f, with the
-//     forward states kept only every `ckpt_every` steps and each segment
-//     recomputed before it is reversed;
+//     forward states kept only every `ckpt_every` steps and recomputed one
+//     window of segments at a time;
 //   * damped Newton (Sec. 7): x <- x - alpha Df^{-1} f, alpha halved until r
 //     decreases.
 //
-// One thread per trajectory (hit, side) for the state and adjoint passes and
-// one per (trajectory, tangent column) for the tangent pass; blocks of one
-// wave, so that the few hundred to few thousand trajectories spread over the
-// compute units.
+// One thread per trajectory (hit, side) for the state pass, per (trajectory,
+// tangent column) for the tangent pass and per (step, trajectory, column) for
+// the adjoint's step Jacobians; blocks of one wave, so that the few hundred to
+// few thousand trajectories spread over the compute units.
 #include <math.h>
 #include <string.h>
 
@@ -71,7 +71,6 @@ struct RefArgs {
     SideMap side[2];        // 0: unstable side (x_u), 1: stable side (x_s)
     int64_t ck;             // checkpoint interval (steps)
     double *ckpt;           // n_ck x 2K x 4 (adjoint; NULL otherwise)
-    double *seg;            // ck x 2K x 4 (adjoint)
     double *yend;           // 2K x 4
     double *dend;           // 3 x 2K x 4 (tangent)
     double *gpart;          // 2K x 3 (adjoint)
@@ -188,62 +187,6 @@ MS_D void rk_tangent_step(double y[4], double v[4], const double *__restrict__ w
     }
 }
 
-// Transpose of one step.  With stages Y_i = y + h sum_j a_ij k_j, k_i = F(Y_i)
-// and y+ = y + h sum_i b_i k_i, a cotangent lam on y+ gives
-//   g_i  = h b_i lam + sum_{j > i} h a_ji mu_j      (cotangent of k_i)
-//   mu_i = A(Y_i)^T g_i                             (cotangent of Y_i)
-//   lam <- lam + sum_i mu_i,   ge += g_i . dF/de(Y_i)
-// with A = dF/dy and dF/de = (0, 0, dw/de Omega_x, dw/de Omega_y).
-MS_D void rk_adjoint_step(d4 y0, const double *__restrict__ w, const double *__restrict__ dwde, double h,
-                          const Model &md, double lam[4], double &ge)
-{
-#pragma clang fp contract(fast)
-    double y[4] = {y0.x, y0.y, y0.z, y0.w};
-    double k[S][4];
-    OmegaD od[S];
-#pragma unroll
-    for (int i = 0; i < S; ++i) {
-        double ys[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            double acc = 0.0;
-#pragma unroll
-            for (int j = 0; j < i; ++j)
-                if (RK_NZ[i][j]) acc += c_cv.a[i][j] * k[j][c];
-            ys[c] = y[c] + h * acc;
-        }
-        od[i] = omega_derivs(md, ys[0], ys[1]);
-        k[i][0] = ys[2];
-        k[i][1] = ys[3];
-        k[i][2] = 2.0 * ys[3] + w[i] * od[i].Ox;
-        k[i][3] = -2.0 * ys[2] + w[i] * od[i].Oy;
-    }
-    double mu[S][4];
-    double dl[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int i = S - 1; i >= 0; --i) {
-        double g[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            double acc = RK_NZB[i] ? c_cv.b[i] * lam[c] : 0.0;
-#pragma unroll
-            for (int j = i + 1; j < S; ++j)
-                if (RK_NZ[j][i]) acc += c_cv.a[j][i] * mu[j][c];
-            g[c] = h * acc;
-        }
-        double wi = w[i];
-        mu[i][0] = wi * (od[i].Oxx * g[2] + od[i].Oxy * g[3]);
-        mu[i][1] = wi * (od[i].Oxy * g[2] + od[i].Oyy * g[3]);
-        mu[i][2] = g[0] - 2.0 * g[3];
-        mu[i][3] = g[1] + 2.0 * g[2];
-        ge += dwde[i] * (od[i].Ox * g[2] + od[i].Oy * g[3]);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) dl[c] += mu[i][c];
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) lam[c] = lam[c] + dl[c];
-}
-
 MS_D const double *stage_row(const double *tab, int64_t s, int32_t steps)
 {
     return tab + (size_t)(s % steps) * S;
@@ -337,49 +280,117 @@ __global__ void __launch_bounds__(RF_BLOCK) k_ref_combine(RefArgs a, int tangent
         }
 }
 
-// Adjoint pass: one thread per trajectory, seeded with dr/dy_end = +2f (u
-// side) or -2f (s side); segments of ck steps are recomputed from their
-// checkpoint into a.seg and then reversed step by step.
-__global__ void __launch_bounds__(RF_BLOCK) k_ref_adjoint(RefArgs a, const double *f)
+// The adjoint runs backwards over windows of consecutive steps (whole
+// checkpoint segments).  For one window:
+//   k_adj_states  per (segment, trajectory): the states before every step of
+//                 the segment, recomputed from its checkpoint;
+//   k_adj_jac     per (step, trajectory, column): the step's Jacobian
+//                 M_n = d y_{n+1} / d y_n (columns 0-3, a tangent step from a
+//                 unit vector) and d y_{n+1} / d e (column 4), all steps of the
+//                 window in parallel;
+//   k_adj_reverse per trajectory: lam <- M_n^T lam and ge += (d y_{n+1}/de) . lam
+//                 for n from the last step of the window down to the first.
+// This is the transpose of the discrete map, step by step (the discrete
+// adjoint), with the sequential part reduced to 4 x 4 products.
+__global__ void __launch_bounds__(RF_BLOCK) k_adj_states(RefArgs a, int64_t s_lo, int64_t s_hi, double *states)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 2 * a.K) return;
-    int side;
-    int64_t k;
-    double y0[4];
-    const double *patch;
-    traj_start(a, t, side, k, y0, patch);
-    const SideMap sm = a.side[side];
     const int64_t T2 = 2 * a.K;
-    double lam[4];
-    const double sg = side ? -2.0 : 2.0;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) lam[c] = sg * f[4 * k + c];
-    double ge = 0.0;
-    const int64_t nseg = ceil_div(sm.nsteps, a.ck);
-    for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
-        const int64_t s0 = sgi * a.ck;
-        const int64_t s1 = s0 + a.ck < sm.nsteps ? s0 + a.ck : sm.nsteps;
-        d4 y = load_d4(a.ckpt + (sgi * T2 + t) * 4);
-        for (int64_t s = s0; s < s1; ++s) {
-            double v[4] = {y.x, y.y, y.z, y.w};
-            store_d4(a.seg + ((s - s0) * T2 + t) * 4, v);
-            if (s + 1 < s1) y = rk_state_step(y, stage_row(sm.w, s, sm.steps), sm.h, a.md);
-        }
-        for (int64_t s = s1 - 1; s >= s0; --s) {
-            d4 ys = load_d4(a.seg + ((s - s0) * T2 + t) * 4);
-            rk_adjoint_step(ys, stage_row(sm.w, s, sm.steps), stage_row(sm.dwde, s, sm.steps), sm.h, a.md, lam, ge);
-        }
+    const int64_t nseg = (s_hi - s_lo + a.ck - 1) / a.ck;
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= nseg * T2) return;
+    const int64_t sg = gid / T2, t = gid - sg * T2;
+    const int side = t >= a.K ? 1 : 0;
+    const SideMap sm = a.side[side];
+    const int64_t s0 = s_lo + sg * a.ck;
+    int64_t s1 = s0 + a.ck < s_hi ? s0 + a.ck : s_hi;
+    if (s1 > sm.nsteps) s1 = sm.nsteps;
+    if (s0 >= s1) return;
+    d4 y = load_d4(a.ckpt + ((s0 / a.ck) * T2 + t) * 4);
+    for (int64_t s = s0; s < s1; ++s) {
+        double v[4] = {y.x, y.y, y.z, y.w};
+        store_d4(states + ((s - s_lo) * T2 + t) * 4, v);
+        if (s + 1 < s1) y = rk_state_step(y, stage_row(sm.w, s, sm.steps), sm.h, a.md);
     }
-    double g0 = 0.0, g1 = 0.0;
+}
+
+__global__ void __launch_bounds__(RF_BLOCK) k_adj_jac(RefArgs a, int64_t s_lo, int64_t s_hi, const double *states,
+                                                      double *jac)
+{
+    const int64_t T2 = 2 * a.K;
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (s_hi - s_lo) * T2 * 5) return;
+    const int64_t cell = gid / 5;
+    const int col = (int)(gid - cell * 5);
+    const int64_t sl = cell / T2, t = cell - sl * T2;
+    const int side = t >= a.K ? 1 : 0;
+    const SideMap sm = a.side[side];
+    const int64_t s = s_lo + sl;
+    if (s >= sm.nsteps) return;
+    const d4 ys = load_d4(states + (sl * T2 + t) * 4);
+    double y[4] = {ys.x, ys.y, ys.z, ys.w};
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (col < 4) v[col] = 1.0;
+    rk_tangent_step(y, v, stage_row(sm.w, s, sm.steps), stage_row(sm.dwde, s, sm.steps), sm.h, a.md, col == 4);
+    store_d4(jac + gid * 4, v);
+}
+
+// lam (4) and ge per trajectory live in adj[5 t ...]; init seeds lam = +-2 f.
+__global__ void __launch_bounds__(RF_BLOCK) k_adj_reverse(RefArgs a, int64_t s_lo, int64_t s_hi, const double *jac,
+                                                          double *adj, const double *f, int init)
+{
+    const int64_t T2 = 2 * a.K;
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T2) return;
+    const int side = t >= a.K ? 1 : 0;
+    const int64_t k = t - (side ? a.K : 0);
+    const SideMap sm = a.side[side];
+    double lam[4], ge;
+    if (init) {
+        const double sg = side ? -2.0 : 2.0;
+        for (int c = 0; c < 4; ++c) lam[c] = sg * f[4 * k + c];
+        ge = 0.0;
+    } else {
+        for (int c = 0; c < 4; ++c) lam[c] = adj[5 * t + c];
+        ge = adj[5 * t + 4];
+    }
+    const int64_t hi = s_hi < sm.nsteps ? s_hi : sm.nsteps;
+    for (int64_t s = hi - 1; s >= s_lo; --s) {
+        const double *J = jac + ((s - s_lo) * T2 + t) * 20;   // 5 columns of 4
+        double m[5][4];
 #pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            const d4 q = load_d4(J + 4 * c);
+            m[c][0] = q.x; m[c][1] = q.y; m[c][2] = q.z; m[c][3] = q.w;
+        }
+        ge += ((m[4][0] * lam[0] + m[4][1] * lam[1]) + m[4][2] * lam[2]) + m[4][3] * lam[3];
+        double nl[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) nl[c] = ((m[c][0] * lam[0] + m[c][1] * lam[1]) + m[c][2] * lam[2]) + m[c][3] * lam[3];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) lam[c] = nl[c];
+    }
+    for (int c = 0; c < 4; ++c) adj[5 * t + c] = lam[c];
+    adj[5 * t + 4] = ge;
+}
+
+// Per trajectory: the gradient with respect to its patch parameters
+// (lam . d1, lam . d2) and its share of d r / d e.
+__global__ void __launch_bounds__(RF_BLOCK) k_adj_finish(RefArgs a, const double *adj)
+{
+    const int64_t T2 = 2 * a.K;
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T2) return;
+    const int side = t >= a.K ? 1 : 0;
+    const int64_t k = t - (side ? a.K : 0);
+    const double *patch = (side ? a.Sp : a.U) + a.pstride * k;
+    double g0 = 0.0, g1 = 0.0;
     for (int c = 0; c < 4; ++c) {
-        g0 += lam[c] * patch[4 + c];
-        g1 += lam[c] * patch[8 + c];
+        g0 += adj[5 * t + c] * patch[4 + c];
+        g1 += adj[5 * t + c] * patch[8 + c];
     }
     a.gpart[3 * t + 0] = g0;
     a.gpart[3 * t + 1] = g1;
-    a.gpart[3 * t + 2] = ge;
+    a.gpart[3 * t + 2] = adj[5 * t + 4];
 }
 
 __global__ void __launch_bounds__(RF_BLOCK) k_ref_grad(RefArgs a, double *g_out)
@@ -541,8 +552,8 @@ __global__ void __launch_bounds__(RF_BLOCK) k_newton_finish(NewtonState ns, int6
 // ---------------------------------------------------------------- host side
 
 struct RefLayout {
-    size_t o_yend, o_dend, o_gpart, o_ckpt, o_seg, o_nw, total;
-    int64_t n_ck;
+    size_t o_yend, o_dend, o_gpart, o_ckpt, o_states, o_jac, o_adj, o_nw, total;
+    int64_t n_ck, win_steps, n_steps_max;
 };
 
 inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -566,6 +577,11 @@ int check_maps(const map_params_t *fwd, const map_params_t *bwd)
     return MS_OK;
 }
 
+// Steps per adjoint window: whole checkpoint segments, as many as fit
+// ADJ_WINDOW_BYTES of states and step Jacobians (at least one segment).
+constexpr int64_t ADJ_WINDOW_BYTES = (int64_t)256 << 20;
+constexpr int64_t ADJ_BYTES_PER_STEP = 32 + 5 * 32;   // per trajectory: state + 5 Jacobian columns
+
 RefLayout ref_layout(int64_t K, const map_params_t *fwd, const map_params_t *bwd, int32_t ck, int32_t mode)
 {
     RefLayout L;
@@ -577,13 +593,22 @@ RefLayout ref_layout(int64_t K, const map_params_t *fwd, const map_params_t *bwd
     L.o_dend = take((mode == MS_REFINE_TANGENT || mode == MS_REFINE_NEWTON) ? 3 * T2 * 32 : 0);
     L.o_gpart = take(mode == MS_REFINE_ADJOINT ? T2 * 24 : 0);
     if (mode == MS_REFINE_ADJOINT) {
-        int64_t a = ceil_div(side_steps(fwd), ck), b = ceil_div(side_steps(bwd), ck);
-        L.n_ck = a > b ? a : b;
+        const int64_t a = side_steps(fwd), b = side_steps(bwd);
+        L.n_steps_max = a > b ? a : b;
+        L.n_ck = ceil_div(L.n_steps_max, ck);
+        int64_t segs = ADJ_WINDOW_BYTES / ((int64_t)(T2 > 0 ? T2 : 1) * ADJ_BYTES_PER_STEP * ck);
+        if (segs < 1) segs = 1;
+        if (segs > L.n_ck) segs = L.n_ck > 0 ? L.n_ck : 1;
+        L.win_steps = segs * ck;
         L.o_ckpt = take((size_t)L.n_ck * T2 * 32);
-        L.o_seg = take((size_t)ck * T2 * 32);
+        L.o_states = take((size_t)L.win_steps * T2 * 32);
+        L.o_jac = take((size_t)L.win_steps * T2 * 160);
+        L.o_adj = take(T2 * 40);
     } else {
         L.o_ckpt = take(0);
-        L.o_seg = take(0);
+        L.o_states = take(0);
+        L.o_jac = take(0);
+        L.o_adj = take(0);
     }
     L.o_nw = take(mode == MS_REFINE_NEWTON ? (size_t)K * (18 * 8 + 3 * 4) + 9 * 256 : 0);
     L.total = o;
@@ -670,16 +695,29 @@ extern "C" int refine_grad(const double *params_dev, int64_t K, const patch_t *U
         MS_LAUNCH("k_ref_combine", k_ref_combine, dim3(blocks_for(K)), dim3(RF_BLOCK), 0, st, a, 1, f_dev, r_dev, J_dev,
                   grad_dev);
     } else {
-        if (mode == MS_REFINE_ADJOINT) {
-            a.ckpt = (double *)(w + L.o_ckpt);
-            a.seg = (double *)(w + L.o_seg);
-        }
+        if (mode == MS_REFINE_ADJOINT) a.ckpt = (double *)(w + L.o_ckpt);
         MS_LAUNCH("k_ref_state", k_ref_state, dim3(blocks_for(T2)), dim3(RF_BLOCK), 0, st, a);
         MS_LAUNCH("k_ref_combine", k_ref_combine, dim3(blocks_for(K)), dim3(RF_BLOCK), 0, st, a, 0, f_dev, r_dev,
                   (double *)nullptr, (double *)nullptr);
         if (mode == MS_REFINE_ADJOINT) {
-            MS_LAUNCH("k_ref_adjoint", k_ref_adjoint, dim3(blocks_for(T2)), dim3(RF_BLOCK), 0, st, a,
-                      (const double *)f_dev);
+            double *states = (double *)(w + L.o_states), *jac = (double *)(w + L.o_jac), *adj = (double *)(w + L.o_adj);
+            const int64_t W = L.win_steps;
+            int64_t nwin = ceil_div(L.n_steps_max, W);
+            if (nwin < 1) nwin = 1;
+            for (int64_t wi = nwin - 1; wi >= 0; --wi) {
+                const int64_t s_lo = wi * W;
+                const int64_t s_hi = s_lo + W < L.n_steps_max ? s_lo + W : L.n_steps_max;
+                const int64_t nseg = ceil_div(s_hi - s_lo, (int64_t)ck);
+                if (s_hi > s_lo) {
+                    MS_LAUNCH("k_adj_states", k_adj_states, dim3(blocks_for(nseg * T2)), dim3(RF_BLOCK), 0, st, a, s_lo,
+                              s_hi, states);
+                    MS_LAUNCH("k_adj_jac", k_adj_jac, dim3(blocks_for((s_hi - s_lo) * T2 * 5)), dim3(RF_BLOCK), 0, st, a,
+                              s_lo, s_hi, (const double *)states, jac);
+                }
+                MS_LAUNCH("k_adj_reverse", k_adj_reverse, dim3(blocks_for(T2)), dim3(RF_BLOCK), 0, st, a, s_lo, s_hi,
+                          (const double *)jac, adj, (const double *)f_dev, (int)(wi == nwin - 1));
+            }
+            MS_LAUNCH("k_adj_finish", k_adj_finish, dim3(blocks_for(T2)), dim3(RF_BLOCK), 0, st, a, (const double *)adj);
             MS_LAUNCH("k_ref_grad", k_ref_grad, dim3(blocks_for(K)), dim3(RF_BLOCK), 0, st, a, grad_dev);
         }
     }

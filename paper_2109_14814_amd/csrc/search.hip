@@ -82,7 +82,7 @@ struct BatchView {
     const uint64_t *cell_base;   // n_pairs + 1 (batch)
     int64_t n_tri;
     int32_t n_pairs;
-    int32_t bm_log2;             // occupancy flags per side: 2^bm_log2 bytes
+    int32_t bm_log2;             // occupancy flags per side: 2^bm_log2 bytes, then as many bits
     int32_t packable;            // every grid has <= 4096 cells per axis
     int32_t pb, tbA, tbB;        // bits of the pair, A- and B-triangle fields of hit keys
     KeyLayout kl;
@@ -162,14 +162,17 @@ MS_D void for_cells(const CellRange &r, const int64_t n[4], F &&f)
             }
 }
 
-// Occupancy flags of the cells of a range held by `other`, as a bit mask in
-// lexicographic order of the cells.  Ranges of up to 8 cells compute the j-th
-// cell from the mixed-radix digits of j, so that all their flag loads are in
-// flight together (the table is far larger than the caches); *big is set for
-// larger ranges, which the caller walks with for_cells.
+// Occupancy bit of hashed cell h in a side's bit table.
+MS_D uint32_t occ_bit(const uint32_t *bits, uint32_t h) { return (bits[h >> 5] >> (h & 31)) & 1u; }
+
+// Occupancy bits of the cells of a range held by the other mesh (its bit
+// table `other`), as a mask in lexicographic order of the cells.  Ranges of
+// up to 8 cells compute the j-th cell from the mixed-radix digits of j, so
+// that all their loads are in flight together; *big is set for larger
+// ranges, which the caller walks with for_cells.
 constexpr int MLP_CELLS = 8;
 
-MS_D uint32_t flag_mask(const CellRange &r, const int64_t n[4], uint64_t cb, const uint8_t *other, int log2,
+MS_D uint32_t flag_mask(const CellRange &r, const int64_t n[4], uint64_t cb, const uint32_t *other, int log2,
                         bool *big)
 {
     const int64_t cnt = range_count(r);
@@ -177,7 +180,7 @@ MS_D uint32_t flag_mask(const CellRange &r, const int64_t n[4], uint64_t cb, con
     if (*big) return 0;
     const uint32_t e1 = (uint32_t)(r.hi[1] - r.lo[1] + 1), e2 = (uint32_t)(r.hi[2] - r.lo[2] + 1),
                    e3 = (uint32_t)(r.hi[3] - r.lo[3] + 1);
-    uint8_t v[MLP_CELLS];
+    uint32_t v[MLP_CELLS];
 #pragma unroll
     for (int j = 0; j < MLP_CELLS; ++j) {
         v[j] = 0;
@@ -187,12 +190,12 @@ MS_D uint32_t flag_mask(const CellRange &r, const int64_t n[4], uint64_t cb, con
             const uint32_t d2 = q % e2; q /= e2;
             const uint32_t d1 = q % e1; q /= e1;
             const int64_t cell = (((r.lo[0] + q) * n[1] + r.lo[1] + d1) * n[2] + r.lo[2] + d2) * n[3] + r.lo[3] + d3;
-            v[j] = other[bm_hash(cb + (uint64_t)cell, log2)];
+            v[j] = occ_bit(other, bm_hash(cb + (uint64_t)cell, log2));
         }
     }
     uint32_t m = 0;
 #pragma unroll
-    for (int j = 0; j < MLP_CELLS; ++j) m |= (uint32_t)(v[j] != 0) << j;
+    for (int j = 0; j < MLP_CELLS; ++j) m |= v[j] << j;
     return m;
 }
 
@@ -431,37 +434,50 @@ __global__ void __launch_bounds__(BLOCK) k_mark(BatchView bv, uint8_t *flags, ui
     }
 }
 
+// Occupancy bytes -> bits (32 flags per word), so that the lookups of
+// k_keys hit a table small enough to stay in the L2 caches.
+__global__ void __launch_bounds__(BLOCK) k_pack(const uint8_t *flags, uint32_t *bits, int64_t n_words)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < n_words; w += stride) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(flags + 32 * w);
+        const uint4 a = p[0], b = p[1];
+        const uint32_t q[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+        uint32_t m = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) m |= (uint32_t)(((q[i] >> (8 * j)) & 0xffu) != 0) << (4 * i + j);
+        bits[w] = m;
+    }
+}
+
 struct KeysOut {
     uint64_t *keys;
     int64_t cap;
-    unsigned long long *ctr;  // [0] entries reserved, [1] blocks done (cleared)
-    uint32_t *hist;           // passes x radix digit counts of the sort
-    uint32_t *sort_status0;   // the sort's pass-0 look-back words (radix per tile)
+    unsigned long long *n_keys;   // entries reserved (cleared); the sort and the cell scan read it
+    uint32_t *hist;               // passes x radix digit counts of the sort
+    uint32_t *sort_status0;       // the sort's pass-0 look-back words (radix per tile)
     int passes, rb, lo_bit;
-    int64_t *n_eff;           // keys to sort (0 on overflow)
     search_stats_t *stats;
-    const unsigned long long *mark_partial;
-    int n_mark_partial;
 };
 
 // Entries of each triangle: the cells of its range that the other mesh also
 // occupies (a cell holding one mesh only cannot hold a pair).  Each block
 // counts the entries of its KEYS_TILE triangles, reserves that many output
-// slots with one atomic add and writes the keys [cell | side | triangle].
-// The blocks' output ranges come out in any order, which the sort makes
-// irrelevant (the keys are distinct).  Also accumulates the digit histograms
-// of every sort pass, clears the sort's pass-0 look-back words of the tiles
-// it writes, and the last block to finish publishes the totals.
+// slots with one atomic add (blocks without entries take none) and writes the
+// keys [cell | side | triangle].  The blocks' output ranges come out in any
+// order, which the sort makes irrelevant (the keys are distinct).  Also
+// accumulates the digit histograms of every sort pass and clears the sort's
+// pass-0 look-back words of the tiles it writes.
 template <bool ONE>
-__global__ void __launch_bounds__(BLOCK) k_keys(BatchView bv, const uint8_t *flags, const uint64_t *rng, KeysOut o)
+__global__ void __launch_bounds__(BLOCK) k_keys(BatchView bv, const uint32_t *bits, const uint64_t *rng, KeysOut o)
 {
     __shared__ uint32_t s_hist[MAX_PASSES * 1024];
     __shared__ uint64_t s_tmp[BLOCK / WAVE];
     __shared__ unsigned long long s_blk0;
-    __shared__ int s_last;
-    const size_t side_bytes = (size_t)1 << bv.bm_log2;
+    const size_t side_words = ((size_t)1 << bv.bm_log2) / 32;
     const int R = 1 << o.rb;
-    for (int i = threadIdx.x; i < o.passes * R; i += BLOCK) s_hist[i] = 0;
     const int64_t base = (int64_t)blockIdx.x * KEYS_TILE;
     uint32_t cnt[KEYS_ITEMS];
     uint64_t mine = 0;
@@ -473,12 +489,12 @@ __global__ void __launch_bounds__(BLOCK) k_keys(BatchView bv, const uint8_t *fla
             TriLoc L = locate<ONE>(bv, gt);
             CellRange r;
             if (range_of<ONE>(bv, rng, gt, L, r)) {
-                const uint8_t *other = flags + (size_t)(1 - L.side) * side_bytes;
+                const uint32_t *other = bits + (size_t)(1 - L.side) * side_words;
                 const PairDesc &P = pair_desc<ONE>(bv, L.p);
                 bool big;
                 const uint32_t m = flag_mask(r, P.g.n, P.cell_base, other, bv.bm_log2, &big);
                 if (!big) c = (uint32_t)__builtin_popcount(m);
-                else for_cells(r, P.g.n, [&](uint64_t cell) { c += other[bm_hash(P.cell_base + cell, bv.bm_log2)] != 0; });
+                else for_cells(r, P.g.n, [&](uint64_t cell) { c += occ_bit(other, bm_hash(P.cell_base + cell, bv.bm_log2)); });
             }
         }
         cnt[i] = c;
@@ -486,30 +502,16 @@ __global__ void __launch_bounds__(BLOCK) k_keys(BatchView bv, const uint8_t *fla
     }
     uint64_t btotal;
     const uint64_t texcl = block_excl(mine, s_tmp, &btotal);
+    if (btotal == 0) return;                      // uniform: every thread saw the same total
+    for (int i = threadIdx.x; i < o.passes * R; i += BLOCK) s_hist[i] = 0;
     if (threadIdx.x == 0) {
-        s_blk0 = btotal ? atomicAdd(&o.ctr[0], (unsigned long long)btotal) : 0ull;
-        __threadfence();
-        s_last = atomicAdd(&o.ctr[1], 1ull) == (unsigned long long)(gridDim.x - 1);
+        const unsigned long long b0 = atomicAdd(o.n_keys, (unsigned long long)btotal);
+        s_blk0 = b0;
+        if ((int64_t)(b0 + btotal) > o.cap) atomicOr((unsigned long long *)&o.stats->overflow, 1ull);
     }
     __syncthreads();
     const uint64_t blk0 = s_blk0;
-    if (s_last) {
-        // the last block publishes the totals (mark partials summed by the whole block)
-        __threadfence();
-        unsigned long long all = 0, bad = 0;
-        for (int i = threadIdx.x; i < o.n_mark_partial; i += BLOCK) { all += o.mark_partial[2 * i]; bad += o.mark_partial[2 * i + 1]; }
-        all = block_sum(all, (unsigned long long *)s_tmp);
-        bad = block_sum(bad, (unsigned long long *)s_tmp);
-        if (threadIdx.x == 0) {
-            const int64_t E = (int64_t)__hip_atomic_load(&o.ctr[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            o.stats->n_entries = E;
-            o.stats->n_entries_all = (int64_t)all;
-            o.stats->n_nonfinite = (int64_t)bad;
-            *o.n_eff = E <= o.cap ? E : 0;
-            if (E > o.cap) atomicOr((unsigned long long *)&o.stats->overflow, 1ull);
-        }
-    }
-    if (btotal > 0 && (int64_t)(blk0 + btotal) <= o.cap) {
+    if ((int64_t)(blk0 + btotal) <= o.cap) {
         const int64_t t0 = (int64_t)blk0 / SORT_TILE_KEYS, t1 = (int64_t)(blk0 + btotal - 1) / SORT_TILE_KEYS;
         for (int64_t w = threadIdx.x; w < (t1 - t0 + 1) * R; w += BLOCK) o.sort_status0[t0 * R + w] = 0;
     }
@@ -521,7 +523,7 @@ __global__ void __launch_bounds__(BLOCK) k_keys(BatchView bv, const uint8_t *fla
         TriLoc L = locate<ONE>(bv, gt);
         CellRange r;
         range_of<ONE>(bv, rng, gt, L, r);
-        const uint8_t *other = flags + (size_t)(1 - L.side) * side_bytes;
+        const uint32_t *other = bits + (size_t)(1 - L.side) * side_words;
         const PairDesc &P = pair_desc<ONE>(bv, L.p);
         const uint64_t cb = P.cell_base;
         const uint64_t low = ((uint64_t)L.side << bv.kl.tb) | (uint64_t)L.t;
@@ -544,14 +546,13 @@ __global__ void __launch_bounds__(BLOCK) k_keys(BatchView bv, const uint8_t *fla
             }
         } else {
             for_cells(r, P.g.n, [&](uint64_t cell) {
-                if (other[bm_hash(cb + cell, bv.bm_log2)]) put(cb + cell);
+                if (occ_bit(other, bm_hash(cb + cell, bv.bm_log2))) put(cb + cell);
             });
         }
     }
     __syncthreads();
-    if (btotal > 0)
-        for (int i = threadIdx.x; i < o.passes * R; i += BLOCK)
-            if (s_hist[i]) atomicAdd(&o.hist[i], s_hist[i]);
+    for (int i = threadIdx.x; i < o.passes * R; i += BLOCK)
+        if (s_hist[i]) atomicAdd(&o.hist[i], s_hist[i]);
 }
 
 struct CellRec {
@@ -598,6 +599,9 @@ struct CellsScanOut {
     uint64_t *bounds;         // n_all + 1
     int64_t *n_all;           // cells (including one-mesh cells)
     search_stats_t *stats;
+    int64_t cap;              // key capacity (the count read is clamped to it)
+    const unsigned long long *mark_partial;
+    int n_mark_partial;
     uint64_t *stat;           // 3 look-back words per tile: [0] here, [1..2] k_cells_keep
     uint32_t *tile_ctr;
 };
@@ -609,9 +613,23 @@ __global__ void __launch_bounds__(BLOCK) k_cells_scan(BatchView bv, const uint64
     __shared__ uint64_t s_tmp64[BLOCK / WAVE];
     __shared__ uint64_t s_base;
     __shared__ uint32_t s_tile;
-    const int64_t n = *n_dev;
+    const int64_t E = *n_dev;
+    const int64_t n = E < o.cap ? E : o.cap;
     const int64_t ntiles = (n + CELLS_TILE - 1) / CELLS_TILE;
     const int sh = bv.kl.cell_shift, tb = bv.kl.tb;
+    if (blockIdx.x == 0) {
+        // totals of the keying kernels: entries, entries before the filter, non-finite triangles
+        unsigned long long all = 0, bad = 0;
+        for (int i = threadIdx.x; i < o.n_mark_partial; i += BLOCK) { all += o.mark_partial[2 * i]; bad += o.mark_partial[2 * i + 1]; }
+        all = block_sum(all, (unsigned long long *)s_tmp64);
+        bad = block_sum(bad, (unsigned long long *)s_tmp64);
+        if (threadIdx.x == 0) {
+            o.stats->n_entries = E;
+            o.stats->n_entries_all = (int64_t)all;
+            o.stats->n_nonfinite = (int64_t)bad;
+        }
+        __syncthreads();
+    }
     if (n == 0) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             *o.n_all = 0;
@@ -848,6 +866,8 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
     __shared__ uint64_t s_cell[ENUM_CELLS];
     __shared__ int64_t s_c0, s_c1, s_e0;
     __shared__ int s_staged;
+    __shared__ uint32_t s_kscan[BLOCK / WAVE];
+    __shared__ unsigned long long s_kbase;
     const int64_t ncells = stats->n_cells;
     const int64_t P = stats->n_slots;
     const int64_t nchunks = ceil_div(P, ENUM_SLOTS);
@@ -914,12 +934,15 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
             __syncthreads();
         }
         int64_t cg = c0;   // cell of this thread's last slot (unstaged path)
-#pragma unroll 1
+        uint64_t packed[ENUM_ITEMS];
+        int32_t prs[ENUM_ITEMS];
+        uint32_t keepm = 0;
+#pragma unroll
         for (int j = 0; j < ENUM_ITEMS; ++j) {
             const int64_t slot = S0 + (int64_t)j * BLOCK + threadIdx.x;
             bool keep = false;
-            uint64_t packed = 0;
-            int32_t pr = 0;
+            packed[j] = 0;
+            prs[j] = 0;
             if (slot < S1) {
                 if (staged) {
                     int lo = 0, hi = (int)nc;          // last staged cell with s_pre <= slot
@@ -933,8 +956,8 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
                     const uint32_t local = (uint32_t)(slot - s_pre[c]);
                     const uint32_t iB = local / (uint32_t)nA, iA = local - iB * (uint32_t)nA;
                     const int ia = s_first[c] + (int)iA, ib = s_first[c] + nA + (int)iB;
-                    pr = s_pair[c];
-                    const PairDesc &Pd = pair_desc<ONE>(bv, pr);
+                    prs[j] = s_pair[c];
+                    const PairDesc &Pd = pair_desc<ONE>(bv, prs[j]);
                     double alo[4], ahi[4], blo[4], bhi[4];
 #pragma unroll
                     for (int d = 0; d < 4; ++d) {
@@ -942,7 +965,7 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
                         blo[d] = s_box[ib][d]; bhi[d] = s_box[ib][4 + d];
                     }
                     keep = enum_pair<ONE>(Pd, s_cell[c], alo, ahi, blo, bhi);
-                    packed = ((uint64_t)(uint32_t)s_t[ia] << 32) | (uint32_t)s_t[ib];
+                    packed[j] = ((uint64_t)(uint32_t)s_t[ia] << 32) | (uint32_t)s_t[ib];
                 } else {
                     while (pstart[cg + 1] <= slot) ++cg;
                     const CellRec cr = cells[cg];
@@ -951,25 +974,34 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
                     const uint64_t iA = local - iB * (uint64_t)cr.nA;
                     const uint64_t kA = keys[cr.start + (int64_t)iA];
                     const uint64_t kB = keys[cr.start + cr.nA + (int64_t)iB];
-                    pr = cr.pair;
-                    const PairDesc &Pd = pair_desc<ONE>(bv, pr);
+                    prs[j] = cr.pair;
+                    const PairDesc &Pd = pair_desc<ONE>(bv, prs[j]);
                     const int32_t ta = (int32_t)(kA & bv.kl.tmask), tb = (int32_t)(kB & bv.kl.tmask);
                     double alo[4], ahi[4], blo[4], bhi[4];
                     tri_box(Pd.A, ta, alo, ahi);
                     tri_box(Pd.B, tb, blo, bhi);
                     keep = enum_pair<ONE>(Pd, (kA >> bv.kl.cell_shift) - Pd.cell_base, alo, ahi, blo, bhi);
-                    packed = ((uint64_t)(uint32_t)ta << 32) | (uint32_t)tb;
+                    packed[j] = ((uint64_t)(uint32_t)ta << 32) | (uint32_t)tb;
                 }
             }
-            const int64_t idx = wave_reserve(keep, (unsigned long long *)&stats->n_cand);
-            if (keep) {
-                if (idx < cand_cap) {
-                    cand[idx] = packed;
-                    cand_pair[idx] = pr;
-                } else {
-                    atomicOr((unsigned long long *)&stats->overflow, 2ull);
-                }
+            keepm |= (uint32_t)keep << j;
+        }
+        // one reservation per chunk: a block scan of the kept counts, one atomic add
+        uint32_t ktot;
+        const uint32_t kex = block_excl((uint32_t)__builtin_popcount(keepm), s_kscan, &ktot);
+        if (threadIdx.x == 0) s_kbase = ktot ? atomicAdd((unsigned long long *)&stats->n_cand, (unsigned long long)ktot) : 0ull;
+        __syncthreads();
+        int64_t idx = (int64_t)s_kbase + kex;
+#pragma unroll
+        for (int j = 0; j < ENUM_ITEMS; ++j) {
+            if (!(keepm >> j & 1)) continue;
+            if (idx < cand_cap) {
+                cand[idx] = packed[j];
+                cand_pair[idx] = prs[j];
+            } else {
+                atomicOr((unsigned long long *)&stats->overflow, 2ull);
             }
+            ++idx;
         }
         __syncthreads();
     }
@@ -1152,7 +1184,7 @@ struct Geometry {
 struct Layout {
     int64_t ent_cap, cand_cap, hits_cap;
     RadixPlan rp;
-    size_t o_flags, o_part, o_rng, o_keys, o_alt, o_sort, o_cstat, o_ctrs, o_bounds, o_cells, o_pstart,
+    size_t o_flags, o_bits, o_part, o_rng, o_keys, o_alt, o_sort, o_cstat, o_ctrs, o_bounds, o_cells, o_pstart,
         o_cand, o_cpair, o_htmp, o_hkeys, o_halt, o_misc, o_desc, o_toff, o_cbase, total;
     int64_t n_kblocks, cell_cap;
 };
@@ -1206,8 +1238,8 @@ int geometry(int64_t n_pairs, const ms_mesh *const *A, const ms_mesh *const *B, 
     if (G.cell_bits + 1 + G.tb > 63)
         return fail(MS_E_KEYBITS, "search: cell index + side + triangle needs more than 63 key bits; coarsen the grid");
     if (G.pb + G.tbA + G.tbB > 64) return fail(MS_E_KEYBITS, "search: pair + triangle indices exceed 64 bits");
-    int lg = bits_for((uint64_t)(G.n_tri > 0 ? G.n_tri : 1)) + 3;
-    G.bm_log2 = lg < 12 ? 12 : (lg > 23 ? 23 : lg);
+    int lg = bits_for((uint64_t)(G.n_tri > 0 ? G.n_tri : 1)) + 2;
+    G.bm_log2 = lg < 12 ? 12 : (lg > 25 ? 25 : lg);
     return MS_OK;
 }
 
@@ -1220,6 +1252,7 @@ void layout(const Geometry &G, Layout &L)
     L.cell_cap = L.ent_cap / 2 + 1;
     const int64_t tiles = L.rp.tiles_cap;
     L.o_flags = take((size_t)2 << G.bm_log2);
+    L.o_bits = take(((size_t)2 << G.bm_log2) / 8);
     L.o_part = take((size_t)MAX_GRID * 16);
     L.o_rng = take((size_t)(G.n_tri + 1) * 8);
     L.o_keys = take((size_t)(L.ent_cap + 1) * 8);
@@ -1309,8 +1342,9 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
     uint64_t *keys = (uint64_t *)(ws + L.o_keys);
     uint64_t *alt = (uint64_t *)(ws + L.o_alt);
     uint64_t *cstat = (uint64_t *)(ws + L.o_cstat);
-    uint32_t *ctrs = (uint32_t *)(ws + L.o_ctrs);     // [0] k_cells_scan, [1] k_cells_keep tile counters;
-                                                      // [4..7] k_keys entry and block counters (2 x u64)
+    uint32_t *ctrs = (uint32_t *)(ws + L.o_ctrs);     // [0] k_cells_scan, [1] k_cells_keep tile counters
+    unsigned long long *n_keys = (unsigned long long *)(ctrs + 4);   // entries reserved by k_keys
+    uint32_t *bits = (uint32_t *)(ws + L.o_bits);
     uint64_t *bounds = (uint64_t *)(ws + L.o_bounds);
     CellRec *cells = (CellRec *)(ws + L.o_cells);
     int64_t *pstart = (int64_t *)(ws + L.o_pstart);
@@ -1319,7 +1353,7 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
     hit_t *htmp = (hit_t *)(ws + L.o_htmp);
     uint64_t *hkeys = (uint64_t *)(ws + L.o_hkeys);
     uint64_t *halt = (uint64_t *)(ws + L.o_halt);
-    int64_t *misc = (int64_t *)(ws + L.o_misc);       // [0] keys to sort, [1] cells (all)
+    int64_t *misc = (int64_t *)(ws + L.o_misc);       // [1] cells (all)
     RadixPlan rp = L.rp;
     radix_ws_carve(rp, ws + L.o_sort);
     const int R = 1 << rp.rb;
@@ -1349,23 +1383,22 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
     MS_LAUNCH("k_prepare", k_prepare, dim3(grid_for(cs2.kstat_words + 16, 256)), dim3(BLOCK), 0, st, cs2);
     const unsigned g_tri = grid_for(G.n_tri);
     MS_LAUNCH("k_mark", k_mark<ONE>, dim3(g_tri), dim3(BLOCK), 0, st, bv, flags, rng, mpart);
+    const int64_t n_words = ((int64_t)2 << G.bm_log2) / 32;
+    MS_LAUNCH("k_pack", k_pack, dim3(grid_for(n_words, 4096)), dim3(BLOCK), 0, st, flags, bits, n_words);
     KeysOut ko;
     ko.keys = keys;
     ko.cap = L.ent_cap;
-    ko.ctr = (unsigned long long *)(ctrs + 4);
+    ko.n_keys = n_keys;
     ko.hist = rp.hist;
     ko.sort_status0 = rp.status;
     ko.passes = rp.passes;
     ko.rb = rp.rb;
     ko.lo_bit = rp.lo_bit;
-    ko.n_eff = misc;
     ko.stats = stats;
-    ko.mark_partial = mpart;
-    ko.n_mark_partial = (int)g_tri;
-    MS_LAUNCH("k_keys", k_keys<ONE>, dim3((unsigned)L.n_kblocks), dim3(BLOCK), 0, st, bv, flags, rng, ko);
+    MS_LAUNCH("k_keys", k_keys<ONE>, dim3((unsigned)L.n_kblocks), dim3(BLOCK), 0, st, bv, bits, rng, ko);
     MS_HIP(hipGetLastError());
     uint64_t *sorted = keys;
-    if ((rc = radix_sort(rp, keys, alt, misc, cstat, 3, st, &sorted))) return rc;
+    if ((rc = radix_sort(rp, keys, alt, (const int64_t *)n_keys, cstat, 3, st, &sorted))) return rc;
     {
         const int64_t g = rp.tiles_cap < 1024 ? rp.tiles_cap : 1024;
         CellsScanOut so;
@@ -1374,7 +1407,11 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
         so.stat = cstat;
         so.tile_ctr = ctrs;
         so.stats = stats;
-        MS_LAUNCH("k_cells_scan", k_cells_scan<ONE>, dim3((unsigned)g), dim3(BLOCK), 0, st, bv, sorted, misc, so);
+        so.cap = L.ent_cap;
+        so.mark_partial = mpart;
+        so.n_mark_partial = (int)g_tri;
+        MS_LAUNCH("k_cells_scan", k_cells_scan<ONE>, dim3((unsigned)g), dim3(BLOCK), 0, st, bv, sorted,
+                  (const int64_t *)n_keys, so);
         CellsOut co;
         co.cells = cells;
         co.pstart = pstart;

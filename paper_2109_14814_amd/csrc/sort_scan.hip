@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(SORT_BLOCK) k_radix_onesweep(const uint64_t *_
                                                                int shift, const uint32_t *__restrict__ hist_pass,
                                                                uint32_t *status, uint32_t *status_next,
                                                                uint32_t *tile_ctr, uint64_t *extra,
-                                                               int extra_per_tile)
+                                                               int extra_per_tile, int64_t cap)
 {
     constexpr int R = 1 << RBT;
     constexpr int DPT = R / SORT_BLOCK;
@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(SORT_BLOCK) k_radix_onesweep(const uint64_t *_
     __shared__ uint32_t s_tile;
 
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
-    const int64_t n = *n_dev;
+    const int64_t n = *n_dev < cap ? *n_dev : cap;
     const int64_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
     if ((int64_t)blockIdx.x >= ntiles) return;   // no tile for this block: leave the counter alone
 
@@ -509,13 +509,13 @@ int radix_sort(const RadixPlan &p, uint64_t *keys, uint64_t *alt, const int64_t 
         int shift = p.lo_bit + p.rb * q;
         if (p.rb == 8)
             MS_LAUNCH("k_radix_onesweep", k_radix_onesweep<8>, dim3((unsigned)g), dim3(SORT_BLOCK), 0, st, src, dst, n_dev, shift,
-                               p.hist + q * r, stat, next, p.tile_ctr + q, ex, extra_per_tile);
+                               p.hist + q * r, stat, next, p.tile_ctr + q, ex, extra_per_tile, p.cap);
         else if (p.rb == 9)
             MS_LAUNCH("k_radix_onesweep", k_radix_onesweep<9>, dim3((unsigned)g), dim3(SORT_BLOCK), 0, st, src, dst, n_dev, shift,
-                               p.hist + q * r, stat, next, p.tile_ctr + q, ex, extra_per_tile);
+                               p.hist + q * r, stat, next, p.tile_ctr + q, ex, extra_per_tile, p.cap);
         else
             MS_LAUNCH("k_radix_onesweep", k_radix_onesweep<10>, dim3((unsigned)g), dim3(SORT_BLOCK), 0, st, src, dst, n_dev,
-                               shift, p.hist + q * r, stat, next, p.tile_ctr + q, ex, extra_per_tile);
+                               shift, p.hist + q * r, stat, next, p.tile_ctr + q, ex, extra_per_tile, p.cap);
         MS_HIP(hipGetLastError());
         uint64_t *t = src; src = dst; dst = t;
     }
