@@ -50,8 +50,8 @@ def algorithmic_bytes(kernel: str, st: dict, mesh_sizes) -> float | None:
         "k_radix_onesweep": 16.0 * E,                 # keys read + written
         "k_cells_scan": 8.0 * E + 8.0 * nall,         # keys read, cell bounds written
         "k_cells_keep": 8.0 * nall + 40.0 * nc,       # cell bounds read, cell records + slot offsets written
-        "k_enum": 16.0 * E + 40.0 * nc + 12.0 * C,    # keys and ranges of the entries, cells, candidates
-        "k_narrow": C * (12.0 + 192.0) + 120.0 * H,   # candidates, 6 vertices, hit records
+        # keys of the entries and their cells; the 6 vertices of every candidate; hit records
+        "k_enum": 16.0 * E + 40.0 * nc + 192.0 * C + 120.0 * H,
     }
     return table.get(kernel)
 
@@ -157,10 +157,10 @@ def main():
     if args.kappa > 0:
         kappa, params, sweep = args.kappa, ms.default_params(A, B, args.kappa), {}
     else:
-        kappa, params, sweep = ms.autotune_kappa(A, B)
+        kappa, params, sweep = ms.autotune_kappa(A, B, hits_cap=1 << 10)
         sweep = {k: round(v, 5) for k, v in sweep.items()}
         log(f"autotuned kappa {kappa}: " + ", ".join(f"{k}: {v:.4f} ms" for k, v in sweep.items()))
-    searcher = ms.Searcher(A, B, params, hits_cap=1 << 14, cand_cap=1 << 20)
+    searcher = ms.Searcher(A, B, params, hits_cap=1 << 10, cand_cap=1 << 20)   # run() grows it if needed
     searcher.run()
     ms_step_prof, kern = time_search(ms, A, B, searcher, args.steps, args.warmup, profile=True)
     hits, st, _ = searcher.results()

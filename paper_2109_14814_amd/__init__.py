@@ -297,7 +297,7 @@ def _time_ms(fn, reps: int) -> float:
 
 
 def autotune_kappa(A: Mesh, B: Mesh, kappas=KAPPAS, reps: int = 20, tie: float = 0.10,
-                   hits_cap: int = 1 << 14, cand_cap: int = 1 << 20):
+                   hits_cap: int = 1 << 10, cand_cap: int = 1 << 20):
     """Cell-edge autotuner for one mesh pair.  The grid of Sec. 6.2.1 only
     needs cells larger than the triangles; the edge is kappa x the mean
     triangle diameter, and the result set does not depend on it.  Times the

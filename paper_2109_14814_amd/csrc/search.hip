@@ -4,24 +4,28 @@
 // Every kernel reads its sizes from device memory, so one call queues a fixed
 // sequence of kernels with no host round trip (and can be captured in a HIP
 // graph):
-//   k_prepare     clear counters, occupancy flags and look-back words
+//   k_prepare     clear counters, occupancy tables and look-back words
 //   k_mark        per triangle: its box from the vertices (Sec. 6.2.2), the
 //                 overlapped cells of its pair's grid (Sec. 6.2.1), one
-//                 occupancy flag per (hashed) cell and side, compact range
+//                 occupancy flag per (hashed) cell and side, fine and coarse;
+//                 compact range
+//   k_pack        occupancy bytes -> bit tables
 //   k_keys        per triangle: the cells that the other mesh also touches
 //                 (a box with triangles of one mesh only cannot hold a pair);
-//                 keys [cell | side | triangle] at offsets from a one-pass
-//                 scan; digit histograms for the sort
+//                 keys [cell | side | triangle] at offsets reserved per
+//                 block; digit histograms for the sort
 //   radix sort    onesweep passes, cells grouped (A's entries before B's)
 //   k_cells_scan  cell starts and A counts of the sorted keys (scan)
 //   k_cells_keep  cells holding both meshes: start, nA, nB, pair; slot
 //                 offsets sum(nA * nB) (scan)
 //   k_enum        slot -> (cell, iA, iB); a pair is kept only in its home cell
 //                 (cell of the componentwise max of the boxes' lower corners)
-//                 and only if the closed boxes overlap (Sec. 6.2.2)
-//   k_narrow      Moller quick test (Sec. 6.2.3), 4x4 solve and inclusion
-//                 (Sec. 6.2.4), hit records
-//   sort          hits by (pair, triA, triB)
+//                 and only if the closed boxes overlap (Sec. 6.2.2); then,
+//                 on the chunk's candidates, the Moller quick test
+//                 (Sec. 6.2.3), the 4x4 solve and inclusion (Sec. 6.2.4),
+//                 hit records
+//   hit sort      by (pair, triA, triB): one block for a small capacity,
+//                 else chunk sort, merge rank and placement
 // A batch keys its cells by a per-pair cell offset, so entries of different
 // pairs never share a cell.
 #include <math.h>
@@ -83,6 +87,7 @@ struct BatchView {
     int64_t n_tri;
     int32_t n_pairs;
     int32_t bm_log2;             // occupancy flags per side: 2^bm_log2 bytes, then as many bits
+    int32_t bc_log2;             // the same for the coarse cells (2x the edge): 2^bc_log2 per side
     int32_t packable;            // every grid has <= 4096 cells per axis
     int32_t pb, tbA, tbB;        // bits of the pair, A- and B-triangle fields of hit keys
     KeyLayout kl;
@@ -150,6 +155,19 @@ MS_D int64_t range_count(const CellRange &r)
     return (r.hi[0] - r.lo[0] + 1) * (r.hi[1] - r.lo[1] + 1) * (r.hi[2] - r.lo[2] + 1) * (r.hi[3] - r.lo[3] + 1);
 }
 
+// The cells of a grid with twice the edge (cell index / 2 per axis), used to
+// skip at once the triangles whose neighbourhood holds no cell of the other
+// mesh.
+MS_D void coarse_of(const CellRange &r, const int64_t n[4], CellRange &rc, int64_t nc[4])
+{
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        rc.lo[d] = r.lo[d] >> 1;
+        rc.hi[d] = r.hi[d] >> 1;
+        nc[d] = (n[d] + 1) >> 1;
+    }
+}
+
 // Visit every cell of a range in lexicographic order (linear cell ids).
 template <typename F>
 MS_D void for_cells(const CellRange &r, const int64_t n[4], F &&f)
@@ -167,10 +185,10 @@ MS_D uint32_t occ_bit(const uint32_t *bits, uint32_t h) { return (bits[h >> 5] >
 
 // Occupancy bits of the cells of a range held by the other mesh (its bit
 // table `other`), as a mask in lexicographic order of the cells.  Ranges of
-// up to 8 cells compute the j-th cell from the mixed-radix digits of j, so
+// up to 16 cells compute the j-th cell from the mixed-radix digits of j, so
 // that all their loads are in flight together; *big is set for larger
 // ranges, which the caller walks with for_cells.
-constexpr int MLP_CELLS = 8;
+constexpr int MLP_CELLS = 16;
 
 MS_D uint32_t flag_mask(const CellRange &r, const int64_t n[4], uint64_t cb, const uint32_t *other, int log2,
                         bool *big)
@@ -178,37 +196,31 @@ MS_D uint32_t flag_mask(const CellRange &r, const int64_t n[4], uint64_t cb, con
     const int64_t cnt = range_count(r);
     *big = cnt > MLP_CELLS;
     if (*big) return 0;
-    const uint32_t e1 = (uint32_t)(r.hi[1] - r.lo[1] + 1), e2 = (uint32_t)(r.hi[2] - r.lo[2] + 1),
-                   e3 = (uint32_t)(r.hi[3] - r.lo[3] + 1);
+    // odometer over the range's cells in lexicographic order (no divisions)
+    int64_t c0 = r.lo[0], c1 = r.lo[1], c2 = r.lo[2], c3 = r.lo[3];
     uint32_t v[MLP_CELLS];
 #pragma unroll
     for (int j = 0; j < MLP_CELLS; ++j) {
         v[j] = 0;
         if (j < cnt) {
-            uint32_t q = (uint32_t)j;
-            const uint32_t d3 = q % e3; q /= e3;
-            const uint32_t d2 = q % e2; q /= e2;
-            const uint32_t d1 = q % e1; q /= e1;
-            const int64_t cell = (((r.lo[0] + q) * n[1] + r.lo[1] + d1) * n[2] + r.lo[2] + d2) * n[3] + r.lo[3] + d3;
+            const int64_t cell = ((c0 * n[1] + c1) * n[2] + c2) * n[3] + c3;
             v[j] = occ_bit(other, bm_hash(cb + (uint64_t)cell, log2));
+            if (++c3 > r.hi[3]) {
+                c3 = r.lo[3];
+                if (++c2 > r.hi[2]) {
+                    c2 = r.lo[2];
+                    if (++c1 > r.hi[1]) {
+                        c1 = r.lo[1];
+                        ++c0;
+                    }
+                }
+            }
         }
     }
     uint32_t m = 0;
 #pragma unroll
     for (int j = 0; j < MLP_CELLS; ++j) m |= v[j] << j;
     return m;
-}
-
-// The j-th cell of a range (lexicographic order).
-MS_D uint64_t range_cell(const CellRange &r, const int64_t n[4], int j)
-{
-    const uint32_t e1 = (uint32_t)(r.hi[1] - r.lo[1] + 1), e2 = (uint32_t)(r.hi[2] - r.lo[2] + 1),
-                   e3 = (uint32_t)(r.hi[3] - r.lo[3] + 1);
-    uint32_t q = (uint32_t)j;
-    const uint32_t d3 = q % e3; q /= e3;
-    const uint32_t d2 = q % e2; q /= e2;
-    const uint32_t d1 = q % e1; q /= e1;
-    return (uint64_t)((((r.lo[0] + q) * n[1] + r.lo[1] + d1) * n[2] + r.lo[2] + d2) * n[3] + r.lo[3] + d3);
 }
 
 // Compact cell range: lo cell per axis in 12 bits (bits 0..47), extent per
@@ -387,6 +399,7 @@ struct ClearSpec {
     uint64_t *kstat;   int64_t kstat_words;      // look-back words
     uint32_t *hist;    int64_t hist_words;       // sort histograms
     uint32_t *ctrs;    int64_t ctr_words;        // tile counters
+    uint32_t *ctrs2;   int64_t ctr2_words;       // more counters
 };
 
 __global__ void __launch_bounds__(BLOCK) k_prepare(ClearSpec c)
@@ -398,6 +411,7 @@ __global__ void __launch_bounds__(BLOCK) k_prepare(ClearSpec c)
     for (int64_t i = g0; i < c.kstat_words; i += stride) c.kstat[i] = 0;
     for (int64_t i = g0; i < c.hist_words; i += stride) c.hist[i] = 0;
     for (int64_t i = g0; i < c.ctr_words; i += stride) c.ctrs[i] = 0;
+    for (int64_t i = g0; i < c.ctr2_words; i += stride) c.ctrs2[i] = 0;
 }
 
 // Occupancy: one byte per hashed global cell and side, set with plain stores
@@ -425,6 +439,11 @@ __global__ void __launch_bounds__(BLOCK) k_mark(BatchView bv, uint8_t *flags, ui
         uint8_t *mine = flags + (size_t)L.side * side_bytes;
         const uint64_t cb = P.cell_base;
         for_cells(r, P.g.n, [&](uint64_t c) { mine[bm_hash(cb + c, bv.bm_log2)] = 1; });
+        CellRange rc;
+        int64_t nc[4];
+        coarse_of(r, P.g.n, rc, nc);
+        uint8_t *cmine = flags + 2 * side_bytes + ((size_t)L.side << bv.bc_log2);
+        for_cells(rc, nc, [&](uint64_t c) { cmine[bm_hash(cb + c, bv.bc_log2)] = 1; });
     }
     all = block_sum(all, s_tmp);
     bad = block_sum(bad, s_tmp);
@@ -479,25 +498,40 @@ __global__ void __launch_bounds__(BLOCK) k_keys(BatchView bv, const uint32_t *bi
     const size_t side_words = ((size_t)1 << bv.bm_log2) / 32;
     const int R = 1 << o.rb;
     const int64_t base = (int64_t)blockIdx.x * KEYS_TILE;
-    uint32_t cnt[KEYS_ITEMS];
+    uint32_t cnt[KEYS_ITEMS], msk[KEYS_ITEMS];
+    uint32_t bigm = 0;
     uint64_t mine = 0;
 #pragma unroll
     for (int i = 0; i < KEYS_ITEMS; ++i) {
         const int64_t gt = base + i * BLOCK + threadIdx.x;
-        uint32_t c = 0;
+        uint32_t c = 0, m = 0;
         if (gt < bv.n_tri) {
             TriLoc L = locate<ONE>(bv, gt);
             CellRange r;
             if (range_of<ONE>(bv, rng, gt, L, r)) {
                 const uint32_t *other = bits + (size_t)(1 - L.side) * side_words;
                 const PairDesc &P = pair_desc<ONE>(bv, L.p);
-                bool big;
-                const uint32_t m = flag_mask(r, P.g.n, P.cell_base, other, bv.bm_log2, &big);
+                CellRange rc;
+                int64_t nc[4];
+                coarse_of(r, P.g.n, rc, nc);
+                const uint32_t *cother = bits + 2 * side_words + ((size_t)(1 - L.side) << bv.bc_log2) / 32;
+                bool bigc;
+                const uint32_t mc = flag_mask(rc, nc, P.cell_base, cother, bv.bc_log2, &bigc);
+                bool big = false;
+                if (!bigc && mc == 0) {
+                    // no coarse cell of the range holds the other mesh: no entry
+                } else {
+                m = flag_mask(r, P.g.n, P.cell_base, other, bv.bm_log2, &big);
                 if (!big) c = (uint32_t)__builtin_popcount(m);
-                else for_cells(r, P.g.n, [&](uint64_t cell) { c += occ_bit(other, bm_hash(P.cell_base + cell, bv.bm_log2)); });
+                else {
+                    bigm |= 1u << i;
+                    for_cells(r, P.g.n, [&](uint64_t cell) { c += occ_bit(other, bm_hash(P.cell_base + cell, bv.bm_log2)); });
+                }
+                }
             }
         }
         cnt[i] = c;
+        msk[i] = m;
         mine += c;
     }
     uint64_t btotal;
@@ -536,14 +570,13 @@ __global__ void __launch_bounds__(BLOCK) k_keys(BatchView bv, const uint32_t *bi
             }
             ++pos;
         };
-        bool big;
-        uint32_t m = flag_mask(r, P.g.n, cb, other, bv.bm_log2, &big);
-        if (!big) {
-            while (m) {
-                const int j = __builtin_ctz(m);
-                m &= m - 1;
-                put(cb + range_cell(r, P.g.n, j));
-            }
+        if (!(bigm >> i & 1)) {
+            const uint32_t m = msk[i];
+            int j = 0;
+            for_cells(r, P.g.n, [&](uint64_t cell) {
+                if (m >> j & 1) put(cb + cell);
+                ++j;
+            });
         } else {
             for_cells(r, P.g.n, [&](uint64_t cell) {
                 if (occ_bit(other, bm_hash(cb + cell, bv.bm_log2))) put(cb + cell);
@@ -820,21 +853,43 @@ MS_D int64_t uniform_i64(int64_t v)
 }
 
 
+MS_D void wave_count(bool p, int64_t *ctr)
+{
+    uint64_t m = ballot(p);
+    if (m && lane_id() == __builtin_ctzll(m)) atomicAdd((unsigned long long *)ctr, (unsigned long long)__builtin_popcountll(m));
+}
+
+MS_D void emit_hit(bool hit, const hit_t &h, uint64_t key, hit_t *hits, uint64_t *hkeys, int64_t cap,
+                   search_stats_t *stats)
+{
+    int64_t idx = wave_reserve(hit, (unsigned long long *)&stats->n_hits);
+    if (hit) {
+        if (idx < cap) {
+            hits[idx] = h;
+            if (hkeys) hkeys[idx] = key;
+        } else {
+            atomicOr((unsigned long long *)&stats->overflow, 4ull);
+        }
+    }
+}
+
 // Slot -> (cell, iA, iB), iA = slot mod nA, iB = slot / nA (Alg. 1).  A pair
 // is kept only in its home cell, the cell of the componentwise max of the two
 // boxes' lower corners (the one cell of both ranges that every overlapping
 // pair has, by monotonicity of the cell map), and only if the closed boxes
 // overlap (Sec. 6.2.2).
 //
-// Each block takes ENUM_SLOTS consecutive slots.  When the cells they fall in
-// have at most ENUM_STAGE entries in all, the block first stages those
-// entries (triangle index and box, computed once from the vertices) and the
-// cell records in LDS, so that every slot reads LDS only; otherwise (very
-// full cells) each slot gathers its two triangles from global memory.
+// Each block takes ENUM_SLOTS consecutive slots.  Of every cell the chunk
+// touches it needs only the A entries of the rows it covers (all of them once
+// it spans more than one row) and the B entries of those rows; when these are
+// at most ENUM_STAGE in all, the block stages their triangle indices and
+// boxes (computed once from the vertices) in LDS, so that every slot reads
+// LDS only.  Otherwise each slot gathers its two triangles from global
+// memory.  One atomic reservation per chunk for the candidates.
 constexpr int ENUM_ITEMS = 16;
 constexpr int ENUM_SLOTS = BLOCK * ENUM_ITEMS;
-constexpr int ENUM_STAGE = 512;
-constexpr int ENUM_CELLS = 256;
+constexpr int ENUM_STAGE = 768;
+constexpr int ENUM_CELLS = BLOCK;
 
 template <bool ONE>
 MS_D bool enum_pair(const PairDesc &Pd, uint64_t cell, const double alo[4], const double ahi[4], const double blo[4],
@@ -856,16 +911,27 @@ constexpr int ENUM_PSTART = 4096;   // slot offsets kept in LDS when the cells a
 template <bool ONE>
 __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *keys, const CellRec *cells,
                                                 const int64_t *pstart_g, search_stats_t *stats, uint64_t *cand,
-                                                int32_t *cand_pair, int64_t cand_cap)
+                                                int32_t *cand_pair, int64_t cand_cap, hit_t *hits, uint64_t *hkeys,
+                                                int64_t hits_cap)
 {
     __shared__ int64_t s_pstart[ENUM_PSTART + 1];
-    __shared__ double s_box[ENUM_STAGE][8];
+    // the staged boxes during enumeration, then the chunk's compacted candidates
+    __shared__ union {
+        double box[ENUM_STAGE][8];
+        struct {
+            uint64_t tt[ENUM_SLOTS];
+            int32_t pair[ENUM_SLOTS];
+        } c;
+    } s_u;
+    static_assert(sizeof(double) * ENUM_STAGE * 8 >= 12 * ENUM_SLOTS, "candidate list overlays the staged boxes");
+    double (*s_box)[8] = s_u.box;
     __shared__ int32_t s_t[ENUM_STAGE];
     __shared__ int64_t s_pre[ENUM_CELLS + 1];
-    __shared__ int32_t s_first[ENUM_CELLS + 1], s_end[ENUM_CELLS], s_nA[ENUM_CELLS], s_pair[ENUM_CELLS];
+    __shared__ int64_t s_start[ENUM_CELLS];
+    __shared__ int32_t s_aoff[ENUM_CELLS + 1], s_boff[ENUM_CELLS], s_ia0[ENUM_CELLS], s_ib0[ENUM_CELLS];
+    __shared__ int32_t s_nA[ENUM_CELLS], s_pair[ENUM_CELLS];
     __shared__ uint64_t s_cell[ENUM_CELLS];
-    __shared__ int64_t s_c0, s_c1, s_e0;
-    __shared__ int s_staged;
+    __shared__ int64_t s_c0, s_c1;
     __shared__ uint32_t s_kscan[BLOCK / WAVE];
     __shared__ unsigned long long s_kbase;
     const int64_t ncells = stats->n_cells;
@@ -882,58 +948,66 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
         const int64_t S0 = chunk * ENUM_SLOTS;
         const int64_t S1 = S0 + ENUM_SLOTS < P ? S0 + ENUM_SLOTS : P;
         if (threadIdx.x == 0) {
-            const int64_t c0 = last_le<int64_t>(pstart, ncells, S0);
-            const int64_t c1 = last_le<int64_t>(pstart, ncells, S1 - 1);
-            const CellRec a = cells[c0], b = cells[c1];
-            const int64_t e0 = a.start, e1 = b.start + b.nA + b.nB;
-            s_c0 = c0;
-            s_c1 = c1;
-            s_e0 = e0;
-            s_staged = (c1 - c0 + 1) <= ENUM_CELLS && (e1 - e0) <= ENUM_STAGE;
+            s_c0 = last_le<int64_t>(pstart, ncells, S0);
+            s_c1 = last_le<int64_t>(pstart, ncells, S1 - 1);
         }
         __syncthreads();
-        const int64_t c0 = s_c0, nc = s_c1 - s_c0 + 1, e0 = s_e0;
-        const bool staged = s_staged != 0;
-        if (staged) {
-            for (int64_t i = threadIdx.x; i < nc; i += BLOCK) {
-                const CellRec cr = cells[c0 + i];
-                const PairDesc &Pd = pair_desc<ONE>(bv, cr.pair);
-                s_pre[i] = pstart[c0 + i];
-                s_first[i] = (int32_t)(cr.start - e0);
-                s_end[i] = (int32_t)(cr.start + cr.nA + cr.nB - e0);
-                s_nA[i] = cr.nA;
-                s_pair[i] = cr.pair;
-                s_cell[i] = (keys[cr.start] >> bv.kl.cell_shift) - Pd.cell_base;
-                if (i == nc - 1) {
-                    s_pre[nc] = pstart[c0 + nc];
-                    s_first[nc] = (int32_t)(cr.start + cr.nA + cr.nB - e0);
-                }
+        const int64_t c0 = s_c0, nc = s_c1 - s_c0 + 1;
+        // the rows of every touched cell that the chunk covers, and the entries they need
+        uint32_t need = 0;
+        if (nc <= ENUM_CELLS && threadIdx.x < nc) {
+            const int64_t c = c0 + threadIdx.x;
+            const CellRec cr = cells[c];
+            const int64_t p0 = pstart[c], p1 = pstart[c + 1];
+            const int64_t l0 = (S0 > p0 ? S0 : p0) - p0, l1 = (S1 < p1 ? S1 : p1) - p0;
+            const int64_t ib0 = l0 / cr.nA, ib1 = (l1 - 1) / cr.nA;
+            int64_t ia0 = 0, ia1 = cr.nA;
+            if (ib0 == ib1) {
+                ia0 = l0 - ib0 * cr.nA;
+                ia1 = (l1 - 1) - ib1 * cr.nA + 1;
             }
+            need = (uint32_t)((ia1 - ia0) + (ib1 - ib0 + 1));
+            const PairDesc &Pd = pair_desc<ONE>(bv, cr.pair);
+            s_pre[threadIdx.x] = p0;
+            s_start[threadIdx.x] = cr.start;
+            s_ia0[threadIdx.x] = (int32_t)ia0;
+            s_ib0[threadIdx.x] = (int32_t)ib0;
+            s_nA[threadIdx.x] = cr.nA;
+            s_pair[threadIdx.x] = cr.pair;
+            s_cell[threadIdx.x] = (keys[cr.start] >> bv.kl.cell_shift) - Pd.cell_base;
+            s_boff[threadIdx.x] = (int32_t)(ia1 - ia0);     // made absolute below
+            if (threadIdx.x == nc - 1) s_pre[nc] = p1;
+        }
+        uint32_t tot;
+        const uint32_t off = block_excl(need, s_kscan, &tot);
+        const bool staged = nc <= ENUM_CELLS && tot <= ENUM_STAGE;
+        if (staged) {
+            if (threadIdx.x < nc) {
+                s_aoff[threadIdx.x] = (int32_t)off;
+                s_boff[threadIdx.x] += (int32_t)off;
+            }
+            if (threadIdx.x == 0) s_aoff[nc] = (int32_t)tot;
             __syncthreads();
-            const int ne = s_first[nc];
-            for (int i = threadIdx.x; i < ne; i += BLOCK) {
-                int lo = 0, hi = (int)nc;             // the last kept cell starting at or before entry i
+            for (int i = threadIdx.x; i < (int)tot; i += BLOCK) {
+                int lo = 0, hi = (int)nc;             // the cell whose staged range holds i
                 while (hi - lo > 1) {
                     const int mid = (lo + hi) >> 1;
-                    if (s_first[mid] <= i) lo = mid;
+                    if (s_aoff[mid] <= i) lo = mid;
                     else hi = mid;
                 }
-                // entries between kept cells belong to one-mesh cells, possibly
-                // of another mesh pair; no slot refers to them
-                if (i >= s_end[lo]) continue;
-                const uint64_t k = keys[e0 + i];
-                const int side = (int)((k >> bv.kl.tb) & 1);
-                const int32_t t = (int32_t)(k & bv.kl.tmask);
+                const bool isB = i >= s_boff[lo];
+                const int64_t e = isB ? s_start[lo] + s_nA[lo] + s_ib0[lo] + (i - s_boff[lo])
+                                      : s_start[lo] + s_ia0[lo] + (i - s_aoff[lo]);
+                const int32_t t = (int32_t)(keys[e] & bv.kl.tmask);
                 const PairDesc &Pd = pair_desc<ONE>(bv, s_pair[lo]);
                 double blo[4], bhi[4];
-                tri_box(side_mesh(Pd, side), t, blo, bhi);
+                tri_box(isB ? Pd.B : Pd.A, t, blo, bhi);
 #pragma unroll
                 for (int d = 0; d < 4; ++d) { s_box[i][d] = blo[d]; s_box[i][4 + d] = bhi[d]; }
                 s_t[i] = t;
             }
             __syncthreads();
         }
-        int64_t cg = c0;   // cell of this thread's last slot (unstaged path)
         uint64_t packed[ENUM_ITEMS];
         int32_t prs[ENUM_ITEMS];
         uint32_t keepm = 0;
@@ -953,9 +1027,10 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
                     }
                     const int c = lo;
                     const int32_t nA = s_nA[c];
-                    const uint32_t local = (uint32_t)(slot - s_pre[c]);
-                    const uint32_t iB = local / (uint32_t)nA, iA = local - iB * (uint32_t)nA;
-                    const int ia = s_first[c] + (int)iA, ib = s_first[c] + nA + (int)iB;
+                    const uint64_t local = (uint64_t)(slot - s_pre[c]);
+                    const uint64_t iB = local / (uint64_t)nA, iA = local - iB * (uint64_t)nA;
+                    const int ia = s_aoff[c] + (int)((int64_t)iA - s_ia0[c]);
+                    const int ib = s_boff[c] + (int)((int64_t)iB - s_ib0[c]);
                     prs[j] = s_pair[c];
                     const PairDesc &Pd = pair_desc<ONE>(bv, prs[j]);
                     double alo[4], ahi[4], blo[4], bhi[4];
@@ -967,9 +1042,9 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
                     keep = enum_pair<ONE>(Pd, s_cell[c], alo, ahi, blo, bhi);
                     packed[j] = ((uint64_t)(uint32_t)s_t[ia] << 32) | (uint32_t)s_t[ib];
                 } else {
-                    while (pstart[cg + 1] <= slot) ++cg;
-                    const CellRec cr = cells[cg];
-                    const uint64_t local = (uint64_t)(slot - pstart[cg]);
+                    const int64_t c = last_le<int64_t>(pstart, ncells, slot);
+                    const CellRec cr = cells[c];
+                    const uint64_t local = (uint64_t)(slot - pstart[c]);
                     const uint64_t iB = local / (uint64_t)cr.nA;
                     const uint64_t iA = local - iB * (uint64_t)cr.nA;
                     const uint64_t kA = keys[cr.start + (int64_t)iA];
@@ -986,88 +1061,78 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
             }
             keepm |= (uint32_t)keep << j;
         }
-        // one reservation per chunk: a block scan of the kept counts, one atomic add
+        // the candidates: counted with one atomic per chunk, stored when asked
+        // for, and compacted into LDS for the narrow phase
         uint32_t ktot;
         const uint32_t kex = block_excl((uint32_t)__builtin_popcount(keepm), s_kscan, &ktot);
         if (threadIdx.x == 0) s_kbase = ktot ? atomicAdd((unsigned long long *)&stats->n_cand, (unsigned long long)ktot) : 0ull;
-        __syncthreads();
-        int64_t idx = (int64_t)s_kbase + kex;
+        __syncthreads();        // (also: every slot is done reading the staged boxes)
+        {
+            uint32_t li = kex;
+            int64_t idx = (int64_t)s_kbase + kex;
 #pragma unroll
-        for (int j = 0; j < ENUM_ITEMS; ++j) {
-            if (!(keepm >> j & 1)) continue;
-            if (idx < cand_cap) {
-                cand[idx] = packed[j];
-                cand_pair[idx] = prs[j];
-            } else {
-                atomicOr((unsigned long long *)&stats->overflow, 2ull);
+            for (int j = 0; j < ENUM_ITEMS; ++j) {
+                if (!(keepm >> j & 1)) continue;
+                s_u.c.tt[li] = packed[j];
+                s_u.c.pair[li] = prs[j];
+                if (cand) {
+                    if (idx < cand_cap) {
+                        cand[idx] = packed[j];
+                        if (cand_pair) cand_pair[idx] = prs[j];
+                    } else {
+                        atomicOr((unsigned long long *)&stats->overflow, 2ull);
+                    }
+                }
+                ++li;
+                ++idx;
             }
-            ++idx;
         }
         __syncthreads();
-    }
-}
-
-MS_D void wave_count(bool p, int64_t *ctr)
-{
-    uint64_t m = ballot(p);
-    if (m && lane_id() == __builtin_ctzll(m)) atomicAdd((unsigned long long *)ctr, (unsigned long long)__builtin_popcountll(m));
-}
-
-MS_D void emit_hit(bool hit, const hit_t &h, uint64_t key, hit_t *hits, uint64_t *hkeys, int64_t cap,
-                   search_stats_t *stats)
-{
-    int64_t idx = wave_reserve(hit, (unsigned long long *)&stats->n_hits);
-    if (hit) {
-        if (idx < cap) {
-            hits[idx] = h;
-            if (hkeys) hkeys[idx] = key;
-        } else {
-            atomicOr((unsigned long long *)&stats->overflow, 4ull);
-        }
-    }
-}
-
-template <bool ONE>
-__global__ void __launch_bounds__(BLOCK) k_narrow(BatchView bv, const uint64_t *cand, const int32_t *cand_pair,
-                                                  int64_t cand_cap, hit_t *hits, uint64_t *hkeys, int64_t hits_cap,
-                                                  search_stats_t *stats)
-{
-    int64_t n = stats->n_cand;
-    if (n > cand_cap) n = cand_cap;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t iters = ceil_div(n, stride);
-    for (int64_t it = 0; it < iters; ++it) {
-        const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + it * stride;
-        int st = PS_AABB;
-        int32_t ta = 0, tb = 0, p = 0;
-        double z[4] = {0, 0, 0, 0};
-        Tri Pt;
-        if (c < n) {
-            const uint64_t pk = cand[c];
-            ta = (int32_t)(pk >> 32);
-            tb = (int32_t)(pk & 0xffffffffu);
-            p = ONE ? 0 : cand_pair[c];
-            const PairDesc &Pd = pair_desc<ONE>(bv, p);
-            Pt = load_tri(Pd.A, ta);
-            const Tri Q = load_tri(Pd.B, tb);
-            if (same_side(Pt, Q) || same_side(Q, Pt)) {
-                st = PS_MOLLER;
-            } else {
-                bool ok = solve_pair(Pt, Q, z);
-                st = !ok ? PS_DEGEN : !inside(z) ? PS_OUTSIDE : PS_HIT;
+        // the narrow phase on the chunk's candidates: Moller quick test
+        // (Sec. 6.2.3), 4x4 solve and inclusion (Sec. 6.2.4), hit records
+        if (ktot) {
+            uint32_t nm = 0, nd = 0, no = 0;
+            for (uint32_t base = 0; base < ktot; base += BLOCK) {
+                const uint32_t i = base + threadIdx.x;
+                int stt = PS_AABB;
+                int32_t ta = 0, tb = 0, p = 0;
+                double z[4] = {0, 0, 0, 0};
+                Tri Pt;
+                if (i < ktot) {
+                    const uint64_t tt = s_u.c.tt[i];
+                    ta = (int32_t)(tt >> 32);
+                    tb = (int32_t)(tt & 0xffffffffu);
+                    p = s_u.c.pair[i];
+                    const PairDesc &Pd = pair_desc<ONE>(bv, p);
+                    Pt = load_tri(Pd.A, ta);
+                    const Tri Q = load_tri(Pd.B, tb);
+                    if (same_side(Pt, Q) || same_side(Q, Pt)) {
+                        stt = PS_MOLLER;
+                    } else {
+                        const bool ok = solve_pair(Pt, Q, z);
+                        stt = !ok ? PS_DEGEN : !inside(z) ? PS_OUTSIDE : PS_HIT;
+                    }
+                }
+                nm += stt == PS_MOLLER;
+                nd += stt == PS_DEGEN;
+                no += stt == PS_OUTSIDE;
+                hit_t h;
+                uint64_t key = 0;
+                if (stt == PS_HIT) {
+                    const PairDesc &Pd = pair_desc<ONE>(bv, p);
+                    make_hit(Pd.A, Pd.B, ta, tb, (uint32_t)p, Pt, z, h);
+                    key = ((uint64_t)p << (bv.tbA + bv.tbB)) | ((uint64_t)(uint32_t)ta << bv.tbB) | (uint32_t)tb;
+                }
+                emit_hit(stt == PS_HIT, h, key, hits, hkeys, hits_cap, stats);
+            }
+            const uint32_t sm = block_sum(nm, s_kscan), sd = block_sum(nd, s_kscan), so = block_sum(no, s_kscan);
+            if (threadIdx.x == 0) {
+                if (sm) atomicAdd((unsigned long long *)&stats->n_moller, (unsigned long long)sm);
+                if (sd) atomicAdd((unsigned long long *)&stats->n_degenerate, (unsigned long long)sd);
+                if (so) atomicAdd((unsigned long long *)&stats->n_outside, (unsigned long long)so);
             }
         }
-        wave_count(st == PS_MOLLER, &stats->n_moller);
-        wave_count(st == PS_DEGEN, &stats->n_degenerate);
-        wave_count(st == PS_OUTSIDE, &stats->n_outside);
-        hit_t h;
-        uint64_t key = 0;
-        if (st == PS_HIT) {
-            const PairDesc &Pd = pair_desc<ONE>(bv, p);
-            make_hit(Pd.A, Pd.B, ta, tb, (uint32_t)p, Pt, z, h);
-            key = ((uint64_t)p << (bv.tbA + bv.tbB)) | ((uint64_t)(uint32_t)ta << bv.tbB) | (uint32_t)tb;
-        }
-        emit_hit(st == PS_HIT, h, key, hits, hkeys, hits_cap, stats);
+        __syncthreads();
     }
 }
 
@@ -1080,6 +1145,26 @@ __global__ void __launch_bounds__(BLOCK) k_hits_place(const hit_t *tmp, const ui
         const hit_t &h = tmp[i];
         const uint64_t key = ((uint64_t)h.flags << (tbA + tbB)) | ((uint64_t)(uint32_t)h.triA << tbB) | (uint32_t)h.triB;
         out[lower_bound_u64(sorted, 0, n, key)] = h;
+    }
+}
+
+// At most HITS_TINY hits: one block ranks every key by counting the smaller
+// ones (the keys are distinct) and places key and record together.
+constexpr int HITS_TINY = 1024;
+
+__global__ void __launch_bounds__(BLOCK) k_hits_tiny(const hit_t *tmp, uint64_t *keys, const int64_t *n_dev,
+                                                     int64_t cap, hit_t *out)
+{
+    __shared__ uint64_t s_k[HITS_TINY];
+    const int n = (int)(*n_dev < cap ? *n_dev : cap);
+    for (int i = threadIdx.x; i < n; i += BLOCK) s_k[i] = keys[i];
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += BLOCK) {
+        const uint64_t k = s_k[i];
+        int r = 0;
+        for (int j = 0; j < n; ++j) r += s_k[j] < k;
+        keys[r] = k;
+        out[r] = tmp[i];
     }
 }
 
@@ -1176,7 +1261,7 @@ struct Geometry {
     int64_t n_pairs, n_tri, max_nA, max_nB;
     int tb, tbA, tbB, pb;
     int cell_bits;
-    int bm_log2;
+    int bm_log2, bc_log2;
     int packable;
     uint64_t total_cells;
 };
@@ -1240,8 +1325,12 @@ int geometry(int64_t n_pairs, const ms_mesh *const *A, const ms_mesh *const *B, 
     if (G.pb + G.tbA + G.tbB > 64) return fail(MS_E_KEYBITS, "search: pair + triangle indices exceed 64 bits");
     int lg = bits_for((uint64_t)(G.n_tri > 0 ? G.n_tri : 1)) + 2;
     G.bm_log2 = lg < 12 ? 12 : (lg > 25 ? 25 : lg);
+    G.bc_log2 = G.bm_log2 - 3;
     return MS_OK;
 }
+
+// Occupancy bytes: fine table (2 sides x 2^bm_log2), then coarse (2 x 2^bc_log2).
+inline size_t flag_bytes(const Geometry &G) { return ((size_t)2 << G.bm_log2) + ((size_t)2 << G.bc_log2); }
 
 void layout(const Geometry &G, Layout &L)
 {
@@ -1251,8 +1340,8 @@ void layout(const Geometry &G, Layout &L)
     L.n_kblocks = ceil_div(G.n_tri > 0 ? G.n_tri : 1, KEYS_TILE);
     L.cell_cap = L.ent_cap / 2 + 1;
     const int64_t tiles = L.rp.tiles_cap;
-    L.o_flags = take((size_t)2 << G.bm_log2);
-    L.o_bits = take(((size_t)2 << G.bm_log2) / 8);
+    L.o_flags = take(flag_bytes(G));
+    L.o_bits = take(flag_bytes(G) / 8);
     L.o_part = take((size_t)MAX_GRID * 16);
     L.o_rng = take((size_t)(G.n_tri + 1) * 8);
     L.o_keys = take((size_t)(L.ent_cap + 1) * 8);
@@ -1263,8 +1352,8 @@ void layout(const Geometry &G, Layout &L)
     L.o_bounds = take((size_t)(L.ent_cap + 2) * 8);
     L.o_cells = take((size_t)L.cell_cap * sizeof(CellRec));
     L.o_pstart = take((size_t)(L.cell_cap + 1) * 8);
-    L.o_cand = take((size_t)(L.cand_cap > 0 ? L.cand_cap : 1) * 8);
-    L.o_cpair = take((size_t)(L.cand_cap > 0 ? L.cand_cap : 1) * 4);
+    L.o_cand = take(8);      // (candidates are stored only into the caller's buffer)
+    L.o_cpair = take(4);
     L.o_htmp = take((size_t)(L.hits_cap > 0 ? L.hits_cap : 1) * sizeof(hit_t));
     L.o_hkeys = take((size_t)(L.hits_cap + 1) * 8);
     L.o_halt = take((size_t)(L.hits_cap + 1) * 8);
@@ -1320,6 +1409,7 @@ BatchView make_view(const Geometry &G, const PairDesc &p0, char *ws, const Layou
     bv.n_tri = G.n_tri;
     bv.n_pairs = (int32_t)G.n_pairs;
     bv.bm_log2 = G.bm_log2;
+    bv.bc_log2 = G.bc_log2;
     bv.packable = G.packable;
     bv.pb = G.pb;
     bv.tbA = G.tbA;
@@ -1348,8 +1438,6 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
     uint64_t *bounds = (uint64_t *)(ws + L.o_bounds);
     CellRec *cells = (CellRec *)(ws + L.o_cells);
     int64_t *pstart = (int64_t *)(ws + L.o_pstart);
-    uint64_t *cand = cand_user ? cand_user : (uint64_t *)(ws + L.o_cand);
-    int32_t *cpair = (int32_t *)(ws + L.o_cpair);
     hit_t *htmp = (hit_t *)(ws + L.o_htmp);
     uint64_t *hkeys = (uint64_t *)(ws + L.o_hkeys);
     uint64_t *halt = (uint64_t *)(ws + L.o_halt);
@@ -1364,26 +1452,19 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
     ClearSpec cs;
     cs.stats = stats;
     cs.flags = (uint64_t *)flags;
-    cs.flag_words = (int64_t)(((size_t)2 << G.bm_log2) / 8);
-    cs.kstat = nullptr;
-    cs.kstat_words = 0;
+    cs.flag_words = (int64_t)(flag_bytes(G) / 8);
+    cs.kstat = rp.passes == 0 ? cstat : nullptr;
+    cs.kstat_words = rp.passes == 0 ? 3 * rp.tiles_cap : 0;
     cs.hist = rp.hist;
     cs.hist_words = (int64_t)rp.passes * R;
     cs.ctrs = rp.tile_ctr;
     cs.ctr_words = rp.passes;
+    cs.ctrs2 = ctrs;
+    cs.ctr2_words = 16;
     MS_LAUNCH("k_prepare", k_prepare, dim3(grid_for(cs.flag_words, 1024)), dim3(BLOCK), 0, st, cs);
-    ClearSpec cs2;
-    memset(&cs2, 0, sizeof cs2);
-    cs2.ctrs = ctrs;
-    cs2.ctr_words = 16;
-    if (rp.passes == 0) {
-        cs2.kstat = cstat;
-        cs2.kstat_words = 3 * rp.tiles_cap;
-    }
-    MS_LAUNCH("k_prepare", k_prepare, dim3(grid_for(cs2.kstat_words + 16, 256)), dim3(BLOCK), 0, st, cs2);
     const unsigned g_tri = grid_for(G.n_tri);
     MS_LAUNCH("k_mark", k_mark<ONE>, dim3(g_tri), dim3(BLOCK), 0, st, bv, flags, rng, mpart);
-    const int64_t n_words = ((int64_t)2 << G.bm_log2) / 32;
+    const int64_t n_words = (int64_t)(flag_bytes(G) / 32);
     MS_LAUNCH("k_pack", k_pack, dim3(grid_for(n_words, 4096)), dim3(BLOCK), 0, st, flags, bits, n_words);
     KeysOut ko;
     ko.keys = keys;
@@ -1421,15 +1502,19 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
         MS_LAUNCH("k_cells_keep", k_cells_keep<ONE>, dim3((unsigned)g), dim3(BLOCK), 0, st, bv, sorted, bounds,
                   misc + 1, co);
     }
-    MS_LAUNCH("k_enum", k_enum<ONE>, dim3(MAX_GRID), dim3(BLOCK), 0, st, bv, sorted, cells, pstart, stats, cand, cpair,
-              cand_cap);
-    MS_LAUNCH("k_narrow", k_narrow<ONE>, dim3(MAX_GRID), dim3(BLOCK), 0, st, bv, cand, cpair, cand_cap, htmp, hkeys,
-                       hits_cap, stats);
+    MS_LAUNCH("k_enum", k_enum<ONE>, dim3(MAX_GRID), dim3(BLOCK), 0, st, bv, sorted, cells, pstart, stats, cand_user,
+              (int32_t *)nullptr, cand_user ? cand_cap : (int64_t)0, htmp, hkeys, hits_cap);
     MS_HIP(hipGetLastError());
     if (hits_cap > 0) {
-        if ((rc = sort_unique_small(hkeys, halt, hkeys, &stats->n_hits, hits_cap, 0, G.pb + G.tbA + G.tbB, st))) return rc;
-        MS_LAUNCH("k_hits_place", k_hits_place, dim3(grid_for(hits_cap, 256)), dim3(BLOCK), 0, st, htmp, hkeys, &stats->n_hits,
-                           hits_cap, G.tbA, G.tbB, hits_dev);
+        if (hits_cap <= HITS_TINY) {
+            MS_LAUNCH("k_hits_tiny", k_hits_tiny, dim3(1), dim3(BLOCK), 0, st, htmp, hkeys, &stats->n_hits, hits_cap,
+                      hits_dev);
+        } else {
+            if ((rc = sort_unique_small(hkeys, halt, hkeys, &stats->n_hits, hits_cap, 0, G.pb + G.tbA + G.tbB, st)))
+                return rc;
+            MS_LAUNCH("k_hits_place", k_hits_place, dim3(grid_for(hits_cap, 256)), dim3(BLOCK), 0, st, htmp, hkeys,
+                      &stats->n_hits, hits_cap, G.tbA, G.tbB, hits_dev);
+        }
         if (pair_offs)
             MS_LAUNCH("k_pair_offsets", k_pair_offsets, dim3(grid_for(G.n_pairs + 1, 64)), dim3(BLOCK), 0, st, hkeys,
                                &stats->n_hits, hits_cap, (int)G.n_pairs, G.tbA + G.tbB, pair_offs);

@@ -52,13 +52,14 @@ def grids_for(fam, kappa):
     return [oracle.default_grid([a, b], kappa) for a, b in fam]
 
 
-@pytest.mark.parametrize("use_graph", [False, True])
-def test_batch_matches_oracle_per_pair(ms, use_graph):
+@pytest.mark.parametrize("use_graph,hits_cap", [(False, 1 << 12), (True, 1 << 12), (False, 1 << 10), (True, 1 << 10)])
+def test_batch_matches_oracle_per_pair(ms, use_graph, hits_cap):
+    """Hit capacities 4096 (chunked hit sort) and 1024 (one-block hit sort)."""
     fam = small_family(24, 3)
     grids = grids_for(fam, 1.5)
     gp = [(ms.Mesh.from_synth(a), ms.Mesh.from_synth(b)) for a, b in fam]
     params = [ms.make_params(g[0], g[2], g[3]) for g in grids]
-    bt = ms.Batch(gp, params, hits_cap=1 << 12, cand_cap=1 << 16)
+    bt = ms.Batch(gp, params, hits_cap=hits_cap, cand_cap=1 << 16)
     bt.run_checked(use_graph)
     per_pair, st = bt.results()
     assert st["overflow"] == 0
@@ -107,17 +108,18 @@ def test_batch_equals_plain_on_the_full_family(ms, kappa):
         assert plain[i][1]["n_cand"] == len(ref.cand)
 
 
-def test_graph_replays_are_identical(ms):
+@pytest.mark.parametrize("hits_cap", [1 << 12, 1 << 10])
+def test_graph_replays_are_identical(ms, hits_cap):
     """Replay the captured graph several times, with eager device work and
     synchronisations in between; every replay gives the eager result."""
     import torch
     fam = small_family(16, 5)
     gp = [(ms.Mesh.from_synth(a), ms.Mesh.from_synth(b)) for a, b in fam]
     params = [ms.default_params(a, b, 1.0) for a, b in gp]
-    eager = ms.Batch(gp, params, hits_cap=1 << 12, cand_cap=1 << 16)
+    eager = ms.Batch(gp, params, hits_cap=hits_cap, cand_cap=1 << 16)
     eager.run_checked(False)
     ref, st_ref = eager.results()
-    bt = ms.Batch(gp, params, hits_cap=1 << 12, cand_cap=1 << 16)
+    bt = ms.Batch(gp, params, hits_cap=hits_cap, cand_cap=1 << 16)
     junk = torch.zeros(1 << 20, device="cuda")
     for rep in range(4):
         bt.run(True)

@@ -101,6 +101,19 @@ def test_grid_cfg1_full_size_matches_grid_oracle(ms, kappa):
     check_against(ref, hits, st, cand, ref)
 
 
+@pytest.mark.parametrize("hits_cap", [1 << 10, 1 << 14])
+def test_grid_cfg1_bench_configuration(ms, hits_cap):
+    """The 512 x 512 workload as the benchmark runs it: no candidate list,
+    cell edge 1.5 x the mean diameter, hit capacity 1024 (one-block hit
+    sort) and 16384 (chunk sort, merge rank, placement)."""
+    A, B = synth.plain_pair(512, 512, 0)
+    grid = oracle.default_grid([A, B], 1.5)
+    ref = oracle.grid_search(A, B, grid[0], grid[2], grid[3])
+    hits, st, cand = gpu_search(ms, A, B, grid, flags=0, hits_cap=hits_cap)
+    assert cand is None
+    check_against(ref, hits, st, None, ref)
+
+
 def test_grid_invariance_world_shift_and_swap(ms):
     A, B = synth.plain_pair(48, 40, 5)
     ref = oracle.bruteforce(A, B)
