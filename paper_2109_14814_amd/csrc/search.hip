@@ -915,16 +915,18 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
                                                 int64_t hits_cap)
 {
     __shared__ int64_t s_pstart[ENUM_PSTART + 1];
-    // the staged boxes during enumeration, then the chunk's compacted candidates
+    // the staged boxes during enumeration (component-major, so that lanes
+    // reading consecutive entries hit distinct banks), then the chunk's
+    // compacted candidates
     __shared__ union {
-        double box[ENUM_STAGE][8];
+        double box[8][ENUM_STAGE];
         struct {
             uint64_t tt[ENUM_SLOTS];
             int32_t pair[ENUM_SLOTS];
         } c;
     } s_u;
     static_assert(sizeof(double) * ENUM_STAGE * 8 >= 12 * ENUM_SLOTS, "candidate list overlays the staged boxes");
-    double (*s_box)[8] = s_u.box;
+    double (*s_box)[ENUM_STAGE] = s_u.box;
     __shared__ int32_t s_t[ENUM_STAGE];
     __shared__ int64_t s_pre[ENUM_CELLS + 1];
     __shared__ int64_t s_start[ENUM_CELLS];
@@ -1003,7 +1005,7 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
                 double blo[4], bhi[4];
                 tri_box(isB ? Pd.B : Pd.A, t, blo, bhi);
 #pragma unroll
-                for (int d = 0; d < 4; ++d) { s_box[i][d] = blo[d]; s_box[i][4 + d] = bhi[d]; }
+                for (int d = 0; d < 4; ++d) { s_box[d][i] = blo[d]; s_box[4 + d][i] = bhi[d]; }
                 s_t[i] = t;
             }
             __syncthreads();
@@ -1036,8 +1038,8 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
                     double alo[4], ahi[4], blo[4], bhi[4];
 #pragma unroll
                     for (int d = 0; d < 4; ++d) {
-                        alo[d] = s_box[ia][d]; ahi[d] = s_box[ia][4 + d];
-                        blo[d] = s_box[ib][d]; bhi[d] = s_box[ib][4 + d];
+                        alo[d] = s_box[d][ia]; ahi[d] = s_box[4 + d][ia];
+                        blo[d] = s_box[d][ib]; bhi[d] = s_box[4 + d][ib];
                     }
                     keep = enum_pair<ONE>(Pd, s_cell[c], alo, ahi, blo, bhi);
                     packed[j] = ((uint64_t)(uint32_t)s_t[ia] << 32) | (uint32_t)s_t[ib];
