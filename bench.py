@@ -40,18 +40,15 @@ def log(*a):
 def algorithmic_bytes(kernel: str, st: dict, mesh_sizes) -> float | None:
     """Bytes a kernel must move per launch, each byte counted once (no
     re-reads): the per-unit figures times the units of one launch."""
-    E, nc, C, H = st["n_entries"], st["n_cells"], st["n_cand"], st["n_hits"]
-    nall = st.get("n_cells_all", nc)
+    E, nc, C, H = st["n_entries"], st["n_groups"], st["n_cand"], st["n_hits"]
     ntot = sum(nt for nt, _ in mesh_sizes)
     nvtot = sum(nv for _, nv in mesh_sizes)
     table = {
         "k_mark": 32.0 * nvtot + 8.0 * ntot,          # vertices read once, compact cell ranges written
-        "k_keys": 8.0 * ntot + 8.0 * E,               # cell ranges read, keys written
-        "k_radix_onesweep": 16.0 * E,                 # keys read + written
-        "k_cells_scan": 8.0 * E + 8.0 * nall,         # keys read, cell bounds written
-        "k_cells_keep": 8.0 * nall + 40.0 * nc,       # cell bounds read, cell records + slot offsets written
-        # keys of the entries and their cells; the 6 vertices of every candidate; hit records
-        "k_enum": 16.0 * E + 40.0 * nc + 192.0 * C + 120.0 * H,
+        "k_keys": 8.0 * ntot + 16.0 * E,              # cell ranges read, entries and their group ranks written
+        "k_scatter": 24.0 * E,                        # entries and ranks read, grouped entries written
+        # grouped entries and their groups; the 6 vertices of every candidate; hit records
+        "k_enum": 8.0 * E + 24.0 * nc + 192.0 * C + 120.0 * H,
     }
     return table.get(kernel)
 

@@ -39,7 +39,7 @@ enum {
     MS_E_CAPACITY = -2,   /* an output buffer is too small; *needed says how large */
     MS_E_HIP = -3,        /* a HIP runtime call failed (text in last_error) */
     MS_E_NONFINITE = -4,  /* non-finite vertex with MS_SEARCH_STRICT */
-    MS_E_KEYBITS = -5,    /* grid too fine: cell index does not fit the sort key */
+    MS_E_KEYBITS = -5,    /* grid too fine: cell index does not fit the entry word */
     MS_E_WORKSPACE = -6   /* workspace too small for this search; query again */
 };
 
@@ -127,7 +127,9 @@ typedef struct {
     double inv_edge;        /* 1 / cell edge, > 0 and finite */
     int64_t n_cells[4];     /* cells per axis, >= 1 */
     int32_t flags;          /* MS_SEARCH_* */
-    int32_t pad;
+    int32_t table_log2;     /* 0: automatic; else log2 of the hashed occupancy table per
+                               side, clamped to [8, 25] (smaller: more cells share a group;
+                               results do not change, only the work) */
 } search_params_t;
 
 /* World = box of both meshes' finite triangles, edge = kappa * mean triangle
@@ -153,10 +155,10 @@ typedef struct {
 
 /* Counters written by a search (device memory, int64 each). */
 typedef struct {
-    int64_t n_entries;       /* (cell, triangle) entries after the both-sides cell filter */
+    int64_t n_entries;       /* (cell, triangle) entries after the both-sides filter on hashed cells */
     int64_t n_entries_all;   /* entries before the filter */
-    int64_t n_cells;         /* distinct cells holding both meshes */
-    int64_t n_slots;         /* sum over those cells of nA * nB */
+    int64_t n_cells;         /* distinct cells holding both meshes (Alg. 1's boxes, exact) */
+    int64_t n_slots;         /* sum over those cells of nA * nB (exact) */
     int64_t n_cand;          /* |C|: distinct box-overlapping pairs */
     int64_t n_moller;        /* candidates rejected by the Moller test */
     int64_t n_degenerate;    /* candidates with a singular 4x4 system */
@@ -164,26 +166,28 @@ typedef struct {
     int64_t n_hits;          /* |H| */
     int64_t n_nonfinite;     /* triangles of A and B excluded */
     int64_t overflow;        /* bit 0: entries > capacity, bit 1: cand, bit 2: hits */
-    int64_t n_cells_all;     /* distinct cells of the filtered entries (one-mesh cells included) */
-    int64_t reserved[4];     /* zero */
+    int64_t n_groups;        /* groups enumerated: hashed cells with A and B entries (>= n_cells) */
+    int64_t n_group_slots;   /* sum over those groups of nA * nB (>= n_slots) */
+    int64_t reserved[3];     /* zero */
 } search_stats_t;
 
 /*
  * search_workspace_size -- bytes of device workspace that search_intersections
  * needs for this pair and grid, with room for cand_cap candidates and
  * hits_cap hits.  Runs an entry-count kernel on `stream` and synchronises it.
- * Returns MS_E_KEYBITS when the sort key [cell | side | triangle] needs more
- * than 63 bits (prod(n_cells) too large for the triangle counts).
+ * Returns MS_E_KEYBITS when the entry word [cell | side | triangle] needs
+ * more than 63 bits (prod(n_cells) too large for the triangle counts).
  */
 int search_workspace_size(const ms_mesh *A, const ms_mesh *B, const search_params_t *params,
                           int64_t cand_cap, int64_t hits_cap, void *stream, size_t *bytes);
 
 /*
  * search_intersections -- H = { (A_i, B_j) : triangles intersect } (Sec. 6.2),
- * by the GPU pipeline: entry keys per covered cell, LDS radix sort, per-cell
- * pair enumeration with the box test (Sec. 6.2.2), Moller quick test
- * (Sec. 6.2.3) and the 4x4 narrow phase (Sec. 6.2.4), hits sorted by
- * (triA, triB).
+ * by the GPU pipeline: one entry per covered cell that both meshes occupy,
+ * entries grouped by hashed cell (counted and scattered, no sort), pair
+ * enumeration inside each group with the same-cell, home-cell and box tests
+ * (Sec. 6.2.2), Moller quick test (Sec. 6.2.3) and the 4x4 narrow phase
+ * (Sec. 6.2.4), hits sorted by (triA, triB).
  *   ws_dev/ws_bytes: workspace from search_workspace_size (not shared with a
  *     concurrent call); cand_cap and hits_cap must not exceed the values the
  *     workspace was sized for.

@@ -37,7 +37,7 @@ HIT_DTYPE = np.dtype([
     ("margin", np.float64),
 ])
 STATS_FIELDS = ("n_entries", "n_entries_all", "n_cells", "n_slots", "n_cand", "n_moller", "n_degenerate",
-                "n_outside", "n_hits", "n_nonfinite", "overflow", "n_cells_all")
+                "n_outside", "n_hits", "n_nonfinite", "overflow", "n_groups", "n_group_slots")
 
 
 class MSearchError(RuntimeError):
@@ -48,7 +48,7 @@ class MSearchError(RuntimeError):
 
 class SearchParams(C.Structure):
     _fields_ = [("world_lo", C.c_double * 4), ("inv_edge", C.c_double), ("n_cells", C.c_int64 * 4),
-                ("flags", C.c_int32), ("pad", C.c_int32)]
+                ("flags", C.c_int32), ("table_log2", C.c_int32)]
 
 
 class MeshInfo(C.Structure):
@@ -196,13 +196,14 @@ def default_params(A: Mesh, B: Mesh, kappa: float) -> SearchParams:
     return p
 
 
-def make_params(w_lo, inv_edge: float, n_cells, flags: int = 0) -> SearchParams:
+def make_params(w_lo, inv_edge: float, n_cells, flags: int = 0, table_log2: int = 0) -> SearchParams:
     p = SearchParams()
     for d in range(4):
         p.world_lo[d] = float(w_lo[d])
         p.n_cells[d] = int(n_cells[d])
     p.inv_edge = float(inv_edge)
     p.flags = int(flags)
+    p.table_log2 = int(table_log2)
     return p
 
 

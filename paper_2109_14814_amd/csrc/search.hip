@@ -4,30 +4,32 @@
 // Every kernel reads its sizes from device memory, so one call queues a fixed
 // sequence of kernels with no host round trip (and can be captured in a HIP
 // graph):
-//   k_prepare     clear counters, occupancy tables and look-back words
+//   k_prepare     clear counters, occupancy bytes and look-back words
 //   k_mark        per triangle: its box from the vertices (Sec. 6.2.2), the
 //                 overlapped cells of its pair's grid (Sec. 6.2.1), one
-//                 occupancy flag per (hashed) cell and side, fine and coarse;
+//                 occupancy byte per (hashed) cell and side, fine and coarse;
 //                 compact range
-//   k_pack        occupancy bytes -> bit tables
-//   k_keys        per triangle: the cells that the other mesh also touches
-//                 (a box with triangles of one mesh only cannot hold a pair);
-//                 keys [cell | side | triangle] at offsets reserved per
-//                 block; digit histograms for the sort
-//   radix sort    onesweep passes, cells grouped (A's entries before B's)
-//   k_cells_scan  cell starts and A counts of the sorted keys (scan)
-//   k_cells_keep  cells holding both meshes: start, nA, nB, pair; slot
+//   k_pack        hashed cells occupied by both meshes as bit tables; each
+//                 such fine cell is a group, with a dense id (the set bits
+//                 before it, by a scan with decoupled look-back)
+//   k_keys        per triangle: the cells of its range in a both-occupied
+//                 group (a cell holding one mesh only cannot hold a pair);
+//                 entries [cell | side | triangle] at offsets reserved per
+//                 block, each with its group and its rank in the group
+//   k_groups      groups holding A and B entries: entry ranges and slot
 //                 offsets sum(nA * nB) (scan)
-//   k_enum        slot -> (cell, iA, iB); a pair is kept only in its home cell
-//                 (cell of the componentwise max of the boxes' lower corners)
-//                 and only if the closed boxes overlap (Sec. 6.2.2); then,
-//                 on the chunk's candidates, the Moller quick test
-//                 (Sec. 6.2.3), the 4x4 solve and inclusion (Sec. 6.2.4),
-//                 hit records
+//   k_scatter     entries to their group's range, A's before B's
+//   k_enum        slot -> (group, iA, iB); a pair is kept only when both
+//                 entries are of one cell, in its home cell (cell of the
+//                 componentwise max of the boxes' lower corners) and only if
+//                 the closed boxes overlap (Sec. 6.2.2); then, on the chunk's
+//                 candidates, the Moller quick test (Sec. 6.2.3), the 4x4
+//                 solve and inclusion (Sec. 6.2.4), hit records; last, the
+//                 exact cell statistics
 //   hit sort      by (pair, triA, triB): one block for a small capacity,
 //                 else chunk sort, merge rank and placement
-// A batch keys its cells by a per-pair cell offset, so entries of different
-// pairs never share a cell.
+// A batch numbers its cells with a per-pair cell offset, so entries of
+// different pairs never share a cell (they may share a group).
 #include <math.h>
 #include <string.h>
 
@@ -46,14 +48,10 @@ constexpr int MAX_GRID = 2048;
 static_assert(MAX_GRID <= MS_COUNT_PARTIALS, "count partials fit the mesh scratch");
 constexpr int KEYS_ITEMS = 4;                         // triangles per thread in k_keys
 constexpr int KEYS_TILE = BLOCK * KEYS_ITEMS;         // triangles per k_keys block
-constexpr int CELLS_ITEMS = 16;
-constexpr int CELLS_TILE = BLOCK * CELLS_ITEMS;       // = SORT_TILE_KEYS entries per k_cells block
-constexpr int MAX_PASSES = 7;
 constexpr uint64_t SFLAG_AGG = 1ull << 62;
 constexpr uint64_t SFLAG_PRE = 2ull << 62;
 constexpr uint64_t SVAL_MASK = (1ull << 62) - 1;
 
-static_assert(CELLS_TILE == SORT_TILE_KEYS, "k_cells tiles follow the sort tiles");
 static_assert(sizeof(search_stats_t) == 16 * 8, "search_stats_t is 16 int64 words");
 
 inline unsigned grid_for(int64_t n, int64_t cap = MAX_GRID)
@@ -395,11 +393,8 @@ MS_D T block_excl(T v, T *s_tmp, T *total)
 
 struct ClearSpec {
     search_stats_t *stats;
-    uint64_t *flags;   int64_t flag_words;
-    uint64_t *kstat;   int64_t kstat_words;      // look-back words
-    uint32_t *hist;    int64_t hist_words;       // sort histograms
-    uint32_t *ctrs;    int64_t ctr_words;        // tile counters
-    uint32_t *ctrs2;   int64_t ctr2_words;       // more counters
+    uint4 *flags;      int64_t flag_vecs;        // occupancy bytes, 16 per store
+    uint64_t *w[3];    int64_t n[3];             // look-back words, counters
 };
 
 __global__ void __launch_bounds__(BLOCK) k_prepare(ClearSpec c)
@@ -407,11 +402,11 @@ __global__ void __launch_bounds__(BLOCK) k_prepare(ClearSpec c)
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c.stats && g0 < (int64_t)(sizeof(search_stats_t) / 8)) ((int64_t *)c.stats)[g0] = 0;
-    for (int64_t i = g0; i < c.flag_words; i += stride) c.flags[i] = 0;
-    for (int64_t i = g0; i < c.kstat_words; i += stride) c.kstat[i] = 0;
-    for (int64_t i = g0; i < c.hist_words; i += stride) c.hist[i] = 0;
-    for (int64_t i = g0; i < c.ctr_words; i += stride) c.ctrs[i] = 0;
-    for (int64_t i = g0; i < c.ctr2_words; i += stride) c.ctrs2[i] = 0;
+    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+    for (int64_t i = g0; i < c.flag_vecs; i += stride) c.flags[i] = z;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        for (int64_t i = g0; i < c.n[k]; i += stride) c.w[k][i] = 0;
 }
 
 // Occupancy: one byte per hashed global cell and side, set with plain stores
@@ -453,50 +448,69 @@ __global__ void __launch_bounds__(BLOCK) k_mark(BatchView bv, uint8_t *flags, ui
     }
 }
 
-// Occupancy bytes -> bits (32 flags per word), so that the lookups of
-// k_keys hit a table small enough to stay in the L2 caches.
-__global__ void __launch_bounds__(BLOCK) k_pack(const uint8_t *flags, uint32_t *bits, int64_t n_words)
+// 32 occupancy bytes -> one word of flags.
+MS_D uint32_t byte_mask(const uint8_t *f)
 {
+    const uint4 *p = reinterpret_cast<const uint4 *>(f);
+    const uint4 a = p[0], b = p[1];
+    const uint32_t q[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    uint32_t m = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) m |= (uint32_t)(((q[i] >> (8 * j)) & 0xffu) != 0) << (4 * i + j);
+    return m;
+}
+
+// The hashed cells that both meshes occupy, as bit tables (fine, then
+// coarse): the AND of the two sides' occupancy bytes.  Every set fine bit is
+// a cell group, whose entry counters and several-cells flag are cleared here.
+__global__ void __launch_bounds__(BLOCK) k_pack(const uint8_t *flags, int bm_log2, int bc_log2, uint32_t *both,
+                                                uint64_t *grp, uint32_t *mix, int64_t n_fwords, int64_t n_cwords)
+{
+    const size_t side = (size_t)1 << bm_log2, cside = (size_t)1 << bc_log2;
+    const int64_t n = n_fwords + n_cwords;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < n_words; w += stride) {
-        const uint4 *p = reinterpret_cast<const uint4 *>(flags + 32 * w);
-        const uint4 a = p[0], b = p[1];
-        const uint32_t q[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-        uint32_t m = 0;
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) m |= (uint32_t)(((q[i] >> (8 * j)) & 0xffu) != 0) << (4 * i + j);
-        bits[w] = m;
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < n; w += stride) {
+        if (w < n_fwords) {
+            uint32_t m = byte_mask(flags + 32 * w) & byte_mask(flags + side + 32 * w);
+            both[w] = m;
+            while (m) {
+                const int64_t h = 32 * w + __builtin_ctz(m);
+                grp[h] = 0;
+                mix[h] = 0;
+                m &= m - 1;
+            }
+        } else {
+            const uint8_t *c = flags + 2 * side + 32 * (w - n_fwords);
+            both[w] = byte_mask(c) & byte_mask(c + cside);
+        }
     }
 }
 
 struct KeysOut {
-    uint64_t *keys;
+    uint64_t *ent;                // [cell | side | triangle]
+    int32_t *epair;               // pair of the entry (batch)
     int64_t cap;
-    unsigned long long *n_keys;   // entries reserved (cleared); the sort and the cell scan read it
-    uint32_t *hist;               // passes x radix digit counts of the sort
-    uint32_t *sort_status0;       // the sort's pass-0 look-back words (radix per tile)
-    int passes, rb, lo_bit;
+    unsigned long long *n_keys;   // entries reserved (cleared)
+    uint32_t *grp;                // per hashed cell h: [2 h] A entries, [2 h + 1] B entries
+    uint64_t *own;                // per hashed cell: the cell of one of its entries (any)
     search_stats_t *stats;
 };
 
-// Entries of each triangle: the cells of its range that the other mesh also
-// occupies (a cell holding one mesh only cannot hold a pair).  Each block
-// counts the entries of its KEYS_TILE triangles, reserves that many output
-// slots with one atomic add (blocks without entries take none) and writes the
-// keys [cell | side | triangle].  The blocks' output ranges come out in any
-// order, which the sort makes irrelevant (the keys are distinct).  Also
-// accumulates the digit histograms of every sort pass and clears the sort's
-// pass-0 look-back words of the tiles it writes.
+// Entries of each triangle: the cells of its range whose hashed cell both
+// meshes occupy (a cell holding one mesh only cannot hold a pair), after the
+// same test on the coarse cells.  Each block counts the entries of its
+// KEYS_TILE triangles, reserves that many output slots with one atomic add
+// (blocks without entries take none) and writes the entries; every stored
+// entry is counted in its group and side, and leaves its cell as the
+// group's sample.
 template <bool ONE>
-__global__ void __launch_bounds__(BLOCK) k_keys(BatchView bv, const uint32_t *bits, const uint64_t *rng, KeysOut o)
+__global__ void __launch_bounds__(BLOCK) k_keys(BatchView bv, const uint32_t *both, const uint64_t *rng, KeysOut o)
 {
-    __shared__ uint32_t s_hist[MAX_PASSES * 1024];
     __shared__ uint64_t s_tmp[BLOCK / WAVE];
     __shared__ unsigned long long s_blk0;
-    const size_t side_words = ((size_t)1 << bv.bm_log2) / 32;
-    const int R = 1 << o.rb;
+    const uint32_t *cboth = both + ((size_t)1 << bv.bm_log2) / 32;
     const int64_t base = (int64_t)blockIdx.x * KEYS_TILE;
     uint32_t cnt[KEYS_ITEMS], msk[KEYS_ITEMS];
     uint32_t bigm = 0;
@@ -509,24 +523,21 @@ __global__ void __launch_bounds__(BLOCK) k_keys(BatchView bv, const uint32_t *bi
             TriLoc L = locate<ONE>(bv, gt);
             CellRange r;
             if (range_of<ONE>(bv, rng, gt, L, r)) {
-                const uint32_t *other = bits + (size_t)(1 - L.side) * side_words;
                 const PairDesc &P = pair_desc<ONE>(bv, L.p);
                 CellRange rc;
                 int64_t nc[4];
                 coarse_of(r, P.g.n, rc, nc);
-                const uint32_t *cother = bits + 2 * side_words + ((size_t)(1 - L.side) << bv.bc_log2) / 32;
                 bool bigc;
-                const uint32_t mc = flag_mask(rc, nc, P.cell_base, cother, bv.bc_log2, &bigc);
-                bool big = false;
-                if (!bigc && mc == 0) {
-                    // no coarse cell of the range holds the other mesh: no entry
-                } else {
-                m = flag_mask(r, P.g.n, P.cell_base, other, bv.bm_log2, &big);
-                if (!big) c = (uint32_t)__builtin_popcount(m);
-                else {
-                    bigm |= 1u << i;
-                    for_cells(r, P.g.n, [&](uint64_t cell) { c += occ_bit(other, bm_hash(P.cell_base + cell, bv.bm_log2)); });
-                }
+                const uint32_t mc = flag_mask(rc, nc, P.cell_base, cboth, bv.bc_log2, &bigc);
+                if (bigc || mc != 0) {
+                    bool big = false;
+                    m = flag_mask(r, P.g.n, P.cell_base, both, bv.bm_log2, &big);
+                    if (!big) {
+                        c = (uint32_t)__builtin_popcount(m);
+                    } else {
+                        bigm |= 1u << i;
+                        for_cells(r, P.g.n, [&](uint64_t cell) { c += occ_bit(both, bm_hash(P.cell_base + cell, bv.bm_log2)); });
+                    }
                 }
             }
         }
@@ -537,19 +548,13 @@ __global__ void __launch_bounds__(BLOCK) k_keys(BatchView bv, const uint32_t *bi
     uint64_t btotal;
     const uint64_t texcl = block_excl(mine, s_tmp, &btotal);
     if (btotal == 0) return;                      // uniform: every thread saw the same total
-    for (int i = threadIdx.x; i < o.passes * R; i += BLOCK) s_hist[i] = 0;
     if (threadIdx.x == 0) {
         const unsigned long long b0 = atomicAdd(o.n_keys, (unsigned long long)btotal);
         s_blk0 = b0;
         if ((int64_t)(b0 + btotal) > o.cap) atomicOr((unsigned long long *)&o.stats->overflow, 1ull);
     }
     __syncthreads();
-    const uint64_t blk0 = s_blk0;
-    if ((int64_t)(blk0 + btotal) <= o.cap) {
-        const int64_t t0 = (int64_t)blk0 / SORT_TILE_KEYS, t1 = (int64_t)(blk0 + btotal - 1) / SORT_TILE_KEYS;
-        for (int64_t w = threadIdx.x; w < (t1 - t0 + 1) * R; w += BLOCK) o.sort_status0[t0 * R + w] = 0;
-    }
-    int64_t pos = (int64_t)(blk0 + texcl);
+    int64_t pos = (int64_t)(s_blk0 + texcl);
 #pragma unroll
     for (int i = 0; i < KEYS_ITEMS; ++i) {
         if (cnt[i] == 0) continue;
@@ -557,16 +562,15 @@ __global__ void __launch_bounds__(BLOCK) k_keys(BatchView bv, const uint32_t *bi
         TriLoc L = locate<ONE>(bv, gt);
         CellRange r;
         range_of<ONE>(bv, rng, gt, L, r);
-        const uint32_t *other = bits + (size_t)(1 - L.side) * side_words;
         const PairDesc &P = pair_desc<ONE>(bv, L.p);
         const uint64_t cb = P.cell_base;
         const uint64_t low = ((uint64_t)L.side << bv.kl.tb) | (uint64_t)L.t;
-        auto put = [&](uint64_t gc) {
-            const uint64_t key = (gc << bv.kl.cell_shift) | low;
-            if (pos < o.cap) {
-                o.keys[pos] = key;
-                for (int q = 0; q < o.passes; ++q)
-                    atomicAdd(&s_hist[q * R + (int)((key >> (o.lo_bit + o.rb * q)) & (uint64_t)(R - 1))], 1u);
+        auto put = [&](uint64_t gc, uint32_t h) {
+            if (pos < o.cap) {      // only stored entries are counted in their group
+                atomicAdd(&o.grp[2 * (size_t)h + L.side], 1u);
+                o.own[h] = gc;
+                o.ent[pos] = (gc << bv.kl.cell_shift) | low;
+                if (!ONE) o.epair[pos] = L.p;
             }
             ++pos;
         };
@@ -574,24 +578,24 @@ __global__ void __launch_bounds__(BLOCK) k_keys(BatchView bv, const uint32_t *bi
             const uint32_t m = msk[i];
             int j = 0;
             for_cells(r, P.g.n, [&](uint64_t cell) {
-                if (m >> j & 1) put(cb + cell);
+                if (m >> j & 1) put(cb + cell, bm_hash(cb + cell, bv.bm_log2));
                 ++j;
             });
         } else {
             for_cells(r, P.g.n, [&](uint64_t cell) {
-                if (occ_bit(other, bm_hash(cb + cell, bv.bm_log2))) put(cb + cell);
+                const uint32_t h = bm_hash(cb + cell, bv.bm_log2);
+                if (occ_bit(both, h)) put(cb + cell, h);
             });
         }
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < o.passes * R; i += BLOCK)
-        if (s_hist[i]) atomicAdd(&o.hist[i], s_hist[i]);
 }
 
+// A kept cell group: its entries, A's then B's, from `start`; h is its
+// hashed cell.
 struct CellRec {
     int64_t start;
     int32_t nA, nB;
-    int32_t pair, pad;
+    int64_t h;
 };
 
 // First index in [lo, hi) whose key is >= k (keys ascending).
@@ -605,244 +609,163 @@ MS_D int64_t lower_bound_u64(const uint64_t *a, int64_t lo, int64_t hi, uint64_t
     return lo;
 }
 
-// The same, galloping from lo (cheap when the answer is close to lo).
-MS_D int64_t gallop_u64(const uint64_t *a, int64_t lo, int64_t hi, uint64_t k)
-{
-    int64_t step = 1, prev = lo;
-    while (lo < hi && a[lo] < k) {
-        prev = lo + 1;
-        lo += step;
-        step <<= 1;
-    }
-    if (lo > hi) lo = hi;
-    return lower_bound_u64(a, prev, lo, k);
-}
+// The groups holding both meshes, in order of their hashed cells.  A group
+// is kept when it has A and B entries; kept groups get consecutive records,
+// entry ranges (sum of nA + nB before them) and slot offsets (sum of
+// nA * nB), from one block scan and a decoupled look-back per tile of
+// GROUP_WORDS words of the both-occupied table.  Each group's counter word
+// becomes its two placement cursors: start (A entries) in the low half,
+// start + nA (B entries) in the high half; a group not kept gets the
+// cursors' high bits set.  Block 0 also gathers the totals of the keying
+// kernels.
+constexpr int GROUP_ITEMS = 4;                   // words of the fine table per thread
+constexpr int GROUP_WORDS = BLOCK * GROUP_ITEMS;
+constexpr uint64_t GRP_DROP = 0x8000000080000000ull;
 
-// Cell boundaries of the sorted keys, as two fully parallel scans (no
-// searching through the key array):
-//   k_cells_scan  per sorted tile: the entries that start a cell and the
-//                 entries of mesh A, each counted by a block scan and a
-//                 decoupled look-back; every cell start e writes
-//                 bounds[ci] = (e << 32) | (A entries before e);
-//   k_cells_keep  per cell: nA, nB from consecutive bounds (A entries sort
-//                 before B entries inside a cell); cells holding both meshes
-//                 are kept, with their slot offsets sum(nA * nB), by a second
-//                 scan and look-back.
-struct CellsScanOut {
-    uint64_t *bounds;         // n_all + 1
-    int64_t *n_all;           // cells (including one-mesh cells)
+struct GroupsOut {
+    const uint32_t *both;     // fine both-occupied bits
+    uint64_t *grp;            // per hashed cell: counters in, cursors out
+    int64_t n_fwords;
+    CellRec *cells;           // kept groups
+    int64_t *pstart;          // kept groups + 1
+    int64_t *kept;            // [0] kept groups, [1] their slots
+    uint64_t *stat;           // 2 look-back words per tile (cleared)
+    uint32_t *tile_ctr;       // (cleared)
     search_stats_t *stats;
-    int64_t cap;              // key capacity (the count read is clamped to it)
+    const unsigned long long *n_keys;
     const unsigned long long *mark_partial;
     int n_mark_partial;
-    uint64_t *stat;           // 3 look-back words per tile: [0] here, [1..2] k_cells_keep
-    uint32_t *tile_ctr;
 };
 
-template <bool ONE>
-__global__ void __launch_bounds__(BLOCK) k_cells_scan(BatchView bv, const uint64_t *keys, const int64_t *n_dev,
-                                                      CellsScanOut o)
+__global__ void __launch_bounds__(BLOCK) k_groups(GroupsOut o)
 {
-    __shared__ uint64_t s_tmp64[BLOCK / WAVE];
-    __shared__ uint64_t s_base;
+    __shared__ uint64_t s_tk[BLOCK / WAVE], s_tp[BLOCK / WAVE];
+    __shared__ uint64_t s_kbase, s_pbase;
     __shared__ uint32_t s_tile;
-    const int64_t E = *n_dev;
-    const int64_t n = E < o.cap ? E : o.cap;
-    const int64_t ntiles = (n + CELLS_TILE - 1) / CELLS_TILE;
-    const int sh = bv.kl.cell_shift, tb = bv.kl.tb;
+    const int64_t ntiles = (o.n_fwords + GROUP_WORDS - 1) / GROUP_WORDS;
     if (blockIdx.x == 0) {
-        // totals of the keying kernels: entries, entries before the filter, non-finite triangles
         unsigned long long all = 0, bad = 0;
-        for (int i = threadIdx.x; i < o.n_mark_partial; i += BLOCK) { all += o.mark_partial[2 * i]; bad += o.mark_partial[2 * i + 1]; }
-        all = block_sum(all, (unsigned long long *)s_tmp64);
-        bad = block_sum(bad, (unsigned long long *)s_tmp64);
+        for (int i = threadIdx.x; i < o.n_mark_partial; i += BLOCK) {
+            all += o.mark_partial[2 * i];
+            bad += o.mark_partial[2 * i + 1];
+        }
+        all = block_sum(all, (unsigned long long *)s_tk);
+        bad = block_sum(bad, (unsigned long long *)s_tp);
         if (threadIdx.x == 0) {
-            o.stats->n_entries = E;
+            o.stats->n_entries = (int64_t)*o.n_keys;
             o.stats->n_entries_all = (int64_t)all;
             o.stats->n_nonfinite = (int64_t)bad;
         }
         __syncthreads();
     }
-    if (n == 0) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            *o.n_all = 0;
-            o.stats->n_cells_all = 0;
-            o.bounds[0] = 0;
-        }
-        return;
-    }
-    if ((int64_t)blockIdx.x >= ntiles) return;   // no tile for this block: leave the counter alone
     for (;;) {
         if (threadIdx.x == 0) s_tile = atomicAdd(o.tile_ctr, 1u);
         __syncthreads();
         const int64_t tile = s_tile;
         __syncthreads();
         if (tile >= ntiles) break;
-        // each thread owns CELLS_ITEMS consecutive entries
-        const int64_t e0 = tile * CELLS_TILE + (int64_t)threadIdx.x * CELLS_ITEMS;
-        uint64_t prev = (e0 > 0 && e0 < n) ? (keys[e0 - 1] >> sh) : ~0ull;
-        uint32_t startm = 0, am = 0;
-        uint64_t cnt = 0;   // (starts << 32) | A entries
+        const int64_t w0 = tile * GROUP_WORDS + (int64_t)threadIdx.x * GROUP_ITEMS;
+        uint32_t m[GROUP_ITEMS];
+        uint64_t kc = 0, pc = 0;     // (kept << 32) | entries; slots
 #pragma unroll
-        for (int i = 0; i < CELLS_ITEMS; ++i) {
-            const int64_t e = e0 + i;
-            if (e < n) {
-                const uint64_t k = keys[e];
-                const uint64_t cell = k >> sh;
-                const bool st = e == 0 || cell != prev;
-                const bool isA = ((k >> tb) & 1) == 0;
-                startm |= (uint32_t)st << i;
-                am |= (uint32_t)isA << i;
-                cnt += ((uint64_t)st << 32) + (uint64_t)isA;
-                prev = cell;
+        for (int j = 0; j < GROUP_ITEMS; ++j) {
+            m[j] = w0 + j < o.n_fwords ? o.both[w0 + j] : 0u;
+            for (uint32_t q = m[j]; q; q &= q - 1) {
+                const uint64_t v = o.grp[32 * (w0 + j) + __builtin_ctz(q)];
+                const uint64_t a = v & 0xffffffffull, b = v >> 32;
+                if (a && b) {
+                    kc += (1ull << 32) + a + b;
+                    pc += a * b;
+                }
             }
         }
-        uint64_t tot;
-        const uint64_t tex = block_excl(cnt, s_tmp64, &tot);
+        uint64_t ktot, ptot;
+        const uint64_t kex = block_excl(kc, s_tk, &ktot);
+        const uint64_t pex = block_excl(pc, s_tp, &ptot);
         if (threadIdx.x < WAVE) {
-            uint64_t ex = 0;
-            uint64_t *w = o.stat + 3 * tile;
+            uint64_t kb = 0, pb = 0;
+            uint64_t *sk = o.stat + 2 * tile, *sp = sk + 1;
             if (tile == 0) {
-                if (threadIdx.x == 0) publish_u64(w, SFLAG_PRE, tot);
+                if (threadIdx.x == 0) {
+                    publish_u64(sp, SFLAG_PRE, ptot);
+                    publish_u64(sk, SFLAG_PRE, ktot);
+                }
             } else {
-                if (threadIdx.x == 0) publish_u64(w, SFLAG_AGG, tot);
-                ex = wave_lookback3(o.stat, tile);
-                if (threadIdx.x == 0) publish_u64(w, SFLAG_PRE, ex + tot);
+                if (threadIdx.x == 0) {
+                    publish_u64(sp, SFLAG_AGG, ptot);
+                    publish_u64(sk, SFLAG_AGG, ktot);
+                }
+                wave_lookback2(o.stat, 2, tile, kb, pb);
+                if (threadIdx.x == 0) {
+                    publish_u64(sp, SFLAG_PRE, pb + ptot);
+                    publish_u64(sk, SFLAG_PRE, kb + ktot);
+                }
             }
             if (threadIdx.x == 0) {
-                s_base = ex;
+                s_kbase = kb;
+                s_pbase = pb;
                 if (tile == ntiles - 1) {
-                    const uint64_t all = ex + tot;
-                    *o.n_all = (int64_t)(all >> 32);
-                    o.stats->n_cells_all = (int64_t)(all >> 32);
-                    o.bounds[all >> 32] = ((uint64_t)n << 32) | (all & 0xffffffffull);
+                    const int64_t nk = (int64_t)((kb + ktot) >> 32), P = (int64_t)(pb + ptot);
+                    o.kept[0] = nk;
+                    o.kept[1] = P;
+                    o.pstart[nk] = P;
+                    o.stats->n_groups = nk;
+                    o.stats->n_group_slots = P;
                 }
             }
         }
         __syncthreads();
-        uint64_t run = s_base + tex;
+        uint64_t kr = s_kbase + kex, pr = s_pbase + pex;
 #pragma unroll
-        for (int i = 0; i < CELLS_ITEMS; ++i) {
-            if (startm >> i & 1) o.bounds[run >> 32] = ((uint64_t)(e0 + i) << 32) | (run & 0xffffffffull);
-            run += ((uint64_t)(startm >> i & 1) << 32) + (uint64_t)(am >> i & 1);
+        for (int j = 0; j < GROUP_ITEMS; ++j) {
+            for (uint32_t q = m[j]; q; q &= q - 1) {
+                const int64_t h = 32 * (w0 + j) + __builtin_ctz(q);
+                uint64_t *gw = o.grp + h;
+                const uint64_t v = *gw;
+                const uint64_t a = v & 0xffffffffull, b = v >> 32;
+                if (a && b) {
+                    const int64_t ki = (int64_t)(kr >> 32), start = (int64_t)(kr & 0xffffffffull);
+                    CellRec cr;
+                    cr.start = start;
+                    cr.nA = (int32_t)a;
+                    cr.nB = (int32_t)b;
+                    cr.h = h;
+                    o.cells[ki] = cr;
+                    o.pstart[ki] = (int64_t)pr;
+                    *gw = (((uint64_t)start + a) << 32) | (uint64_t)start;
+                    kr += (1ull << 32) + a + b;
+                    pr += a * b;
+                } else {
+                    *gw = GRP_DROP;
+                }
+            }
         }
         __syncthreads();
     }
 }
 
-struct CellsOut {
-    CellRec *cells;
-    int64_t *pstart;          // n_cells + 1
-    uint64_t *stat;           // the same 3 words per tile as k_cells_scan
-    uint32_t *tile_ctr;
-    search_stats_t *stats;
-};
-
+// Entries to their group's range: the group's cursor of the entry's side
+// gives the position (A entries first).  Entries of groups holding one mesh
+// only are dropped.  An entry whose cell differs from its group's sample
+// flags the group as holding several cells.
 template <bool ONE>
-__global__ void __launch_bounds__(BLOCK) k_cells_keep(BatchView bv, const uint64_t *keys, const uint64_t *bounds,
-                                                      const int64_t *n_all_dev, CellsOut o)
+__global__ void __launch_bounds__(BLOCK) k_scatter(const uint64_t *ent, const int32_t *epair,
+                                                   const unsigned long long *n_keys, int64_t cap, uint32_t *grp,
+                                                   const uint64_t *own, uint32_t *mix, int bm_log2, int cell_shift,
+                                                   int tb, uint64_t *out, int32_t *opair)
 {
-    __shared__ uint32_t s_tmp32[BLOCK / WAVE];
-    __shared__ uint64_t s_tmp64[BLOCK / WAVE];
-    __shared__ uint64_t s_cbase, s_pbase;
-    __shared__ uint32_t s_tile;
-    const int64_t nall = *n_all_dev;
-    const int64_t ntiles = (nall + CELLS_TILE - 1) / CELLS_TILE;
-    const int sh = bv.kl.cell_shift;
-    if (nall == 0) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            o.stats->n_cells = 0;
-            o.stats->n_slots = 0;
-            o.pstart[0] = 0;
-        }
-        return;
-    }
-    if ((int64_t)blockIdx.x >= ntiles) return;
-    for (;;) {
-        if (threadIdx.x == 0) s_tile = atomicAdd(o.tile_ctr, 1u);
-        __syncthreads();
-        const int64_t tile = s_tile;
-        __syncthreads();
-        if (tile >= ntiles) break;
-        const int64_t c0 = tile * CELLS_TILE + (int64_t)threadIdx.x * CELLS_ITEMS;
-        uint32_t keepm = 0, ccount = 0;
-        uint64_t pcount = 0;
-        int32_t na[CELLS_ITEMS], nb[CELLS_ITEMS];
-        int64_t st[CELLS_ITEMS];
-        uint64_t v1 = c0 < nall ? bounds[c0] : 0;
-#pragma unroll
-        for (int i = 0; i < CELLS_ITEMS; ++i) {
-            const int64_t c = c0 + i;
-            na[i] = nb[i] = 0;
-            st[i] = 0;
-            if (c < nall) {
-                const uint64_t v0 = v1;
-                v1 = bounds[c + 1];
-                const int64_t s0 = (int64_t)(v0 >> 32), s1 = (int64_t)(v1 >> 32);
-                const int64_t a = (int64_t)((v1 & 0xffffffffull) - (v0 & 0xffffffffull));
-                const int64_t b = (s1 - s0) - a;
-                if (a > 0 && b > 0) {
-                    keepm |= 1u << i;
-                    st[i] = s0;
-                    na[i] = (int32_t)a;
-                    nb[i] = (int32_t)b;
-                    ++ccount;
-                    pcount += (uint64_t)a * (uint64_t)b;
-                }
-            }
-        }
-        uint32_t ctot;
-        uint64_t ptot;
-        const uint32_t cex = block_excl(ccount, s_tmp32, &ctot);
-        const uint64_t pex = block_excl(pcount, s_tmp64, &ptot);
-        if (threadIdx.x < WAVE) {
-            uint64_t cb = 0, pb = 0;
-            uint64_t *sc = o.stat + 3 * tile + 1, *sp = sc + 1;
-            if (tile == 0) {
-                if (threadIdx.x == 0) {
-                    publish_u64(sp, SFLAG_PRE, ptot);
-                    publish_u64(sc, SFLAG_PRE, ctot);
-                }
-            } else {
-                if (threadIdx.x == 0) {
-                    publish_u64(sp, SFLAG_AGG, ptot);
-                    publish_u64(sc, SFLAG_AGG, ctot);
-                }
-                wave_lookback2(o.stat + 1, 3, tile, cb, pb);
-                if (threadIdx.x == 0) {
-                    publish_u64(sp, SFLAG_PRE, pb + ptot);
-                    publish_u64(sc, SFLAG_PRE, cb + ctot);
-                }
-            }
-            if (threadIdx.x == 0) {
-                s_cbase = cb;
-                s_pbase = pb;
-                if (tile == ntiles - 1) {
-                    const int64_t nc = (int64_t)(cb + ctot), P = (int64_t)(pb + ptot);
-                    o.stats->n_cells = nc;
-                    o.stats->n_slots = P;
-                    o.pstart[nc] = P;
-                }
-            }
-        }
-        __syncthreads();
-        int64_t ci = (int64_t)s_cbase + cex;
-        uint64_t ps = s_pbase + pex;
-#pragma unroll
-        for (int i = 0; i < CELLS_ITEMS; ++i) {
-            if (!(keepm >> i & 1)) continue;
-            CellRec cr;
-            cr.start = st[i];
-            cr.nA = na[i];
-            cr.nB = nb[i];
-            cr.pair = ONE ? 0 : pair_of_cell<ONE>(bv, keys[st[i]] >> sh);
-            cr.pad = 0;
-            o.cells[ci] = cr;
-            o.pstart[ci] = (int64_t)ps;
-            ps += (uint64_t)na[i] * (uint64_t)nb[i];
-            ++ci;
-        }
-        __syncthreads();
+    const int64_t nk = (int64_t)*n_keys;
+    const int64_t n = nk < cap ? nk : cap;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint64_t e = ent[i];
+        const uint64_t gc = e >> cell_shift;
+        const uint32_t h = bm_hash(gc, bm_log2);
+        const uint32_t pos = atomicAdd(&grp[2 * (size_t)h + ((e >> tb) & 1)], 1u);
+        if (pos & 0x80000000u) continue;
+        out[pos] = e;
+        if (!ONE) opair[pos] = epair[i];
+        if (own[h] != gc) atomicOr(&mix[h], 1u);
     }
 }
 
@@ -873,23 +796,29 @@ MS_D void emit_hit(bool hit, const hit_t &h, uint64_t key, hit_t *hits, uint64_t
     }
 }
 
-// Slot -> (cell, iA, iB), iA = slot mod nA, iB = slot / nA (Alg. 1).  A pair
-// is kept only in its home cell, the cell of the componentwise max of the two
-// boxes' lower corners (the one cell of both ranges that every overlapping
-// pair has, by monotonicity of the cell map), and only if the closed boxes
-// overlap (Sec. 6.2.2).
+// Slot -> (group, iA, iB), iA = slot mod nA, iB = slot / nA (Alg. 1).  A
+// group holds the entries of every cell with the same hashed id, so a pair
+// of entries counts only when both are entries of the same cell; the pair
+// is then kept only in its home cell, the cell of the componentwise max of
+// the two boxes' lower corners (the one cell of both ranges that every
+// overlapping pair has, by monotonicity of the cell map), and only if the
+// closed boxes overlap (Sec. 6.2.2).
 //
-// Each block takes ENUM_SLOTS consecutive slots.  Of every cell the chunk
+// Each block takes ENUM_SLOTS consecutive slots.  Of every group the chunk
 // touches it needs only the A entries of the rows it covers (all of them once
 // it spans more than one row) and the B entries of those rows; when these are
-// at most ENUM_STAGE in all, the block stages their triangle indices and
-// boxes (computed once from the vertices) in LDS, so that every slot reads
-// LDS only.  Otherwise each slot gathers its two triangles from global
-// memory.  One atomic reservation per chunk for the candidates.
+// at most ENUM_STAGE in all, the block stages their cells, triangle indices
+// and boxes (computed once from the vertices) in LDS, so that every slot
+// reads LDS only.  Otherwise each slot gathers its two triangles from global
+// memory.  One atomic reservation per chunk for the candidates, then the
+// narrow phase on the chunk's candidates.  Last, the exact cell statistics
+// (Alg. 1's boxes and slots) of the groups that start in the chunk.
 constexpr int ENUM_ITEMS = 16;
 constexpr int ENUM_SLOTS = BLOCK * ENUM_ITEMS;
 constexpr int ENUM_STAGE = 768;
 constexpr int ENUM_CELLS = BLOCK;
+constexpr int ENUM_GROUP = ENUM_STAGE;        // group cells held in LDS for the statistics
+constexpr int ENUM_GRID = 512;                // one block per CU fits (LDS): two rounds
 
 template <bool ONE>
 MS_D bool enum_pair(const PairDesc &Pd, uint64_t cell, const double alo[4], const double ahi[4], const double blo[4],
@@ -906,13 +835,44 @@ MS_D bool enum_pair(const PairDesc &Pd, uint64_t cell, const double alo[4], cons
     return ov && (uint64_t)cell_linear(h, Pd.g.n) == cell;
 }
 
-constexpr int ENUM_PSTART = 4096;   // slot offsets kept in LDS when the cells are this few
+template <bool ONE>
+MS_D int entry_pair(const int32_t *kpair, int64_t e)
+{
+    if constexpr (ONE) return 0;
+    else return kpair[e];
+}
+
+// Exact cell statistics of a group holding several cells, by the whole
+// block: per A entry, the B entries of its own cell are its slots, and the
+// first A entry of a cell with B entries adds the cell.  The group's cells
+// go through LDS (s_cell, ENUM_GROUP entries) when they fit.
+MS_D void group_stats(const uint64_t *keys, const CellRec &cr, int sh, uint64_t *s_cell, unsigned long long &xc,
+                      unsigned long long &xs)
+{
+    const int n = cr.nA + cr.nB;
+    const bool lds = n <= ENUM_GROUP;
+    if (lds)
+        for (int i = threadIdx.x; i < n; i += BLOCK) s_cell[i] = keys[cr.start + i] >> sh;
+    __syncthreads();
+    for (int i = threadIdx.x; i < cr.nA; i += BLOCK) {
+        const uint64_t ci = lds ? s_cell[i] : keys[cr.start + i] >> sh;
+        uint32_t nb = 0, before = 0;
+        for (int j = 0; j < cr.nB; ++j) nb += (lds ? s_cell[cr.nA + j] : keys[cr.start + cr.nA + j] >> sh) == ci;
+        for (int j = 0; j < i; ++j) before += (lds ? s_cell[j] : keys[cr.start + j] >> sh) == ci;
+        xs += nb;
+        xc += (nb > 0 && before == 0);
+    }
+    __syncthreads();
+}
+
+constexpr int ENUM_PSTART = 4096;   // slot offsets kept in LDS when the groups are this few
 
 template <bool ONE>
-__global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *keys, const CellRec *cells,
-                                                const int64_t *pstart_g, search_stats_t *stats, uint64_t *cand,
-                                                int32_t *cand_pair, int64_t cand_cap, hit_t *hits, uint64_t *hkeys,
-                                                int64_t hits_cap)
+__global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *keys, const int32_t *kpair,
+                                                const CellRec *cells, const int64_t *pstart_g, const int64_t *kept,
+                                                const uint32_t *mix,
+                                                search_stats_t *stats, uint64_t *cand, int32_t *cand_pair,
+                                                int64_t cand_cap, hit_t *hits, uint64_t *hkeys, int64_t hits_cap)
 {
     __shared__ int64_t s_pstart[ENUM_PSTART + 1];
     // the staged boxes during enumeration (component-major, so that lanes
@@ -928,19 +888,24 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
     static_assert(sizeof(double) * ENUM_STAGE * 8 >= 12 * ENUM_SLOTS, "candidate list overlays the staged boxes");
     double (*s_box)[ENUM_STAGE] = s_u.box;
     __shared__ int32_t s_t[ENUM_STAGE];
+    __shared__ uint64_t s_ec[ENUM_STAGE];
+    __shared__ int32_t s_ep[ONE ? 1 : ENUM_STAGE];
     __shared__ int64_t s_pre[ENUM_CELLS + 1];
     __shared__ int64_t s_start[ENUM_CELLS];
     __shared__ int32_t s_aoff[ENUM_CELLS + 1], s_boff[ENUM_CELLS], s_ia0[ENUM_CELLS], s_ib0[ENUM_CELLS];
-    __shared__ int32_t s_nA[ENUM_CELLS], s_pair[ENUM_CELLS];
-    __shared__ uint64_t s_cell[ENUM_CELLS];
+    __shared__ int32_t s_nA[ENUM_CELLS];
     __shared__ int64_t s_c0, s_c1;
     __shared__ uint32_t s_kscan[BLOCK / WAVE];
     __shared__ unsigned long long s_kbase;
-    const int64_t ncells = stats->n_cells;
-    const int64_t P = stats->n_slots;
+    __shared__ unsigned long long s_st[BLOCK / WAVE];
+    __shared__ uint32_t s_nmix;
+    unsigned long long xc = 0, xs = 0;      // exact cells and slots
+    const int64_t ncells = kept[0];
+    const int64_t P = kept[1];
     const int64_t nchunks = ceil_div(P, ENUM_SLOTS);
-    if ((int64_t)blockIdx.x >= nchunks) return;
+    const int sh = bv.kl.cell_shift;
     const bool lds_pre = ncells <= ENUM_PSTART;
+    if ((int64_t)blockIdx.x < nchunks) {
     if (lds_pre) {
         for (int64_t i = threadIdx.x; i <= ncells; i += BLOCK) s_pstart[i] = pstart_g[i];
         __syncthreads();
@@ -955,7 +920,7 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
         }
         __syncthreads();
         const int64_t c0 = s_c0, nc = s_c1 - s_c0 + 1;
-        // the rows of every touched cell that the chunk covers, and the entries they need
+        // the rows of every touched group that the chunk covers, and the entries they need
         uint32_t need = 0;
         if (nc <= ENUM_CELLS && threadIdx.x < nc) {
             const int64_t c = c0 + threadIdx.x;
@@ -969,14 +934,11 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
                 ia1 = (l1 - 1) - ib1 * cr.nA + 1;
             }
             need = (uint32_t)((ia1 - ia0) + (ib1 - ib0 + 1));
-            const PairDesc &Pd = pair_desc<ONE>(bv, cr.pair);
             s_pre[threadIdx.x] = p0;
             s_start[threadIdx.x] = cr.start;
             s_ia0[threadIdx.x] = (int32_t)ia0;
             s_ib0[threadIdx.x] = (int32_t)ib0;
             s_nA[threadIdx.x] = cr.nA;
-            s_pair[threadIdx.x] = cr.pair;
-            s_cell[threadIdx.x] = (keys[cr.start] >> bv.kl.cell_shift) - Pd.cell_base;
             s_boff[threadIdx.x] = (int32_t)(ia1 - ia0);     // made absolute below
             if (threadIdx.x == nc - 1) s_pre[nc] = p1;
         }
@@ -991,7 +953,7 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
             if (threadIdx.x == 0) s_aoff[nc] = (int32_t)tot;
             __syncthreads();
             for (int i = threadIdx.x; i < (int)tot; i += BLOCK) {
-                int lo = 0, hi = (int)nc;             // the cell whose staged range holds i
+                int lo = 0, hi = (int)nc;             // the group whose staged range holds i
                 while (hi - lo > 1) {
                     const int mid = (lo + hi) >> 1;
                     if (s_aoff[mid] <= i) lo = mid;
@@ -1000,13 +962,17 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
                 const bool isB = i >= s_boff[lo];
                 const int64_t e = isB ? s_start[lo] + s_nA[lo] + s_ib0[lo] + (i - s_boff[lo])
                                       : s_start[lo] + s_ia0[lo] + (i - s_aoff[lo]);
-                const int32_t t = (int32_t)(keys[e] & bv.kl.tmask);
-                const PairDesc &Pd = pair_desc<ONE>(bv, s_pair[lo]);
+                const uint64_t key = keys[e];
+                const int32_t t = (int32_t)(key & bv.kl.tmask);
+                const int p = entry_pair<ONE>(kpair, e);
+                const PairDesc &Pd = pair_desc<ONE>(bv, p);
                 double blo[4], bhi[4];
                 tri_box(isB ? Pd.B : Pd.A, t, blo, bhi);
 #pragma unroll
                 for (int d = 0; d < 4; ++d) { s_box[d][i] = blo[d]; s_box[4 + d][i] = bhi[d]; }
                 s_t[i] = t;
+                s_ec[i] = key >> sh;
+                if (!ONE) s_ep[i] = p;
             }
             __syncthreads();
         }
@@ -1021,7 +987,7 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
             prs[j] = 0;
             if (slot < S1) {
                 if (staged) {
-                    int lo = 0, hi = (int)nc;          // last staged cell with s_pre <= slot
+                    int lo = 0, hi = (int)nc;          // last staged group with s_pre <= slot
                     while (hi - lo > 1) {
                         const int mid = (lo + hi) >> 1;
                         if (s_pre[mid] <= slot) lo = mid;
@@ -1033,32 +999,39 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
                     const uint64_t iB = local / (uint64_t)nA, iA = local - iB * (uint64_t)nA;
                     const int ia = s_aoff[c] + (int)((int64_t)iA - s_ia0[c]);
                     const int ib = s_boff[c] + (int)((int64_t)iB - s_ib0[c]);
-                    prs[j] = s_pair[c];
-                    const PairDesc &Pd = pair_desc<ONE>(bv, prs[j]);
-                    double alo[4], ahi[4], blo[4], bhi[4];
+                    const uint64_t ca = s_ec[ia];
+                    if (ca == s_ec[ib]) {
+                        prs[j] = ONE ? 0 : s_ep[ia];
+                        const PairDesc &Pd = pair_desc<ONE>(bv, prs[j]);
+                        double alo[4], ahi[4], blo[4], bhi[4];
 #pragma unroll
-                    for (int d = 0; d < 4; ++d) {
-                        alo[d] = s_box[d][ia]; ahi[d] = s_box[4 + d][ia];
-                        blo[d] = s_box[d][ib]; bhi[d] = s_box[4 + d][ib];
+                        for (int d = 0; d < 4; ++d) {
+                            alo[d] = s_box[d][ia]; ahi[d] = s_box[4 + d][ia];
+                            blo[d] = s_box[d][ib]; bhi[d] = s_box[4 + d][ib];
+                        }
+                        keep = enum_pair<ONE>(Pd, ca - Pd.cell_base, alo, ahi, blo, bhi);
+                        packed[j] = ((uint64_t)(uint32_t)s_t[ia] << 32) | (uint32_t)s_t[ib];
                     }
-                    keep = enum_pair<ONE>(Pd, s_cell[c], alo, ahi, blo, bhi);
-                    packed[j] = ((uint64_t)(uint32_t)s_t[ia] << 32) | (uint32_t)s_t[ib];
                 } else {
                     const int64_t c = last_le<int64_t>(pstart, ncells, slot);
                     const CellRec cr = cells[c];
                     const uint64_t local = (uint64_t)(slot - pstart[c]);
                     const uint64_t iB = local / (uint64_t)cr.nA;
                     const uint64_t iA = local - iB * (uint64_t)cr.nA;
-                    const uint64_t kA = keys[cr.start + (int64_t)iA];
+                    const int64_t eA = cr.start + (int64_t)iA;
+                    const uint64_t kA = keys[eA];
                     const uint64_t kB = keys[cr.start + cr.nA + (int64_t)iB];
-                    prs[j] = cr.pair;
-                    const PairDesc &Pd = pair_desc<ONE>(bv, prs[j]);
-                    const int32_t ta = (int32_t)(kA & bv.kl.tmask), tb = (int32_t)(kB & bv.kl.tmask);
-                    double alo[4], ahi[4], blo[4], bhi[4];
-                    tri_box(Pd.A, ta, alo, ahi);
-                    tri_box(Pd.B, tb, blo, bhi);
-                    keep = enum_pair<ONE>(Pd, (kA >> bv.kl.cell_shift) - Pd.cell_base, alo, ahi, blo, bhi);
-                    packed[j] = ((uint64_t)(uint32_t)ta << 32) | (uint32_t)tb;
+                    const uint64_t ca = kA >> sh;
+                    if (ca == (kB >> sh)) {
+                        prs[j] = entry_pair<ONE>(kpair, eA);
+                        const PairDesc &Pd = pair_desc<ONE>(bv, prs[j]);
+                        const int32_t ta = (int32_t)(kA & bv.kl.tmask), tb = (int32_t)(kB & bv.kl.tmask);
+                        double alo[4], ahi[4], blo[4], bhi[4];
+                        tri_box(Pd.A, ta, alo, ahi);
+                        tri_box(Pd.B, tb, blo, bhi);
+                        keep = enum_pair<ONE>(Pd, ca - Pd.cell_base, alo, ahi, blo, bhi);
+                        packed[j] = ((uint64_t)(uint32_t)ta << 32) | (uint32_t)tb;
+                    }
                 }
             }
             keepm |= (uint32_t)keep << j;
@@ -1134,7 +1107,33 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
                 if (so) atomicAdd((unsigned long long *)&stats->n_outside, (unsigned long long)so);
             }
         }
+        // exact statistics of the groups that start in this chunk: a group of
+        // one cell adds the cell and nA * nB slots; the groups of several
+        // cells are listed and counted by the whole block
+        if (threadIdx.x == 0) s_nmix = 0;
         __syncthreads();
+        for (int64_t c = c0 + threadIdx.x; c < c0 + nc; c += BLOCK) {
+            if (pstart[c] < S0) continue;
+            const CellRec cr = cells[c];
+            if (mix[cr.h]) {
+                s_u.c.pair[atomicAdd(&s_nmix, 1u)] = (int32_t)(c - c0);
+            } else {
+                xc += 1;
+                xs += (unsigned long long)cr.nA * (unsigned long long)cr.nB;
+            }
+        }
+        __syncthreads();
+        for (uint32_t k = 0; k < s_nmix; ++k) {
+            const CellRec cr = cells[c0 + s_u.c.pair[k]];
+            group_stats(keys, cr, sh, s_ec, xc, xs);
+        }
+        __syncthreads();
+    }
+    const unsigned long long sc = block_sum(xc, s_st), ss = block_sum(xs, s_st);
+    if (threadIdx.x == 0) {
+        if (sc) atomicAdd((unsigned long long *)&stats->n_cells, sc);
+        if (ss) atomicAdd((unsigned long long *)&stats->n_slots, ss);
+    }
     }
 }
 
@@ -1270,10 +1269,9 @@ struct Geometry {
 
 struct Layout {
     int64_t ent_cap, cand_cap, hits_cap;
-    RadixPlan rp;
-    size_t o_flags, o_bits, o_part, o_rng, o_keys, o_alt, o_sort, o_cstat, o_ctrs, o_bounds, o_cells, o_pstart,
-        o_cand, o_cpair, o_htmp, o_hkeys, o_halt, o_misc, o_desc, o_toff, o_cbase, total;
-    int64_t n_kblocks, cell_cap;
+    size_t o_flags, o_both, o_grp, o_own, o_mix, o_gstat, o_ctrs, o_part, o_rng, o_ent, o_epair, o_sorted, o_spair,
+        o_cells, o_pstart, o_htmp, o_hkeys, o_halt, o_misc, o_desc, o_toff, o_cbase, total;
+    int64_t n_kblocks, cell_cap, n_fwords, n_cwords, n_gtiles;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -1327,6 +1325,10 @@ int geometry(int64_t n_pairs, const ms_mesh *const *A, const ms_mesh *const *B, 
     if (G.pb + G.tbA + G.tbB > 64) return fail(MS_E_KEYBITS, "search: pair + triangle indices exceed 64 bits");
     int lg = bits_for((uint64_t)(G.n_tri > 0 ? G.n_tri : 1)) + 2;
     G.bm_log2 = lg < 12 ? 12 : (lg > 25 ? 25 : lg);
+    int req = 0;     // a table size asked for by any pair (the largest)
+    for (int64_t i = 0; i < n_pairs; ++i)
+        if (prm[i].table_log2 > req) req = prm[i].table_log2;
+    if (req > 0) G.bm_log2 = req < 8 ? 8 : (req > 25 ? 25 : req);
     G.bc_log2 = G.bm_log2 - 3;
     return MS_OK;
 }
@@ -1338,24 +1340,27 @@ void layout(const Geometry &G, Layout &L)
 {
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
-    L.rp = radix_plan(G.tb, G.cell_bits + 1, L.ent_cap);
+    const int64_t n_ids = (int64_t)1 << G.bm_log2;       // groups: fine hashed cells
     L.n_kblocks = ceil_div(G.n_tri > 0 ? G.n_tri : 1, KEYS_TILE);
     L.cell_cap = L.ent_cap / 2 + 1;
-    const int64_t tiles = L.rp.tiles_cap;
+    L.n_fwords = n_ids / 32;
+    L.n_cwords = ((int64_t)1 << G.bc_log2) / 32;
+    L.n_gtiles = ceil_div(L.n_fwords, GROUP_WORDS);
     L.o_flags = take(flag_bytes(G));
-    L.o_bits = take(flag_bytes(G) / 8);
+    L.o_both = take((size_t)(L.n_fwords + L.n_cwords) * 4);
+    L.o_grp = take((size_t)n_ids * 8);
+    L.o_own = take((size_t)n_ids * 8);
+    L.o_mix = take((size_t)n_ids * 4);
+    L.o_gstat = take((size_t)L.n_gtiles * 16);
+    L.o_ctrs = take(64);
     L.o_part = take((size_t)MAX_GRID * 16);
     L.o_rng = take((size_t)(G.n_tri + 1) * 8);
-    L.o_keys = take((size_t)(L.ent_cap + 1) * 8);
-    L.o_alt = take((size_t)(L.ent_cap + 1) * 8);
-    L.o_sort = take(radix_ws_bytes(L.rp));
-    L.o_cstat = take((size_t)tiles * 24);
-    L.o_ctrs = take(64);
-    L.o_bounds = take((size_t)(L.ent_cap + 2) * 8);
+    L.o_ent = take((size_t)(L.ent_cap + 1) * 8);
+    L.o_epair = take((size_t)(L.ent_cap + 1) * 4);
+    L.o_sorted = take((size_t)(L.ent_cap + 1) * 8);
+    L.o_spair = take((size_t)(L.ent_cap + 1) * 4);
     L.o_cells = take((size_t)L.cell_cap * sizeof(CellRec));
     L.o_pstart = take((size_t)(L.cell_cap + 1) * 8);
-    L.o_cand = take(8);      // (candidates are stored only into the caller's buffer)
-    L.o_cpair = take(4);
     L.o_htmp = take((size_t)(L.hits_cap > 0 ? L.hits_cap : 1) * sizeof(hit_t));
     L.o_hkeys = take((size_t)(L.hits_cap + 1) * 8);
     L.o_halt = take((size_t)(L.hits_cap + 1) * 8);
@@ -1429,83 +1434,69 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
 {
     int rc;
     uint8_t *flags = (uint8_t *)(ws + L.o_flags);
+    uint32_t *both = (uint32_t *)(ws + L.o_both);
+    uint64_t *grp = (uint64_t *)(ws + L.o_grp);
+    uint64_t *own = (uint64_t *)(ws + L.o_own);
+    uint32_t *mix = (uint32_t *)(ws + L.o_mix);
+    uint64_t *gstat = (uint64_t *)(ws + L.o_gstat);
+    uint32_t *ctrs = (uint32_t *)(ws + L.o_ctrs);     // [1] k_groups tile counter
+    unsigned long long *n_keys = (unsigned long long *)(ctrs + 4);   // entries reserved by k_keys
     unsigned long long *mpart = (unsigned long long *)(ws + L.o_part);
     uint64_t *rng = (uint64_t *)(ws + L.o_rng);
-    uint64_t *keys = (uint64_t *)(ws + L.o_keys);
-    uint64_t *alt = (uint64_t *)(ws + L.o_alt);
-    uint64_t *cstat = (uint64_t *)(ws + L.o_cstat);
-    uint32_t *ctrs = (uint32_t *)(ws + L.o_ctrs);     // [0] k_cells_scan, [1] k_cells_keep tile counters
-    unsigned long long *n_keys = (unsigned long long *)(ctrs + 4);   // entries reserved by k_keys
-    uint32_t *bits = (uint32_t *)(ws + L.o_bits);
-    uint64_t *bounds = (uint64_t *)(ws + L.o_bounds);
+    uint64_t *ent = (uint64_t *)(ws + L.o_ent);
+    int32_t *epair = (int32_t *)(ws + L.o_epair);
+    uint64_t *sorted = (uint64_t *)(ws + L.o_sorted);
+    int32_t *spair = (int32_t *)(ws + L.o_spair);
     CellRec *cells = (CellRec *)(ws + L.o_cells);
     int64_t *pstart = (int64_t *)(ws + L.o_pstart);
     hit_t *htmp = (hit_t *)(ws + L.o_htmp);
     uint64_t *hkeys = (uint64_t *)(ws + L.o_hkeys);
     uint64_t *halt = (uint64_t *)(ws + L.o_halt);
-    int64_t *misc = (int64_t *)(ws + L.o_misc);       // [1] cells (all)
-    RadixPlan rp = L.rp;
-    radix_ws_carve(rp, ws + L.o_sort);
-    const int R = 1 << rp.rb;
+    int64_t *misc = (int64_t *)(ws + L.o_misc);       // [1..2] kept groups and their slots
 
-    // 1. clear: counters, flags, the keys' look-back words, sort histograms
-    //    and tile counters, the other tile counters (and, with no sort pass,
-    //    the cell scans' words)
+    // 1. clear: stats, occupancy bytes, look-back words, counters
     ClearSpec cs;
     cs.stats = stats;
-    cs.flags = (uint64_t *)flags;
-    cs.flag_words = (int64_t)(flag_bytes(G) / 8);
-    cs.kstat = rp.passes == 0 ? cstat : nullptr;
-    cs.kstat_words = rp.passes == 0 ? 3 * rp.tiles_cap : 0;
-    cs.hist = rp.hist;
-    cs.hist_words = (int64_t)rp.passes * R;
-    cs.ctrs = rp.tile_ctr;
-    cs.ctr_words = rp.passes;
-    cs.ctrs2 = ctrs;
-    cs.ctr2_words = 16;
-    MS_LAUNCH("k_prepare", k_prepare, dim3(grid_for(cs.flag_words, 1024)), dim3(BLOCK), 0, st, cs);
+    cs.flags = (uint4 *)flags;
+    cs.flag_vecs = (int64_t)(flag_bytes(G) / 16);
+    cs.w[0] = gstat;
+    cs.n[0] = 2 * L.n_gtiles;
+    cs.w[1] = (uint64_t *)ctrs;
+    cs.n[1] = 8;
+    cs.w[2] = nullptr;
+    cs.n[2] = 0;
+    MS_LAUNCH("k_prepare", k_prepare, dim3(grid_for(cs.flag_vecs, 1024)), dim3(BLOCK), 0, st, cs);
     const unsigned g_tri = grid_for(G.n_tri);
     MS_LAUNCH("k_mark", k_mark<ONE>, dim3(g_tri), dim3(BLOCK), 0, st, bv, flags, rng, mpart);
-    const int64_t n_words = (int64_t)(flag_bytes(G) / 32);
-    MS_LAUNCH("k_pack", k_pack, dim3(grid_for(n_words, 4096)), dim3(BLOCK), 0, st, flags, bits, n_words);
+    MS_LAUNCH("k_pack", k_pack, dim3(grid_for(L.n_fwords + L.n_cwords, 4096)), dim3(BLOCK), 0, st, flags, G.bm_log2,
+              G.bc_log2, both, grp, mix, L.n_fwords, L.n_cwords);
     KeysOut ko;
-    ko.keys = keys;
+    ko.ent = ent;
+    ko.epair = epair;
     ko.cap = L.ent_cap;
     ko.n_keys = n_keys;
-    ko.hist = rp.hist;
-    ko.sort_status0 = rp.status;
-    ko.passes = rp.passes;
-    ko.rb = rp.rb;
-    ko.lo_bit = rp.lo_bit;
+    ko.grp = (uint32_t *)grp;
+    ko.own = own;
     ko.stats = stats;
-    MS_LAUNCH("k_keys", k_keys<ONE>, dim3((unsigned)L.n_kblocks), dim3(BLOCK), 0, st, bv, bits, rng, ko);
-    MS_HIP(hipGetLastError());
-    uint64_t *sorted = keys;
-    if ((rc = radix_sort(rp, keys, alt, (const int64_t *)n_keys, cstat, 3, st, &sorted))) return rc;
-    {
-        const int64_t g = rp.tiles_cap < 1024 ? rp.tiles_cap : 1024;
-        CellsScanOut so;
-        so.bounds = bounds;
-        so.n_all = misc + 1;
-        so.stat = cstat;
-        so.tile_ctr = ctrs;
-        so.stats = stats;
-        so.cap = L.ent_cap;
-        so.mark_partial = mpart;
-        so.n_mark_partial = (int)g_tri;
-        MS_LAUNCH("k_cells_scan", k_cells_scan<ONE>, dim3((unsigned)g), dim3(BLOCK), 0, st, bv, sorted,
-                  (const int64_t *)n_keys, so);
-        CellsOut co;
-        co.cells = cells;
-        co.pstart = pstart;
-        co.stat = cstat;
-        co.tile_ctr = ctrs + 1;
-        co.stats = stats;
-        MS_LAUNCH("k_cells_keep", k_cells_keep<ONE>, dim3((unsigned)g), dim3(BLOCK), 0, st, bv, sorted, bounds,
-                  misc + 1, co);
-    }
-    MS_LAUNCH("k_enum", k_enum<ONE>, dim3(MAX_GRID), dim3(BLOCK), 0, st, bv, sorted, cells, pstart, stats, cand_user,
-              (int32_t *)nullptr, cand_user ? cand_cap : (int64_t)0, htmp, hkeys, hits_cap);
+    MS_LAUNCH("k_keys", k_keys<ONE>, dim3((unsigned)L.n_kblocks), dim3(BLOCK), 0, st, bv, both, rng, ko);
+    GroupsOut go;
+    go.both = both;
+    go.grp = grp;
+    go.n_fwords = L.n_fwords;
+    go.cells = cells;
+    go.pstart = pstart;
+    go.kept = misc + 1;
+    go.stat = gstat;
+    go.tile_ctr = ctrs + 1;
+    go.stats = stats;
+    go.n_keys = n_keys;
+    go.mark_partial = mpart;
+    go.n_mark_partial = (int)g_tri;
+    MS_LAUNCH("k_groups", k_groups, dim3((unsigned)(L.n_gtiles < 1024 ? L.n_gtiles : 1024)), dim3(BLOCK), 0, st, go);
+    MS_LAUNCH("k_scatter", k_scatter<ONE>, dim3(grid_for(L.ent_cap)), dim3(BLOCK), 0, st, ent, epair, n_keys,
+              L.ent_cap, (uint32_t *)grp, own, mix, G.bm_log2, G.tb + 1, G.tb, sorted, spair);
+    MS_LAUNCH("k_enum", k_enum<ONE>, dim3(ENUM_GRID), dim3(BLOCK), 0, st, bv, sorted, spair, cells, pstart, misc + 1,
+              mix, stats, cand_user, (int32_t *)nullptr, cand_user ? cand_cap : (int64_t)0, htmp, hkeys, hits_cap);
     MS_HIP(hipGetLastError());
     if (hits_cap > 0) {
         if (hits_cap <= HITS_TINY) {

@@ -37,11 +37,11 @@ def assert_hits_equal(got, want):
         assert np.max(np.abs(got["X"] - want["X"])) <= TOL
 
 
-def gpu_search(ms, A, B, grid, flags=None, hits_cap=1 << 14, cand_cap=1 << 20):
+def gpu_search(ms, A, B, grid, flags=None, hits_cap=1 << 14, cand_cap=1 << 20, table_log2=0):
     lo, hi, inv, n = grid
     f = ms.MS_SEARCH_CANDIDATES if flags is None else flags
     ga, gb = ms.Mesh.from_synth(A), ms.Mesh.from_synth(B)
-    p = ms.make_params(lo, inv, n, f)
+    p = ms.make_params(lo, inv, n, f, table_log2)
     s = ms.Searcher(ga, gb, p, hits_cap=hits_cap, cand_cap=cand_cap)
     s.run()
     hits, st, cand = s.results()
@@ -112,6 +112,23 @@ def test_grid_cfg1_bench_configuration(ms, hits_cap):
     hits, st, cand = gpu_search(ms, A, B, grid, flags=0, hits_cap=hits_cap)
     assert cand is None
     check_against(ref, hits, st, None, ref)
+
+
+@pytest.mark.parametrize("seed,kappa,table_log2", [(0, 1.0, 8), (1, 0.5, 9), (2, 2.0, 10), (0, 1.5, 12)])
+def test_small_hash_tables_share_groups(ms, seed, kappa, table_log2):
+    """Hashed occupancy tables far smaller than the number of occupied
+    cells: many cells share a group (several cells per hashed cell), so the
+    enumeration must pair only entries of one cell and the statistics must
+    separate the cells.  Everything matches the oracle exactly."""
+    A, B = synth.plain_pair(64, 64, seed)
+    ref = oracle.bruteforce(A, B)
+    grid = oracle.default_grid([A, B], kappa)
+    gref = oracle.grid_search(A, B, grid[0], grid[2], grid[3])
+    hits, st, cand = gpu_search(ms, A, B, grid, table_log2=table_log2)
+    check_against(ref, hits, st, cand, gref)
+    assert st["n_groups"] >= 1 and st["n_group_slots"] >= st["n_slots"]
+    if table_log2 <= 9:
+        assert st["n_group_slots"] > st["n_slots"]      # cells did share groups
 
 
 def test_grid_invariance_world_shift_and_swap(ms):
