@@ -53,7 +53,7 @@ def algorithmic_bytes(kernel: str, st: dict, mesh_sizes) -> float | None:
     return table.get(kernel)
 
 
-SEARCH_SOURCES = ("mesh.hip", "sort_scan.hip", "search.hip", "predicate.hpp", "ms_internal.hpp")
+SEARCH_SOURCES = ("mesh.hip", "small_sort.hip", "search.hip", "predicate.hpp", "ms_internal.hpp")
 
 
 def source_digest() -> str:

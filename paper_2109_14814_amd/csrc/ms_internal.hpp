@@ -173,49 +173,13 @@ inline int bits_for(uint64_t x)   // bits needed to store values 0..x
     return b;
 }
 
-// -------------------------------------------------- internal sort/scan API
-
-// LSD radix sort of 64-bit keys on bits [lo_bit, lo_bit + n_bits), stable,
-// with RB-bit digits (RB in 8..10 chosen for the fewest passes).  Before the
-// first pass the caller must have: accumulated the digit histograms of every
-// pass into hist, cleared the tile counters, and cleared the pass-0
-// look-back words of the tiles in use; each pass clears the next pass's
-// words itself.
-constexpr int SORT_TILE_KEYS = 4096;
-
-struct RadixPlan {
-    int lo_bit, n_bits, passes, rb;
-    int64_t cap, tiles_cap;
-    uint32_t *hist;       // passes x 2^rb
-    uint32_t *status;     // passes x tiles_cap x 2^rb
-    uint32_t *tile_ctr;   // passes
-};
-
-RadixPlan radix_plan(int lo_bit, int n_bits, int64_t cap);
-size_t radix_ws_bytes(const RadixPlan &p);
-void radix_ws_carve(RadixPlan &p, void *base);
-// The key count is min(*n_dev, p.cap).  Sorted keys end in *result (keys or
-// alt).  In its last pass each block
-// also clears extra[tile * extra_per_tile ...] (a later kernel's words).
-int radix_sort(const RadixPlan &p, uint64_t *keys, uint64_t *alt, const int64_t *n_dev, uint64_t *extra,
-               int extra_per_tile, hipStream_t st, uint64_t **result);
+// ------------------------------------------------------ internal sort API
 
 // Sort of distinct 64-bit keys in two kernels: chunks of 4096 sorted in LDS,
 // then every key placed by its rank in the other chunks (cost grows with
 // n^2 / 4096; meant for small n such as hit lists).  n from device memory.
 int sort_unique_small(const uint64_t *in, uint64_t *tmp, uint64_t *out, const int64_t *n_dev, int64_t cap,
                       int lo_bit, int n_bits, hipStream_t st);   // n = min(*n_dev, cap)
-
-// Exclusive scan of n 32-bit counts into 64-bit offsets; out[n] = total.
-// n from the host; total also added to *total_dev if non-NULL.
-size_t scan_ws_bytes();
-int scan_u32_to_i64(const uint32_t *in, int64_t *out, int64_t n, int64_t *total_dev, void *ws, hipStream_t st);
-// Exclusive scan of a device-sized (*n_dev) array of int64, cap on host;
-// out[n] = total, also stored to *total_dev.
-int scan_i64_dev(const int64_t *in, int64_t *out, const int64_t *n_dev, int64_t cap, int64_t *total_dev,
-                 void *ws, hipStream_t st);
-
-int launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st);
 
 // ------------------------------------------------------------- profiling
 

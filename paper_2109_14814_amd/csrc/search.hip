@@ -825,14 +825,50 @@ MS_D bool enum_pair(const PairDesc &Pd, uint64_t cell, const double alo[4], cons
                     const double bhi[4])
 {
     bool ov = true;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) ov = ov && (alo[d] <= bhi[d]) && (blo[d] <= ahi[d]);
+    if (!ov) return false;
     int64_t h[4];
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
-        ov = ov && (alo[d] <= bhi[d]) && (blo[d] <= ahi[d]);
         const double m = alo[d] > blo[d] ? alo[d] : blo[d];
         h[d] = cell_of(m, Pd.g.wlo[d], Pd.g.inv, Pd.g.n[d]);
     }
-    return ov && (uint64_t)cell_linear(h, Pd.g.n) == cell;
+    return (uint64_t)cell_linear(h, Pd.g.n) == cell;
+}
+
+// Bounds of local cell `cell` in t = (x - wlo) * inv per axis, such that
+// cell_of(x) == that axis's coordinate exactly when lo <= t and not t >= hi:
+// lo = -inf on the first cell, hi = NaN on the last (no upper bound), else
+// the cell's integer edges (floor(t) == c <=> c <= t < c + 1 in FP64).
+MS_D void home_bounds(const GridView &g, uint64_t cell, double (*gb)[ENUM_CELLS], int k)
+{
+    int64_t c[4];
+    uint64_t r = cell;
+#pragma unroll
+    for (int d = 3; d >= 0; --d) {
+        c[d] = (int64_t)(r % (uint64_t)g.n[d]);
+        r /= (uint64_t)g.n[d];
+    }
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        gb[d][k] = c[d] == 0 ? -INFINITY : (double)c[d];
+        gb[4 + d][k] = c[d] == g.n[d] - 1 ? (double)NAN : (double)(c[d] + 1);
+    }
+}
+
+// Slot offset inside a group -> (row iB, column iA) for rows of nA; the
+// 32-bit division is much cheaper and covers every group below 2^32 slots.
+MS_D void split_slot(uint64_t local, uint32_t nA, uint64_t &iB, uint64_t &iA)
+{
+    if (local <= 0xffffffffull) {
+        const uint32_t l = (uint32_t)local, q = l / nA;
+        iB = q;
+        iA = l - q * nA;
+    } else {
+        iB = local / nA;
+        iA = local - iB * nA;
+    }
 }
 
 template <bool ONE>
@@ -899,6 +935,9 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
     __shared__ unsigned long long s_kbase;
     __shared__ unsigned long long s_st[BLOCK / WAVE];
     __shared__ uint32_t s_nmix;
+    __shared__ uint64_t s_gcell[ENUM_CELLS];
+    __shared__ double s_gb[8][ENUM_CELLS];            // per staged group: t-bounds of its cell
+    __shared__ double s_gw[ONE ? 1 : 5][ENUM_CELLS];  // per staged group: wlo, inv (batch)
     unsigned long long xc = 0, xs = 0;      // exact cells and slots
     const int64_t ncells = kept[0];
     const int64_t P = kept[1];
@@ -917,15 +956,22 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
         if (threadIdx.x == 0) {
             s_c0 = last_le<int64_t>(pstart, ncells, S0);
             s_c1 = last_le<int64_t>(pstart, ncells, S1 - 1);
+            s_nmix = 0;
         }
         __syncthreads();
         const int64_t c0 = s_c0, nc = s_c1 - s_c0 + 1;
         // the rows of every touched group that the chunk covers, and the entries they need
         uint32_t need = 0;
+        bool first_here = false;     // the group's first slot is in this chunk (it is counted here)
+        uint32_t mixv = 0;
+        uint64_t gslots = 0;
         if (nc <= ENUM_CELLS && threadIdx.x < nc) {
             const int64_t c = c0 + threadIdx.x;
             const CellRec cr = cells[c];
             const int64_t p0 = pstart[c], p1 = pstart[c + 1];
+            first_here = p0 >= S0;
+            if (first_here) mixv = mix[cr.h];      // used after the narrow phase
+            gslots = (uint64_t)cr.nA * (uint64_t)cr.nB;
             const int64_t l0 = (S0 > p0 ? S0 : p0) - p0, l1 = (S1 < p1 ? S1 : p1) - p0;
             const int64_t ib0 = l0 / cr.nA, ib1 = (l1 - 1) / cr.nA;
             int64_t ia0 = 0, ia1 = cr.nA;
@@ -975,6 +1021,22 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
                 if (!ONE) s_ep[i] = p;
             }
             __syncthreads();
+            // per group: the cell of its first staged entry (every entry's
+            // cell, unless the group holds several) and that cell's bounds
+            // in the grid's coordinate t = (x - wlo) * inv
+            if (threadIdx.x < nc) {
+                const int i0 = s_aoff[threadIdx.x];
+                const uint64_t gc = s_ec[i0];
+                const PairDesc &Pd = pair_desc<ONE>(bv, ONE ? 0 : s_ep[i0]);
+                home_bounds(Pd.g, gc - Pd.cell_base, s_gb, threadIdx.x);
+                s_gcell[threadIdx.x] = gc;
+                if (!ONE) {
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) s_gw[d][threadIdx.x] = Pd.g.wlo[d];
+                    s_gw[4][threadIdx.x] = Pd.g.inv;
+                }
+            }
+            __syncthreads();
         }
         uint64_t packed[ENUM_ITEMS];
         int32_t prs[ENUM_ITEMS];
@@ -995,29 +1057,47 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
                     }
                     const int c = lo;
                     const int32_t nA = s_nA[c];
-                    const uint64_t local = (uint64_t)(slot - s_pre[c]);
-                    const uint64_t iB = local / (uint64_t)nA, iA = local - iB * (uint64_t)nA;
+                    uint64_t iB, iA;
+                    split_slot((uint64_t)(slot - s_pre[c]), (uint32_t)nA, iB, iA);
                     const int ia = s_aoff[c] + (int)((int64_t)iA - s_ia0[c]);
                     const int ib = s_boff[c] + (int)((int64_t)iB - s_ib0[c]);
                     const uint64_t ca = s_ec[ia];
                     if (ca == s_ec[ib]) {
                         prs[j] = ONE ? 0 : s_ep[ia];
-                        const PairDesc &Pd = pair_desc<ONE>(bv, prs[j]);
                         double alo[4], ahi[4], blo[4], bhi[4];
+                        bool ov = true;
 #pragma unroll
                         for (int d = 0; d < 4; ++d) {
                             alo[d] = s_box[d][ia]; ahi[d] = s_box[4 + d][ia];
                             blo[d] = s_box[d][ib]; bhi[d] = s_box[4 + d][ib];
+                            ov = ov && (alo[d] <= bhi[d]) && (blo[d] <= ahi[d]);
                         }
-                        keep = enum_pair<ONE>(Pd, ca - Pd.cell_base, alo, ahi, blo, bhi);
+                        if (ov) {
+                            if (ca == s_gcell[c]) {
+                                // home cell = the group's cell: per axis, the
+                                // max of the lower corners falls in its bounds
+                                bool in = true;
+#pragma unroll
+                                for (int d = 0; d < 4; ++d) {
+                                    const double m = alo[d] > blo[d] ? alo[d] : blo[d];
+                                    const double wl = ONE ? bv.p0.g.wlo[d] : s_gw[d][c];
+                                    const double iv = ONE ? bv.p0.g.inv : s_gw[4][c];
+                                    const double t = (m - wl) * iv;
+                                    in = in && (t >= s_gb[d][c]) && !(t >= s_gb[4 + d][c]);
+                                }
+                                keep = in;
+                            } else {
+                                const PairDesc &Pd = pair_desc<ONE>(bv, prs[j]);
+                                keep = enum_pair<ONE>(Pd, ca - Pd.cell_base, alo, ahi, blo, bhi);
+                            }
+                        }
                         packed[j] = ((uint64_t)(uint32_t)s_t[ia] << 32) | (uint32_t)s_t[ib];
                     }
                 } else {
                     const int64_t c = last_le<int64_t>(pstart, ncells, slot);
                     const CellRec cr = cells[c];
-                    const uint64_t local = (uint64_t)(slot - pstart[c]);
-                    const uint64_t iB = local / (uint64_t)cr.nA;
-                    const uint64_t iA = local - iB * (uint64_t)cr.nA;
+                    uint64_t iB, iA;
+                    split_slot((uint64_t)(slot - pstart[c]), (uint32_t)cr.nA, iB, iA);
                     const int64_t eA = cr.start + (int64_t)iA;
                     const uint64_t kA = keys[eA];
                     const uint64_t kB = keys[cr.start + cr.nA + (int64_t)iB];
@@ -1110,16 +1190,26 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
         // exact statistics of the groups that start in this chunk: a group of
         // one cell adds the cell and nA * nB slots; the groups of several
         // cells are listed and counted by the whole block
-        if (threadIdx.x == 0) s_nmix = 0;
         __syncthreads();
-        for (int64_t c = c0 + threadIdx.x; c < c0 + nc; c += BLOCK) {
-            if (pstart[c] < S0) continue;
-            const CellRec cr = cells[c];
-            if (mix[cr.h]) {
-                s_u.c.pair[atomicAdd(&s_nmix, 1u)] = (int32_t)(c - c0);
-            } else {
-                xc += 1;
-                xs += (unsigned long long)cr.nA * (unsigned long long)cr.nB;
+        if (nc <= ENUM_CELLS) {
+            if (first_here) {
+                if (mixv) {
+                    s_u.c.pair[atomicAdd(&s_nmix, 1u)] = (int32_t)threadIdx.x;
+                } else {
+                    xc += 1;
+                    xs += gslots;
+                }
+            }
+        } else {
+            for (int64_t c = c0 + threadIdx.x; c < c0 + nc; c += BLOCK) {
+                if (pstart[c] < S0) continue;
+                const CellRec cr = cells[c];
+                if (mix[cr.h]) {
+                    s_u.c.pair[atomicAdd(&s_nmix, 1u)] = (int32_t)(c - c0);
+                } else {
+                    xc += 1;
+                    xs += (unsigned long long)cr.nA * (unsigned long long)cr.nB;
+                }
             }
         }
         __syncthreads();
