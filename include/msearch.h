@@ -190,7 +190,11 @@ int search_workspace_size(const ms_mesh *A, const ms_mesh *B, const search_param
  * (Sec. 6.2.4), hits sorted by (triA, triB).
  *   ws_dev/ws_bytes: workspace from search_workspace_size (not shared with a
  *     concurrent call); cand_cap and hits_cap must not exceed the values the
- *     workspace was sized for.
+ *     workspace was sized for.  The workspace keeps state from one search to
+ *     the next (occupancy marks tagged with a search counter, so that no
+ *     clearing pass runs); results never depend on its contents, but zero it
+ *     once after allocation so that the work counters of its first search
+ *     (n_entries, n_groups, n_group_slots) carry no leftover marks.
  *   hits_dev/hits_cap: output records, sorted by (triA, triB).
  *   stats_dev: one search_stats_t in device memory, written by the search.
  *   cand_dev/cand_cap: with MS_SEARCH_CANDIDATES, receives C as packed

@@ -131,6 +131,13 @@ def _dev_bytes(n: int):
     return torch.empty(max(int(n), 1), dtype=torch.uint8, device="cuda")
 
 
+def _workspace(n: int):
+    """A search workspace, zeroed once so that the work counters of its
+    first search are not inflated by leftover occupancy marks."""
+    torch = _torch()
+    return torch.zeros(max(int(n), 1), dtype=torch.uint8, device="cuda")
+
+
 class Mesh:
     """A triangulated vertex grid resident in HBM (mesh_build).
 
@@ -227,7 +234,7 @@ class Searcher:
         _check(lib().search_workspace_size(self.A.handle, self.B.handle, C.byref(self.params), self.cand_cap,
                                            self.hits_cap, _stream(), C.byref(nb)))
         self.ws_bytes = int(nb.value)
-        self.ws = _dev_bytes(self.ws_bytes)
+        self.ws = _workspace(self.ws_bytes)
         self.hits = _dev_bytes(self.hits_cap * HIT_DTYPE.itemsize)
         want_cand = bool(self.params.flags & MS_SEARCH_CANDIDATES)
         self.cand = _dev_bytes(self.cand_cap * 8) if want_cand else None
@@ -381,7 +388,7 @@ class Batch:
                                   _stream(), C.byref(h), C.byref(nb)))
         self.handle = h
         self.ws_bytes = int(nb.value)
-        self.ws = _dev_bytes(self.ws_bytes)
+        self.ws = _workspace(self.ws_bytes)
         self.hits = _dev_bytes(self.hits_cap * HIT_DTYPE.itemsize)
 
     def run(self, use_graph: bool = True) -> None:

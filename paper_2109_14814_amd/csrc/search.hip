@@ -4,11 +4,11 @@
 // Every kernel reads its sizes from device memory, so one call queues a fixed
 // sequence of kernels with no host round trip (and can be captured in a HIP
 // graph):
-//   k_prepare     clear counters, occupancy bytes and look-back words
 //   k_mark        per triangle: its box from the vertices (Sec. 6.2.2), the
 //                 overlapped cells of its pair's grid (Sec. 6.2.1), one
-//                 occupancy byte per (hashed) cell and side, fine and coarse;
-//                 compact range
+//                 occupancy byte per (hashed) cell and side, fine and coarse,
+//                 holding the search's epoch value (no clearing between
+//                 searches); compact range; block 0 clears the counters
 //   k_pack        hashed cells occupied by both meshes as bit tables; each
 //                 such fine cell is a group, with a dense id (the set bits
 //                 before it, by a scan with decoupled look-back)
@@ -354,7 +354,7 @@ MS_D void publish_u64(uint64_t *w, uint64_t flag, uint64_t v)
     __hip_atomic_store(w, flag | v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <typename T>
+template <int NT = BLOCK, typename T>
 MS_D T block_sum(T v, T *s_tmp)
 {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -362,12 +362,12 @@ MS_D T block_sum(T v, T *s_tmp)
     if (lane_id() == 0) s_tmp[threadIdx.x / WAVE] = v;
     __syncthreads();
     T t = 0;
-    for (int i = 0; i < BLOCK / WAVE; ++i) t += s_tmp[i];
+    for (int i = 0; i < NT / WAVE; ++i) t += s_tmp[i];
     return t;
 }
 
-// Exclusive scan of one value per thread over the block; *total = sum.
-template <typename T>
+// Exclusive scan of one value per thread over the block (NT threads); *total = sum.
+template <int NT = BLOCK, typename T>
 MS_D T block_excl(T v, T *s_tmp, T *total)
 {
     const int lane = lane_id(), w = threadIdx.x / WAVE;
@@ -380,7 +380,7 @@ MS_D T block_excl(T v, T *s_tmp, T *total)
     if (lane == WAVE - 1) s_tmp[w] = x;
     __syncthreads();
     T add = 0, tot = 0;
-    for (int i = 0; i < BLOCK / WAVE; ++i) {
+    for (int i = 0; i < NT / WAVE; ++i) {
         T t = s_tmp[i];
         if (i < w) add += t;
         tot += t;
@@ -409,14 +409,30 @@ __global__ void __launch_bounds__(BLOCK) k_prepare(ClearSpec c)
         for (int64_t i = g0; i < c.n[k]; i += stride) c.w[k][i] = 0;
 }
 
+// Occupancy marks carry the search's epoch value v in 1..255 (the search
+// count mod 255, plus one), so that the tables need no clearing between
+// searches: a byte counts as set only when it holds v.  The search whose v
+// wraps back to 1 finds the tables cleared by the one before it.  A byte
+// left over from another use of the workspace can only add occupancy, which
+// adds work but never changes a result.
+MS_D uint8_t epoch_value(const uint64_t *epoch) { return (uint8_t)(*epoch % 255u + 1u); }
+
 // Occupancy: one byte per hashed global cell and side, set with plain stores
 // (all writers store the same value).  Stores each triangle's compact cell
-// range and per-block entry / non-finite totals.
+// range and per-block entry / non-finite totals.  Block 0 also clears the
+// search's counters.
 template <bool ONE>
-__global__ void __launch_bounds__(BLOCK) k_mark(BatchView bv, uint8_t *flags, uint64_t *rng,
-                                                unsigned long long *partial)
+__global__ void __launch_bounds__(BLOCK) k_mark(BatchView bv, uint8_t *flags, const uint64_t *epoch, uint64_t *rng,
+                                                unsigned long long *partial, ClearSpec c)
 {
     __shared__ unsigned long long s_tmp[BLOCK / WAVE];
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < (int)(sizeof(search_stats_t) / 8)) ((int64_t *)c.stats)[threadIdx.x] = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            for (int64_t i = threadIdx.x; i < c.n[k]; i += BLOCK) c.w[k][i] = 0;
+    }
+    const uint8_t v = epoch_value(epoch);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     unsigned long long all = 0, bad = 0;
     const size_t side_bytes = (size_t)1 << bv.bm_log2;
@@ -433,12 +449,12 @@ __global__ void __launch_bounds__(BLOCK) k_mark(BatchView bv, uint8_t *flags, ui
         all += (unsigned long long)range_count(r);
         uint8_t *mine = flags + (size_t)L.side * side_bytes;
         const uint64_t cb = P.cell_base;
-        for_cells(r, P.g.n, [&](uint64_t c) { mine[bm_hash(cb + c, bv.bm_log2)] = 1; });
+        for_cells(r, P.g.n, [&](uint64_t c) { mine[bm_hash(cb + c, bv.bm_log2)] = v; });
         CellRange rc;
         int64_t nc[4];
         coarse_of(r, P.g.n, rc, nc);
         uint8_t *cmine = flags + 2 * side_bytes + ((size_t)L.side << bv.bc_log2);
-        for_cells(rc, nc, [&](uint64_t c) { cmine[bm_hash(cb + c, bv.bc_log2)] = 1; });
+        for_cells(rc, nc, [&](uint64_t c) { cmine[bm_hash(cb + c, bv.bc_log2)] = v; });
     }
     all = block_sum(all, s_tmp);
     bad = block_sum(bad, s_tmp);
@@ -448,8 +464,8 @@ __global__ void __launch_bounds__(BLOCK) k_mark(BatchView bv, uint8_t *flags, ui
     }
 }
 
-// 32 occupancy bytes -> one word of flags.
-MS_D uint32_t byte_mask(const uint8_t *f)
+// 32 occupancy bytes -> one word of flags (bytes equal to v).
+MS_D uint32_t byte_mask(const uint8_t *f, uint32_t v)
 {
     const uint4 *p = reinterpret_cast<const uint4 *>(f);
     const uint4 a = p[0], b = p[1];
@@ -458,22 +474,24 @@ MS_D uint32_t byte_mask(const uint8_t *f)
 #pragma unroll
     for (int i = 0; i < 8; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) m |= (uint32_t)(((q[i] >> (8 * j)) & 0xffu) != 0) << (4 * i + j);
+        for (int j = 0; j < 4; ++j) m |= (uint32_t)(((q[i] >> (8 * j)) & 0xffu) == v) << (4 * i + j);
     return m;
 }
 
 // The hashed cells that both meshes occupy, as bit tables (fine, then
 // coarse): the AND of the two sides' occupancy bytes.  Every set fine bit is
 // a cell group, whose entry counters and several-cells flag are cleared here.
-__global__ void __launch_bounds__(BLOCK) k_pack(const uint8_t *flags, int bm_log2, int bc_log2, uint32_t *both,
-                                                uint64_t *grp, uint32_t *mix, int64_t n_fwords, int64_t n_cwords)
+__global__ void __launch_bounds__(BLOCK) k_pack(const uint8_t *flags, const uint64_t *epoch, int bm_log2, int bc_log2,
+                                                uint32_t *both, uint64_t *grp, uint32_t *mix, int64_t n_fwords,
+                                                int64_t n_cwords)
 {
+    const uint32_t v = epoch_value(epoch);
     const size_t side = (size_t)1 << bm_log2, cside = (size_t)1 << bc_log2;
     const int64_t n = n_fwords + n_cwords;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < n; w += stride) {
         if (w < n_fwords) {
-            uint32_t m = byte_mask(flags + 32 * w) & byte_mask(flags + side + 32 * w);
+            uint32_t m = byte_mask(flags + 32 * w, v) & byte_mask(flags + side + 32 * w, v);
             both[w] = m;
             while (m) {
                 const int64_t h = 32 * w + __builtin_ctz(m);
@@ -483,7 +501,7 @@ __global__ void __launch_bounds__(BLOCK) k_pack(const uint8_t *flags, int bm_log
             }
         } else {
             const uint8_t *c = flags + 2 * side + 32 * (w - n_fwords);
-            both[w] = byte_mask(c) & byte_mask(c + cside);
+            both[w] = byte_mask(c, v) & byte_mask(c + cside, v);
         }
     }
 }
@@ -635,6 +653,7 @@ struct GroupsOut {
     const unsigned long long *n_keys;
     const unsigned long long *mark_partial;
     int n_mark_partial;
+    uint64_t *epoch;          // advanced here (the occupancy tables are no longer read)
 };
 
 __global__ void __launch_bounds__(BLOCK) k_groups(GroupsOut o)
@@ -652,6 +671,7 @@ __global__ void __launch_bounds__(BLOCK) k_groups(GroupsOut o)
         all = block_sum(all, (unsigned long long *)s_tk);
         bad = block_sum(bad, (unsigned long long *)s_tp);
         if (threadIdx.x == 0) {
+            *o.epoch += 1;
             o.stats->n_entries = (int64_t)*o.n_keys;
             o.stats->n_entries_all = (int64_t)all;
             o.stats->n_nonfinite = (int64_t)bad;
@@ -747,13 +767,16 @@ __global__ void __launch_bounds__(BLOCK) k_groups(GroupsOut o)
 // Entries to their group's range: the group's cursor of the entry's side
 // gives the position (A entries first).  Entries of groups holding one mesh
 // only are dropped.  An entry whose cell differs from its group's sample
-// flags the group as holding several cells.
+// flags the group as holding several cells.  When the next search's epoch
+// value wraps to 1, the occupancy tables are cleared here.
 template <bool ONE>
 __global__ void __launch_bounds__(BLOCK) k_scatter(const uint64_t *ent, const int32_t *epair,
                                                    const unsigned long long *n_keys, int64_t cap, uint32_t *grp,
                                                    const uint64_t *own, uint32_t *mix, int bm_log2, int cell_shift,
-                                                   int tb, uint64_t *out, int32_t *opair)
+                                                   int tb, uint64_t *out, int32_t *opair, const uint64_t *epoch,
+                                                   uint4 *flags, int64_t flag_vecs)
 {
+    const uint64_t ep = *epoch;                 // (read early, used last)
     const int64_t nk = (int64_t)*n_keys;
     const int64_t n = nk < cap ? nk : cap;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -766,6 +789,10 @@ __global__ void __launch_bounds__(BLOCK) k_scatter(const uint64_t *ent, const in
         out[pos] = e;
         if (!ONE) opair[pos] = epair[i];
         if (own[h] != gc) atomicOr(&mix[h], 1u);
+    }
+    if (ep % 255u == 0) {
+        const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < flag_vecs; i += stride) flags[i] = z;
     }
 }
 
@@ -813,8 +840,9 @@ MS_D void emit_hit(bool hit, const hit_t &h, uint64_t key, hit_t *hits, uint64_t
 // memory.  One atomic reservation per chunk for the candidates, then the
 // narrow phase on the chunk's candidates.  Last, the exact cell statistics
 // (Alg. 1's boxes and slots) of the groups that start in the chunk.
-constexpr int ENUM_ITEMS = 16;
-constexpr int ENUM_SLOTS = BLOCK * ENUM_ITEMS;
+constexpr int ENUM_BLOCK = 1024;              // 4 waves per SIMD
+constexpr int ENUM_ITEMS = 4;
+constexpr int ENUM_SLOTS = ENUM_BLOCK * ENUM_ITEMS;
 constexpr int ENUM_STAGE = 768;
 constexpr int ENUM_CELLS = BLOCK;
 constexpr int ENUM_GROUP = ENUM_STAGE;        // group cells held in LDS for the statistics
@@ -888,9 +916,9 @@ MS_D void group_stats(const uint64_t *keys, const CellRec &cr, int sh, uint64_t 
     const int n = cr.nA + cr.nB;
     const bool lds = n <= ENUM_GROUP;
     if (lds)
-        for (int i = threadIdx.x; i < n; i += BLOCK) s_cell[i] = keys[cr.start + i] >> sh;
+        for (int i = threadIdx.x; i < n; i += ENUM_BLOCK) s_cell[i] = keys[cr.start + i] >> sh;
     __syncthreads();
-    for (int i = threadIdx.x; i < cr.nA; i += BLOCK) {
+    for (int i = threadIdx.x; i < cr.nA; i += ENUM_BLOCK) {
         const uint64_t ci = lds ? s_cell[i] : keys[cr.start + i] >> sh;
         uint32_t nb = 0, before = 0;
         for (int j = 0; j < cr.nB; ++j) nb += (lds ? s_cell[cr.nA + j] : keys[cr.start + cr.nA + j] >> sh) == ci;
@@ -904,7 +932,7 @@ MS_D void group_stats(const uint64_t *keys, const CellRec &cr, int sh, uint64_t 
 constexpr int ENUM_PSTART = 4096;   // slot offsets kept in LDS when the groups are this few
 
 template <bool ONE>
-__global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *keys, const int32_t *kpair,
+__global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_t *keys, const int32_t *kpair,
                                                 const CellRec *cells, const int64_t *pstart_g, const int64_t *kept,
                                                 const uint32_t *mix,
                                                 search_stats_t *stats, uint64_t *cand, int32_t *cand_pair,
@@ -931,9 +959,9 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
     __shared__ int32_t s_aoff[ENUM_CELLS + 1], s_boff[ENUM_CELLS], s_ia0[ENUM_CELLS], s_ib0[ENUM_CELLS];
     __shared__ int32_t s_nA[ENUM_CELLS];
     __shared__ int64_t s_c0, s_c1;
-    __shared__ uint32_t s_kscan[BLOCK / WAVE];
+    __shared__ uint32_t s_kscan[ENUM_BLOCK / WAVE];
     __shared__ unsigned long long s_kbase;
-    __shared__ unsigned long long s_st[BLOCK / WAVE];
+    __shared__ unsigned long long s_st[ENUM_BLOCK / WAVE];
     __shared__ uint32_t s_nmix;
     __shared__ uint64_t s_gcell[ENUM_CELLS];
     __shared__ double s_gb[8][ENUM_CELLS];            // per staged group: t-bounds of its cell
@@ -946,7 +974,7 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
     const bool lds_pre = ncells <= ENUM_PSTART;
     if ((int64_t)blockIdx.x < nchunks) {
     if (lds_pre) {
-        for (int64_t i = threadIdx.x; i <= ncells; i += BLOCK) s_pstart[i] = pstart_g[i];
+        for (int64_t i = threadIdx.x; i <= ncells; i += ENUM_BLOCK) s_pstart[i] = pstart_g[i];
         __syncthreads();
     }
     const int64_t *pstart = lds_pre ? s_pstart : pstart_g;
@@ -989,7 +1017,7 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
             if (threadIdx.x == nc - 1) s_pre[nc] = p1;
         }
         uint32_t tot;
-        const uint32_t off = block_excl(need, s_kscan, &tot);
+        const uint32_t off = block_excl<ENUM_BLOCK>(need, s_kscan, &tot);
         const bool staged = nc <= ENUM_CELLS && tot <= ENUM_STAGE;
         if (staged) {
             if (threadIdx.x < nc) {
@@ -998,7 +1026,7 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
             }
             if (threadIdx.x == 0) s_aoff[nc] = (int32_t)tot;
             __syncthreads();
-            for (int i = threadIdx.x; i < (int)tot; i += BLOCK) {
+            for (int i = threadIdx.x; i < (int)tot; i += ENUM_BLOCK) {
                 int lo = 0, hi = (int)nc;             // the group whose staged range holds i
                 while (hi - lo > 1) {
                     const int mid = (lo + hi) >> 1;
@@ -1043,7 +1071,7 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
         uint32_t keepm = 0;
 #pragma unroll
         for (int j = 0; j < ENUM_ITEMS; ++j) {
-            const int64_t slot = S0 + (int64_t)j * BLOCK + threadIdx.x;
+            const int64_t slot = S0 + (int64_t)j * ENUM_BLOCK + threadIdx.x;
             bool keep = false;
             packed[j] = 0;
             prs[j] = 0;
@@ -1119,7 +1147,7 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
         // the candidates: counted with one atomic per chunk, stored when asked
         // for, and compacted into LDS for the narrow phase
         uint32_t ktot;
-        const uint32_t kex = block_excl((uint32_t)__builtin_popcount(keepm), s_kscan, &ktot);
+        const uint32_t kex = block_excl<ENUM_BLOCK>((uint32_t)__builtin_popcount(keepm), s_kscan, &ktot);
         if (threadIdx.x == 0) s_kbase = ktot ? atomicAdd((unsigned long long *)&stats->n_cand, (unsigned long long)ktot) : 0ull;
         __syncthreads();        // (also: every slot is done reading the staged boxes)
         {
@@ -1147,7 +1175,7 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
         // (Sec. 6.2.3), 4x4 solve and inclusion (Sec. 6.2.4), hit records
         if (ktot) {
             uint32_t nm = 0, nd = 0, no = 0;
-            for (uint32_t base = 0; base < ktot; base += BLOCK) {
+            for (uint32_t base = 0; base < ktot; base += ENUM_BLOCK) {
                 const uint32_t i = base + threadIdx.x;
                 int stt = PS_AABB;
                 int32_t ta = 0, tb = 0, p = 0;
@@ -1180,7 +1208,7 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
                 }
                 emit_hit(stt == PS_HIT, h, key, hits, hkeys, hits_cap, stats);
             }
-            const uint32_t sm = block_sum(nm, s_kscan), sd = block_sum(nd, s_kscan), so = block_sum(no, s_kscan);
+            const uint32_t sm = block_sum<ENUM_BLOCK>(nm, s_kscan), sd = block_sum<ENUM_BLOCK>(nd, s_kscan), so = block_sum<ENUM_BLOCK>(no, s_kscan);
             if (threadIdx.x == 0) {
                 if (sm) atomicAdd((unsigned long long *)&stats->n_moller, (unsigned long long)sm);
                 if (sd) atomicAdd((unsigned long long *)&stats->n_degenerate, (unsigned long long)sd);
@@ -1201,7 +1229,7 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
                 }
             }
         } else {
-            for (int64_t c = c0 + threadIdx.x; c < c0 + nc; c += BLOCK) {
+            for (int64_t c = c0 + threadIdx.x; c < c0 + nc; c += ENUM_BLOCK) {
                 if (pstart[c] < S0) continue;
                 const CellRec cr = cells[c];
                 if (mix[cr.h]) {
@@ -1219,7 +1247,7 @@ __global__ void __launch_bounds__(BLOCK) k_enum(BatchView bv, const uint64_t *ke
         }
         __syncthreads();
     }
-    const unsigned long long sc = block_sum(xc, s_st), ss = block_sum(xs, s_st);
+    const unsigned long long sc = block_sum<ENUM_BLOCK>(xc, s_st), ss = block_sum<ENUM_BLOCK>(xs, s_st);
     if (threadIdx.x == 0) {
         if (sc) atomicAdd((unsigned long long *)&stats->n_cells, sc);
         if (ss) atomicAdd((unsigned long long *)&stats->n_slots, ss);
@@ -1359,7 +1387,7 @@ struct Geometry {
 
 struct Layout {
     int64_t ent_cap, cand_cap, hits_cap;
-    size_t o_flags, o_both, o_grp, o_own, o_mix, o_gstat, o_ctrs, o_part, o_rng, o_ent, o_epair, o_sorted, o_spair,
+    size_t o_epoch, o_flags, o_both, o_grp, o_own, o_mix, o_gstat, o_ctrs, o_part, o_rng, o_ent, o_epair, o_sorted, o_spair,
         o_cells, o_pstart, o_htmp, o_hkeys, o_halt, o_misc, o_desc, o_toff, o_cbase, total;
     int64_t n_kblocks, cell_cap, n_fwords, n_cwords, n_gtiles;
 };
@@ -1436,6 +1464,7 @@ void layout(const Geometry &G, Layout &L)
     L.n_fwords = n_ids / 32;
     L.n_cwords = ((int64_t)1 << G.bc_log2) / 32;
     L.n_gtiles = ceil_div(L.n_fwords, GROUP_WORDS);
+    L.o_epoch = take(64);         // first, so that every layout of a workspace shares it
     L.o_flags = take(flag_bytes(G));
     L.o_both = take((size_t)(L.n_fwords + L.n_cwords) * 4);
     L.o_grp = take((size_t)n_ids * 8);
@@ -1523,6 +1552,7 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
             search_stats_t *stats, uint64_t *cand_user, int64_t cand_cap, int64_t *pair_offs, hipStream_t st)
 {
     int rc;
+    uint64_t *epoch = (uint64_t *)(ws + L.o_epoch);
     uint8_t *flags = (uint8_t *)(ws + L.o_flags);
     uint32_t *both = (uint32_t *)(ws + L.o_both);
     uint64_t *grp = (uint64_t *)(ws + L.o_grp);
@@ -1544,22 +1574,19 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
     uint64_t *halt = (uint64_t *)(ws + L.o_halt);
     int64_t *misc = (int64_t *)(ws + L.o_misc);       // [1..2] kept groups and their slots
 
-    // 1. clear: stats, occupancy bytes, look-back words, counters
+    // counters and look-back words: cleared by k_mark's block 0; the
+    // occupancy tables need no clearing (epoch-valued marks)
     ClearSpec cs;
+    memset(&cs, 0, sizeof cs);
     cs.stats = stats;
-    cs.flags = (uint4 *)flags;
-    cs.flag_vecs = (int64_t)(flag_bytes(G) / 16);
     cs.w[0] = gstat;
     cs.n[0] = 2 * L.n_gtiles;
     cs.w[1] = (uint64_t *)ctrs;
     cs.n[1] = 8;
-    cs.w[2] = nullptr;
-    cs.n[2] = 0;
-    MS_LAUNCH("k_prepare", k_prepare, dim3(grid_for(cs.flag_vecs, 1024)), dim3(BLOCK), 0, st, cs);
     const unsigned g_tri = grid_for(G.n_tri);
-    MS_LAUNCH("k_mark", k_mark<ONE>, dim3(g_tri), dim3(BLOCK), 0, st, bv, flags, rng, mpart);
-    MS_LAUNCH("k_pack", k_pack, dim3(grid_for(L.n_fwords + L.n_cwords, 4096)), dim3(BLOCK), 0, st, flags, G.bm_log2,
-              G.bc_log2, both, grp, mix, L.n_fwords, L.n_cwords);
+    MS_LAUNCH("k_mark", k_mark<ONE>, dim3(g_tri), dim3(BLOCK), 0, st, bv, flags, epoch, rng, mpart, cs);
+    MS_LAUNCH("k_pack", k_pack, dim3(grid_for(L.n_fwords + L.n_cwords, 4096)), dim3(BLOCK), 0, st, flags, epoch,
+              G.bm_log2, G.bc_log2, both, grp, mix, L.n_fwords, L.n_cwords);
     KeysOut ko;
     ko.ent = ent;
     ko.epair = epair;
@@ -1582,10 +1609,12 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
     go.n_keys = n_keys;
     go.mark_partial = mpart;
     go.n_mark_partial = (int)g_tri;
+    go.epoch = epoch;
     MS_LAUNCH("k_groups", k_groups, dim3((unsigned)(L.n_gtiles < 1024 ? L.n_gtiles : 1024)), dim3(BLOCK), 0, st, go);
     MS_LAUNCH("k_scatter", k_scatter<ONE>, dim3(grid_for(L.ent_cap)), dim3(BLOCK), 0, st, ent, epair, n_keys,
-              L.ent_cap, (uint32_t *)grp, own, mix, G.bm_log2, G.tb + 1, G.tb, sorted, spair);
-    MS_LAUNCH("k_enum", k_enum<ONE>, dim3(ENUM_GRID), dim3(BLOCK), 0, st, bv, sorted, spair, cells, pstart, misc + 1,
+              L.ent_cap, (uint32_t *)grp, own, mix, G.bm_log2, G.tb + 1, G.tb, sorted, spair, epoch, (uint4 *)flags,
+              (int64_t)(flag_bytes(G) / 16));
+    MS_LAUNCH("k_enum", k_enum<ONE>, dim3(ENUM_GRID), dim3(ENUM_BLOCK), 0, st, bv, sorted, spair, cells, pstart, misc + 1,
               mix, stats, cand_user, (int32_t *)nullptr, cand_user ? cand_cap : (int64_t)0, htmp, hkeys, hits_cap);
     MS_HIP(hipGetLastError());
     if (hits_cap > 0) {
