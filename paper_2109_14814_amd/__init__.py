@@ -304,7 +304,7 @@ def _time_ms(fn, reps: int) -> float:
     return e0.elapsed_time(e1) / reps
 
 
-def autotune_kappa(A: Mesh, B: Mesh, kappas=KAPPAS, reps: int = 20, tie: float = 0.10,
+def autotune_kappa(A: Mesh, B: Mesh, kappas=KAPPAS, reps: int = 20, tie: float = 0.03,
                    hits_cap: int = 1 << 10, cand_cap: int = 1 << 20):
     """Cell-edge autotuner for one mesh pair.  The grid of Sec. 6.2.1 only
     needs cells larger than the triangles; the edge is kappa x the mean

@@ -46,7 +46,7 @@ namespace {
 constexpr int BLOCK = 256;
 constexpr int MAX_GRID = 2048;
 static_assert(MAX_GRID <= MS_COUNT_PARTIALS, "count partials fit the mesh scratch");
-constexpr int KEYS_ITEMS = 4;                         // triangles per thread in k_keys
+constexpr int KEYS_ITEMS = 1;                         // triangles per thread in k_keys
 constexpr int KEYS_TILE = BLOCK * KEYS_ITEMS;         // triangles per k_keys block
 constexpr uint64_t SFLAG_AGG = 1ull << 62;
 constexpr uint64_t SFLAG_PRE = 2ull << 62;
@@ -929,6 +929,68 @@ MS_D void group_stats(const uint64_t *keys, const CellRec &cr, int sh, uint64_t 
     __syncthreads();
 }
 
+// A staged slot: its group c (last with s_pre[c] <= slot) and the staged
+// indices of its A and B entries.
+struct StagedSlot {
+    int c, ia, ib;
+};
+
+MS_D StagedSlot staged_slot(int64_t slot, int nc, const int64_t *s_pre, const int32_t *s_nA, const int32_t *s_aoff,
+                            const int32_t *s_ia0, const int32_t *s_boff, const int32_t *s_ib0)
+{
+    int lo = 0, hi = nc;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_pre[mid] <= slot) lo = mid;
+        else hi = mid;
+    }
+    uint64_t iB, iA;
+    split_slot((uint64_t)(slot - s_pre[lo]), (uint32_t)s_nA[lo], iB, iA);
+    StagedSlot q;
+    q.c = lo;
+    q.ia = s_aoff[lo] + (int)((int64_t)iA - s_ia0[lo]);
+    q.ib = s_boff[lo] + (int)((int64_t)iB - s_ib0[lo]);
+    return q;
+}
+
+// One slot from global memory (chunks whose entries do not fit the LDS
+// stage): its group by binary search, both entries, both boxes from the
+// vertices.
+struct SlotOut {
+    uint64_t packed;    // (triA << 32) | triB
+    int32_t pr;         // pair
+    int32_t keep;
+};
+
+template <bool ONE>
+MS_D SlotOut global_slot(const BatchView &bv, const uint64_t *keys, const int32_t *kpair, const CellRec *cells,
+                         const int64_t *pstart, int64_t ncells, int64_t slot)
+{
+    SlotOut o;
+    o.packed = 0;
+    o.pr = 0;
+    o.keep = 0;
+    const int sh = bv.kl.cell_shift;
+    const int64_t c = last_le<int64_t>(pstart, ncells, slot);
+    const CellRec cr = cells[c];
+    uint64_t iB, iA;
+    split_slot((uint64_t)(slot - pstart[c]), (uint32_t)cr.nA, iB, iA);
+    const int64_t eA = cr.start + (int64_t)iA;
+    const uint64_t kA = keys[eA];
+    const uint64_t kB = keys[cr.start + cr.nA + (int64_t)iB];
+    const uint64_t ca = kA >> sh;
+    const int32_t ta = (int32_t)(kA & bv.kl.tmask), tb = (int32_t)(kB & bv.kl.tmask);
+    o.packed = ((uint64_t)(uint32_t)ta << 32) | (uint32_t)tb;
+    if (ca != (kB >> sh)) return o;
+    o.pr = entry_pair<ONE>(kpair, eA);
+    const PairDesc &Pd = pair_desc<ONE>(bv, o.pr);
+    double alo[4], ahi[4], blo[4], bhi[4];
+    tri_box(Pd.A, ta, alo, ahi);
+    tri_box(Pd.B, tb, blo, bhi);
+    o.keep = enum_pair<ONE>(Pd, ca - Pd.cell_base, alo, ahi, blo, bhi);
+    return o;
+}
+
 constexpr int ENUM_PSTART = 4096;   // slot offsets kept in LDS when the groups are this few
 
 template <bool ONE>
@@ -1066,32 +1128,19 @@ __global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_
             }
             __syncthreads();
         }
-        uint64_t packed[ENUM_ITEMS];
-        int32_t prs[ENUM_ITEMS];
+        // pass 1: the keep bit of each slot (the pair of a kept slot is
+        // found again in pass 2, so that no per-slot state is held)
         uint32_t keepm = 0;
-#pragma unroll
+#pragma unroll 1
         for (int j = 0; j < ENUM_ITEMS; ++j) {
             const int64_t slot = S0 + (int64_t)j * ENUM_BLOCK + threadIdx.x;
             bool keep = false;
-            packed[j] = 0;
-            prs[j] = 0;
             if (slot < S1) {
                 if (staged) {
-                    int lo = 0, hi = (int)nc;          // last staged group with s_pre <= slot
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        if (s_pre[mid] <= slot) lo = mid;
-                        else hi = mid;
-                    }
-                    const int c = lo;
-                    const int32_t nA = s_nA[c];
-                    uint64_t iB, iA;
-                    split_slot((uint64_t)(slot - s_pre[c]), (uint32_t)nA, iB, iA);
-                    const int ia = s_aoff[c] + (int)((int64_t)iA - s_ia0[c]);
-                    const int ib = s_boff[c] + (int)((int64_t)iB - s_ib0[c]);
+                    const StagedSlot q = staged_slot(slot, (int)nc, s_pre, s_nA, s_aoff, s_ia0, s_boff, s_ib0);
+                    const int c = q.c, ia = q.ia, ib = q.ib;
                     const uint64_t ca = s_ec[ia];
                     if (ca == s_ec[ib]) {
-                        prs[j] = ONE ? 0 : s_ep[ia];
                         double alo[4], ahi[4], blo[4], bhi[4];
                         bool ov = true;
 #pragma unroll
@@ -1115,31 +1164,13 @@ __global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_
                                 }
                                 keep = in;
                             } else {
-                                const PairDesc &Pd = pair_desc<ONE>(bv, prs[j]);
+                                const PairDesc &Pd = pair_desc<ONE>(bv, ONE ? 0 : s_ep[ia]);
                                 keep = enum_pair<ONE>(Pd, ca - Pd.cell_base, alo, ahi, blo, bhi);
                             }
                         }
-                        packed[j] = ((uint64_t)(uint32_t)s_t[ia] << 32) | (uint32_t)s_t[ib];
                     }
                 } else {
-                    const int64_t c = last_le<int64_t>(pstart, ncells, slot);
-                    const CellRec cr = cells[c];
-                    uint64_t iB, iA;
-                    split_slot((uint64_t)(slot - pstart[c]), (uint32_t)cr.nA, iB, iA);
-                    const int64_t eA = cr.start + (int64_t)iA;
-                    const uint64_t kA = keys[eA];
-                    const uint64_t kB = keys[cr.start + cr.nA + (int64_t)iB];
-                    const uint64_t ca = kA >> sh;
-                    if (ca == (kB >> sh)) {
-                        prs[j] = entry_pair<ONE>(kpair, eA);
-                        const PairDesc &Pd = pair_desc<ONE>(bv, prs[j]);
-                        const int32_t ta = (int32_t)(kA & bv.kl.tmask), tb = (int32_t)(kB & bv.kl.tmask);
-                        double alo[4], ahi[4], blo[4], bhi[4];
-                        tri_box(Pd.A, ta, alo, ahi);
-                        tri_box(Pd.B, tb, blo, bhi);
-                        keep = enum_pair<ONE>(Pd, ca - Pd.cell_base, alo, ahi, blo, bhi);
-                        packed[j] = ((uint64_t)(uint32_t)ta << 32) | (uint32_t)tb;
-                    }
+                    keep = global_slot<ONE>(bv, keys, kpair, cells, pstart, ncells, slot).keep != 0;
                 }
             }
             keepm |= (uint32_t)keep << j;
@@ -1153,15 +1184,26 @@ __global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_
         {
             uint32_t li = kex;
             int64_t idx = (int64_t)s_kbase + kex;
-#pragma unroll
-            for (int j = 0; j < ENUM_ITEMS; ++j) {
-                if (!(keepm >> j & 1)) continue;
-                s_u.c.tt[li] = packed[j];
-                s_u.c.pair[li] = prs[j];
+#pragma unroll 1
+            for (uint32_t m = keepm; m; m &= m - 1) {
+                const int64_t slot = S0 + (int64_t)__builtin_ctz(m) * ENUM_BLOCK + threadIdx.x;
+                uint64_t packed;
+                int32_t pr;
+                if (staged) {
+                    const StagedSlot q = staged_slot(slot, (int)nc, s_pre, s_nA, s_aoff, s_ia0, s_boff, s_ib0);
+                    packed = ((uint64_t)(uint32_t)s_t[q.ia] << 32) | (uint32_t)s_t[q.ib];
+                    pr = ONE ? 0 : s_ep[q.ia];
+                } else {
+                    const SlotOut so = global_slot<ONE>(bv, keys, kpair, cells, pstart, ncells, slot);
+                    packed = so.packed;
+                    pr = so.pr;
+                }
+                s_u.c.tt[li] = packed;
+                s_u.c.pair[li] = pr;
                 if (cand) {
                     if (idx < cand_cap) {
-                        cand[idx] = packed[j];
-                        if (cand_pair) cand_pair[idx] = prs[j];
+                        cand[idx] = packed;
+                        if (cand_pair) cand_pair[idx] = pr;
                     } else {
                         atomicOr((unsigned long long *)&stats->overflow, 2ull);
                     }
