@@ -840,8 +840,8 @@ MS_D void emit_hit(bool hit, const hit_t &h, uint64_t key, hit_t *hits, uint64_t
 // memory.  One atomic reservation per chunk for the candidates, then the
 // narrow phase on the chunk's candidates.  Last, the exact cell statistics
 // (Alg. 1's boxes and slots) of the groups that start in the chunk.
-constexpr int ENUM_BLOCK = 1024;              // 4 waves per SIMD
-constexpr int ENUM_ITEMS = 4;
+constexpr int ENUM_BLOCK = 512;               // 2 waves per SIMD; the narrow phase needs the registers
+constexpr int ENUM_ITEMS = 8;
 constexpr int ENUM_SLOTS = ENUM_BLOCK * ENUM_ITEMS;
 constexpr int ENUM_STAGE = 768;
 constexpr int ENUM_CELLS = BLOCK;
