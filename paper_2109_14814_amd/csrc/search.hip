@@ -448,13 +448,22 @@ __global__ void __launch_bounds__(BLOCK) k_mark(BatchView bv, uint8_t *flags, co
         rng[gt] = pack_range(r, bv.packable != 0);
         all += (unsigned long long)range_count(r);
         uint8_t *mine = flags + (size_t)L.side * side_bytes;
-        const uint64_t cb = P.cell_base;
-        for_cells(r, P.g.n, [&](uint64_t c) { mine[bm_hash(cb + c, bv.bm_log2)] = v; });
-        CellRange rc;
-        int64_t nc[4];
-        coarse_of(r, P.g.n, rc, nc);
         uint8_t *cmine = flags + 2 * side_bytes + ((size_t)L.side << bv.bc_log2);
-        for_cells(rc, nc, [&](uint64_t c) { cmine[bm_hash(cb + c, bv.bc_log2)] = v; });
+        const uint64_t cb = P.cell_base;
+        const int64_t *n = P.g.n;
+        const int64_t nc1 = (n[1] + 1) >> 1, nc2 = (n[2] + 1) >> 1, nc3 = (n[3] + 1) >> 1;
+        // each fine cell and its coarse cell (index / 2 per axis; a coarse
+        // cell shared by several fine cells is simply marked again)
+        for (int64_t c0 = r.lo[0]; c0 <= r.hi[0]; ++c0)
+            for (int64_t c1 = r.lo[1]; c1 <= r.hi[1]; ++c1)
+                for (int64_t c2 = r.lo[2]; c2 <= r.hi[2]; ++c2) {
+                    const int64_t fb = ((c0 * n[1] + c1) * n[2] + c2) * n[3];
+                    const int64_t cbz = (((c0 >> 1) * nc1 + (c1 >> 1)) * nc2 + (c2 >> 1)) * nc3;
+                    for (int64_t c3 = r.lo[3]; c3 <= r.hi[3]; ++c3) {
+                        mine[bm_hash(cb + (uint64_t)(fb + c3), bv.bm_log2)] = v;
+                        cmine[bm_hash(cb + (uint64_t)(cbz + (c3 >> 1)), bv.bc_log2)] = v;
+                    }
+                }
     }
     all = block_sum(all, s_tmp);
     bad = block_sum(bad, s_tmp);
