@@ -1188,7 +1188,16 @@ __global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_
         // for, and compacted into LDS for the narrow phase
         uint32_t ktot;
         const uint32_t kex = block_excl<ENUM_BLOCK>((uint32_t)__builtin_popcount(keepm), s_kscan, &ktot);
-        if (threadIdx.x == 0) s_kbase = ktot ? atomicAdd((unsigned long long *)&stats->n_cand, (unsigned long long)ktot) : 0ull;
+        if (threadIdx.x == 0) {
+            // the chunk's place in the candidate list matters only when the
+            // list is stored; otherwise the count needs no reply
+            unsigned long long b = 0;
+            if (ktot) {
+                if (cand) b = atomicAdd((unsigned long long *)&stats->n_cand, (unsigned long long)ktot);
+                else atomicAdd((unsigned long long *)&stats->n_cand, (unsigned long long)ktot);
+            }
+            s_kbase = b;
+        }
         __syncthreads();        // (also: every slot is done reading the staged boxes)
         {
             uint32_t li = kex;
