@@ -118,13 +118,6 @@ MS_D int pair_of_tri(const BatchView &bv, int64_t gt)
     else return (int)last_le<int64_t>(bv.tri_off, bv.n_pairs, gt);
 }
 
-template <bool ONE>
-MS_D int pair_of_cell(const BatchView &bv, uint64_t gcell)
-{
-    if constexpr (ONE) return 0;
-    else return (int)last_le<uint64_t>(bv.cell_base, bv.n_pairs, gcell);
-}
-
 MS_D uint32_t bm_hash(uint64_t cell, int log2)
 {
     return (uint32_t)((cell * 0x9E3779B97F4A7C15ull) >> (64 - log2));
@@ -318,7 +311,6 @@ MS_D uint64_t wave_lookback_s(const uint64_t *status, int64_t stride, int64_t ti
 }
 
 MS_D uint64_t wave_lookback(const uint64_t *status, int64_t tile) { return wave_lookback_s(status, 1, tile); }
-MS_D uint64_t wave_lookback3(const uint64_t *status, int64_t tile) { return wave_lookback_s(status, 3, tile); }
 
 // The same over pairs of words (a, b) published together (tile i's pair at
 // status[i * stride], status[i * stride + 1]): a predecessor is ready when
@@ -391,9 +383,10 @@ MS_D T block_excl(T v, T *s_tmp, T *total)
 
 // ---------------------------------------------------------------- kernels
 
+// Counters to clear at the start of a search (by k_mark's first block) or of
+// the all-pairs test (by k_prepare).
 struct ClearSpec {
     search_stats_t *stats;
-    uint4 *flags;      int64_t flag_vecs;        // occupancy bytes, 16 per store
     uint64_t *w[3];    int64_t n[3];             // look-back words, counters
 };
 
@@ -402,8 +395,6 @@ __global__ void __launch_bounds__(BLOCK) k_prepare(ClearSpec c)
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c.stats && g0 < (int64_t)(sizeof(search_stats_t) / 8)) ((int64_t *)c.stats)[g0] = 0;
-    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
-    for (int64_t i = g0; i < c.flag_vecs; i += stride) c.flags[i] = z;
 #pragma unroll
     for (int k = 0; k < 3; ++k)
         for (int64_t i = g0; i < c.n[k]; i += stride) c.w[k][i] = 0;
@@ -804,13 +795,6 @@ __global__ void __launch_bounds__(BLOCK) k_scatter(const uint64_t *ent, const in
         for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < flag_vecs; i += stride) flags[i] = z;
     }
 }
-
-MS_D int64_t uniform_i64(int64_t v)
-{
-    return ((int64_t)__builtin_amdgcn_readfirstlane((int)(v >> 32)) << 32) |
-           (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
-}
-
 
 MS_D void wave_count(bool p, int64_t *ctr)
 {
