@@ -129,7 +129,7 @@ def main():
     ap.add_argument("--n", type=int, default=512, help="quads per axis of each surface")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--kappa", type=float, default=0.0, help="cell edge / mean triangle diameter (0 = autotune)")
-    ap.add_argument("--legs", default="search,allpairs,family,rk8,refine,copy,cpu")
+    ap.add_argument("--legs", default="search,allpairs,family,layers,rk8,refine,copy,cpu")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -254,6 +254,45 @@ def main():
         out["family_tris_total"] = int(sum(ga.n_tris + gb.n_tris for ga, gb in gp))
         log(f"family: 256 plain searches in {t_f * 1e3:.2f} ms, batched graph {t_b * 1e3:.2f} ms, counts equal={same}")
         del bt, srch, gp
+
+    # ---------------- the layer search of Sec. 5 / 6.4 at the paper's shape
+    if "layers" in legs:
+        lp = synth.layered_pair(1024, 2048, 34, 14, args.seed)
+        U, S = ms.Mesh.from_synth(lp.U), ms.Mesh.from_synth(lp.S)
+        ls = ms.LayerSearch(U, S, lp.D_u, lp.lam_u, lp.D_s, lp.lam_s, lp.n_layers, hits_cap=1 << 16)
+        log(f"layers: autotuned kappa {ls.kappa}: " + ", ".join(f"{k}: {v:.3f} ms" for k, v in ls.kappa_times.items()))
+        ls.run(True)
+        torch.cuda.synchronize()
+        reps = 10
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ls.batch.run(True)
+        torch.cuda.synchronize()
+        t_l = (time.perf_counter() - t0) / reps
+        lst = ls.batch.stats_dict()
+        srch = [ms.Searcher(a, b, p, hits_cap=1 << 12, cand_cap=1 << 18) for (a, b), p in zip(ls.meshes, ls.params)]
+        for sr in srch:
+            sr.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for sr in srch:
+            sr.run()
+        torch.cuda.synchronize()
+        t_p = time.perf_counter() - t0
+        pst = [sr.results()[1] for sr in srch]
+        same = lst["overflow"] == 0 and all(lst[k] == sum(q[k] for q in pst) for k in ("n_cand", "n_hits", "n_cells", "n_slots"))
+        quads = int(sum((a.n_tris // 2) * (b.n_tris // 2) for a, b in ls.meshes))
+        out["layers_pairs"] = len(ls.meshes)
+        out["layers_kappa"] = ls.kappa
+        out["layers_batched_ms"] = t_l * 1e3
+        out["layers_plain_ms"] = t_p * 1e3
+        out["layers_quad_pairs"] = quads
+        out["layers_quad_pairs_per_s"] = quads / t_l
+        out["layers_hits"] = int(lst["n_hits"])
+        out["layers_counts_equal_plain"] = bool(same)
+        log(f"layers: {len(ls.meshes)} half-layer pairs ({quads:.3e} quad pairs) batched in {t_l * 1e3:.2f} ms, "
+            f"pair by pair {t_p * 1e3:.2f} ms, {lst['n_hits']} hits, counts equal={same}")
+        del ls, srch, U, S
 
     # ---------------- propagated patches: F^+-3, boxes, search, refinement
     if "rk8" in legs:

@@ -385,6 +385,52 @@ int refine_newton(const double *params_in_dev, double *params_out_dev, int64_t K
                   const newton_params_t *np, double *f_dev, double *r_dev, int32_t *status_dev,
                   int32_t *trials_dev, void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * The method of layers (Sec. 5).  With lambda_u and lambda_s the multipliers
+ * of the internal dynamics on the unstable and stable manifolds and
+ * T x (-D, D) their fundamental domains, the half-layers are
+ *   U_n^+ : s in [D lambda_u^(n-1), D lambda_u^n],   U_n^- : the same with -s,
+ *   S_n^+ : s in [D / lambda_s^(n-1), D / lambda_s^n], S_n^- : the same with -s.
+ * Since F maps U_n onto U_(n+1) and S_n onto S_(n-1), every heteroclinic
+ * orbit meets some pair (U_n, S_n) or (U_n, S_(n-1)) with n >= 1, so a search
+ * up to layer L examines the 8 half-layer pairs of each layer: U_n^a against
+ * S_n^b and S_(n-1)^b, a, b in {+, -} (the paper: 14 layers, 112 pairs).
+ * Host functions; no device work, no stream.
+ */
+typedef struct {
+    int32_t u_layer, u_sign;   /* U_n^(+/-): n >= 1, sign +1 or -1 */
+    int32_t s_layer, s_sign;   /* S_m^(+/-): m = n or n - 1 */
+} layer_pair_t;
+
+/*
+ * layer_pairs -- the 8 * n_layers half-layer pairs for layers 1..n_layers,
+ * ordered by n, then U's sign (+ first), then S_n before S_(n-1), then S's
+ * sign (+ first).  *n_out = 8 * n_layers; MS_E_CAPACITY (out untouched)
+ * when cap is smaller; MS_E_ARG for n_layers < 0 or a NULL pointer.
+ */
+int layer_pairs(int32_t n_layers, layer_pair_t *out, int32_t cap, int32_t *n_out);
+
+/*
+ * half_layer_bounds -- [lo, hi] of |s| for half-layer `layer` (unstable:
+ * D lambda^(layer-1) and D lambda^layer; stable: D / lambda^(layer-1) and
+ * D / lambda^layer), ordered lo < hi.  MS_E_ARG unless D > 0, lambda > 0,
+ * lambda != 1 and both bounds finite.
+ */
+int half_layer_bounds(double D, double lambda, int32_t stable, int32_t layer, double *lo, double *hi);
+
+/*
+ * half_layer_columns -- the columns [*k0, *k1] of a mesh with s samples
+ * s_host[0..n_s_v) (strictly increasing) that form the half-layer of sign
+ * `sign` (+1 or -1): the columns from the sample equal to one boundary to
+ * the sample equal to the other (equality within a relative 1e-12; the
+ * manifold's globalization produces the boundaries as samples, Sec. 6.2).
+ * A mesh over columns [k0, k1] of an AoS vertex grid starts at vertex
+ * k0 * n_theta_v, with n_s_v = k1 - k0 + 1 (no copy).  MS_E_ARG when a
+ * boundary is not a sample or the samples do not increase.
+ */
+int half_layer_columns(const double *s_host, int32_t n_s_v, double D, double lambda, int32_t stable, int32_t layer,
+                       int32_t sign, int32_t *k0, int32_t *k1);
+
 #ifdef __cplusplus
 }
 #endif

@@ -378,3 +378,47 @@ def default_grid(meshes, kappa: float):
     inv = 1.0 / edge
     n = np.array([max(1, int(math.ceil((hi[d] - lo[d]) * inv))) for d in range(4)], dtype=np.int64)
     return lo, hi, inv, n
+
+
+# ---------------------------------------------------------------------------
+# The method of layers (Sec. 5)
+# ---------------------------------------------------------------------------
+
+def layer_pairs(n_layers: int) -> list[tuple[int, int, int, int]]:
+    """The half-layer pairs a search up to layer L examines (Sec. 5, Sec. 6.2):
+    for n = 1..L, U_n^a against S_n^b and S_(n-1)^b, a, b in {+1, -1}, as
+    tuples (n, a, m, b); ordered by n, a (+ first), m (n first), b (+ first)."""
+    out = []
+    for n in range(1, n_layers + 1):
+        for a in (1, -1):
+            for m in (n, n - 1):
+                for b in (1, -1):
+                    out.append((n, a, m, b))
+    return out
+
+
+def half_layer_interval(D: float, lam: float, stable: bool, layer: int, sign: int) -> tuple[float, float]:
+    """The s interval of half-layer `layer` of sign `sign` (Sec. 5): unstable
+    |s| in [D lam^(n-1), D lam^n], stable |s| in [D / lam^(n-1), D / lam^n];
+    returned as (lo, hi) in s, lo < hi."""
+    if stable:
+        ends = (D / lam ** (layer - 1), D / lam ** layer)
+    else:
+        ends = (D * lam ** (layer - 1), D * lam ** layer)
+    a, b = min(ends), max(ends)
+    return (a, b) if sign > 0 else (-b, -a)
+
+
+def half_layer_columns(s, D: float, lam: float, stable: bool, layer: int, sign: int,
+                       rel: float = 1e-12) -> tuple[int, int]:
+    """The columns of a mesh (s samples increasing) whose s lie in the
+    half-layer's interval (the boundaries admitted within a relative `rel`):
+    (first, last).  Raises ValueError when fewer than two samples lie in it or
+    a boundary is not a sample."""
+    s = np.asarray(s, dtype=np.float64)
+    lo, hi = half_layer_interval(D, lam, stable, layer, sign)
+    tol = rel * max(abs(lo), abs(hi))
+    inside = np.nonzero((s >= lo - tol) & (s <= hi + tol))[0]
+    if len(inside) < 2 or abs(s[inside[0]] - lo) > tol or abs(s[inside[-1]] - hi) > tol:
+        raise ValueError("half-layer boundaries are not samples of the mesh")
+    return int(inside[0]), int(inside[-1])

@@ -24,7 +24,8 @@ MS_SEARCH_CANDIDATES, MS_SEARCH_STRICT = 1, 2
 EXPORTS = ("last_error", "mesh_build", "mesh_free", "mesh_info", "mesh_update", "search_default_params",
            "search_workspace_size", "search_intersections", "search_intersections_async", "narrow_allpairs", "propagate_vertices",
            "search_profile_enable", "search_profile_read", "batch_create", "batch_search", "batch_needed",
-           "batch_free", "refine_workspace_size", "refine_grad", "refine_newton")
+           "batch_free", "refine_workspace_size", "refine_grad", "refine_newton", "layer_pairs",
+           "half_layer_bounds", "half_layer_columns")
 
 MS_REFINE_RESIDUAL, MS_REFINE_ADJOINT, MS_REFINE_TANGENT, MS_REFINE_NEWTON = 0, 1, 2, 3
 NEWTON_STATUS = {0: "converged", 1: "trial limit", 2: "step too small", 3: "singular", 4: "non-finite"}
@@ -107,6 +108,11 @@ def lib():
         L.refine_newton.argtypes = [P, P, I64, P, P, I32, MP, MP, C.POINTER(NewtonParams), P, P, P, P, P,
                                     C.c_size_t, P]
         L.refine_newton.restype = C.c_int
+        L.layer_pairs.argtypes = [I32, P, I32, C.POINTER(C.c_int32)]; L.layer_pairs.restype = C.c_int
+        L.half_layer_bounds.argtypes = [D, D, I32, I32, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.half_layer_bounds.restype = C.c_int
+        L.half_layer_columns.argtypes = [P, I32, D, D, I32, I32, I32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.half_layer_columns.restype = C.c_int
         _lib = L
     return _lib
 
@@ -145,6 +151,8 @@ class Mesh:
 
     def __init__(self, verts, theta, s, periodic: bool, layout: int = MS_LAYOUT_AOS):
         torch = _torch()
+        self.periodic = bool(periodic)
+        self.layout = layout
         v = torch.as_tensor(verts, dtype=torch.float64)
         if layout == MS_LAYOUT_SOA:
             v = v.permute(2, 0, 1)
@@ -184,6 +192,13 @@ class Mesh:
     @classmethod
     def from_synth(cls, m, layout: int = MS_LAYOUT_AOS):
         return cls(m.verts, m.theta, m.s, m.periodic, layout)
+
+    def columns(self, k0: int, k1: int) -> "Mesh":
+        """The mesh over s-columns k0..k1 of this one (a half-layer), sharing
+        its device vertices (AoS layout)."""
+        if self.layout != MS_LAYOUT_AOS:
+            raise ValueError("column sub-meshes need the AoS layout")
+        return Mesh(self.verts[k0:k1 + 1], self.theta, self.s[k0:k1 + 1], self.periodic)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -338,6 +353,71 @@ def autotune_batch_kappa(pairs, kappas=(1.0, 1.5, 2.0, 3.0), reps: int = 3, tie:
     fastest = min(times.values())
     kappa = min(k for k in kappas if times[k] <= fastest * (1.0 + tie))
     return kappa, [default_params(a, b, kappa) for a, b in pairs], times
+
+
+LAYER_PAIR_DTYPE = np.dtype([("u_layer", "<i4"), ("u_sign", "<i4"), ("s_layer", "<i4"), ("s_sign", "<i4")])
+
+
+def layer_pairs(n_layers: int) -> np.ndarray:
+    """The 8 n_layers half-layer pairs of a search up to layer n_layers
+    (layer_pairs)."""
+    out = np.zeros(max(8 * int(n_layers), 1), dtype=LAYER_PAIR_DTYPE)
+    n = C.c_int32()
+    _check(lib().layer_pairs(int(n_layers), out.ctypes.data_as(C.c_void_p), len(out), C.byref(n)))
+    return out[: n.value]
+
+
+def half_layer_bounds(D: float, lam: float, stable: bool, layer: int) -> tuple[float, float]:
+    lo, hi = C.c_double(), C.c_double()
+    _check(lib().half_layer_bounds(float(D), float(lam), int(bool(stable)), int(layer), C.byref(lo), C.byref(hi)))
+    return lo.value, hi.value
+
+
+def half_layer_columns(s, D: float, lam: float, stable: bool, layer: int, sign: int) -> tuple[int, int]:
+    """Columns (k0, k1) of a mesh with s samples `s` forming the half-layer
+    (half_layer_columns)."""
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    k0, k1 = C.c_int32(), C.c_int32()
+    _check(lib().half_layer_columns(s.ctypes.data_as(C.c_void_p), len(s), float(D), float(lam), int(bool(stable)),
+                                    int(layer), int(sign), C.byref(k0), C.byref(k1)))
+    return k0.value, k1.value
+
+
+class LayerSearch:
+    """The connection search of Sec. 5 / 6.2 up to layer n_layers: the
+    half-layer pairs of an unstable mesh U (multiplier lam_u, fundamental
+    domain D_u) and a stable mesh S (lam_s, D_s), each half-layer a column
+    sub-mesh sharing the vertices, searched together as one batch."""
+
+    def __init__(self, U: Mesh, S: Mesh, D_u: float, lam_u: float, D_s: float, lam_s: float, n_layers: int,
+                 kappa=None, hits_cap: int = 1 << 16, cand_cap: int = 1 << 22):
+        self.pairs = layer_pairs(n_layers)
+        cache = {}
+
+        def half(mesh, stable, D, lam, layer, sign):
+            key = (stable, layer, sign)
+            if key not in cache:
+                cache[key] = mesh.columns(*half_layer_columns(mesh.s, D, lam, stable, layer, sign))
+            return cache[key]
+
+        self.meshes = [(half(U, False, D_u, lam_u, int(p["u_layer"]), int(p["u_sign"])),
+                        half(S, True, D_s, lam_s, int(p["s_layer"]), int(p["s_sign"]))) for p in self.pairs]
+        self.halves = cache
+        if kappa is None:
+            self.kappa, params, self.kappa_times = autotune_batch_kappa(self.meshes, hits_cap=hits_cap,
+                                                                        cand_cap=cand_cap)
+        else:
+            self.kappa, self.kappa_times = float(kappa), {}
+            params = [default_params(a, b, self.kappa) for a, b in self.meshes]
+        self.params = params
+        self.batch = Batch(self.meshes, params, hits_cap=hits_cap, cand_cap=cand_cap)
+
+    def run(self, use_graph: bool = True) -> None:
+        self.batch.run_checked(use_graph)
+
+    def results(self):
+        """(per-pair hit arrays, in the order of self.pairs; stats)."""
+        return self.batch.results()
 
 
 def profile_enable(on: bool = True):

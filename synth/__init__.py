@@ -112,6 +112,74 @@ def plain_pair(n_quads_theta: int, n_quads_s: int, seed: int = 0,
     return a, b
 
 
+def layered_s(D: float, lam: float, stable: bool, first: int, last: int, m_quads: int,
+              m_core: int = 4) -> np.ndarray:
+    """s samples of a manifold mesh whose columns contain the half-layer
+    boundaries b_n = D lam^n (unstable) or D / lam^n (stable) for
+    n = first-1 .. last: every half-layer [b_(n-1), b_n] (and its mirror) in
+    m_quads quads, the core |s| < b_(first-1) in m_core quads; increasing."""
+    b = [D / lam ** n if stable else D * lam ** n for n in range(first - 1, last + 1)]
+    pos = [np.array([b[0]])]
+    for n in range(1, len(b)):
+        pos.append(np.linspace(b[n - 1], b[n], m_quads + 1)[1:])
+    pos = np.concatenate(pos)
+    core = np.linspace(-b[0], b[0], m_core + 1)[1:-1]
+    return np.concatenate([-pos[::-1], core, pos])
+
+
+def layered_mesh(n_theta: int, s: np.ndarray, coeffs: SurfaceCoeffs, eps: float = 0.0, shift: float = 0.0,
+                 D: float = 1.0, lam: float = 2.0) -> Mesh:
+    """Periodic mesh over theta_i = 2 pi i / n_theta and the given s samples;
+    the surface is the closed form P at sigma = s / max|s| (bounded), plus
+    eps * (0, 0, sin(2 theta - shift), cos(2 pi l(s))) with l(s) =
+    log(|s| / D) / |log lam| the continuous layer index (layer n is
+    n - 1 <= l <= n).  With eps != 0 it meets the eps = 0 surface
+    transversally at the isolated points theta = shift / 2 + k pi / 2,
+    l = n - 3/4 and n - 1/4: eight in every half-layer."""
+    theta = TWO_PI * np.arange(n_theta, dtype=np.float64) / n_theta
+    s = np.asarray(s, dtype=np.float64)
+    sigma = s / np.max(np.abs(s))
+    th, sg = theta[None, :], sigma[:, None]
+    verts = eval_surface(coeffs, th, sg)
+    if eps:
+        ell = np.log(np.maximum(np.abs(s), 1e-300) / D) / abs(math.log(lam))
+        th2, el2 = np.broadcast_arrays(th, ell[:, None])
+        verts[..., 2] += eps * np.sin(2.0 * th2 - shift)
+        verts[..., 3] += eps * np.cos(TWO_PI * el2)
+    return Mesh(np.ascontiguousarray(verts), theta, s.copy(), True)
+
+
+@dataclasses.dataclass
+class LayeredPair:
+    U: Mesh            # unstable-manifold mesh, layers 1..n_layers
+    S: Mesh            # stable-manifold mesh, layers 0..n_layers
+    D_u: float
+    lam_u: float
+    D_s: float
+    lam_s: float
+    n_layers: int
+
+
+def layered_pair(n_theta_u: int, n_theta_s: int, m_quads: int, n_layers: int, seed: int = 0,
+                 D_u: float = 0.05, lam_u: float = 1.35, D_s: float = 0.05, lam_s: float = 1 / 1.35,
+                 m_core: int = 4) -> LayeredPair:
+    """The layer-search workload of Sec. 5 / 6.4 in synthetic form: an
+    unstable mesh with n_theta_u theta samples and the stable one with
+    n_theta_s, each half-layer m_quads quads in s (the paper: 1024 / 2048
+    samples, 35 columns, 14 layers).  Both surfaces share the closed form of
+    `seed`; the stable one is displaced as in layered_mesh (shift drawn from
+    seed + 1), so the two cross at isolated points inside every half-layer
+    pair (U_n^a, S_n^a) (sigma = s / max|s| agrees between the meshes because
+    both reach the same max|s|)."""
+    su = layered_s(D_u, lam_u, False, 1, n_layers, m_quads, m_core)
+    ss = layered_s(D_s, lam_s, True, 0, n_layers, m_quads, m_core)
+    c = surface_coeffs(seed)
+    shift = float(np.random.default_rng(seed + 1).uniform(0.0, TWO_PI))
+    U = layered_mesh(n_theta_u, su, c)
+    S = layered_mesh(n_theta_s, ss, c, eps=0.05, shift=shift, D=D_s, lam=lam_s)
+    return LayeredPair(U, S, D_u, lam_u, D_s, lam_s, n_layers)
+
+
 def crop(mesh: Mesh, i0: int, ni: int, k0: int, nk: int) -> Mesh:
     """Non-periodic crop of ni x nk quads starting at quad (i0, k0)."""
     idx = (np.arange(i0, i0 + ni + 1) % mesh.n_theta_v)
