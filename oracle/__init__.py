@@ -71,6 +71,10 @@ def lib():
         L.orc_energy_balance.argtypes = [P, D, D, I32, I32, P]; L.orc_energy_balance.restype = C.c_int
         L.orc_mismatch.argtypes = [P, I64, P, P, D, D, I32, I32, I32, P, P, P, P, C.c_int]
         L.orc_mismatch.restype = C.c_int
+        L.orc_pertbp_anomaly.argtypes = [D, D, P, P, P, P]; L.orc_pertbp_anomaly.restype = None
+        L.orc_pertbp_hamiltonian.argtypes = [P, D, D, D]; L.orc_pertbp_hamiltonian.restype = D
+        L.orc_pertbp_flow.argtypes = [P, P, P, I64, D, D, D, D, I64, C.c_int]
+        L.orc_pertbp_flow.restype = C.c_int
         L.orc_max_threads.argtypes = []; L.orc_max_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -226,6 +230,41 @@ def rk8_tangent(states: np.ndarray, dirs: np.ndarray, e_col: int, mu: float, e: 
 def jacobi(state, mu: float) -> float:
     y = np.ascontiguousarray(state, dtype=np.float64)
     return float(lib().orc_jacobi(_ptr(y), float(mu)))
+
+
+def pertbp_anomaly(t: float, eps: float):
+    """(E, rho, n, nu) of the primaries' orbit at time t (Sec. 3.3): eccentric
+    anomaly, separation 1 - eps cos E, rate of the true anomaly, true anomaly."""
+    v = [C.c_double() for _ in range(4)]
+    lib().orc_pertbp_anomaly(float(t), float(eps), *[C.byref(x) for x in v])
+    return tuple(x.value for x in v)
+
+
+def pertbp_hamiltonian(state, mu: float, eps: float, t: float) -> float:
+    z = np.ascontiguousarray(state, dtype=np.float64)
+    return float(lib().orc_pertbp_hamiltonian(_ptr(z), float(mu), float(eps), float(t)))
+
+
+def pertbp_flow(states: np.ndarray, mu: float, eps: float, t0: float, t1: float, nsteps: int,
+                stm: bool = False, nthreads: int = 0):
+    """Flow of the position-momentum elliptic problem from t0 to t1 in nsteps
+    RK8 steps; returns out (n,4) or (out, stm (n,4,4)) with stm[p, i, j] =
+    d out_i / d in_j."""
+    x = np.ascontiguousarray(states, dtype=np.float64).reshape(-1, 4)
+    out = np.empty_like(x)
+    M = np.empty((x.shape[0], 4, 4)) if stm else None
+    rc = lib().orc_pertbp_flow(_ptr(x), _ptr(out), _ptr(M) if stm else None, x.shape[0], float(mu), float(eps),
+                               float(t0), float(t1), int(nsteps), int(nthreads))
+    if rc != 0:
+        raise RuntimeError("orc_pertbp_flow failed")
+    return (out, M) if stm else out
+
+
+def pertbp_map(states: np.ndarray, mu: float, eps: float, steps_per_period: int, n_periods: int,
+               stm: bool = False, nthreads: int = 0):
+    """Stroboscopic map F^n_periods at periapse (t from 0 to 2 pi n_periods)."""
+    return pertbp_flow(states, mu, eps, 0.0, 2.0 * np.pi * n_periods, steps_per_period * abs(n_periods),
+                       stm=stm, nthreads=nthreads)
 
 
 def energy_balance(state, mu: float, e: float, steps_per_period: int, n_periods: int) -> float:

@@ -21,6 +21,9 @@
  *   3. brute force over all triangle pairs        (Sec. 2.2, the plain definition)
  *   4. uniform-grid search with per-box lists     (Sec. 6.2.1)
  *   5. RK8 stroboscopic map, tangent, invariants  (Sec. 3, Sec. 4.1, Sec. 7)
+ *   6. the elliptic problem in position-momentum
+ *      coordinates, its flow and state transition
+ *      matrix                                      (Sec. 3.3, Sec. 4.1, Sec. 7)
  */
 #include <math.h>
 #include <stdint.h>
@@ -941,6 +944,170 @@ ORC_API int orc_mismatch(const double *params, int64_t K, const double *pu, cons
         }
     }
     return err ? -1 : 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 6. The elliptic problem in position-momentum coordinates (Sec. 3.3)        */
+/* ------------------------------------------------------------------------ */
+
+/* The primaries move on a Kepler ellipse of semi-major axis 1, eccentricity
+ * eps and period 2 pi, with periapse at t = 0, 2 pi, ... (mean anomaly M = t).
+ * The frame turns with the line of the primaries but is not rescaled: their
+ * separation is rho(t) = 1 - eps cos E(t), E the eccentric anomaly, and they
+ * sit at (-mu rho, 0) and ((1 - mu) rho, 0).  With n(t) = d nu / dt (nu the
+ * true anomaly) the Hamiltonian is
+ *   H = (px^2 + py^2)/2 + n (px y - py x) - (1 - mu)/r1 - mu/r2,
+ *   r1 = |(x + mu rho, y)|,  r2 = |(x - (1 - mu) rho, y)|,
+ * and the state z = (x, y, px, py) obeys z' = J grad H, J = [[0, I], [-I, 0]]. */
+
+/* Eccentric anomaly: the root of g(E) = E - eps sin E - M.  g is increasing
+ * (g' = 1 - eps cos E > 0) and |E - M| = eps |sin E| <= eps, so the root lies
+ * in [M - eps, M + eps]; plain bisection until the bracket stops shrinking
+ * pins it to the last bit.  M is first reduced to [-pi, pi] (E - M is 2 pi
+ * periodic in M). */
+static double kepler_E(double M, double eps)
+{
+    double k = floor(M / ORC_2PI + 0.5);
+    double Mr = M - k * ORC_2PI;
+    double lo = Mr - eps, hi = Mr + eps;
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        if (mid - eps * sin(mid) - Mr < 0.0) lo = mid;
+        else hi = mid;
+    }
+    double glo = fabs(lo - eps * sin(lo) - Mr), ghi = fabs(hi - eps * sin(hi) - Mr);
+    return (glo <= ghi ? lo : hi) + k * ORC_2PI;
+}
+
+/* E(t), rho(t) = 1 - eps cos E, n(t) = sqrt(1 - eps^2) / rho^2 (the rate of
+ * the true anomaly: dE/dt = 1/rho and d nu/dE = sqrt(1 - eps^2)/rho), and
+ * nu(t) itself from tan(nu/2) = sqrt((1+eps)/(1-eps)) tan(E/2), continued
+ * through the periapse passages. */
+ORC_API void orc_pertbp_anomaly(double t, double eps, double *E, double *rho, double *n, double *nu)
+{
+    double Ea = kepler_E(t, eps);
+    double r = 1.0 - eps * cos(Ea);
+    double k = floor(Ea / ORC_2PI + 0.5);
+    double Er = Ea - k * ORC_2PI;
+    double v = 2.0 * atan2(sqrt(1.0 + eps) * sin(0.5 * Er), sqrt(1.0 - eps) * cos(0.5 * Er));
+    if (E) *E = Ea;
+    if (rho) *rho = r;
+    if (n) *n = sqrt(1.0 - eps * eps) / (r * r);
+    if (nu) *nu = v + k * ORC_2PI;
+}
+
+/* H at (z, t). */
+ORC_API double orc_pertbp_hamiltonian(const double *z, double mu, double eps, double t)
+{
+    double rho, n;
+    orc_pertbp_anomaly(t, eps, NULL, &rho, &n, NULL);
+    double x = z[0], y = z[1], px = z[2], py = z[3];
+    double r1 = sqrt((x + mu * rho) * (x + mu * rho) + y * y);
+    double r2 = sqrt((x - (1.0 - mu) * rho) * (x - (1.0 - mu) * rho) + y * y);
+    return 0.5 * (px * px + py * py) + n * (px * y - py * x) - (1.0 - mu) / r1 - mu / r2;
+}
+
+/* Gradient and Hessian of H in (x, y, px, py) at time t, then
+ * z' = J grad H and, for a tangent column v, v' = J Hess(H) v. */
+static void pertbp_rhs(double mu, double eps, double t, const double *z, const double *V, int ncol,
+                       double *dz, double *dV)
+{
+    double rho, n;
+    orc_pertbp_anomaly(t, eps, NULL, &rho, &n, NULL);
+    double x = z[0], y = z[1], px = z[2], py = z[3];
+    double d1 = x + mu * rho, d2 = x - (1.0 - mu) * rho;
+    double r1s = d1 * d1 + y * y, r2s = d2 * d2 + y * y;
+    double r1 = sqrt(r1s), r2 = sqrt(r2s);
+    double a1 = (1.0 - mu) / (r1s * r1), a2 = mu / (r2s * r2);                 /* m_i / r_i^3 */
+    double b1 = 3.0 * (1.0 - mu) / (r1s * r1s * r1), b2 = 3.0 * mu / (r2s * r2s * r2);   /* 3 m_i / r_i^5 */
+    double g[4];                                   /* grad H */
+    g[0] = -n * py + a1 * d1 + a2 * d2;
+    g[1] = n * px + a1 * y + a2 * y;
+    g[2] = px + n * y;
+    g[3] = py - n * x;
+    dz[0] = g[2];
+    dz[1] = g[3];
+    dz[2] = -g[0];
+    dz[3] = -g[1];
+    if (ncol == 0) return;
+    double Hs[4][4];                               /* Hess H (symmetric) */
+    Hs[0][0] = a1 + a2 - b1 * d1 * d1 - b2 * d2 * d2;
+    Hs[1][1] = a1 + a2 - b1 * y * y - b2 * y * y;
+    Hs[0][1] = Hs[1][0] = -b1 * d1 * y - b2 * d2 * y;
+    Hs[0][2] = Hs[2][0] = 0.0;
+    Hs[0][3] = Hs[3][0] = -n;
+    Hs[1][2] = Hs[2][1] = n;
+    Hs[1][3] = Hs[3][1] = 0.0;
+    Hs[2][2] = Hs[3][3] = 1.0;
+    Hs[2][3] = Hs[3][2] = 0.0;
+    for (int j = 0; j < ncol; ++j) {
+        const double *v = V + 4 * j;
+        double w[4];
+        for (int i = 0; i < 4; ++i) w[i] = Hs[i][0] * v[0] + Hs[i][1] * v[1] + Hs[i][2] * v[2] + Hs[i][3] * v[3];
+        double *dv = dV + 4 * j;
+        dv[0] = w[2];
+        dv[1] = w[3];
+        dv[2] = -w[0];
+        dv[3] = -w[1];
+    }
+}
+
+/* One RK8 step of the state with ncol tangent columns (column-major, V[4 j + i]). */
+static void pertbp_step(double mu, double eps, double t0, double h, double *z, double *V, int ncol)
+{
+    double k[11][4], K[11][16], zs[4], Vs[16];
+    for (int i = 0; i < 11; ++i) {
+        for (int c = 0; c < 4; ++c) {
+            double acc = 0.0;
+            for (int j = 0; j < i; ++j) acc += CV_A[i][j] * k[j][c];
+            zs[c] = z[c] + h * acc;
+        }
+        for (int c = 0; c < 4 * ncol; ++c) {
+            double acc = 0.0;
+            for (int j = 0; j < i; ++j) acc += CV_A[i][j] * K[j][c];
+            Vs[c] = V[c] + h * acc;
+        }
+        pertbp_rhs(mu, eps, t0 + CV_C[i] * h, zs, Vs, ncol, k[i], K[i]);
+    }
+    for (int c = 0; c < 4; ++c) {
+        double acc = 0.0;
+        for (int i = 0; i < 11; ++i) acc += CV_B[i] * k[i][c];
+        z[c] = z[c] + h * acc;
+    }
+    for (int c = 0; c < 4 * ncol; ++c) {
+        double acc = 0.0;
+        for (int i = 0; i < 11; ++i) acc += CV_B[i] * K[i][c];
+        V[c] = V[c] + h * acc;
+    }
+}
+
+/* Flow from t0 to t1 in nsteps equal RK8 steps (stage k of step s at time
+ * t0 + s h + c_k h, h = (t1 - t0)/nsteps).  out: n x 4.  stm (optional):
+ * n x 16, row-major d out_i / d in_j, from the variational equations
+ * integrated with the same stages (the exact derivative of the discrete
+ * flow).  The stroboscopic map F^m is t0 = 0, t1 = 2 pi m. */
+ORC_API int orc_pertbp_flow(const double *in, double *out, double *stm, int64_t n, double mu, double eps,
+                            double t0, double t1, int64_t nsteps, int nthreads)
+{
+    if (nsteps < 0 || !(eps >= 0.0 && eps < 1.0)) return -1;
+    cv_init();
+    double h = nsteps > 0 ? (t1 - t0) / (double)nsteps : 0.0;
+    int ncol = stm ? 4 : 0;
+    int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 4)
+    for (int64_t p = 0; p < n; ++p) {
+        double z[4], V[16];
+        for (int c = 0; c < 4; ++c) z[c] = in[4 * p + c];
+        for (int j = 0; j < 4; ++j)
+            for (int i = 0; i < 4; ++i) V[4 * j + i] = i == j ? 1.0 : 0.0;
+        for (int64_t s = 0; s < nsteps; ++s) pertbp_step(mu, eps, t0 + (double)s * h, h, z, V, ncol);
+        for (int c = 0; c < 4; ++c) out[4 * p + c] = z[c];
+        if (stm)
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) stm[16 * p + 4 * i + j] = V[4 * j + i];
+    }
+    return 0;
 }
 
 /* Threads the OpenMP loops of this library use. */

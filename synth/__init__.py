@@ -293,6 +293,26 @@ def random_states(n: int, seed: int, center=UNSTABLE_BASE, spread: float = 1e-2)
     return np.ascontiguousarray(c[None, :] + rng.uniform(-spread, spread, size=(n, 4)))
 
 
+def periapse_position_momentum(states: np.ndarray, eps: float) -> np.ndarray:
+    """Pulsating-coordinate states (x, y, x', y') at periapse (f = 0) rewritten
+    as states (x, y, px, py) of the non-pulsating position-momentum frame at
+    t = 0: positions scale by the separation 1 - eps, velocities by
+    (1 - eps) n0 with n0 = sqrt(1 - eps^2) / (1 - eps)^2 the rate of the true
+    anomaly, and p = v + n0 (-y, x).  Used to seed both frames with the same
+    physical points."""
+    z = np.asarray(states, dtype=np.float64)
+    n0 = math.sqrt(1.0 - eps * eps) / (1.0 - eps) ** 2
+    q = (1.0 - eps) * z[..., :2]
+    v = (1.0 - eps) * n0 * z[..., 2:]
+    p = v + n0 * np.stack([-q[..., 1], q[..., 0]], axis=-1)
+    return np.ascontiguousarray(np.concatenate([q, p], axis=-1))
+
+
+def pm_random_states(n: int, seed: int, eps: float, center=UNSTABLE_BASE, spread: float = 1e-2) -> np.ndarray:
+    """random_states mapped to the position-momentum frame at periapse."""
+    return periapse_position_momentum(random_states(n, seed, center, spread), eps)
+
+
 # ---------------------------------------------------------------------------
 # Planted refinement problems (known roots of the mismatch)
 # ---------------------------------------------------------------------------
