@@ -129,7 +129,7 @@ def main():
     ap.add_argument("--n", type=int, default=512, help="quads per axis of each surface")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--kappa", type=float, default=0.0, help="cell edge / mean triangle diameter (0 = autotune)")
-    ap.add_argument("--legs", default="search,allpairs,family,layers,rk8,refine,copy,cpu")
+    ap.add_argument("--legs", default="search,allpairs,family,layers,rk8,pertbp,refine,copy,cpu")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -335,6 +335,41 @@ def main():
         log(f"propagated: F^3 + F^-3 of 2 x {base_u.numel() // 4} vertices in {t_rk * 1e3:.1f} ms, search "
             f"{t_s * 1e3:.2f} ms ({len(hp)} hits), refine {t_r * 1e3:.1f} ms ({int(np.sum(sr == 0))} converged)")
         del gu, gs, base_u, base_s, sp
+
+    # ------------- the position-momentum model of Sec. 3.3: F^+-3 and DF^3
+    if "pertbp" in legs:
+        MU, ECC, STEPS = 2.527e-5, 0.0094, 4000
+        (mu_mesh, _), (ms_mesh, _) = synth.propagated_patches(2048, 256, args.seed)
+        zu = torch.tensor(synth.periapse_position_momentum(mu_mesh.verts.reshape(-1, 4), ECC)).cuda()
+        zs = torch.tensor(synth.periapse_position_momentum(ms_mesh.verts.reshape(-1, 4), ECC)).cuda()
+        ou, os_ = torch.empty_like(zu), torch.empty_like(zs)
+        ms.pertbp_map(zu[:1024], MU, ECC, STEPS, 1)          # stage table, warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ms.pertbp_map(zu, MU, ECC, STEPS, 3, out=ou)
+        ms.pertbp_map(zs, MU, ECC, STEPS, -3, out=os_)
+        torch.cuda.synchronize()
+        t_pm = time.perf_counter() - t0
+        vsteps = (zu.shape[0] + zs.shape[0]) * STEPS * 3
+        out["pertbp_vertex_steps_per_s"] = vsteps / t_pm
+        out["pertbp_ms_F3_and_Fm3_two_patches"] = t_pm * 1e3
+        n_stm = 1 << 18
+        zst = zu[:n_stm].contiguous()
+        stm_t = {}
+        for cols in (1, 2, 4):
+            ms.pertbp_map_stm(zst[:256], MU, ECC, STEPS, 1, cols_per_thread=cols)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ms.pertbp_map_stm(zst, MU, ECC, STEPS, 3, cols_per_thread=cols)
+            torch.cuda.synchronize()
+            stm_t[cols] = time.perf_counter() - t0
+        best = min(stm_t, key=stm_t.get)
+        out["pertbp_stm_vertex_steps_per_s"] = n_stm * STEPS * 3 / stm_t[best]
+        out["pertbp_stm_ms_by_cols_per_thread"] = {str(k): v * 1e3 for k, v in stm_t.items()}
+        log(f"pertbp: F^3 + F^-3 of 2 x {zu.shape[0]} states in {t_pm * 1e3:.1f} ms "
+            f"({vsteps / t_pm:.3e} vertex-steps/s); DF^3 of {n_stm} states in "
+            + ", ".join(f"{v * 1e3:.1f} ms ({k} cols/thread)" for k, v in stm_t.items()))
+        del zu, zs, ou, os_, zst
 
     # ------------------------- plain device copy (HBM reference, counter scale)
     if "copy" in legs:

@@ -297,6 +297,41 @@ typedef struct {
 int propagate_vertices(const double *in_dev, double *out_dev, int64_t n_vertices,
                        const map_params_t *params, void *stream);
 
+/*
+ * The same problem in the position-momentum coordinates of Sec. 3.3: time t,
+ * primaries on a Kepler ellipse of semi-major axis 1, eccentricity
+ * params->e and period 2 pi with periapse at t = 0, 2 pi, ...; the frame
+ * turns with the primaries but is not rescaled, so they sit at (-mu rho, 0)
+ * and ((1 - mu) rho, 0) with rho(t) = 1 - e cos E(t), E - e sin E = t.  The
+ * state z = (x, y, px, py) follows Hamilton's equations of
+ *   H = (px^2 + py^2)/2 + n(t) (px y - py x) - (1 - mu)/r1 - mu/r2,
+ *   r1 = |(x + mu rho, y)|, r2 = |(x - (1 - mu) rho, y)|,
+ * n(t) the rate of the primaries' true anomaly.  The stroboscopic map F
+ * advances t by 2 pi from a periapse (Sec. 4.1); steps_per_period RK8 steps
+ * (Cooper & Verner) per period, F^n_periods, negative = backwards.
+ */
+
+/* pertbp_map -- out = F^n(in) for n_states states (x, y, px, py), AoS 4
+ * doubles each, device arrays.  in_dev may equal out_dev.  Asynchronous on
+ * stream; MS_E_ARG for a bad pointer, steps_per_period <= 0, e outside
+ * [0, 1) or mu outside [0, 1]. */
+int pertbp_map(const double *in_dev, double *out_dev, int64_t n_states, const map_params_t *params,
+               void *stream);
+
+/* pertbp_map_stm -- F^n(in) and its state transition matrix DF^n (the
+ * matrices of the derivative formulas of Sec. 7), from the variational
+ * equations integrated with the same RK8 stages (the exact derivative of the
+ * discrete map).
+ *   out_dev  n_states x 4 (may be NULL; may equal in_dev)
+ *   stm_dev  n_states x 16, row-major per state: stm[16 p + 4 i + j] =
+ *            d out_i / d in_j; must not overlap in_dev or out_dev.
+ *   cols_per_thread  1, 2 or 4 columns of DF per GPU thread (4 / cols
+ *            threads per state), or 0 for the default (4); a tuning choice
+ *            only, the results are identical.
+ * Asynchronous; errors as pertbp_map. */
+int pertbp_map_stm(const double *in_dev, double *out_dev, double *stm_dev, int64_t n_states,
+                   const map_params_t *params, int32_t cols_per_thread, void *stream);
+
 /* ------------------------------------------------------------ refinement */
 
 /*

@@ -25,7 +25,7 @@ EXPORTS = ("last_error", "mesh_build", "mesh_free", "mesh_info", "mesh_update", 
            "search_workspace_size", "search_intersections", "search_intersections_async", "narrow_allpairs", "propagate_vertices",
            "search_profile_enable", "search_profile_read", "batch_create", "batch_search", "batch_needed",
            "batch_free", "refine_workspace_size", "refine_grad", "refine_newton", "layer_pairs",
-           "half_layer_bounds", "half_layer_columns")
+           "half_layer_bounds", "half_layer_columns", "pertbp_map", "pertbp_map_stm")
 
 MS_REFINE_RESIDUAL, MS_REFINE_ADJOINT, MS_REFINE_TANGENT, MS_REFINE_NEWTON = 0, 1, 2, 3
 NEWTON_STATUS = {0: "converged", 1: "trial limit", 2: "step too small", 3: "singular", 4: "non-finite"}
@@ -91,6 +91,10 @@ def lib():
         L.narrow_allpairs.argtypes = [P, P, P, I64, P, P, P]; L.narrow_allpairs.restype = C.c_int
         L.propagate_vertices.argtypes = [P, P, I64, C.POINTER(MapParams), P]
         L.propagate_vertices.restype = C.c_int
+        L.pertbp_map.argtypes = [P, P, I64, C.POINTER(MapParams), P]
+        L.pertbp_map.restype = C.c_int
+        L.pertbp_map_stm.argtypes = [P, P, P, I64, C.POINTER(MapParams), I32, P]
+        L.pertbp_map_stm.restype = C.c_int
         L.mesh_update.argtypes = [P, P]; L.mesh_update.restype = C.c_int
         L.batch_create.argtypes = [I32, P, P, P, I64, I64, P, C.POINTER(P), C.POINTER(C.c_size_t)]
         L.batch_create.restype = C.c_int
@@ -542,6 +546,35 @@ def propagate(states, mu: float, e: float, steps_per_period: int, n_periods: int
     _check(lib().propagate_vertices(C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()), x.numel() // 4,
                                     C.byref(p), _stream()))
     return out
+
+
+def pertbp_map(states, mu: float, eps: float, steps_per_period: int, n_periods: int, out=None):
+    """F^n_periods of (n, 4) position-momentum states (x, y, px, py) of the
+    elliptic problem of Sec. 3.3 on the GPU (pertbp_map of the C ABI)."""
+    torch = _torch()
+    x = torch.as_tensor(states, dtype=torch.float64).to("cuda").contiguous()
+    assert x.shape[-1] == 4
+    if out is None:
+        out = torch.empty_like(x)
+    p = MapParams(float(mu), float(eps), int(steps_per_period), int(n_periods))
+    _check(lib().pertbp_map(C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()), x.numel() // 4, C.byref(p),
+                            _stream()))
+    return out
+
+
+def pertbp_map_stm(states, mu: float, eps: float, steps_per_period: int, n_periods: int,
+                   cols_per_thread: int = 0, want_out: bool = True):
+    """(F^n(states), DF^n) on the GPU (pertbp_map_stm of the C ABI): out (n, 4)
+    (None unless want_out) and stm (n, 4, 4) with stm[p, i, j] = d out_i / d in_j."""
+    torch = _torch()
+    x = torch.as_tensor(states, dtype=torch.float64).to("cuda").contiguous().reshape(-1, 4)
+    out = torch.empty_like(x) if want_out else None
+    stm = torch.empty((x.shape[0], 4, 4), dtype=torch.float64, device="cuda")
+    p = MapParams(float(mu), float(eps), int(steps_per_period), int(n_periods))
+    _check(lib().pertbp_map_stm(C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()) if out is not None else None,
+                                C.c_void_p(stm.data_ptr()), x.shape[0], C.byref(p), int(cols_per_thread),
+                                _stream()))
+    return out, stm
 
 
 # ------------------------------------------------------------- refinement

@@ -53,6 +53,31 @@ Tableau make_tableau()
     return T;
 }
 
+// Root of Kepler's equation E - e sin E = M for the primaries' orbit
+// (Sec. 3.3, mean anomaly M = t).  E - M is 2 pi periodic in M and lies in
+// [-e, e]; Newton's method from E = M + e sin M, kept inside that bracket
+// (a step that leaves it is replaced by bisection), converges for every
+// 0 <= e < 1.
+double eccentric_anomaly(double M, double e)
+{
+    const double k = floor(M / RK_TWO_PI + 0.5);
+    const double Mr = M - k * RK_TWO_PI;
+    double lo = Mr - e, hi = Mr + e;
+    double E = Mr + e * sin(Mr);
+    if (!(E >= lo && E <= hi)) E = Mr;
+    for (int it = 0; it < 100 && e > 0.0; ++it) {
+        const double g = E - e * sin(E) - Mr;
+        if (g == 0.0) break;
+        if (g < 0.0) lo = E; else hi = E;
+        double En = E - g / (1.0 - e * cos(E));
+        if (!(En > lo && En < hi)) En = 0.5 * (lo + hi);
+        const bool done = fabs(En - E) <= 2e-16 * (1.0 + fabs(E));
+        E = En;
+        if (done) break;
+    }
+    return E + k * RK_TWO_PI;
+}
+
 // Stage tables per (device, e, steps per period, kind), kept for the life of
 // the process.
 std::mutex g_tab_mu;
@@ -89,12 +114,21 @@ int stage_table(double e, int steps, int kind, double **out)
     if (it != g_tabs.end()) { *out = it->second; return MS_OK; }
     const Tableau &T = cv_tableau();
     const double h = RK_TWO_PI / (double)steps;
-    std::vector<double> w((size_t)steps * S);
+    const int per = kind == STAGE_RHO_N ? 2 : 1;
+    std::vector<double> w((size_t)steps * S * per);
     for (int n = 0; n < steps; ++n)
         for (int i = 0; i < S; ++i) {
-            double cf = cos((double)n * h + T.c[i] * h);
-            double om = 1.0 / (1.0 + e * cf);
-            w[(size_t)n * S + i] = kind == STAGE_W ? om : -cf * om * om;
+            const double a = (double)n * h + T.c[i] * h;
+            const size_t at = ((size_t)n * S + i) * per;
+            if (kind == STAGE_RHO_N) {
+                double rho = 1.0 - e * cos(eccentric_anomaly(a, e));
+                w[at] = rho;
+                w[at + 1] = sqrt(1.0 - e * e) / (rho * rho);
+            } else {
+                double cf = cos(a);
+                double om = 1.0 / (1.0 + e * cf);
+                w[at] = kind == STAGE_W ? om : -cf * om * om;
+            }
         }
     double *d = nullptr;
     MS_HIP(hipMalloc(&d, w.size() * sizeof(double)));

@@ -1,8 +1,9 @@
 // rk8_core.hpp -- pieces shared by the stroboscopic map (rk8.hip) and the
 // refinement kernels (refine.hip): the Cooper-Verner order-8 tableau, the
 // per-step stage tables of the time-dependent factor w(f) = 1 / (1 + e cos f),
-// and the vector field of the planar elliptic restricted three-body problem in
-// pulsating rotating coordinates (the model family of Sec. 3.2-3.3).
+// and the vector fields of the planar elliptic restricted three-body problem:
+// pulsating rotating coordinates with the true anomaly as time, and the
+// position-momentum form with time t of Sec. 3.3.
 #pragma once
 
 #include "ms_internal.hpp"
@@ -32,12 +33,16 @@ bool cv_pattern_ok();
 
 // Host: device table of one period of stage values, steps x RK_S doubles,
 // entry (n, i) at the abscissa f = (n + c_i) h, h = 2 pi / steps.
-//   STAGE_W    w(f) = 1 / (1 + e cos f)
-//   STAGE_DWDE dw/de = -cos f w(f)^2
-// w is 2 pi periodic and even in f, so one table serves every period and
-// both directions of integration.  Cached per (device, e, steps, kind) for
-// the life of the process.
-enum { STAGE_W = 0, STAGE_DWDE = 1 };
+//   STAGE_W     w(f) = 1 / (1 + e cos f)
+//   STAGE_DWDE  dw/de = -cos f w(f)^2
+//   STAGE_RHO_N two doubles per entry at the time t = (n + c_i) h: the
+//               separation of the primaries rho = 1 - e cos E(t) and the
+//               rate of their true anomaly n(t) = sqrt(1 - e^2) / rho^2, E the
+//               eccentric anomaly (E - e sin E = t, periapse at t = 0).
+// All are 2 pi periodic and even in the abscissa, so one table serves every
+// period and both directions of integration.  Cached per (device, e, steps,
+// kind) for the life of the process.
+enum { STAGE_W = 0, STAGE_DWDE = 1, STAGE_RHO_N = 2 };
 int stage_table(double e, int steps, int kind, double **out);
 
 struct Model {
@@ -62,6 +67,54 @@ MS_D void rk_field(const Model &md, double w, const double y[4], double k[4])
     k[1] = y[3];
     k[2] = 2.0 * y[3] + w * Ox;
     k[3] = -2.0 * y[2] + w * Oy;
+}
+
+// Position-momentum model (Sec. 3.3) at a stage with separation rho and
+// frame rate n: z' = J grad H for
+//   H = (px^2 + py^2)/2 + n (px y - py x) - (1 - mu)/r1 - mu/r2,
+//   r1 = |(x + mu rho, y)|, r2 = |(x - (1 - mu) rho, y)|.
+MS_D void pm_field(const Model &md, double rho, double n, const double z[4], double k[4])
+{
+#pragma clang fp contract(fast)
+    double x = z[0], y = z[1];
+    double d1 = x + md.mu * rho, d2 = x - md.one_minus_mu * rho;
+    double y2 = y * y;
+    double r1s = d1 * d1 + y2, r2s = d2 * d2 + y2;
+    double r1 = sqrt(r1s), r2 = sqrt(r2s);
+    double a1 = md.one_minus_mu / (r1s * r1), a2 = md.mu / (r2s * r2);   // m_i / r_i^3
+    k[0] = z[2] + n * y;
+    k[1] = z[3] - n * x;
+    k[2] = n * z[3] - a1 * d1 - a2 * d2;
+    k[3] = -n * z[2] - (a1 + a2) * y;
+}
+
+// The same field with NC tangent columns v: v' = J Hess(H) v.
+template <int NC>
+MS_D void pm_field_var(const Model &md, double rho, double n, const double z[4], const double v[NC][4],
+                       double k[4], double kv[NC][4])
+{
+#pragma clang fp contract(fast)
+    double x = z[0], y = z[1];
+    double d1 = x + md.mu * rho, d2 = x - md.one_minus_mu * rho;
+    double y2 = y * y;
+    double r1s = d1 * d1 + y2, r2s = d2 * d2 + y2;
+    double r1 = sqrt(r1s), r2 = sqrt(r2s);
+    double a1 = md.one_minus_mu / (r1s * r1), a2 = md.mu / (r2s * r2);   // m_i / r_i^3
+    double b1 = 3.0 * a1 / r1s, b2 = 3.0 * a2 / r2s;                       // 3 m_i / r_i^5
+    double hxx = a1 + a2 - b1 * d1 * d1 - b2 * d2 * d2;
+    double hyy = a1 + a2 - (b1 + b2) * y2;
+    double hxy = -(b1 * d1 + b2 * d2) * y;
+    k[0] = z[2] + n * y;
+    k[1] = z[3] - n * x;
+    k[2] = n * z[3] - a1 * d1 - a2 * d2;
+    k[3] = -n * z[2] - (a1 + a2) * y;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        kv[c][0] = v[c][2] + n * v[c][1];
+        kv[c][1] = v[c][3] - n * v[c][0];
+        kv[c][2] = n * v[c][3] - hxx * v[c][0] - hxy * v[c][1];
+        kv[c][3] = -n * v[c][2] - hxy * v[c][0] - hyy * v[c][1];
+    }
 }
 
 // Gradient and Hessian of Omega at (x, y).
