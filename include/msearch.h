@@ -19,8 +19,11 @@
  *     HIP include); NULL means the default stream.  All device work is queued
  *     on that stream.  Unless stated otherwise a call returns once its work is
  *     queued.
- *   - FP64 throughout.  Floating-point expressions in the kernels are built
- *     with contraction off, so each operation rounds once as written.
+ *   - FP64 throughout.  The search kernels are built with contraction off,
+ *     so each operation of the pair predicate rounds once as written (the
+ *     oracle does the same, and the decisions agree bit for bit).  The
+ *     Runge-Kutta and refinement kernels let the compiler fuse multiply-adds;
+ *     their results agree with the oracle within the stated tolerances.
  */
 #ifndef MSEARCH_H
 #define MSEARCH_H
