@@ -129,7 +129,7 @@ def main():
     ap.add_argument("--n", type=int, default=512, help="quads per axis of each surface")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--kappa", type=float, default=0.0, help="cell edge / mean triangle diameter (0 = autotune)")
-    ap.add_argument("--legs", default="search,allpairs,family,layers,rk8,pertbp,refine,copy,cpu")
+    ap.add_argument("--legs", default="search,allpairs,family,layers,rk8,pertbp,spectral,refine,copy,cpu")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -370,6 +370,43 @@ def main():
             f"({vsteps / t_pm:.3e} vertex-steps/s); DF^3 of {n_stm} states in "
             + ", ".join(f"{v * 1e3:.1f} ms ({k} cols/thread)" for k, v in stm_t.items()))
         del zu, zs, ou, os_, zst
+
+    # ------------- spectral theta operations (Sec. 6.1 translation, Sec. 7)
+    if "spectral" in legs:
+        N_TH, M_ROWS = 2048, 4096
+        rng = np.random.default_rng(args.seed)
+        rows = torch.randn((M_ROWS, N_TH, 4), dtype=torch.float64, device="cuda",
+                           generator=torch.Generator(device="cuda").manual_seed(args.seed))
+        rho = torch.tensor(rng.uniform(-np.pi, np.pi, M_ROWS), device="cuda")
+        dst = torch.empty_like(rows)
+        sp_t = {}
+        for order in (0, 1):
+            ms.theta_shift(rows, rho, order, out=dst)
+            torch.cuda.synchronize()
+            reps = 10
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ms.theta_shift(rows, rho, order, out=dst)
+            torch.cuda.synchronize()
+            sp_t[order] = (time.perf_counter() - t0) / reps
+        nbytes = 2 * rows.numel() * 8
+        out["spectral_shift_ms"] = sp_t[0] * 1e3
+        out["spectral_shift_GBps"] = nbytes / sp_t[0] / 1e9
+        out["spectral_derivative_ms"] = sp_t[1] * 1e3
+        nq = 1 << 16
+        qr = torch.tensor(rng.integers(0, M_ROWS, nq), device="cuda")
+        qt = torch.tensor(rng.uniform(0, 2 * np.pi, nq), device="cuda")
+        ms.theta_interp(rows, qr, qt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ms.theta_interp(rows, qr, qt)
+        torch.cuda.synchronize()
+        t_i = time.perf_counter() - t0
+        out["spectral_interp_queries_per_s"] = nq / t_i
+        log(f"spectral: shift of {M_ROWS} rows x {N_TH} samples in {sp_t[0] * 1e3:.3f} ms "
+            f"({nbytes / sp_t[0] / 1e9:.0f} GB/s algorithmic), derivative {sp_t[1] * 1e3:.3f} ms; "
+            f"{nq} interpolations in {t_i * 1e3:.2f} ms")
+        del rows, dst
 
     # ------------------------- plain device copy (HBM reference, counter scale)
     if "copy" in legs:

@@ -335,6 +335,39 @@ int pertbp_map(const double *in_dev, double *out_dev, int64_t n_states, const ma
 int pertbp_map_stm(const double *in_dev, double *out_dev, double *stm_dev, int64_t n_states,
                    const map_params_t *params, int32_t cols_per_thread, void *stream);
 
+/* ------------------------------------------------------- theta spectral */
+
+/*
+ * Periodic functions of theta sampled at theta_i = 2 pi i / n_theta (Sec. 6.1):
+ * a "row" is the n_theta vertices of one s-value of a mesh grid, AoS 4
+ * doubles per vertex (x, y, px, py), theta fastest, rows back to back: element
+ * (r, i) at 4 (r n_theta + i).  The operations act on each coordinate
+ * separately through the discrete Fourier series over the signed
+ * frequencies k in (-n_theta/2, n_theta/2]; for even n_theta the term at
+ * n_theta/2 is the real mode cos(n_theta theta / 2), so real rows give real
+ * results.
+ */
+
+/* theta_shift -- for each row r,
+ *   out(r, i) = d^order/dtheta^order of a_r(theta_i + rho_r),
+ * by an FFT, multiplication of coefficient k by (j k)^order e^{j k rho_r} and
+ * the inverse FFT (the translation of Sec. 6.1, used with rho = -n omega to
+ * put the points F^n(W(theta_i, s)) = W(theta_i + n omega, lambda^n s) back on
+ * the theta grid; order 1 is the theta derivative of Sec. 7).
+ *   rho_dev  n_rows doubles (one shift per row), or NULL to use rho for all.
+ *   n_theta  a power of two, 2 ... 2048; order 0, 1 or 2.
+ * in_dev may equal out_dev.  Asynchronous; MS_E_ARG for bad sizes or
+ * pointers. */
+int theta_shift(const double *in_dev, double *out_dev, int32_t n_theta, int64_t n_rows, const double *rho_dev,
+                double rho, int32_t order, void *stream);
+
+/* theta_interp -- trigonometric interpolation (Sec. 7): out_dev[4 q + c] is
+ * the value at theta_dev[q] of the trigonometric polynomial through the
+ * samples of row row_dev[q] (coordinate c).  Any n_theta >= 1.  A query with
+ * a row outside [0, n_rows) or a non-finite theta yields NaN.  Asynchronous. */
+int theta_interp(const double *rows_dev, int32_t n_theta, int64_t n_rows, const int64_t *row_dev,
+                 const double *theta_dev, int64_t n_query, double *out_dev, void *stream);
+
 /* ------------------------------------------------------------ refinement */
 
 /*

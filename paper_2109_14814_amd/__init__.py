@@ -25,7 +25,7 @@ EXPORTS = ("last_error", "mesh_build", "mesh_free", "mesh_info", "mesh_update", 
            "search_workspace_size", "search_intersections", "search_intersections_async", "narrow_allpairs", "propagate_vertices",
            "search_profile_enable", "search_profile_read", "batch_create", "batch_search", "batch_needed",
            "batch_free", "refine_workspace_size", "refine_grad", "refine_newton", "layer_pairs",
-           "half_layer_bounds", "half_layer_columns", "pertbp_map", "pertbp_map_stm")
+           "half_layer_bounds", "half_layer_columns", "pertbp_map", "pertbp_map_stm", "theta_shift", "theta_interp")
 
 MS_REFINE_RESIDUAL, MS_REFINE_ADJOINT, MS_REFINE_TANGENT, MS_REFINE_NEWTON = 0, 1, 2, 3
 NEWTON_STATUS = {0: "converged", 1: "trial limit", 2: "step too small", 3: "singular", 4: "non-finite"}
@@ -95,6 +95,10 @@ def lib():
         L.pertbp_map.restype = C.c_int
         L.pertbp_map_stm.argtypes = [P, P, P, I64, C.POINTER(MapParams), I32, P]
         L.pertbp_map_stm.restype = C.c_int
+        L.theta_shift.argtypes = [P, P, I32, I64, P, D, I32, P]
+        L.theta_shift.restype = C.c_int
+        L.theta_interp.argtypes = [P, I32, I64, P, P, I64, P, P]
+        L.theta_interp.restype = C.c_int
         L.mesh_update.argtypes = [P, P]; L.mesh_update.restype = C.c_int
         L.batch_create.argtypes = [I32, P, P, P, I64, I64, P, C.POINTER(P), C.POINTER(C.c_size_t)]
         L.batch_create.restype = C.c_int
@@ -575,6 +579,44 @@ def pertbp_map_stm(states, mu: float, eps: float, steps_per_period: int, n_perio
                                 C.c_void_p(stm.data_ptr()), x.shape[0], C.byref(p), int(cols_per_thread),
                                 _stream()))
     return out, stm
+
+
+def theta_shift(rows, rho, order: int = 0, out=None):
+    """d^order/dtheta^order of a(theta_i + rho) for rows (..., n_theta, 4)
+    (a cuda float64 tensor or array; rho a number or one value per row):
+    theta_shift of the C ABI."""
+    torch = _torch()
+    x = torch.as_tensor(rows, dtype=torch.float64).to("cuda").contiguous()
+    assert x.shape[-1] == 4 and x.dim() >= 2
+    n_theta = x.shape[-2]
+    n_rows = x.numel() // (4 * n_theta) if x.numel() else int(np.prod(x.shape[:-2]))
+    if out is None:
+        out = torch.empty_like(x)
+    if np.ndim(rho) == 0 and not torch.is_tensor(rho):
+        rd, rv = None, float(rho)
+    else:
+        rd = torch.as_tensor(rho, dtype=torch.float64).to("cuda").contiguous().reshape(-1)
+        if rd.numel() != n_rows:
+            raise ValueError("rho: one value per row")
+        rv = 0.0
+    _check(lib().theta_shift(_ptr(x), _ptr(out), int(n_theta), int(n_rows), _ptr(rd), rv, int(order), _stream()))
+    return out
+
+
+def theta_interp(rows, row_index, theta):
+    """Trigonometric interpolation: values (n_query, 4) at theta[q] of row
+    row_index[q] of rows (n_rows, n_theta, 4): theta_interp of the C ABI."""
+    torch = _torch()
+    x = torch.as_tensor(rows, dtype=torch.float64).to("cuda").contiguous()
+    assert x.shape[-1] == 4 and x.dim() == 3
+    r = torch.as_tensor(row_index, dtype=torch.int64).to("cuda").contiguous().reshape(-1)
+    t = torch.as_tensor(theta, dtype=torch.float64).to("cuda").contiguous().reshape(-1)
+    if r.numel() != t.numel():
+        raise ValueError("one row index per theta")
+    out = torch.empty((t.numel(), 4), dtype=torch.float64, device="cuda")
+    _check(lib().theta_interp(_ptr(x), int(x.shape[1]), int(x.shape[0]), _ptr(r), _ptr(t), t.numel(), _ptr(out),
+                              _stream()))
+    return out
 
 
 # ------------------------------------------------------------- refinement
