@@ -10,14 +10,18 @@
 //
 // theta_shift: one workgroup per row.  The two real pairs of a vertex are
 // packed as complex sequences z0 = x + i y and z1 = px + i py (the spectral
-// multiplier is Hermitian, so it acts on both parts independently); both sit
-// in LDS and go through a radix-4 Stockham FFT (a last radix-2 pass for odd
-// log2 n_theta), in place: each pass reads its butterflies into registers,
-// waits, then writes them back, so one buffer per sequence suffices.  The
-// twiddle factors e^{-2 pi i m / N} come from a table of N values made once
-// per (device, N) on the host and read through the caches.  The
-// multiplier (j k)^order e^{j k rho} is applied between the forward and the
-// inverse transform, and the result is scaled by 1 / n_theta on the way out.
+// multiplier is Hermitian, so it acts on both parts independently) and go
+// through a Stockham FFT of radix 8 (a last pass of radix 4 or 2 for the
+// remaining factor) that keeps both sequences in LDS, in place: each pass
+// reads its butterflies into registers, waits, then writes them back.  The
+// LDS index is padded by one slot per 8 so that the strided writes of the
+// first passes spread over the banks.  The first forward pass reads the row
+// straight from global memory and the last inverse pass writes it back
+// (scaled by 1 / N); the inverse runs the radices in reverse order, so the
+// last forward pass, the multiplier (j k)^order e^{j k rho} and the first
+// inverse pass work on the same registers with no LDS round trip between
+// them.  The twiddle factors e^{-2 pi i m / N} come from a table of N values
+// made once per (device, N) on the host and read through the caches.
 //
 // theta_interp: one wave per query, the barycentric form of the
 // trigonometric interpolant (no transform): with theta = theta_i0 + delta,
@@ -37,8 +41,20 @@ namespace ms {
 namespace {
 
 constexpr int SP_THREADS = 256;
-constexpr int SP_MAX_LOG2 = 11;   // n_theta <= 2048: 2 x 32 KiB of LDS per row
+constexpr int SP_MAX_LOG2 = 11;   // n_theta <= 2048: 2 x 36 KiB of LDS per row
 constexpr double SP_PI = 3.141592653589793238462643383279502884;
+#ifndef SP_RADIX
+#define SP_RADIX 8                // largest radix of a pass (4 or 8)
+#endif
+#ifndef SP_PAD_SHIFT
+#define SP_PAD_SHIFT 3            // one pad slot per 2^SP_PAD_SHIFT LDS elements (0: none)
+#endif
+
+// LDS slot of element i: padded so that the strided writes of the first
+// passes (stride R elements) spread over the banks.
+MS_D int pslot(int i) { return SP_PAD_SHIFT ? i + (i >> SP_PAD_SHIFT) : i; }
+template <int N>
+constexpr int padded_size() { return SP_PAD_SHIFT ? N + (N >> SP_PAD_SHIFT) : N; }
 
 MS_D double2 cmul(double2 a, double2 b)
 {
@@ -48,7 +64,26 @@ MS_D double2 cmul(double2 a, double2 b)
 MS_D double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 MS_D double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 
-// R-point DFT in place (R = 2 or 4); INV selects the sign of the exponent.
+// Multiplication by -i (forward) or +i (inverse).
+template <bool INV>
+MS_D double2 mul_mi(double2 b)
+{
+    return INV ? make_double2(-b.y, b.x) : make_double2(b.y, -b.x);
+}
+
+// 4-point DFT of (a, b, c, d) in place.
+template <bool INV>
+MS_D void dft4(double2 &a, double2 &b, double2 &c, double2 &d)
+{
+    double2 a0 = cadd(a, c), a1 = csub(a, c);
+    double2 b0 = cadd(b, d), b1 = mul_mi<INV>(csub(b, d));
+    a = cadd(a0, b0);
+    c = csub(a0, b0);
+    b = cadd(a1, b1);
+    d = csub(a1, b1);
+}
+
+// R-point DFT in place (R = 2, 4 or 8); INV selects the sign of the exponent.
 template <int R, bool INV>
 MS_D void small_dft(double2 *v)
 {
@@ -56,24 +91,66 @@ MS_D void small_dft(double2 *v)
         double2 a = v[0], b = v[1];
         v[0] = cadd(a, b);
         v[1] = csub(a, b);
+    } else if constexpr (R == 4) {
+        dft4<INV>(v[0], v[1], v[2], v[3]);
     } else {
-        double2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
-        double2 b0 = cadd(v[1], v[3]), b1 = csub(v[1], v[3]);
-        // -i b1 (forward) or +i b1 (inverse)
-        double2 jb1 = INV ? make_double2(-b1.y, b1.x) : make_double2(b1.y, -b1.x);
-        v[0] = cadd(a0, b0);
-        v[2] = csub(a0, b0);
-        v[1] = cadd(a1, jb1);
-        v[3] = csub(a1, jb1);
+        // even and odd halves, then X[k] = E[k] + w^k O[k], X[k+4] = E[k] - w^k O[k],
+        // w = e^{-+i pi / 4}
+        double2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+        double2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+        dft4<INV>(e0, e1, e2, e3);
+        dft4<INV>(o0, o1, o2, o3);
+        const double h = 0.70710678118654752440084436210484903928;
+        // w o1, w^2 o2 = -+i o2, w^3 o3
+        double2 t1 = INV ? make_double2((o1.x - o1.y) * h, (o1.x + o1.y) * h)
+                         : make_double2((o1.x + o1.y) * h, (o1.y - o1.x) * h);
+        double2 t2 = mul_mi<INV>(o2);
+        double2 t3 = INV ? make_double2(-(o3.x + o3.y) * h, (o3.x - o3.y) * h)
+                         : make_double2((o3.y - o3.x) * h, -(o3.x + o3.y) * h);
+        v[0] = cadd(e0, o0);
+        v[4] = csub(e0, o0);
+        v[1] = cadd(e1, t1);
+        v[5] = csub(e1, t1);
+        v[2] = cadd(e2, t2);
+        v[6] = csub(e2, t2);
+        v[3] = cadd(e3, t3);
+        v[7] = csub(e3, t3);
     }
 }
 
-// One Stockham pass of radix R over both sequences: butterfly j reads
-// z[j + r N/R], twiddles by e^{-+2 pi i r (j mod Ns) / (Ns R)} (entry
-// r (j mod Ns) N / (Ns R) of the table, conjugated for the inverse),
-// transforms, and writes z[(j / Ns) Ns R + (j mod Ns) + r Ns].
-template <int N, int R, bool INV>
-MS_D void stockham_pass(double2 (*z)[N], int Ns, const double2 *__restrict__ tw)
+// Radix of pass p of the forward transform: SP_RADIX while it fits, then 4
+// or 2 for the remaining factor.  The inverse transform runs the same radices
+// in reverse order, so that its first pass takes exactly the values the last
+// forward pass leaves in each thread's registers.
+template <int LOGN>
+struct Plan {
+    static constexpr int LR = SP_RADIX == 8 ? 3 : 2;
+    static constexpr int FULL = LOGN / LR;
+    static constexpr int REST = LOGN % LR;
+    static constexpr int NP = FULL + (REST ? 1 : 0);
+    static constexpr int radix(int p) { return p < FULL ? SP_RADIX : (REST == 2 ? 4 : 2); }
+    // sub-transform length Ns before forward pass p
+    static constexpr int ns_fwd(int p) { return p == 0 ? 1 : ns_fwd(p - 1) * radix(p - 1); }
+    static constexpr int radix_inv(int p) { return radix(NP - 1 - p); }
+    static constexpr int ns_inv(int p) { return p == 0 ? 1 : ns_inv(p - 1) * radix_inv(p - 1); }
+};
+
+// Where a pass takes its inputs from and puts its outputs.
+enum { FROM_LDS = 0, FROM_GLOBAL = 1 };
+
+// Stockham pass of radix R, sub-transform length Ns, over both sequences.
+// Butterfly j takes element j + r N/R (r = 0..R-1), twiddles it by
+// e^{-+2 pi i r (j mod Ns) / (Ns R)} (entry r (j mod Ns) N / (Ns R) of the
+// table, conjugated for the inverse), transforms, and gives element
+// (j / Ns) Ns R + (j mod Ns) + r Ns.  Inputs come from LDS or, for the first
+// forward pass, from the row in global memory; outputs go to LDS or, for the
+// last inverse pass, to global memory scaled by 1/N.  With MID the pass is
+// the last forward pass fused with the spectral multiplier and the first
+// inverse pass (radix R, Ns = 1).  One thread carries both sequences of its
+// butterflies, so vertices move between global memory and registers whole.
+template <int N, int R, int Ns, bool INV, int SRC, bool TO_GLOBAL, bool MID>
+MS_D void pass(double2 (*z)[padded_size<N>()], const double2 *__restrict__ tw, const double *src, double *dst,
+               double rho, int order)
 {
     constexpr int NB = N / R;
     constexpr int PER = (NB + SP_THREADS - 1) / SP_THREADS;
@@ -83,12 +160,20 @@ MS_D void stockham_pass(double2 (*z)[N], int Ns, const double2 *__restrict__ tw)
         const int j = threadIdx.x + q * SP_THREADS;
         if (NB % SP_THREADS == 0 || j < NB) {
 #pragma unroll
-            for (int s = 0; s < 2; ++s)
-#pragma unroll
-                for (int r = 0; r < R; ++r) v[s][q][r] = z[s][j + r * NB];
+            for (int r = 0; r < R; ++r) {
+                const int e = j + r * NB;
+                if constexpr (SRC == FROM_GLOBAL) {
+                    d4 w = load_d4(src + 4 * e);
+                    v[0][q][r] = make_double2(w.x, w.y);
+                    v[1][q][r] = make_double2(w.z, w.w);
+                } else {
+                    v[0][q][r] = z[0][pslot(e)];
+                    v[1][q][r] = z[1][pslot(e)];
+                }
+            }
             const int k = j % Ns;
             if (k != 0) {
-                const int stride = N / (Ns * R);
+                constexpr int stride = N / (Ns * R);
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
                     double2 w = tw[r * k * stride];
@@ -99,35 +184,83 @@ MS_D void stockham_pass(double2 (*z)[N], int Ns, const double2 *__restrict__ tw)
             }
 #pragma unroll
             for (int s = 0; s < 2; ++s) small_dft<R, INV>(v[s][q]);
+            if constexpr (MID) {
+                // here Ns = N / R, so the outputs are the coefficients k = j + r N/R
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int kk = j + r * NB;
+                    double2 m;
+                    if (2 * kk == N) {
+                        // the cosine mode: Re[(j N/2)^order e^{j (N/2) rho}]
+                        const double h = 0.5 * (double)N;
+                        double sn, cs;
+                        sincos(h * rho, &sn, &cs);
+                        m = make_double2(order == 0 ? cs : order == 1 ? -h * sn : -h * h * cs, 0.0);
+                    } else {
+                        const double ks = 2 * kk > N ? (double)(kk - N) : (double)kk;
+                        double sn, cs;
+                        sincos(ks * rho, &sn, &cs);
+                        m = make_double2(cs, sn);
+                        if (order == 1) m = make_double2(-ks * sn, ks * cs);
+                        else if (order == 2) m = make_double2(-ks * ks * cs, -ks * ks * sn);
+                    }
+                    v[0][q][r] = cmul(v[0][q][r], m);
+                    v[1][q][r] = cmul(v[1][q][r], m);
+                }
+                // first inverse pass: the same butterfly j, Ns = 1, no twiddles
+#pragma unroll
+                for (int s = 0; s < 2; ++s) small_dft<R, true>(v[s][q]);
+            }
         }
     }
-    __syncthreads();
+    // outputs of the fused pass follow the first inverse pass (Ns = 1)
+    constexpr int ns_out = MID ? 1 : Ns;
+    if constexpr (SRC == FROM_LDS && !TO_GLOBAL) __syncthreads();   // all reads before any write
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int j = threadIdx.x + q * SP_THREADS;
         if (NB % SP_THREADS == 0 || j < NB) {
-            const int k = j % Ns;
-            const int base = (j / Ns) * Ns * R + k;
+            const int base = (j / ns_out) * ns_out * R + j % ns_out;
 #pragma unroll
-            for (int s = 0; s < 2; ++s)
-#pragma unroll
-                for (int r = 0; r < R; ++r) z[s][base + r * Ns] = v[s][q][r];
+            for (int r = 0; r < R; ++r) {
+                const int e = base + r * ns_out;
+                if constexpr (TO_GLOBAL) {
+                    const double inv = 1.0 / (double)N;
+                    double2 *o = reinterpret_cast<double2 *>(dst + 4 * e);
+                    o[0] = make_double2(v[0][q][r].x * inv, v[0][q][r].y * inv);
+                    o[1] = make_double2(v[1][q][r].x * inv, v[1][q][r].y * inv);
+                } else {
+                    z[0][pslot(e)] = v[0][q][r];
+                    z[1][pslot(e)] = v[1][q][r];
+                }
+            }
         }
     }
-    __syncthreads();
+    if constexpr (!TO_GLOBAL) __syncthreads();
 }
 
-template <int LOGN, bool INV>
-MS_D void fft2(double2 (*z)[1 << LOGN], const double2 *__restrict__ tw)
+template <int LOGN, int P>
+MS_D void forward_passes(double2 (*z)[padded_size<1 << LOGN>()], const double2 *tw, const double *src)
 {
-    constexpr int N = 1 << LOGN;
-    int Ns = 1;
-#pragma unroll
-    for (int p = 0; p < LOGN / 2; ++p) {
-        stockham_pass<N, 4, INV>(z, Ns, tw);
-        Ns *= 4;
+    using PL = Plan<LOGN>;
+    if constexpr (P < PL::NP - 1) {
+        constexpr int N = 1 << LOGN;
+        constexpr int NS = PL::ns_fwd(P);
+        pass<N, PL::radix(P), NS, false, P == 0 ? FROM_GLOBAL : FROM_LDS, false, false>(z, tw, src, nullptr, 0.0, 0);
+        forward_passes<LOGN, P + 1>(z, tw, src);
     }
-    if constexpr (LOGN & 1) stockham_pass<N, 2, INV>(z, Ns, tw);
+}
+
+template <int LOGN, int P>
+MS_D void inverse_passes(double2 (*z)[padded_size<1 << LOGN>()], const double2 *tw, double *dst)
+{
+    using PL = Plan<LOGN>;
+    if constexpr (P < PL::NP) {
+        constexpr int N = 1 << LOGN;
+        constexpr int NS = PL::ns_inv(P);
+        pass<N, PL::radix_inv(P), NS, true, FROM_LDS, P == PL::NP - 1, false>(z, tw, nullptr, dst, 0.0, 0);
+        inverse_passes<LOGN, P + 1>(z, tw, dst);
+    }
 }
 
 template <int LOGN>
@@ -135,47 +268,20 @@ __global__ void __launch_bounds__(SP_THREADS) k_theta_shift(const double *in, do
                                                             const double2 *__restrict__ tw, const double *rho_dev,
                                                             double rho, int order)
 {
+    using PL = Plan<LOGN>;
     constexpr int N = 1 << LOGN;
-    __shared__ double2 z[2][N];
+    __shared__ double2 z[2][padded_size<N>()];
     const int64_t row = blockIdx.x;
     const double *src = in + row * (int64_t)N * 4;
-    for (int i = threadIdx.x; i < N; i += SP_THREADS) {
-        d4 v = load_d4(src + 4 * i);
-        z[0][i] = make_double2(v.x, v.y);
-        z[1][i] = make_double2(v.z, v.w);
-    }
-    __syncthreads();
-    fft2<LOGN, false>(z, tw);
-    const double r = rho_dev ? rho_dev[row] : rho;
-    for (int k = threadIdx.x; k < N; k += SP_THREADS) {
-        double2 m;
-        if (2 * k == N) {
-            // the cosine mode: Re[(j N/2)^order e^{j (N/2) rho}]
-            const double h = 0.5 * (double)N;
-            double sn, cs;
-            sincos(h * r, &sn, &cs);
-            m = make_double2(order == 0 ? cs : order == 1 ? -h * sn : -h * h * cs, 0.0);
-        } else {
-            const double ks = 2 * k > N ? (double)(k - N) : (double)k;
-            double sn, cs;
-            sincos(ks * r, &sn, &cs);
-            m = make_double2(cs, sn);
-            if (order == 1) m = make_double2(-ks * sn, ks * cs);
-            else if (order == 2) m = make_double2(-ks * ks * cs, -ks * ks * sn);
-        }
-        z[0][k] = cmul(z[0][k], m);
-        z[1][k] = cmul(z[1][k], m);
-    }
-    __syncthreads();
-    fft2<LOGN, true>(z, tw);
-    const double inv = 1.0 / (double)N;
     double *dst = out + row * (int64_t)N * 4;
-    for (int i = threadIdx.x; i < N; i += SP_THREADS) {
-        double2 a = z[0][i], b = z[1][i];
-        double2 *o = reinterpret_cast<double2 *>(dst + 4 * i);
-        o[0] = make_double2(a.x * inv, a.y * inv);
-        o[1] = make_double2(b.x * inv, b.y * inv);
-    }
+    const double r = rho_dev ? rho_dev[row] : rho;
+    forward_passes<LOGN, 0>(z, tw, src);
+    // last forward pass + multiplier + first inverse pass, in registers
+    constexpr int PM = PL::NP - 1;
+    constexpr int NSM = PL::ns_fwd(PM);
+    pass<N, PL::radix(PM), NSM, false, PM == 0 ? FROM_GLOBAL : FROM_LDS, PL::NP == 1, true>(z, tw, src, dst, r,
+                                                                                            order);
+    inverse_passes<LOGN, 1>(z, tw, dst);
 }
 
 constexpr int IP_WAVES = 4;
