@@ -295,7 +295,11 @@ typedef struct {
  * propagate_vertices -- out = F^n(in) for n_vertices states (x, y, x', y'),
  * AoS 4 doubles each, by the 11-stage order-8 explicit Runge-Kutta method of
  * Cooper & Verner (1972) with fixed steps (the globalization maps
- * F^{+-k} of Sec. 4.3).  in_dev may equal out_dev.  Asynchronous.
+ * F^{+-k} of Sec. 4.3).  in_dev may equal out_dev.  Asynchronous.  The
+ * first call for a given (device, e, steps_per_period) also builds a small
+ * table of stage values (allocated and copied synchronously, kept for the
+ * life of the process); make that call before capturing a stream into a
+ * graph.
  */
 int propagate_vertices(const double *in_dev, double *out_dev, int64_t n_vertices,
                        const map_params_t *params, void *stream);
@@ -317,7 +321,10 @@ int propagate_vertices(const double *in_dev, double *out_dev, int64_t n_vertices
 /* pertbp_map -- out = F^n(in) for n_states states (x, y, px, py), AoS 4
  * doubles each, device arrays.  in_dev may equal out_dev.  Asynchronous on
  * stream; MS_E_ARG for a bad pointer, steps_per_period <= 0, e outside
- * [0, 1) or mu outside [0, 1]. */
+ * [0, 1) or mu outside [0, 1].  The first call for a given (device, e,
+ * steps_per_period) solves Kepler's equation for the stage times of one
+ * period and keeps the table for the life of the process (synchronous
+ * allocation and copy: make that call before capturing a graph). */
 int pertbp_map(const double *in_dev, double *out_dev, int64_t n_states, const map_params_t *params,
                void *stream);
 
@@ -357,7 +364,9 @@ int pertbp_map_stm(const double *in_dev, double *out_dev, double *stm_dev, int64
  *   rho_dev  n_rows doubles (one shift per row), or NULL to use rho for all.
  *   n_theta  a power of two, 2 ... 2048; order 0, 1 or 2.
  * in_dev may equal out_dev.  Asynchronous; MS_E_ARG for bad sizes or
- * pointers. */
+ * pointers.  The first call for a given (device, n_theta) builds the
+ * table of twiddle factors (synchronous allocation and copy, kept for the
+ * life of the process: make that call before capturing a graph). */
 int theta_shift(const double *in_dev, double *out_dev, int32_t n_theta, int64_t n_rows, const double *rho_dev,
                 double rho, int32_t order, void *stream);
 
