@@ -373,7 +373,8 @@ int theta_shift(const double *in_dev, double *out_dev, int32_t n_theta, int64_t 
 /* theta_interp -- trigonometric interpolation (Sec. 7): out_dev[4 q + c] is
  * the value at theta_dev[q] of the trigonometric polynomial through the
  * samples of row row_dev[q] (coordinate c).  Any n_theta >= 1.  A query with
- * a row outside [0, n_rows) or a non-finite theta yields NaN.  Asynchronous. */
+ * a row outside [0, n_rows), a non-finite theta, or a theta so large that
+ * theta n_theta / (2 pi) overflows yields NaN.  Asynchronous. */
 int theta_interp(const double *rows_dev, int32_t n_theta, int64_t n_rows, const int64_t *row_dev,
                  const double *theta_dev, int64_t n_query, double *out_dev, void *stream);
 

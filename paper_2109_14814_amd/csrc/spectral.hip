@@ -304,8 +304,12 @@ __global__ void __launch_bounds__(64 * IP_WAVES) k_theta_interp(const double *in
     const double step = 2.0 * SP_PI / (double)N;
     // nearest sample i0 (reduced to [0, N)) and the offset delta from it
     const double i0f = rint(th / step);
+    if (!isfinite(i0f)) {       // |theta| beyond any meaningful angle: no index to take
+        if (lane < 4) o[lane] = NAN;
+        return;
+    }
     const double delta = th - i0f * step;
-    int64_t i0 = (int64_t)fmod(i0f, (double)N);
+    int64_t i0 = (int64_t)fmod(i0f, (double)N);   // exact, in (-N, N)
     if (i0 < 0) i0 += N;
     if (fabs(delta) < 1e-200) {
         if (lane < 4) o[lane] = a[4 * i0 + lane];

@@ -97,7 +97,7 @@ def test_interp_matches_oracle(ms, N):
 
 def test_interp_out_of_range_is_nan(ms):
     rows = _rows(3, 16, 1, smooth=True)
-    got = ms.theta_interp(rows, [0, 3, -1, 1], [0.2, 0.2, 0.2, float("nan")]).cpu().numpy()
+    got = ms.theta_interp(rows, [0, 3, -1, 1, 2], [0.2, 0.2, 0.2, float("nan"), 1e308]).cpu().numpy()
     assert np.all(np.isfinite(got[0])) and np.all(np.isnan(got[1:]))
 
 
