@@ -53,6 +53,20 @@ def algorithmic_bytes(kernel: str, st: dict, mesh_sizes) -> float | None:
     return table.get(kernel)
 
 
+# FP64 flops per unit of work of the Runge-Kutta kernels, counted from the
+# algorithm (a multiply-add counts 2; each inverse square root counts its
+# seed and two Newton steps, 12): the stage sums of the 11-stage method
+# (39 non-zero a_ij, 5 non-zero b_i) over 4 state components are 396 flops
+# per step; the pulsating field is 50 per stage, the position-momentum field
+# 52; with 4 tangent columns the variational terms add 74 per stage and the
+# stage sums of the 16 tangent components 1584 per step.
+FP64_PEAK_TFLOPS = 78.6
+RK_FLOPS = {
+    "k_rk8_map": 396 + 11 * 50,                      # per vertex-step: 946
+    "k_pm_flow<0>": 396 + 11 * 52,                   # per state-step: 968
+    "k_pm_flow<4>": 396 + 11 * 52 + 11 * 74 + 1584,  # per state-step with DF: 3366
+}
+
 SEARCH_SOURCES = ("mesh.hip", "small_sort.hip", "search.hip", "predicate.hpp", "ms_internal.hpp")
 
 
@@ -72,6 +86,36 @@ def source_digest() -> str:
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "search_512x512_traffic.txt")
+
+
+def file_digest(path: str) -> str:
+    import hashlib
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+SPECTRAL_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "theta_shift_4096x2048_traffic.txt")
+
+
+def spectral_traffic(kernel: str) -> float | None:
+    """HBM bytes per launch of a spectral kernel from its committed counter
+    summary, or None when it is missing or was taken on other sources."""
+    if not os.path.exists(SPECTRAL_TRAFFIC_FILE):
+        return None
+    digest, rows = None, {}
+    for line in open(SPECTRAL_TRAFFIC_FILE):
+        f = line.split()
+        if len(f) >= 2 and f[0] == "source_digest":
+            digest = f[1]
+        elif len(f) == 5 and f[0].startswith("k_"):
+            try:
+                rows[f[0]] = float(f[4])
+            except ValueError:
+                pass
+    src = os.path.join(ROOT, "paper_2109_14814_amd", "csrc", "spectral.hip")
+    if digest != file_digest(src):
+        return None
+    return rows.get(kernel)
 
 
 def measured_traffic(kernel: str) -> float | None:
@@ -198,6 +242,9 @@ def main():
         "kernels_launches_per_step": kern_launches,
         "roofline": roofline,
     }
+    # rooflines of the other legs' main kernels (filled in by the legs below)
+    leg_roof = {}
+    out["leg_rooflines"] = leg_roof
 
     # ------------------------------------------- all-pairs forced test rate
     if "allpairs" in legs:
@@ -326,6 +373,10 @@ def main():
         t_r = time.perf_counter() - t0
         vsteps = 2 * base_u.numel() // 4 * STEPS * 3
         out["rk8_vertex_steps_per_s"] = vsteps / t_rk
+        tf = vsteps * RK_FLOPS["k_rk8_map"] / t_rk / 1e12
+        leg_roof["k_rk8_map"] = {"bound": "alu", "achieved": round(tf, 2), "peak": FP64_PEAK_TFLOPS,
+                                 "unit": "TFLOP/s", "frac": round(tf / FP64_PEAK_TFLOPS, 4),
+                                 "flops_per_vertex_step": RK_FLOPS["k_rk8_map"]}
         out["rk8_ms_F3_and_Fm3_two_patches"] = t_rk * 1e3
         out["propagated_search_ms_incl_setup"] = t_s * 1e3
         out["propagated_hits"] = int(len(hp))
@@ -352,6 +403,10 @@ def main():
         t_pm = time.perf_counter() - t0
         vsteps = (zu.shape[0] + zs.shape[0]) * STEPS * 3
         out["pertbp_vertex_steps_per_s"] = vsteps / t_pm
+        tf = vsteps * RK_FLOPS["k_pm_flow<0>"] / t_pm / 1e12
+        leg_roof["k_pm_flow<0>"] = {"bound": "alu", "achieved": round(tf, 2), "peak": FP64_PEAK_TFLOPS,
+                                    "unit": "TFLOP/s", "frac": round(tf / FP64_PEAK_TFLOPS, 4),
+                                    "flops_per_state_step": RK_FLOPS["k_pm_flow<0>"]}
         out["pertbp_ms_F3_and_Fm3_two_patches"] = t_pm * 1e3
         n_stm = 1 << 18
         zst = zu[:n_stm].contiguous()
@@ -365,6 +420,10 @@ def main():
             stm_t[cols] = time.perf_counter() - t0
         best = min(stm_t, key=stm_t.get)
         out["pertbp_stm_vertex_steps_per_s"] = n_stm * STEPS * 3 / stm_t[best]
+        tf = n_stm * STEPS * 3 * RK_FLOPS["k_pm_flow<4>"] / stm_t[4] / 1e12
+        leg_roof["k_pm_flow<4>"] = {"bound": "alu", "achieved": round(tf, 2), "peak": FP64_PEAK_TFLOPS,
+                                    "unit": "TFLOP/s", "frac": round(tf / FP64_PEAK_TFLOPS, 4),
+                                    "flops_per_state_step": RK_FLOPS["k_pm_flow<4>"]}
         out["pertbp_stm_ms_by_cols_per_thread"] = {str(k): v * 1e3 for k, v in stm_t.items()}
         log(f"pertbp: F^3 + F^-3 of 2 x {zu.shape[0]} states in {t_pm * 1e3:.1f} ms "
             f"({vsteps / t_pm:.3e} vertex-steps/s); DF^3 of {n_stm} states in "
@@ -392,6 +451,11 @@ def main():
         nbytes = 2 * rows.numel() * 8
         out["spectral_shift_ms"] = sp_t[0] * 1e3
         out["spectral_shift_GBps"] = nbytes / sp_t[0] / 1e9
+        gbs = nbytes / sp_t[0] / 1e9
+        leg_roof["k_theta_shift<11>"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                         "traffic": spectral_traffic("k_theta_shift<11>"),
+                                         "bytes_per_launch": nbytes}
         out["spectral_derivative_ms"] = sp_t[1] * 1e3
         nq = 1 << 16
         qr = torch.tensor(rng.integers(0, M_ROWS, nq), device="cuda")
