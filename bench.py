@@ -173,7 +173,7 @@ def main():
     ap.add_argument("--n", type=int, default=512, help="quads per axis of each surface")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--kappa", type=float, default=0.0, help="cell edge / mean triangle diameter (0 = autotune)")
-    ap.add_argument("--legs", default="search,allpairs,family,layers,rk8,pertbp,spectral,refine,copy,cpu")
+    ap.add_argument("--legs", default="search,allpairs,family,layers,rk8,pertbp,spectral,ft,refine,copy,cpu")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -471,6 +471,39 @@ def main():
             f"({nbytes / sp_t[0] / 1e9:.0f} GB/s algorithmic), derivative {sp_t[1] * 1e3:.3f} ms; "
             f"{nq} interpolations in {t_i * 1e3:.2f} ms")
         del rows, dst
+
+    # ------------- Fourier-Taylor chart partials, local and through F^3 (Sec. 7)
+    if "ft" in legs:
+        N_TH, ORDER, NQ = 2048, 25, 4096
+        rng = np.random.default_rng(args.seed)
+        th = 2 * np.pi * np.arange(N_TH) / N_TH
+        base = synth.periapse_position_momentum(np.array(synth.UNSTABLE_BASE), 0.0094)
+        coeffs = np.zeros((ORDER + 1, N_TH, 4))
+        coeffs[0] = base[None, :]
+        for k in range(ORDER + 1):
+            for q in range(8):
+                amp = (1e-3 if k == 0 else 1e-2 / (k + 1) ** 2) / (1 + q) ** 2
+                coeffs[k] += amp * (rng.standard_normal(4)[None, :] * np.cos(q * th)[:, None]
+                                    + rng.standard_normal(4)[None, :] * np.sin(q * th)[:, None])
+        chart = ms.FourierTaylor(coeffs)
+        qt = torch.tensor(rng.uniform(0, 2 * np.pi, NQ), device="cuda")
+        qs = torch.tensor(rng.uniform(-0.05, 0.05, NQ), device="cuda")
+        chart.partials(qt[:64], qs[:64])
+        chart.partials(qt[:64], qs[:64], 3, 0.61, 1.35, 2.527e-5, 0.0094, 4000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        chart.partials(qt, qs)
+        torch.cuda.synchronize()
+        t_loc = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        chart.partials(qt, qs, 3, 0.61, 1.35, 2.527e-5, 0.0094, 4000)
+        torch.cuda.synchronize()
+        t_glob = time.perf_counter() - t0
+        out["ft_local_partials_per_s"] = NQ / t_loc
+        out["ft_global_partials_ms"] = t_glob * 1e3
+        log(f"fourier-taylor: {NQ} local chart partials (N={N_TH}, order {ORDER}) in {t_loc * 1e3:.3f} ms; "
+            f"globalized through F^3 / DF^3 in {t_glob * 1e3:.1f} ms")
+        del chart
 
     # ------------------------- plain device copy (HBM reference, counter scale)
     if "copy" in legs:

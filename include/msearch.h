@@ -336,8 +336,9 @@ int pertbp_map(const double *in_dev, double *out_dev, int64_t n_states, const ma
  *   stm_dev  n_states x 16, row-major per state: stm[16 p + 4 i + j] =
  *            d out_i / d in_j; must not overlap in_dev or out_dev.
  *   cols_per_thread  1, 2 or 4 columns of DF per GPU thread (4 / cols
- *            threads per state), or 0 for the default (4); a tuning choice
- *            only, the results are identical.
+ *            threads per state), or 0 for the default (4 from 131,072 states
+ *            up, 2 from 65,536, else 1); a tuning choice only, the results
+ *            are identical.
  * Asynchronous; errors as pertbp_map. */
 int pertbp_map_stm(const double *in_dev, double *out_dev, double *stm_dev, int64_t n_states,
                    const map_params_t *params, int32_t cols_per_thread, void *stream);
@@ -370,6 +371,15 @@ int pertbp_map_stm(const double *in_dev, double *out_dev, double *stm_dev, int64
 int theta_shift(const double *in_dev, double *out_dev, int32_t n_theta, int64_t n_rows, const double *rho_dev,
                 double rho, int32_t order, void *stream);
 
+/* theta_spectrum -- the forward transform of each row (the FFT step of
+ * Sec. 6.1 and Sec. 7): out(r, j) = (Z0(j), Z1(j)) / n_theta for the
+ * frequencies j = 0..n_theta-1 in natural order, where z0 = x + i y and
+ * z1 = px + i py are a row's coordinate pairs as complex sequences; stored
+ * as 4 doubles per frequency (Re Z0, Im Z0, Re Z1, Im Z1), the layout of the
+ * rows.  n_theta a power of two, 2 ... 2048.  Asynchronous; the first call
+ * per (device, n_theta) builds the twiddle table as theta_shift does. */
+int theta_spectrum(const double *in_dev, double *out_dev, int32_t n_theta, int64_t n_rows, void *stream);
+
 /* theta_interp -- trigonometric interpolation (Sec. 7): out_dev[4 q + c] is
  * the value at theta_dev[q] of the trigonometric polynomial through the
  * samples of row row_dev[q] (coordinate c).  Any n_theta >= 1.  A query with
@@ -377,6 +387,33 @@ int theta_shift(const double *in_dev, double *out_dev, int32_t n_theta, int64_t 
  * theta n_theta / (2 pi) overflows yields NaN.  Asynchronous. */
 int theta_interp(const double *rows_dev, int32_t n_theta, int64_t n_rows, const int64_t *row_dev,
                  const double *theta_dev, int64_t n_query, double *out_dev, void *stream);
+
+/* ------------------------------------------------- Fourier-Taylor charts */
+
+/*
+ * ft_partials -- points and partial derivatives of a Fourier-Taylor
+ * parameterization W(theta, s) = sum_{k=0}^{order} W_k(theta) s^k of a
+ * manifold (Sec. 7), locally or globalized through the stroboscopic map:
+ *   W_glob(theta, s) = F^m(W(theta - m omega, lambda^-m s)),
+ *   dW_glob/dtheta = DF^m dW/dtheta,   dW_glob/ds = lambda^-m DF^m dW/ds,
+ * with the partials of W taken at (theta - m omega, lambda^-m s) (the s
+ * series differentiated term by term, the theta derivative by multiplying
+ * the spectrum by i j, both interpolated trigonometrically at theta).
+ *   spec_dev   the coefficients' spectra: theta_spectrum of the (order + 1)
+ *              rows W_k(theta_i), i = 0..n_theta-1 (so (order + 1) x n_theta
+ *              x 4 doubles).  Any n_theta >= 1 is accepted here.
+ *   theta_dev, s_dev  n_query parameters.
+ *   map        NULL or n_periods == 0: the local chart (omega, lambda
+ *              unused).  Else m = map->n_periods (negative for a stable
+ *              manifold, with its multiplier lambda) and F, DF are those of
+ *              pertbp_map_stm with map's mu, e and steps.
+ *   w_dev, dth_dev, ds_dev  n_query x 4 outputs.
+ *   stm_dev    n_query x 16 doubles of workspace (DF^m per query, row-major;
+ *              left there on return); required when m != 0.
+ * Asynchronous.  A query with a non-finite theta or s yields NaN. */
+int ft_partials(const double *spec_dev, int32_t n_theta, int32_t order, const double *theta_dev,
+                const double *s_dev, int64_t n_query, double omega, double lambda, const map_params_t *map,
+                double *w_dev, double *dth_dev, double *ds_dev, double *stm_dev, void *stream);
 
 /* ------------------------------------------------------------ refinement */
 

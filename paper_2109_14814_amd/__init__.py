@@ -25,7 +25,8 @@ EXPORTS = ("last_error", "mesh_build", "mesh_free", "mesh_info", "mesh_update", 
            "search_workspace_size", "search_intersections", "search_intersections_async", "narrow_allpairs", "propagate_vertices",
            "search_profile_enable", "search_profile_read", "batch_create", "batch_search", "batch_needed",
            "batch_free", "refine_workspace_size", "refine_grad", "refine_newton", "layer_pairs",
-           "half_layer_bounds", "half_layer_columns", "pertbp_map", "pertbp_map_stm", "theta_shift", "theta_interp")
+           "half_layer_bounds", "half_layer_columns", "pertbp_map", "pertbp_map_stm", "theta_shift", "theta_interp", "theta_spectrum",
+           "ft_partials")
 
 MS_REFINE_RESIDUAL, MS_REFINE_ADJOINT, MS_REFINE_TANGENT, MS_REFINE_NEWTON = 0, 1, 2, 3
 NEWTON_STATUS = {0: "converged", 1: "trial limit", 2: "step too small", 3: "singular", 4: "non-finite"}
@@ -99,6 +100,10 @@ def lib():
         L.theta_shift.restype = C.c_int
         L.theta_interp.argtypes = [P, I32, I64, P, P, I64, P, P]
         L.theta_interp.restype = C.c_int
+        L.theta_spectrum.argtypes = [P, P, I32, I64, P]
+        L.theta_spectrum.restype = C.c_int
+        L.ft_partials.argtypes = [P, I32, I32, P, P, I64, D, D, C.POINTER(MapParams), P, P, P, P, P]
+        L.ft_partials.restype = C.c_int
         L.mesh_update.argtypes = [P, P]; L.mesh_update.restype = C.c_int
         L.batch_create.argtypes = [I32, P, P, P, I64, I64, P, C.POINTER(P), C.POINTER(C.c_size_t)]
         L.batch_create.restype = C.c_int
@@ -617,6 +622,51 @@ def theta_interp(rows, row_index, theta):
     _check(lib().theta_interp(_ptr(x), int(x.shape[1]), int(x.shape[0]), _ptr(r), _ptr(t), t.numel(), _ptr(out),
                               _stream()))
     return out
+
+
+def theta_spectrum(rows, out=None):
+    """Spectra of rows (..., n_theta, 4): (Z0, Z1) / n_theta per frequency as
+    4 doubles (theta_spectrum of the C ABI)."""
+    torch = _torch()
+    x = torch.as_tensor(rows, dtype=torch.float64).to("cuda").contiguous()
+    assert x.shape[-1] == 4 and x.dim() >= 2
+    n_theta = x.shape[-2]
+    n_rows = int(np.prod(x.shape[:-2])) if x.dim() > 2 else 1
+    if out is None:
+        out = torch.empty_like(x)
+    _check(lib().theta_spectrum(_ptr(x), _ptr(out), int(n_theta), n_rows, _stream()))
+    return out
+
+
+class FourierTaylor:
+    """A Fourier-Taylor chart W(theta, s) = sum_k W_k(theta) s^k from its
+    sampled coefficients coeffs (order + 1, n_theta, 4); the spectra are
+    computed once on the GPU."""
+
+    def __init__(self, coeffs):
+        torch = _torch()
+        c = torch.as_tensor(coeffs, dtype=torch.float64).to("cuda").contiguous()
+        assert c.dim() == 3 and c.shape[-1] == 4
+        self.order, self.n_theta = c.shape[0] - 1, c.shape[1]
+        self.spec = theta_spectrum(c)
+
+    def partials(self, theta, s, m: int = 0, omega: float = 0.0, lam: float = 1.0, mu: float = 0.0,
+                 eps: float = 0.0, steps_per_period: int = 1):
+        """(W, dW/dtheta, dW/ds), each (n, 4), at the parameters (theta, s) of
+        the chart globalized by m periods (m = 0: the local chart)."""
+        torch = _torch()
+        t = torch.as_tensor(theta, dtype=torch.float64).to("cuda").contiguous().reshape(-1)
+        sv = torch.as_tensor(s, dtype=torch.float64).to("cuda").contiguous().reshape(-1)
+        if t.numel() != sv.numel():
+            raise ValueError("one s per theta")
+        n = t.numel()
+        w, dth, ds = (torch.empty((n, 4), dtype=torch.float64, device="cuda") for _ in range(3))
+        stm = torch.empty((n, 16), dtype=torch.float64, device="cuda") if m != 0 else None
+        mp = MapParams(float(mu), float(eps), int(steps_per_period), int(m))
+        _check(lib().ft_partials(_ptr(self.spec), int(self.n_theta), int(self.order), _ptr(t), _ptr(sv), n,
+                                 float(omega), float(lam), C.byref(mp), _ptr(w), _ptr(dth), _ptr(ds), _ptr(stm),
+                                 _stream()))
+        return w, dth, ds
 
 
 # ------------------------------------------------------------- refinement

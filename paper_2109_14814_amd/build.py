@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libmsearch.so")
-SOURCES = ["mesh.hip", "small_sort.hip", "search.hip", "rk8.hip", "refine.hip", "layers.hip", "pertbp.hip", "spectral.hip"]
+SOURCES = ["mesh.hip", "small_sort.hip", "search.hip", "rk8.hip", "refine.hip", "layers.hip", "pertbp.hip", "spectral.hip", "fourier_taylor.hip"]
 ARCH = os.environ.get("MSEARCH_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}", "-ffp-contract=off",

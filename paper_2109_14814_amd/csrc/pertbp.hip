@@ -15,8 +15,9 @@
 // state, each carrying the state and NC of the 4 tangent columns (the
 // variational equations integrated with the same stages, so the result is
 // the exact derivative of the discrete map): NC = 4 computes the field once
-// per state (the default: fastest on gfx950 although it runs at one wave
-// per SIMD), NC = 1 keeps the fewest registers live.
+// per state (the default for large batches: fastest on gfx950 although it
+// runs at one wave per SIMD), NC = 1 keeps the fewest registers live and
+// gives small batches four times the threads.
 #include <math.h>
 
 #include <string>
@@ -169,7 +170,9 @@ extern "C" int pertbp_map_stm(const double *in_dev, double *out_dev, double *stm
 {
     int rc = pm_check("pertbp_map_stm", in_dev, stm_dev, n_states, p);
     if (rc) return rc;
-    if (cols_per_thread == 0) cols_per_thread = 4;
+    // default: four columns per thread (the least work per state) once the
+    // batch fills the chip with them, else more threads per state
+    if (cols_per_thread == 0) cols_per_thread = n_states >= (1 << 17) ? 4 : n_states >= (1 << 16) ? 2 : 1;
     if (cols_per_thread != 1 && cols_per_thread != 2 && cols_per_thread != 4)
         return fail(MS_E_ARG, "pertbp_map_stm: cols_per_thread must be 0, 1, 2 or 4");
     if (n_states == 0) return MS_OK;

@@ -284,6 +284,26 @@ __global__ void __launch_bounds__(SP_THREADS) k_theta_shift(const double *in, do
     inverse_passes<LOGN, 1>(z, tw, dst);
 }
 
+// Forward transform only: out(r, j) = (Z0(j), Z1(j)) / N in natural order,
+// four doubles per frequency (Re Z0, Im Z0, Re Z1, Im Z1), the layout of the
+// input rows.
+template <int LOGN>
+__global__ void __launch_bounds__(SP_THREADS) k_theta_spectrum(const double *in, double *out,
+                                                               const double2 *__restrict__ tw)
+{
+    using PL = Plan<LOGN>;
+    constexpr int N = 1 << LOGN;
+    __shared__ double2 z[2][padded_size<N>()];
+    const int64_t row = blockIdx.x;
+    const double *src = in + row * (int64_t)N * 4;
+    double *dst = out + row * (int64_t)N * 4;
+    forward_passes<LOGN, 0>(z, tw, src);
+    constexpr int PM = PL::NP - 1;
+    constexpr int NSM = PL::ns_fwd(PM);
+    // the last forward pass (Ns = N / R) writes coefficient j + r N/R of butterfly j
+    pass<N, PL::radix(PM), NSM, false, PM == 0 ? FROM_GLOBAL : FROM_LDS, true, false>(z, tw, src, dst, 0.0, 0);
+}
+
 constexpr int IP_WAVES = 4;
 
 __global__ void __launch_bounds__(64 * IP_WAVES) k_theta_interp(const double *in, int N, int64_t n_rows,
@@ -378,10 +398,46 @@ int twiddles(int N, const double2 **out)
     return MS_OK;
 }
 
+template <int LOGN>
+void launch_spectrum(const double *in, double *out, const double2 *tw, int64_t n_rows, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_theta_spectrum<LOGN>, dim3((unsigned)n_rows), dim3(SP_THREADS), 0, st, in, out, tw);
+}
+
 }  // namespace
 }  // namespace ms
 
 using namespace ms;
+
+extern "C" int theta_spectrum(const double *in_dev, double *out_dev, int32_t n_theta, int64_t n_rows, void *stream)
+{
+    if (n_rows < 0 || (n_rows > 0 && (!in_dev || !out_dev))) return fail(MS_E_ARG, "theta_spectrum: bad argument");
+    if (n_theta < 2 || n_theta > (1 << SP_MAX_LOG2) || (n_theta & (n_theta - 1)))
+        return fail(MS_E_ARG, "theta_spectrum: n_theta must be a power of two in [2, 2048]");
+    if (n_rows > 0x7fffffff) return fail(MS_E_ARG, "theta_spectrum: too many rows for one launch");
+    if (n_rows == 0) return MS_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const double2 *tw = nullptr;
+    int rc = twiddles(n_theta, &tw);
+    if (rc) return rc;
+    int lg = 0;
+    while ((1 << lg) < n_theta) ++lg;
+    switch (lg) {
+    case 1: launch_spectrum<1>(in_dev, out_dev, tw, n_rows, st); break;
+    case 2: launch_spectrum<2>(in_dev, out_dev, tw, n_rows, st); break;
+    case 3: launch_spectrum<3>(in_dev, out_dev, tw, n_rows, st); break;
+    case 4: launch_spectrum<4>(in_dev, out_dev, tw, n_rows, st); break;
+    case 5: launch_spectrum<5>(in_dev, out_dev, tw, n_rows, st); break;
+    case 6: launch_spectrum<6>(in_dev, out_dev, tw, n_rows, st); break;
+    case 7: launch_spectrum<7>(in_dev, out_dev, tw, n_rows, st); break;
+    case 8: launch_spectrum<8>(in_dev, out_dev, tw, n_rows, st); break;
+    case 9: launch_spectrum<9>(in_dev, out_dev, tw, n_rows, st); break;
+    case 10: launch_spectrum<10>(in_dev, out_dev, tw, n_rows, st); break;
+    default: launch_spectrum<11>(in_dev, out_dev, tw, n_rows, st); break;
+    }
+    MS_HIP(hipGetLastError());
+    return MS_OK;
+}
 
 extern "C" int theta_shift(const double *in_dev, double *out_dev, int32_t n_theta, int64_t n_rows,
                            const double *rho_dev, double rho, int32_t order, void *stream)

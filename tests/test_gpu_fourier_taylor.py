@@ -1,0 +1,96 @@
+"""GPU parity of the forward theta spectra and of the Fourier-Taylor chart
+points and partials, local and globalized through F^m and DF^m (Sec. 7),
+against the oracle (numpy FFT; Horner, FFT derivative and trigonometric
+interpolation; the oracle's map and matrix).  Bars: spectra 1e-13 x max|a|;
+local values 1e-11 x scale, the theta partial with an extra N/2 (the
+derivative weights frequency j by j); globalized values and partials 1e-10
+relative to the largest entry (the matrices reach ~1e2)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import fourier_taylor as ft
+
+pytestmark = pytest.mark.gpu
+
+MU, ECC = 2.527e-5, 0.0094
+
+
+@pytest.fixture(scope="module")
+def ms():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2109_14814_amd as ms
+    ms.lib()
+    return ms
+
+
+def _chart(N, P, seed, base):
+    rng = np.random.default_rng(seed)
+    th = 2 * np.pi * np.arange(N) / N
+    c = np.zeros((P + 1, N, 4))
+    c[0] = np.asarray(base)[None, :]
+    for k in range(P + 1):
+        for q in range(min(6, N // 2)):
+            amp = (1e-3 if k == 0 else 1e-2 / (k + 1) ** 2) / (1 + q) ** 2
+            c[k] += amp * (rng.standard_normal(4)[None, :] * np.cos(q * th)[:, None]
+                           + rng.standard_normal(4)[None, :] * np.sin(q * th)[:, None])
+        c[k] += 1e-9 * rng.standard_normal((N, 4))          # a little full-band content
+    return c
+
+
+@pytest.mark.parametrize("N", [2, 8, 64, 2048])
+def test_spectrum_matches_numpy(ms, N):
+    rows = np.random.default_rng(N).standard_normal((7, N, 4))
+    got = ms.theta_spectrum(rows).cpu().numpy()
+    z0 = np.fft.fft(rows[..., 0] + 1j * rows[..., 1], axis=-1) / N
+    z1 = np.fft.fft(rows[..., 2] + 1j * rows[..., 3], axis=-1) / N
+    ref = np.stack([z0.real, z0.imag, z1.real, z1.imag], axis=-1)
+    assert np.max(np.abs(got - ref)) < 1e-13 * max(1.0, np.abs(rows).max()) * np.log2(max(N, 2))
+
+
+@pytest.mark.parametrize("N,P", [(16, 3), (64, 10), (512, 20), (2048, 25)])
+def test_local_partials_match_oracle(ms, N, P):
+    c = _chart(N, P, N + P, (0.9, 0.0, 0.0, 0.97))
+    chart = ms.FourierTaylor(c)
+    rng = np.random.default_rng(P)
+    th = rng.uniform(-7, 7, 203)
+    s = rng.uniform(-0.8, 0.8, 203)
+    th[:3] = 2 * np.pi * np.array([0, 1, N - 1]) / N
+    w, dth, ds = (x.cpu().numpy() for x in chart.partials(th, s))
+    for q in range(len(th)):
+        rw, rth, rs = ft.local(c, th[q], s[q])
+        assert np.max(np.abs(w[q] - rw)) < 1e-11
+        assert np.max(np.abs(dth[q] - rth)) < 1e-11 * max(1.0, N / 2)
+        assert np.max(np.abs(ds[q] - rs)) < 1e-11 * P
+
+
+@pytest.mark.parametrize("m,lam,stable", [(3, 1.35, False), (-3, 1 / 1.35, True)])
+def test_globalized_partials_match_oracle(ms, m, lam, stable):
+    base = synth.periapse_position_momentum(np.array(synth.STABLE_BASE if stable else synth.UNSTABLE_BASE), ECC)
+    c = _chart(256, 8, 7, base)
+    chart = ms.FourierTaylor(c)
+    rng = np.random.default_rng(9)
+    th = rng.uniform(0, 2 * np.pi, 13)
+    s = rng.uniform(-0.05, 0.05, 13)
+    omega = 0.61
+    w, dth, ds = (x.cpu().numpy() for x in chart.partials(th, s, m, omega, lam, MU, ECC, 4000))
+    for q in range(len(th)):
+        rw, rth, rs = ft.globalized(c, th[q], s[q], m, omega, lam, MU, ECC, 4000)
+        assert np.max(np.abs(w[q] - rw)) < 1e-10
+        assert np.max(np.abs(dth[q] - rth)) < 1e-10 * max(1.0, np.abs(rth).max())
+        assert np.max(np.abs(ds[q] - rs)) < 1e-10 * max(1.0, np.abs(rs).max())
+
+
+def test_edges(ms):
+    c = _chart(32, 0, 1, (0.9, 0.0, 0.0, 0.97))                 # order 0: W = W_0(theta)
+    chart = ms.FourierTaylor(c)
+    w, dth, ds = (x.cpu().numpy() for x in chart.partials([0.3, float("nan")], [0.5, 0.1]))
+    rw, rth, _ = ft.local(c, 0.3, 0.5)
+    assert np.max(np.abs(w[0] - rw)) < 1e-12 and np.max(np.abs(dth[0] - rth)) < 1e-10
+    assert np.all(ds[0] == 0.0) and np.all(np.isnan(w[1]))
+    e = chart.partials([], [])
+    assert e[0].shape == (0, 4)
+    with pytest.raises(ms.MSearchError):
+        ms.theta_spectrum(np.zeros((2, 12, 4)))
