@@ -92,3 +92,22 @@ def test_zero_periods_is_local():
     l_ = ft.local(c, 0.3, 0.1)
     for a, b in zip(g, l_):
         assert np.array_equal(a, b)
+
+
+def test_newton_finds_a_planted_root():
+    """Charts built to meet at a known parameter point: damped Newton from a
+    perturbed start converges to it, with r falling quadratically."""
+    import synth
+    bu = synth.periapse_position_momentum(np.array(synth.UNSTABLE_BASE), ECC)
+    bs = synth.periapse_position_momentum(np.array(synth.STABLE_BASE), ECC)
+    chart_u, chart_s = (2, 0.61, 1.35), (-2, 0.47, 1 / 1.35)
+    root = np.array([1.3, 0.02, 4.1, -0.015])
+    cu, cs = ft.planted_charts(32, 4, 11, root, chart_u, chart_s, MU, ECC, 1000, bu, bs)
+    f, _ = (ft.globalized(cu, root[0], root[1], *chart_u, MU, ECC, 1000)[0]
+            - ft.globalized(cs, root[2], root[3], *chart_s, MU, ECC, 1000)[0]), None
+    assert np.max(np.abs(f)) < 1e-12
+    x0 = root + np.array([2e-4, -1e-4, 1.5e-4, 1e-4])
+    x, fo, r, st, tr, hist = ft.newton(cu, cs, x0[None], chart_u, chart_s, MU, ECC, 1000, tol=1e-12, history=True)
+    assert st[0] == 0 and np.max(np.abs(x[0] - root)) < 1e-9
+    seq = hist[0]
+    assert len(seq) >= 3 and seq[2] < 1e-3 * seq[1] and seq[1] < 1e-2 * seq[0]
