@@ -504,6 +504,32 @@ int refine_newton(const double *params_in_dev, double *params_out_dev, int64_t K
                   int32_t *trials_dev, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * ft_newton -- the same damped Newton iteration (same alpha rule, stopping
+ * rules and status codes) for two globalized Fourier-Taylor charts (Sec. 7):
+ *   f(x) = W_U(theta_u, s_u) - W_S(theta_s, s_s),
+ *   Df = [dW_U/dtheta, dW_U/ds, -dW_S/dtheta, -dW_S/ds],
+ * x = (theta_u, s_u, theta_s, s_s), each chart evaluated by ft_partials
+ * with its own m, omega and lambda and the map's mu, e and steps_per_period
+ * (map->n_periods is ignored).  One iteration evaluates both charts at the
+ * trial points of the running problems; the stream is synchronised once per
+ * iteration to stop as soon as no problem is running.  Workspace:
+ * ft_newton_workspace_size(K) bytes. */
+typedef struct {
+    const double *spec_dev;   /* theta_spectrum of the chart's order + 1 coefficient rows */
+    int32_t n_theta;
+    int32_t order;
+    int32_t n_periods;        /* m of the globalization: > 0 unstable, < 0 stable, 0 local */
+    int32_t reserved;
+    double omega;             /* rotation number of the chart's circle */
+    double lambda;            /* multiplier of the chart's s direction */
+} ft_chart_t;
+
+int ft_newton_workspace_size(int64_t K, size_t *bytes);
+int ft_newton(const double *params_in_dev, double *params_out_dev, int64_t K, const ft_chart_t *U,
+              const ft_chart_t *S, const map_params_t *map, const newton_params_t *np, double *f_dev,
+              double *r_dev, int32_t *status_dev, int32_t *trials_dev, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * The method of layers (Sec. 5).  With lambda_u and lambda_s the multipliers
  * of the internal dynamics on the unstable and stable manifolds and
  * T x (-D, D) their fundamental domains, the half-layers are

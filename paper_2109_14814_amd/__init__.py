@@ -26,7 +26,7 @@ EXPORTS = ("last_error", "mesh_build", "mesh_free", "mesh_info", "mesh_update", 
            "search_profile_enable", "search_profile_read", "batch_create", "batch_search", "batch_needed",
            "batch_free", "refine_workspace_size", "refine_grad", "refine_newton", "layer_pairs",
            "half_layer_bounds", "half_layer_columns", "pertbp_map", "pertbp_map_stm", "theta_shift", "theta_interp", "theta_spectrum",
-           "ft_partials")
+           "ft_partials", "ft_newton_workspace_size", "ft_newton")
 
 MS_REFINE_RESIDUAL, MS_REFINE_ADJOINT, MS_REFINE_TANGENT, MS_REFINE_NEWTON = 0, 1, 2, 3
 NEWTON_STATUS = {0: "converged", 1: "trial limit", 2: "step too small", 3: "singular", 4: "non-finite"}
@@ -64,6 +64,11 @@ class MapParams(C.Structure):
 
 class NewtonParams(C.Structure):
     _fields_ = [("max_trials", C.c_int32), ("tol", C.c_double), ("alpha0", C.c_double), ("alpha_min", C.c_double)]
+
+
+class FtChart(C.Structure):
+    _fields_ = [("spec_dev", C.c_void_p), ("n_theta", C.c_int32), ("order", C.c_int32), ("n_periods", C.c_int32),
+                ("reserved", C.c_int32), ("omega", C.c_double), ("lam", C.c_double)]
 
 
 _lib = None
@@ -104,6 +109,11 @@ def lib():
         L.theta_spectrum.restype = C.c_int
         L.ft_partials.argtypes = [P, I32, I32, P, P, I64, D, D, C.POINTER(MapParams), P, P, P, P, P]
         L.ft_partials.restype = C.c_int
+        L.ft_newton_workspace_size.argtypes = [I64, C.POINTER(C.c_size_t)]
+        L.ft_newton_workspace_size.restype = C.c_int
+        L.ft_newton.argtypes = [P, P, I64, C.POINTER(FtChart), C.POINTER(FtChart), C.POINTER(MapParams),
+                                C.POINTER(NewtonParams), P, P, P, P, P, C.c_size_t, P]
+        L.ft_newton.restype = C.c_int
         L.mesh_update.argtypes = [P, P]; L.mesh_update.restype = C.c_int
         L.batch_create.argtypes = [I32, P, P, P, I64, I64, P, C.POINTER(P), C.POINTER(C.c_size_t)]
         L.batch_create.restype = C.c_int
@@ -667,6 +677,34 @@ class FourierTaylor:
                                  float(omega), float(lam), C.byref(mp), _ptr(w), _ptr(dth), _ptr(ds), _ptr(stm),
                                  _stream()))
         return w, dth, ds
+
+
+def ft_newton(params, chart_u: "FourierTaylor", glob_u, chart_s: "FourierTaylor", glob_s, mu: float, eps: float,
+              steps_per_period: int, max_trials: int = 40, tol: float = 1e-12, alpha0: float = 1.0,
+              alpha_min: float = 2.0 ** -30):
+    """Damped Newton on two globalized Fourier-Taylor charts (ft_newton of the
+    C ABI); glob_u / glob_s are (m, omega, lambda).  Returns (x, f, r, status,
+    trials) as cuda tensors."""
+    torch = _torch()
+    x = torch.as_tensor(params, dtype=torch.float64).reshape(-1, 4).to("cuda").contiguous()
+    K = x.shape[0]
+    cu = FtChart(chart_u.spec.data_ptr(), chart_u.n_theta, chart_u.order, int(glob_u[0]), 0, float(glob_u[1]),
+                 float(glob_u[2]))
+    cs = FtChart(chart_s.spec.data_ptr(), chart_s.n_theta, chart_s.order, int(glob_s[0]), 0, float(glob_s[1]),
+                 float(glob_s[2]))
+    mp = MapParams(float(mu), float(eps), int(steps_per_period), 0)
+    nb = C.c_size_t()
+    _check(lib().ft_newton_workspace_size(K, C.byref(nb)))
+    ws = _dev_bytes(nb.value)
+    xo = torch.empty_like(x)
+    f = torch.empty((K, 4), dtype=torch.float64, device="cuda")
+    r = torch.empty((K,), dtype=torch.float64, device="cuda")
+    st = torch.empty((K,), dtype=torch.int32, device="cuda")
+    tr = torch.empty((K,), dtype=torch.int32, device="cuda")
+    npar = NewtonParams(int(max_trials), float(tol), float(alpha0), float(alpha_min))
+    _check(lib().ft_newton(_ptr(x), _ptr(xo), K, C.byref(cu), C.byref(cs), C.byref(mp), C.byref(npar), _ptr(f),
+                           _ptr(r), _ptr(st), _ptr(tr), _ptr(ws), nb.value, _stream()))
+    return xo, f, r, st, tr
 
 
 # ------------------------------------------------------------- refinement

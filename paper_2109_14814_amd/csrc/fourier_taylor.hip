@@ -17,11 +17,15 @@
 // Globalization: the local evaluation at (theta - m omega, lambda^-m s) (the
 // s-derivative already scaled by lambda^-m), then F^m and DF^m of the point
 // by the position-momentum map, then the two partials multiplied by DF^m.
+//
+// Refinement (ft_newton): the damped Newton iteration of Sec. 7 on
+// f = W_u(theta_u, s_u) - W_s(theta_s, s_s) with Df from the four partials,
+// one ft_partials per chart and one decision kernel per iteration.
 #include <math.h>
 
 #include <string>
 
-#include "ms_internal.hpp"
+#include "newton.hpp"
 
 namespace ms {
 namespace {
@@ -119,10 +123,158 @@ __global__ void __launch_bounds__(256) k_apply_stm(const double *__restrict__ st
     }
 }
 
+// Parameters and partials of one side of the Newton problems.
+struct FtSide {
+    double *th, *s, *w, *dth, *ds, *stm;
+};
+
+MS_D void ftn_split(int64_t k, const NewtonState &ns, const FtSide &u, const FtSide &v)
+{
+    u.th[k] = ns.q[4 * k + 0];
+    u.s[k] = ns.q[4 * k + 1];
+    v.th[k] = ns.q[4 * k + 2];
+    v.s[k] = ns.q[4 * k + 3];
+}
+
+__global__ void __launch_bounds__(256) k_ftn_init(const double *x0, NewtonState ns, int64_t K, FtSide u, FtSide v,
+                                                  unsigned long long *running)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0) running[0] = running[1] = 0;
+    if (k >= K) return;
+    newton_init(k, x0, ns);
+    ftn_split(k, ns, u, v);
+}
+
+// One decision per running problem; counts the problems still running in
+// running[par] and clears the other counter for the next iteration.
+__global__ void __launch_bounds__(256) k_ftn_update(NewtonState ns, NewtonCfg cfg, int64_t K, FtSide u, FtSide v,
+                                                    unsigned long long *running, int par)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0) running[par ^ 1] = 0;
+    if (k >= K || ns.status[k] >= 0) return;
+    double f[4], M[4][4];
+    for (int c = 0; c < 4; ++c) {
+        f[c] = u.w[4 * k + c] - v.w[4 * k + c];
+        M[c][0] = u.dth[4 * k + c];
+        M[c][1] = u.ds[4 * k + c];
+        M[c][2] = -v.dth[4 * k + c];
+        M[c][3] = -v.ds[4 * k + c];
+    }
+    newton_decide(k, f, M, ns, cfg);
+    if (ns.status[k] < 0) {
+        ftn_split(k, ns, u, v);
+        atomicAdd(&running[par], 1ull);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_ftn_finish(NewtonState ns, int64_t K, double *x_out, double *f_out,
+                                                    double *r_out, int32_t *st_out, int32_t *tr_out)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    newton_finish(k, ns, x_out, f_out, r_out, st_out, tr_out);
+}
+
+// Workspace layout of ft_newton for K problems (256-byte aligned pieces).
+struct FtnLayout {
+    size_t total;
+    size_t o[24];
+};
+
+FtnLayout ftn_layout(int64_t K)
+{
+    FtnLayout L;
+    const size_t d4b = (size_t)K * 32, d1b = (size_t)K * 8, i1b = (size_t)K * 4, d16b = (size_t)K * 128;
+    const size_t sizes[] = {d4b, d4b, d4b, d4b, d1b, d1b, i1b, i1b, i1b,     // p q delta fp rp alpha status trials based
+                            d1b, d1b, d4b, d4b, d4b, d16b,                   // side u: th s w dth ds stm
+                            d1b, d1b, d4b, d4b, d4b, d16b,                   // side s
+                            16};                                             // running counters
+    size_t at = 0;
+    for (size_t i = 0; i < sizeof(sizes) / sizeof(sizes[0]); ++i) {
+        L.o[i] = at;
+        at += (sizes[i] + 255) & ~(size_t)255;
+    }
+    L.total = at;
+    return L;
+}
+
 }  // namespace
 }  // namespace ms
 
 using namespace ms;
+
+extern "C" int ft_newton_workspace_size(int64_t K, size_t *bytes)
+{
+    if (K < 0 || !bytes) return fail(MS_E_ARG, "ft_newton_workspace_size: bad argument");
+    *bytes = ftn_layout(K).total;
+    return MS_OK;
+}
+
+extern "C" int ft_newton(const double *params_in_dev, double *params_out_dev, int64_t K, const ft_chart_t *U,
+                         const ft_chart_t *S, const map_params_t *map, const newton_params_t *np, double *f_dev,
+                         double *r_dev, int32_t *status_dev, int32_t *trials_dev, void *ws, size_t ws_bytes,
+                         void *stream)
+{
+    if (K < 0 || !U || !S || !map || !np || (K > 0 && (!params_in_dev || !params_out_dev)))
+        return fail(MS_E_ARG, "ft_newton: bad argument");
+    if (np->max_trials < 0 || np->max_trials > 100000) return fail(MS_E_ARG, "ft_newton: max_trials out of range");
+    if (!(np->alpha0 > 0.0 && np->alpha0 <= 1.0) || !(np->alpha_min > 0.0) || !(np->tol >= 0.0))
+        return fail(MS_E_ARG, "ft_newton: need 0 < alpha0 <= 1, alpha_min > 0, tol >= 0");
+    if (!U->spec_dev || !S->spec_dev) return fail(MS_E_ARG, "ft_newton: chart spectra missing");
+    if (K == 0) return MS_OK;
+    if (K > ((int64_t)1 << 28)) return fail(MS_E_ARG, "ft_newton: K too large");
+    const FtnLayout L = ftn_layout(K);
+    if (!ws || ws_bytes < L.total) return fail(MS_E_WORKSPACE, "ft_newton: workspace too small");
+    char *w = (char *)ws;
+    NewtonState ns;
+    ns.p = (double *)(w + L.o[0]);
+    ns.q = (double *)(w + L.o[1]);
+    ns.delta = (double *)(w + L.o[2]);
+    ns.fp = (double *)(w + L.o[3]);
+    ns.rp = (double *)(w + L.o[4]);
+    ns.alpha = (double *)(w + L.o[5]);
+    ns.status = (int32_t *)(w + L.o[6]);
+    ns.trials = (int32_t *)(w + L.o[7]);
+    ns.based = (int32_t *)(w + L.o[8]);
+    FtSide su{(double *)(w + L.o[9]), (double *)(w + L.o[10]), (double *)(w + L.o[11]), (double *)(w + L.o[12]),
+              (double *)(w + L.o[13]), (double *)(w + L.o[14])};
+    FtSide ss{(double *)(w + L.o[15]), (double *)(w + L.o[16]), (double *)(w + L.o[17]), (double *)(w + L.o[18]),
+              (double *)(w + L.o[19]), (double *)(w + L.o[20])};
+    unsigned long long *running = (unsigned long long *)(w + L.o[21]);
+    NewtonCfg cfg;
+    cfg.tol2 = np->tol * np->tol;
+    cfg.alpha0 = np->alpha0;
+    cfg.alpha_min = np->alpha_min;
+    cfg.max_trials = np->max_trials;
+    hipStream_t st = (hipStream_t)stream;
+    const dim3 grid((unsigned)ceil_div(K, 256));
+    map_params_t mu_map = *map, ms_map = *map;
+    mu_map.n_periods = U->n_periods;
+    ms_map.n_periods = S->n_periods;
+    hipLaunchKernelGGL(k_ftn_init, grid, dim3(256), 0, st, params_in_dev, ns, K, su, ss, running);
+    MS_HIP(hipGetLastError());
+    for (int it = 0; it <= np->max_trials; ++it) {
+        int rc = ft_partials(U->spec_dev, U->n_theta, U->order, su.th, su.s, K, U->omega, U->lambda, &mu_map, su.w,
+                             su.dth, su.ds, su.stm, stream);
+        if (rc) return rc;
+        rc = ft_partials(S->spec_dev, S->n_theta, S->order, ss.th, ss.s, K, S->omega, S->lambda, &ms_map, ss.w,
+                         ss.dth, ss.ds, ss.stm, stream);
+        if (rc) return rc;
+        const int par = it & 1;
+        hipLaunchKernelGGL(k_ftn_update, grid, dim3(256), 0, st, ns, cfg, K, su, ss, running, par);
+        MS_HIP(hipGetLastError());
+        unsigned long long left = 0;
+        MS_HIP(hipMemcpyAsync(&left, running + par, sizeof left, hipMemcpyDeviceToHost, st));
+        MS_HIP(hipStreamSynchronize(st));
+        if (left == 0) break;
+    }
+    hipLaunchKernelGGL(k_ftn_finish, grid, dim3(256), 0, st, ns, K, params_out_dev, f_dev, r_dev, status_dev,
+                       trials_dev);
+    MS_HIP(hipGetLastError());
+    return MS_OK;
+}
 
 extern "C" int ft_partials(const double *spec_dev, int32_t n_theta, int32_t order, const double *theta_dev,
                            const double *s_dev, int64_t n_query, double omega, double lambda,

@@ -25,6 +25,7 @@
 
 #include <mutex>
 
+#include "newton.hpp"
 #include "rk8_core.hpp"
 
 namespace ms {
@@ -407,73 +408,11 @@ __global__ void __launch_bounds__(RF_BLOCK) k_ref_grad(RefArgs a, double *g_out)
 
 // ------------------------------------------------------------ damped Newton
 
-enum { NW_RUNNING = -1, NW_CONVERGED = 0, NW_LIMIT = 1, NW_STALLED = 2, NW_SINGULAR = 3, NW_NONFINITE = 4 };
-
-struct NewtonState {
-    double *p, *q, *delta, *fp;   // K x 4
-    double *rp, *alpha;           // K
-    int32_t *status, *trials, *based;
-};
-
-struct NewtonCfg {
-    double tol2, alpha0, alpha_min;
-    int32_t max_trials;
-};
-
-// Solve M z = r (4 x 4) by Gaussian elimination with partial pivoting: pivot
-// = first row of largest magnitude; an exact zero pivot means singular.
-MS_D bool gepp4(double M[4][4], double r[4], double z[4])
-{
-    bool ok = true;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        int piv = k;
-        double best = fabs(M[k][k]);
-#pragma unroll
-        for (int i = k + 1; i < 4; ++i) {
-            double v = fabs(M[i][k]);
-            if (v > best) { best = v; piv = i; }
-        }
-#pragma unroll
-        for (int i = k + 1; i < 4; ++i) {
-            bool sw = piv == i;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                double x = M[k][j], y = M[i][j];
-                M[k][j] = sw ? y : x;
-                M[i][j] = sw ? x : y;
-            }
-            double x = r[k], y = r[i];
-            r[k] = sw ? y : x;
-            r[i] = sw ? x : y;
-        }
-        ok = ok && (M[k][k] != 0.0);
-#pragma unroll
-        for (int i = k + 1; i < 4; ++i) {
-            double l = M[i][k] / M[k][k];
-#pragma unroll
-            for (int j = k + 1; j < 4; ++j) M[i][j] = M[i][j] - l * M[k][j];
-            r[i] = r[i] - l * r[k];
-        }
-    }
-#pragma unroll
-    for (int k = 3; k >= 0; --k) {
-        double acc = 0.0;
-#pragma unroll
-        for (int j = k + 1; j < 4; ++j) acc = acc + M[k][j] * z[j];
-        z[k] = (r[k] - acc) / M[k][k];
-    }
-    return ok;
-}
-
 __global__ void __launch_bounds__(RF_BLOCK) k_newton_init(const double *x0, NewtonState ns, int64_t K)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= K) return;
-    for (int c = 0; c < 4; ++c) ns.q[4 * k + c] = x0[4 * k + c];
-    ns.status[k] = NW_RUNNING;
-    ns.trials[k] = 0;
-    ns.based[k] = 0;
+    newton_init(k, x0, ns);
 }
 
 // One decision per running hit after the tangent pass at its trial point q.
@@ -483,54 +422,15 @@ __global__ void __launch_bounds__(RF_BLOCK) k_newton_update(RefArgs a, NewtonSta
     if (k >= a.K || ns.status[k] >= 0) return;
     const int64_t T2 = 2 * a.K;
     const double *yu = a.yend + 4 * k, *ys = a.yend + 4 * (a.K + k);
-    double f[4], r = 0.0;
+    double f[4], M[4][4];
     for (int c = 0; c < 4; ++c) {
         f[c] = yu[c] - ys[c];
-        r += f[c] * f[c];
+        M[c][0] = a.dend[(0 * T2 + k) * 4 + c];
+        M[c][1] = a.dend[(1 * T2 + k) * 4 + c];
+        M[c][2] = -a.dend[(0 * T2 + a.K + k) * 4 + c];
+        M[c][3] = -a.dend[(1 * T2 + a.K + k) * 4 + c];
     }
-    int st = NW_RUNNING;
-    bool accept;
-    if (!ns.based[k]) {
-        accept = true;
-        if (!isfinite(r)) st = NW_NONFINITE;
-    } else {
-        ns.trials[k] += 1;
-        accept = r < ns.rp[k];
-    }
-    if (accept && st == NW_RUNNING) {
-        for (int c = 0; c < 4; ++c) {
-            ns.p[4 * k + c] = ns.q[4 * k + c];
-            ns.fp[4 * k + c] = f[c];
-        }
-        ns.rp[k] = r;
-        ns.alpha[k] = cfg.alpha0;
-        ns.based[k] = 1;
-        if (r <= cfg.tol2) {
-            st = NW_CONVERGED;
-        } else {
-            double M[4][4], rhs[4], z[4];
-            for (int c = 0; c < 4; ++c) {
-                M[c][0] = a.dend[(0 * T2 + k) * 4 + c];
-                M[c][1] = a.dend[(1 * T2 + k) * 4 + c];
-                M[c][2] = -a.dend[(0 * T2 + a.K + k) * 4 + c];
-                M[c][3] = -a.dend[(1 * T2 + a.K + k) * 4 + c];
-                rhs[c] = -f[c];
-            }
-            if (!gepp4(M, rhs, z)) st = NW_SINGULAR;
-            else
-                for (int c = 0; c < 4; ++c) ns.delta[4 * k + c] = z[c];
-        }
-    } else if (st == NW_RUNNING) {
-        double al = ns.alpha[k] * 0.5;
-        ns.alpha[k] = al;
-        if (al < cfg.alpha_min) st = NW_STALLED;
-    }
-    if (st == NW_RUNNING && ns.trials[k] >= cfg.max_trials) st = NW_LIMIT;
-    if (st == NW_RUNNING) {
-        double al = ns.alpha[k];
-        for (int c = 0; c < 4; ++c) ns.q[4 * k + c] = ns.p[4 * k + c] + al * ns.delta[4 * k + c];
-    }
-    ns.status[k] = st;
+    newton_decide(k, f, M, ns, cfg);
 }
 
 __global__ void __launch_bounds__(RF_BLOCK) k_newton_finish(NewtonState ns, int64_t K, double *x_out, double *f_out,
@@ -538,15 +438,7 @@ __global__ void __launch_bounds__(RF_BLOCK) k_newton_finish(NewtonState ns, int6
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= K) return;
-    int st = ns.status[k] < 0 ? NW_LIMIT : ns.status[k];
-    const bool based = ns.based[k] != 0;
-    for (int c = 0; c < 4; ++c) {
-        x_out[4 * k + c] = based ? ns.p[4 * k + c] : ns.q[4 * k + c];
-        if (f_out) f_out[4 * k + c] = based ? ns.fp[4 * k + c] : NAN;
-    }
-    if (r_out) r_out[k] = based ? ns.rp[k] : NAN;
-    if (st_out) st_out[k] = st;
-    if (tr_out) tr_out[k] = ns.trials[k];
+    newton_finish(k, ns, x_out, f_out, r_out, st_out, tr_out);
 }
 
 // ---------------------------------------------------------------- host side

@@ -94,3 +94,33 @@ def test_edges(ms):
     assert e[0].shape == (0, 4)
     with pytest.raises(ms.MSearchError):
         ms.theta_spectrum(np.zeros((2, 12, 4)))
+
+
+def test_newton_matches_oracle_on_a_planted_root(ms):
+    """Two charts built by the oracle to meet at a known parameter point; 12
+    perturbed starts refined on the GPU and by the oracle: the same status,
+    the planted root, and the same number of trial points (within one)."""
+    bu = synth.periapse_position_momentum(np.array(synth.UNSTABLE_BASE), ECC)
+    bs = synth.periapse_position_momentum(np.array(synth.STABLE_BASE), ECC)
+    gu, gs = (2, 0.61, 1.35), (-2, 0.47, 1 / 1.35)
+    root = np.array([1.3, 0.02, 4.1, -0.015])
+    cu, cs = ft.planted_charts(64, 5, 11, root, gu, gs, MU, ECC, 1000, bu, bs)
+    rng = np.random.default_rng(4)
+    x0 = root[None, :] + rng.uniform(-3e-4, 3e-4, (12, 4))
+    ref = ft.newton(cu, cs, x0, gu, gs, MU, ECC, 1000, tol=1e-12)
+    got = [t.cpu().numpy() for t in ms.ft_newton(x0, ms.FourierTaylor(cu), gu, ms.FourierTaylor(cs), gs,
+                                                  MU, ECC, 1000, tol=1e-12)]
+    assert np.array_equal(got[3], ref[3])
+    ok = ref[3] == 0
+    assert ok.all()
+    assert np.max(np.abs(got[0][ok] - root)) < 1e-9 and np.max(np.abs(got[0] - ref[0])) < 1e-9
+    assert np.max(np.abs(got[4] - ref[4])) <= 1
+    assert np.all(got[2] <= 1e-24)
+    # a trial limit of one: both stop with status 1 after one trial point
+    lim = [t.cpu().numpy() for t in ms.ft_newton(x0[:3], ms.FourierTaylor(cu), gu, ms.FourierTaylor(cs), gs,
+                                                  MU, ECC, 1000, max_trials=1)]
+    ref1 = ft.newton(cu, cs, x0[:3], gu, gs, MU, ECC, 1000, max_trials=1)
+    assert np.array_equal(lim[3], ref1[3]) and np.array_equal(lim[4], ref1[4])
+    # one step x0 - Df^-1 f: the ~1e-12 differences of f and Df between the two
+    # sides reach x through Df^-1, whose entries are ~1e2 here
+    assert np.max(np.abs(lim[0] - ref1[0])) < 1e-8
