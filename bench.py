@@ -501,9 +501,36 @@ def main():
         t_glob = time.perf_counter() - t0
         out["ft_local_partials_per_s"] = NQ / t_loc
         out["ft_global_partials_ms"] = t_glob * 1e3
+        # damped Newton on two charts made to meet at a known point: the stable
+        # chart's s^0 coefficient is shifted so that its local point at the
+        # root is F^2 of the unstable chart's globalized point (GPU map)
+        MU_JE, ECC_JE, ST = 2.527e-5, 0.0094, 4000
+        gu, gs = (2, 0.61, 1.35), (-2, 0.47, 1 / 1.35)
+        root = np.array([1.3, 0.02, 4.1, -0.015])
+        cs = coeffs.copy()
+        cs[0] += (synth.periapse_position_momentum(np.array(synth.STABLE_BASE), ECC_JE) - base)[None, :]
+        pu = chart.partials([root[0]], [root[1]], *gu, MU_JE, ECC_JE, ST)[0]
+        loc_s = ms.FourierTaylor(cs).partials([root[2] - gs[0] * gs[1]], [gs[2] ** (-gs[0]) * root[3]])[0]
+        target = ms.pertbp_map(pu, MU_JE, ECC_JE, ST, -gs[0])
+        cs[0] += (target - loc_s).cpu().numpy()[0][None, :]
+        chart_s = ms.FourierTaylor(cs)
+        KN = 256
+        x0 = root[None, :] + rng.uniform(-3e-4, 3e-4, (KN, 4))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xn, fn, rn, stn, trn = ms.ft_newton(x0, chart, gu, chart_s, gs, MU_JE, ECC_JE, ST, tol=1e-12)
+        torch.cuda.synchronize()
+        t_newton = time.perf_counter() - t0
+        stn = stn.cpu().numpy()
+        out["ft_newton_ms"] = t_newton * 1e3
+        out["ft_newton_converged"] = int(np.sum(stn == 0))
+        out["ft_newton_max_root_error"] = float(np.max(np.abs(xn.cpu().numpy() - root)))
+        out["ft_newton_max_trials_used"] = int(trn.cpu().numpy().max())
         log(f"fourier-taylor: {NQ} local chart partials (N={N_TH}, order {ORDER}) in {t_loc * 1e3:.3f} ms; "
-            f"globalized through F^3 / DF^3 in {t_glob * 1e3:.1f} ms")
-        del chart
+            f"globalized through F^3 / DF^3 in {t_glob * 1e3:.1f} ms; Newton on {KN} starts "
+            f"{t_newton * 1e3:.1f} ms ({int(np.sum(stn == 0))} converged, root error "
+            f"{out['ft_newton_max_root_error']:.1e})")
+        del chart, chart_s
 
     # ------------------------- plain device copy (HBM reference, counter scale)
     if "copy" in legs:

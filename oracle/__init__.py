@@ -6,7 +6,9 @@ package imports nothing from the product path.
 
 Python side of the plain C oracle in oracle.c (loaded through ctypes); see
 that file for the definitions and their sources in the paper.  exact.py holds
-the rational-arithmetic checks.
+the rational-arithmetic checks, spectral.py the FFT translation, derivative
+and trigonometric interpolation in theta, fourier_taylor.py the Fourier-Taylor
+charts, their globalized partials and the chart-based Newton.
 """
 from __future__ import annotations
 
