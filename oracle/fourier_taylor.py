@@ -155,3 +155,30 @@ def planted_charts(N: int, order: int, seed: int, root, chart_u, chart_s, mu: fl
     target = pertbp_map(pu[None], mu, eps, steps_per_period, -m_s)[0]
     cs[0] += (target - local_s)[None, :]
     return cu, cs
+
+
+def continuation_predict(x0, omega0, domega, x1=None, omega1=None):
+    """Initial guess for the connection at rotation numbers
+    (omega_u, omega_s) = omega0 + domega (paper Sec. 8): x0 itself on a first
+    step (no earlier solution x1), else the linear predictor
+        x = x0 + q (x0 - x1),  q = domega_u / (omega_u0 - omega_u1),
+    with q = domega_s / (omega_s0 - omega_s1) instead when domega_u = 0 (and
+    q = 0 when both are 0).  Rows: x (K, 4) = (theta_u, s_u, theta_s, s_s),
+    omega (K, 2) = (omega_u, omega_s)."""
+    x0 = np.asarray(x0, dtype=np.float64).reshape(-1, 4)
+    if x1 is None:
+        return x0.copy()
+    x1 = np.asarray(x1, dtype=np.float64).reshape(-1, 4)
+    o0 = np.asarray(omega0, dtype=np.float64).reshape(-1, 2)
+    o1 = np.asarray(omega1, dtype=np.float64).reshape(-1, 2)
+    d = np.asarray(domega, dtype=np.float64).reshape(-1, 2)
+    out = np.empty_like(x0)
+    for k in range(x0.shape[0]):
+        if d[k, 0] != 0.0:
+            q = d[k, 0] / (o0[k, 0] - o1[k, 0])
+        elif d[k, 1] != 0.0:
+            q = d[k, 1] / (o0[k, 1] - o1[k, 1])
+        else:
+            q = 0.0
+        out[k] = x0[k] + q * (x0[k] - x1[k])
+    return out

@@ -111,3 +111,21 @@ def test_newton_finds_a_planted_root():
     assert st[0] == 0 and np.max(np.abs(x[0] - root)) < 1e-9
     seq = hist[0]
     assert len(seq) >= 3 and seq[2] < 1e-3 * seq[1] and seq[1] < 1e-2 * seq[0]
+
+
+def test_continuation_predictor():
+    """Exact for solutions that move linearly along the line of rotation
+    numbers; the s ratio when omega_u does not change; x0 on a first step."""
+    rng = np.random.default_rng(6)
+    a, b = rng.standard_normal((5, 4)), rng.standard_normal((5, 4))
+    dirn = np.array([[0.3, -0.2]] * 5)
+    w0 = np.array([[0.61, 0.47]] * 5)
+    x = lambda t: a + t * b                          # the solution at omega = w0 + t dirn
+    w1 = w0 - 0.01 * dirn
+    got = ft.continuation_predict(x(0.0), w0, 0.02 * dirn, x(-0.01), w1)
+    assert np.max(np.abs(got - x(0.02))) < 1e-13
+    only_s = np.array([[0.0, 0.4]] * 5)
+    got = ft.continuation_predict(x(0.0), w0, 0.05 * only_s, x(-0.02), w0 - 0.02 * only_s)
+    assert np.max(np.abs(got - x(0.05))) < 1e-13
+    assert np.array_equal(ft.continuation_predict(x(0.0), w0, 0.02 * dirn), x(0.0))
+    assert np.array_equal(ft.continuation_predict(x(0.0), w0, 0 * dirn, x(-0.01), w1), x(0.0))
