@@ -525,6 +525,17 @@ typedef struct {
 } ft_chart_t;
 
 int ft_newton_workspace_size(int64_t K, size_t *bytes);
+
+/* continuation_predict -- initial guesses for a continuation step along a
+ * line of rotation numbers (Sec. 8): for row k, x = x0 on a first step
+ * (x1_dev == NULL), else
+ *   x = x0 + q (x0 - x1),  q = domega_u / (omega_u0 - omega_u1),
+ * or q = domega_s / (omega_s0 - omega_s1) when domega_u == 0 (q = 0 when
+ * both are 0).  x0, x1, out: K x 4 (theta_u, s_u, theta_s, s_s); omega0,
+ * omega1, domega: K x 2 (omega_u, omega_s).  out may equal x0.  A zero
+ * denominator gives non-finite rows.  Asynchronous. */
+int continuation_predict(const double *x0_dev, const double *omega0_dev, const double *domega_dev,
+                         const double *x1_dev, const double *omega1_dev, int64_t K, double *out_dev, void *stream);
 int ft_newton(const double *params_in_dev, double *params_out_dev, int64_t K, const ft_chart_t *U,
               const ft_chart_t *S, const map_params_t *map, const newton_params_t *np, double *f_dev,
               double *r_dev, int32_t *status_dev, int32_t *trials_dev, void *ws, size_t ws_bytes, void *stream);

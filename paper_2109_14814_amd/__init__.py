@@ -26,7 +26,7 @@ EXPORTS = ("last_error", "mesh_build", "mesh_free", "mesh_info", "mesh_update", 
            "search_profile_enable", "search_profile_read", "batch_create", "batch_search", "batch_needed",
            "batch_free", "refine_workspace_size", "refine_grad", "refine_newton", "layer_pairs",
            "half_layer_bounds", "half_layer_columns", "pertbp_map", "pertbp_map_stm", "theta_shift", "theta_interp", "theta_spectrum",
-           "ft_partials", "ft_newton_workspace_size", "ft_newton")
+           "ft_partials", "ft_newton_workspace_size", "ft_newton", "continuation_predict")
 
 MS_REFINE_RESIDUAL, MS_REFINE_ADJOINT, MS_REFINE_TANGENT, MS_REFINE_NEWTON = 0, 1, 2, 3
 NEWTON_STATUS = {0: "converged", 1: "trial limit", 2: "step too small", 3: "singular", 4: "non-finite"}
@@ -114,6 +114,8 @@ def lib():
         L.ft_newton.argtypes = [P, P, I64, C.POINTER(FtChart), C.POINTER(FtChart), C.POINTER(MapParams),
                                 C.POINTER(NewtonParams), P, P, P, P, P, C.c_size_t, P]
         L.ft_newton.restype = C.c_int
+        L.continuation_predict.argtypes = [P, P, P, P, P, I64, P, P]
+        L.continuation_predict.restype = C.c_int
         L.mesh_update.argtypes = [P, P]; L.mesh_update.restype = C.c_int
         L.batch_create.argtypes = [I32, P, P, P, I64, I64, P, C.POINTER(P), C.POINTER(C.c_size_t)]
         L.batch_create.restype = C.c_int
@@ -705,6 +707,23 @@ def ft_newton(params, chart_u: "FourierTaylor", glob_u, chart_s: "FourierTaylor"
     _check(lib().ft_newton(_ptr(x), _ptr(xo), K, C.byref(cu), C.byref(cs), C.byref(mp), C.byref(npar), _ptr(f),
                            _ptr(r), _ptr(st), _ptr(tr), _ptr(ws), nb.value, _stream()))
     return xo, f, r, st, tr
+
+
+def continuation_predict(x0, omega0, domega, x1=None, omega1=None):
+    """Initial guesses for a continuation step (continuation_predict of the C
+    ABI): rows x (K, 4), omega (K, 2).  Returns a cuda tensor (K, 4)."""
+    torch = _torch()
+    dev = lambda a, w: torch.as_tensor(a, dtype=torch.float64).to("cuda").contiguous().reshape(-1, w)
+    a0 = dev(x0, 4)
+    K = a0.shape[0]
+    o0, d = dev(omega0, 2), dev(domega, 2)
+    a1 = dev(x1, 4) if x1 is not None else None
+    o1 = dev(omega1, 2) if x1 is not None else None
+    if any(t.shape[0] != K for t in (o0, d) + ((a1, o1) if a1 is not None else ())):
+        raise ValueError("one row per problem in every argument")
+    out = torch.empty_like(a0)
+    _check(lib().continuation_predict(_ptr(a0), _ptr(o0), _ptr(d), _ptr(a1), _ptr(o1), K, _ptr(out), _stream()))
+    return out
 
 
 # ------------------------------------------------------------- refinement

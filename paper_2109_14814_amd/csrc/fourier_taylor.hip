@@ -177,6 +177,24 @@ __global__ void __launch_bounds__(256) k_ftn_finish(NewtonState ns, int64_t K, d
     newton_finish(k, ns, x_out, f_out, r_out, st_out, tr_out);
 }
 
+// Linear continuation predictor (Sec. 8), one row per thread.
+__global__ void __launch_bounds__(256) k_cont_predict(const double *x0, const double *x1, const double *om0,
+                                                      const double *om1, const double *dom, int64_t K, double *out)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    double q = 0.0;
+    if (x1) {
+        if (dom[2 * k] != 0.0) q = dom[2 * k] / (om0[2 * k] - om1[2 * k]);
+        else if (dom[2 * k + 1] != 0.0) q = dom[2 * k + 1] / (om0[2 * k + 1] - om1[2 * k + 1]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const double a = x0[4 * k + c];
+        out[4 * k + c] = x1 ? a + q * (a - x1[4 * k + c]) : a;
+    }
+}
+
 // Workspace layout of ft_newton for K problems (256-byte aligned pieces).
 struct FtnLayout {
     size_t total;
@@ -204,6 +222,20 @@ FtnLayout ftn_layout(int64_t K)
 }  // namespace ms
 
 using namespace ms;
+
+extern "C" int continuation_predict(const double *x0_dev, const double *omega0_dev, const double *domega_dev,
+                                    const double *x1_dev, const double *omega1_dev, int64_t K, double *out_dev,
+                                    void *stream)
+{
+    if (K < 0 || (K > 0 && (!x0_dev || !out_dev || (x1_dev && (!omega0_dev || !omega1_dev || !domega_dev)))))
+        return fail(MS_E_ARG, "continuation_predict: bad argument");
+    if (K == 0) return MS_OK;
+    if (ceil_div(K, 256) > 0x7fffffff) return fail(MS_E_ARG, "continuation_predict: too many rows");
+    hipLaunchKernelGGL(k_cont_predict, dim3((unsigned)ceil_div(K, 256)), dim3(256), 0, (hipStream_t)stream, x0_dev,
+                       x1_dev, omega0_dev, omega1_dev, domega_dev, K, out_dev);
+    MS_HIP(hipGetLastError());
+    return MS_OK;
+}
 
 extern "C" int ft_newton_workspace_size(int64_t K, size_t *bytes)
 {

@@ -124,3 +124,39 @@ def test_newton_matches_oracle_on_a_planted_root(ms):
     # one step x0 - Df^-1 f: the ~1e-12 differences of f and Df between the two
     # sides reach x through Df^-1, whose entries are ~1e2 here
     assert np.max(np.abs(lim[0] - ref1[0])) < 1e-8
+
+
+def test_continuation_predictor_matches_oracle(ms):
+    rng = np.random.default_rng(12)
+    K = 333
+    x0, x1 = rng.standard_normal((K, 4)), rng.standard_normal((K, 4))
+    w0, w1 = rng.uniform(0.4, 0.7, (K, 2)), rng.uniform(0.4, 0.7, (K, 2))
+    dw = rng.uniform(-0.01, 0.01, (K, 2))
+    dw[::3, 0] = 0.0                                  # the omega_s branch
+    dw[::7] = 0.0                                     # no change at all
+    got = ms.continuation_predict(x0, w0, dw, x1, w1).cpu().numpy()
+    ref = ft.continuation_predict(x0, w0, dw, x1, w1)
+    assert np.max(np.abs(got - ref)) < 1e-12
+    assert np.array_equal(ms.continuation_predict(x0, w0, dw).cpu().numpy(), x0)
+
+
+def test_continuation_step(ms):
+    """Charts whose meeting point moves linearly with the rotation number of
+    the unstable torus: from the solutions at omega_u0 and omega_u1 the
+    predictor lands on the solution at omega_u0 + d, and Newton from there
+    converges at once (from the previous solution it needs more trials)."""
+    bu = synth.periapse_position_momentum(np.array(synth.UNSTABLE_BASE), ECC)
+    bs = synth.periapse_position_momentum(np.array(synth.STABLE_BASE), ECC)
+    gs = (-2, 0.47, 1 / 1.35)
+    r0, v = np.array([1.3, 0.02, 4.1, -0.015]), np.array([0.5, 0.01, -0.3, 0.004])
+    root = lambda w: r0 + (w - 0.61) * v
+    w0, w1, d = 0.61, 0.60, 0.02
+    gu = lambda w: (2, w, 1.35)
+    cu, cs = ft.planted_charts(64, 5, 11, root(w0 + d), gu(w0 + d), gs, MU, ECC, 1000, bu, bs)
+    x_pred = ms.continuation_predict(root(w0)[None], [[w0, 0.47]], [[d, 0.0]], root(w1)[None], [[w1, 0.47]])
+    assert np.max(np.abs(x_pred.cpu().numpy()[0] - root(w0 + d))) < 1e-12
+    starts = np.stack([x_pred.cpu().numpy()[0], root(w0)])
+    x, f, r, st, tr = (t.cpu().numpy() for t in ms.ft_newton(starts, ms.FourierTaylor(cu), gu(w0 + d),
+                                                               ms.FourierTaylor(cs), gs, MU, ECC, 1000))
+    assert np.all(st == 0) and np.max(np.abs(x - root(w0 + d))) < 1e-9
+    assert tr[0] <= 1 and tr[1] > tr[0]
