@@ -602,6 +602,44 @@ def main():
                                "cores": oracle.max_threads(), "kind": "oracle",
                                "sample": f"{reps} full 512^2 grid searches (same grid), {per * 1e3:.1f} ms each"}
         log(f"cpu oracle: {per * 1e3:.1f} ms per search on {oracle.max_threads()} threads")
+        # the oracle of the other rows on bounded samples of their workloads
+        # (each a few seconds), in the units of the GPU legs
+        from oracle import fourier_taylor as oft
+        from oracle import spectral as osp
+        ob = {}
+        y0 = synth.random_states(8192, args.seed, synth.UNSTABLE_BASE, 1e-3)
+        t0 = time.perf_counter()
+        oracle.rk8_map(y0, 2.528e-5, 0.0094, 4000, 1)
+        dt = time.perf_counter() - t0
+        ob["rk8_map"] = {"value": 8192 * 4000 / dt, "unit": "vertex-steps/s",
+                         "sample": f"F^1 of 8192 states, 4000 steps ({dt:.2f} s)"}
+        z0 = synth.pm_random_states(512, args.seed, 0.0094, synth.UNSTABLE_BASE, 1e-3)
+        t0 = time.perf_counter()
+        oracle.pertbp_map(z0, 2.527e-5, 0.0094, 4000, 1)
+        dt = time.perf_counter() - t0
+        ob["pertbp_map"] = {"value": 512 * 4000 / dt, "unit": "state-steps/s",
+                            "sample": f"F^1 of 512 states, 4000 steps ({dt:.2f} s)"}
+        t0 = time.perf_counter()
+        oracle.pertbp_map(z0[:128], 2.527e-5, 0.0094, 4000, 1, stm=True)
+        dt = time.perf_counter() - t0
+        ob["pertbp_stm"] = {"value": 128 * 4000 / dt, "unit": "state-steps/s (with DF)",
+                            "sample": f"DF^1 of 128 states, 4000 steps ({dt:.2f} s)"}
+        rows = np.random.default_rng(args.seed).standard_normal((2048, 2048, 4))
+        rho = np.random.default_rng(args.seed + 1).uniform(-np.pi, np.pi, 2048)
+        t0 = time.perf_counter()
+        osp.shift_derivative(rows, rho, 0)
+        dt = time.perf_counter() - t0
+        ob["theta_shift"] = {"value": rows.nbytes * 2 / dt / 1e9, "unit": "GB/s (read + write once)",
+                             "sample": f"2048 rows x 2048 samples ({dt:.2f} s)"}
+        c = np.random.default_rng(args.seed).standard_normal((26, 2048, 4)) * 1e-3
+        t0 = time.perf_counter()
+        for q in range(1024):
+            oft.local(c, 0.1 * q, 0.01)
+        dt = time.perf_counter() - t0
+        ob["ft_local_partials"] = {"value": 1024 / dt, "unit": "points/s (order 25, N = 2048)",
+                                   "sample": f"1024 points ({dt:.2f} s)"}
+        out["oracle_baselines"] = ob
+        log("cpu oracle, other rows: " + ", ".join(f"{k} {v['value']:.3g} {v['unit']}" for k, v in ob.items()))
 
     print(json.dumps(out), flush=True)
 
