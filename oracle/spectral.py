@@ -63,3 +63,36 @@ def interpolate(rows: np.ndarray, theta) -> np.ndarray:
     if N % 2 == 0:
         e[..., N // 2] = np.cos(N / 2 * th[..., 0])
     return (e @ A).real / N
+
+
+def globalize(grid, s, n_max: int, omega: float, lam: float, direction: int, mu: float, eps: float,
+              steps_per_period: int):
+    """The globalized mesh of Sec. 6.1 from a fundamental-domain grid
+    grid (n_s, N, 4) = W(theta_i, s_k) (s increasing).  For n = 0..n_max the
+    points F^{d n}(W(theta_i, s_k)) = W(theta_i + d n omega, lam^{d n} s_k)
+    (d = +1 for an unstable manifold with the map F, -1 for a stable one with
+    F^-1 and its own lam) are shifted back by rho = -d n omega, giving
+    W(theta_i, lam^{d n} s_k).  The rows are returned sorted by their s
+    values, with the row s = 0 (the torus) kept once.  Returns (mesh (M, N,
+    4), s (M,), source (M, 2) = (n, k) of each row).  F is the position-momentum
+    map (oracle.pertbp_map), applied to the base grid n times at once."""
+    from . import pertbp_map
+    g = np.asarray(grid, dtype=np.float64)
+    n_s, N = g.shape[0], g.shape[1]
+    sv = np.asarray(s, dtype=np.float64)
+    rows, svals, src = [], [], []
+    for n in range(n_max + 1):
+        if n == 0:
+            P = g.copy()
+        else:
+            P = pertbp_map(g.reshape(-1, 4), mu, eps, steps_per_period, direction * n).reshape(g.shape)
+            P = shift_derivative(P, -direction * n * omega, 0)
+        for k in range(n_s):
+            if n > 0 and sv[k] == 0.0:
+                continue
+            rows.append(P[k])
+            svals.append(lam ** (direction * n) * sv[k])
+            src.append((n, k))
+    order = sorted(range(len(svals)), key=lambda i: svals[i])
+    return (np.stack([rows[i] for i in order]), np.array([svals[i] for i in order]),
+            np.array([src[i] for i in order]))
