@@ -173,7 +173,7 @@ def main():
     ap.add_argument("--n", type=int, default=512, help="quads per axis of each surface")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--kappa", type=float, default=0.0, help="cell edge / mean triangle diameter (0 = autotune)")
-    ap.add_argument("--legs", default="search,allpairs,family,layers,rk8,pertbp,spectral,ft,refine,copy,cpu")
+    ap.add_argument("--legs", default="search,allpairs,family,layers,rk8,pertbp,spectral,globalize,ft,refine,copy,cpu")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -471,6 +471,30 @@ def main():
             f"({nbytes / sp_t[0] / 1e9:.0f} GB/s algorithmic), derivative {sp_t[1] * 1e3:.3f} ms; "
             f"{nq} interpolations in {t_i * 1e3:.2f} ms")
         del rows, dst
+
+    # ------------- globalized manifold mesh (Sec. 6.1): 14 layers of a 2048 x 35 grid
+    if "globalize" in legs:
+        N_TH, K_S, N_MAX = 2048, 17, 14
+        s_grid = np.array([k * 0.02 / K_S for k in range(-K_S, K_S + 1)])
+        th = 2 * np.pi * np.arange(N_TH) / N_TH
+        base = synth.periapse_position_momentum(np.array(synth.UNSTABLE_BASE), 0.0094)
+        rng = np.random.default_rng(args.seed)
+        d1, d2 = rng.standard_normal(4), rng.standard_normal(4)
+        grid = (base[None, None, :] + 1e-3 * (np.cos(th)[None, :, None] * d1 + np.sin(2 * th)[None, :, None] * d2)
+                + s_grid[:, None, None] * d2[None, None, :])
+        g_dev = torch.tensor(grid, device="cuda")
+        ms.globalize(g_dev, s_grid, 1, 0.61, 1.35, 1, 2.527e-5, 0.0094, 4000)      # tables, warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rows_g, s_g = ms.globalize(g_dev, s_grid, N_MAX, 0.61, 1.35, 1, 2.527e-5, 0.0094, 4000)
+        torch.cuda.synchronize()
+        t_gl = time.perf_counter() - t0
+        out["globalize_ms"] = t_gl * 1e3
+        out["globalize_rows"] = int(rows_g.shape[0])
+        out["globalize_state_steps_per_s"] = N_MAX * grid.shape[0] * N_TH * 4000 / t_gl
+        log(f"globalize: {N_MAX} layers of a {grid.shape[0]} x {N_TH} grid -> {rows_g.shape[0]} rows in "
+            f"{t_gl * 1e3:.1f} ms ({out['globalize_state_steps_per_s']:.3e} state-steps/s)")
+        del g_dev, rows_g
 
     # ------------- Fourier-Taylor chart partials, local and through F^3 (Sec. 7)
     if "ft" in legs:

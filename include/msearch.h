@@ -380,6 +380,28 @@ int theta_shift(const double *in_dev, double *out_dev, int32_t n_theta, int64_t 
  * per (device, n_theta) builds the twiddle table as theta_shift does. */
 int theta_spectrum(const double *in_dev, double *out_dev, int32_t n_theta, int64_t n_rows, void *stream);
 
+/*
+ * globalize_manifold -- the globalized mesh of a manifold (Sec. 6.1).  From
+ * the fundamental-domain grid W(theta_i, s_k) (grid_dev: n_s rows of
+ * n_theta vertices, AoS 4 doubles, s_host[k] strictly increasing), for
+ * n = 1..n_max the points F^(d n)(W(theta_i, s_k)) = W(theta_i + d n omega,
+ * lambda^(d n) s_k) are shifted back by -d n omega (theta_shift), giving
+ * W(theta_i, lambda^(d n) s_k); d = map->n_periods = +1 for an unstable
+ * manifold (the map F, multiplier lambda > 1) or -1 for a stable one (F^-1,
+ * its multiplier lambda < 1).  F is the position-momentum map of pertbp_map
+ * with map's mu, e and steps_per_period, applied once per layer to the
+ * previous layer's points.  The rows, s = lambda^(d n) s_k, are written to
+ * out_dev sorted by s (the row s = 0, the torus, once), with their s values
+ * in s_out_host and their number in *n_rows_out; MS_E_CAPACITY (with
+ * *n_rows_out set) when out_rows_cap is smaller.  n_theta a power of two,
+ * 2 ... 2048.  Workspace: globalize_workspace_size bytes.  Synchronous (the
+ * sorted order is computed on the host).
+ */
+int globalize_workspace_size(int32_t n_theta, int32_t n_s, int32_t n_max, size_t *bytes);
+int globalize_manifold(const double *grid_dev, const double *s_host, int32_t n_theta, int32_t n_s, int32_t n_max,
+                       double omega, double lambda, const map_params_t *map, double *out_dev, int64_t out_rows_cap,
+                       double *s_out_host, int64_t *n_rows_out, void *ws, size_t ws_bytes, void *stream);
+
 /* theta_interp -- trigonometric interpolation (Sec. 7): out_dev[4 q + c] is
  * the value at theta_dev[q] of the trigonometric polynomial through the
  * samples of row row_dev[q] (coordinate c).  Any n_theta >= 1.  A query with

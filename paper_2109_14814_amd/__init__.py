@@ -26,7 +26,8 @@ EXPORTS = ("last_error", "mesh_build", "mesh_free", "mesh_info", "mesh_update", 
            "search_profile_enable", "search_profile_read", "batch_create", "batch_search", "batch_needed",
            "batch_free", "refine_workspace_size", "refine_grad", "refine_newton", "layer_pairs",
            "half_layer_bounds", "half_layer_columns", "pertbp_map", "pertbp_map_stm", "theta_shift", "theta_interp", "theta_spectrum",
-           "ft_partials", "ft_newton_workspace_size", "ft_newton", "continuation_predict")
+           "ft_partials", "ft_newton_workspace_size", "ft_newton", "continuation_predict",
+           "globalize_workspace_size", "globalize_manifold")
 
 MS_REFINE_RESIDUAL, MS_REFINE_ADJOINT, MS_REFINE_TANGENT, MS_REFINE_NEWTON = 0, 1, 2, 3
 NEWTON_STATUS = {0: "converged", 1: "trial limit", 2: "step too small", 3: "singular", 4: "non-finite"}
@@ -116,6 +117,11 @@ def lib():
         L.ft_newton.restype = C.c_int
         L.continuation_predict.argtypes = [P, P, P, P, P, I64, P, P]
         L.continuation_predict.restype = C.c_int
+        L.globalize_workspace_size.argtypes = [I32, I32, I32, C.POINTER(C.c_size_t)]
+        L.globalize_workspace_size.restype = C.c_int
+        L.globalize_manifold.argtypes = [P, P, I32, I32, I32, D, D, C.POINTER(MapParams), P, I64, P,
+                                         C.POINTER(I64), P, C.c_size_t, P]
+        L.globalize_manifold.restype = C.c_int
         L.mesh_update.argtypes = [P, P]; L.mesh_update.restype = C.c_int
         L.batch_create.argtypes = [I32, P, P, P, I64, I64, P, C.POINTER(P), C.POINTER(C.c_size_t)]
         L.batch_create.restype = C.c_int
@@ -648,6 +654,33 @@ def theta_spectrum(rows, out=None):
         out = torch.empty_like(x)
     _check(lib().theta_spectrum(_ptr(x), _ptr(out), int(n_theta), n_rows, _stream()))
     return out
+
+
+def globalize(grid, s, n_max: int, omega: float, lam: float, direction: int, mu: float, eps: float,
+              steps_per_period: int):
+    """Globalized manifold mesh of Sec. 6.1 (globalize_manifold of the C ABI)
+    from a fundamental-domain grid (n_s, n_theta, 4) at the increasing s
+    values s; direction +1 (unstable, F) or -1 (stable, F^-1).  Returns
+    (rows (M, n_theta, 4) cuda tensor, s values (M,) numpy array)."""
+    torch = _torch()
+    g = torch.as_tensor(grid, dtype=torch.float64).to("cuda").contiguous()
+    assert g.dim() == 3 and g.shape[-1] == 4
+    n_s, n_theta = g.shape[0], g.shape[1]
+    sv = np.ascontiguousarray(s, dtype=np.float64)
+    if sv.shape != (n_s,):
+        raise ValueError("one s value per grid row")
+    cap = n_s * (int(n_max) + 1)
+    out = torch.empty((cap, n_theta, 4), dtype=torch.float64, device="cuda")
+    s_out = np.empty(cap)
+    nb = C.c_size_t()
+    _check(lib().globalize_workspace_size(n_theta, n_s, int(n_max), C.byref(nb)))
+    ws = _dev_bytes(nb.value)
+    m = C.c_int64()
+    mp = MapParams(float(mu), float(eps), int(steps_per_period), int(direction))
+    _check(lib().globalize_manifold(_ptr(g), sv.ctypes.data_as(C.c_void_p), n_theta, n_s, int(n_max), float(omega),
+                                    float(lam), C.byref(mp), _ptr(out), cap, s_out.ctypes.data_as(C.c_void_p),
+                                    C.byref(m), _ptr(ws), nb.value, _stream()))
+    return out[: m.value], s_out[: m.value]
 
 
 class FourierTaylor:

@@ -29,6 +29,7 @@
 // d = i0 - i reduced to [-N/2, N/2), g = cot for even N and 1 / sin for odd N.
 #include <math.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <string>
@@ -263,17 +264,21 @@ MS_D void inverse_passes(double2 (*z)[padded_size<1 << LOGN>()], const double2 *
     }
 }
 
+// row_map (optional): output row of each input row; a negative entry drops
+// the row.
 template <int LOGN>
 __global__ void __launch_bounds__(SP_THREADS) k_theta_shift(const double *in, double *out,
                                                             const double2 *__restrict__ tw, const double *rho_dev,
-                                                            double rho, int order)
+                                                            double rho, int order, const int64_t *row_map)
 {
     using PL = Plan<LOGN>;
     constexpr int N = 1 << LOGN;
     __shared__ double2 z[2][padded_size<N>()];
     const int64_t row = blockIdx.x;
+    const int64_t orow = row_map ? row_map[row] : row;
+    if (orow < 0) return;   // the whole block
     const double *src = in + row * (int64_t)N * 4;
-    double *dst = out + row * (int64_t)N * 4;
+    double *dst = out + orow * (int64_t)N * 4;
     const double r = rho_dev ? rho_dev[row] : rho;
     forward_passes<LOGN, 0>(z, tw, src);
     // last forward pass + multiplier + first inverse pass, in registers
@@ -364,10 +369,10 @@ __global__ void __launch_bounds__(64 * IP_WAVES) k_theta_interp(const double *in
 
 template <int LOGN>
 void launch_shift(const double *in, double *out, const double2 *tw, int64_t n_rows, const double *rho_dev,
-                  double rho, int order, hipStream_t st)
+                  double rho, int order, hipStream_t st, const int64_t *row_map = nullptr)
 {
     hipLaunchKernelGGL(k_theta_shift<LOGN>, dim3((unsigned)n_rows), dim3(SP_THREADS), 0, st, in, out, tw, rho_dev,
-                       rho, order);
+                       rho, order, row_map);
 }
 
 // e^{-2 pi i m / N}, m = 0..N-1, per (device, N), kept for the life of the
@@ -404,10 +409,117 @@ void launch_spectrum(const double *in, double *out, const double2 *tw, int64_t n
     hipLaunchKernelGGL(k_theta_spectrum<LOGN>, dim3((unsigned)n_rows), dim3(SP_THREADS), 0, st, in, out, tw);
 }
 
+// theta_shift on validated arguments (n_theta a power of two in range).
+int shift_rows(const double *in, double *out, int n_theta, int64_t n_rows, const double *rho_dev, double rho,
+               int order, const int64_t *row_map, hipStream_t st)
+{
+    const double2 *tw = nullptr;
+    int rc = twiddles(n_theta, &tw);
+    if (rc) return rc;
+    int lg = 0;
+    while ((1 << lg) < n_theta) ++lg;
+    switch (lg) {
+    case 1: launch_shift<1>(in, out, tw, n_rows, rho_dev, rho, order, st, row_map); break;
+    case 2: launch_shift<2>(in, out, tw, n_rows, rho_dev, rho, order, st, row_map); break;
+    case 3: launch_shift<3>(in, out, tw, n_rows, rho_dev, rho, order, st, row_map); break;
+    case 4: launch_shift<4>(in, out, tw, n_rows, rho_dev, rho, order, st, row_map); break;
+    case 5: launch_shift<5>(in, out, tw, n_rows, rho_dev, rho, order, st, row_map); break;
+    case 6: launch_shift<6>(in, out, tw, n_rows, rho_dev, rho, order, st, row_map); break;
+    case 7: launch_shift<7>(in, out, tw, n_rows, rho_dev, rho, order, st, row_map); break;
+    case 8: launch_shift<8>(in, out, tw, n_rows, rho_dev, rho, order, st, row_map); break;
+    case 9: launch_shift<9>(in, out, tw, n_rows, rho_dev, rho, order, st, row_map); break;
+    case 10: launch_shift<10>(in, out, tw, n_rows, rho_dev, rho, order, st, row_map); break;
+    default: launch_shift<11>(in, out, tw, n_rows, rho_dev, rho, order, st, row_map); break;
+    }
+    MS_HIP(hipGetLastError());
+    return MS_OK;
+}
+
+// Row copies through a row map (negative entries dropped): the unshifted
+// layer of the globalized mesh.
+__global__ void __launch_bounds__(256) k_copy_rows(const double *in, double *out, const int64_t *row_map,
+                                                   int64_t n_rows, int N)
+{
+    const int64_t per = (int64_t)N * 2;   // double2 per row
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_rows * per) return;
+    const int64_t row = i / per, e = i - row * per;
+    const int64_t orow = row_map[row];
+    if (orow < 0) return;
+    reinterpret_cast<double2 *>(out)[orow * per + e] = reinterpret_cast<const double2 *>(in)[i];
+}
+
 }  // namespace
 }  // namespace ms
 
 using namespace ms;
+
+extern "C" int globalize_workspace_size(int32_t n_theta, int32_t n_s, int32_t n_max, size_t *bytes)
+{
+    if (!bytes || n_theta < 1 || n_s < 0 || n_max < 0) return fail(MS_E_ARG, "globalize_workspace_size: bad argument");
+    const size_t grid = (size_t)n_s * n_theta * 32;
+    const size_t map = (size_t)(n_max + 1) * n_s * 8;
+    *bytes = ((grid + 255) & ~(size_t)255) + ((map + 255) & ~(size_t)255);
+    return MS_OK;
+}
+
+extern "C" int globalize_manifold(const double *grid_dev, const double *s_host, int32_t n_theta, int32_t n_s,
+                                  int32_t n_max, double omega, double lambda, const map_params_t *map,
+                                  double *out_dev, int64_t out_rows_cap, double *s_out_host, int64_t *n_rows_out,
+                                  void *ws, size_t ws_bytes, void *stream)
+{
+    if (!s_host || !map || !n_rows_out || n_s < 1 || n_max < 0 || (!grid_dev) || (!s_out_host))
+        return fail(MS_E_ARG, "globalize_manifold: bad argument");
+    if (n_theta < 2 || n_theta > (1 << SP_MAX_LOG2) || (n_theta & (n_theta - 1)))
+        return fail(MS_E_ARG, "globalize_manifold: n_theta must be a power of two in [2, 2048]");
+    if (map->n_periods != 1 && map->n_periods != -1)
+        return fail(MS_E_ARG, "globalize_manifold: map->n_periods must be +1 (unstable) or -1 (stable)");
+    if (!(lambda > 0.0) || !isfinite(lambda) || !isfinite(omega))
+        return fail(MS_E_ARG, "globalize_manifold: need lambda > 0 and a finite omega");
+    for (int k = 0; k < n_s; ++k)
+        if (!isfinite(s_host[k]) || (k > 0 && !(s_host[k] > s_host[k - 1])))
+            return fail(MS_E_ARG, "globalize_manifold: s must be finite and strictly increasing");
+    const int d = map->n_periods;
+    // the rows (n, k) and their s values, sorted by s (s = 0 kept once)
+    struct Entry { double s; int n, k; };
+    std::vector<Entry> ent;
+    for (int n = 0; n <= n_max; ++n)
+        for (int k = 0; k < n_s; ++k) {
+            if (n > 0 && s_host[k] == 0.0) continue;
+            ent.push_back({pow(lambda, (double)(d * n)) * s_host[k], n, k});
+        }
+    std::stable_sort(ent.begin(), ent.end(), [](const Entry &a, const Entry &b) { return a.s < b.s; });
+    const int64_t M = (int64_t)ent.size();
+    *n_rows_out = M;
+    if (!out_dev || out_rows_cap < M) return fail(MS_E_CAPACITY, "globalize_manifold: output holds too few rows");
+    size_t need = 0;
+    int rc = globalize_workspace_size(n_theta, n_s, n_max, &need);
+    if (rc) return rc;
+    if (!ws || ws_bytes < need) return fail(MS_E_WORKSPACE, "globalize_manifold: workspace too small");
+    std::vector<int64_t> rmap((size_t)(n_max + 1) * n_s, -1);
+    for (int64_t r = 0; r < M; ++r) {
+        rmap[(size_t)ent[r].n * n_s + ent[r].k] = r;
+        s_out_host[r] = ent[r].s;
+    }
+    double *P = (double *)ws;
+    int64_t *rmap_dev = (int64_t *)((char *)ws + (((size_t)n_s * n_theta * 32 + 255) & ~(size_t)255));
+    hipStream_t st = (hipStream_t)stream;
+    MS_HIP(hipMemcpyAsync(rmap_dev, rmap.data(), rmap.size() * 8, hipMemcpyHostToDevice, st));
+    MS_HIP(hipStreamSynchronize(st));   // rmap is a host vector of this call
+    const int64_t n_states = (int64_t)n_s * n_theta;
+    hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)ceil_div(n_states * 2, 256)), dim3(256), 0, st, grid_dev, out_dev,
+                       rmap_dev, (int64_t)n_s, (int)n_theta);
+    MS_HIP(hipGetLastError());
+    if (n_max > 0) MS_HIP(hipMemcpyAsync(P, grid_dev, (size_t)n_states * 32, hipMemcpyDeviceToDevice, st));
+    for (int n = 1; n <= n_max; ++n) {
+        // P <- F^d(P) = F^(d n)(grid), then W(theta_i, lambda^(d n) s_k) = P shifted by -d n omega
+        if ((rc = pertbp_map(P, P, n_states, map, stream))) return rc;
+        if ((rc = shift_rows(P, out_dev, n_theta, n_s, nullptr, -(double)(d * n) * omega, 0,
+                             rmap_dev + (size_t)n * n_s, st)))
+            return rc;
+    }
+    return MS_OK;
+}
 
 extern "C" int theta_spectrum(const double *in_dev, double *out_dev, int32_t n_theta, int64_t n_rows, void *stream)
 {
@@ -449,27 +561,7 @@ extern "C" int theta_shift(const double *in_dev, double *out_dev, int32_t n_thet
     if (!rho_dev && !isfinite(rho)) return fail(MS_E_ARG, "theta_shift: rho must be finite");
     if (n_rows > 0x7fffffff) return fail(MS_E_ARG, "theta_shift: too many rows for one launch");
     if (n_rows == 0) return MS_OK;
-    hipStream_t st = (hipStream_t)stream;
-    const double2 *tw = nullptr;
-    int rc = twiddles(n_theta, &tw);
-    if (rc) return rc;
-    int lg = 0;
-    while ((1 << lg) < n_theta) ++lg;
-    switch (lg) {
-    case 1: launch_shift<1>(in_dev, out_dev, tw, n_rows, rho_dev, rho, order, st); break;
-    case 2: launch_shift<2>(in_dev, out_dev, tw, n_rows, rho_dev, rho, order, st); break;
-    case 3: launch_shift<3>(in_dev, out_dev, tw, n_rows, rho_dev, rho, order, st); break;
-    case 4: launch_shift<4>(in_dev, out_dev, tw, n_rows, rho_dev, rho, order, st); break;
-    case 5: launch_shift<5>(in_dev, out_dev, tw, n_rows, rho_dev, rho, order, st); break;
-    case 6: launch_shift<6>(in_dev, out_dev, tw, n_rows, rho_dev, rho, order, st); break;
-    case 7: launch_shift<7>(in_dev, out_dev, tw, n_rows, rho_dev, rho, order, st); break;
-    case 8: launch_shift<8>(in_dev, out_dev, tw, n_rows, rho_dev, rho, order, st); break;
-    case 9: launch_shift<9>(in_dev, out_dev, tw, n_rows, rho_dev, rho, order, st); break;
-    case 10: launch_shift<10>(in_dev, out_dev, tw, n_rows, rho_dev, rho, order, st); break;
-    default: launch_shift<11>(in_dev, out_dev, tw, n_rows, rho_dev, rho, order, st); break;
-    }
-    MS_HIP(hipGetLastError());
-    return MS_OK;
+    return shift_rows(in_dev, out_dev, n_theta, n_rows, rho_dev, rho, order, nullptr, (hipStream_t)stream);
 }
 
 extern "C" int theta_interp(const double *rows_dev, int32_t n_theta, int64_t n_rows, const int64_t *row_dev,
