@@ -60,3 +60,12 @@ def test_argument_errors_need_no_gpu():
     p = ms.MapParams(0.01, 0.0, 0, 1)
     assert L.propagate_vertices(None, None, 10, ctypes.byref(p), None) == ms.MS_E_ARG
     assert L.mesh_free(None) == ms.MS_OK
+
+
+def test_header_is_plain_c():
+    """A C caller can include the header: it compiles as C99 with warnings as errors."""
+    import shutil
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    subprocess.run(["gcc", "-fsyntax-only", "-x", "c", "-std=c99", "-Wall", "-Wextra", "-Werror", HEADER],
+                   check=True)
