@@ -1036,7 +1036,15 @@ __global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_
     for (int64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
         const int64_t S0 = chunk * ENUM_SLOTS;
         const int64_t S1 = S0 + ENUM_SLOTS < P ? S0 + ENUM_SLOTS : P;
-        if (threadIdx.x == 0) {
+        if (lds_pre) {
+            // the one i with pstart[i] <= x < pstart[i + 1], for x = S0, S1 - 1
+            for (int64_t i = threadIdx.x; i < ncells; i += ENUM_BLOCK) {
+                const int64_t a = s_pstart[i], b = s_pstart[i + 1];
+                if (a <= S0 && S0 < b) s_c0 = i;
+                if (a <= S1 - 1 && S1 - 1 < b) s_c1 = i;
+            }
+            if (threadIdx.x == 0) s_nmix = 0;
+        } else if (threadIdx.x == 0) {
             s_c0 = last_le<int64_t>(pstart, ncells, S0);
             s_c1 = last_le<int64_t>(pstart, ncells, S1 - 1);
             s_nmix = 0;
@@ -1124,14 +1132,38 @@ __global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_
         // pass 1: the keep bit of each slot (the pair of a kept slot is
         // found again in pass 2, so that no per-slot state is held)
         uint32_t keepm = 0;
+        // a thread's slots lie ENUM_BLOCK apart: the group and the (iB, iA)
+        // split are found once per group entered, then advanced by
+        // ENUM_BLOCK = qa * nA + ra slots at a time
+        int c = 0, ia = 0, ib = 0;
+        int64_t pend = 0;
+        uint32_t nAc = 1, iA = 0, qa = 0, ra = 0;
 #pragma unroll 1
         for (int j = 0; j < ENUM_ITEMS; ++j) {
             const int64_t slot = S0 + (int64_t)j * ENUM_BLOCK + threadIdx.x;
             bool keep = false;
             if (slot < S1) {
                 if (staged) {
-                    const StagedSlot q = staged_slot(slot, (int)nc, s_pre, s_nA, s_aoff, s_ia0, s_boff, s_ib0);
-                    const int c = q.c, ia = q.ia, ib = q.ib;
+                    if (j == 0 || slot >= pend) {
+                        const StagedSlot q = staged_slot(slot, (int)nc, s_pre, s_nA, s_aoff, s_ia0, s_boff, s_ib0);
+                        c = q.c;
+                        ia = q.ia;
+                        ib = q.ib;
+                        nAc = (uint32_t)s_nA[c];
+                        pend = s_pre[c + 1];
+                        iA = (uint32_t)(ia - s_aoff[c] + s_ia0[c]);
+                        qa = (uint32_t)ENUM_BLOCK / nAc;
+                        ra = (uint32_t)ENUM_BLOCK - qa * nAc;
+                    } else {
+                        iA += ra;
+                        ia += (int)ra;
+                        ib += (int)qa;
+                        if (iA >= nAc) {
+                            iA -= nAc;
+                            ia -= (int)nAc;
+                            ++ib;
+                        }
+                    }
                     const uint64_t ca = s_ec[ia];
                     if (ca == s_ec[ib]) {
                         double alo[4], ahi[4], blo[4], bhi[4];
