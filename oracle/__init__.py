@@ -64,6 +64,8 @@ def lib():
         L.orc_grid_search.argtypes = [C.POINTER(_Mesh), C.POINTER(_Mesh), P, D, P, C.POINTER(_Result), C.c_int]
         L.orc_grid_search.restype = C.c_int
         L.orc_grid_entries.argtypes = [C.POINTER(_Mesh), P, D, P]; L.orc_grid_entries.restype = I64
+        L.orc_cell_of.argtypes = [D, D, D, I64]; L.orc_cell_of.restype = I64
+        L.orc_tri_entries.argtypes = [C.POINTER(_Mesh), I64, P, D, P, P, I64]; L.orc_tri_entries.restype = I64
         L.orc_result_free.argtypes = [C.POINTER(_Result)]; L.orc_result_free.restype = None
         L.orc_rk8_tableau.argtypes = [P, P, P]; L.orc_rk8_tableau.restype = None
         L.orc_rk8_map.argtypes = [P, P, I64, D, D, I32, I32, C.c_int]; L.orc_rk8_map.restype = C.c_int
@@ -192,6 +194,26 @@ def grid_entries(mesh, w_lo, inv_edge: float, n_cells) -> int:
     wl = np.ascontiguousarray(w_lo, dtype=np.float64)
     nc = np.ascontiguousarray(n_cells, dtype=np.int64)
     return int(lib().orc_grid_entries(om.ref, _ptr(wl), float(inv_edge), _ptr(nc)))
+
+
+def cell_of(x: float, w_lo: float, inv_edge: float, n: int) -> int:
+    """Cell of coordinate x on one axis of the grid (Sec. 6.2.1, 0-based
+    floor form, clamped to [0, n - 1])."""
+    return int(lib().orc_cell_of(float(x), float(w_lo), float(inv_edge), int(n)))
+
+
+def tri_entries(mesh, t: int, w_lo, inv_edge: float, n_cells) -> np.ndarray | None:
+    """Linear cell ids of triangle t's grid entries, in the grid search's
+    emission order; None for a non-finite triangle."""
+    om = OMesh(mesh)
+    wl = np.ascontiguousarray(w_lo, dtype=np.float64)
+    nc = np.ascontiguousarray(n_cells, dtype=np.int64)
+    cnt = int(lib().orc_tri_entries(om.ref, int(t), _ptr(wl), float(inv_edge), _ptr(nc), None, 0))
+    if cnt < 0:
+        return None
+    out = np.zeros(max(cnt, 1), np.int64)
+    lib().orc_tri_entries(om.ref, int(t), _ptr(wl), float(inv_edge), _ptr(nc), _ptr(out), cnt)
+    return out[:cnt]
 
 
 def max_threads() -> int:

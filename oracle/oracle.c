@@ -507,7 +507,7 @@ static int cmp_entry(const void *x, const void *y)
     return (a->tri > b->tri) - (a->tri < b->tri);
 }
 
-/* Entries covered by triangle t's box: count and optional emission. */
+/* Cell range [clo, chi] per axis covered by a box, and its number of cells. */
 static int64_t tri_cells(const double lo[4], const double hi[4], const double wlo[4],
                          double inv_edge, const int64_t n[4], int64_t clo[4], int64_t chi[4])
 {
@@ -518,6 +518,23 @@ static int64_t tri_cells(const double lo[4], const double hi[4], const double wl
         cnt *= chi[d] - clo[d] + 1;
     }
     return cnt;
+}
+
+/* Linear id of cell (c0, c1, c2, c3): axis 3 varies fastest. */
+static int64_t cell_linear(int64_t c0, int64_t c1, int64_t c2, int64_t c3, const int64_t n[4])
+{
+    return ((c0 * n[1] + c1) * n[2] + c2) * n[3] + c3;
+}
+
+/* The linear ids of the cells of a range, in lexicographic order, written to
+ * out[0 .. count) (the per-box list entries of one triangle). */
+static void range_cells(const int64_t clo[4], const int64_t chi[4], const int64_t n[4], int64_t *out)
+{
+    int64_t o = 0;
+    for (int64_t c0 = clo[0]; c0 <= chi[0]; ++c0)
+        for (int64_t c1 = clo[1]; c1 <= chi[1]; ++c1)
+            for (int64_t c2 = clo[2]; c2 <= chi[2]; ++c2)
+                for (int64_t c3 = clo[3]; c3 <= chi[3]; ++c3) out[o++] = cell_linear(c0, c1, c2, c3, n);
 }
 
 /* The grid search of Sec. 6.2.1 followed by the AABB test, the Moller test
@@ -559,24 +576,26 @@ ORC_API int orc_grid_search(const orc_mesh *A, const orc_mesh *B, const double *
     entry_t *ent = (entry_t *)malloc((size_t)(E ? E : 1) * sizeof(entry_t));
     if (!ent) return -1;
     /* (2) emit entries, then group them by box */
+    int ent_err = 0;
     for (int sd = 0; sd < 2; ++sd) {
-#pragma omp parallel for num_threads(nt) schedule(static)
+#pragma omp parallel for num_threads(nt) schedule(static) reduction(| : ent_err)
         for (int64_t t = 0; t < ntri[sd]; ++t) {
             if (!T[sd].fin[t]) continue;
             int64_t clo[4], chi[4];
-            tri_cells(T[sd].lo + 4 * t, T[sd].hi + 4 * t, wlo, inv_edge, n, clo, chi);
+            int64_t cnt = tri_cells(T[sd].lo + 4 * t, T[sd].hi + 4 * t, wlo, inv_edge, n, clo, chi);
+            int64_t *cells = (int64_t *)malloc((size_t)cnt * sizeof(int64_t));
+            if (!cells) { ent_err = 1; continue; }
+            range_cells(clo, chi, n, cells);
             int64_t o = off[sd][t];
-            for (int64_t c0 = clo[0]; c0 <= chi[0]; ++c0)
-                for (int64_t c1 = clo[1]; c1 <= chi[1]; ++c1)
-                    for (int64_t c2 = clo[2]; c2 <= chi[2]; ++c2)
-                        for (int64_t c3 = clo[3]; c3 <= chi[3]; ++c3) {
-                            ent[o].cell = ((c0 * n[1] + c1) * n[2] + c2) * n[3] + c3;
-                            ent[o].tri = t; ent[o].side = sd; ent[o].pad = 0;
-                            ++o;
-                        }
+            for (int64_t j = 0; j < cnt; ++j, ++o) {
+                ent[o].cell = cells[j];
+                ent[o].tri = t; ent[o].side = sd; ent[o].pad = 0;
+            }
+            free(cells);
         }
         free(off[sd]);
     }
+    if (ent_err) { free(ent); table_free(&T[0]); table_free(&T[1]); return -1; }
     qsort(ent, (size_t)E, sizeof(entry_t), cmp_entry);
 
     /* box boundaries */
@@ -638,6 +657,28 @@ ORC_API int orc_grid_search(const orc_mesh *A, const orc_mesh *B, const double *
     int rc = narrow_list(A, &T[0], B, &T[1], all, u, res, nt);
     table_free(&T[0]); table_free(&T[1]);
     return rc;
+}
+
+/* The cell map itself, for its pins: cell_of on one axis, and the linear
+ * cell ids of triangle t's entries in the order the grid search emits them
+ * (returns their number; writes at most cap of them; -1 for a non-finite
+ * triangle). */
+ORC_API int64_t orc_cell_of(double x, double wlo, double inv_edge, int64_t n)
+{
+    return cell_of(x, wlo, inv_edge, n);
+}
+
+ORC_API int64_t orc_tri_entries(const orc_mesh *m, int64_t t, const double *wlo, double inv_edge,
+                                const int64_t *ncell, int64_t *out, int64_t cap)
+{
+    double p[3][4], lo[4], hi[4];
+    int64_t clo[4], chi[4];
+    orc_tri_verts(m, t, p);
+    if (!tri_finite(p)) return -1;
+    tri_box(p, lo, hi);
+    int64_t cnt = tri_cells(lo, hi, wlo, inv_edge, ncell, clo, chi);
+    if (cnt <= cap) range_cells(clo, chi, ncell, out);
+    return cnt;
 }
 
 /* Total (cell, tri) entries for a grid (exact recount, for tests). */
