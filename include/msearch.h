@@ -61,7 +61,10 @@ enum {
                              Borrowed: must outlive the handle. */
     MS_LAYOUT_SOA = 1     /* four planes x[n_s_v][n_theta_v], y, p_x, p_y, back to
                              back (the four N x M arrays of Sec. 6.1, stored with
-                             theta fastest).  Copied into an owned AoS buffer. */
+                             theta fastest).  Copied into an owned AoS buffer by
+                             mesh_build and again by every mesh_update, which reads
+                             the planes at the pointer given to mesh_build (keep them
+                             valid while the handle may be updated). */
 };
 
 /*
@@ -103,9 +106,12 @@ int mesh_info(const ms_mesh *mesh, ms_mesh_info_t *out);
 /*
  * mesh_update -- tell the handle that the caller changed the vertex values
  * in place (same grid, same buffer; e.g. after propagate_vertices on
- * `stream`).  Searches read the current vertices anyway; this only marks the
- * statistics of mesh_info (and so search_default_params) for recomputation on
- * `stream`.  Queues nothing and allocates nothing.
+ * `stream`).  An AoS mesh's searches read the caller's vertices directly, so
+ * for it this only marks the statistics of mesh_info (and so
+ * search_default_params) for recomputation on `stream`, and queues nothing.
+ * An SoA mesh's searches read the handle's AoS copy: mesh_update queues the
+ * conversion of the current planes into that copy on `stream`.  Allocates
+ * nothing.
  */
 int mesh_update(ms_mesh *mesh, void *stream);
 
@@ -171,7 +177,9 @@ typedef struct {
     int64_t overflow;        /* bit 0: entries > capacity, bit 1: cand, bit 2: hits */
     int64_t n_groups;        /* groups enumerated: hashed cells with A and B entries (>= n_cells) */
     int64_t n_group_slots;   /* sum over those groups of nA * nB (>= n_slots) */
-    int64_t reserved[3];     /* zero */
+    int64_t n_chunks_unstaged; /* enumeration chunks whose entries did not fit on-chip (crowded
+                                  cells; their slots were read from device memory) */
+    int64_t reserved[2];     /* zero */
 } search_stats_t;
 
 /*

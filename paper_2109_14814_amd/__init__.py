@@ -40,7 +40,8 @@ HIT_DTYPE = np.dtype([
     ("margin", np.float64),
 ])
 STATS_FIELDS = ("n_entries", "n_entries_all", "n_cells", "n_slots", "n_cand", "n_moller", "n_degenerate",
-                "n_outside", "n_hits", "n_nonfinite", "overflow", "n_groups", "n_group_slots")
+                "n_outside", "n_hits", "n_nonfinite", "overflow", "n_groups", "n_group_slots",
+                "n_chunks_unstaged")
 
 
 class MSearchError(RuntimeError):

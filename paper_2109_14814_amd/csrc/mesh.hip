@@ -211,7 +211,9 @@ extern "C" int mesh_build(const double *verts_dev, int32_t n_theta_v, int32_t n_
         if (g > 4096) g = 4096;
         hipLaunchKernelGGL(k_soa_to_aos, dim3((unsigned)g), dim3(MB_BLOCK), 0, st, verts_dev, m->owned_V, nv);
         V = m->owned_V;
+        m->soa_src = verts_dev;
     }
+    m->n_verts = nv;
     if ((e = hipMalloc(&m->theta_dev, (size_t)(n_theta_v > 0 ? n_theta_v : 1) * 8)) != hipSuccess)
         return cleanup(hip_fail(e, "hipMalloc theta"));
     if ((e = hipMalloc(&m->s_dev, (size_t)(n_s_v > 0 ? n_s_v : 1) * 8)) != hipSuccess)
@@ -258,6 +260,14 @@ extern "C" int mesh_update(ms_mesh *m, void *stream)
     if (!m) return fail(MS_E_ARG, "mesh_update: NULL mesh");
     m->upd_stream = (hipStream_t)stream;
     m->info_stale = 1;
+    if (m->soa_src && m->n_verts > 0) {
+        // an SoA mesh searches its own AoS copy: convert the changed planes again
+        int64_t g = ceil_div(m->n_verts, MB_BLOCK);
+        if (g > 4096) g = 4096;
+        hipLaunchKernelGGL(k_soa_to_aos, dim3((unsigned)g), dim3(MB_BLOCK), 0, m->upd_stream, m->soa_src, m->owned_V,
+                           m->n_verts);
+        MS_HIP(hipGetLastError());
+    }
     return MS_OK;
 }
 

@@ -207,6 +207,8 @@ constexpr int MS_COUNT_PARTIALS = 2048;
 struct ms_mesh {
     ms::MeshView view;
     double *owned_V;          // AoS copy for MS_LAYOUT_SOA
+    const double *soa_src;    // the caller's SoA planes (MS_LAYOUT_SOA), converted again by mesh_update
+    int64_t n_verts;
     double *theta_dev, *s_dev;
     int64_t *scratch;         // small device scratch: per-block partials of the statistics pass
     int64_t *counter;         // MS_COUNT_PARTIALS device words (entry counting of workspace queries)

@@ -1082,6 +1082,7 @@ __global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_
         uint32_t tot;
         const uint32_t off = block_excl<ENUM_BLOCK>(need, s_kscan, &tot);
         const bool staged = nc <= ENUM_CELLS && tot <= ENUM_STAGE;
+        if (!staged && threadIdx.x == 0) atomicAdd((unsigned long long *)&stats->n_chunks_unstaged, 1ull);
         if (staged) {
             if (threadIdx.x < nc) {
                 s_aoff[threadIdx.x] = (int32_t)off;

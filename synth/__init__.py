@@ -243,6 +243,33 @@ def affine_mesh(p0, d_theta, d_s, theta, s) -> Mesh:
     return Mesh(np.ascontiguousarray(v), theta.copy(), s.copy(), False)
 
 
+def lattice_plant(n_plane: int, n_wave: int, m: int, amp: float = 0.02, power: float = 1.0, seed: int = 0):
+    """Many isolated crossings, for large hit counts and crowded cells.
+
+    A is the plane (x, y, 0, 0) over [0, 1]^2 on an n_plane x n_plane quad
+    grid whose x samples are (i / n_plane)^power (power > 1 crowds A's
+    triangles towards x = 0).  B is the graph
+      (x, y, amp sin(2 pi m x + phi), amp sin(2 pi m y + psi)) + small tilt
+    over [-0.01, 1.01]^2 on an n_wave x n_wave quad grid.  The two meet near
+    the (2m)^2 common zeros of the two sines in the unit square: about
+    (2m)^2 triangle pairs intersect.  phi, psi and the tilt are seeded."""
+    rng = np.random.default_rng(seed)
+    phi, psi = rng.uniform(0.1, 0.9, 2) * TWO_PI
+    tilt = rng.uniform(-1e-3, 1e-3, 2)
+    xa = (np.arange(n_plane + 1) / n_plane) ** power
+    ya = np.arange(n_plane + 1) / n_plane
+    VA = np.zeros((n_plane + 1, n_plane + 1, 4))
+    VA[:, :, 0] = xa[None, :]
+    VA[:, :, 1] = ya[:, None]
+    A = Mesh(np.ascontiguousarray(VA), xa.copy(), ya.copy(), False)
+    g = np.linspace(-0.01, 1.01, n_wave + 1)
+    X, Y = np.meshgrid(g, g)
+    VB = np.stack([X, Y, amp * np.sin(TWO_PI * m * X + phi) + tilt[0] * Y,
+                   amp * np.sin(TWO_PI * m * Y + psi) + tilt[1] * X], -1)
+    B = Mesh(np.ascontiguousarray(VB), g.copy(), g.copy(), False)
+    return A, B
+
+
 # ---------------------------------------------------------------------------
 # Propagated-mesh patches (stroboscopic map workloads)
 # ---------------------------------------------------------------------------

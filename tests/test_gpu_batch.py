@@ -80,7 +80,8 @@ def test_batch_matches_oracle_per_pair(ms, use_graph, hits_cap, table_log2):
 @pytest.mark.parametrize("kappa", [1.0, 2.0])
 def test_batch_equals_plain_on_the_full_family(ms, kappa):
     """The 256-pair continuation family at its full sizes: the batched search
-    (one graph launch) reproduces the 256 plain searches bit for bit.  At the
+    (one graph launch) reproduces the 256 plain searches bit for bit, and
+    every pair equals the oracle's grid search.  At the
     finer grid, cells of one pair's mesh alone sit between the cells of
     another pair in key order (a regression case of the enumeration's entry
     staging)."""
@@ -102,13 +103,17 @@ def test_batch_equals_plain_on_the_full_family(ms, kappa):
     assert st["n_cand"] == sum(p[1]["n_cand"] for p in plain)
     assert st["n_slots"] == sum(p[1]["n_slots"] for p in plain)
     assert st["n_cells"] == sum(p[1]["n_cells"] for p in plain)
-    # a sample of pairs against the oracle's grid search with the same grids
-    for i in (0, 17, 101, 255):
-        a, b = fam[i]
+    # every pair against the oracle's grid search with the same grids
+    n_slots = n_cells = 0
+    for i, (a, b) in enumerate(fam):
         g = grids[i]
         ref = oracle.grid_search(a, b, g[0], g[2], g[3])
         assert_same_hits(per_pair[i], ref.hits)
-        assert plain[i][1]["n_cand"] == len(ref.cand)
+        assert plain[i][1]["n_cand"] == len(ref.cand), i
+        assert plain[i][1]["n_entries_all"] == ref.n_entries, i
+        n_slots += ref.n_slots
+        n_cells += ref.n_boxes
+    assert st["n_slots"] == n_slots and st["n_cells"] == n_cells
 
 
 @pytest.mark.parametrize("hits_cap", [1 << 12, 1 << 10])

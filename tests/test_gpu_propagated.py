@@ -4,9 +4,10 @@ Small patches: the unstable patch pushed by F^3 and a planted stable patch
 pulled back by F^-3, both propagated by the oracle, are searched by the GPU
 and by the oracle on the same vertex bytes (index sets bit-exact).  Full-size
 patches (2049 x 257 vertices each): the GPU propagates, updates the boxes,
-searches and refines; results are checked by properties that hold at any
-size (independence of the cell edge, A/B transposition, hits next to the
-planted point, Newton converging to the planted root)."""
+searches and refines; the search is compared with the oracle's grid search
+on the propagated vertex bytes copied back, and checked by properties
+(independence of the cell edge, A/B transposition, hits next to the planted
+point, Newton converging to the planted root)."""
 import numpy as np
 import pytest
 
@@ -67,6 +68,57 @@ def test_small_propagated_patches_match_oracle(ms, nq, kappa):
     assert np.max(np.abs(hits["sA"] - star[1])) < 4 * 2e-3 / nq[1] + 1e-6
 
 
+def host_mesh(g, like):
+    """The vertices of GPU mesh g copied back, on like's grid."""
+    v = g.verts.cpu().numpy().reshape(like.verts.shape)
+    return synth.Mesh(np.ascontiguousarray(v), like.theta.copy(), like.s.copy(), like.periodic)
+
+
+def check_oracle_on_device_bytes(ms, ga, gb, U, S, kappa):
+    """Search parity at full size on the same bytes: the GPU search (with its
+    candidate list) against oracle.grid_search of the vertices copied back,
+    on the same grid."""
+    d = ms.default_params(ga, gb, kappa)
+    lo, inv, n = list(d.world_lo), d.inv_edge, list(d.n_cells)
+    s = ms.Searcher(ga, gb, ms.make_params(lo, inv, n, ms.MS_SEARCH_CANDIDATES), hits_cap=1 << 14,
+                    cand_cap=1 << 22)
+    s.run()
+    hits, st, cand = s.results()
+    A, B = host_mesh(ga, U), host_mesh(gb, S)
+    ref = oracle.grid_search(A, B, np.array(lo), inv, np.array(n, np.int64))
+    print(f"  full size: cand={len(ref.cand)} hits={len(ref.hits)} entries={ref.n_entries}", flush=True)
+    assert st["overflow"] == 0
+    assert np.array_equal(np.sort(cand), ref.cand)
+    assert np.array_equal(_pairs(hits), ref.hit_pairs)
+    for f in ("u", "v", "a", "b", "thA", "sA", "thB", "sB", "margin"):
+        if len(hits):
+            assert np.max(np.abs(hits[f] - ref.hits[f])) <= 1e-10, f
+    if len(hits):
+        assert np.max(np.abs(hits["X"] - ref.hits["X"])) <= 1e-10
+    assert st["n_entries_all"] == ref.n_entries
+    assert st["n_cells"] == ref.n_boxes and st["n_slots"] == ref.n_slots
+    assert st["n_moller"] == ref.counts["moller_reject"] and st["n_outside"] == ref.counts["outside"]
+    assert st["n_degenerate"] == ref.counts["degenerate"]
+    return ref
+
+
+def test_full_size_config2_patches_match_oracle(ms):
+    """The propagated-mesh workload exactly as the benchmark builds it: the
+    2049 x 257-vertex patches around (0.92, 0, 0, 0.05) and
+    (1.08, 0, 0, -0.05), F^3 and F^-3 on the GPU at 4000 steps per period,
+    searched on the GPU and by the oracle on the same propagated bytes."""
+    import torch
+    (U, _), (S, _) = synth.propagated_patches(2048, 256, 0)
+    ga, gb = ms.Mesh.from_synth(U), ms.Mesh.from_synth(S)
+    for g, n in ((ga, 3), (gb, -3)):
+        flat = g.verts.view(-1, 4)
+        ms.propagate(flat, MU, ECC, 4000, n, out=flat)
+        g.update()
+    torch.cuda.synchronize()
+    for kappa in (1.0, 2.0):
+        check_oracle_on_device_bytes(ms, ga, gb, U, S, kappa)
+
+
 def test_full_size_propagated_search_and_refinement(ms):
     """The propagated-patch workload at full size: 2049 x 257 vertices per
     patch (2^20 triangles each), F^3 and F^-3 on the GPU at 4000 steps per
@@ -93,6 +145,8 @@ def test_full_size_propagated_search_and_refinement(ms):
     (h1, s1), (h2, s2) = results
     assert np.array_equal(_pairs(h1), _pairs(h2)) and s1["n_cand"] == s2["n_cand"]
     assert len(h1) > 0
+    # the oracle's grid search on the very vertex bytes the GPU propagated
+    check_oracle_on_device_bytes(ms, ga, gb, U, S, 1.0)
     sw = ms.Searcher(gb, ga, ms.default_params(gb, ga, 1.0), hits_cap=1 << 14, cand_cap=1 << 22)
     sw.run()
     hb, stb, _ = sw.results()

@@ -105,7 +105,8 @@ def test_grid_cfg1_full_size_matches_grid_oracle(ms, kappa):
 def test_grid_cfg1_bench_configuration(ms, hits_cap):
     """The 512 x 512 workload as the benchmark runs it: no candidate list,
     cell edge 1.5 x the mean diameter, hit capacity 1024 (one-block hit
-    sort) and 16384 (chunk sort, merge rank, placement)."""
+    sort) and 16384 (the chunked hit sort, here with its one chunk; the merge
+    across chunks runs in the lattice-plant tests with more than 4096 hits)."""
     A, B = synth.plain_pair(512, 512, 0)
     grid = oracle.default_grid([A, B], 1.5)
     ref = oracle.grid_search(A, B, grid[0], grid[2], grid[3])
@@ -238,6 +239,35 @@ def test_soa_layout_same_results(ms):
     s.run()
     hits, st, cand = s.results()
     check_against(ref, hits, st, np.sort(cand))
+
+
+def test_soa_planes_changed_in_place_then_update(ms):
+    """An SoA mesh whose planes the caller rewrites in place: after
+    mesh_update the search sees the new vertices (the AoS search and the
+    oracle on the new values), and before it the handle keeps the old ones."""
+    A, B = synth.plain_pair(64, 64, 1)
+    A2, _ = synth.plain_pair(64, 64, 4)          # new values for A, same grid
+    lo, hi, inv, n = oracle.default_grid([A, B, A2], 2.0)
+    ga = ms.Mesh.from_synth(A, ms.MS_LAYOUT_SOA)
+    gb = ms.Mesh.from_synth(B, ms.MS_LAYOUT_SOA)
+    p = ms.make_params(lo, inv, n, ms.MS_SEARCH_CANDIDATES)
+    s = ms.Searcher(ga, gb, p)
+    s.run()
+    before = s.results()
+    check_against(oracle.bruteforce(A, B), before[0], before[1], np.sort(before[2]))
+    import torch
+    ga.verts.copy_(torch.as_tensor(A2.verts).permute(2, 0, 1).to("cuda"))   # the four planes, in place
+    ga.update()
+    s.run()
+    hits, st, cand = s.results()
+    ref = oracle.bruteforce(A2, B)
+    check_against(ref, hits, st, np.sort(cand))
+    aos = ms.Searcher(ms.Mesh.from_synth(A2), ms.Mesh.from_synth(B), p)
+    aos.run()
+    ha, sa, ca = aos.results()
+    assert np.array_equal(_pairs(hits), _pairs(ha)) and np.array_equal(np.sort(cand), np.sort(ca))
+    assert not np.array_equal(np.sort(before[2]), np.sort(cand))       # the update changed the result
+    assert ga.info()["n_tris"] == A2.n_tris
 
 
 def test_capacity_overflow_reports_and_retries(ms):
