@@ -274,6 +274,34 @@ int batch_needed(const ms_batch *batch, const search_stats_t *stats_host, int64_
 int batch_free(ms_batch *batch);
 
 /*
+ * One-call form of the batched search (the independent searches of many
+ * half-layer pairs of Sec. 6.4, or of a torus family, in one call).
+ * search_batched_workspace_size -- workspace bytes for these pairs with
+ *   room for hits_cap hits (counts entries: runs kernels on `stream` and
+ *   synchronises it).
+ * search_intersections_batched -- search every pair: hits sorted by (pair,
+ *   triA, triB) with hit_t.flags = pair index, pair_hit_offsets_dev[n_pairs +
+ *   1] (int64, device) the offsets of each pair's hits, stats_dev the totals.
+ *   Every pair keeps its own grid (per_pair[i]).  The library keeps the plans
+ *   of its last 8 distinct calls (keyed by the pairs' meshes, vertex
+ *   pointers and grids, and by the buffers): a repeated call reuses its plan
+ *   and, with use_graph != 0, launches the HIP graph captured by its first
+ *   call.  Asynchronous, except that the first call of a plan with
+ *   use_graph != 0 synchronises `stream` once before capturing (so capture
+ *   such a call into a graph of your own only with use_graph = 0).
+ *   Overflow is reported in stats_dev->overflow (check after synchronising);
+ *   call search_batched_workspace_size again with the counts to size anew.
+ *   Releasing an old plan waits for its last launch.  Calls that overlap on
+ *   one workspace race.
+ */
+int search_batched_workspace_size(int32_t n_pairs, const ms_mesh *const *A, const ms_mesh *const *B,
+                                  const search_params_t *per_pair, int64_t hits_cap, void *stream, size_t *bytes);
+int search_intersections_batched(int32_t n_pairs, const ms_mesh *const *A, const ms_mesh *const *B,
+                                 const search_params_t *per_pair, void *ws_dev, size_t ws_bytes, hit_t *hits_dev,
+                                 int64_t hits_cap, int64_t *pair_hit_offsets_dev, search_stats_t *stats_dev,
+                                 int32_t use_graph, void *stream);
+
+/*
  * Kernel timing for benchmarks.  While enabled (per calling thread), every
  * kernel that mesh_info and the searches queue on an uncaptured stream is
  * launched with a start and a stop event that take that dispatch's own begin
@@ -303,11 +331,9 @@ typedef struct {
  * propagate_vertices -- out = F^n(in) for n_vertices states (x, y, x', y'),
  * AoS 4 doubles each, by the 11-stage order-8 explicit Runge-Kutta method of
  * Cooper & Verner (1972) with fixed steps (the globalization maps
- * F^{+-k} of Sec. 4.3).  in_dev may equal out_dev.  Asynchronous.  The
- * first call for a given (device, e, steps_per_period) also builds a small
- * table of stage values (allocated and copied synchronously, kept for the
- * life of the process); make that call before capturing a stream into a
- * graph.
+ * F^{+-k} of Sec. 4.3).  in_dev may equal out_dev.  Asynchronous: queues one
+ * kernel (the stage weights w(f) are computed on the GPU inside it), allocates
+ * nothing, never synchronises, and can be captured into a HIP graph.
  */
 int propagate_vertices(const double *in_dev, double *out_dev, int64_t n_vertices,
                        const map_params_t *params, void *stream);
@@ -329,10 +355,9 @@ int propagate_vertices(const double *in_dev, double *out_dev, int64_t n_vertices
 /* pertbp_map -- out = F^n(in) for n_states states (x, y, px, py), AoS 4
  * doubles each, device arrays.  in_dev may equal out_dev.  Asynchronous on
  * stream; MS_E_ARG for a bad pointer, steps_per_period <= 0, e outside
- * [0, 1) or mu outside [0, 1].  The first call for a given (device, e,
- * steps_per_period) solves Kepler's equation for the stage times of one
- * period and keeps the table for the life of the process (synchronous
- * allocation and copy: make that call before capturing a graph). */
+ * [0, 1) or mu outside [0, 1].  The kernel solves Kepler's equation for the
+ * stage times on the GPU; the call allocates nothing, never synchronises and
+ * can be captured into a HIP graph. */
 int pertbp_map(const double *in_dev, double *out_dev, int64_t n_states, const map_params_t *params,
                void *stream);
 
@@ -477,9 +502,11 @@ enum {
 };
 
 /* Workspace bytes of refine_grad (mode 0-2) or refine_newton (mode 3) for K
- * hits.  The adjoint needs K x 2 x (steps / ckpt_every) x 32 B of checkpoints
- * plus a window of recomputed states and step Jacobians (at most 256 MiB, at
- * least one checkpoint segment). */
+ * hits.  Holds the stage values of one period per side (steps_per_period x 11
+ * doubles of w(f), and as many of dw/de except in residual mode, computed by
+ * the call itself); the adjoint also needs K x 2 x (steps / ckpt_every) x 32 B
+ * of checkpoints plus a window of recomputed states and step Jacobians (at
+ * most 256 MiB, at least one checkpoint segment). */
 int refine_workspace_size(int64_t K, const map_params_t *fwd, const map_params_t *bwd, int32_t ckpt_every,
                           int32_t mode, size_t *bytes);
 
@@ -497,8 +524,10 @@ int refine_workspace_size(int64_t K, const map_params_t *fwd, const map_params_t
  * and the cotangent is carried back through the transposed steps; the result
  * does not depend on ckpt_every (bit for bit).  The tangent integrates the
  * variational equations with the same method, so both give the derivative of
- * the discrete map.  ws: refine_workspace_size bytes.  Asynchronous on
- * `stream`.
+ * the discrete map.  ws: refine_workspace_size bytes (the call writes every
+ * part it reads).  Asynchronous on `stream`: queues kernels only, allocates
+ * nothing, never synchronises, and can be captured into a HIP graph whatever
+ * the values of e and steps_per_period.
  */
 int refine_grad(const double *params_dev, int64_t K, const patch_t *U_dev, const patch_t *S_dev,
                 int32_t patch_stride, const map_params_t *fwd, const map_params_t *bwd, int32_t ckpt_every,

@@ -24,7 +24,7 @@ MS_SEARCH_CANDIDATES, MS_SEARCH_STRICT = 1, 2
 EXPORTS = ("last_error", "mesh_build", "mesh_free", "mesh_info", "mesh_update", "search_default_params",
            "search_workspace_size", "search_intersections", "search_intersections_async", "narrow_allpairs", "propagate_vertices",
            "search_profile_enable", "search_profile_read", "batch_create", "batch_search", "batch_needed",
-           "batch_free", "refine_workspace_size", "refine_grad", "refine_newton", "layer_pairs",
+           "batch_free", "search_batched_workspace_size", "search_intersections_batched", "refine_workspace_size", "refine_grad", "refine_newton", "layer_pairs",
            "half_layer_bounds", "half_layer_columns", "pertbp_map", "pertbp_map_stm", "theta_shift", "theta_interp", "theta_spectrum",
            "ft_partials", "ft_newton_workspace_size", "ft_newton", "continuation_predict",
            "globalize_workspace_size", "globalize_manifold")
@@ -129,6 +129,10 @@ def lib():
         L.batch_search.argtypes = [P, P, C.c_size_t, P, I64, P, P, I32, P]; L.batch_search.restype = C.c_int
         L.batch_needed.argtypes = [P, P, P]; L.batch_needed.restype = C.c_int
         L.batch_free.argtypes = [P]; L.batch_free.restype = C.c_int
+        L.search_batched_workspace_size.argtypes = [I32, P, P, P, I64, P, C.POINTER(C.c_size_t)]
+        L.search_batched_workspace_size.restype = C.c_int
+        L.search_intersections_batched.argtypes = [I32, P, P, P, P, C.c_size_t, P, I64, P, P, I32, P]
+        L.search_intersections_batched.restype = C.c_int
         L.search_profile_enable.argtypes = [C.c_int]; L.search_profile_enable.restype = C.c_int
         L.search_profile_read.argtypes = [C.c_char_p, C.c_size_t, P, C.c_int, C.POINTER(C.c_int)]
         L.search_profile_read.restype = C.c_int
@@ -546,6 +550,45 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def search_batched(pairs, params, hits_cap: int = 1 << 16, use_graph: bool = True, buffers=None):
+    """search_intersections_batched of the C ABI: every (A, B) mesh pair of
+    `pairs` with its own grid; returns (per-pair hit arrays sorted by (triA,
+    triB), stats dict, buffers).  Pass the returned buffers back to repeat the
+    search on the same buffers (the library then reuses its plan and graph);
+    they are re-sized when the counts outgrow them."""
+    torch = _torch()
+    n = len(pairs)
+    A = (C.c_void_p * n)(*[a.handle for a, _ in pairs])
+    B = (C.c_void_p * n)(*[b.handle for _, b in pairs])
+    P = (SearchParams * n)(*params)
+    if buffers is None:
+        nb = C.c_size_t()
+        _check(lib().search_batched_workspace_size(n, A, B, P, int(hits_cap), _stream(), C.byref(nb)))
+        buffers = {"ws": _workspace(nb.value), "hits": _dev_bytes(int(hits_cap) * HIT_DTYPE.itemsize),
+                   "hits_cap": int(hits_cap), "offs": torch.zeros(n + 1, dtype=torch.int64, device="cuda"),
+                   "stats": _dev_bytes(16 * 8)}
+    b = buffers
+    for _ in range(3):
+        _check(lib().search_intersections_batched(n, A, B, P, C.c_void_p(b["ws"].data_ptr()), b["ws"].numel(),
+                                                  C.c_void_p(b["hits"].data_ptr()), b["hits_cap"],
+                                                  C.c_void_p(b["offs"].data_ptr()), C.c_void_p(b["stats"].data_ptr()),
+                                                  int(bool(use_graph)), _stream()))
+        st = _stats_dict(b["stats"])
+        if st["overflow"] == 0:
+            break
+        b["hits_cap"] = max(b["hits_cap"], st["n_hits"])
+        nb = C.c_size_t()
+        _check(lib().search_batched_workspace_size(n, A, B, P, b["hits_cap"], _stream(), C.byref(nb)))
+        b["ws"] = _workspace(max(nb.value, b["ws"].numel()))
+        b["hits"] = _dev_bytes(b["hits_cap"] * HIT_DTYPE.itemsize)
+    else:
+        raise MSearchError(MS_E_CAPACITY, "search_batched: capacity still exceeded")
+    nh = min(st["n_hits"], b["hits_cap"])
+    hits = np.frombuffer(b["hits"][: nh * HIT_DTYPE.itemsize].cpu().numpy().tobytes(), dtype=HIT_DTYPE)
+    off = b["offs"].cpu().numpy()
+    return [hits[off[i]:off[i + 1]] for i in range(n)], st, b
 
 
 def narrow_allpairs(A: Mesh, B: Mesh, hits_cap: int = 1 << 16):

@@ -6,10 +6,10 @@
 //
 // Same fixed-step order-8 Runge-Kutta method as the pulsating map.  The
 // time-dependent coefficients, the separation rho(t) of the primaries and the
-// rate n(t) of their true anomaly, come from Kepler's equation; they are
-// tabulated once per (e, steps) for the stage times of one period (both are
-// 2 pi periodic and even in t, so the table serves every period and both
-// directions) and read with uniform loads.
+// rate n(t) of their true anomaly, come from Kepler's equation; each block
+// solves it for the stage times of RK_CHUNK steps at a time into LDS (both
+// are 2 pi periodic and even in t, so one period's values serve every period
+// and both directions).  Nothing is allocated; every call can be captured.
 //
 // The map runs one thread per state.  The matrix runs 4 / NC threads per
 // state, each carrying the state and NC of the 4 tangent columns (the
@@ -35,38 +35,76 @@ constexpr int PM_BLOCK = 128;
 template <int NC>
 __global__ void __launch_bounds__(PM_BLOCK) k_pm_flow(const double *__restrict__ in, double *out,
                                                       double *__restrict__ stm, int64_t n, Model md, Tableau T,
-                                                      const double2 *__restrict__ tab, int steps, int64_t nsteps,
-                                                      double h)
+                                                      double ecc, int steps, int64_t nsteps, double h)
 {
 #pragma clang fp contract(fast)
     constexpr int G = NC > 0 ? 4 / NC : 1;   // threads per state
     constexpr int NV = NC > 0 ? NC : 1;
+    __shared__ double2 s_rn[RK_CHUNK * S];
+    __shared__ double s_c[S];
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+        if (threadIdx.x == i) s_c[i] = T.c[i];
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= n * G) return;
-    const int64_t p = gid / G;
-    const int g = (int)(gid - p * G);
-    d4 s = load_d4(in + 4 * p);
-    double z[4] = {s.x, s.y, s.z, s.w};
+    const bool live = gid < n * G;      // every thread of the block fills the stage values
+    const int64_t p = live ? gid / G : 0;
+    const int g = (int)(gid - (gid / G) * G);
+    double z[4] = {0.0, 0.0, 0.0, 0.0};
+    if (live) {
+        const d4 s = load_d4(in + 4 * p);
+        z[0] = s.x; z[1] = s.y; z[2] = s.z; z[3] = s.w;
+    }
     double v[NV][4];
 #pragma unroll
     for (int c = 0; c < NV; ++c)
 #pragma unroll
         for (int i = 0; i < 4; ++i) v[c][i] = (i == g * NC + c) ? 1.0 : 0.0;
-    int n_in = 0;
-    for (int64_t st = 0; st < nsteps; ++st) {
-        const double2 *row = tab + (size_t)n_in * S;
-        double k[S][4];
-        double kv[S][NV][4];
+    int64_t n_in = 0;
+    for (int64_t st0 = 0; st0 < nsteps; st0 += RK_CHUNK) {
+        const int cnt = nsteps - st0 < RK_CHUNK ? (int)(nsteps - st0) : RK_CHUNK;
+        __syncthreads();      // the previous chunk's values are no longer read (and s_c is written)
+        fill_stage_chunk(s_rn, s_c, n_in, cnt, steps, [&](double t) { return kepler_rho_n(t, ecc); });
+        __syncthreads();
+        n_in = (n_in + cnt) % steps;
+        if (!live) continue;
+        for (int jj = 0; jj < cnt; ++jj) {
+            const double2 *row = s_rn + jj * S;
+            double k[S][4];
+            double kv[S][NV][4];
 #pragma unroll
-        for (int i = 0; i < S; ++i) {
-            double zs[4], vs[NV][4];
+            for (int i = 0; i < S; ++i) {
+                double zs[4], vs[NV][4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int j = 0; j < i; ++j)
+                        if (RK_NZ[i][j]) acc += T.a[i][j] * k[j][c];
+                    zs[c] = z[c] + h * acc;
+                }
+                if constexpr (NC > 0) {
+#pragma unroll
+                    for (int q = 0; q < NC; ++q)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            double acc = 0.0;
+#pragma unroll
+                            for (int j = 0; j < i; ++j)
+                                if (RK_NZ[i][j]) acc += T.a[i][j] * kv[j][q][c];
+                            vs[q][c] = v[q][c] + h * acc;
+                        }
+                }
+                const double2 rn = row[i];
+                if constexpr (NC > 0) pm_field_var<NC>(md, rn.x, rn.y, zs, vs, k[i], kv[i]);
+                else pm_field(md, rn.x, rn.y, zs, k[i]);
+            }
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 double acc = 0.0;
 #pragma unroll
-                for (int j = 0; j < i; ++j)
-                    if (RK_NZ[i][j]) acc += T.a[i][j] * k[j][c];
-                zs[c] = z[c] + h * acc;
+                for (int i = 0; i < S; ++i)
+                    if (RK_NZB[i]) acc += T.b[i] * k[i][c];
+                z[c] = z[c] + h * acc;
             }
             if constexpr (NC > 0) {
 #pragma unroll
@@ -75,37 +113,14 @@ __global__ void __launch_bounds__(PM_BLOCK) k_pm_flow(const double *__restrict__
                     for (int c = 0; c < 4; ++c) {
                         double acc = 0.0;
 #pragma unroll
-                        for (int j = 0; j < i; ++j)
-                            if (RK_NZ[i][j]) acc += T.a[i][j] * kv[j][q][c];
-                        vs[q][c] = v[q][c] + h * acc;
+                        for (int i = 0; i < S; ++i)
+                            if (RK_NZB[i]) acc += T.b[i] * kv[i][q][c];
+                        v[q][c] = v[q][c] + h * acc;
                     }
             }
-            const double2 rn = row[i];
-            if constexpr (NC > 0) pm_field_var<NC>(md, rn.x, rn.y, zs, vs, k[i], kv[i]);
-            else pm_field(md, rn.x, rn.y, zs, k[i]);
         }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            double acc = 0.0;
-#pragma unroll
-            for (int i = 0; i < S; ++i)
-                if (RK_NZB[i]) acc += T.b[i] * k[i][c];
-            z[c] = z[c] + h * acc;
-        }
-        if constexpr (NC > 0) {
-#pragma unroll
-            for (int q = 0; q < NC; ++q)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    double acc = 0.0;
-#pragma unroll
-                    for (int i = 0; i < S; ++i)
-                        if (RK_NZB[i]) acc += T.b[i] * kv[i][q][c];
-                    v[q][c] = v[q][c] + h * acc;
-                }
-        }
-        if (++n_in == steps) n_in = 0;
     }
+    if (!live) return;
     if (out && g == 0) {
         double2 *o = reinterpret_cast<double2 *>(out + 4 * p);
         o[0] = make_double2(z[0], z[1]);
@@ -134,9 +149,6 @@ int pm_check(const char *who, const double *in_dev, const void *out_dev, int64_t
 template <int NC>
 int pm_launch(const double *in, double *out, double *stm, int64_t n, const map_params_t *p, hipStream_t st)
 {
-    double *tab = nullptr;
-    int rc = stage_table(p->e, p->steps_per_period, STAGE_RHO_N, &tab);
-    if (rc) return rc;
     const int np = p->n_periods < 0 ? -p->n_periods : p->n_periods;
     const int64_t nsteps = (int64_t)p->steps_per_period * np;
     const double h = (p->n_periods < 0 ? -RK_TWO_PI : RK_TWO_PI) / (double)p->steps_per_period;
@@ -146,8 +158,7 @@ int pm_launch(const double *in, double *out, double *stm, int64_t n, const map_p
     if (n > (((int64_t)1 << 32) - PM_BLOCK) / G) return fail(MS_E_ARG, "pertbp: too many states for one launch");
     Model md{p->mu, 1.0 - p->mu};
     hipLaunchKernelGGL(k_pm_flow<NC>, dim3((unsigned)ceil_div(threads, PM_BLOCK)), dim3(PM_BLOCK), 0, st, in, out,
-                       stm, n, md, cv_tableau(), reinterpret_cast<const double2 *>(tab), p->steps_per_period,
-                       nsteps, h);
+                       stm, n, md, cv_tableau(), p->e, p->steps_per_period, nsteps, h);
     MS_HIP(hipGetLastError());
     return MS_OK;
 }

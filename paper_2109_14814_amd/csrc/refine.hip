@@ -23,40 +23,23 @@
 #include <math.h>
 #include <string.h>
 
-#include <mutex>
-
 #include "newton.hpp"
 #include "rk8_core.hpp"
 
 namespace ms {
 
-// The tableau in constant memory (one copy per device, uploaded on first use).
-__constant__ Tableau c_cv;
+// The tableau in constant memory, initialised at compile time (every device
+// holds it from the moment the code object is loaded).
+__constant__ Tableau c_cv = cv_make_tableau();
 
 namespace {
 
 constexpr int S = RK_S;
 constexpr int RF_BLOCK = 64;
 
-std::mutex g_cv_mu;
-uint64_t g_cv_ready = 0;   // bit per device
-
-int upload_tableau()
-{
-    int dev = 0;
-    MS_HIP(hipGetDevice(&dev));
-    if (dev >= 64) return fail(MS_E_ARG, "refine: device index above 63");
-    std::lock_guard<std::mutex> lk(g_cv_mu);
-    if (g_cv_ready >> dev & 1) return MS_OK;
-    if (!cv_pattern_ok()) return fail(MS_E_ARG, "refine: internal tableau pattern mismatch");
-    MS_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_cv), &cv_tableau(), sizeof(Tableau), 0, hipMemcpyHostToDevice));
-    g_cv_ready |= 1ull << dev;
-    return MS_OK;
-}
-
 struct SideMap {
-    const double *w;       // stage table w(f), steps x S
-    const double *dwde;    // stage table dw/de, steps x S
+    const double *w;       // stage values w(f), steps x S (in the workspace)
+    const double *dwde;    // stage values dw/de, steps x S (in the workspace)
     double h;              // signed step
     int64_t nsteps;
     int32_t steps;         // steps per period
@@ -406,6 +389,29 @@ __global__ void __launch_bounds__(RF_BLOCK) k_ref_grad(RefArgs a, double *g_out)
     g_out[5 * k + 4] = gu[2] + gs[2];
 }
 
+// The stage values of both sides for one period (entry (n, i) at step n of
+// a period, stage i), into the workspace: w, and dw/de when wanted.
+struct TableArgs {
+    double *w[2], *dwde[2];
+    int32_t steps[2];
+    double e;
+};
+
+__global__ void __launch_bounds__(256) k_ref_tables(TableArgs t)
+{
+    const int64_t n0 = (int64_t)t.steps[0] * S, n1 = (int64_t)t.steps[1] * S;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n0 + n1) return;
+    const int sd = i >= n0;
+    const int64_t k = sd ? i - n0 : i;
+    const int64_t step = k / S;
+    const int q = (int)(k - step * S);
+    const double cf = cos(stage_abscissa(step, c_cv.c[q], t.steps[sd]));
+    const double om = 1.0 / (1.0 + t.e * cf);
+    t.w[sd][k] = om;
+    if (t.dwde[sd]) t.dwde[sd][k] = -cf * om * om;
+}
+
 // ------------------------------------------------------------ damped Newton
 
 __global__ void __launch_bounds__(RF_BLOCK) k_newton_init(const double *x0, NewtonState ns, int64_t K)
@@ -444,7 +450,7 @@ __global__ void __launch_bounds__(RF_BLOCK) k_newton_finish(NewtonState ns, int6
 // ---------------------------------------------------------------- host side
 
 struct RefLayout {
-    size_t o_yend, o_dend, o_gpart, o_ckpt, o_states, o_jac, o_adj, o_nw, total;
+    size_t o_w[2], o_dwde[2], o_yend, o_dend, o_gpart, o_ckpt, o_states, o_jac, o_adj, o_nw, total;
     int64_t n_ck, win_steps, n_steps_max;
 };
 
@@ -481,6 +487,12 @@ RefLayout ref_layout(int64_t K, const map_params_t *fwd, const map_params_t *bwd
     const size_t T2 = (size_t)(2 * K);
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = al256(o + (bytes ? bytes : 1)); return at; };
+    const map_params_t *m[2] = {fwd, bwd};
+    for (int sd = 0; sd < 2; ++sd) {
+        const size_t tb = (size_t)m[sd]->steps_per_period * S * 8;
+        L.o_w[sd] = take(tb);
+        L.o_dwde[sd] = take(mode != MS_REFINE_RESIDUAL ? tb : 0);
+    }
     L.o_yend = take(T2 * 32);
     L.o_dend = take((mode == MS_REFINE_TANGENT || mode == MS_REFINE_NEWTON) ? 3 * T2 * 32 : 0);
     L.o_gpart = take(mode == MS_REFINE_ADJOINT ? T2 * 24 : 0);
@@ -507,9 +519,13 @@ RefLayout ref_layout(int64_t K, const map_params_t *fwd, const map_params_t *bwd
     return L;
 }
 
+// Kernel arguments of one call, with the stage values of both sides in the
+// workspace; queues the kernel that computes them.
 int make_args(RefArgs &a, const double *params, int64_t K, const patch_t *U, const patch_t *Sp, int32_t stride,
-              const map_params_t *fwd, const map_params_t *bwd, int32_t ck, int need_dwde)
+              const map_params_t *fwd, const map_params_t *bwd, int32_t ck, int need_dwde, char *ws,
+              const RefLayout &L, hipStream_t st)
 {
+    if (!cv_pattern_ok()) return fail(MS_E_ARG, "refine: internal tableau pattern mismatch");
     memset(&a, 0, sizeof a);
     a.params = params;
     a.U = (const double *)U;
@@ -519,21 +535,23 @@ int make_args(RefArgs &a, const double *params, int64_t K, const patch_t *U, con
     a.md = Model{fwd->mu, 1.0 - fwd->mu};
     a.ck = ck;
     const map_params_t *m[2] = {fwd, bwd};
+    TableArgs t;
+    t.e = fwd->e;
     for (int sd = 0; sd < 2; ++sd) {
         SideMap &sm = a.side[sd];
-        int rc = stage_table(m[sd]->e, m[sd]->steps_per_period, STAGE_W, (double **)&sm.w);
-        if (rc) return rc;
-        if (need_dwde) {
-            rc = stage_table(m[sd]->e, m[sd]->steps_per_period, STAGE_DWDE, (double **)&sm.dwde);
-            if (rc) return rc;
-        } else {
-            sm.dwde = sm.w;
-        }
+        t.w[sd] = (double *)(ws + L.o_w[sd]);
+        t.dwde[sd] = need_dwde ? (double *)(ws + L.o_dwde[sd]) : nullptr;
+        t.steps[sd] = m[sd]->steps_per_period;
+        sm.w = t.w[sd];
+        sm.dwde = need_dwde ? t.dwde[sd] : t.w[sd];
         sm.nsteps = side_steps(m[sd]);
         sm.steps = m[sd]->steps_per_period;
         sm.h = (m[sd]->n_periods < 0 ? -RK_TWO_PI : RK_TWO_PI) / (double)m[sd]->steps_per_period;
     }
-    return upload_tableau();
+    const int64_t n = ((int64_t)t.steps[0] + t.steps[1]) * S;
+    MS_LAUNCH("k_ref_tables", k_ref_tables, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, t);
+    MS_HIP(hipGetLastError());
+    return MS_OK;
 }
 
 unsigned blocks_for(int64_t n) { return (unsigned)ceil_div(n > 0 ? n : 1, RF_BLOCK); }
@@ -573,14 +591,15 @@ extern "C" int refine_grad(const double *params_dev, int64_t K, const patch_t *U
     const int32_t ck = mode == MS_REFINE_ADJOINT ? ckpt_every : 1;
     RefLayout L = ref_layout(K, fwd, bwd, ck, mode);
     if (!ws || ws_bytes < L.total) return fail(MS_E_WORKSPACE, "refine_grad: workspace too small");
-    RefArgs a;
-    if ((rc = make_args(a, params_dev, K, U_dev, S_dev, patch_stride, fwd, bwd, ck, mode != MS_REFINE_RESIDUAL)))
-        return rc;
     char *w = (char *)ws;
+    hipStream_t st = (hipStream_t)stream;
+    RefArgs a;
+    if ((rc = make_args(a, params_dev, K, U_dev, S_dev, patch_stride, fwd, bwd, ck, mode != MS_REFINE_RESIDUAL, w, L,
+                        st)))
+        return rc;
     a.yend = (double *)(w + L.o_yend);
     a.dend = (double *)(w + L.o_dend);
     a.gpart = (double *)(w + L.o_gpart);
-    hipStream_t st = (hipStream_t)stream;
     const int64_t T2 = 2 * K;
     if (mode == MS_REFINE_TANGENT) {
         MS_LAUNCH("k_ref_tangent", k_ref_tangent, dim3(blocks_for(3 * T2)), dim3(RF_BLOCK), 0, st, a);
@@ -650,8 +669,9 @@ extern "C" int refine_newton(const double *params_in_dev, double *params_out_dev
         ns.based = (int32_t *)take((size_t)K * 4);
         if ((size_t)(o) > L.total) return fail(MS_E_WORKSPACE, "refine_newton: internal layout");
     }
+    hipStream_t st = (hipStream_t)stream;
     RefArgs a;
-    if ((rc = make_args(a, ns.q, K, U_dev, S_dev, patch_stride, fwd, bwd, 1, 1))) return rc;
+    if ((rc = make_args(a, ns.q, K, U_dev, S_dev, patch_stride, fwd, bwd, 1, 1, w, L, st))) return rc;
     a.yend = (double *)(w + L.o_yend);
     a.dend = (double *)(w + L.o_dend);
     a.status = ns.status;
@@ -660,7 +680,6 @@ extern "C" int refine_newton(const double *params_in_dev, double *params_out_dev
     cfg.alpha0 = np->alpha0;
     cfg.alpha_min = np->alpha_min;
     cfg.max_trials = np->max_trials;
-    hipStream_t st = (hipStream_t)stream;
     const int64_t T2 = 2 * K;
     MS_LAUNCH("k_newton_init", k_newton_init, dim3(blocks_for(K)), dim3(RF_BLOCK), 0, st, params_in_dev, ns, K);
     for (int it = 0; it <= np->max_trials; ++it) {

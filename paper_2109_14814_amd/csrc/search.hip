@@ -33,6 +33,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1908,12 +1909,33 @@ int batch_upload(ms_batch *b, char *ws, const Layout &L, hipStream_t st)
 }  // namespace
 }  // namespace ms
 
+namespace ms {
+namespace {
+
+// A batch plan: geometry, pair descriptors and offsets; with `count`, the
+// entries before filtering are counted (kernels, synchronises) and *ws_bytes
+// is the workspace for them.
+int plan_batch(int32_t n_pairs, const ms_mesh *const *A, const ms_mesh *const *B, const search_params_t *params,
+               int64_t hits_cap, int64_t cand_cap, bool count, void *stream, ms_batch **out, size_t *ws_bytes);
+
+}  // namespace
+}  // namespace ms
+
 extern "C" int batch_create(int32_t n_pairs, const ms_mesh *const *A, const ms_mesh *const *B,
                             const search_params_t *params, int64_t hits_cap, int64_t cand_cap, void *stream,
                             ms_batch **out, size_t *ws_bytes)
 {
     if (!out || !ws_bytes || n_pairs < 1 || !A || !B || !params || hits_cap < 0 || cand_cap < 0)
         return fail(MS_E_ARG, "batch_create: bad argument");
+    return plan_batch(n_pairs, A, B, params, hits_cap, cand_cap, true, stream, out, ws_bytes);
+}
+
+namespace ms {
+namespace {
+
+int plan_batch(int32_t n_pairs, const ms_mesh *const *A, const ms_mesh *const *B, const search_params_t *params,
+               int64_t hits_cap, int64_t cand_cap, bool count, void *stream, ms_batch **out, size_t *ws_bytes)
+{
     *out = nullptr;
     ms_batch *b = new ms_batch();
     b->graph = nullptr;
@@ -1943,7 +1965,7 @@ extern "C" int batch_create(int32_t n_pairs, const ms_mesh *const *A, const ms_m
     b->cell_base[(size_t)n_pairs] = cb;
     b->tri_off[(size_t)n_pairs] = to;
     int64_t E = 0;
-    if ((rc = count_entries(n_pairs, A, B, params, (unsigned long long *)A[0]->counter, (hipStream_t)stream, E))) {
+    if (count && (rc = count_entries(n_pairs, A, B, params, (unsigned long long *)A[0]->counter, (hipStream_t)stream, E))) {
         batch_free(b);
         return rc;
     }
@@ -1956,10 +1978,13 @@ extern "C" int batch_create(int32_t n_pairs, const ms_mesh *const *A, const ms_m
     L.cand_cap = cand_cap;
     L.hits_cap = hits_cap;
     layout(b->G, L);
-    *ws_bytes = L.total;
+    if (ws_bytes) *ws_bytes = L.total;
     *out = b;
     return MS_OK;
 }
+
+}  // namespace
+}  // namespace ms
 
 extern "C" int batch_free(ms_batch *b)
 {
@@ -2036,6 +2061,113 @@ extern "C" int batch_needed(const ms_batch *b, const search_stats_t *stats_host,
     needed[0] = L.hits_cap;
     needed[1] = L.cand_cap;
     needed[2] = (int64_t)L.total;
+    return MS_OK;
+}
+
+// ------------------------------------------------------ one-call batched form
+
+namespace ms {
+namespace {
+
+// Plans of search_intersections_batched, reused by calls with the same
+// pairs (descriptor bytes: vertex pointers, grid sizes, cell grids), the
+// same buffers and the same device, so that a repeated call launches the
+// graph it captured.  A few are kept; the oldest is released when a new one
+// is needed (after its last launch has finished).
+struct BatchedPlan {
+    std::vector<PairDesc> key;
+    int device;
+    void *ws, *hits, *offs, *stats;
+    size_t ws_bytes;
+    int64_t hits_cap;
+    ms_batch *plan;
+    hipEvent_t done;
+};
+
+constexpr size_t BATCHED_PLANS = 8;
+std::mutex g_bp_mu;
+std::vector<BatchedPlan> g_bp;
+
+bool same_plan(const BatchedPlan &p, const std::vector<PairDesc> &key, int dev, void *ws, size_t ws_bytes,
+               void *hits, int64_t hits_cap, void *offs, void *stats)
+{
+    return p.device == dev && p.ws == ws && p.ws_bytes == ws_bytes && p.hits == hits && p.hits_cap == hits_cap &&
+           p.offs == offs && p.stats == stats && p.key.size() == key.size() &&
+           memcmp(p.key.data(), key.data(), key.size() * sizeof(PairDesc)) == 0;
+}
+
+}  // namespace
+}  // namespace ms
+
+extern "C" int search_batched_workspace_size(int32_t n_pairs, const ms_mesh *const *A, const ms_mesh *const *B,
+                                             const search_params_t *per_pair, int64_t hits_cap, void *stream,
+                                             size_t *bytes)
+{
+    if (!bytes || n_pairs < 1 || !A || !B || !per_pair || hits_cap < 0)
+        return fail(MS_E_ARG, "search_batched_workspace_size: bad argument");
+    ms_batch *b = nullptr;
+    int rc = plan_batch(n_pairs, A, B, per_pair, hits_cap, 0, true, stream, &b, bytes);
+    batch_free(b);
+    return rc;
+}
+
+extern "C" int search_intersections_batched(int32_t n_pairs, const ms_mesh *const *A, const ms_mesh *const *B,
+                                            const search_params_t *per_pair, void *ws_dev, size_t ws_bytes,
+                                            hit_t *hits_dev, int64_t hits_cap, int64_t *pair_hit_offsets_dev,
+                                            search_stats_t *stats_dev, int32_t use_graph, void *stream)
+{
+    if (n_pairs < 1 || !A || !B || !per_pair || !ws_dev || !stats_dev || !pair_hit_offsets_dev || hits_cap < 0 ||
+        (hits_cap > 0 && !hits_dev))
+        return fail(MS_E_ARG, "search_intersections_batched: bad argument");
+    Geometry G;
+    int rc = geometry(n_pairs, A, B, per_pair, G);
+    if (rc) return rc;
+    std::vector<PairDesc> key((size_t)n_pairs);
+    {
+        uint64_t cb = 0;
+        int64_t to = 0;
+        for (int32_t i = 0; i < n_pairs; ++i) {
+            uint64_t c = 0;
+            pair_cells(&per_pair[i], c);
+            key[(size_t)i] = make_desc(A[i], B[i], &per_pair[i], cb, to);
+            cb += c;
+            to += (int64_t)A[i]->view.n_tris + B[i]->view.n_tris;
+        }
+    }
+    int dev = 0;
+    MS_HIP(hipGetDevice(&dev));
+    hipStream_t st = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lk(g_bp_mu);
+    BatchedPlan *bp = nullptr;
+    for (BatchedPlan &p : g_bp)
+        if (same_plan(p, key, dev, ws_dev, ws_bytes, hits_dev, hits_cap, pair_hit_offsets_dev, stats_dev)) bp = &p;
+    if (!bp) {
+        if (g_bp.size() >= BATCHED_PLANS) {
+            BatchedPlan &old = g_bp.front();
+            (void)hipEventSynchronize(old.done);
+            (void)hipEventDestroy(old.done);
+            batch_free(old.plan);
+            g_bp.erase(g_bp.begin());
+        }
+        BatchedPlan np;
+        np.key = key;
+        np.device = dev;
+        np.ws = ws_dev;
+        np.ws_bytes = ws_bytes;
+        np.hits = hits_dev;
+        np.hits_cap = hits_cap;
+        np.offs = pair_hit_offsets_dev;
+        np.stats = stats_dev;
+        if ((rc = plan_batch(n_pairs, A, B, per_pair, hits_cap, 0, false, stream, &np.plan, nullptr))) return rc;
+        hipError_t e = hipEventCreateWithFlags(&np.done, hipEventDisableTiming);
+        if (e != hipSuccess) { batch_free(np.plan); return hip_fail(e, "hipEventCreate"); }
+        g_bp.push_back(np);
+        bp = &g_bp.back();
+    }
+    if ((rc = batch_search(bp->plan, ws_dev, ws_bytes, hits_dev, hits_cap, pair_hit_offsets_dev, stats_dev, use_graph,
+                           stream)))
+        return rc;
+    MS_HIP(hipEventRecord(bp->done, st));
     return MS_OK;
 }
 

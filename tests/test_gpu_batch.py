@@ -154,3 +154,32 @@ def test_batch_overflow_is_reported_and_replanned(ms):
     assert st["overflow"] == 0
     for (a, b), hits in zip(fam, per_pair):
         assert_same_hits(hits, oracle.bruteforce(a, b).hits)
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_one_call_batched_search(ms, use_graph):
+    """search_intersections_batched (one call, plans kept by the library):
+    per pair equal to the oracle; repeating the call on the same buffers
+    reuses the plan (and graph) and gives the same bits; a call with a
+    changed grid gives that grid's (identical) hits."""
+    fam = small_family(20, 11)
+    gp = [(ms.Mesh.from_synth(a), ms.Mesh.from_synth(b)) for a, b in fam]
+    params = [ms.make_params(g[0], g[2], g[3]) for g in grids_for(fam, 1.5)]
+    per_pair, st, buf = ms.search_batched(gp, params, hits_cap=1 << 12, use_graph=use_graph)
+    assert st["overflow"] == 0
+    tot_h = 0
+    for (a, b), hits in zip(fam, per_pair):
+        ref = oracle.bruteforce(a, b)
+        assert_same_hits(hits, ref.hits)
+        tot_h += len(ref.hits)
+    assert st["n_hits"] == tot_h > 0
+    for _ in range(3):
+        again, st2, buf = ms.search_batched(gp, params, use_graph=use_graph, buffers=buf)
+        assert st2 == st
+        for g, r in zip(again, per_pair):
+            assert_same_hits(g, r, exact=True)
+    params2 = [ms.make_params(g[0], g[2], g[3]) for g in grids_for(fam, 3.0)]
+    other, st3, _ = ms.search_batched(gp, params2, use_graph=use_graph, buffers=buf)
+    assert st3["n_hits"] == tot_h
+    for g, r in zip(other, per_pair):
+        assert_same_hits(g, r, exact=True)
