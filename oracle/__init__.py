@@ -50,7 +50,7 @@ class _Result(C.Structure):
 def lib():
     global _lib
     if _lib is None:
-        path = _build.ensure_built()
+        path = os.environ.get("ORACLE_LIB") or _build.ensure_built()   # ORACLE_LIB: the sanitizer build
         L = C.CDLL(path)
         P, I64, I32, D = C.c_void_p, C.c_int64, C.c_int32, C.c_double
         L.orc_n_tris.argtypes = [C.POINTER(_Mesh)]; L.orc_n_tris.restype = I64

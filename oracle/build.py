@@ -26,6 +26,23 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+# Checker build for the sanitizer run of the oracle pins (tests/test_sanitized_cpu.py):
+# AddressSanitizer and UndefinedBehaviorSanitizer, same floating-point flags.
+SAN_LIB = os.path.join(HERE, "liboracle_san.so")
+SAN_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-ffp-contract=off",
+             "-fno-fast-math", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall", "-Wextra",
+             "-Wno-unused-parameter", "-fvisibility=hidden"]
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    cmd = ["gcc", *SAN_FLAGS, SRC, "-o", SAN_LIB + ".tmp", "-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(SAN_LIB + ".tmp", SAN_LIB)
+    return SAN_LIB
+
+
 def ensure_built() -> str:
     if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         build()

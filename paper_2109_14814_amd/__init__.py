@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmsearch.so")
+# MSEARCH_LIB selects another build of the same library (the host-sanitizer build of the CPU checks)
+LIB_PATH = os.environ.get("MSEARCH_LIB") or os.path.join(_HERE, "libmsearch.so")
 
 MS_OK, MS_E_ARG, MS_E_CAPACITY, MS_E_HIP, MS_E_NONFINITE, MS_E_KEYBITS, MS_E_WORKSPACE = 0, -1, -2, -3, -4, -5, -6
 MS_LAYOUT_AOS, MS_LAYOUT_SOA = 0, 1

@@ -23,16 +23,27 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}", "-ff
          "-Wall", "-Wno-unused-function", "-Wno-unused-result", "-I", INCLUDE]
 
 
+# Host-side checker build for the CPU sanitizer run (tests/test_sanitized_cpu.py):
+# AddressSanitizer and UndefinedBehaviorSanitizer on the host code only (the
+# argument checks, planning and layouts); the device code is built as usual.
+SAN_LIB = os.path.join(HERE, "libmsearch_san.so")
+HOST_SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+
+
 def sources():
     return [os.path.join(CSRC, s) for s in SOURCES]
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 4, sanitize: bool = False) -> str:
     objs = []
     procs = []
+    extra = HOST_SAN if sanitize else []
+    out = SAN_LIB if sanitize else LIB
+    tag = ".san.o" if sanitize else ".o"
     for src in sources():
-        obj = os.path.join(CSRC, os.path.basename(src) + ".o")
-        cmd = ["hipcc", *[f for f in FLAGS if f != "-shared"], "-c", src, "-o", obj]
+        obj = os.path.join(CSRC, os.path.basename(src) + tag)
+        cmd = ["hipcc", *[f for f in FLAGS if f != "-shared"], *extra, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((subprocess.Popen(cmd), src))
@@ -44,14 +55,14 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     for p, s in procs:
         if p.wait() != 0:
             raise RuntimeError(f"hipcc failed on {s}")
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", LIB + ".tmp"]
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *extra, *objs, "-o", out + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(out + ".tmp", out)
     for o in objs:
         os.remove(o)
-    return LIB
+    return out
 
 
 if __name__ == "__main__":
