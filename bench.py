@@ -1,10 +1,13 @@
 """Benchmark of the mesh-intersection search on one MI355X.
 
 One step = one pass of the search hot path over the 512 x 512-quad workload
-(two seeded torus-like surfaces of 524,288 triangles each, FP64): recompute
-both meshes' triangle boxes from the HBM-resident vertices, then the full
-keyed-grid search (entry keys, radix sort, cell pairs, box test, Moller
-test, 4x4 narrow phase, sorted hits).  Prints one JSON line.
+(two seeded torus-like surfaces of 524,288 triangles each, FP64): both
+meshes' vertices refreshed in place (mesh_update), then the full keyed-grid
+search from the HBM-resident vertices (cell occupancy, entries in cells that
+both meshes occupy, grouping by hashed cell with counts and a scan -- no
+sort --, slot enumeration with the same-cell, home-cell and box tests, the
+Moller test, the 4x4 narrow phase, hits sorted by (pair, triA, triB)).
+Prints one JSON line.
 
 The cell edge is picked by the package's autotuner unless --kappa is given.
 
@@ -46,9 +49,10 @@ def algorithmic_bytes(kernel: str, st: dict, mesh_sizes) -> float | None:
     table = {
         "k_mark": 32.0 * nvtot + 8.0 * ntot,          # vertices read once, compact cell ranges written
         "k_keys": 8.0 * ntot + 16.0 * E,              # cell ranges read, entries and their group ranks written
-        "k_scatter": 24.0 * E,                        # entries and ranks read, grouped entries written
-        # grouped entries and their groups; the 6 vertices of every candidate; hit records
-        "k_enum": 8.0 * E + 24.0 * nc + 192.0 * C + 120.0 * H,
+        # entries, ranks and hashed cells read; grouped entries and their boxes written
+        "k_scatter": 88.0 * E,
+        # grouped entries, their boxes and their groups; the 6 vertices of every candidate; hit records
+        "k_enum": 72.0 * E + 24.0 * nc + 192.0 * C + 120.0 * H,
     }
     return table.get(kernel)
 

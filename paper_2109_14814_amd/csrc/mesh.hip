@@ -235,6 +235,7 @@ extern "C" int mesh_build(const double *verts_dev, int32_t n_theta_v, int32_t n_
     mv.nq = (int32_t)nq;
     mv.periodic = periodic ? 1 : 0;
     mv.n_tris = (int32_t)ntri;
+    mv.inv_nq = nq > 0 ? 1.0 / (double)nq : 0.0;
 
     m->upd_stream = st;
     m->info_stale = 1;

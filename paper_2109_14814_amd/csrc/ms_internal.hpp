@@ -40,6 +40,7 @@ struct MeshView {
     int32_t periodic;
     int32_t n_tris;
     int32_t pad;
+    double inv_nq;         // 1 / nq (0 without quads): the row of a quad without an integer division
 };
 
 // Vertex ids (in the AoS array) of triangle t in narrow-phase order.
@@ -54,6 +55,36 @@ MS_HD void tri_vertex_ids(const MeshView &m, int32_t t, int32_t &v1, int32_t &v2
     int32_t r0 = k * m.n_theta_v, r1 = r0 + m.n_theta_v;
     if (h == 0) { v1 = r0 + i1; v2 = r0 + i;  v3 = r1 + i; }
     else        { v1 = r1 + i;  v2 = r1 + i1; v3 = r0 + i1; }
+}
+
+// Row k and column i of quad q = i + k * nq: the quotient from the FP64
+// product q * (1 / nq), whose error is far below one for q < 2^31, corrected
+// by one step.
+MS_D void quad_row_col(const MeshView &m, int32_t q, int32_t &k, int32_t &i)
+{
+    int32_t kk = (int32_t)((double)q * m.inv_nq);
+    int64_t r = (int64_t)q - (int64_t)kk * m.nq;
+    if (r < 0) {
+        --kk;
+        r += m.nq;
+    } else if (r >= m.nq) {
+        ++kk;
+        r -= m.nq;
+    }
+    k = kk;
+    i = (int32_t)r;
+}
+
+// tri_vertex_ids with the row found by quad_row_col.
+MS_D void tri_vertex_ids_d(const MeshView &m, int32_t t, int32_t &v1, int32_t &v2, int32_t &v3)
+{
+    int32_t k, i;
+    quad_row_col(m, t >> 1, k, i);
+    int32_t i1 = i + 1;
+    if (i1 == m.n_theta_v) i1 = 0;
+    const int32_t r0 = k * m.n_theta_v, r1 = r0 + m.n_theta_v;
+    if ((t & 1) == 0) { v1 = r0 + i1; v2 = r0 + i;  v3 = r1 + i; }
+    else              { v1 = r1 + i;  v2 = r1 + i1; v3 = r0 + i1; }
 }
 
 struct d4 { double x, y, z, w; };

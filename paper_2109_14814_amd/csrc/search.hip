@@ -4,30 +4,34 @@
 // Every kernel reads its sizes from device memory, so one call queues a fixed
 // sequence of kernels with no host round trip (and can be captured in a HIP
 // graph):
-//   k_mark        per triangle: its box from the vertices (Sec. 6.2.2), the
-//                 overlapped cells of its pair's grid (Sec. 6.2.1), one
-//                 occupancy byte per (hashed) cell and side, fine and coarse,
-//                 holding the search's epoch value (no clearing between
-//                 searches); compact range; block 0 clears the counters
-//   k_pack        hashed cells occupied by both meshes as bit tables; each
-//                 such fine cell is a group, with a dense id (the set bits
-//                 before it, by a scan with decoupled look-back)
+//   k_mark        per quad (two triangles): the cells of its four vertices,
+//                 each triangle's cell range as the min / max of its
+//                 vertices' cells (the cell map is monotone), one occupancy
+//                 byte per (hashed) cell and side of the union of the two
+//                 ranges, holding the search's epoch value (no clearing
+//                 between searches); compact ranges; per-block totals;
+//                 block 0 clears the counters
+//   k_pack        hashed cells occupied by both meshes as bit tables (fine
+//                 and coarse); each both-occupied fine cell is a group whose
+//                 counters are cleared here
 //   k_keys        per triangle: the cells of its range in a both-occupied
 //                 group (a cell holding one mesh only cannot hold a pair);
 //                 entries [cell | side | triangle] at offsets reserved per
 //                 block, each with its group and its rank in the group
 //   k_groups      groups holding A and B entries: entry ranges and slot
-//                 offsets sum(nA * nB) (scan)
-//   k_scatter     entries to their group's range, A's before B's
+//                 offsets sum(nA * nB) (scan with decoupled look-back)
+//   k_scatter     entries to their group's range, A's before B's, each with
+//                 its triangle's box (Sec. 6.2.2)
 //   k_enum        slot -> (group, iA, iB); a pair is kept only when both
 //                 entries are of one cell, in its home cell (cell of the
 //                 componentwise max of the boxes' lower corners) and only if
 //                 the closed boxes overlap (Sec. 6.2.2); then, on the chunk's
 //                 candidates, the Moller quick test (Sec. 6.2.3), the 4x4
 //                 solve and inclusion (Sec. 6.2.4), hit records; last, the
-//                 exact cell statistics
-//   hit sort      by (pair, triA, triB): one block for a small capacity,
-//                 else chunk sort, merge rank and placement
+//                 exact cell statistics into sharded counters
+//   k_finish      the statistics, the next epoch value, and the hits sorted
+//                 by (pair, triA, triB) when there are at most 1024 of them
+//                 (above, a chunk sort, merge rank and placement first)
 // A batch numbers its cells with a per-pair cell offset, so entries of
 // different pairs never share a cell (they may share a group).
 #include <math.h>
@@ -35,6 +39,7 @@
 
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "ms_internal.hpp"
@@ -47,8 +52,11 @@ namespace {
 constexpr int BLOCK = 256;
 constexpr int MAX_GRID = 2048;
 static_assert(MAX_GRID <= MS_COUNT_PARTIALS, "count partials fit the mesh scratch");
-constexpr int KEYS_ITEMS = 1;                         // triangles per thread in k_keys
-constexpr int KEYS_TILE = BLOCK * KEYS_ITEMS;         // triangles per k_keys block
+constexpr int TILE_TRIS = 2 * BLOCK;                  // triangles of a tile: one quad per thread
+// Counter lines of the enumeration (cand, moller, degen, outside, cells,
+// slots, unstaged chunks), one 128-byte line each.
+constexpr int STAT_SHARDS = 8;
+constexpr int SHARD_WORDS = 16;
 constexpr uint64_t SFLAG_AGG = 1ull << 62;
 constexpr uint64_t SFLAG_PRE = 2ull << 62;
 constexpr uint64_t SVAL_MASK = (1ull << 62) - 1;
@@ -68,26 +76,36 @@ struct KeyLayout {
 };
 
 // One mesh pair with its grid.  Cells of this pair have global ids
-// cell_base + linear cell; its triangles have global indices tri_off +
-// [0, nA) (A) and tri_off + nA + [0, nB) (B).
+// cell_base + linear cell.  Its triangles are cut into tiles of TILE_TRIS
+// triangles (BLOCK quads) of one mesh each: tiles tile_off + [0, tilesA)
+// hold A's, the next ceil(nB / TILE_TRIS) hold B's, so that the pair and
+// the side are the same for every thread of a block that works on one tile.
 struct PairDesc {
     MeshView A, B;
     GridView g;
     uint64_t cell_base;
-    int64_t tri_off;
+    int64_t tile_off;
     int32_t nA, nB;
+    int32_t tilesA, pad_;
+    uint64_t st[4];     // linear-id strides of the cells: n1 n2 n3, n2 n3, n3, 1
+    uint64_t fbs[4];    // fine table: linear-id strides of its blocks (cell index / 2 per axis)
+    uint64_t fbh[4];    //   and fbs * HASH_MUL mod 2^64
+    uint64_t cbs[4];    // coarse table (cell index / 2 per axis): strides of its blocks
+    uint64_t cbh[4];    //   (cell index / 4 per axis) and cbs * HASH_MUL
+    double nm1[4];      // n_d - 1
 };
 
 struct BatchView {
     PairDesc p0;                 // the pair of a single search
     const PairDesc *pairs;       // device array of a batch
-    const int64_t *tri_off;      // n_pairs + 1 (batch)
+    const int64_t *tile_off;     // n_pairs + 1 (batch): first triangle tile of each pair
     const uint64_t *cell_base;   // n_pairs + 1 (batch)
-    int64_t n_tri;
+    int64_t n_tiles;             // triangle tiles of all pairs
     int32_t n_pairs;
     int32_t bm_log2;             // occupancy flags per side: 2^bm_log2 bytes, then as many bits
     int32_t bc_log2;             // the same for the coarse cells (2x the edge): 2^bc_log2 per side
     int32_t packable;            // every grid has <= 4096 cells per axis
+    int32_t c32;                 // every grid has < 2^31 cells per axis (32-bit cell ranges)
     int32_t pb, tbA, tbB;        // bits of the pair, A- and B-triangle fields of hit keys
     KeyLayout kl;
 };
@@ -112,16 +130,18 @@ MS_D int64_t last_le(const T *a, int64_t n, T x)
     return lo;
 }
 
-template <bool ONE>
-MS_D int pair_of_tri(const BatchView &bv, int64_t gt)
-{
-    if constexpr (ONE) return 0;
-    else return (int)last_le<int64_t>(bv.tri_off, bv.n_pairs, gt);
-}
 
-MS_D uint32_t bm_hash(uint64_t cell, int log2)
+// Multiplier of the hashed tables (the odd 64-bit constant nearest 2^64 / phi).
+constexpr uint64_t HASH_MUL = 0x9E3779B97F4A7C15ull;
+
+
+// The top log2 bits (log2 <= 32) of a product id * HASH_MUL mod 2^64.  The
+// product is linear in the id, so the products of neighbouring ids follow
+// from one of them by adding per-axis products (stride_d * HASH_MUL), with
+// no multiplication per cell.
+MS_D uint32_t hash_of_product(uint64_t prod, int log2)
 {
-    return (uint32_t)((cell * 0x9E3779B97F4A7C15ull) >> (64 - log2));
+    return (uint32_t)(prod >> 32) >> (32 - log2);
 }
 
 struct CellRange {
@@ -172,47 +192,226 @@ MS_D void for_cells(const CellRange &r, const int64_t n[4], F &&f)
             }
 }
 
+// The same with the coordinates of each cell: f(c, linear id).
+template <typename F>
+MS_D void for_cells_xy(const CellRange &r, const int64_t n[4], F &&f)
+{
+    int64_t c[4];
+    for (c[0] = r.lo[0]; c[0] <= r.hi[0]; ++c[0])
+        for (c[1] = r.lo[1]; c[1] <= r.hi[1]; ++c[1])
+            for (c[2] = r.lo[2]; c[2] <= r.hi[2]; ++c[2]) {
+                const int64_t base = ((c[0] * n[1] + c[1]) * n[2] + c[2]) * n[3];
+                for (c[3] = r.lo[3]; c[3] <= r.hi[3]; ++c[3]) f(c, (uint64_t)(base + c[3]));
+            }
+}
+
 // Occupancy bit of hashed cell h in a side's bit table.
 MS_D uint32_t occ_bit(const uint32_t *bits, uint32_t h) { return (bits[h >> 5] >> (h & 31)) & 1u; }
 
-// Occupancy bits of the cells of a range held by the other mesh (its bit
-// table `other`), as a mask in lexicographic order of the cells.  Ranges of
-// up to 16 cells compute the j-th cell from the mixed-radix digits of j, so
-// that all their loads are in flight together; *big is set for larger
-// ranges, which the caller walks with for_cells.
-constexpr int MLP_CELLS = 16;
+// ------------------------------------------- 32-bit cell ranges (the usual grids)
 
-MS_D uint32_t flag_mask(const CellRange &r, const int64_t n[4], uint64_t cb, const uint32_t *other, int log2,
-                        bool *big)
+// Cell of coordinate x on an axis of n < 2^31 cells (nm1 = n - 1):
+// clamp(floor((x - wlo) * inv), 0, n - 1) in FP64 with the clamp taken before
+// the conversion, so that one 32-bit conversion remains; equal to cell_of
+// (a negative or NaN floor clamps to 0, anything from n - 1 up to n - 1).
+MS_D int32_t cell_of32(double x, double wlo, double inv, double nm1)
 {
-    const int64_t cnt = range_count(r);
-    *big = cnt > MLP_CELLS;
-    if (*big) return 0;
-    // odometer over the range's cells in lexicographic order (no divisions)
-    int64_t c0 = r.lo[0], c1 = r.lo[1], c2 = r.lo[2], c3 = r.lo[3];
-    uint32_t v[MLP_CELLS];
+    const double t = (x - wlo) * inv;
+    return (int32_t)fmin(fmax(floor(t), 0.0), nm1);
+}
+
+// A triangle's cell range: lowest cell and extent (hi - lo) per axis.
+struct Range32 {
+    int32_t lo[4], e[4];
+};
+
+// 4D box of triangle t (as tri_box), its vertex ids found without an
+// integer division.
+MS_D bool tri_box_d(const MeshView &m, int32_t t, double lo[4], double hi[4])
+{
+    int32_t i1, i2, i3;
+    tri_vertex_ids_d(m, t, i1, i2, i3);
+    const d4 a = load_d4(m.V + 4 * (int64_t)i1), b = load_d4(m.V + 4 * (int64_t)i2),
+             c = load_d4(m.V + 4 * (int64_t)i3);
+    const double va[4] = {a.x, a.y, a.z, a.w}, vb[4] = {b.x, b.y, b.z, b.w}, vc[4] = {c.x, c.y, c.z, c.w};
+    bool fin = true;
 #pragma unroll
-    for (int j = 0; j < MLP_CELLS; ++j) {
-        v[j] = 0;
-        if (j < cnt) {
-            const int64_t cell = ((c0 * n[1] + c1) * n[2] + c2) * n[3] + c3;
-            v[j] = occ_bit(other, bm_hash(cb + (uint64_t)cell, log2));
-            if (++c3 > r.hi[3]) {
-                c3 = r.lo[3];
-                if (++c2 > r.hi[2]) {
-                    c2 = r.lo[2];
-                    if (++c1 > r.hi[1]) {
-                        c1 = r.lo[1];
-                        ++c0;
-                    }
-                }
-            }
-        }
+    for (int d = 0; d < 4; ++d) {
+        lo[d] = fmin(fmin(va[d], vb[d]), vc[d]);
+        hi[d] = fmax(fmax(va[d], vb[d]), vc[d]);
+        fin = fin && isfinite(va[d]) && isfinite(vb[d]) && isfinite(vc[d]);
     }
+    return fin;
+}
+
+// The range on the coarse grid (cell index / 2 per axis).
+MS_D Range32 coarse_range(const Range32 &r)
+{
+    Range32 c;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        c.lo[d] = r.lo[d] >> 1;
+        c.e[d] = ((r.lo[d] + r.e[d]) >> 1) - c.lo[d];
+    }
+    return c;
+}
+
+// True when every axis of the range has one or two cells: its cells are then
+// lo + b for the positions b in {0,1}^4 (bit 3 - d of b for axis d, so that
+// ascending b is the lexicographic order) with b inside the extent mask.
+MS_D bool range_small(const Range32 &r) { return (r.e[0] | r.e[1] | r.e[2] | r.e[3]) <= 1; }
+
+MS_D uint32_t extent_mask(const Range32 &r)
+{
+    return (uint32_t)(r.e[0] << 3 | r.e[1] << 2 | r.e[2] << 1 | r.e[3]);
+}
+
+// ------------------------------------------------- blocked hashed tables
+//
+// The occupancy tables (fine cells, and coarse cells of twice the edge) are
+// hashed by blocks: a cell's 2x2x2x2 block (cell index / 2 per axis) picks a
+// 16-byte line of the table -- the top lg - 4 bits of (pair's cell base +
+// the block's linear id) * HASH_MUL -- and the low bit of each cell index
+// the byte in it.  Neighbouring cells thus share cache lines, so that the
+// marks and tests of a wave touch few lines; two cells share a hashed index
+// only when their blocks' hashes collide.  bs: linear-id strides of the
+// blocks of the table's grid.
+
+// Hashed index of cell c (coordinates on the table's grid).
+MS_D uint32_t blocked_index(const int64_t c[4], const uint64_t bs[4], uint64_t cb, int lg)
+{
+    uint64_t lin = 0;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) lin += (uint64_t)(c[d] >> 1) * bs[d];
+    const uint32_t par = (uint32_t)((c[0] & 1) << 3 | (c[1] & 1) << 2 | (c[2] & 1) << 1 | (c[3] & 1));
+    return hash_of_product((cb + lin) * HASH_MUL, lg - 4) << 4 | par;
+}
+
+// The 16 positions of a small range in Gray-code order (each step moves one
+// axis by one cell): step k visits position k ^ (k >> 1).
+template <int K>
+struct GrayStep {
+    static constexpr int b = K ^ (K >> 1);
+    static constexpr int flip = K == 0 ? 0 : b ^ ((K - 1) ^ ((K - 1) >> 1));
+    static constexpr int axis = flip == 8 ? 0 : flip == 4 ? 1 : flip == 2 ? 2 : 3;
+    static constexpr bool up = (b & flip) != 0;
+};
+
+// Walk over the positions of a small range u: the hash product of the
+// current block and the parity bits of the range's lowest cell.  Moving up
+// along axis d enters the next block only from an odd cell index, so the
+// per-axis steps of the product are bh[d] or 0 per range.
+struct BlockWalk {
+    uint64_t p;
+    uint64_t up[4], dn[4];
+    uint32_t par0;
+};
+
+MS_D void walk_init(BlockWalk &w, const Range32 &u, const uint64_t bs[4], const uint64_t bh[4], uint64_t cb)
+{
+    uint64_t lin = 0;
+    w.par0 = 0;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        lin += (uint64_t)(u.lo[d] >> 1) * bs[d];
+        const bool odd = (u.lo[d] & 1) != 0;
+        w.up[d] = odd ? bh[d] : 0ull;
+        w.dn[d] = odd ? 0ull - bh[d] : 0ull;
+        w.par0 |= (uint32_t)(u.lo[d] & 1) << (3 - d);
+    }
+    w.p = (cb + lin) * HASH_MUL;
+}
+
+template <int K>
+MS_D uint32_t walk_index(BlockWalk &w, int lg)
+{
+    if constexpr (K > 0) w.p += GrayStep<K>::up ? w.up[GrayStep<K>::axis] : w.dn[GrayStep<K>::axis];
+    return hash_of_product(w.p, lg - 4) << 4 | (w.par0 ^ (uint32_t)GrayStep<K>::b);
+}
+
+// A side's occupancy table inside the byte region at base: the table at
+// base + off (2^lg bytes).  The same for a bit table of 2^lg bits at w.
+struct TabRef {
+    uint8_t *base;
+    uint32_t off;
+    int lg;
+};
+
+struct BitRef {
+    const uint32_t *w;
+    int lg;
+};
+
+// Marks (value v) the cells of the small range u whose positions are in m.
+template <int... Ks>
+MS_D void mark_walk(const TabRef &t, BlockWalk w, uint32_t m, uint8_t v, std::integer_sequence<int, Ks...>)
+{
+    ((void)[&] {
+        const uint32_t i = walk_index<Ks>(w, t.lg);
+        if ((m >> GrayStep<Ks>::b) & 1u) t.base[t.off + i] = v;
+    }(), ...);
+}
+
+// Both-occupied bits of the cells of the small range u whose positions are
+// in m, as a mask over the positions (bit b for position b); the loads are
+// independent, so they are in flight together.
+template <int... Ks>
+MS_D uint32_t bits_walk(const BitRef &t, BlockWalk w, uint32_t m, std::integer_sequence<int, Ks...>)
+{
+    uint32_t r = 0;
+    ((void)[&] {
+        const uint32_t i = walk_index<Ks>(w, t.lg);
+        if ((m >> GrayStep<Ks>::b) & 1u) r |= ((t.w[i >> 5] >> (i & 31)) & 1u) << GrayStep<Ks>::b;
+    }(), ...);
+    return r;
+}
+
+// The cells of a range of any size, in lexicographic order, with their
+// coordinates (Range32 form).
+template <typename F>
+MS_D void for_cells32(const Range32 &r, F &&f)
+{
+    int64_t c[4];
+    for (c[0] = r.lo[0]; c[0] <= r.lo[0] + r.e[0]; ++c[0])
+        for (c[1] = r.lo[1]; c[1] <= r.lo[1] + r.e[1]; ++c[1])
+            for (c[2] = r.lo[2]; c[2] <= r.lo[2] + r.e[2]; ++c[2])
+                for (c[3] = r.lo[3]; c[3] <= r.lo[3] + r.e[3]; ++c[3]) f(c);
+}
+
+// The positions of a small range r inside its own extent.
+MS_D uint32_t range_positions(const Range32 &r)
+{
+    const uint32_t nem = ~extent_mask(r);
     uint32_t m = 0;
 #pragma unroll
-    for (int j = 0; j < MLP_CELLS; ++j) m |= v[j] << j;
+    for (int b = 0; b < 16; ++b) m |= (uint32_t)((b & nem) == 0) << b;
     return m;
+}
+
+// Marks every cell of range r (any size).
+MS_D void mark_range(const TabRef &t, const Range32 &r, const uint64_t bs[4], const uint64_t bh[4], uint64_t cb,
+                     uint8_t v)
+{
+    if (range_small(r)) {
+        BlockWalk w;
+        walk_init(w, r, bs, bh, cb);
+        mark_walk(t, w, range_positions(r), v, std::make_integer_sequence<int, 16>{});
+        return;
+    }
+    for_cells32(r, [&](const int64_t *c) { t.base[t.off + blocked_index(c, bs, cb, t.lg)] = v; });
+}
+
+// Number of cells of range r whose both-occupied bit is set (any range).
+MS_D uint32_t count_both(const BitRef &t, const Range32 &r, const uint64_t bs[4], const uint64_t bh[4], uint64_t cb)
+{
+    if (range_small(r)) {
+        BlockWalk w;
+        walk_init(w, r, bs, bh, cb);
+        return (uint32_t)__builtin_popcount(bits_walk(t, w, range_positions(r), std::make_integer_sequence<int, 16>{}));
+    }
+    uint32_t n = 0;
+    for_cells32(r, [&](const int64_t *c) { n += occ_bit(t.w, blocked_index(c, bs, cb, t.lg)); });
+    return n;
 }
 
 // Compact cell range: lo cell per axis in 12 bits (bits 0..47), extent per
@@ -244,25 +443,47 @@ MS_D void unpack_range(uint64_t v, CellRange &r)
     }
 }
 
-// Where triangle gt lives: pair, side, local index.
-struct TriLoc {
+MS_D const MeshView &side_mesh(const PairDesc &P, int side) { return side ? P.B : P.A; }
+
+// Where a triangle tile lives: pair, side, its first local triangle and the
+// side's triangle count.  Every value is the same for the whole block.
+struct TileLoc {
     int p, side;
-    int32_t t;
+    int32_t t0, n;
 };
 
-template <bool ONE>
-MS_D TriLoc locate(const BatchView &bv, int64_t gt)
+// The pair of a batch tile, found by all threads of the block at once (a
+// block-wide call); the pair of a single search is 0.
+template <bool ONE, int NT = BLOCK>
+MS_D int tile_pair_search(const BatchView &bv, int64_t tile, int *s_p)
 {
-    TriLoc L;
-    L.p = pair_of_tri<ONE>(bv, gt);
-    const PairDesc &P = pair_desc<ONE>(bv, L.p);
-    int64_t local = gt - P.tri_off;
-    L.side = local >= P.nA;
-    L.t = (int32_t)(L.side ? local - P.nA : local);
-    return L;
+    if constexpr (ONE) {
+        return 0;
+    } else {
+        __syncthreads();          // the previous search's result is no longer read
+        for (int p = threadIdx.x; p < bv.n_pairs; p += NT)
+            if (bv.tile_off[p] <= tile && tile < bv.tile_off[p + 1]) *s_p = p;
+        __syncthreads();
+        return __builtin_amdgcn_readfirstlane(*s_p);
+    }
 }
 
-MS_D const MeshView &side_mesh(const PairDesc &P, int side) { return side ? P.B : P.A; }
+// Location of tile `tile` given a pair p with tile_off[p] <= tile (the pairs
+// after p are stepped through, empty ones included).
+template <bool ONE>
+MS_D TileLoc tile_loc(const BatchView &bv, int64_t tile, int p)
+{
+    TileLoc L;
+    if constexpr (!ONE)
+        while (bv.tile_off[p + 1] <= tile) ++p;
+    const PairDesc &P = pair_desc<ONE>(bv, p);
+    const int64_t lt = tile - P.tile_off;
+    L.p = p;
+    L.side = lt >= P.tilesA;
+    L.t0 = (int32_t)((L.side ? lt - P.tilesA : lt) * TILE_TRIS);
+    L.n = L.side ? P.nB : P.nA;
+    return L;
+}
 
 // Cell range of triangle t (global index gt) from its compact record, or from
 // its vertices when the range did not pack.
@@ -277,11 +498,57 @@ MS_D bool range_at(const uint64_t *rng, int64_t gt, const MeshView &m, int32_t t
     return tri_cells(m, t, g, r);
 }
 
-template <bool ONE>
-MS_D bool range_of(const BatchView &bv, const uint64_t *rng, int64_t gt, const TriLoc &L, CellRange &r)
+
+MS_D uint64_t pack_range32(const Range32 &r, bool packable)
 {
-    const PairDesc &P = pair_desc<ONE>(bv, L.p);
-    return range_at(rng, gt, side_mesh(P, L.side), L.t, P.g, r);
+    if (!packable || (r.e[0] | r.e[1] | r.e[2] | r.e[3]) > 15) return RNG_FROM_BOX;
+    return (uint64_t)r.lo[0] | (uint64_t)r.lo[1] << 12 | (uint64_t)r.lo[2] << 24 | (uint64_t)r.lo[3] << 36 |
+           (uint64_t)r.e[0] << 48 | (uint64_t)r.e[1] << 52 | (uint64_t)r.e[2] << 56 | (uint64_t)r.e[3] << 60;
+}
+
+MS_D void unpack_range32(uint64_t v, Range32 &r)
+{
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        r.lo[d] = (int32_t)((v >> (12 * d)) & 4095);
+        r.e[d] = (int32_t)((v >> (48 + 4 * d)) & 15);
+    }
+}
+
+// Cell range of triangle t of mesh m on grid P (32-bit form), or false for a
+// non-finite triangle.
+MS_D bool tri_range32(const MeshView &m, int32_t t, const PairDesc &P, Range32 &r)
+{
+    double lo[4], hi[4];
+    if (!tri_box_d(m, t, lo, hi)) return false;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        r.lo[d] = cell_of32(lo[d], P.g.wlo[d], P.g.inv, P.nm1[d]);
+        r.e[d] = cell_of32(hi[d], P.g.wlo[d], P.g.inv, P.nm1[d]) - r.lo[d];
+    }
+    return true;
+}
+
+// The same from the compact record written by k_mark, or from the vertices
+// when the range did not pack.
+MS_D bool range32_at(const uint64_t *rng, int64_t gt, const MeshView &m, int32_t t, const PairDesc &P, Range32 &r)
+{
+    const uint64_t v = rng[gt];
+    if (v == RNG_NONFINITE) return false;
+    if (v != RNG_FROM_BOX) {
+        unpack_range32(v, r);
+        return true;
+    }
+    return tri_range32(m, t, P, r);
+}
+
+// Logical block index that gives each XCD a contiguous run of the grid's
+// blocks (workgroups are dealt to the 8 XCDs in turn, so block b runs on XCD
+// b mod 8): neighbouring tiles, which share vertex rows, then share an L2.
+MS_D int64_t xcd_block(int64_t b, int64_t nb)
+{
+    if (nb % 8 != 0) return b;
+    return (b % 8) * (nb / 8) + b / 8;
 }
 
 // Decoupled look-back over 64-bit status words [flag:2 | value:62] of the
@@ -409,11 +676,111 @@ __global__ void __launch_bounds__(BLOCK) k_prepare(ClearSpec c)
 // adds work but never changes a result.
 MS_D uint8_t epoch_value(const uint64_t *epoch) { return (uint8_t)(*epoch % 255u + 1u); }
 
+// ---------------------------------------------------------------- quad tiles
+//
+// k_mark and k_keys give each thread one quad of the vertex grid, i.e. both
+// its triangles: T1 = (W(i+1,k), W(i,k), W(i,k+1)) and T2 = (W(i,k+1),
+// W(i+1,k+1), W(i+1,k)) share the vertices W(i+1,k) and W(i,k+1).  The cell
+// map is monotone, so a triangle's cell range is the min / max of its
+// vertices' cells: each of the four vertices is converted once.
+
+// Positions b of a small range (bit 3 - d of b = offset along axis d) whose
+// offset along axis d is 1.
+MS_D uint32_t axis_one(int d) { return d == 0 ? 0xFF00u : d == 1 ? 0xF0F0u : d == 2 ? 0xCCCCu : 0xAAAAu; }
+
+// The positions of the range u (range_small) that lie in triangle range r.
+MS_D uint32_t position_mask(const Range32 &u, const Range32 &r)
+{
+    uint32_t m = 0xFFFFu;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        if (r.lo[d] != u.lo[d]) m &= axis_one(d);                // offset 0 not covered
+        if (r.lo[d] + r.e[d] == u.lo[d]) m &= ~axis_one(d);     // offset 1 not covered
+    }
+    return m;
+}
+
+// Smallest range holding both ranges.
+MS_D Range32 range_union(const Range32 &a, const Range32 &b)
+{
+    Range32 u;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        u.lo[d] = min(a.lo[d], b.lo[d]);
+        u.e[d] = max(a.lo[d] + a.e[d], b.lo[d] + b.e[d]) - u.lo[d];
+    }
+    return u;
+}
+
+// Marks, in one pass over the 16 positions of their union, the cells of the
+// quad's finite triangles (ok1, ok2); a union wider than two cells on some
+// axis marks each triangle on its own.
+MS_D void mark_quad(const TabRef &t, const Range32 &r1, bool ok1, const Range32 &r2, bool ok2,
+                    const uint64_t bs[4], const uint64_t bh[4], uint64_t cb, uint8_t v)
+{
+    if (!ok1 && !ok2) return;
+    const Range32 u = ok1 && ok2 ? range_union(r1, r2) : (ok1 ? r1 : r2);
+    if (range_small(u)) {
+        const uint32_t m = (ok1 ? position_mask(u, r1) : 0u) | (ok2 ? position_mask(u, r2) : 0u);
+        BlockWalk w;
+        walk_init(w, u, bs, bh, cb);
+        mark_walk(t, w, m, v, std::make_integer_sequence<int, 16>{});
+        return;
+    }
+    if (ok1) mark_range(t, r1, bs, bh, cb, v);
+    if (ok2) mark_range(t, r2, bs, bh, cb, v);
+}
+
+// Cells of the four vertices of a quad (a = W(i,k), b = W(i+1,k),
+// c = W(i,k+1), d = W(i+1,k+1)) and whether each vertex is finite.
+struct QuadVerts {
+    int32_t c[4][4];
+    bool fin[4];
+};
+
+MS_D void quad_vertices(const MeshView &m, int32_t q, const PairDesc &P, QuadVerts &qv)
+{
+    int32_t k, i;
+    quad_row_col(m, q, k, i);
+    int32_t i1 = i + 1;
+    if (i1 == m.n_theta_v) i1 = 0;
+    const int32_t r0 = k * m.n_theta_v, r1 = r0 + m.n_theta_v;
+    const int32_t id[4] = {r0 + i, r0 + i1, r1 + i, r1 + i1};
+    d4 x[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[j] = load_d4(m.V + 4 * (int64_t)id[j]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const double w[4] = {x[j].x, x[j].y, x[j].z, x[j].w};
+        qv.fin[j] = (int)isfinite(w[0]) & (int)isfinite(w[1]) & (int)isfinite(w[2]) & (int)isfinite(w[3]);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) qv.c[j][d] = cell_of32(w[d], P.g.wlo[d], P.g.inv, P.nm1[d]);
+    }
+}
+
+// The cell ranges of the quad's triangles T1 (vertices b, a, c) and T2
+// (c, d, b); ok1 / ok2: the triangle is finite.
+MS_D void quad_ranges(const QuadVerts &qv, Range32 &r1, bool &ok1, Range32 &r2, bool &ok2)
+{
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const int32_t mn = min(qv.c[1][d], qv.c[2][d]), mx = max(qv.c[1][d], qv.c[2][d]);
+        r1.lo[d] = min(mn, qv.c[0][d]);
+        r1.e[d] = max(mx, qv.c[0][d]) - r1.lo[d];
+        r2.lo[d] = min(mn, qv.c[3][d]);
+        r2.e[d] = max(mx, qv.c[3][d]) - r2.lo[d];
+    }
+    ok1 = qv.fin[0] & qv.fin[1] & qv.fin[2];
+    ok2 = qv.fin[1] & qv.fin[2] & qv.fin[3];
+}
+
 // Occupancy: one byte per hashed global cell and side, set with plain stores
-// (all writers store the same value).  Stores each triangle's compact cell
-// range and per-block entry / non-finite totals.  Block 0 also clears the
-// search's counters.
-template <bool ONE>
+// (all writers store the same value), fine and coarse.  Stores each
+// triangle's compact cell range and per-block entry / non-finite totals.
+// Block 0 also clears the search's counters.  One thread per quad; each
+// block takes a contiguous run of quad tiles, and the runs of neighbouring
+// blocks share an XCD (xcd_block).
+template <bool ONE, bool C32>
 __global__ void __launch_bounds__(BLOCK) k_mark(BatchView bv, uint8_t *flags, const uint64_t *epoch, uint64_t *rng,
                                                 unsigned long long *partial, ClearSpec c)
 {
@@ -425,37 +792,59 @@ __global__ void __launch_bounds__(BLOCK) k_mark(BatchView bv, uint8_t *flags, co
             for (int64_t i = threadIdx.x; i < c.n[k]; i += BLOCK) c.w[k][i] = 0;
     }
     const uint8_t v = epoch_value(epoch);
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     unsigned long long all = 0, bad = 0;
-    const size_t side_bytes = (size_t)1 << bv.bm_log2;
-    for (int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gt < bv.n_tri; gt += stride) {
-        TriLoc L = locate<ONE>(bv, gt);
+    const int lg = bv.bm_log2, lc = bv.bc_log2;
+    const int64_t ntiles = bv.n_tiles;
+    const int64_t per = ceil_div(ntiles, gridDim.x);
+    const int64_t t0 = xcd_block(blockIdx.x, gridDim.x) * per;
+    const int64_t t1 = t0 + per < ntiles ? t0 + per : ntiles;
+    __shared__ int s_p;
+    int p = t0 < t1 ? tile_pair_search<ONE>(bv, t0, &s_p) : 0;
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const TileLoc L = tile_loc<ONE>(bv, tile, p);
+        p = L.p;
+        const int32_t q = (L.t0 >> 1) + (int32_t)threadIdx.x;
+        if (2 * q >= L.n) continue;
+        const int64_t g = tile * TILE_TRIS + 2 * (int64_t)threadIdx.x;
         const PairDesc &P = pair_desc<ONE>(bv, L.p);
-        CellRange r;
-        if (!tri_cells(side_mesh(P, L.side), L.t, P.g, r)) {
-            ++bad;
-            rng[gt] = RNG_NONFINITE;
-            continue;
-        }
-        rng[gt] = pack_range(r, bv.packable != 0);
-        all += (unsigned long long)range_count(r);
-        uint8_t *mine = flags + (size_t)L.side * side_bytes;
-        uint8_t *cmine = flags + 2 * side_bytes + ((size_t)L.side << bv.bc_log2);
-        const uint64_t cb = P.cell_base;
-        const int64_t *n = P.g.n;
-        const int64_t nc1 = (n[1] + 1) >> 1, nc2 = (n[2] + 1) >> 1, nc3 = (n[3] + 1) >> 1;
-        // each fine cell and its coarse cell (index / 2 per axis; a coarse
-        // cell shared by several fine cells is simply marked again)
-        for (int64_t c0 = r.lo[0]; c0 <= r.hi[0]; ++c0)
-            for (int64_t c1 = r.lo[1]; c1 <= r.hi[1]; ++c1)
-                for (int64_t c2 = r.lo[2]; c2 <= r.hi[2]; ++c2) {
-                    const int64_t fb = ((c0 * n[1] + c1) * n[2] + c2) * n[3];
-                    const int64_t cbz = (((c0 >> 1) * nc1 + (c1 >> 1)) * nc2 + (c2 >> 1)) * nc3;
-                    for (int64_t c3 = r.lo[3]; c3 <= r.hi[3]; ++c3) {
-                        mine[bm_hash(cb + (uint64_t)(fb + c3), bv.bm_log2)] = v;
-                        cmine[bm_hash(cb + (uint64_t)(cbz + (c3 >> 1)), bv.bc_log2)] = v;
-                    }
+        const MeshView &m = side_mesh(P, L.side);
+        uint8_t *fine = flags + ((size_t)L.side << lg);
+        uint8_t *coarse = flags + ((size_t)2 << lg) + ((size_t)L.side << lc);
+        if constexpr (C32) {
+            QuadVerts qv;
+            quad_vertices(m, q, P, qv);
+            Range32 r1, r2;
+            bool ok1, ok2;
+            quad_ranges(qv, r1, ok1, r2, ok2);
+            ulonglong2 rr;
+            rr.x = ok1 ? pack_range32(r1, bv.packable != 0) : RNG_NONFINITE;
+            rr.y = ok2 ? pack_range32(r2, bv.packable != 0) : RNG_NONFINITE;
+            *reinterpret_cast<ulonglong2 *>(rng + g) = rr;
+            bad += (unsigned long long)(!ok1) + (unsigned long long)(!ok2);
+            if (ok1) all += (unsigned long long)((r1.e[0] + 1) * (r1.e[1] + 1)) * (unsigned long long)((r1.e[2] + 1) * (r1.e[3] + 1));
+            if (ok2) all += (unsigned long long)((r2.e[0] + 1) * (r2.e[1] + 1)) * (unsigned long long)((r2.e[2] + 1) * (r2.e[3] + 1));
+            mark_quad(TabRef{flags, (uint32_t)L.side << lg, lg}, r1, ok1, r2, ok2, P.fbs, P.fbh, P.cell_base, v);
+            mark_quad(TabRef{flags, ((uint32_t)2 << lg) + ((uint32_t)L.side << lc), lc}, coarse_range(r1), ok1,
+                      coarse_range(r2), ok2, P.cbs, P.cbh, P.cell_base, v);
+        } else {
+            // grids of 2^31 cells or more along an axis: 64-bit cells, one triangle at a time
+            const uint64_t cb = P.cell_base;
+            for (int h = 0; h < 2; ++h) {
+                CellRange r;
+                if (!tri_cells(m, 2 * q + h, P.g, r)) {
+                    ++bad;
+                    rng[g + h] = RNG_NONFINITE;
+                    continue;
                 }
+                rng[g + h] = RNG_FROM_BOX;
+                all += (unsigned long long)range_count(r);
+                for_cells_xy(r, P.g.n, [&](const int64_t *c, uint64_t) { fine[blocked_index(c, P.fbs, cb, lg)] = v; });
+                CellRange rc;
+                int64_t nc[4];
+                coarse_of(r, P.g.n, rc, nc);
+                for_cells_xy(rc, nc, [&](const int64_t *c, uint64_t) { coarse[blocked_index(c, P.cbs, cb, lc)] = v; });
+            }
+        }
     }
     all = block_sum(all, s_tmp);
     bad = block_sum(bad, s_tmp);
@@ -507,9 +896,19 @@ __global__ void __launch_bounds__(BLOCK) k_pack(const uint8_t *flags, const uint
     }
 }
 
+// Whether any coarse cell of the range is occupied by both meshes (a
+// triangle whose coarse neighbourhood holds no cell of the other mesh has no
+// entry at all).
+MS_D bool coarse_any(const BatchView &bv, const uint32_t *cboth, const PairDesc &P, const Range32 &rc)
+{
+    return count_both(BitRef{cboth, bv.bc_log2}, rc, P.cbs, P.cbh, P.cell_base) != 0;
+}
+
 struct KeysOut {
     uint64_t *ent;                // [cell | side | triangle]
     int32_t *epair;               // pair of the entry (batch)
+    uint32_t *erank;              // rank of the entry among its group's entries of its side
+    uint32_t *ehash;              // the entry's hashed cell (its group)
     int64_t cap;
     unsigned long long *n_keys;   // entries reserved (cleared)
     uint32_t *grp;                // per hashed cell h: [2 h] A entries, [2 h + 1] B entries
@@ -519,53 +918,80 @@ struct KeysOut {
 
 // Entries of each triangle: the cells of its range whose hashed cell both
 // meshes occupy (a cell holding one mesh only cannot hold a pair), after the
-// same test on the coarse cells.  Each block counts the entries of its
-// KEYS_TILE triangles, reserves that many output slots with one atomic add
-// (blocks without entries take none) and writes the entries; every stored
-// entry is counted in its group and side, and leaves its cell as the
-// group's sample.
-template <bool ONE>
-__global__ void __launch_bounds__(BLOCK) k_keys(BatchView bv, const uint32_t *both, const uint64_t *rng, KeysOut o)
+// same test on the coarse cells.  One thread per triangle (KEYS_BLOCK =
+// TILE_TRIS threads: one tile per block).  Each block counts the entries of
+// its tile, reserves that many output slots with one atomic add (blocks
+// without entries take none) and writes the entries; every stored entry is
+// counted in its group and side (its rank there is kept for the placement,
+// its hashed cell with it), and leaves its cell as the group's sample.  One
+// block more than the tiles sums k_mark's per-block totals and clears the
+// enumeration's counter lines, beside the others.
+constexpr int KEYS_BLOCK = TILE_TRIS;
+
+struct KeysTotals {
+    const unsigned long long *mark_partial;   // per k_mark block: entries, non-finite triangles
+    int n_mark_partial;
+    unsigned long long *shards;               // the enumeration's counter lines, cleared here
+};
+
+template <bool ONE, bool C32>
+__global__ void __launch_bounds__(KEYS_BLOCK) k_keys(BatchView bv, const uint32_t *both, const uint64_t *rng, KeysOut o,
+                                                     KeysTotals kt)
 {
-    __shared__ uint64_t s_tmp[BLOCK / WAVE];
+    __shared__ uint64_t s_tmp[KEYS_BLOCK / WAVE];
     __shared__ unsigned long long s_blk0;
-    const uint32_t *cboth = both + ((size_t)1 << bv.bm_log2) / 32;
-    const int64_t base = (int64_t)blockIdx.x * KEYS_TILE;
-    uint32_t cnt[KEYS_ITEMS], msk[KEYS_ITEMS];
-    uint32_t bigm = 0;
-    uint64_t mine = 0;
-#pragma unroll
-    for (int i = 0; i < KEYS_ITEMS; ++i) {
-        const int64_t gt = base + i * BLOCK + threadIdx.x;
-        uint32_t c = 0, m = 0;
-        if (gt < bv.n_tri) {
-            TriLoc L = locate<ONE>(bv, gt);
-            CellRange r;
-            if (range_of<ONE>(bv, rng, gt, L, r)) {
-                const PairDesc &P = pair_desc<ONE>(bv, L.p);
+    const int lg = bv.bm_log2, lc = bv.bc_log2;
+    const uint32_t *cboth = both + ((size_t)1 << lg) / 32;
+    const int64_t tile = blockIdx.x;
+    if (tile >= bv.n_tiles) {
+        if (tile == (bv.n_tiles > 0 ? bv.n_tiles : 1)) {
+            unsigned long long all = 0, bad = 0;
+            for (int i = threadIdx.x; i < kt.n_mark_partial; i += KEYS_BLOCK) {
+                all += kt.mark_partial[2 * i];
+                bad += kt.mark_partial[2 * i + 1];
+            }
+            all = block_sum<KEYS_BLOCK>(all, (unsigned long long *)s_tmp);
+            bad = block_sum<KEYS_BLOCK>(bad, (unsigned long long *)s_tmp);
+            if (threadIdx.x == 0) {
+                o.stats->n_entries_all = (int64_t)all;
+                o.stats->n_nonfinite = (int64_t)bad;
+            }
+            if (threadIdx.x < STAT_SHARDS * SHARD_WORDS) kt.shards[threadIdx.x] = 0;
+        }
+        return;
+    }
+    __shared__ int s_p;
+    const TileLoc L = tile_loc<ONE>(bv, tile, tile_pair_search<ONE, KEYS_BLOCK>(bv, tile, &s_p));
+    const int32_t t = L.t0 + (int32_t)threadIdx.x;
+    const int64_t g = tile * TILE_TRIS + threadIdx.x;
+    const PairDesc &P = pair_desc<ONE>(bv, L.p);
+    const MeshView &m = side_mesh(P, L.side);
+    const uint64_t cb = P.cell_base;
+    uint32_t cnt = 0;
+    Range32 r;
+    if (t < L.n) {
+        if constexpr (C32) {
+            if (range32_at(rng, g, m, t, P, r) && coarse_any(bv, cboth, P, coarse_range(r)))
+                cnt = count_both(BitRef{both, lg}, r, P.fbs, P.fbh, cb);
+        } else {
+            CellRange rr;
+            if (range_at(rng, g, m, t, P.g, rr)) {
                 CellRange rc;
                 int64_t nc[4];
-                coarse_of(r, P.g.n, rc, nc);
-                bool bigc;
-                const uint32_t mc = flag_mask(rc, nc, P.cell_base, cboth, bv.bc_log2, &bigc);
-                if (bigc || mc != 0) {
-                    bool big = false;
-                    m = flag_mask(r, P.g.n, P.cell_base, both, bv.bm_log2, &big);
-                    if (!big) {
-                        c = (uint32_t)__builtin_popcount(m);
-                    } else {
-                        bigm |= 1u << i;
-                        for_cells(r, P.g.n, [&](uint64_t cell) { c += occ_bit(both, bm_hash(P.cell_base + cell, bv.bm_log2)); });
-                    }
-                }
+                coarse_of(rr, P.g.n, rc, nc);
+                uint32_t any = 0;
+                for_cells_xy(rc, nc, [&](const int64_t *c, uint64_t) {
+                    any |= occ_bit(cboth, blocked_index(c, P.cbs, cb, lc));
+                });
+                if (any)
+                    for_cells_xy(rr, P.g.n, [&](const int64_t *c, uint64_t) {
+                        cnt += occ_bit(both, blocked_index(c, P.fbs, cb, lg));
+                    });
             }
         }
-        cnt[i] = c;
-        msk[i] = m;
-        mine += c;
     }
     uint64_t btotal;
-    const uint64_t texcl = block_excl(mine, s_tmp, &btotal);
+    const uint64_t texcl = block_excl<KEYS_BLOCK>((uint64_t)cnt, s_tmp, &btotal);
     if (btotal == 0) return;                      // uniform: every thread saw the same total
     if (threadIdx.x == 0) {
         const unsigned long long b0 = atomicAdd(o.n_keys, (unsigned long long)btotal);
@@ -573,39 +999,33 @@ __global__ void __launch_bounds__(BLOCK) k_keys(BatchView bv, const uint32_t *bo
         if ((int64_t)(b0 + btotal) > o.cap) atomicOr((unsigned long long *)&o.stats->overflow, 1ull);
     }
     __syncthreads();
+    if (cnt == 0) return;
     int64_t pos = (int64_t)(s_blk0 + texcl);
-#pragma unroll
-    for (int i = 0; i < KEYS_ITEMS; ++i) {
-        if (cnt[i] == 0) continue;
-        const int64_t gt = base + i * BLOCK + threadIdx.x;
-        TriLoc L = locate<ONE>(bv, gt);
-        CellRange r;
-        range_of<ONE>(bv, rng, gt, L, r);
-        const PairDesc &P = pair_desc<ONE>(bv, L.p);
-        const uint64_t cb = P.cell_base;
-        const uint64_t low = ((uint64_t)L.side << bv.kl.tb) | (uint64_t)L.t;
-        auto put = [&](uint64_t gc, uint32_t h) {
-            if (pos < o.cap) {      // only stored entries are counted in their group
-                atomicAdd(&o.grp[2 * (size_t)h + L.side], 1u);
-                o.own[h] = gc;
-                o.ent[pos] = (gc << bv.kl.cell_shift) | low;
-                if (!ONE) o.epair[pos] = L.p;
-            }
-            ++pos;
-        };
-        if (!(bigm >> i & 1)) {
-            const uint32_t m = msk[i];
-            int j = 0;
-            for_cells(r, P.g.n, [&](uint64_t cell) {
-                if (m >> j & 1) put(cb + cell, bm_hash(cb + cell, bv.bm_log2));
-                ++j;
-            });
-        } else {
-            for_cells(r, P.g.n, [&](uint64_t cell) {
-                const uint32_t h = bm_hash(cb + cell, bv.bm_log2);
-                if (occ_bit(both, h)) put(cb + cell, h);
-            });
+    const uint64_t low = ((uint64_t)L.side << bv.kl.tb) | (uint64_t)t;
+    auto put = [&](uint64_t gc, uint32_t hh) {
+        if (pos < o.cap) {      // only stored entries are counted in their group
+            o.erank[pos] = atomicAdd(&o.grp[2 * (size_t)hh + L.side], 1u);
+            o.ehash[pos] = hh;
+            o.own[hh] = gc;
+            o.ent[pos] = (gc << bv.kl.cell_shift) | low;
+            if (!ONE) o.epair[pos] = L.p;
         }
+        ++pos;
+    };
+    if constexpr (C32) {
+        for_cells32(r, [&](const int64_t *c) {
+            const uint32_t hh = blocked_index(c, P.fbs, cb, lg);
+            if (occ_bit(both, hh))
+                put(cb + (uint64_t)c[0] * P.st[0] + (uint64_t)c[1] * P.st[1] + (uint64_t)c[2] * P.st[2] + (uint64_t)c[3],
+                    hh);
+        });
+    } else {
+        CellRange rr;
+        range_at(rng, g, m, t, P.g, rr);
+        for_cells_xy(rr, P.g.n, [&](const int64_t *c, uint64_t cell) {
+            const uint32_t hh = blocked_index(c, P.fbs, cb, lg);
+            if (occ_bit(both, hh)) put(cb + cell, hh);
+        });
     }
 }
 
@@ -635,9 +1055,8 @@ MS_D int64_t lower_bound_u64(const uint64_t *a, int64_t lo, int64_t hi, uint64_t
 // GROUP_WORDS words of the both-occupied table.  Each group's counter word
 // becomes its two placement cursors: start (A entries) in the low half,
 // start + nA (B entries) in the high half; a group not kept gets the
-// cursors' high bits set.  Block 0 also gathers the totals of the keying
-// kernels.
-constexpr int GROUP_ITEMS = 4;                   // words of the fine table per thread
+// cursors' high bits set.
+constexpr int GROUP_ITEMS = 16;                  // words of the fine table per thread
 constexpr int GROUP_WORDS = BLOCK * GROUP_ITEMS;
 constexpr uint64_t GRP_DROP = 0x8000000080000000ull;
 
@@ -651,11 +1070,12 @@ struct GroupsOut {
     uint64_t *stat;           // 2 look-back words per tile (cleared)
     uint32_t *tile_ctr;       // (cleared)
     search_stats_t *stats;
-    const unsigned long long *n_keys;
-    const unsigned long long *mark_partial;
-    int n_mark_partial;
-    uint64_t *epoch;          // advanced here (the occupancy tables are no longer read)
 };
+
+// Tiles at most this many take their tile from the block index: every block
+// is then resident at once (one per CU suffices), so the look-back cannot wait
+// on a tile that never starts; more tiles take theirs from a counter.
+constexpr int GROUP_DIRECT_TILES = 256;
 
 __global__ void __launch_bounds__(BLOCK) k_groups(GroupsOut o)
 {
@@ -663,27 +1083,18 @@ __global__ void __launch_bounds__(BLOCK) k_groups(GroupsOut o)
     __shared__ uint64_t s_kbase, s_pbase;
     __shared__ uint32_t s_tile;
     const int64_t ntiles = (o.n_fwords + GROUP_WORDS - 1) / GROUP_WORDS;
-    if (blockIdx.x == 0) {
-        unsigned long long all = 0, bad = 0;
-        for (int i = threadIdx.x; i < o.n_mark_partial; i += BLOCK) {
-            all += o.mark_partial[2 * i];
-            bad += o.mark_partial[2 * i + 1];
+    const bool direct = ntiles <= GROUP_DIRECT_TILES;
+    for (int round = 0;; ++round) {
+        int64_t tile;
+        if (direct) {
+            if (round > 0) break;
+            tile = blockIdx.x;
+        } else {
+            if (threadIdx.x == 0) s_tile = atomicAdd(o.tile_ctr, 1u);
+            __syncthreads();
+            tile = s_tile;
+            __syncthreads();
         }
-        all = block_sum(all, (unsigned long long *)s_tk);
-        bad = block_sum(bad, (unsigned long long *)s_tp);
-        if (threadIdx.x == 0) {
-            *o.epoch += 1;
-            o.stats->n_entries = (int64_t)*o.n_keys;
-            o.stats->n_entries_all = (int64_t)all;
-            o.stats->n_nonfinite = (int64_t)bad;
-        }
-        __syncthreads();
-    }
-    for (;;) {
-        if (threadIdx.x == 0) s_tile = atomicAdd(o.tile_ctr, 1u);
-        __syncthreads();
-        const int64_t tile = s_tile;
-        __syncthreads();
         if (tile >= ntiles) break;
         const int64_t w0 = tile * GROUP_WORDS + (int64_t)threadIdx.x * GROUP_ITEMS;
         uint32_t m[GROUP_ITEMS];
@@ -765,36 +1176,61 @@ __global__ void __launch_bounds__(BLOCK) k_groups(GroupsOut o)
     }
 }
 
-// Entries to their group's range: the group's cursor of the entry's side
-// gives the position (A entries first).  Entries of groups holding one mesh
-// only are dropped.  An entry whose cell differs from its group's sample
-// flags the group as holding several cells.  When the next search's epoch
-// value wraps to 1, the occupancy tables are cleared here.
+// Entries to their group's range: the group's start for the entry's side
+// plus the entry's rank among them (A entries first), each with its
+// triangle's box (from the vertices), so that the enumeration reads the box
+// with the entry.  Entries of groups holding one mesh only are dropped.  An
+// entry whose cell differs from its group's sample flags the group as
+// holding several cells.  When the next search's epoch value wraps to 1,
+// the occupancy tables are cleared here.
 template <bool ONE>
-__global__ void __launch_bounds__(BLOCK) k_scatter(const uint64_t *ent, const int32_t *epair,
-                                                   const unsigned long long *n_keys, int64_t cap, uint32_t *grp,
-                                                   const uint64_t *own, uint32_t *mix, int bm_log2, int cell_shift,
-                                                   int tb, uint64_t *out, int32_t *opair, const uint64_t *epoch,
+__global__ void __launch_bounds__(BLOCK) k_scatter(BatchView bv, const uint64_t *ent, const int32_t *epair,
+                                                   const uint32_t *erank, const uint32_t *ehash,
+                                                   const unsigned long long *n_keys, int64_t cap,
+                                                   const uint32_t *grp, const uint64_t *own, uint32_t *mix,
+                                                   uint64_t *out, int32_t *opair, double *sbox, const uint64_t *epoch,
                                                    uint4 *flags, int64_t flag_vecs)
 {
     const uint64_t ep = *epoch;                 // (read early, used last)
     const int64_t nk = (int64_t)*n_keys;
     const int64_t n = nk < cap ? nk : cap;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int tb = bv.kl.tb;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const uint64_t e = ent[i];
-        const uint64_t gc = e >> cell_shift;
-        const uint32_t h = bm_hash(gc, bm_log2);
-        const uint32_t pos = atomicAdd(&grp[2 * (size_t)h + ((e >> tb) & 1)], 1u);
-        if (pos & 0x80000000u) continue;
+        const uint32_t r = erank[i];
+        const int p = ONE ? 0 : epair[i];
+        const uint64_t gc = e >> bv.kl.cell_shift;
+        const uint32_t h = ehash[i];
+        const int side = (int)((e >> tb) & 1);
+        const uint32_t c = grp[2 * (size_t)h + side];
+        double lo[4], hi[4];
+        const PairDesc &Pd = pair_desc<ONE>(bv, p);
+        tri_box_d(side_mesh(Pd, side), (int32_t)(e & bv.kl.tmask), lo, hi);
+        if (c & 0x80000000u) continue;
+        const uint32_t pos = c + r;
         out[pos] = e;
-        if (!ONE) opair[pos] = epair[i];
+        if (!ONE) opair[pos] = p;
+        double2 *b = reinterpret_cast<double2 *>(sbox + 8 * (size_t)pos);
+        b[0] = make_double2(lo[0], lo[1]);
+        b[1] = make_double2(lo[2], lo[3]);
+        b[2] = make_double2(hi[0], hi[1]);
+        b[3] = make_double2(hi[2], hi[3]);
         if (own[h] != gc) atomicOr(&mix[h], 1u);
     }
-    if (ep % 255u == 0) {
+    if ((ep + 1) % 255u == 0) {          // the next search's value wraps to 1 (k_finish advances the epoch)
         const uint4 z = make_uint4(0u, 0u, 0u, 0u);
         for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < flag_vecs; i += stride) flags[i] = z;
     }
+}
+
+// Box of grouped entry e (lo in [0..3], hi in [4..7]).
+MS_D void entry_box(const double *sbox, int64_t e, double lo[4], double hi[4])
+{
+    const double2 *b = reinterpret_cast<const double2 *>(sbox + 8 * e);
+    const double2 a0 = b[0], a1 = b[1], a2 = b[2], a3 = b[3];
+    lo[0] = a0.x; lo[1] = a0.y; lo[2] = a1.x; lo[3] = a1.y;
+    hi[0] = a2.x; hi[1] = a2.y; hi[2] = a3.x; hi[3] = a3.y;
 }
 
 MS_D void wave_count(bool p, int64_t *ctr)
@@ -957,8 +1393,8 @@ struct SlotOut {
 };
 
 template <bool ONE>
-MS_D SlotOut global_slot(const BatchView &bv, const uint64_t *keys, const int32_t *kpair, const CellRec *cells,
-                         const int64_t *pstart, int64_t ncells, int64_t slot)
+MS_D SlotOut global_slot(const BatchView &bv, const uint64_t *keys, const int32_t *kpair, const double *sbox,
+                         const CellRec *cells, const int64_t *pstart, int64_t ncells, int64_t slot)
 {
     SlotOut o;
     o.packed = 0;
@@ -969,9 +1405,9 @@ MS_D SlotOut global_slot(const BatchView &bv, const uint64_t *keys, const int32_
     const CellRec cr = cells[c];
     uint64_t iB, iA;
     split_slot((uint64_t)(slot - pstart[c]), (uint32_t)cr.nA, iB, iA);
-    const int64_t eA = cr.start + (int64_t)iA;
+    const int64_t eA = cr.start + (int64_t)iA, eB = cr.start + cr.nA + (int64_t)iB;
     const uint64_t kA = keys[eA];
-    const uint64_t kB = keys[cr.start + cr.nA + (int64_t)iB];
+    const uint64_t kB = keys[eB];
     const uint64_t ca = kA >> sh;
     const int32_t ta = (int32_t)(kA & bv.kl.tmask), tb = (int32_t)(kB & bv.kl.tmask);
     o.packed = ((uint64_t)(uint32_t)ta << 32) | (uint32_t)tb;
@@ -979,8 +1415,8 @@ MS_D SlotOut global_slot(const BatchView &bv, const uint64_t *keys, const int32_
     o.pr = entry_pair<ONE>(kpair, eA);
     const PairDesc &Pd = pair_desc<ONE>(bv, o.pr);
     double alo[4], ahi[4], blo[4], bhi[4];
-    tri_box(Pd.A, ta, alo, ahi);
-    tri_box(Pd.B, tb, blo, bhi);
+    entry_box(sbox, eA, alo, ahi);
+    entry_box(sbox, eB, blo, bhi);
     o.keep = enum_pair<ONE>(Pd, ca - Pd.cell_base, alo, ahi, blo, bhi);
     return o;
 }
@@ -989,10 +1425,11 @@ constexpr int ENUM_PSTART = 4096;   // slot offsets kept in LDS when the groups 
 
 template <bool ONE>
 __global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_t *keys, const int32_t *kpair,
-                                                const CellRec *cells, const int64_t *pstart_g, const int64_t *kept,
+                                                const double *sbox, const CellRec *cells, const int64_t *pstart_g, const int64_t *kept,
                                                 const uint32_t *mix,
                                                 search_stats_t *stats, uint64_t *cand, int32_t *cand_pair,
-                                                int64_t cand_cap, hit_t *hits, uint64_t *hkeys, int64_t hits_cap)
+                                                int64_t cand_cap, hit_t *hits, uint64_t *hkeys, int64_t hits_cap,
+                                                unsigned long long *epart)
 {
     __shared__ int64_t s_pstart[ENUM_PSTART + 1];
     // the staged boxes during enumeration (component-major, so that lanes
@@ -1023,6 +1460,10 @@ __global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_
     __shared__ double s_gb[8][ENUM_CELLS];            // per staged group: t-bounds of its cell
     __shared__ double s_gw[ONE ? 1 : 5][ENUM_CELLS];  // per staged group: wlo, inv (batch)
     unsigned long long xc = 0, xs = 0;      // exact cells and slots
+    // the block's counts (thread 0), added at its end to one of STAT_SHARDS
+    // counter lines (block index mod STAT_SHARDS): same-line atomics of
+    // hundreds of blocks would serialise; k_finish sums the lines
+    unsigned long long b_cand = 0, b_moller = 0, b_degen = 0, b_outside = 0, b_unstaged = 0;
     const int64_t ncells = kept[0];
     const int64_t P = kept[1];
     const int64_t nchunks = ceil_div(P, ENUM_SLOTS);
@@ -1083,7 +1524,7 @@ __global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_
         uint32_t tot;
         const uint32_t off = block_excl<ENUM_BLOCK>(need, s_kscan, &tot);
         const bool staged = nc <= ENUM_CELLS && tot <= ENUM_STAGE;
-        if (!staged && threadIdx.x == 0) atomicAdd((unsigned long long *)&stats->n_chunks_unstaged, 1ull);
+        if (!staged && threadIdx.x == 0) ++b_unstaged;
         if (staged) {
             if (threadIdx.x < nc) {
                 s_aoff[threadIdx.x] = (int32_t)off;
@@ -1104,9 +1545,8 @@ __global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_
                 const uint64_t key = keys[e];
                 const int32_t t = (int32_t)(key & bv.kl.tmask);
                 const int p = entry_pair<ONE>(kpair, e);
-                const PairDesc &Pd = pair_desc<ONE>(bv, p);
                 double blo[4], bhi[4];
-                tri_box(isB ? Pd.B : Pd.A, t, blo, bhi);
+                entry_box(sbox, e, blo, bhi);
 #pragma unroll
                 for (int d = 0; d < 4; ++d) { s_box[d][i] = blo[d]; s_box[4 + d][i] = bhi[d]; }
                 s_t[i] = t;
@@ -1123,7 +1563,7 @@ __global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_
                 const PairDesc &Pd = pair_desc<ONE>(bv, ONE ? 0 : s_ep[i0]);
                 home_bounds(Pd.g, gc - Pd.cell_base, s_gb, threadIdx.x);
                 s_gcell[threadIdx.x] = gc;
-                if (!ONE) {
+                if constexpr (!ONE) {
 #pragma unroll
                     for (int d = 0; d < 4; ++d) s_gw[d][threadIdx.x] = Pd.g.wlo[d];
                     s_gw[4][threadIdx.x] = Pd.g.inv;
@@ -1184,8 +1624,14 @@ __global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_
 #pragma unroll
                                 for (int d = 0; d < 4; ++d) {
                                     const double m = alo[d] > blo[d] ? alo[d] : blo[d];
-                                    const double wl = ONE ? bv.p0.g.wlo[d] : s_gw[d][c];
-                                    const double iv = ONE ? bv.p0.g.inv : s_gw[4][c];
+                                    double wl, iv;
+                                    if constexpr (ONE) {
+                                        wl = bv.p0.g.wlo[d];
+                                        iv = bv.p0.g.inv;
+                                    } else {
+                                        wl = s_gw[d][c];
+                                        iv = s_gw[4][c];
+                                    }
                                     const double t = (m - wl) * iv;
                                     in = in && (t >= s_gb[d][c]) && !(t >= s_gb[4 + d][c]);
                                 }
@@ -1197,7 +1643,7 @@ __global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_
                         }
                     }
                 } else {
-                    keep = global_slot<ONE>(bv, keys, kpair, cells, pstart, ncells, slot).keep != 0;
+                    keep = global_slot<ONE>(bv, keys, kpair, sbox, cells, pstart, ncells, slot).keep != 0;
                 }
             }
             keepm |= (uint32_t)keep << j;
@@ -1212,7 +1658,7 @@ __global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_
             unsigned long long b = 0;
             if (ktot) {
                 if (cand) b = atomicAdd((unsigned long long *)&stats->n_cand, (unsigned long long)ktot);
-                else atomicAdd((unsigned long long *)&stats->n_cand, (unsigned long long)ktot);
+                else b_cand += ktot;
             }
             s_kbase = b;
         }
@@ -1230,7 +1676,7 @@ __global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_
                     packed = ((uint64_t)(uint32_t)s_t[q.ia] << 32) | (uint32_t)s_t[q.ib];
                     pr = ONE ? 0 : s_ep[q.ia];
                 } else {
-                    const SlotOut so = global_slot<ONE>(bv, keys, kpair, cells, pstart, ncells, slot);
+                    const SlotOut so = global_slot<ONE>(bv, keys, kpair, sbox, cells, pstart, ncells, slot);
                     packed = so.packed;
                     pr = so.pr;
                 }
@@ -1288,9 +1734,9 @@ __global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_
             }
             const uint32_t sm = block_sum<ENUM_BLOCK>(nm, s_kscan), sd = block_sum<ENUM_BLOCK>(nd, s_kscan), so = block_sum<ENUM_BLOCK>(no, s_kscan);
             if (threadIdx.x == 0) {
-                if (sm) atomicAdd((unsigned long long *)&stats->n_moller, (unsigned long long)sm);
-                if (sd) atomicAdd((unsigned long long *)&stats->n_degenerate, (unsigned long long)sd);
-                if (so) atomicAdd((unsigned long long *)&stats->n_outside, (unsigned long long)so);
+                b_moller += sm;
+                b_degen += sd;
+                b_outside += so;
             }
         }
         // exact statistics of the groups that start in this chunk: a group of
@@ -1325,11 +1771,14 @@ __global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_
         }
         __syncthreads();
     }
+    }
     const unsigned long long sc = block_sum<ENUM_BLOCK>(xc, s_st), ss = block_sum<ENUM_BLOCK>(xs, s_st);
     if (threadIdx.x == 0) {
-        if (sc) atomicAdd((unsigned long long *)&stats->n_cells, sc);
-        if (ss) atomicAdd((unsigned long long *)&stats->n_slots, ss);
-    }
+        unsigned long long *w = epart + SHARD_WORDS * (blockIdx.x % STAT_SHARDS);
+        const unsigned long long c[7] = {b_cand, b_moller, b_degen, b_outside, sc, ss, b_unstaged};
+#pragma unroll
+        for (int k = 0; k < 7; ++k)
+            if (c[k]) atomicAdd(w + k, c[k]);
     }
 }
 
@@ -1345,23 +1794,56 @@ __global__ void __launch_bounds__(BLOCK) k_hits_place(const hit_t *tmp, const ui
     }
 }
 
-// At most HITS_TINY hits: one block ranks every key by counting the smaller
-// ones (the keys are distinct) and places key and record together.
+// The end of a search, one block: the enumeration's counter lines summed
+// into the statistics, the epoch advanced (the occupancy tables of this
+// search are no longer read), and, for a hit capacity of at most HITS_TINY,
+// the hits ranked by counting the smaller keys (the keys are distinct) and
+// placed, key and record together.
 constexpr int HITS_TINY = 1024;
+constexpr int FIN_BLOCK = 256;
 
-__global__ void __launch_bounds__(BLOCK) k_hits_tiny(const hit_t *tmp, uint64_t *keys, const int64_t *n_dev,
-                                                     int64_t cap, hit_t *out)
+struct FinishArgs {
+    search_stats_t *stats;
+    uint64_t *epoch;
+    const unsigned long long *n_keys;
+    const unsigned long long *shards;
+    int tiny;                  // sort the hits here
+    const hit_t *tmp;
+    uint64_t *keys;
+    int64_t cap;
+    hit_t *out;
+};
+
+__global__ void __launch_bounds__(FIN_BLOCK) k_finish(FinishArgs a)
 {
     __shared__ uint64_t s_k[HITS_TINY];
-    const int n = (int)(*n_dev < cap ? *n_dev : cap);
-    for (int i = threadIdx.x; i < n; i += BLOCK) s_k[i] = keys[i];
+    if (threadIdx.x < 7) {
+        unsigned long long v = 0;
+        for (int i = 0; i < STAT_SHARDS; ++i) v += a.shards[SHARD_WORDS * i + threadIdx.x];
+        search_stats_t *st = a.stats;
+        switch (threadIdx.x) {
+        case 0: st->n_cand += (int64_t)v; break;
+        case 1: st->n_moller = (int64_t)v; break;
+        case 2: st->n_degenerate = (int64_t)v; break;
+        case 3: st->n_outside = (int64_t)v; break;
+        case 4: st->n_cells = (int64_t)v; break;
+        case 5: st->n_slots = (int64_t)v; break;
+        default: st->n_chunks_unstaged = (int64_t)v; break;
+        }
+    } else if (threadIdx.x == 7) {
+        *a.epoch += 1;
+        a.stats->n_entries = (int64_t)*a.n_keys;
+    }
+    if (!a.tiny) return;
+    const int n = (int)(a.stats->n_hits < a.cap ? a.stats->n_hits : a.cap);
+    for (int i = threadIdx.x; i < n; i += FIN_BLOCK) s_k[i] = a.keys[i];
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += BLOCK) {
+    for (int i = threadIdx.x; i < n; i += FIN_BLOCK) {
         const uint64_t k = s_k[i];
         int r = 0;
         for (int j = 0; j < n; ++j) r += s_k[j] < k;
-        keys[r] = k;
-        out[r] = tmp[i];
+        a.keys[r] = k;
+        a.out[r] = a.tmp[i];
     }
 }
 
@@ -1455,17 +1937,18 @@ __global__ void __launch_bounds__(BLOCK) k_count_all(PairDesc pd, unsigned long 
 // ------------------------------------------------------------- host side
 
 struct Geometry {
-    int64_t n_pairs, n_tri, max_nA, max_nB;
+    int64_t n_pairs, n_tri, n_tiles, max_nA, max_nB;
     int tb, tbA, tbB, pb;
     int cell_bits;
     int bm_log2, bc_log2;
-    int packable;
+    int packable, c32;
     uint64_t total_cells;
 };
 
 struct Layout {
     int64_t ent_cap, cand_cap, hits_cap;
-    size_t o_epoch, o_flags, o_both, o_grp, o_own, o_mix, o_gstat, o_ctrs, o_part, o_rng, o_ent, o_epair, o_sorted, o_spair,
+    size_t o_epoch, o_flags, o_both, o_grp, o_own, o_mix, o_gstat, o_ctrs, o_part, o_epart, o_rng, o_ent, o_epair, o_erank, o_ehash, o_sorted,
+        o_spair, o_sbox,
         o_cells, o_pstart, o_htmp, o_hkeys, o_halt, o_misc, o_desc, o_toff, o_cbase, total;
     int64_t n_kblocks, cell_cap, n_fwords, n_cwords, n_gtiles;
 };
@@ -1493,6 +1976,7 @@ int geometry(int64_t n_pairs, const ms_mesh *const *A, const ms_mesh *const *B, 
     memset(&G, 0, sizeof G);
     G.n_pairs = n_pairs;
     G.packable = 1;
+    G.c32 = 1;
     unsigned __int128 total = 0;
     for (int64_t i = 0; i < n_pairs; ++i) {
         if (!A[i] || !B[i]) return fail(MS_E_ARG, "search: NULL mesh");
@@ -1501,10 +1985,13 @@ int geometry(int64_t n_pairs, const ms_mesh *const *A, const ms_mesh *const *B, 
         if (rc) return rc;
         total += c;
         G.n_tri += (int64_t)A[i]->view.n_tris + B[i]->view.n_tris;
+        G.n_tiles += ceil_div(A[i]->view.n_tris, TILE_TRIS) + ceil_div(B[i]->view.n_tris, TILE_TRIS);
         if (A[i]->view.n_tris > G.max_nA) G.max_nA = A[i]->view.n_tris;
         if (B[i]->view.n_tris > G.max_nB) G.max_nB = B[i]->view.n_tris;
-        for (int d = 0; d < 4; ++d)
+        for (int d = 0; d < 4; ++d) {
             if (prm[i].n_cells[d] > 4096) G.packable = 0;
+            if (prm[i].n_cells[d] > (int64_t)0x7fffffff) G.c32 = 0;
+        }
     }
     if (total > ((unsigned __int128)1 << 62)) return fail(MS_E_KEYBITS, "search: the grids have more than 2^62 cells");
     G.total_cells = (uint64_t)total;
@@ -1537,7 +2024,7 @@ void layout(const Geometry &G, Layout &L)
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
     const int64_t n_ids = (int64_t)1 << G.bm_log2;       // groups: fine hashed cells
-    L.n_kblocks = ceil_div(G.n_tri > 0 ? G.n_tri : 1, KEYS_TILE);
+    L.n_kblocks = G.n_tiles > 0 ? G.n_tiles : 1;
     L.cell_cap = L.ent_cap / 2 + 1;
     L.n_fwords = n_ids / 32;
     L.n_cwords = ((int64_t)1 << G.bc_log2) / 32;
@@ -1551,11 +2038,15 @@ void layout(const Geometry &G, Layout &L)
     L.o_gstat = take((size_t)L.n_gtiles * 16);
     L.o_ctrs = take(64);
     L.o_part = take((size_t)MAX_GRID * 16);
-    L.o_rng = take((size_t)(G.n_tri + 1) * 8);
+    L.o_epart = take((size_t)STAT_SHARDS * SHARD_WORDS * 8);
+    L.o_rng = take((size_t)(G.n_tiles * TILE_TRIS + 1) * 8);
     L.o_ent = take((size_t)(L.ent_cap + 1) * 8);
     L.o_epair = take((size_t)(L.ent_cap + 1) * 4);
+    L.o_erank = take((size_t)(L.ent_cap + 1) * 4);
+    L.o_ehash = take((size_t)(L.ent_cap + 1) * 4);
     L.o_sorted = take((size_t)(L.ent_cap + 1) * 8);
     L.o_spair = take((size_t)(L.ent_cap + 1) * 4);
+    L.o_sbox = take((size_t)(L.ent_cap + 1) * 64);
     L.o_cells = take((size_t)L.cell_cap * sizeof(CellRec));
     L.o_pstart = take((size_t)(L.cell_cap + 1) * 8);
     L.o_htmp = take((size_t)(L.hits_cap > 0 ? L.hits_cap : 1) * sizeof(hit_t));
@@ -1587,7 +2078,7 @@ bool fit_entries(const Geometry &G, Layout &L, size_t ws_bytes)
     return true;
 }
 
-PairDesc make_desc(const ms_mesh *A, const ms_mesh *B, const search_params_t *p, uint64_t cell_base, int64_t tri_off)
+PairDesc make_desc(const ms_mesh *A, const ms_mesh *B, const search_params_t *p, uint64_t cell_base, int64_t tile_off)
 {
     PairDesc d;
     memset(&d, 0, sizeof d);
@@ -1596,9 +2087,31 @@ PairDesc make_desc(const ms_mesh *A, const ms_mesh *B, const search_params_t *p,
     for (int k = 0; k < 4; ++k) { d.g.wlo[k] = p->world_lo[k]; d.g.n[k] = p->n_cells[k]; }
     d.g.inv = p->inv_edge;
     d.cell_base = cell_base;
-    d.tri_off = tri_off;
+    d.tile_off = tile_off;
     d.nA = A->view.n_tris;
     d.nB = B->view.n_tris;
+    d.tilesA = (int32_t)ceil_div(d.nA, TILE_TRIS);
+    const uint64_t n1 = (uint64_t)p->n_cells[1], n2 = (uint64_t)p->n_cells[2], n3 = (uint64_t)p->n_cells[3];
+    d.st[0] = n1 * n2 * n3;
+    d.st[1] = n2 * n3;
+    d.st[2] = n3;
+    d.st[3] = 1;
+    // blocks of the fine table: (n + 1) / 2 per axis; of the coarse table: (n + 3) / 4
+    const uint64_t f1 = (n1 + 1) >> 1, f2 = (n2 + 1) >> 1, f3 = (n3 + 1) >> 1;
+    const uint64_t c1 = (n1 + 3) >> 2, c2 = (n2 + 3) >> 2, c3 = (n3 + 3) >> 2;
+    d.fbs[0] = f1 * f2 * f3;
+    d.fbs[1] = f2 * f3;
+    d.fbs[2] = f3;
+    d.fbs[3] = 1;
+    d.cbs[0] = c1 * c2 * c3;
+    d.cbs[1] = c2 * c3;
+    d.cbs[2] = c3;
+    d.cbs[3] = 1;
+    for (int k = 0; k < 4; ++k) {
+        d.fbh[k] = d.fbs[k] * HASH_MUL;
+        d.cbh[k] = d.cbs[k] * HASH_MUL;
+        d.nm1[k] = (double)(p->n_cells[k] - 1);
+    }
     return d;
 }
 
@@ -1608,13 +2121,14 @@ BatchView make_view(const Geometry &G, const PairDesc &p0, char *ws, const Layou
     memset(&bv, 0, sizeof bv);
     bv.p0 = p0;
     bv.pairs = (const PairDesc *)(ws + L.o_desc);
-    bv.tri_off = (const int64_t *)(ws + L.o_toff);
+    bv.tile_off = (const int64_t *)(ws + L.o_toff);
     bv.cell_base = (const uint64_t *)(ws + L.o_cbase);
-    bv.n_tri = G.n_tri;
+    bv.n_tiles = G.n_tiles;
     bv.n_pairs = (int32_t)G.n_pairs;
     bv.bm_log2 = G.bm_log2;
     bv.bc_log2 = G.bc_log2;
     bv.packable = G.packable;
+    bv.c32 = G.c32;
     bv.pb = G.pb;
     bv.tbA = G.tbA;
     bv.tbB = G.tbB;
@@ -1640,11 +2154,15 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
     uint32_t *ctrs = (uint32_t *)(ws + L.o_ctrs);     // [1] k_groups tile counter
     unsigned long long *n_keys = (unsigned long long *)(ctrs + 4);   // entries reserved by k_keys
     unsigned long long *mpart = (unsigned long long *)(ws + L.o_part);
+    unsigned long long *epart = (unsigned long long *)(ws + L.o_epart);
     uint64_t *rng = (uint64_t *)(ws + L.o_rng);
     uint64_t *ent = (uint64_t *)(ws + L.o_ent);
     int32_t *epair = (int32_t *)(ws + L.o_epair);
+    uint32_t *erank = (uint32_t *)(ws + L.o_erank);
+    uint32_t *ehash = (uint32_t *)(ws + L.o_ehash);
     uint64_t *sorted = (uint64_t *)(ws + L.o_sorted);
     int32_t *spair = (int32_t *)(ws + L.o_spair);
+    double *sbox = (double *)(ws + L.o_sbox);
     CellRec *cells = (CellRec *)(ws + L.o_cells);
     int64_t *pstart = (int64_t *)(ws + L.o_pstart);
     hit_t *htmp = (hit_t *)(ws + L.o_htmp);
@@ -1661,19 +2179,32 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
     cs.n[0] = 2 * L.n_gtiles;
     cs.w[1] = (uint64_t *)ctrs;
     cs.n[1] = 8;
-    const unsigned g_tri = grid_for(G.n_tri);
-    MS_LAUNCH("k_mark", k_mark<ONE>, dim3(g_tri), dim3(BLOCK), 0, st, bv, flags, epoch, rng, mpart, cs);
+    const unsigned g_tri = (unsigned)(G.n_tiles < MAX_GRID ? (G.n_tiles > 0 ? G.n_tiles : 1) : MAX_GRID);
+    if (G.c32)
+        MS_LAUNCH("k_mark", (k_mark<ONE, true>), dim3(g_tri), dim3(BLOCK), 0, st, bv, flags, epoch, rng, mpart, cs);
+    else
+        MS_LAUNCH("k_mark", (k_mark<ONE, false>), dim3(g_tri), dim3(BLOCK), 0, st, bv, flags, epoch, rng, mpart, cs);
     MS_LAUNCH("k_pack", k_pack, dim3(grid_for(L.n_fwords + L.n_cwords, 4096)), dim3(BLOCK), 0, st, flags, epoch,
               G.bm_log2, G.bc_log2, both, grp, mix, L.n_fwords, L.n_cwords);
     KeysOut ko;
     ko.ent = ent;
     ko.epair = epair;
+    ko.erank = erank;
+    ko.ehash = ehash;
     ko.cap = L.ent_cap;
     ko.n_keys = n_keys;
     ko.grp = (uint32_t *)grp;
     ko.own = own;
     ko.stats = stats;
-    MS_LAUNCH("k_keys", k_keys<ONE>, dim3((unsigned)L.n_kblocks), dim3(BLOCK), 0, st, bv, both, rng, ko);
+    KeysTotals kt;
+    kt.mark_partial = mpart;
+    kt.n_mark_partial = (int)g_tri;
+    kt.shards = epart;
+    const unsigned n_kb = (unsigned)(G.n_tiles > 0 ? G.n_tiles : 1) + 1;   // + the totals block
+    if (G.c32)
+        MS_LAUNCH("k_keys", (k_keys<ONE, true>), dim3(n_kb), dim3(KEYS_BLOCK), 0, st, bv, both, rng, ko, kt);
+    else
+        MS_LAUNCH("k_keys", (k_keys<ONE, false>), dim3(n_kb), dim3(KEYS_BLOCK), 0, st, bv, both, rng, ko, kt);
     GroupsOut go;
     go.both = both;
     go.grp = grp;
@@ -1684,32 +2215,37 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
     go.stat = gstat;
     go.tile_ctr = ctrs + 1;
     go.stats = stats;
-    go.n_keys = n_keys;
-    go.mark_partial = mpart;
-    go.n_mark_partial = (int)g_tri;
-    go.epoch = epoch;
     MS_LAUNCH("k_groups", k_groups, dim3((unsigned)(L.n_gtiles < 1024 ? L.n_gtiles : 1024)), dim3(BLOCK), 0, st, go);
-    MS_LAUNCH("k_scatter", k_scatter<ONE>, dim3(grid_for(L.ent_cap)), dim3(BLOCK), 0, st, ent, epair, n_keys,
-              L.ent_cap, (uint32_t *)grp, own, mix, G.bm_log2, G.tb + 1, G.tb, sorted, spair, epoch, (uint4 *)flags,
+    static_assert(GROUP_DIRECT_TILES <= 1024, "a direct k_groups launch has one block per tile");
+    MS_LAUNCH("k_scatter", k_scatter<ONE>, dim3(grid_for(L.ent_cap, 1024)), dim3(BLOCK), 0, st, bv, ent, epair, erank,
+              ehash, n_keys, L.ent_cap, (uint32_t *)grp, own, mix, sorted, spair, sbox, epoch, (uint4 *)flags,
               (int64_t)(flag_bytes(G) / 16));
-    MS_LAUNCH("k_enum", k_enum<ONE>, dim3(ENUM_GRID), dim3(ENUM_BLOCK), 0, st, bv, sorted, spair, cells, pstart, misc + 1,
-              mix, stats, cand_user, (int32_t *)nullptr, cand_user ? cand_cap : (int64_t)0, htmp, hkeys, hits_cap);
+    MS_LAUNCH("k_enum", k_enum<ONE>, dim3(ENUM_GRID), dim3(ENUM_BLOCK), 0, st, bv, sorted, spair, sbox, cells, pstart,
+              misc + 1, mix, stats, cand_user, (int32_t *)nullptr, cand_user ? cand_cap : (int64_t)0, htmp, hkeys,
+              hits_cap, epart);
     MS_HIP(hipGetLastError());
-    if (hits_cap > 0) {
-        if (hits_cap <= HITS_TINY) {
-            MS_LAUNCH("k_hits_tiny", k_hits_tiny, dim3(1), dim3(BLOCK), 0, st, htmp, hkeys, &stats->n_hits, hits_cap,
-                      hits_dev);
-        } else {
-            if ((rc = sort_unique_small(hkeys, halt, hkeys, &stats->n_hits, hits_cap, 0, G.pb + G.tbA + G.tbB, st)))
-                return rc;
-            MS_LAUNCH("k_hits_place", k_hits_place, dim3(grid_for(hits_cap, 256)), dim3(BLOCK), 0, st, htmp, hkeys,
-                      &stats->n_hits, hits_cap, G.tbA, G.tbB, hits_dev);
-        }
-        if (pair_offs)
-            MS_LAUNCH("k_pair_offsets", k_pair_offsets, dim3(grid_for(G.n_pairs + 1, 64)), dim3(BLOCK), 0, st, hkeys,
-                               &stats->n_hits, hits_cap, (int)G.n_pairs, G.tbA + G.tbB, pair_offs);
-        MS_HIP(hipGetLastError());
+    const bool tiny = hits_cap > 0 && hits_cap <= HITS_TINY;
+    if (hits_cap > HITS_TINY) {
+        if ((rc = sort_unique_small(hkeys, halt, hkeys, &stats->n_hits, hits_cap, 0, G.pb + G.tbA + G.tbB, st)))
+            return rc;
+        MS_LAUNCH("k_hits_place", k_hits_place, dim3(grid_for(hits_cap, 256)), dim3(BLOCK), 0, st, htmp, hkeys,
+                  &stats->n_hits, hits_cap, G.tbA, G.tbB, hits_dev);
     }
+    FinishArgs fa;
+    fa.stats = stats;
+    fa.epoch = epoch;
+    fa.n_keys = n_keys;
+    fa.shards = epart;
+    fa.tiny = tiny ? 1 : 0;
+    fa.tmp = htmp;
+    fa.keys = hkeys;
+    fa.cap = hits_cap;
+    fa.out = hits_dev;
+    MS_LAUNCH("k_finish", k_finish, dim3(1), dim3(FIN_BLOCK), 0, st, fa);
+    if (hits_cap > 0 && pair_offs)
+        MS_LAUNCH("k_pair_offsets", k_pair_offsets, dim3(grid_for(G.n_pairs + 1, 64)), dim3(BLOCK), 0, st, hkeys,
+                  &stats->n_hits, hits_cap, (int)G.n_pairs, G.tbA + G.tbB, pair_offs);
+    MS_HIP(hipGetLastError());
     return MS_OK;
 }
 
@@ -1877,7 +2413,7 @@ extern "C" int narrow_allpairs(const ms_mesh *A, const ms_mesh *B, hit_t *hits_d
 struct ms_batch {
     ms::Geometry G;
     std::vector<ms::PairDesc> desc;
-    std::vector<int64_t> tri_off;
+    std::vector<int64_t> tile_off;
     std::vector<uint64_t> cell_base;
     int64_t ent_all;             // entries before filtering (workspace sizing)
     int64_t hits_cap, cand_cap;
@@ -1901,7 +2437,7 @@ int batch_upload(ms_batch *b, char *ws, const Layout &L, hipStream_t st)
 {
     const int64_t np = b->G.n_pairs;
     MS_HIP(hipMemcpyAsync(ws + L.o_desc, b->desc.data(), (size_t)np * sizeof(PairDesc), hipMemcpyHostToDevice, st));
-    MS_HIP(hipMemcpyAsync(ws + L.o_toff, b->tri_off.data(), (size_t)(np + 1) * 8, hipMemcpyHostToDevice, st));
+    MS_HIP(hipMemcpyAsync(ws + L.o_toff, b->tile_off.data(), (size_t)(np + 1) * 8, hipMemcpyHostToDevice, st));
     MS_HIP(hipMemcpyAsync(ws + L.o_cbase, b->cell_base.data(), (size_t)(np + 1) * 8, hipMemcpyHostToDevice, st));
     return MS_OK;
 }
@@ -1949,7 +2485,7 @@ int plan_batch(int32_t n_pairs, const ms_mesh *const *A, const ms_mesh *const *B
         if (e != hipSuccess) { delete b; return hip_fail(e, "hipStreamCreate"); }
     }
     b->desc.resize((size_t)n_pairs);
-    b->tri_off.resize((size_t)n_pairs + 1);
+    b->tile_off.resize((size_t)n_pairs + 1);
     b->cell_base.resize((size_t)n_pairs + 1);
     uint64_t cb = 0;
     int64_t to = 0;
@@ -1958,12 +2494,12 @@ int plan_batch(int32_t n_pairs, const ms_mesh *const *A, const ms_mesh *const *B
         pair_cells(&params[i], c);
         b->desc[(size_t)i] = make_desc(A[i], B[i], &params[i], cb, to);
         b->cell_base[(size_t)i] = cb;
-        b->tri_off[(size_t)i] = to;
+        b->tile_off[(size_t)i] = to;
         cb += c;
-        to += (int64_t)A[i]->view.n_tris + B[i]->view.n_tris;
+        to += ceil_div(A[i]->view.n_tris, TILE_TRIS) + ceil_div(B[i]->view.n_tris, TILE_TRIS);
     }
     b->cell_base[(size_t)n_pairs] = cb;
-    b->tri_off[(size_t)n_pairs] = to;
+    b->tile_off[(size_t)n_pairs] = to;
     int64_t E = 0;
     if (count && (rc = count_entries(n_pairs, A, B, params, (unsigned long long *)A[0]->counter, (hipStream_t)stream, E))) {
         batch_free(b);
@@ -2131,7 +2667,7 @@ extern "C" int search_intersections_batched(int32_t n_pairs, const ms_mesh *cons
             pair_cells(&per_pair[i], c);
             key[(size_t)i] = make_desc(A[i], B[i], &per_pair[i], cb, to);
             cb += c;
-            to += (int64_t)A[i]->view.n_tris + B[i]->view.n_tris;
+            to += ceil_div(A[i]->view.n_tris, TILE_TRIS) + ceil_div(B[i]->view.n_tris, TILE_TRIS);
         }
     }
     int dev = 0;
