@@ -234,6 +234,34 @@ int search_intersections_async(const ms_mesh *A, const ms_mesh *B, const search_
                                int64_t *cand_dev, int64_t cand_cap, void *stream);
 
 /*
+ * search_intersections_noalloc -- for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): search_intersections_async with no workspace argument.
+ * The workspace is a fixed device array inside the library,
+ * MS_NOALLOC_SCRATCH_BYTES per GPU, held from library load to process end;
+ * the call allocates nothing (no hipMalloc, no hipFree).  The caller still
+ * passes the outputs (hits, stats, candidates), as for the other searches.
+ *   - Every call on a GPU shares that GPU's array, which keeps the last
+ *     call's contents (results never depend on them; the counters the
+ *     search needs cleared are cleared by its first kernel).  Calls that
+ *     overlap on one GPU (other streams, other threads) race: serialise them.
+ *   - table_log2 = 0 picks the largest hashed table whose fixed part (tables,
+ *     per-triangle ranges, hit buffers) takes at most half of the array; the
+ *     rest holds the entries.  Returns MS_E_WORKSPACE, with the bytes needed
+ *     in last_error(), when the fixed part alone exceeds the array (meshes of
+ *     more than a few million triangles, or a large explicit table_log2 or
+ *     hits_cap).  Entries beyond the rest set stats_dev->overflow bit 0, like
+ *     the other asynchronous search; read it after the stream completes.
+ *   - Asynchronous (returns once queued); with MS_SEARCH_STRICT it first
+ *     waits for the meshes' statistics (mesh_info).  The first call on a
+ *     device looks up the array's device address (no allocation).
+ */
+#define MS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int search_intersections_noalloc(const ms_mesh *A, const ms_mesh *B, const search_params_t *params,
+                                 hit_t *hits_dev, int64_t hits_cap, search_stats_t *stats_dev,
+                                 int64_t *cand_dev, int64_t cand_cap, void *stream);
+
+/*
  * narrow_allpairs -- the full pair test (Moller, 4x4 solve, inclusion) on every
  * pair of A x B with no grid and no early exit (the box test is evaluated and
  * folded into the decision): the "tri-pair tests/s" workload.  Hits are

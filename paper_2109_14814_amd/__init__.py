@@ -23,7 +23,8 @@ MS_SEARCH_CANDIDATES, MS_SEARCH_STRICT = 1, 2
 
 # Exported entry points (the C ABI of include/msearch.h).
 EXPORTS = ("last_error", "mesh_build", "mesh_free", "mesh_info", "mesh_update", "search_default_params",
-           "search_workspace_size", "search_intersections", "search_intersections_async", "narrow_allpairs", "propagate_vertices",
+           "search_workspace_size", "search_intersections", "search_intersections_async",
+           "search_intersections_noalloc", "narrow_allpairs", "propagate_vertices",
            "search_profile_enable", "search_profile_read", "batch_create", "batch_search", "batch_needed",
            "batch_free", "search_batched_workspace_size", "search_intersections_batched", "refine_workspace_size", "refine_grad", "refine_newton", "layer_pairs",
            "half_layer_bounds", "half_layer_columns", "pertbp_map", "pertbp_map_stm", "theta_shift", "theta_interp", "theta_spectrum",
@@ -97,6 +98,8 @@ def lib():
         L.search_intersections.restype = C.c_int
         L.search_intersections_async.argtypes = [P, P, C.POINTER(SearchParams), P, C.c_size_t, P, I64, P, P, I64, P]
         L.search_intersections_async.restype = C.c_int
+        L.search_intersections_noalloc.argtypes = [P, P, C.POINTER(SearchParams), P, I64, P, P, I64, P]
+        L.search_intersections_noalloc.restype = C.c_int
         L.narrow_allpairs.argtypes = [P, P, P, I64, P, P, P]; L.narrow_allpairs.restype = C.c_int
         L.propagate_vertices.argtypes = [P, P, I64, C.POINTER(MapParams), P]
         L.propagate_vertices.restype = C.c_int
@@ -477,6 +480,18 @@ def search(A: Mesh, B: Mesh, params: SearchParams, hits_cap: int = 1 << 16, cand
     s = Searcher(A, B, params, hits_cap, cand_cap)
     s.run()
     return s.results()
+
+
+def search_noalloc(A: Mesh, B: Mesh, params: SearchParams, hits, stats, cand=None) -> None:
+    """Queue search_intersections_noalloc into caller-owned device buffers
+    (hits: hits_cap x 120 bytes, stats: 128 bytes, cand: optional int64
+    tensor); the library's fixed scratch is the workspace."""
+    hits_cap = hits.numel() * hits.element_size() // HIT_DTYPE.itemsize
+    cand_ptr = C.c_void_p(cand.data_ptr()) if cand is not None else None
+    cand_cap = cand.numel() if cand is not None else 0
+    _check(lib().search_intersections_noalloc(A.handle, B.handle, C.byref(params), C.c_void_p(hits.data_ptr()),
+                                              int(hits_cap), C.c_void_p(stats.data_ptr()), cand_ptr, int(cand_cap),
+                                              _stream()))
 
 
 class Batch:

@@ -2383,6 +2383,97 @@ extern "C" int search_intersections_async(const ms_mesh *A, const ms_mesh *B, co
                         stream, G, L, want_cand);
 }
 
+// ----------------------------------------------- search without allocation
+
+namespace ms {
+namespace {
+
+// The workspace of search_intersections_noalloc: one fixed array per GPU,
+// from library load to process end.  Host code never passes the array's
+// name to a kernel (on the host it is only a stand-in for the symbol): it
+// uses the device address that hipGetSymbolAddress returns for the current
+// device, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[MS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[SCRATCH_DEVICES];
+
+int scratch_address(void **out)
+{
+    int dev = 0;
+    MS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= SCRATCH_DEVICES) return fail(MS_E_ARG, "search_intersections_noalloc: device index too large");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(MS_E_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MS_OK;
+}
+
+// Size of a layout without entries (tables, per-triangle ranges, hit
+// buffers) for the table size in G.
+size_t fixed_bytes(const Geometry &G, int64_t hits_cap)
+{
+    Layout L;
+    memset(&L, 0, sizeof L);
+    L.hits_cap = hits_cap;
+    layout(G, L);
+    return L.total;
+}
+
+}  // namespace
+}  // namespace ms
+
+extern "C" int search_intersections_noalloc(const ms_mesh *A, const ms_mesh *B, const search_params_t *params,
+                                            hit_t *hits_dev, int64_t hits_cap, search_stats_t *stats_dev,
+                                            int64_t *cand_dev, int64_t cand_cap, void *stream)
+{
+    if (!A || !B || !params || !stats_dev) return fail(MS_E_ARG, "search_intersections_noalloc: NULL argument");
+    if (hits_cap < 0 || cand_cap < 0) return fail(MS_E_ARG, "search_intersections_noalloc: negative capacity");
+    if (hits_cap > (int64_t)(MS_NOALLOC_SCRATCH_BYTES / sizeof(hit_t)))
+        return fail(MS_E_WORKSPACE, "search_intersections_noalloc: hits_cap does not fit the fixed scratch");
+    // The automatic hashed-table size is lowered until tables, per-triangle
+    // ranges and hit buffers take at most half of the scratch (the rest holds
+    // the entries); the results do not depend on the table size.
+    search_params_t p = *params;
+    if (p.table_log2 == 0) {
+        Geometry G;
+        int rc = geometry(1, &A, &B, &p, G);
+        if (rc) return rc;
+        int lg = G.bm_log2;
+        for (; lg > 12; --lg) {
+            G.bm_log2 = lg;
+            G.bc_log2 = lg - 3;
+            if (fixed_bytes(G, hits_cap) <= MS_NOALLOC_SCRATCH_BYTES / 2) break;
+        }
+        p.table_log2 = lg;
+    }
+    {
+        Geometry G;
+        int rc = geometry(1, &A, &B, &p, G);
+        if (rc) return rc;
+        const size_t need = fixed_bytes(G, hits_cap);
+        if (need > MS_NOALLOC_SCRATCH_BYTES)
+            return fail(MS_E_WORKSPACE, "search_intersections_noalloc: the meshes need " + std::to_string(need) +
+                                            " bytes of tables before any entry, above the fixed scratch of " +
+                                            std::to_string((size_t)MS_NOALLOC_SCRATCH_BYTES) + " bytes");
+    }
+    void *ws = nullptr;
+    int rc = scratch_address(&ws);
+    if (rc) return rc;
+    Geometry G;
+    Layout L;
+    bool want_cand = false;
+    return search_queue(A, B, &p, ws, MS_NOALLOC_SCRATCH_BYTES, hits_dev, hits_cap, stats_dev, cand_dev, cand_cap,
+                        nullptr, stream, G, L, want_cand);
+}
+
 extern "C" int narrow_allpairs(const ms_mesh *A, const ms_mesh *B, hit_t *hits_dev, int64_t hits_cap,
                                int64_t *n_hits_dev, search_stats_t *stats_dev, void *stream)
 {
