@@ -57,36 +57,91 @@ def algorithmic_bytes(kernel: str, st: dict, mesh_sizes) -> float | None:
     return table.get(kernel)
 
 
-# FP64 flops per unit of work of the Runge-Kutta kernels, counted from the
-# algorithm (a multiply-add counts 2; each inverse square root counts its
-# seed and two Newton steps, 12): the stage sums of the 11-stage method
-# (39 non-zero a_ij, 5 non-zero b_i) over 4 state components are 396 flops
-# per step; the pulsating field is 50 per stage, the position-momentum field
-# 52; with 4 tangent columns the variational terms add 74 per stage and the
-# stage sums of the 16 tangent components 1584 per step.
+# FP64 flops per unit of work, counted from the method as written: every
+# add, subtract, multiply, divide and square root is one flop (a multiply-add
+# is two), whatever instructions the kernels spend on it.
+#   Runge-Kutta step: the stage sums of the 11-stage method (39 non-zero
+#   a_ij, 5 non-zero b_i) over 4 state components are 396 flops per step.
+#   Pulsating field (Sec. 3.2), per stage: the two offsets 2, y^2 1, the two
+#   squared distances 4, per primary r = sqrt(r^2), r^3 and m / r^3 4 (8),
+#   Omega_x 4, Omega_y 3, the two Coriolis rows 6: 28.
+#   Position-momentum field (Sec. 3.3), per stage: offsets 4, y^2 1, squared
+#   distances 4, m / r^3 per primary 8, the four rows 13: 30.
+#   Its variational terms with 4 tangent columns, per stage: 1 / r^2 and
+#   3 m / r^5 per primary 6, the Hessian entries 13 (a1 + a2 formed once),
+#   J Hess v 14 per column (56): 75; the stage sums of the 16 tangent
+#   components add 1584 per step.
+#   Triangle-pair test (Sec. 6.2.3-6.2.4), forced (no early exit): the
+#   Moller same-side test 39 each way (edges 6, normal 9, three signed
+#   distances 24), the 4x4 system 20 to form, 46 to eliminate (6 divisions)
+#   and 20 to back-substitute (4 divisions), inclusion 2: 166 per pair.
 FP64_PEAK_TFLOPS = 78.6
 RK_FLOPS = {
-    "k_rk8_map": 396 + 11 * 50,                      # per vertex-step: 946
-    "k_pm_flow<0>": 396 + 11 * 52,                   # per state-step: 968
-    "k_pm_flow<4>": 396 + 11 * 52 + 11 * 74 + 1584,  # per state-step with DF: 3366
+    "k_rk8_map": 396 + 11 * 28,                      # per vertex-step: 704
+    "k_pm_flow<0>": 396 + 11 * 30,                   # per state-step: 726
+    "k_pm_flow<4>": 396 + 11 * 30 + 11 * 75 + 1584,  # per state-step with DF: 3135
 }
+PAIR_TEST_FLOPS = 166
+# Peak issue rate of FP64 vector instructions: a wave64 instruction occupies
+# a 16-lane SIMD for 4 cycles; 256 CUs x 4 SIMDs at 2.4 GHz.
+FP64_WAVE_INSTS_PER_S = 256 * 4 * 2.4e9 / 4
 
 SEARCH_SOURCES = ("mesh.hip", "small_sort.hip", "search.hip", "predicate.hpp", "ms_internal.hpp")
+# The sources each kernel family is built from (counters are valid only for these).
+SOURCE_GROUPS = {
+    "search": SEARCH_SOURCES,
+    "rk8": ("rk8.hip", "rk8_core.hpp", "ms_internal.hpp"),
+    "pertbp": ("pertbp.hip", "rk8.hip", "rk8_core.hpp", "ms_internal.hpp"),
+}
 
 
-def source_digest() -> str:
-    """Digest of the sources of the search kernels (the hardware counters in
+def source_digest(group: str = "search") -> str:
+    """Digest of the sources of a kernel family (the hardware counters in
     profiles/ are valid only for the sources they were taken on)."""
-    import glob
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2109_14814_amd", "csrc")
-    files = [os.path.join(csrc, f) for f in SEARCH_SOURCES]
-    for f in files:
+    for f in SOURCE_GROUPS[group]:
         h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+FP64_FILE = os.path.join(ROOT, "profiles", "fp64_valu_counters.txt")
+
+
+def fp64_counters(kernel: str) -> dict | None:
+    """Per-dispatch FP64 VALU instruction counts of `kernel` from the
+    committed rocprofv3 summary, or None when it is missing or was taken on
+    other sources."""
+    if not os.path.exists(FP64_FILE):
+        return None
+    cols = None
+    for line in open(FP64_FILE):
+        f = line.split()
+        if not f or f[0].startswith("#"):
+            continue
+        if f[0] == "kernel":
+            cols = f
+            continue
+        if cols and f[0] == kernel and len(f) == len(cols):
+            row = dict(zip(cols, f))
+            if row["digest"] != source_digest(row["group"]):
+                return None
+            return {k: float(v) for k, v in row.items() if k not in ("kernel", "group", "digest")}
+    return None
+
+
+def fp64_issue(kernel: str, launch_s: float) -> dict:
+    """Issue fraction of `kernel`: its FP64 VALU wave-instructions per
+    dispatch (counters) over what the chip can issue in the launch's
+    duration; None without valid counters."""
+    c = fp64_counters(kernel)
+    if c is None or launch_s <= 0:
+        return {"issue_frac": None, "fp64_insts_per_launch": None}
+    return {"issue_frac": round(c["fp64_insts"] / (launch_s * FP64_WAVE_INSTS_PER_S), 4),
+            "fp64_insts_per_launch": c["fp64_insts"]}
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "search_512x512_traffic.txt")
@@ -142,6 +197,83 @@ def measured_traffic(kernel: str) -> float | None:
     if digest != source_digest():
         return None
     return rows.get(kernel)
+
+
+def batch_roofline(ms, batch, pairs) -> dict:
+    """Dominant kernel of one batched search (launched without a graph, so
+    that every dispatch carries its own start / stop events): its
+    algorithmic bytes (the same table as the plain search, summed over the
+    batch's meshes and counts) over its dispatch duration."""
+    import torch
+    ms.profile_enable(True)
+    batch.run(False)
+    torch.cuda.synchronize()
+    rows = ms.profile_read()
+    ms.profile_enable(False)
+    per = {}
+    for name, t in rows:
+        per[name] = per.get(name, 0.0) + t
+    st = batch.stats_dict()
+    sizes = [(m.n_tris, len(m.theta) * len(m.s)) for pr in pairs for m in pr]
+    cands = [k for k in per if algorithmic_bytes(k, st, sizes) is not None]
+    dom = max(cands, key=per.get)
+    b = algorithmic_bytes(dom, st, sizes)
+    gbs = b / (per[dom] * 1e-3) / 1e9
+    return {"kernel": dom, "bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 5), "launch_ms": round(per[dom], 5), "bytes_per_launch": b,
+            "kernels_ms": {k: round(v, 5) for k, v in per.items()}}
+
+
+SQ_FILE = os.path.join(ROOT, "profiles", "search_512x512_sq_counters.txt")
+# 32-bit VALU lane operations per second without FMA or packed forms: 16 lanes
+# per SIMD per cycle, 4 SIMDs per CU, 256 CUs at 2.4 GHz.
+VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
+
+
+def sq_valu_per_dispatch(kernel: str) -> float | None:
+    """SQ_INSTS_VALU per dispatch of a search kernel from the committed
+    counter summary, or None when it is missing or was taken on other
+    sources."""
+    import re
+    if not os.path.exists(SQ_FILE):
+        return None
+    digest, rows = None, {}
+    for line in open(SQ_FILE):
+        f = line.split()
+        if "source_digest" in f:
+            digest = f[f.index("source_digest") + 1]
+        elif len(f) >= 4 and f[0].startswith("k_"):
+            try:
+                rows[re.sub(r"<.*>", "", f[0])] = float(f[2]) * float(f[3])
+            except ValueError:
+                pass
+    if digest != source_digest():
+        return None
+    return rows.get(kernel)
+
+
+def search_roofline(kernel: str, launch_ms: float, alg_bytes: float) -> dict:
+    """Roofline of the dominant search kernel against the unit its counters
+    show busiest: HBM (algorithmic bytes, and the measured traffic) or the
+    VALU issue rate (executed VALU instructions from the SQ counters: the
+    cell hashing and bit tests have no algorithmic flop count)."""
+    t = launch_ms * 1e-3
+    gbs = alg_bytes / t / 1e9
+    traffic = measured_traffic(kernel)
+    hbm = {"achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 5),
+           "traffic": traffic, "traffic_frac": round(traffic / t / 1e9 / HBM_PEAK_GBS, 5) if traffic else None}
+    valu = sq_valu_per_dispatch(kernel)
+    out = {"kernel": kernel, "avg_launch_ms": round(launch_ms, 6), "bytes_per_launch": alg_bytes,
+           "source_digest": source_digest()}
+    if valu is not None and valu * 64 / t / VALU_LANE_OPS_PER_S > max(hbm["frac"], hbm["traffic_frac"] or 0.0):
+        tops = valu * 64 / t / 1e12
+        out.update({"bound": "alu", "achieved": round(tops, 3), "peak": round(VALU_LANE_OPS_PER_S / 1e12, 2),
+                    "unit": "TOP/s", "frac": round(tops * 1e12 / VALU_LANE_OPS_PER_S, 4),
+                    "basis": "executed VALU lane operations (SQ_INSTS_VALU x 64, committed counters) per launch",
+                    "traffic": traffic, "hbm": hbm})
+    else:
+        out.update({"bound": "hbm", **hbm})
+    return out
 
 
 def time_search(ms, A, B, searcher, steps, warmup, profile=False):
@@ -219,13 +351,7 @@ def main():
     kern_total = {k: sum(v) / args.steps for k, v in kern.items()}
     dominant = max((k for k in kern_total if algorithmic_bytes(k, st, mesh_sizes) is not None),
                    key=lambda k: kern_total[k])
-    dom_ms = kern_avg[dominant]
-    dom_bytes = algorithmic_bytes(dominant, st, mesh_sizes)
-    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-    roofline = {"kernel": dominant, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(dominant),
-                "avg_launch_ms": round(dom_ms, 6), "bytes_per_launch": dom_bytes,
-                "source_digest": source_digest()}
+    roofline = search_roofline(dominant, kern_avg[dominant], algorithmic_bytes(dominant, st, mesh_sizes))
 
     out = {
         "metric": METRIC,
@@ -239,6 +365,7 @@ def main():
                                f"({A.n_tris} triangles each), FP64, seed {args.seed}",
                    "kappa": kappa, "world_cells": list(params.n_cells)},
         "ms_per_step_with_kernel_events": ms_step_prof,
+        "search_tris_per_s": (A.n_tris + B.n_tris) / (ms_step * 1e-3),
         "kappa_autotune_ms": sweep,
         "search_stats": st,
         "kernels_ms_avg": {k: round(v, 6) for k, v in kern_avg.items()},
@@ -265,6 +392,10 @@ def main():
         pairs0 = A0.n_tris * B0.n_tris
         out["allpairs_tests_per_s"] = pairs0 / t_ap
         out["allpairs_ms"] = t_ap * 1e3
+        tf = pairs0 * PAIR_TEST_FLOPS / t_ap / 1e12
+        leg_roof["k_allpairs"] = {"bound": "alu", "achieved": round(tf, 2), "peak": FP64_PEAK_TFLOPS,
+                                  "unit": "TFLOP/s", "frac": round(tf / FP64_PEAK_TFLOPS, 4),
+                                  "flops_per_pair": PAIR_TEST_FLOPS, **fp64_issue("k_allpairs", t_ap)}
         log(f"allpairs: {t_ap * 1e3:.3f} ms for {pairs0} pairs -> {pairs0 / t_ap:.3e} tests/s")
 
     # ------------------------------------- family: plain per-pair searches
@@ -303,6 +434,8 @@ def main():
         out["family_batched_over_plain"] = t_f / t_b
         out["family_batched_counts_equal_plain"] = bool(same)
         out["family_tris_total"] = int(sum(ga.n_tris + gb.n_tris for ga, gb in gp))
+        out["family_batched_tris_per_s"] = out["family_tris_total"] / t_b
+        leg_roof["family_batched"] = batch_roofline(ms, bt, gp)
         log(f"family: 256 plain searches in {t_f * 1e3:.2f} ms, batched graph {t_b * 1e3:.2f} ms, counts equal={same}")
         del bt, srch, gp
 
@@ -341,6 +474,7 @@ def main():
         out["layers_quad_pairs_per_s"] = quads / t_l
         out["layers_hits"] = int(lst["n_hits"])
         out["layers_counts_equal_plain"] = bool(same)
+        leg_roof["layers_batched"] = batch_roofline(ms, ls.batch, ls.meshes)
         log(f"layers: {len(ls.meshes)} half-layer pairs ({quads:.3e} quad pairs) batched in {t_l * 1e3:.2f} ms, "
             f"pair by pair {t_p * 1e3:.2f} ms, {lst['n_hits']} hits, counts equal={same}")
         del ls, srch, U, S
@@ -380,7 +514,7 @@ def main():
         tf = vsteps * RK_FLOPS["k_rk8_map"] / t_rk / 1e12
         leg_roof["k_rk8_map"] = {"bound": "alu", "achieved": round(tf, 2), "peak": FP64_PEAK_TFLOPS,
                                  "unit": "TFLOP/s", "frac": round(tf / FP64_PEAK_TFLOPS, 4),
-                                 "flops_per_vertex_step": RK_FLOPS["k_rk8_map"]}
+                                 "flops_per_vertex_step": RK_FLOPS["k_rk8_map"], **fp64_issue("k_rk8_map", t_rk / 2)}
         out["rk8_ms_F3_and_Fm3_two_patches"] = t_rk * 1e3
         out["propagated_search_ms_incl_setup"] = t_s * 1e3
         out["propagated_hits"] = int(len(hp))
@@ -410,7 +544,8 @@ def main():
         tf = vsteps * RK_FLOPS["k_pm_flow<0>"] / t_pm / 1e12
         leg_roof["k_pm_flow<0>"] = {"bound": "alu", "achieved": round(tf, 2), "peak": FP64_PEAK_TFLOPS,
                                     "unit": "TFLOP/s", "frac": round(tf / FP64_PEAK_TFLOPS, 4),
-                                    "flops_per_state_step": RK_FLOPS["k_pm_flow<0>"]}
+                                    "flops_per_state_step": RK_FLOPS["k_pm_flow<0>"],
+                                    **fp64_issue("k_pm_flow<0>", t_pm / 2)}
         out["pertbp_ms_F3_and_Fm3_two_patches"] = t_pm * 1e3
         n_stm = 1 << 18
         zst = zu[:n_stm].contiguous()
@@ -427,7 +562,8 @@ def main():
         tf = n_stm * STEPS * 3 * RK_FLOPS["k_pm_flow<4>"] / stm_t[4] / 1e12
         leg_roof["k_pm_flow<4>"] = {"bound": "alu", "achieved": round(tf, 2), "peak": FP64_PEAK_TFLOPS,
                                     "unit": "TFLOP/s", "frac": round(tf / FP64_PEAK_TFLOPS, 4),
-                                    "flops_per_state_step": RK_FLOPS["k_pm_flow<4>"]}
+                                    "flops_per_state_step": RK_FLOPS["k_pm_flow<4>"],
+                                    **fp64_issue("k_pm_flow<4>", stm_t[4])}
         out["pertbp_stm_ms_by_cols_per_thread"] = {str(k): v * 1e3 for k, v in stm_t.items()}
         log(f"pertbp: F^3 + F^-3 of 2 x {zu.shape[0]} states in {t_pm * 1e3:.1f} ms "
             f"({vsteps / t_pm:.3e} vertex-steps/s); DF^3 of {n_stm} states in "
