@@ -921,12 +921,15 @@ struct KeysOut {
 // same test on the coarse cells.  One thread per triangle (KEYS_BLOCK =
 // TILE_TRIS threads: one tile per block).  Each block counts the entries of
 // its tile, reserves that many output slots with one atomic add (blocks
-// without entries take none) and writes the entries; every stored entry is
-// counted in its group and side (its rank there is kept for the placement,
-// its hashed cell with it), and leaves its cell as the group's sample.  One
-// block more than the tiles sums k_mark's per-block totals and clears the
-// enumeration's counter lines, beside the others.
+// without entries take none) and writes the entries, listed in LDS first
+// when they are few enough, so that all threads write them together; every
+// stored entry is counted in its group and side (its rank there is kept for
+// the placement, its hashed cell with it), and the first of each side
+// leaves its cell as the group's sample.  One block more than the tiles
+// sums k_mark's per-block totals and clears the enumeration's counter
+// lines, beside the others.
 constexpr int KEYS_BLOCK = TILE_TRIS;
+constexpr int KEYS_STAGE = 2048;          // entries of a block staged in LDS (more: each thread writes its own)
 
 struct KeysTotals {
     const unsigned long long *mark_partial;   // per k_mark block: entries, non-finite triangles
@@ -940,6 +943,9 @@ __global__ void __launch_bounds__(KEYS_BLOCK) k_keys(BatchView bv, const uint32_
 {
     __shared__ uint64_t s_tmp[KEYS_BLOCK / WAVE];
     __shared__ unsigned long long s_blk0;
+    __shared__ uint32_t s_kh[KEYS_STAGE];     // staged entries: hashed cell, cell, thread
+    __shared__ uint64_t s_kc[KEYS_STAGE];
+    __shared__ uint16_t s_kt[KEYS_STAGE];
     const int lg = bv.bm_log2, lc = bv.bc_log2;
     const uint32_t *cboth = both + ((size_t)1 << lg) / 32;
     const int64_t tile = blockIdx.x;
@@ -999,14 +1005,64 @@ __global__ void __launch_bounds__(KEYS_BLOCK) k_keys(BatchView bv, const uint32_
         if ((int64_t)(b0 + btotal) > o.cap) atomicOr((unsigned long long *)&o.stats->overflow, 1ull);
     }
     __syncthreads();
-    if (cnt == 0) return;
-    int64_t pos = (int64_t)(s_blk0 + texcl);
-    const uint64_t low = ((uint64_t)L.side << bv.kl.tb) | (uint64_t)t;
-    auto put = [&](uint64_t gc, uint32_t hh) {
-        if (pos < o.cap) {      // only stored entries are counted in their group
-            o.erank[pos] = atomicAdd(&o.grp[2 * (size_t)hh + L.side], 1u);
+    const uint64_t blk0 = s_blk0;
+    if (btotal <= KEYS_STAGE) {
+        // the block's entries through LDS: each thread lists its own at its
+        // offset, then every thread takes every KEYS_BLOCK-th entry, so
+        // that the group counters are advanced by all threads at once and
+        // the entry stores are contiguous
+        if (cnt) {
+            uint32_t k = (uint32_t)texcl;
+            auto stage = [&](uint64_t gc, uint32_t hh) {
+                s_kh[k] = hh;
+                s_kc[k] = gc;
+                s_kt[k] = (uint16_t)threadIdx.x;
+                ++k;
+            };
+            if constexpr (C32) {
+                for_cells32(r, [&](const int64_t *c) {
+                    const uint32_t hh = blocked_index(c, P.fbs, cb, lg);
+                    if (occ_bit(both, hh))
+                        stage(cb + (uint64_t)c[0] * P.st[0] + (uint64_t)c[1] * P.st[1] + (uint64_t)c[2] * P.st[2] +
+                                  (uint64_t)c[3],
+                              hh);
+                });
+            } else {
+                CellRange rr;
+                range_at(rng, g, m, t, P.g, rr);
+                for_cells_xy(rr, P.g.n, [&](const int64_t *c, uint64_t cell) {
+                    const uint32_t hh = blocked_index(c, P.fbs, cb, lg);
+                    if (occ_bit(both, hh)) stage(cb + cell, hh);
+                });
+            }
+        }
+        __syncthreads();
+        const uint64_t side_bits = (uint64_t)L.side << bv.kl.tb;
+        for (uint32_t i = threadIdx.x; i < (uint32_t)btotal; i += KEYS_BLOCK) {
+            const int64_t pos = (int64_t)(blk0 + i);
+            if (pos >= o.cap) break;           // only stored entries are counted in their group
+            const uint32_t hh = s_kh[i];
+            const uint64_t gc = s_kc[i];
+            const uint32_t rank = atomicAdd(&o.grp[2 * (size_t)hh + L.side], 1u);
+            o.erank[pos] = rank;
             o.ehash[pos] = hh;
-            o.own[hh] = gc;
+            if (rank == 0) o.own[hh] = gc;     // the first entry of each side: the group's sample
+            o.ent[pos] = (gc << bv.kl.cell_shift) | side_bits | (uint64_t)(uint32_t)(L.t0 + s_kt[i]);
+            if (!ONE) o.epair[pos] = L.p;
+        }
+        return;
+    }
+    if (cnt == 0) return;
+    int64_t pos = (int64_t)(blk0 + texcl);
+    const uint64_t low = ((uint64_t)L.side << bv.kl.tb) | (uint64_t)t;
+    // only stored entries are counted in their group; the first entry of
+    // each side leaves its cell as the group's sample
+    auto put = [&](uint64_t gc, uint32_t hh) {
+        if (pos < o.cap) {
+            const uint32_t rank = atomicAdd(&o.grp[2 * (size_t)hh + L.side], 1u);
+            o.erank[pos] = rank;
+            o.ehash[pos] = hh;
+            if (rank == 0) o.own[hh] = gc;
             o.ent[pos] = (gc << bv.kl.cell_shift) | low;
             if (!ONE) o.epair[pos] = L.p;
         }
@@ -1058,6 +1114,8 @@ MS_D int64_t lower_bound_u64(const uint64_t *a, int64_t lo, int64_t hi, uint64_t
 // cursors' high bits set.
 constexpr int GROUP_ITEMS = 16;                  // words of the fine table per thread
 constexpr int GROUP_WORDS = BLOCK * GROUP_ITEMS;
+constexpr int GROUP_SEG = 8;                     // set bits per thread when the tile's are listed
+constexpr int GROUP_LIST = BLOCK * GROUP_SEG;
 constexpr uint64_t GRP_DROP = 0x8000000080000000ull;
 
 struct GroupsOut {
@@ -1079,9 +1137,10 @@ constexpr int GROUP_DIRECT_TILES = 256;
 
 __global__ void __launch_bounds__(BLOCK) k_groups(GroupsOut o)
 {
-    __shared__ uint64_t s_tk[BLOCK / WAVE], s_tp[BLOCK / WAVE];
+    __shared__ uint64_t s_tk[BLOCK / WAVE], s_tp[BLOCK / WAVE], s_tn[BLOCK / WAVE];
     __shared__ uint64_t s_kbase, s_pbase;
     __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_list[GROUP_LIST];
     const int64_t ntiles = (o.n_fwords + GROUP_WORDS - 1) / GROUP_WORDS;
     const bool direct = ntiles <= GROUP_DIRECT_TILES;
     for (int round = 0;; ++round) {
@@ -1099,15 +1158,54 @@ __global__ void __launch_bounds__(BLOCK) k_groups(GroupsOut o)
         const int64_t w0 = tile * GROUP_WORDS + (int64_t)threadIdx.x * GROUP_ITEMS;
         uint32_t m[GROUP_ITEMS];
         uint64_t kc = 0, pc = 0;     // (kept << 32) | entries; slots
+        uint32_t nb = 0;
 #pragma unroll
         for (int j = 0; j < GROUP_ITEMS; ++j) {
             m[j] = w0 + j < o.n_fwords ? o.both[w0 + j] : 0u;
-            for (uint32_t q = m[j]; q; q &= q - 1) {
-                const uint64_t v = o.grp[32 * (w0 + j) + __builtin_ctz(q)];
-                const uint64_t a = v & 0xffffffffull, b = v >> 32;
+            nb += (uint32_t)__builtin_popcount(m[j]);
+        }
+        // The tile's set bits, in order, split evenly over the threads
+        // (GROUP_SEG at most each), so that every thread issues the loads of
+        // its groups' counters together; a denser tile is walked word by
+        // word by each thread.
+        uint64_t nbt;
+        const uint64_t nboff = block_excl((uint64_t)nb, s_tn, &nbt);
+        const bool listed = nbt <= (uint64_t)GROUP_LIST;
+        uint32_t seg0 = 0, segn = 0;
+        uint32_t gh[GROUP_SEG];
+        uint64_t gv[GROUP_SEG];
+        if (listed) {
+            uint32_t k = (uint32_t)nboff;
+#pragma unroll
+            for (int j = 0; j < GROUP_ITEMS; ++j)
+                for (uint32_t q = m[j]; q; q &= q - 1) s_list[k++] = (uint32_t)(32 * (w0 + j)) + (uint32_t)__builtin_ctz(q);
+            __syncthreads();
+            const uint32_t per = ((uint32_t)nbt + BLOCK - 1) / BLOCK;
+            seg0 = threadIdx.x * per;
+            segn = seg0 < (uint32_t)nbt ? ((uint32_t)nbt - seg0 < per ? (uint32_t)nbt - seg0 : per) : 0u;
+#pragma unroll
+            for (int k2 = 0; k2 < GROUP_SEG; ++k2) {
+                gh[k2] = (uint32_t)k2 < segn ? s_list[seg0 + k2] : 0u;
+                gv[k2] = (uint32_t)k2 < segn ? o.grp[gh[k2]] : 0ull;
+            }
+#pragma unroll
+            for (int k2 = 0; k2 < GROUP_SEG; ++k2) {
+                const uint64_t a = gv[k2] & 0xffffffffull, b = gv[k2] >> 32;
                 if (a && b) {
                     kc += (1ull << 32) + a + b;
                     pc += a * b;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < GROUP_ITEMS; ++j) {
+                for (uint32_t q = m[j]; q; q &= q - 1) {
+                    const uint64_t v = o.grp[32 * (w0 + j) + __builtin_ctz(q)];
+                    const uint64_t a = v & 0xffffffffull, b = v >> 32;
+                    if (a && b) {
+                        kc += (1ull << 32) + a + b;
+                        pc += a * b;
+                    }
                 }
             }
         }
@@ -1148,29 +1246,37 @@ __global__ void __launch_bounds__(BLOCK) k_groups(GroupsOut o)
         }
         __syncthreads();
         uint64_t kr = s_kbase + kex, pr = s_pbase + pex;
-#pragma unroll
-        for (int j = 0; j < GROUP_ITEMS; ++j) {
-            for (uint32_t q = m[j]; q; q &= q - 1) {
-                const int64_t h = 32 * (w0 + j) + __builtin_ctz(q);
-                uint64_t *gw = o.grp + h;
-                const uint64_t v = *gw;
-                const uint64_t a = v & 0xffffffffull, b = v >> 32;
-                if (a && b) {
-                    const int64_t ki = (int64_t)(kr >> 32), start = (int64_t)(kr & 0xffffffffull);
-                    CellRec cr;
-                    cr.start = start;
-                    cr.nA = (int32_t)a;
-                    cr.nB = (int32_t)b;
-                    cr.h = h;
-                    o.cells[ki] = cr;
-                    o.pstart[ki] = (int64_t)pr;
-                    *gw = (((uint64_t)start + a) << 32) | (uint64_t)start;
-                    kr += (1ull << 32) + a + b;
-                    pr += a * b;
-                } else {
-                    *gw = GRP_DROP;
-                }
+        // each group's record and cursors, in the order of the scan
+        auto place = [&](int64_t h, uint64_t v) {
+            uint64_t *gw = o.grp + h;
+            const uint64_t a = v & 0xffffffffull, b = v >> 32;
+            if (a && b) {
+                const int64_t ki = (int64_t)(kr >> 32), start = (int64_t)(kr & 0xffffffffull);
+                CellRec cr;
+                cr.start = start;
+                cr.nA = (int32_t)a;
+                cr.nB = (int32_t)b;
+                cr.h = h;
+                o.cells[ki] = cr;
+                o.pstart[ki] = (int64_t)pr;
+                *gw = (((uint64_t)start + a) << 32) | (uint64_t)start;
+                kr += (1ull << 32) + a + b;
+                pr += a * b;
+            } else {
+                *gw = GRP_DROP;
             }
+        };
+        if (listed) {
+#pragma unroll
+            for (int k2 = 0; k2 < GROUP_SEG; ++k2)
+                if ((uint32_t)k2 < segn) place(gh[k2], gv[k2]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < GROUP_ITEMS; ++j)
+                for (uint32_t q = m[j]; q; q &= q - 1) {
+                    const int64_t h = 32 * (w0 + j) + __builtin_ctz(q);
+                    place(h, o.grp[h]);
+                }
         }
         __syncthreads();
     }
@@ -1394,14 +1500,17 @@ struct SlotOut {
 
 template <bool ONE>
 MS_D SlotOut global_slot(const BatchView &bv, const uint64_t *keys, const int32_t *kpair, const double *sbox,
-                         const CellRec *cells, const int64_t *pstart, int64_t ncells, int64_t slot)
+                         const CellRec *cells, const int64_t *pstart, int64_t c0, int64_t nc, const int64_t *s_pre,
+                         int64_t slot)
 {
     SlotOut o;
     o.packed = 0;
     o.pr = 0;
     o.keep = 0;
     const int sh = bv.kl.cell_shift;
-    const int64_t c = last_le<int64_t>(pstart, ncells, slot);
+    // the slot's group among the chunk's nc groups from c0: their slot
+    // starts in LDS (s_pre) when they are few, else in global memory
+    const int64_t c = s_pre ? c0 + last_le<int64_t>(s_pre, nc, slot) : c0 + last_le<int64_t>(pstart + c0, nc, slot);
     const CellRec cr = cells[c];
     uint64_t iB, iA;
     split_slot((uint64_t)(slot - pstart[c]), (uint32_t)cr.nA, iB, iA);
@@ -1419,6 +1528,44 @@ MS_D SlotOut global_slot(const BatchView &bv, const uint64_t *keys, const int32_
     entry_box(sbox, eB, blo, bhi);
     o.keep = enum_pair<ONE>(Pd, ca - Pd.cell_base, alo, ahi, blo, bhi);
     return o;
+}
+
+// For x0 <= x1, the last i0 and i1 in [0, n) with a[i] <= x (a ascending,
+// a[0] <= x0), found by the whole block at once: each round splits every
+// open range [lo, hi) into ENUM_BLOCK parts, one per thread, and keeps the
+// part where a[i] <= x stops holding (two loads per thread and round;
+// log_ENUM_BLOCK(n) rounds).  s_r[0..1] = [lo, hi) for x0, s_r[2..3] for x1;
+// the results are s_r[0] and s_r[2].  Ends with a barrier.
+MS_D void block_last_le2(const int64_t *a, int64_t n, int64_t x0, int64_t x1, int64_t *s_r)
+{
+    if (threadIdx.x == 0) {
+        s_r[0] = 0;
+        s_r[1] = n;
+        s_r[2] = 0;
+        s_r[3] = n;
+    }
+    __syncthreads();
+    for (;;) {
+        const int64_t lo0 = s_r[0], hi0 = s_r[1], lo1 = s_r[2], hi1 = s_r[3];
+        if (hi0 - lo0 <= 1 && hi1 - lo1 <= 1) break;
+        __syncthreads();      // every thread has read the ranges
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int64_t lo = k ? lo1 : lo0, hi = k ? hi1 : hi0, x = k ? x1 : x0;
+            if (hi - lo <= 1) continue;
+            const int64_t step = (hi - lo + ENUM_BLOCK - 1) / ENUM_BLOCK;
+            const int64_t i = lo + (int64_t)threadIdx.x * step;
+            if (i < hi && a[i] <= x) {
+                const int64_t j = i + step;
+                if (j >= hi || a[j] > x) {
+                    s_r[2 * k] = i;
+                    s_r[2 * k + 1] = j < hi ? j : hi;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    __syncthreads();
 }
 
 constexpr int ENUM_PSTART = 4096;   // slot offsets kept in LDS when the groups are this few
@@ -1452,6 +1599,7 @@ __global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_
     __shared__ int32_t s_aoff[ENUM_CELLS + 1], s_boff[ENUM_CELLS], s_ia0[ENUM_CELLS], s_ib0[ENUM_CELLS];
     __shared__ int32_t s_nA[ENUM_CELLS];
     __shared__ int64_t s_c0, s_c1;
+    __shared__ int64_t s_rng[4];
     __shared__ uint32_t s_kscan[ENUM_BLOCK / WAVE];
     __shared__ unsigned long long s_kbase;
     __shared__ unsigned long long s_st[ENUM_BLOCK / WAVE];
@@ -1486,13 +1634,17 @@ __global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_
                 if (a <= S1 - 1 && S1 - 1 < b) s_c1 = i;
             }
             if (threadIdx.x == 0) s_nmix = 0;
-        } else if (threadIdx.x == 0) {
-            s_c0 = last_le<int64_t>(pstart, ncells, S0);
-            s_c1 = last_le<int64_t>(pstart, ncells, S1 - 1);
-            s_nmix = 0;
+        } else {
+            block_last_le2(pstart, ncells, S0, S1 - 1, s_rng);
+            if (threadIdx.x == 0) {
+                s_c0 = s_rng[0];
+                s_c1 = s_rng[2];
+                s_nmix = 0;
+            }
         }
         __syncthreads();
         const int64_t c0 = s_c0, nc = s_c1 - s_c0 + 1;
+        const int64_t *pre_lds = nc <= ENUM_CELLS ? s_pre : nullptr;
         // the rows of every touched group that the chunk covers, and the entries they need
         uint32_t need = 0;
         bool first_here = false;     // the group's first slot is in this chunk (it is counted here)
@@ -1643,7 +1795,7 @@ __global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_
                         }
                     }
                 } else {
-                    keep = global_slot<ONE>(bv, keys, kpair, sbox, cells, pstart, ncells, slot).keep != 0;
+                    keep = global_slot<ONE>(bv, keys, kpair, sbox, cells, pstart, c0, nc, pre_lds, slot).keep != 0;
                 }
             }
             keepm |= (uint32_t)keep << j;
@@ -1676,7 +1828,7 @@ __global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_
                     packed = ((uint64_t)(uint32_t)s_t[q.ia] << 32) | (uint32_t)s_t[q.ib];
                     pr = ONE ? 0 : s_ep[q.ia];
                 } else {
-                    const SlotOut so = global_slot<ONE>(bv, keys, kpair, sbox, cells, pstart, ncells, slot);
+                    const SlotOut so = global_slot<ONE>(bv, keys, kpair, sbox, cells, pstart, c0, nc, pre_lds, slot);
                     packed = so.packed;
                     pr = so.pr;
                 }

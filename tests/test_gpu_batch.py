@@ -103,6 +103,11 @@ def test_batch_equals_plain_on_the_full_family(ms, kappa):
     assert st["n_cand"] == sum(p[1]["n_cand"] for p in plain)
     assert st["n_slots"] == sum(p[1]["n_slots"] for p in plain)
     assert st["n_cells"] == sum(p[1]["n_cells"] for p in plain)
+    if kappa == 1.0:
+        # more kept groups than the enumeration holds in LDS (its chunks find
+        # their groups by the block-wide search) and chunks that gather
+        # their entries from global memory
+        assert st["n_groups"] > 4096 and st["n_chunks_unstaged"] > 0
     # every pair against the oracle's grid search with the same grids
     n_slots = n_cells = 0
     for i, (a, b) in enumerate(fam):
