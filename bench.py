@@ -332,11 +332,12 @@ def main():
     mesh_sizes = [(A.n_tris, Am.verts.shape[0] * Am.verts.shape[1]), (B.n_tris, Bm.verts.shape[0] * Bm.verts.shape[1])]
     logical_pairs = A.n_tris * B.n_tris
     if args.kappa > 0:
-        kappa, params, sweep = args.kappa, ms.default_params(A, B, args.kappa), {}
+        kappa, params, sweep, tuned = args.kappa, ms.default_params(A, B, args.kappa), {}, None
     else:
-        kappa, params, sweep = ms.autotune_kappa(A, B, hits_cap=1 << 10)
-        sweep = {k: round(v, 5) for k, v in sweep.items()}
-        log(f"autotuned kappa {kappa}: " + ", ".join(f"{k}: {v:.4f} ms" for k, v in sweep.items()))
+        tuned, params, sweep = ms.autotune_kappa(A, B, hits_cap=1 << 10)
+        kappa = tuned["kappa"]
+        log(f"tuned ({tuned['cache']}): kappa {kappa}, table_log2 {tuned['table_log2']}, enum_shape "
+            f"{tuned['enum_shape']}" + "".join(f"; {k}: {v:.4f} ms" for k, v in sweep.items()))
     searcher = ms.Searcher(A, B, params, hits_cap=1 << 10, cand_cap=1 << 20)   # run() grows it if needed
     searcher.run()
     ms_step_prof, kern = time_search(ms, A, B, searcher, args.steps, args.warmup, profile=True)
@@ -363,10 +364,12 @@ def main():
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"plain search, two seeded torus surfaces of {args.n}x{args.n} quads "
                                f"({A.n_tris} triangles each), FP64, seed {args.seed}",
-                   "kappa": kappa, "world_cells": list(params.n_cells)},
+                   "kappa": kappa, "table_log2": params.table_log2, "enum_shape": params.enum_shape,
+                   "world_cells": list(params.n_cells)},
         "ms_per_step_with_kernel_events": ms_step_prof,
         "search_tris_per_s": (A.n_tris + B.n_tris) / (ms_step * 1e-3),
-        "kappa_autotune_ms": sweep,
+        "tuned": tuned,
+        "tune_sweep_ms": sweep,
         "search_stats": st,
         "kernels_ms_avg": {k: round(v, 6) for k, v in kern_avg.items()},
         "kernels_ms_per_step": {k: round(v, 6) for k, v in kern_total.items()},
@@ -402,8 +405,9 @@ def main():
     if "family" in legs:
         fam = synth.family(256, args.seed)
         gp = [(ms.Mesh.from_synth(a), ms.Mesh.from_synth(b)) for a, b in fam]
-        fkappa, fparams, fsweep = ms.autotune_batch_kappa(gp)
-        log(f"family: autotuned kappa {fkappa}: " + ", ".join(f"{k}: {v:.3f} ms" for k, v in fsweep.items()))
+        ftuned, fparams, fsweep = ms.autotune_batch_kappa(gp)
+        fkappa = ftuned["kappa"]
+        log(f"family: tuned ({ftuned['cache']}) {ftuned}" + "".join(f"; {k}: {v:.3f} ms" for k, v in fsweep.items()))
         srch = [ms.Searcher(ga, gb, p, hits_cap=1 << 12, cand_cap=1 << 18) for (ga, gb), p in zip(gp, fparams)]
         for s in srch:
             s.run()
@@ -427,6 +431,7 @@ def main():
         same = bst["overflow"] == 0 and all(bst[k] == sum(p[k] for p in plain_stats)
                                             for k in ("n_cand", "n_hits", "n_cells", "n_slots"))
         out["family_kappa"] = fkappa
+        out["family_tuned"] = ftuned
         out["family_plain_meshes_per_s"] = len(srch) / t_f
         out["family_plain_ms_total"] = t_f * 1e3
         out["family_batched_meshes_per_s"] = len(srch) / t_b
@@ -444,7 +449,7 @@ def main():
         lp = synth.layered_pair(1024, 2048, 34, 14, args.seed)
         U, S = ms.Mesh.from_synth(lp.U), ms.Mesh.from_synth(lp.S)
         ls = ms.LayerSearch(U, S, lp.D_u, lp.lam_u, lp.D_s, lp.lam_s, lp.n_layers, hits_cap=1 << 16)
-        log(f"layers: autotuned kappa {ls.kappa}: " + ", ".join(f"{k}: {v:.3f} ms" for k, v in ls.kappa_times.items()))
+        log(f"layers: tuned {ls.tuned}" + "".join(f"; {k}: {v:.3f} ms" for k, v in ls.kappa_times.items()))
         ls.run(True)
         torch.cuda.synchronize()
         reps = 10
@@ -468,6 +473,7 @@ def main():
         quads = int(sum((a.n_tris // 2) * (b.n_tris // 2) for a, b in ls.meshes))
         out["layers_pairs"] = len(ls.meshes)
         out["layers_kappa"] = ls.kappa
+        out["layers_tuned"] = ls.tuned
         out["layers_batched_ms"] = t_l * 1e3
         out["layers_plain_ms"] = t_p * 1e3
         out["layers_quad_pairs"] = quads

@@ -139,10 +139,24 @@ typedef struct {
     int32_t table_log2;     /* 0: automatic; else log2 of the hashed occupancy table per
                                side, clamped to [8, 25] (smaller: more cells share a group;
                                results do not change, only the work) */
+    int32_t enum_shape;     /* work tile of the pair enumeration (MS_ENUM_*; 0: MS_ENUM_HALF;
+                               a batch takes its first pair's); results do not change,
+                               only the time */
+    int32_t reserved;       /* 0 */
 } search_params_t;
 
-/* World = box of both meshes' finite triangles, edge = kappa * mean triangle
- * diameter of both meshes, n_cells[d] = max(1, ceil(span_d * inv_edge)). */
+/* Enumeration work tiles: a block takes a chunk of consecutive slots and
+ * stages the entries they need in LDS. */
+enum {
+    MS_ENUM_WIDE = 1,       /* 512 threads x 8 slots, up to 768 staged entries: one block per CU */
+    MS_ENUM_HALF = 2,       /* 256 threads x 8 slots, up to 384 staged entries: two blocks per CU */
+    MS_ENUM_QUARTER = 3     /* 128 threads x 8 slots, up to 192 staged entries: four blocks per CU */
+};
+
+/* World = box of both meshes' finite triangles, edge = kappa * the geometric
+ * mean of the two meshes' mean triangle diameters (longest edge; one mesh's
+ * alone when the other has no finite triangle), n_cells[d] = max(1,
+ * ceil(span_d * inv_edge)); table_log2 = 0, enum_shape = 0. */
 int search_default_params(const ms_mesh *A, const ms_mesh *B, double kappa, search_params_t *out);
 
 /*

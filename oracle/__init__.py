@@ -414,12 +414,15 @@ def damped_newton(params, patch_u, patch_s, mu: float, e: float, steps_per_perio
 
 
 def default_grid(meshes, kappa: float):
-    """World = box of all finite vertices; edge = kappa x mean over both meshes
-    of the triangles' longest 4D edge; cells per axis = max(1, ceil(span x
-    inv_edge)).  Returns (w_lo, w_hi, inv_edge, n_cells).  Test helper."""
+    """World = box of all finite vertices; edge = kappa x the geometric mean
+    over the meshes of each mesh's mean longest 4D triangle edge (a mesh
+    without finite triangles left out); cells per axis = max(1, ceil(span x
+    inv_edge)).  Returns (w_lo, w_hi, inv_edge, n_cells).  Test helper: the
+    grid only decides which pairs are examined (Sec. 6.2.1), never the hit
+    set."""
     import math
     lo = np.full(4, np.inf); hi = np.full(4, -np.inf)
-    tot, cnt = 0.0, 0
+    means = []
     for m in meshes:
         v = m.verts
         fin = np.all(np.isfinite(v.reshape(-1, 4)), axis=1)
@@ -436,8 +439,17 @@ def default_grid(meshes, kappa: float):
         t2 = np.maximum(np.maximum(nrm(c - d), nrm(b - d)), e_diag)
         allt = np.concatenate([t1.ravel(), t2.ravel()])
         allt = allt[np.isfinite(allt)]
-        tot += float(allt.sum()); cnt += allt.size
-    edge = kappa * (tot / max(cnt, 1))
+        if allt.size:
+            means.append(float(allt.sum()) / allt.size)
+    if len(means) == 2:
+        gm = math.sqrt(means[0] * means[1])
+    elif means:
+        gm = float(np.prod(means)) ** (1.0 / len(means))
+    else:
+        gm = 0.0
+    edge = kappa * gm
+    if not (edge > 0.0 and math.isfinite(edge)):
+        edge = 1.0
     inv = 1.0 / edge
     n = np.array([max(1, int(math.ceil((hi[d] - lo[d]) * inv))) for d in range(4)], dtype=np.int64)
     return lo, hi, inv, n

@@ -13,6 +13,8 @@ import os
 
 import numpy as np
 
+from . import tune as _tune
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 # MSEARCH_LIB selects another build of the same library (the host-sanitizer build of the CPU checks)
 LIB_PATH = os.environ.get("MSEARCH_LIB") or os.path.join(_HERE, "libmsearch.so")
@@ -20,6 +22,7 @@ LIB_PATH = os.environ.get("MSEARCH_LIB") or os.path.join(_HERE, "libmsearch.so")
 MS_OK, MS_E_ARG, MS_E_CAPACITY, MS_E_HIP, MS_E_NONFINITE, MS_E_KEYBITS, MS_E_WORKSPACE = 0, -1, -2, -3, -4, -5, -6
 MS_LAYOUT_AOS, MS_LAYOUT_SOA = 0, 1
 MS_SEARCH_CANDIDATES, MS_SEARCH_STRICT = 1, 2
+MS_ENUM_WIDE, MS_ENUM_HALF, MS_ENUM_QUARTER = 1, 2, 3
 
 # Exported entry points (the C ABI of include/msearch.h).
 EXPORTS = ("last_error", "mesh_build", "mesh_free", "mesh_info", "mesh_update", "search_default_params",
@@ -54,7 +57,7 @@ class MSearchError(RuntimeError):
 
 class SearchParams(C.Structure):
     _fields_ = [("world_lo", C.c_double * 4), ("inv_edge", C.c_double), ("n_cells", C.c_int64 * 4),
-                ("flags", C.c_int32), ("table_log2", C.c_int32)]
+                ("flags", C.c_int32), ("table_log2", C.c_int32), ("enum_shape", C.c_int32), ("reserved", C.c_int32)]
 
 
 class MeshInfo(C.Structure):
@@ -258,7 +261,7 @@ def default_params(A: Mesh, B: Mesh, kappa: float) -> SearchParams:
     return p
 
 
-def make_params(w_lo, inv_edge: float, n_cells, flags: int = 0, table_log2: int = 0) -> SearchParams:
+def make_params(w_lo, inv_edge: float, n_cells, flags: int = 0, table_log2: int = 0, enum_shape: int = 0) -> SearchParams:
     p = SearchParams()
     for d in range(4):
         p.world_lo[d] = float(w_lo[d])
@@ -266,6 +269,7 @@ def make_params(w_lo, inv_edge: float, n_cells, flags: int = 0, table_log2: int 
     p.inv_edge = float(inv_edge)
     p.flags = int(flags)
     p.table_log2 = int(table_log2)
+    p.enum_shape = int(enum_shape)
     return p
 
 
@@ -345,7 +349,7 @@ class Searcher:
         return hits, st, cand
 
 
-KAPPAS = (0.5, 0.75, 1.0, 1.5, 2.0, 3.0, 4.0)
+KAPPAS = _tune.KAPPAS
 
 
 def _time_ms(fn, reps: int) -> float:
@@ -359,40 +363,58 @@ def _time_ms(fn, reps: int) -> float:
     return e0.elapsed_time(e1) / reps
 
 
-def autotune_kappa(A: Mesh, B: Mesh, kappas=KAPPAS, reps: int = 20, tie: float = 0.03,
-                   hits_cap: int = 1 << 10, cand_cap: int = 1 << 20):
-    """Cell-edge autotuner for one mesh pair.  The grid of Sec. 6.2.1 only
-    needs cells larger than the triangles; the edge is kappa x the mean
-    triangle diameter, and the result set does not depend on it.  Times the
-    search at every kappa and returns the smallest kappa within `tie` of the
-    fastest (so that near-ties resolve the same way every run), its
-    parameters and the timings {kappa: ms}."""
-    times = {}
-    for k in kappas:
-        s = Searcher(A, B, default_params(A, B, k), hits_cap, cand_cap)
+def _device_tag() -> str:
+    torch = _torch()
+    pr = torch.cuda.get_device_properties(torch.cuda.current_device())
+    arch = getattr(pr, "gcnArchName", "") or pr.name
+    return f"{arch.split(':')[0]}x{pr.multi_processor_count}"
+
+
+def tuned_params(A: Mesh, B: Mesh, choice: dict) -> SearchParams:
+    """The search parameters of a tuned choice (tune.tune)."""
+    p = default_params(A, B, choice["kappa"])
+    p.table_log2 = int(choice["table_log2"])
+    p.enum_shape = int(choice["enum_shape"])
+    return p
+
+
+def autotune(pairs, batch: bool = False, reps: int | None = None, hits_cap: int = 1 << 16,
+             cand_cap: int = 1 << 20, use_cache: bool = True, cache_path: str | None = None):
+    """The tuned (kappa, table_log2, enum_shape) of a plain search of one
+    pair or of a batched search of many (tune.tune: joint sweep, cached per
+    size bucket).  Returns (choice, per-pair parameters, timings)."""
+    if reps is None:
+        reps = 3 if batch else 20
+
+    def measure(kappa, table, shape):
+        ch = {"kappa": kappa, "table_log2": table, "enum_shape": shape}
+        params = [tuned_params(a, b, ch) for a, b in pairs]
+        if batch:
+            bt = Batch(pairs, params, hits_cap=hits_cap, cand_cap=cand_cap)
+            bt.run_checked(True)
+            t = _time_ms(lambda: bt.run(True), reps)
+            bt.close()
+            return t
+        s = Searcher(pairs[0][0], pairs[0][1], params[0], hits_cap, cand_cap)
         s.run()
-        times[k] = _time_ms(s.run_async, reps)
+        t = _time_ms(s.run_async, reps)
         s.check_overflow()
-    fastest = min(times.values())
-    kappa = min(k for k in kappas if times[k] <= fastest * (1.0 + tie))
-    return kappa, default_params(A, B, kappa), times
+        return t
+
+    choice, times = _tune.tune(pairs, measure, _device_tag(), batch, use_cache, cache_path)
+    return choice, [tuned_params(a, b, choice) for a, b in pairs], times
 
 
-def autotune_batch_kappa(pairs, kappas=(1.0, 1.5, 2.0, 3.0), reps: int = 3, tie: float = 0.03,
-                         hits_cap: int = 1 << 16, cand_cap: int = 1 << 22):
-    """The same for a batch of mesh pairs searched together (one kappa for
-    every pair, one captured graph per trial).  Returns (kappa, per-pair
-    parameters, timings)."""
-    times = {}
-    for k in kappas:
-        params = [default_params(a, b, k) for a, b in pairs]
-        bt = Batch(pairs, params, hits_cap=hits_cap, cand_cap=cand_cap)
-        bt.run_checked(True)
-        times[k] = _time_ms(lambda: bt.run(True), reps)
-        del bt
-    fastest = min(times.values())
-    kappa = min(k for k in kappas if times[k] <= fastest * (1.0 + tie))
-    return kappa, [default_params(a, b, kappa) for a, b in pairs], times
+def autotune_kappa(A: Mesh, B: Mesh, hits_cap: int = 1 << 10, cand_cap: int = 1 << 20, use_cache: bool = True):
+    """The tuned choice for one mesh pair: (choice, parameters, timings)."""
+    choice, params, times = autotune([(A, B)], False, hits_cap=hits_cap, cand_cap=cand_cap, use_cache=use_cache)
+    return choice, params[0], times
+
+
+def autotune_batch_kappa(pairs, hits_cap: int = 1 << 16, cand_cap: int = 1 << 22, use_cache: bool = True):
+    """The tuned choice for a batch (one choice for every pair, one captured
+    graph per trial): (choice, per-pair parameters, timings)."""
+    return autotune(pairs, True, hits_cap=hits_cap, cand_cap=cand_cap, use_cache=use_cache)
 
 
 LAYER_PAIR_DTYPE = np.dtype([("u_layer", "<i4"), ("u_sign", "<i4"), ("s_layer", "<i4"), ("s_sign", "<i4")])
@@ -444,10 +466,11 @@ class LayerSearch:
                         half(S, True, D_s, lam_s, int(p["s_layer"]), int(p["s_sign"]))) for p in self.pairs]
         self.halves = cache
         if kappa is None:
-            self.kappa, params, self.kappa_times = autotune_batch_kappa(self.meshes, hits_cap=hits_cap,
+            self.tuned, params, self.kappa_times = autotune_batch_kappa(self.meshes, hits_cap=hits_cap,
                                                                         cand_cap=cand_cap)
+            self.kappa = self.tuned["kappa"]
         else:
-            self.kappa, self.kappa_times = float(kappa), {}
+            self.kappa, self.kappa_times, self.tuned = float(kappa), {}, None
             params = [default_params(a, b, self.kappa) for a, b in self.meshes]
         self.params = params
         self.batch = Batch(self.meshes, params, hits_cap=hits_cap, cand_cap=cand_cap)

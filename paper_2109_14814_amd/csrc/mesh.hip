@@ -293,8 +293,13 @@ extern "C" int search_default_params(const ms_mesh *A, const ms_mesh *B, double 
         lo[d] = fmin(A->info.lo[d], B->info.lo[d]);
         hi[d] = fmax(A->info.hi[d], B->info.hi[d]);
     }
+    // the geometric mean of the two meshes' mean triangle diameters: for
+    // meshes of unequal resolution, a cell between the two sizes keeps the
+    // coarse mesh's triangles to a few cells each and the fine mesh's cells
+    // to a few of its triangles per coarse triangle
     int64_t na = A->info.n_tris - A->info.n_nonfinite, nb = B->info.n_tris - B->info.n_nonfinite;
-    double diam = (na + nb) > 0 ? (A->info.mean_diam * (double)na + B->info.mean_diam * (double)nb) / (double)(na + nb) : 0.0;
+    const double dA = A->info.mean_diam, dB = B->info.mean_diam;
+    double diam = (na > 0 && nb > 0) ? sqrt(dA * dB) : (na > 0 ? dA : (nb > 0 ? dB : 0.0));
     double edge = kappa * diam;
     bool empty = !(lo[0] <= hi[0]);
     if (!(edge > 0.0) || !isfinite(edge)) edge = 1.0;

@@ -1367,22 +1367,30 @@ MS_D void emit_hit(bool hit, const hit_t &h, uint64_t key, hit_t *hits, uint64_t
 // overlapping pair has, by monotonicity of the cell map), and only if the
 // closed boxes overlap (Sec. 6.2.2).
 //
-// Each block takes ENUM_SLOTS consecutive slots.  Of every group the chunk
-// touches it needs only the A entries of the rows it covers (all of them once
-// it spans more than one row) and the B entries of those rows; when these are
-// at most ENUM_STAGE in all, the block stages their cells, triangle indices
-// and boxes (computed once from the vertices) in LDS, so that every slot
-// reads LDS only.  Otherwise each slot gathers its two triangles from global
+// Each block takes a chunk of S::slots consecutive slots.  Of every group the
+// chunk touches it needs only the A entries of the rows it covers (all of
+// them once it spans more than one row) and the B entries of those rows; when
+// these are at most S::stage in all, the block stages their cells, triangle
+// indices and boxes in LDS, so that every slot reads LDS only.  Otherwise each slot gathers its two triangles from global
 // memory.  One atomic reservation per chunk for the candidates, then the
 // narrow phase on the chunk's candidates.  Last, the exact cell statistics
 // (Alg. 1's boxes and slots) of the groups that start in the chunk.
-constexpr int ENUM_BLOCK = 512;               // 2 waves per SIMD; the narrow phase needs the registers
-constexpr int ENUM_ITEMS = 8;
-constexpr int ENUM_SLOTS = ENUM_BLOCK * ENUM_ITEMS;
-constexpr int ENUM_STAGE = 768;
-constexpr int ENUM_CELLS = BLOCK;
-constexpr int ENUM_GROUP = ENUM_STAGE;        // group cells held in LDS for the statistics
-constexpr int ENUM_GRID = 512;                // one block per CU fits (LDS): two rounds
+//
+// The work-tile shape: NT threads per block, ITEMS slots per thread (a chunk
+// is NT * ITEMS slots), STAGE staged entries, CELLS groups per chunk held in
+// LDS, PSTART slot offsets held in LDS, GRID blocks.  The narrow phase needs
+// about 200 registers, so a SIMD holds two waves: one 512-thread block per
+// CU, or two 256-thread blocks when their LDS fits twice.  Results do not
+// depend on the shape, only the time.
+template <int NT, int ITEMS, int STAGE, int CELLS, int PSTART, int GRID>
+struct EnumShape {
+    static constexpr int block = NT, items = ITEMS, slots = NT * ITEMS, stage = STAGE, cells = CELLS,
+                         pstart = PSTART, grid = GRID;
+    static_assert(ITEMS <= 32 && CELLS <= NT, "keep bits per thread; one group per thread");
+};
+using EnumWide = EnumShape<512, 8, 768, 256, 4096, 512>;     // one block per CU, two rounds
+using EnumHalf = EnumShape<256, 8, 384, 128, 2048, 1024>;    // two blocks per CU, two rounds
+using EnumQuarter = EnumShape<128, 8, 192, 64, 1024, 2048>;  // four blocks per CU, two rounds
 
 template <bool ONE>
 MS_D bool enum_pair(const PairDesc &Pd, uint64_t cell, const double alo[4], const double ahi[4], const double blo[4],
@@ -1405,7 +1413,8 @@ MS_D bool enum_pair(const PairDesc &Pd, uint64_t cell, const double alo[4], cons
 // cell_of(x) == that axis's coordinate exactly when lo <= t and not t >= hi:
 // lo = -inf on the first cell, hi = NaN on the last (no upper bound), else
 // the cell's integer edges (floor(t) == c <=> c <= t < c + 1 in FP64).
-MS_D void home_bounds(const GridView &g, uint64_t cell, double (*gb)[ENUM_CELLS], int k)
+template <int CELLS>
+MS_D void home_bounds(const GridView &g, uint64_t cell, double (*gb)[CELLS], int k)
 {
     int64_t c[4];
     uint64_t r = cell;
@@ -1445,16 +1454,17 @@ MS_D int entry_pair(const int32_t *kpair, int64_t e)
 // Exact cell statistics of a group holding several cells, by the whole
 // block: per A entry, the B entries of its own cell are its slots, and the
 // first A entry of a cell with B entries adds the cell.  The group's cells
-// go through LDS (s_cell, ENUM_GROUP entries) when they fit.
+// go through LDS (s_cell, GROUP entries) when they fit.  NT threads.
+template <int NT, int GROUP>
 MS_D void group_stats(const uint64_t *keys, const CellRec &cr, int sh, uint64_t *s_cell, unsigned long long &xc,
                       unsigned long long &xs)
 {
     const int n = cr.nA + cr.nB;
-    const bool lds = n <= ENUM_GROUP;
+    const bool lds = n <= GROUP;
     if (lds)
-        for (int i = threadIdx.x; i < n; i += ENUM_BLOCK) s_cell[i] = keys[cr.start + i] >> sh;
+        for (int i = threadIdx.x; i < n; i += NT) s_cell[i] = keys[cr.start + i] >> sh;
     __syncthreads();
-    for (int i = threadIdx.x; i < cr.nA; i += ENUM_BLOCK) {
+    for (int i = threadIdx.x; i < cr.nA; i += NT) {
         const uint64_t ci = lds ? s_cell[i] : keys[cr.start + i] >> sh;
         uint32_t nb = 0, before = 0;
         for (int j = 0; j < cr.nB; ++j) nb += (lds ? s_cell[cr.nA + j] : keys[cr.start + cr.nA + j] >> sh) == ci;
@@ -1532,10 +1542,11 @@ MS_D SlotOut global_slot(const BatchView &bv, const uint64_t *keys, const int32_
 
 // For x0 <= x1, the last i0 and i1 in [0, n) with a[i] <= x (a ascending,
 // a[0] <= x0), found by the whole block at once: each round splits every
-// open range [lo, hi) into ENUM_BLOCK parts, one per thread, and keeps the
-// part where a[i] <= x stops holding (two loads per thread and round;
-// log_ENUM_BLOCK(n) rounds).  s_r[0..1] = [lo, hi) for x0, s_r[2..3] for x1;
-// the results are s_r[0] and s_r[2].  Ends with a barrier.
+// open range [lo, hi) into NT parts, one per thread, and keeps the part
+// where a[i] <= x stops holding (two loads per thread and round; log_NT(n)
+// rounds).  s_r[0..1] = [lo, hi) for x0, s_r[2..3] for x1; the results are
+// s_r[0] and s_r[2].  Ends with a barrier.
+template <int NT>
 MS_D void block_last_le2(const int64_t *a, int64_t n, int64_t x0, int64_t x1, int64_t *s_r)
 {
     if (threadIdx.x == 0) {
@@ -1553,7 +1564,7 @@ MS_D void block_last_le2(const int64_t *a, int64_t n, int64_t x0, int64_t x1, in
         for (int k = 0; k < 2; ++k) {
             const int64_t lo = k ? lo1 : lo0, hi = k ? hi1 : hi0, x = k ? x1 : x0;
             if (hi - lo <= 1) continue;
-            const int64_t step = (hi - lo + ENUM_BLOCK - 1) / ENUM_BLOCK;
+            const int64_t step = (hi - lo + NT - 1) / NT;
             const int64_t i = lo + (int64_t)threadIdx.x * step;
             if (i < hi && a[i] <= x) {
                 const int64_t j = i + step;
@@ -1568,16 +1579,16 @@ MS_D void block_last_le2(const int64_t *a, int64_t n, int64_t x0, int64_t x1, in
     __syncthreads();
 }
 
-constexpr int ENUM_PSTART = 4096;   // slot offsets kept in LDS when the groups are this few
-
-template <bool ONE>
-__global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_t *keys, const int32_t *kpair,
+template <bool ONE, class S>
+__global__ void __launch_bounds__(S::block) k_enum(BatchView bv, const uint64_t *keys, const int32_t *kpair,
                                                 const double *sbox, const CellRec *cells, const int64_t *pstart_g, const int64_t *kept,
                                                 const uint32_t *mix,
                                                 search_stats_t *stats, uint64_t *cand, int32_t *cand_pair,
                                                 int64_t cand_cap, hit_t *hits, uint64_t *hkeys, int64_t hits_cap,
                                                 unsigned long long *epart)
 {
+    constexpr int ENUM_BLOCK = S::block, ENUM_ITEMS = S::items, ENUM_SLOTS = S::slots, ENUM_STAGE = S::stage,
+                  ENUM_GROUP = S::stage, ENUM_CELLS = S::cells, ENUM_PSTART = S::pstart;
     __shared__ int64_t s_pstart[ENUM_PSTART + 1];
     // the staged boxes during enumeration (component-major, so that lanes
     // reading consecutive entries hit distinct banks), then the chunk's
@@ -1635,7 +1646,7 @@ __global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_
             }
             if (threadIdx.x == 0) s_nmix = 0;
         } else {
-            block_last_le2(pstart, ncells, S0, S1 - 1, s_rng);
+            block_last_le2<ENUM_BLOCK>(pstart, ncells, S0, S1 - 1, s_rng);
             if (threadIdx.x == 0) {
                 s_c0 = s_rng[0];
                 s_c1 = s_rng[2];
@@ -1713,7 +1724,7 @@ __global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_
                 const int i0 = s_aoff[threadIdx.x];
                 const uint64_t gc = s_ec[i0];
                 const PairDesc &Pd = pair_desc<ONE>(bv, ONE ? 0 : s_ep[i0]);
-                home_bounds(Pd.g, gc - Pd.cell_base, s_gb, threadIdx.x);
+                home_bounds<ENUM_CELLS>(Pd.g, gc - Pd.cell_base, s_gb, threadIdx.x);
                 s_gcell[threadIdx.x] = gc;
                 if constexpr (!ONE) {
 #pragma unroll
@@ -1919,7 +1930,7 @@ __global__ void __launch_bounds__(ENUM_BLOCK) k_enum(BatchView bv, const uint64_
         __syncthreads();
         for (uint32_t k = 0; k < s_nmix; ++k) {
             const CellRec cr = cells[c0 + s_u.c.pair[k]];
-            group_stats(keys, cr, sh, s_ec, xc, xs);
+            group_stats<ENUM_BLOCK, ENUM_GROUP>(keys, cr, sh, s_ec, xc, xs);
         }
         __syncthreads();
     }
@@ -2094,6 +2105,7 @@ struct Geometry {
     int cell_bits;
     int bm_log2, bc_log2;
     int packable, c32;
+    int enum_shape;
     uint64_t total_cells;
 };
 
@@ -2165,6 +2177,13 @@ int geometry(int64_t n_pairs, const ms_mesh *const *A, const ms_mesh *const *B, 
         if (prm[i].table_log2 > req) req = prm[i].table_log2;
     if (req > 0) G.bm_log2 = req < 8 ? 8 : (req > 25 ? 25 : req);
     G.bc_log2 = G.bm_log2 - 3;
+    G.enum_shape = 0;    // the shape of the first pair that asks for one, else MS_ENUM_HALF
+    for (int64_t i = 0; i < n_pairs; ++i) {
+        if (prm[i].enum_shape < 0 || prm[i].enum_shape > MS_ENUM_QUARTER)
+            return fail(MS_E_ARG, "search: enum_shape must be 0 or an MS_ENUM_* value");
+        if (G.enum_shape == 0) G.enum_shape = prm[i].enum_shape;
+    }
+    if (G.enum_shape == 0) G.enum_shape = MS_ENUM_HALF;
     return MS_OK;
 }
 
@@ -2372,9 +2391,18 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
     MS_LAUNCH("k_scatter", k_scatter<ONE>, dim3(grid_for(L.ent_cap, 1024)), dim3(BLOCK), 0, st, bv, ent, epair, erank,
               ehash, n_keys, L.ent_cap, (uint32_t *)grp, own, mix, sorted, spair, sbox, epoch, (uint4 *)flags,
               (int64_t)(flag_bytes(G) / 16));
-    MS_LAUNCH("k_enum", k_enum<ONE>, dim3(ENUM_GRID), dim3(ENUM_BLOCK), 0, st, bv, sorted, spair, sbox, cells, pstart,
-              misc + 1, mix, stats, cand_user, (int32_t *)nullptr, cand_user ? cand_cap : (int64_t)0, htmp, hkeys,
-              hits_cap, epart);
+    if (G.enum_shape == MS_ENUM_QUARTER)
+        MS_LAUNCH("k_enum", (k_enum<ONE, EnumQuarter>), dim3(EnumQuarter::grid), dim3(EnumQuarter::block), 0, st, bv,
+                  sorted, spair, sbox, cells, pstart, misc + 1, mix, stats, cand_user, (int32_t *)nullptr,
+                  cand_user ? cand_cap : (int64_t)0, htmp, hkeys, hits_cap, epart);
+    else if (G.enum_shape == MS_ENUM_HALF)
+        MS_LAUNCH("k_enum", (k_enum<ONE, EnumHalf>), dim3(EnumHalf::grid), dim3(EnumHalf::block), 0, st, bv, sorted,
+                  spair, sbox, cells, pstart, misc + 1, mix, stats, cand_user, (int32_t *)nullptr,
+                  cand_user ? cand_cap : (int64_t)0, htmp, hkeys, hits_cap, epart);
+    else
+        MS_LAUNCH("k_enum", (k_enum<ONE, EnumWide>), dim3(EnumWide::grid), dim3(EnumWide::block), 0, st, bv, sorted,
+                  spair, sbox, cells, pstart, misc + 1, mix, stats, cand_user, (int32_t *)nullptr,
+                  cand_user ? cand_cap : (int64_t)0, htmp, hkeys, hits_cap, epart);
     MS_HIP(hipGetLastError());
     const bool tiny = hits_cap > 0 && hits_cap <= HITS_TINY;
     if (hits_cap > HITS_TINY) {

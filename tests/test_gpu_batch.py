@@ -52,16 +52,17 @@ def grids_for(fam, kappa):
     return [oracle.default_grid([a, b], kappa) for a, b in fam]
 
 
-@pytest.mark.parametrize("use_graph,hits_cap,table_log2", [(False, 1 << 12, 0), (True, 1 << 12, 0),
-                                                          (False, 1 << 10, 0), (True, 1 << 10, 0),
-                                                          (False, 1 << 12, 9)])
-def test_batch_matches_oracle_per_pair(ms, use_graph, hits_cap, table_log2):
+@pytest.mark.parametrize("use_graph,hits_cap,table_log2,shape", [(False, 1 << 12, 0, 0), (True, 1 << 12, 0, 0),
+                                                                (False, 1 << 10, 0, 0), (True, 1 << 10, 0, 0),
+                                                                (False, 1 << 12, 9, 0), (True, 1 << 12, 0, 1),
+                                                                (True, 1 << 12, 14, 3)])
+def test_batch_matches_oracle_per_pair(ms, use_graph, hits_cap, table_log2, shape):
     """Hit capacities 4096 (chunked hit sort) and 1024 (one-block hit sort);
     a small hashed table, where cells of different pairs share groups."""
     fam = small_family(24, 3)
     grids = grids_for(fam, 1.5)
     gp = [(ms.Mesh.from_synth(a), ms.Mesh.from_synth(b)) for a, b in fam]
-    params = [ms.make_params(g[0], g[2], g[3], 0, table_log2) for g in grids]
+    params = [ms.make_params(g[0], g[2], g[3], 0, table_log2, shape) for g in grids]
     bt = ms.Batch(gp, params, hits_cap=hits_cap, cand_cap=1 << 16)
     bt.run_checked(use_graph)
     per_pair, st = bt.results()

@@ -37,11 +37,11 @@ def assert_hits_equal(got, want):
         assert np.max(np.abs(got["X"] - want["X"])) <= TOL
 
 
-def gpu_search(ms, A, B, grid, flags=None, hits_cap=1 << 14, cand_cap=1 << 20, table_log2=0):
+def gpu_search(ms, A, B, grid, flags=None, hits_cap=1 << 14, cand_cap=1 << 20, table_log2=0, enum_shape=0):
     lo, hi, inv, n = grid
     f = ms.MS_SEARCH_CANDIDATES if flags is None else flags
     ga, gb = ms.Mesh.from_synth(A), ms.Mesh.from_synth(B)
-    p = ms.make_params(lo, inv, n, f, table_log2)
+    p = ms.make_params(lo, inv, n, f, table_log2, enum_shape)
     s = ms.Searcher(ga, gb, p, hits_cap=hits_cap, cand_cap=cand_cap)
     s.run()
     hits, st, cand = s.results()
@@ -113,6 +113,40 @@ def test_grid_cfg1_bench_configuration(ms, hits_cap):
     hits, st, cand = gpu_search(ms, A, B, grid, flags=0, hits_cap=hits_cap)
     assert cand is None
     check_against(ref, hits, st, None, ref)
+
+
+@pytest.mark.parametrize("shape", [1, 2, 3])
+@pytest.mark.parametrize("kappa,table_log2", [(2.5, 16), (0.75, 20)])
+def test_tuned_tuples_match_grid_oracle(ms, shape, kappa, table_log2):
+    """Tuples the autotuner may pick (cell edge, hashed table size,
+    enumeration work tile) away from the defaults: each gives the oracle's
+    candidates, hits and exact cell statistics."""
+    A, B = synth.plain_pair(96, 96, 3)
+    grid = oracle.default_grid([A, B], kappa)
+    ref = oracle.grid_search(A, B, grid[0], grid[2], grid[3])
+    hits, st, cand = gpu_search(ms, A, B, grid, table_log2=table_log2, enum_shape=shape)
+    check_against(ref, hits, st, cand, ref)
+
+
+@pytest.mark.parametrize("shape,table_log2", [(3, 22), (1, 24)])
+def test_grid_cfg1_tuned_tuple(ms, shape, table_log2):
+    """The 512 x 512 workload at non-default tuned tuples, against the grid
+    oracle."""
+    A, B = synth.plain_pair(512, 512, 0)
+    grid = oracle.default_grid([A, B], 1.5)
+    ref = oracle.grid_search(A, B, grid[0], grid[2], grid[3])
+    hits, st, cand = gpu_search(ms, A, B, grid, flags=0, hits_cap=1 << 10, table_log2=table_log2, enum_shape=shape)
+    check_against(ref, hits, st, None, ref)
+
+
+def test_enum_shape_out_of_range_is_an_error(ms):
+    A, B = synth.plain_pair(16, 16, 0)
+    ga, gb = ms.Mesh.from_synth(A), ms.Mesh.from_synth(B)
+    p = ms.default_params(ga, gb, 1.0)
+    p.enum_shape = 4
+    with pytest.raises(ms.MSearchError) as ei:
+        ms.Searcher(ga, gb, p)
+    assert ei.value.code == ms.MS_E_ARG
 
 
 @pytest.mark.parametrize("seed,kappa,table_log2", [(0, 1.0, 8), (1, 0.5, 9), (2, 2.0, 10), (0, 1.5, 12)])
