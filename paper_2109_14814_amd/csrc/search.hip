@@ -89,9 +89,9 @@ struct PairDesc {
     int32_t tilesA, pad_;
     uint64_t st[4];     // linear-id strides of the cells: n1 n2 n3, n2 n3, n3, 1
     uint64_t fbs[4];    // fine table: linear-id strides of its blocks (cell index / 2 per axis)
-    uint64_t fbh[4];    //   and fbs * HASH_MUL mod 2^64
+    uint32_t fbh[4];    //   and fbs * HASH_MUL mod 2^32
     uint64_t cbs[4];    // coarse table (cell index / 2 per axis): strides of its blocks
-    uint64_t cbh[4];    //   (cell index / 4 per axis) and cbs * HASH_MUL
+    uint32_t cbh[4];    //   (cell index / 4 per axis) and cbs * HASH_MUL mod 2^32
     double nm1[4];      // n_d - 1
 };
 
@@ -131,17 +131,18 @@ MS_D int64_t last_le(const T *a, int64_t n, T x)
 }
 
 
-// Multiplier of the hashed tables (the odd 64-bit constant nearest 2^64 / phi).
-constexpr uint64_t HASH_MUL = 0x9E3779B97F4A7C15ull;
+// Multiplier of the hashed tables (the odd 32-bit constant nearest 2^32 / phi).
+constexpr uint32_t HASH_MUL = 0x9E3779B1u;
 
 
-// The top log2 bits (log2 <= 32) of a product id * HASH_MUL mod 2^64.  The
-// product is linear in the id, so the products of neighbouring ids follow
-// from one of them by adding per-axis products (stride_d * HASH_MUL), with
-// no multiplication per cell.
-MS_D uint32_t hash_of_product(uint64_t prod, int log2)
+// The top log2 bits (1 <= log2 <= 31) of a product id * HASH_MUL mod 2^32 (of
+// the id mod 2^32: ids that differ by a multiple of 2^32 share a hash, which
+// only costs work).  The product is linear in the id, so the products of
+// neighbouring ids follow from one of them by adding per-axis products
+// (stride_d * HASH_MUL), with no multiplication per cell.
+MS_D uint32_t hash_of_product(uint32_t prod, int log2)
 {
-    return (uint32_t)(prod >> 32) >> (32 - log2);
+    return prod >> (32 - log2);
 }
 
 struct CellRange {
@@ -271,7 +272,7 @@ MS_D uint32_t extent_mask(const Range32 &r)
 // The occupancy tables (fine cells, and coarse cells of twice the edge) are
 // hashed by blocks: a cell's 2x2x2x2 block (cell index / 2 per axis) picks a
 // 16-byte line of the table -- the top lg - 4 bits of (pair's cell base +
-// the block's linear id) * HASH_MUL -- and the low bit of each cell index
+// the block's linear id) * HASH_MUL mod 2^32 -- and the low bit of each cell index
 // the byte in it.  Neighbouring cells thus share cache lines, so that the
 // marks and tests of a wave touch few lines; two cells share a hashed index
 // only when their blocks' hashes collide.  bs: linear-id strides of the
@@ -280,11 +281,11 @@ MS_D uint32_t extent_mask(const Range32 &r)
 // Hashed index of cell c (coordinates on the table's grid).
 MS_D uint32_t blocked_index(const int64_t c[4], const uint64_t bs[4], uint64_t cb, int lg)
 {
-    uint64_t lin = 0;
+    uint32_t lin = (uint32_t)cb;
 #pragma unroll
-    for (int d = 0; d < 4; ++d) lin += (uint64_t)(c[d] >> 1) * bs[d];
+    for (int d = 0; d < 4; ++d) lin += (uint32_t)(c[d] >> 1) * (uint32_t)bs[d];
     const uint32_t par = (uint32_t)((c[0] & 1) << 3 | (c[1] & 1) << 2 | (c[2] & 1) << 1 | (c[3] & 1));
-    return hash_of_product((cb + lin) * HASH_MUL, lg - 4) << 4 | par;
+    return hash_of_product(lin * HASH_MUL, lg - 4) << 4 | par;
 }
 
 // The 16 positions of a small range in Gray-code order (each step moves one
@@ -302,24 +303,24 @@ struct GrayStep {
 // along axis d enters the next block only from an odd cell index, so the
 // per-axis steps of the product are bh[d] or 0 per range.
 struct BlockWalk {
-    uint64_t p;
-    uint64_t up[4], dn[4];
+    uint32_t p;
+    uint32_t up[4], dn[4];
     uint32_t par0;
 };
 
-MS_D void walk_init(BlockWalk &w, const Range32 &u, const uint64_t bs[4], const uint64_t bh[4], uint64_t cb)
+MS_D void walk_init(BlockWalk &w, const Range32 &u, const uint64_t bs[4], const uint32_t bh[4], uint64_t cb)
 {
-    uint64_t lin = 0;
+    uint32_t lin = (uint32_t)cb;
     w.par0 = 0;
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
-        lin += (uint64_t)(u.lo[d] >> 1) * bs[d];
+        lin += (uint32_t)(u.lo[d] >> 1) * (uint32_t)bs[d];
         const bool odd = (u.lo[d] & 1) != 0;
-        w.up[d] = odd ? bh[d] : 0ull;
-        w.dn[d] = odd ? 0ull - bh[d] : 0ull;
+        w.up[d] = odd ? bh[d] : 0u;
+        w.dn[d] = odd ? 0u - bh[d] : 0u;
         w.par0 |= (uint32_t)(u.lo[d] & 1) << (3 - d);
     }
-    w.p = (cb + lin) * HASH_MUL;
+    w.p = lin * HASH_MUL;
 }
 
 template <int K>
@@ -389,7 +390,7 @@ MS_D uint32_t range_positions(const Range32 &r)
 }
 
 // Marks every cell of range r (any size).
-MS_D void mark_range(const TabRef &t, const Range32 &r, const uint64_t bs[4], const uint64_t bh[4], uint64_t cb,
+MS_D void mark_range(const TabRef &t, const Range32 &r, const uint64_t bs[4], const uint32_t bh[4], uint64_t cb,
                      uint8_t v)
 {
     if (range_small(r)) {
@@ -402,7 +403,7 @@ MS_D void mark_range(const TabRef &t, const Range32 &r, const uint64_t bs[4], co
 }
 
 // Number of cells of range r whose both-occupied bit is set (any range).
-MS_D uint32_t count_both(const BitRef &t, const Range32 &r, const uint64_t bs[4], const uint64_t bh[4], uint64_t cb)
+MS_D uint32_t count_both(const BitRef &t, const Range32 &r, const uint64_t bs[4], const uint32_t bh[4], uint64_t cb)
 {
     if (range_small(r)) {
         BlockWalk w;
@@ -716,7 +717,7 @@ MS_D Range32 range_union(const Range32 &a, const Range32 &b)
 // quad's finite triangles (ok1, ok2); a union wider than two cells on some
 // axis marks each triangle on its own.
 MS_D void mark_quad(const TabRef &t, const Range32 &r1, bool ok1, const Range32 &r2, bool ok2,
-                    const uint64_t bs[4], const uint64_t bh[4], uint64_t cb, uint8_t v)
+                    const uint64_t bs[4], const uint32_t bh[4], uint64_t cb, uint8_t v)
 {
     if (!ok1 && !ok2) return;
     const Range32 u = ok1 && ok2 ? range_union(r1, r2) : (ok1 ? r1 : r2);
@@ -1322,7 +1323,7 @@ __global__ void __launch_bounds__(BLOCK) k_scatter(BatchView bv, const uint64_t 
         b[1] = make_double2(lo[2], lo[3]);
         b[2] = make_double2(hi[0], hi[1]);
         b[3] = make_double2(hi[2], hi[3]);
-        if (own[h] != gc) atomicOr(&mix[h], 1u);
+        if (own[h] != gc) mix[h] = 1u;    // every writer stores the same value
     }
     if ((ep + 1) % 255u == 0) {          // the next search's value wraps to 1 (k_finish advances the epoch)
         const uint4 z = make_uint4(0u, 0u, 0u, 0u);
@@ -1451,26 +1452,61 @@ MS_D int entry_pair(const int32_t *kpair, int64_t e)
     else return kpair[e];
 }
 
-// Exact cell statistics of a group holding several cells, by the whole
-// block: per A entry, the B entries of its own cell are its slots, and the
-// first A entry of a cell with B entries adds the cell.  The group's cells
-// go through LDS (s_cell, GROUP entries) when they fit.  NT threads.
-template <int NT, int GROUP>
-MS_D void group_stats(const uint64_t *keys, const CellRec &cr, int sh, uint64_t *s_cell, unsigned long long &xc,
+// Exact cell statistics of a group holding several cells (cells whose hashes
+// collide), by the whole block of NT threads: each cell's A and B entries are
+// counted in an LDS table keyed by the cell (s_tab: GS_SLOTS keys, then as
+// many count words, then an overflow flag), then every cell with entries of
+// both meshes adds itself and nA * nB slots.  A group of more distinct cells
+// than the table holds is counted per A entry instead.
+constexpr int GS_SLOTS = 64;
+
+template <int NT>
+MS_D void group_stats(const uint64_t *keys, const CellRec &cr, int sh, uint64_t *s_tab, unsigned long long &xc,
                       unsigned long long &xs)
 {
-    const int n = cr.nA + cr.nB;
-    const bool lds = n <= GROUP;
-    if (lds)
-        for (int i = threadIdx.x; i < n; i += NT) s_cell[i] = keys[cr.start + i] >> sh;
+    constexpr uint64_t EMPTY = ~0ull;
+    uint64_t *s_key = s_tab, *s_cnt = s_tab + GS_SLOTS, *s_full = s_tab + 2 * GS_SLOTS;
+    for (int i = threadIdx.x; i < GS_SLOTS; i += NT) {
+        s_key[i] = EMPTY;
+        s_cnt[i] = 0;
+    }
+    if (threadIdx.x == 0) *s_full = 0;
     __syncthreads();
-    for (int i = threadIdx.x; i < cr.nA; i += NT) {
-        const uint64_t ci = lds ? s_cell[i] : keys[cr.start + i] >> sh;
-        uint32_t nb = 0, before = 0;
-        for (int j = 0; j < cr.nB; ++j) nb += (lds ? s_cell[cr.nA + j] : keys[cr.start + cr.nA + j] >> sh) == ci;
-        for (int j = 0; j < i; ++j) before += (lds ? s_cell[j] : keys[cr.start + j] >> sh) == ci;
-        xs += nb;
-        xc += (nb > 0 && before == 0);
+    const int n = cr.nA + cr.nB;
+    for (int i = threadIdx.x; i < n; i += NT) {
+        const uint64_t c = keys[cr.start + i] >> sh;
+        const unsigned long long add = i < cr.nA ? 1ull : (1ull << 32);   // nA in the low half, nB in the high
+        uint32_t slot = (uint32_t)((c * 0x9E3779B97F4A7C15ull) >> 58);
+        bool done = false;
+        for (int probe = 0; probe < GS_SLOTS && !done; ++probe) {
+            const unsigned long long k =
+                atomicCAS((unsigned long long *)&s_key[slot], (unsigned long long)EMPTY, (unsigned long long)c);
+            if (k == EMPTY || k == c) {
+                atomicAdd((unsigned long long *)&s_cnt[slot], add);
+                done = true;
+            } else {
+                slot = (slot + 1) & (GS_SLOTS - 1);
+            }
+        }
+        if (!done) *s_full = 1;
+    }
+    __syncthreads();
+    if (*s_full == 0) {
+        for (int i = threadIdx.x; i < GS_SLOTS; i += NT) {
+            if (s_key[i] == EMPTY) continue;
+            const uint64_t v = s_cnt[i], a = v & 0xffffffffull, b = v >> 32;
+            xs += a * b;
+            xc += (a > 0 && b > 0);
+        }
+    } else {
+        for (int i = threadIdx.x; i < cr.nA; i += NT) {
+            const uint64_t ci = keys[cr.start + i] >> sh;
+            uint32_t nb = 0, before = 0;
+            for (int j = 0; j < cr.nB; ++j) nb += (keys[cr.start + cr.nA + j] >> sh) == ci;
+            for (int j = 0; j < i; ++j) before += (keys[cr.start + j] >> sh) == ci;
+            xs += nb;
+            xc += (nb > 0 && before == 0);
+        }
     }
     __syncthreads();
 }
@@ -1588,7 +1624,8 @@ __global__ void __launch_bounds__(S::block) k_enum(BatchView bv, const uint64_t 
                                                 unsigned long long *epart)
 {
     constexpr int ENUM_BLOCK = S::block, ENUM_ITEMS = S::items, ENUM_SLOTS = S::slots, ENUM_STAGE = S::stage,
-                  ENUM_GROUP = S::stage, ENUM_CELLS = S::cells, ENUM_PSTART = S::pstart;
+                  ENUM_CELLS = S::cells, ENUM_PSTART = S::pstart;
+    static_assert(ENUM_STAGE > 2 * GS_SLOTS, "the staged cells hold a group's statistics table");
     __shared__ int64_t s_pstart[ENUM_PSTART + 1];
     // the staged boxes during enumeration (component-major, so that lanes
     // reading consecutive entries hit distinct banks), then the chunk's
@@ -1930,7 +1967,7 @@ __global__ void __launch_bounds__(S::block) k_enum(BatchView bv, const uint64_t 
         __syncthreads();
         for (uint32_t k = 0; k < s_nmix; ++k) {
             const CellRec cr = cells[c0 + s_u.c.pair[k]];
-            group_stats<ENUM_BLOCK, ENUM_GROUP>(keys, cr, sh, s_ec, xc, xs);
+            group_stats<ENUM_BLOCK>(keys, cr, sh, s_ec, xc, xs);
         }
         __syncthreads();
     }
@@ -2279,8 +2316,8 @@ PairDesc make_desc(const ms_mesh *A, const ms_mesh *B, const search_params_t *p,
     d.cbs[2] = c3;
     d.cbs[3] = 1;
     for (int k = 0; k < 4; ++k) {
-        d.fbh[k] = d.fbs[k] * HASH_MUL;
-        d.cbh[k] = d.cbs[k] * HASH_MUL;
+        d.fbh[k] = (uint32_t)d.fbs[k] * HASH_MUL;
+        d.cbh[k] = (uint32_t)d.cbs[k] * HASH_MUL;
         d.nm1[k] = (double)(p->n_cells[k] - 1);
     }
     return d;
