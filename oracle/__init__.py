@@ -61,7 +61,7 @@ def lib():
         L.orc_moller_reject.argtypes = [P, P]; L.orc_moller_reject.restype = C.c_int
         L.orc_bruteforce.argtypes = [C.POINTER(_Mesh), C.POINTER(_Mesh), C.c_int, C.POINTER(_Result), C.c_int]
         L.orc_bruteforce.restype = C.c_int
-        L.orc_grid_search.argtypes = [C.POINTER(_Mesh), C.POINTER(_Mesh), P, D, P, C.POINTER(_Result), C.c_int]
+        L.orc_grid_search.argtypes = [C.POINTER(_Mesh), C.POINTER(_Mesh), P, D, P, C.c_int, C.POINTER(_Result), C.c_int]
         L.orc_grid_search.restype = C.c_int
         L.orc_grid_entries.argtypes = [C.POINTER(_Mesh), P, D, P]; L.orc_grid_entries.restype = I64
         L.orc_cell_of.argtypes = [D, D, D, I64]; L.orc_cell_of.restype = I64
@@ -174,14 +174,17 @@ def bruteforce(meshA, meshB, forced: bool = False, nthreads: int = 0) -> SearchR
     return out
 
 
-def grid_search(meshA, meshB, w_lo, inv_edge: float, n_cells, nthreads: int = 0) -> SearchResult:
+def grid_search(meshA, meshB, w_lo, inv_edge: float, n_cells, nthreads: int = 0, prune: bool = False) -> SearchResult:
     """Uniform-grid search with per-box lists (paper Sec. 6.2.1), then the
-    AABB, Moller and narrow-phase tests; C and H are sorted and distinct."""
+    AABB, Moller and narrow-phase tests; C and H are sorted and distinct.
+    prune: the world-bound restriction of Sec. 6.2.1 (triangles whose box
+    misses the other mesh's box take no part in the grid)."""
     a, b = OMesh(meshA), OMesh(meshB)
     wl = np.ascontiguousarray(w_lo, dtype=np.float64)
     nc = np.ascontiguousarray(n_cells, dtype=np.int64)
     res = _Result()
-    rc = lib().orc_grid_search(a.ref, b.ref, _ptr(wl), float(inv_edge), _ptr(nc), C.byref(res), int(nthreads))
+    rc = lib().orc_grid_search(a.ref, b.ref, _ptr(wl), float(inv_edge), _ptr(nc), int(bool(prune)), C.byref(res),
+                               int(nthreads))
     if rc != 0:
         raise RuntimeError(f"orc_grid_search failed ({rc})")
     out = SearchResult(res)

@@ -543,9 +543,15 @@ static void range_cells(const int64_t clo[4], const int64_t chi[4], const int64_
  * (3) all A x B pairs in every box that holds both, AABB-tested; (4) the
  * union over boxes (pairs that share several boxes counted once); (5) the
  * Moller test and 4x4 solve on each distinct candidate.  The world origin
- * w_lo, inverse cell edge and cells per axis n[4] are inputs. */
+ * w_lo, inverse cell edge and cells per axis n[4] are inputs.
+ *
+ * prune != 0: the world-bound restriction remarked on in Sec. 6.2.1 -- the
+ * grid only holds triangles whose box meets the other mesh's box (the box of
+ * that mesh's finite triangles); no pair with a triangle outside can have
+ * overlapping boxes.  n_entries still counts every finite triangle's cells;
+ * n_boxes and n_slots are those of the restricted grid. */
 ORC_API int orc_grid_search(const orc_mesh *A, const orc_mesh *B, const double *wlo,
-                            double inv_edge, const int64_t *ncell, orc_result *res, int nthreads)
+                            double inv_edge, const int64_t *ncell, int prune, orc_result *res, int nthreads)
 {
     memset(res, 0, sizeof *res);
     int64_t n[4] = {ncell[0], ncell[1], ncell[2], ncell[3]};
@@ -555,24 +561,43 @@ ORC_API int orc_grid_search(const orc_mesh *A, const orc_mesh *B, const double *
     if (table_build(A, &T[0], &res->counts[6]) || table_build(B, &T[1], &res->counts[7])) return -1;
     int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
 
-    /* (1) entry counts and offsets */
+    /* each mesh's box over its finite triangles (for the pruning) */
     int64_t ntri[2] = {T[0].n, T[1].n};
+    double mlo[2][4], mhi[2][4];
+    for (int sd = 0; sd < 2; ++sd) {
+        for (int d = 0; d < 4; ++d) { mlo[sd][d] = INFINITY; mhi[sd][d] = -INFINITY; }
+        for (int64_t t = 0; t < ntri[sd]; ++t) {
+            if (!T[sd].fin[t]) continue;
+            for (int d = 0; d < 4; ++d) {
+                if (T[sd].lo[4 * t + d] < mlo[sd][d]) mlo[sd][d] = T[sd].lo[4 * t + d];
+                if (T[sd].hi[4 * t + d] > mhi[sd][d]) mhi[sd][d] = T[sd].hi[4 * t + d];
+            }
+        }
+    }
+
+    /* (1) entry counts and offsets (all finite triangles counted; the
+     * pruned ones emit nothing) */
     int64_t *off[2];
-    int64_t E = 0;
+    int64_t E = 0, E_all = 0;
     for (int sd = 0; sd < 2; ++sd) {
         off[sd] = (int64_t *)malloc((size_t)(ntri[sd] + 1) * sizeof(int64_t));
         if (!off[sd]) return -1;
-#pragma omp parallel for num_threads(nt) schedule(static)
+        int64_t all = 0;
+#pragma omp parallel for num_threads(nt) schedule(static) reduction(+ : all)
         for (int64_t t = 0; t < ntri[sd]; ++t) {
             int64_t clo[4], chi[4];
-            off[sd][t] = T[sd].fin[t] ? tri_cells(T[sd].lo + 4 * t, T[sd].hi + 4 * t, wlo, inv_edge, n, clo, chi) : 0;
+            int64_t c = T[sd].fin[t] ? tri_cells(T[sd].lo + 4 * t, T[sd].hi + 4 * t, wlo, inv_edge, n, clo, chi) : 0;
+            all += c;
+            if (prune && c && !boxes_overlap(T[sd].lo + 4 * t, T[sd].hi + 4 * t, mlo[1 - sd], mhi[1 - sd])) c = 0;
+            off[sd][t] = c;
         }
+        E_all += all;
         int64_t run = E;
         for (int64_t t = 0; t < ntri[sd]; ++t) { int64_t c = off[sd][t]; off[sd][t] = run; run += c; }
         off[sd][ntri[sd]] = run;
         E = run;
     }
-    res->n_entries = E;
+    res->n_entries = E_all;
     entry_t *ent = (entry_t *)malloc((size_t)(E ? E : 1) * sizeof(entry_t));
     if (!ent) return -1;
     /* (2) emit entries, then group them by box */
@@ -580,7 +605,7 @@ ORC_API int orc_grid_search(const orc_mesh *A, const orc_mesh *B, const double *
     for (int sd = 0; sd < 2; ++sd) {
 #pragma omp parallel for num_threads(nt) schedule(static) reduction(| : ent_err)
         for (int64_t t = 0; t < ntri[sd]; ++t) {
-            if (!T[sd].fin[t]) continue;
+            if (!T[sd].fin[t] || off[sd][t + 1] == off[sd][t]) continue;    /* non-finite or pruned */
             int64_t clo[4], chi[4];
             int64_t cnt = tri_cells(T[sd].lo + 4 * t, T[sd].hi + 4 * t, wlo, inv_edge, n, clo, chi);
             int64_t *cells = (int64_t *)malloc((size_t)cnt * sizeof(int64_t));

@@ -144,3 +144,85 @@ def test_empty_meshes():
         lo, hi, inv, n = oracle.default_grid([A, B], 1.0)
         g = oracle.grid_search(x, y, lo, inv, n)
         assert len(g.cand) == 0 and len(g.hits) == 0
+
+
+# --------------------------------------------------- world-bound pruning
+
+def _shifted_pair(n, shift, seed=0):
+    """The plain pair with B moved along x, so that part of each mesh lies
+    outside the other's box."""
+    A, B = synth.plain_pair(n, n, seed)
+    V = B.verts.copy()
+    V[..., 0] += shift
+    return A, synth.Mesh(V, B.theta, B.s, B.periodic)
+
+
+def _tri_boxes(m):
+    boxes = []
+    for t in range(oracle.n_tris(m)):
+        v = oracle.tri_verts(m, t)
+        boxes.append((v.min(axis=0), v.max(axis=0), bool(np.all(np.isfinite(v)))))
+    return boxes
+
+
+def _pruned_stats_numpy(A, B, grid):
+    """Boxes and slots of the restricted grid of Sec. 6.2.1, counted
+    independently: the triangles whose box meets the other mesh's box (over
+    its finite triangles), their cells, and per cell nA * nB."""
+    lo, _, inv, n = grid
+    bx = [_tri_boxes(A), _tri_boxes(B)]
+    mb = []
+    for boxes in bx:
+        fl = [b for b in boxes if b[2]]
+        mb.append((np.min([b[0] for b in fl], axis=0), np.max([b[1] for b in fl], axis=0)))
+    counts = {}
+    kept = [0, 0]
+    for sd, (m, boxes) in enumerate(zip((A, B), bx)):
+        olo, ohi = mb[1 - sd]
+        for t, (tlo, thi, fin) in enumerate(boxes):
+            if not fin or not (np.all(tlo <= ohi) and np.all(olo <= thi)):
+                continue
+            kept[sd] += 1
+            for c in oracle.tri_entries(m, t, lo, inv, n):
+                counts.setdefault(int(c), [0, 0])[sd] += 1
+    both = [v for v in counts.values() if v[0] and v[1]]
+    return len(both), sum(a * b for a, b in both), kept
+
+
+@pytest.mark.parametrize("shift", [0.0, 0.9, 1.7])
+def test_pruning_keeps_hits_and_candidates(shift):
+    """The restricted grid finds the same candidates and hits (no pair with a
+    triangle outside the other mesh's box has overlapping boxes), counts the
+    same entries before the restriction, and its boxes and slots are those
+    of the triangles that meet the other mesh's box."""
+    A, B = _shifted_pair(24, shift)
+    grid = oracle.default_grid([A, B], 1.0)
+    full = oracle.grid_search(A, B, grid[0], grid[2], grid[3])
+    pr = oracle.grid_search(A, B, grid[0], grid[2], grid[3], prune=True)
+    assert np.array_equal(pr.cand, full.cand)
+    assert np.array_equal(pr.hits["triA"], full.hits["triA"]) and np.array_equal(pr.hits["triB"], full.hits["triB"])
+    assert pr.n_entries == full.n_entries
+    nb, ns, kept = _pruned_stats_numpy(A, B, grid)
+    assert (pr.n_boxes, pr.n_slots) == (nb, ns)
+    if shift == 0.0:
+        assert (pr.n_boxes, pr.n_slots) == (full.n_boxes, full.n_slots)
+    else:
+        # the shifted pair loses triangles on both sides (and slots, where
+        # a lost triangle shared a cell with the other mesh)
+        assert kept[0] < oracle.n_tris(A) and kept[1] < oracle.n_tris(B)
+        assert pr.n_slots <= full.n_slots
+
+
+def test_pruning_with_nonfinite_triangles():
+    """A vertex made NaN removes its triangles from the boxes of Sec. 6.2.1:
+    the restricted grid still equals the independent count."""
+    A, B = _shifted_pair(16, 1.2, seed=3)
+    V = A.verts.copy()
+    V[3, 5, 1] = np.nan
+    A = synth.Mesh(V, A.theta, A.s, A.periodic)
+    grid = oracle.default_grid([A, B], 1.5)
+    full = oracle.grid_search(A, B, grid[0], grid[2], grid[3])
+    pr = oracle.grid_search(A, B, grid[0], grid[2], grid[3], prune=True)
+    assert np.array_equal(pr.cand, full.cand)
+    nb, ns, _ = _pruned_stats_numpy(A, B, grid)
+    assert (pr.n_boxes, pr.n_slots) == (nb, ns)
