@@ -480,6 +480,25 @@ def main():
         out["layers_quad_pairs_per_s"] = quads / t_l
         out["layers_hits"] = int(lst["n_hits"])
         out["layers_counts_equal_plain"] = bool(same)
+        # the same search without world-bound pruning, same tuned tuple
+        lsu = ms.LayerSearch(U, S, lp.D_u, lp.lam_u, lp.D_s, lp.lam_s, lp.n_layers, kappa=ls.kappa, hits_cap=1 << 16,
+                             prune=False)
+        for pu, pt in zip(lsu.params, ls.params):
+            pu.table_log2, pu.enum_shape = pt.table_log2, pt.enum_shape
+        lsu.batch = ms.Batch(lsu.meshes, lsu.params, hits_cap=1 << 16, cand_cap=1 << 22)
+        lsu.run(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            lsu.batch.run(True)
+        torch.cuda.synchronize()
+        t_u = (time.perf_counter() - t0) / reps
+        ust = lsu.batch.stats_dict()
+        out["layers_batched_ms_unpruned"] = t_u * 1e3
+        out["layers_pruned_counts_equal_unpruned"] = bool(ust["n_hits"] == lst["n_hits"] and ust["n_cand"] == lst["n_cand"])
+        log(f"layers: without world-bound pruning {t_u * 1e3:.2f} ms (hits {ust['n_hits']}, candidates equal "
+            f"{ust['n_cand'] == lst['n_cand']})")
+        del lsu
         leg_roof["layers_batched"] = batch_roofline(ms, ls.batch, ls.meshes)
         log(f"layers: {len(ls.meshes)} half-layer pairs ({quads:.3e} quad pairs) batched in {t_l * 1e3:.2f} ms, "
             f"pair by pair {t_p * 1e3:.2f} ms, {lst['n_hits']} hits, counts equal={same}")

@@ -120,7 +120,13 @@ int mesh_update(ms_mesh *mesh, void *stream);
 /* Search flags. */
 enum {
     MS_SEARCH_CANDIDATES = 1,   /* also write the candidate set C to cand_dev */
-    MS_SEARCH_STRICT = 2        /* fail with MS_E_NONFINITE if a mesh has non-finite triangles */
+    MS_SEARCH_STRICT = 2,       /* fail with MS_E_NONFINITE if a mesh has non-finite triangles */
+    MS_SEARCH_PRUNE = 4         /* world-bound pruning (Sec. 6.2.1): a triangle whose box misses the
+                                   other mesh's box (over its finite vertices, computed by the search
+                                   itself: one block per mesh, so it pays for small meshes such as
+                                   half-layers) takes no part in the grid.  Hits and candidates do not
+                                   change; n_cells and n_slots then describe the pruned grid
+                                   (n_entries_all still counts every finite triangle's cells). */
 };
 
 /*

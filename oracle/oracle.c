@@ -547,7 +547,7 @@ static void range_cells(const int64_t clo[4], const int64_t chi[4], const int64_
  *
  * prune != 0: the world-bound restriction remarked on in Sec. 6.2.1 -- the
  * grid only holds triangles whose box meets the other mesh's box (the box of
- * that mesh's finite triangles); no pair with a triangle outside can have
+ * that mesh's finite vertices); no pair with a triangle outside can have
  * overlapping boxes.  n_entries still counts every finite triangle's cells;
  * n_boxes and n_slots are those of the restricted grid. */
 ORC_API int orc_grid_search(const orc_mesh *A, const orc_mesh *B, const double *wlo,
@@ -561,16 +561,20 @@ ORC_API int orc_grid_search(const orc_mesh *A, const orc_mesh *B, const double *
     if (table_build(A, &T[0], &res->counts[6]) || table_build(B, &T[1], &res->counts[7])) return -1;
     int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
 
-    /* each mesh's box over its finite triangles (for the pruning) */
+    /* each mesh's box over its finite vertices (for the pruning; it holds
+     * every finite triangle) */
     int64_t ntri[2] = {T[0].n, T[1].n};
+    const orc_mesh *M[2] = {A, B};
     double mlo[2][4], mhi[2][4];
     for (int sd = 0; sd < 2; ++sd) {
         for (int d = 0; d < 4; ++d) { mlo[sd][d] = INFINITY; mhi[sd][d] = -INFINITY; }
-        for (int64_t t = 0; t < ntri[sd]; ++t) {
-            if (!T[sd].fin[t]) continue;
+        const int64_t nv = ntri[sd] > 0 ? (int64_t)M[sd]->n_theta_v * M[sd]->n_s_v : 0;
+        for (int64_t k = 0; k < nv; ++k) {
+            const double *x = M[sd]->V + 4 * k;
+            if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(x[3]))) continue;
             for (int d = 0; d < 4; ++d) {
-                if (T[sd].lo[4 * t + d] < mlo[sd][d]) mlo[sd][d] = T[sd].lo[4 * t + d];
-                if (T[sd].hi[4 * t + d] > mhi[sd][d]) mhi[sd][d] = T[sd].hi[4 * t + d];
+                if (x[d] < mlo[sd][d]) mlo[sd][d] = x[d];
+                if (x[d] > mhi[sd][d]) mhi[sd][d] = x[d];
             }
         }
     }

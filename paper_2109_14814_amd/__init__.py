@@ -21,7 +21,7 @@ LIB_PATH = os.environ.get("MSEARCH_LIB") or os.path.join(_HERE, "libmsearch.so")
 
 MS_OK, MS_E_ARG, MS_E_CAPACITY, MS_E_HIP, MS_E_NONFINITE, MS_E_KEYBITS, MS_E_WORKSPACE = 0, -1, -2, -3, -4, -5, -6
 MS_LAYOUT_AOS, MS_LAYOUT_SOA = 0, 1
-MS_SEARCH_CANDIDATES, MS_SEARCH_STRICT = 1, 2
+MS_SEARCH_CANDIDATES, MS_SEARCH_STRICT, MS_SEARCH_PRUNE = 1, 2, 4
 MS_ENUM_WIDE, MS_ENUM_HALF, MS_ENUM_QUARTER = 1, 2, 3
 
 # Exported entry points (the C ABI of include/msearch.h).
@@ -370,25 +370,27 @@ def _device_tag() -> str:
     return f"{arch.split(':')[0]}x{pr.multi_processor_count}"
 
 
-def tuned_params(A: Mesh, B: Mesh, choice: dict) -> SearchParams:
+def tuned_params(A: Mesh, B: Mesh, choice: dict, flags: int = 0) -> SearchParams:
     """The search parameters of a tuned choice (tune.tune)."""
     p = default_params(A, B, choice["kappa"])
     p.table_log2 = int(choice["table_log2"])
     p.enum_shape = int(choice["enum_shape"])
+    p.flags = int(flags)
     return p
 
 
 def autotune(pairs, batch: bool = False, reps: int | None = None, hits_cap: int = 1 << 16,
-             cand_cap: int = 1 << 20, use_cache: bool = True, cache_path: str | None = None):
+             cand_cap: int = 1 << 20, use_cache: bool = True, cache_path: str | None = None, flags: int = 0):
     """The tuned (kappa, table_log2, enum_shape) of a plain search of one
     pair or of a batched search of many (tune.tune: joint sweep, cached per
-    size bucket).  Returns (choice, per-pair parameters, timings)."""
+    size bucket), timed with the search flags `flags`.  Returns (choice,
+    per-pair parameters, timings)."""
     if reps is None:
         reps = 3 if batch else 20
 
     def measure(kappa, table, shape):
         ch = {"kappa": kappa, "table_log2": table, "enum_shape": shape}
-        params = [tuned_params(a, b, ch) for a, b in pairs]
+        params = [tuned_params(a, b, ch, flags) for a, b in pairs]
         if batch:
             bt = Batch(pairs, params, hits_cap=hits_cap, cand_cap=cand_cap)
             bt.run_checked(True)
@@ -401,8 +403,9 @@ def autotune(pairs, batch: bool = False, reps: int | None = None, hits_cap: int 
         s.check_overflow()
         return t
 
-    choice, times = _tune.tune(pairs, measure, _device_tag(), batch, use_cache, cache_path)
-    return choice, [tuned_params(a, b, choice) for a, b in pairs], times
+    choice, times = _tune.tune(pairs, measure, _device_tag() + (f"|flags{flags}" if flags else ""), batch, use_cache,
+                               cache_path)
+    return choice, [tuned_params(a, b, choice, flags) for a, b in pairs], times
 
 
 def autotune_kappa(A: Mesh, B: Mesh, hits_cap: int = 1 << 10, cand_cap: int = 1 << 20, use_cache: bool = True):
@@ -411,10 +414,11 @@ def autotune_kappa(A: Mesh, B: Mesh, hits_cap: int = 1 << 10, cand_cap: int = 1 
     return choice, params[0], times
 
 
-def autotune_batch_kappa(pairs, hits_cap: int = 1 << 16, cand_cap: int = 1 << 22, use_cache: bool = True):
+def autotune_batch_kappa(pairs, hits_cap: int = 1 << 16, cand_cap: int = 1 << 22, use_cache: bool = True,
+                         flags: int = 0):
     """The tuned choice for a batch (one choice for every pair, one captured
     graph per trial): (choice, per-pair parameters, timings)."""
-    return autotune(pairs, True, hits_cap=hits_cap, cand_cap=cand_cap, use_cache=use_cache)
+    return autotune(pairs, True, hits_cap=hits_cap, cand_cap=cand_cap, use_cache=use_cache, flags=flags)
 
 
 LAYER_PAIR_DTYPE = np.dtype([("u_layer", "<i4"), ("u_sign", "<i4"), ("s_layer", "<i4"), ("s_sign", "<i4")])
@@ -452,7 +456,7 @@ class LayerSearch:
     sub-mesh sharing the vertices, searched together as one batch."""
 
     def __init__(self, U: Mesh, S: Mesh, D_u: float, lam_u: float, D_s: float, lam_s: float, n_layers: int,
-                 kappa=None, hits_cap: int = 1 << 16, cand_cap: int = 1 << 22):
+                 kappa=None, hits_cap: int = 1 << 16, cand_cap: int = 1 << 22, prune: bool = True):
         self.pairs = layer_pairs(n_layers)
         cache = {}
 
@@ -465,13 +469,18 @@ class LayerSearch:
         self.meshes = [(half(U, False, D_u, lam_u, int(p["u_layer"]), int(p["u_sign"])),
                         half(S, True, D_s, lam_s, int(p["s_layer"]), int(p["s_sign"]))) for p in self.pairs]
         self.halves = cache
+        # world-bound pruning (Sec. 6.2.1): a half-layer's triangles outside
+        # the other half-layer's box take no part (the hits do not change)
+        flags = MS_SEARCH_PRUNE if prune else 0
         if kappa is None:
             self.tuned, params, self.kappa_times = autotune_batch_kappa(self.meshes, hits_cap=hits_cap,
-                                                                        cand_cap=cand_cap)
+                                                                        cand_cap=cand_cap, flags=flags)
             self.kappa = self.tuned["kappa"]
         else:
             self.kappa, self.kappa_times, self.tuned = float(kappa), {}, None
             params = [default_params(a, b, self.kappa) for a, b in self.meshes]
+            for p in params:
+                p.flags = flags
         self.params = params
         self.batch = Batch(self.meshes, params, hits_cap=hits_cap, cand_cap=cand_cap)
 

@@ -86,7 +86,7 @@ struct PairDesc {
     uint64_t cell_base;
     int64_t tile_off;
     int32_t nA, nB;
-    int32_t tilesA, pad_;
+    int32_t tilesA, prune;     // prune: MS_SEARCH_PRUNE
     uint64_t st[4];     // linear-id strides of the cells: n1 n2 n3, n2 n3, n3, 1
     uint64_t fbs[4];    // fine table: linear-id strides of its blocks (cell index / 2 per axis)
     uint32_t fbh[4];    //   and fbs * HASH_MUL mod 2^32
@@ -418,7 +418,7 @@ MS_D uint32_t count_both(const BitRef &t, const Range32 &r, const uint64_t bs[4]
 // Compact cell range: lo cell per axis in 12 bits (bits 0..47), extent per
 // axis in 4 bits (48..63).  Two values no range can take mark a non-finite
 // triangle and a range too large to pack (recomputed from the box).
-constexpr uint64_t RNG_NONFINITE = ~0ull;
+constexpr uint64_t RNG_NONFINITE = ~0ull;   // no entries: a non-finite or pruned triangle
 constexpr uint64_t RNG_FROM_BOX = ~0ull - 1;
 
 MS_D uint64_t pack_range(const CellRange &r, bool packable)
@@ -739,7 +739,24 @@ struct QuadVerts {
     bool fin[4];
 };
 
-MS_D void quad_vertices(const MeshView &m, int32_t q, const PairDesc &P, QuadVerts &qv)
+// Whether the box of the triangle with vertices u, v, w meets the box ob
+// (lo[4], hi[4]): closed intervals, per axis.
+MS_D bool tri_meets_box(const d4 &u, const d4 &v, const d4 &w, const double *ob)
+{
+    const double a[4] = {u.x, u.y, u.z, u.w}, b[4] = {v.x, v.y, v.z, v.w}, c[4] = {w.x, w.y, w.z, w.w};
+    bool meet = true;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const double lo = fmin(fmin(a[d], b[d]), c[d]), hi = fmax(fmax(a[d], b[d]), c[d]);
+        meet = meet && lo <= ob[4 + d] && ob[d] <= hi;
+    }
+    return meet;
+}
+
+// ob: the other mesh's box (MS_SEARCH_PRUNE) or null; keep1 / keep2: the
+// quad's triangles meet it (always true without pruning).
+MS_D void quad_vertices(const MeshView &m, int32_t q, const PairDesc &P, QuadVerts &qv, const double *ob,
+                        bool &keep1, bool &keep2)
 {
     int32_t k, i;
     quad_row_col(m, q, k, i);
@@ -750,6 +767,11 @@ MS_D void quad_vertices(const MeshView &m, int32_t q, const PairDesc &P, QuadVer
     d4 x[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) x[j] = load_d4(m.V + 4 * (int64_t)id[j]);
+    keep1 = keep2 = true;
+    if (ob) {
+        keep1 = tri_meets_box(x[1], x[0], x[2], ob);    // T1 = (b, a, c)
+        keep2 = tri_meets_box(x[2], x[3], x[1], ob);    // T2 = (c, d, b)
+    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const double w[4] = {x[j].x, x[j].y, x[j].z, x[j].w};
@@ -775,6 +797,66 @@ MS_D void quad_ranges(const QuadVerts &qv, Range32 &r1, bool &ok1, Range32 &r2, 
     ok2 = qv.fin[1] & qv.fin[2] & qv.fin[3];
 }
 
+// World-bound pruning (MS_SEARCH_PRUNE, Sec. 6.2.1): the box of each mesh of
+// each pair over its finite vertices (lo = +inf, hi = -inf without one), one
+// block per (pair, side), written to pbox[8 (2 p + side) ..] as lo[4], hi[4].
+// Every finite triangle lies in it.  Pairs without the flag write nothing.
+constexpr int BOUNDS_BLOCK = 1024;
+
+template <bool ONE>
+__global__ void __launch_bounds__(BOUNDS_BLOCK) k_bounds(BatchView bv, double *pbox)
+{
+    __shared__ double s_red[8][BOUNDS_BLOCK / WAVE];
+    const int p = (int)(blockIdx.x >> 1), side = (int)(blockIdx.x & 1);
+    const PairDesc &P = pair_desc<ONE>(bv, p);
+    if (!P.prune) return;
+    const MeshView &m = side_mesh(P, side);
+    double v[8];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        v[d] = INFINITY;
+        v[4 + d] = -INFINITY;
+    }
+    const int64_t nv = m.n_tris > 0 ? (int64_t)m.n_theta_v * m.n_s_v : 0;
+    constexpr int U = 4;     // loads in flight per thread
+    for (int64_t base = 0; base < nv; base += (int64_t)U * BOUNDS_BLOCK) {
+        d4 x[U];
+        bool in[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t j = base + (int64_t)u * BOUNDS_BLOCK + threadIdx.x;
+            in[u] = j < nv;
+            if (in[u]) x[u] = load_d4(m.V + 4 * j);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!in[u]) continue;
+            const double w[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
+            if (!(isfinite(w[0]) && isfinite(w[1]) && isfinite(w[2]) && isfinite(w[3]))) continue;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                v[d] = fmin(v[d], w[d]);
+                v[4 + d] = fmax(v[4 + d], w[d]);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        for (int o = WAVE / 2; o > 0; o >>= 1) {
+            const double u = __shfl_xor(v[k], o);
+            v[k] = k < 4 ? fmin(v[k], u) : fmax(v[k], u);
+        }
+        if (lane_id() == 0) s_red[k][threadIdx.x / WAVE] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        const int k = threadIdx.x;
+        double r = s_red[k][0];
+        for (int w = 1; w < BOUNDS_BLOCK / WAVE; ++w) r = k < 4 ? fmin(r, s_red[k][w]) : fmax(r, s_red[k][w]);
+        pbox[8 * (int64_t)blockIdx.x + k] = r;
+    }
+}
+
 // Occupancy: one byte per hashed global cell and side, set with plain stores
 // (all writers store the same value), fine and coarse.  Stores each
 // triangle's compact cell range and per-block entry / non-finite totals.
@@ -783,7 +865,7 @@ MS_D void quad_ranges(const QuadVerts &qv, Range32 &r1, bool &ok1, Range32 &r2, 
 // blocks share an XCD (xcd_block).
 template <bool ONE, bool C32>
 __global__ void __launch_bounds__(BLOCK) k_mark(BatchView bv, uint8_t *flags, const uint64_t *epoch, uint64_t *rng,
-                                                unsigned long long *partial, ClearSpec c)
+                                                const double *pbox, unsigned long long *partial, ClearSpec c)
 {
     __shared__ unsigned long long s_tmp[BLOCK / WAVE];
     if (blockIdx.x == 0) {
@@ -811,22 +893,27 @@ __global__ void __launch_bounds__(BLOCK) k_mark(BatchView bv, uint8_t *flags, co
         const MeshView &m = side_mesh(P, L.side);
         uint8_t *fine = flags + ((size_t)L.side << lg);
         uint8_t *coarse = flags + ((size_t)2 << lg) + ((size_t)L.side << lc);
+        // the other mesh's box when pruning: a triangle that misses it is
+        // counted (its cells) but neither marked nor keyed
+        const double *ob = P.prune ? pbox + 8 * (2 * (int64_t)L.p + (1 - L.side)) : nullptr;
         if constexpr (C32) {
             QuadVerts qv;
-            quad_vertices(m, q, P, qv);
+            bool keep1, keep2;
+            quad_vertices(m, q, P, qv, ob, keep1, keep2);
             Range32 r1, r2;
             bool ok1, ok2;
             quad_ranges(qv, r1, ok1, r2, ok2);
+            const bool k1 = ok1 && keep1, k2 = ok2 && keep2;
             ulonglong2 rr;
-            rr.x = ok1 ? pack_range32(r1, bv.packable != 0) : RNG_NONFINITE;
-            rr.y = ok2 ? pack_range32(r2, bv.packable != 0) : RNG_NONFINITE;
+            rr.x = k1 ? pack_range32(r1, bv.packable != 0) : RNG_NONFINITE;
+            rr.y = k2 ? pack_range32(r2, bv.packable != 0) : RNG_NONFINITE;
             *reinterpret_cast<ulonglong2 *>(rng + g) = rr;
             bad += (unsigned long long)(!ok1) + (unsigned long long)(!ok2);
             if (ok1) all += (unsigned long long)((r1.e[0] + 1) * (r1.e[1] + 1)) * (unsigned long long)((r1.e[2] + 1) * (r1.e[3] + 1));
             if (ok2) all += (unsigned long long)((r2.e[0] + 1) * (r2.e[1] + 1)) * (unsigned long long)((r2.e[2] + 1) * (r2.e[3] + 1));
-            mark_quad(TabRef{flags, (uint32_t)L.side << lg, lg}, r1, ok1, r2, ok2, P.fbs, P.fbh, P.cell_base, v);
-            mark_quad(TabRef{flags, ((uint32_t)2 << lg) + ((uint32_t)L.side << lc), lc}, coarse_range(r1), ok1,
-                      coarse_range(r2), ok2, P.cbs, P.cbh, P.cell_base, v);
+            mark_quad(TabRef{flags, (uint32_t)L.side << lg, lg}, r1, k1, r2, k2, P.fbs, P.fbh, P.cell_base, v);
+            mark_quad(TabRef{flags, ((uint32_t)2 << lg) + ((uint32_t)L.side << lc), lc}, coarse_range(r1), k1,
+                      coarse_range(r2), k2, P.cbs, P.cbh, P.cell_base, v);
         } else {
             // grids of 2^31 cells or more along an axis: 64-bit cells, one triangle at a time
             const uint64_t cb = P.cell_base;
@@ -837,8 +924,19 @@ __global__ void __launch_bounds__(BLOCK) k_mark(BatchView bv, uint8_t *flags, co
                     rng[g + h] = RNG_NONFINITE;
                     continue;
                 }
-                rng[g + h] = RNG_FROM_BOX;
                 all += (unsigned long long)range_count(r);
+                if (ob) {
+                    double lo[4], hi[4];
+                    tri_box(m, 2 * q + h, lo, hi);
+                    bool meet = true;
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) meet = meet && lo[d] <= ob[4 + d] && ob[d] <= hi[d];
+                    if (!meet) {
+                        rng[g + h] = RNG_NONFINITE;
+                        continue;
+                    }
+                }
+                rng[g + h] = RNG_FROM_BOX;
                 for_cells_xy(r, P.g.n, [&](const int64_t *c, uint64_t) { fine[blocked_index(c, P.fbs, cb, lg)] = v; });
                 CellRange rc;
                 int64_t nc[4];
@@ -2143,12 +2241,13 @@ struct Geometry {
     int bm_log2, bc_log2;
     int packable, c32;
     int enum_shape;
+    int prune;          // some pair asks for world-bound pruning
     uint64_t total_cells;
 };
 
 struct Layout {
     int64_t ent_cap, cand_cap, hits_cap;
-    size_t o_epoch, o_flags, o_both, o_grp, o_own, o_mix, o_gstat, o_ctrs, o_part, o_epart, o_rng, o_ent, o_epair, o_erank, o_ehash, o_sorted,
+    size_t o_epoch, o_flags, o_both, o_pbox, o_grp, o_own, o_mix, o_gstat, o_ctrs, o_part, o_epart, o_rng, o_ent, o_epair, o_erank, o_ehash, o_sorted,
         o_spair, o_sbox,
         o_cells, o_pstart, o_htmp, o_hkeys, o_halt, o_misc, o_desc, o_toff, o_cbase, total;
     int64_t n_kblocks, cell_cap, n_fwords, n_cwords, n_gtiles;
@@ -2221,6 +2320,8 @@ int geometry(int64_t n_pairs, const ms_mesh *const *A, const ms_mesh *const *B, 
         if (G.enum_shape == 0) G.enum_shape = prm[i].enum_shape;
     }
     if (G.enum_shape == 0) G.enum_shape = MS_ENUM_HALF;
+    for (int64_t i = 0; i < n_pairs; ++i)
+        if (prm[i].flags & MS_SEARCH_PRUNE) G.prune = 1;
     return MS_OK;
 }
 
@@ -2246,6 +2347,7 @@ void layout(const Geometry &G, Layout &L)
     L.o_gstat = take((size_t)L.n_gtiles * 16);
     L.o_ctrs = take(64);
     L.o_part = take((size_t)MAX_GRID * 16);
+    L.o_pbox = take((size_t)(G.n_pairs > 0 ? G.n_pairs : 1) * 2 * 8 * sizeof(double));
     L.o_epart = take((size_t)STAT_SHARDS * SHARD_WORDS * 8);
     L.o_rng = take((size_t)(G.n_tiles * TILE_TRIS + 1) * 8);
     L.o_ent = take((size_t)(L.ent_cap + 1) * 8);
@@ -2299,6 +2401,7 @@ PairDesc make_desc(const ms_mesh *A, const ms_mesh *B, const search_params_t *p,
     d.nA = A->view.n_tris;
     d.nB = B->view.n_tris;
     d.tilesA = (int32_t)ceil_div(d.nA, TILE_TRIS);
+    d.prune = (p->flags & MS_SEARCH_PRUNE) != 0;
     const uint64_t n1 = (uint64_t)p->n_cells[1], n2 = (uint64_t)p->n_cells[2], n3 = (uint64_t)p->n_cells[3];
     d.st[0] = n1 * n2 * n3;
     d.st[1] = n2 * n3;
@@ -2362,6 +2465,7 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
     uint32_t *ctrs = (uint32_t *)(ws + L.o_ctrs);     // [1] k_groups tile counter
     unsigned long long *n_keys = (unsigned long long *)(ctrs + 4);   // entries reserved by k_keys
     unsigned long long *mpart = (unsigned long long *)(ws + L.o_part);
+    double *pbox = (double *)(ws + L.o_pbox);
     unsigned long long *epart = (unsigned long long *)(ws + L.o_epart);
     uint64_t *rng = (uint64_t *)(ws + L.o_rng);
     uint64_t *ent = (uint64_t *)(ws + L.o_ent);
@@ -2388,10 +2492,15 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
     cs.w[1] = (uint64_t *)ctrs;
     cs.n[1] = 8;
     const unsigned g_tri = (unsigned)(G.n_tiles < MAX_GRID ? (G.n_tiles > 0 ? G.n_tiles : 1) : MAX_GRID);
+    if (G.prune)
+        MS_LAUNCH("k_bounds", k_bounds<ONE>, dim3((unsigned)(2 * (G.n_pairs > 0 ? G.n_pairs : 1))),
+                  dim3(BOUNDS_BLOCK), 0, st, bv, pbox);
     if (G.c32)
-        MS_LAUNCH("k_mark", (k_mark<ONE, true>), dim3(g_tri), dim3(BLOCK), 0, st, bv, flags, epoch, rng, mpart, cs);
+        MS_LAUNCH("k_mark", (k_mark<ONE, true>), dim3(g_tri), dim3(BLOCK), 0, st, bv, flags, epoch, rng, pbox, mpart,
+                  cs);
     else
-        MS_LAUNCH("k_mark", (k_mark<ONE, false>), dim3(g_tri), dim3(BLOCK), 0, st, bv, flags, epoch, rng, mpart, cs);
+        MS_LAUNCH("k_mark", (k_mark<ONE, false>), dim3(g_tri), dim3(BLOCK), 0, st, bv, flags, epoch, rng, pbox, mpart,
+                  cs);
     MS_LAUNCH("k_pack", k_pack, dim3(grid_for(L.n_fwords + L.n_cwords, 4096)), dim3(BLOCK), 0, st, flags, epoch,
               G.bm_log2, G.bc_log2, both, grp, mix, L.n_fwords, L.n_cwords);
     KeysOut ko;

@@ -189,3 +189,38 @@ def test_one_call_batched_search(ms, use_graph):
     assert st3["n_hits"] == tot_h
     for g, r in zip(other, per_pair):
         assert_same_hits(g, r, exact=True)
+
+
+def test_pruned_graph_replay_follows_moved_vertices(ms):
+    """World-bound pruning in a captured graph: the meshes' boxes are
+    computed by the search itself, so after B's vertices move in place a
+    replay prunes against the new boxes and equals fresh plain searches, with
+    and without pruning."""
+    import torch
+    fam = small_family(12, 7)
+    gp = [(ms.Mesh.from_synth(a), ms.Mesh.from_synth(b)) for a, b in fam]
+    params = []
+    for a, b in gp:
+        p = ms.default_params(a, b, 1.0)
+        p.flags = ms.MS_SEARCH_PRUNE
+        params.append(p)
+    bt = ms.Batch(gp, params, hits_cap=1 << 12, cand_cap=1 << 16)
+    bt.run_checked(True)
+    for shift in (0.35, -0.6):
+        for _, b in gp:
+            b.verts[..., 0] += shift
+            b.update()
+        torch.cuda.synchronize()
+        bt.run(True)
+        torch.cuda.synchronize()
+        got, st = bt.results()
+        assert st["overflow"] == 0
+        n_hits = 0
+        for (a, b), p, g in zip(gp, params, got):
+            hits, _, _ = ms.search(a, b, p, hits_cap=1 << 12, cand_cap=1 << 18)
+            assert_same_hits(g, hits, exact=True)
+            q = ms.make_params(list(p.world_lo), p.inv_edge, list(p.n_cells))
+            full, _, _ = ms.search(a, b, q, hits_cap=1 << 12, cand_cap=1 << 18)
+            assert_same_hits(g, full, exact=True)
+            n_hits += len(g)
+        assert n_hits == st["n_hits"]

@@ -79,3 +79,35 @@ def test_layer_search_equals_plain_searches(ms):
         assert_same_hits(x1, hits)
         tot += len(hits)
     assert tot == st0["n_hits"] and tot > 0
+
+
+def test_pruned_layer_search(ms):
+    """The layer search with and without world-bound pruning: the same hits
+    and candidates per pair; the cells and slots of each pair equal the
+    oracle's restricted grid."""
+    lp = synth.layered_pair(64, 96, 6, 3, 2)
+    U, S = ms.Mesh.from_synth(lp.U), ms.Mesh.from_synth(lp.S)
+    ls_p = ms.LayerSearch(U, S, lp.D_u, lp.lam_u, lp.D_s, lp.lam_s, lp.n_layers, kappa=1.5, hits_cap=1 << 14)
+    ls_f = ms.LayerSearch(U, S, lp.D_u, lp.lam_u, lp.D_s, lp.lam_s, lp.n_layers, kappa=1.5, hits_cap=1 << 14,
+                          prune=False)
+    ls_p.run(True)
+    ls_f.run(True)
+    hp, stp = ls_p.results()
+    hf, stf = ls_f.results()
+    for x, y in zip(hp, hf):
+        assert_same_hits(x, y)
+    assert stp["n_cand"] == stf["n_cand"] and stp["n_entries_all"] == stf["n_entries_all"]
+    cells = slots = 0
+    for (a, b), p in zip(ls_p.meshes, ls_p.params):
+        assert p.flags & ms.MS_SEARCH_PRUNE
+    for p in oracle.layer_pairs(lp.n_layers):
+        n, sa, m, sb = p
+        ku = oracle.half_layer_columns(lp.U.s, lp.D_u, lp.lam_u, False, n, sa)
+        ks = oracle.half_layer_columns(lp.S.s, lp.D_s, lp.lam_s, True, m, sb)
+        A, B = half(lp.U, ku), half(lp.S, ks)
+        g = oracle.default_grid([A, B], 1.5)
+        ref = oracle.grid_search(A, B, g[0], g[2], g[3], prune=True)
+        cells += ref.n_boxes
+        slots += ref.n_slots
+    assert (stp["n_cells"], stp["n_slots"]) == (cells, slots)
+    assert stp["n_slots"] <= stf["n_slots"]

@@ -344,3 +344,26 @@ def test_default_params_match_oracle_grid(ms):
     assert np.allclose(list(p.world_lo), lo, rtol=0, atol=0)
     assert abs(p.inv_edge - inv) / inv < 1e-12
     assert np.abs(np.array(list(p.n_cells)) - n).max() <= 1
+
+
+def _shifted_pair(n, shift, seed=0):
+    A, B = synth.plain_pair(n, n, seed)
+    V = B.verts.copy()
+    V[..., 0] += shift
+    return A, synth.Mesh(V, B.theta, B.s, B.periodic)
+
+
+@pytest.mark.parametrize("n,shift,kappa", [(48, 0.9, 1.0), (48, 1.7, 2.0), (96, 0.6, 1.5), (512, 0.4, 1.5)])
+def test_pruned_search_matches_pruned_oracle(ms, n, shift, kappa):
+    """World-bound pruning (MS_SEARCH_PRUNE, Sec. 6.2.1) on pairs shifted so
+    that part of each mesh lies outside the other's box: candidates and hits
+    equal the unpruned oracle's, and every counter equals the oracle's
+    restricted grid."""
+    A, B = _shifted_pair(n, shift)
+    grid = oracle.default_grid([A, B], kappa)
+    full = oracle.grid_search(A, B, grid[0], grid[2], grid[3])
+    pr = oracle.grid_search(A, B, grid[0], grid[2], grid[3], prune=True)
+    hits, st, cand = gpu_search(ms, A, B, grid, flags=ms.MS_SEARCH_CANDIDATES | ms.MS_SEARCH_PRUNE)
+    check_against(full, hits, st, cand)
+    assert st["n_entries_all"] == pr.n_entries == full.n_entries
+    assert (st["n_cells"], st["n_slots"]) == (pr.n_boxes, pr.n_slots)

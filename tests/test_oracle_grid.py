@@ -168,13 +168,14 @@ def _tri_boxes(m):
 def _pruned_stats_numpy(A, B, grid):
     """Boxes and slots of the restricted grid of Sec. 6.2.1, counted
     independently: the triangles whose box meets the other mesh's box (over
-    its finite triangles), their cells, and per cell nA * nB."""
+    its finite vertices), their cells, and per cell nA * nB."""
     lo, _, inv, n = grid
     bx = [_tri_boxes(A), _tri_boxes(B)]
     mb = []
-    for boxes in bx:
-        fl = [b for b in boxes if b[2]]
-        mb.append((np.min([b[0] for b in fl], axis=0), np.max([b[1] for b in fl], axis=0)))
+    for m in (A, B):
+        v = m.verts.reshape(-1, 4)
+        v = v[np.all(np.isfinite(v), axis=1)]
+        mb.append((v.min(axis=0), v.max(axis=0)))
     counts = {}
     kept = [0, 0]
     for sd, (m, boxes) in enumerate(zip((A, B), bx)):
@@ -214,7 +215,7 @@ def test_pruning_keeps_hits_and_candidates(shift):
 
 
 def test_pruning_with_nonfinite_triangles():
-    """A vertex made NaN removes its triangles from the boxes of Sec. 6.2.1:
+    """A vertex made NaN leaves the mesh's box and removes its triangles:
     the restricted grid still equals the independent count."""
     A, B = _shifted_pair(16, 1.2, seed=3)
     V = A.verts.copy()
