@@ -522,11 +522,20 @@ def main():
         t_rk = time.perf_counter() - t0
         t0 = time.perf_counter()
         gu.update(); gs.update()
-        pp = ms.default_params(gu, gs, kappa)
+        # the propagated patches are a regime of their own (millions of
+        # box-overlapping pairs): their own tuned tuple
+        ptuned, pp, _ = ms.autotune_kappa(gu, gs, hits_cap=1 << 14, cand_cap=1 << 22)
+        t0 = time.perf_counter()
         sp = ms.Searcher(gu, gs, pp, hits_cap=1 << 14, cand_cap=1 << 22)
         sp.run()
         hp, stp, _ = sp.results()
         t_s = time.perf_counter() - t0
+        sp.run()
+        torch.cuda.synchronize()
+        t_q = ms._time_ms(sp.run_async, 5)
+        out["propagated_search_ms"] = t_q
+        out["propagated_search_tuned"] = ptuned
+        out["propagated_search_stats"] = stp
         x0 = np.stack([hp["thA"], hp["sA"], hp["thB"], hp["sB"]], axis=1)
         t0 = time.perf_counter()
         xr, _, rr, sr, tr = ms.refine_newton(x0, ms.patch_row(pr.patch_u), ms.patch_row(pr.patches_s[0]),
@@ -547,7 +556,9 @@ def main():
         out["propagated_refined_converged"] = int(np.sum(sr == 0))
         out["propagated_root_error"] = float(np.max(np.abs(xr.cpu().numpy() - pr.roots[0]))) if len(hp) else None
         log(f"propagated: F^3 + F^-3 of 2 x {base_u.numel() // 4} vertices in {t_rk * 1e3:.1f} ms, search "
-            f"{t_s * 1e3:.2f} ms ({len(hp)} hits), refine {t_r * 1e3:.1f} ms ({int(np.sum(sr == 0))} converged)")
+            f"{t_q:.2f} ms ({t_s * 1e3:.2f} ms with set-up; {len(hp)} hits, {stp['n_cand']} candidates, tuned "
+            f"kappa {ptuned['kappa']}, tile {ptuned['enum_shape']}), refine {t_r * 1e3:.1f} ms "
+            f"({int(np.sum(sr == 0))} converged)")
         del gu, gs, base_u, base_s, sp
 
     # ------------- the position-momentum model of Sec. 3.3: F^+-3 and DF^3

@@ -19,7 +19,7 @@ import json
 import math
 import os
 
-KAPPAS = (0.5, 0.75, 1.0, 1.5, 2.0, 3.0, 4.0)
+KAPPAS = (0.25, 0.35, 0.5, 0.75, 1.0, 1.5, 2.0, 3.0, 4.0)
 BATCH_KAPPAS = (1.0, 1.5, 2.0, 3.0)
 SHAPES = (1, 2, 3)          # MS_ENUM_WIDE, MS_ENUM_HALF, MS_ENUM_QUARTER
 DEFAULT_SHAPE = 2
