@@ -88,9 +88,9 @@ struct PairDesc {
     int32_t nA, nB;
     int32_t tilesA, prune;     // prune: MS_SEARCH_PRUNE
     uint64_t st[4];     // linear-id strides of the cells: n1 n2 n3, n2 n3, n3, 1
-    uint64_t fbs[4];    // fine table: linear-id strides of its blocks (cell index / 2 per axis)
+    uint32_t fbs[4];    // fine table: linear-id strides of its blocks (cell index / 2 per axis), mod 2^32
     uint32_t fbh[4];    //   and fbs * HASH_MUL mod 2^32
-    uint64_t cbs[4];    // coarse table (cell index / 2 per axis): strides of its blocks
+    uint32_t cbs[4];    // coarse table (cell index / 2 per axis): strides of its blocks, mod 2^32
     uint32_t cbh[4];    //   (cell index / 4 per axis) and cbs * HASH_MUL mod 2^32
     double nm1[4];      // n_d - 1
 };
@@ -279,7 +279,7 @@ MS_D uint32_t extent_mask(const Range32 &r)
 // blocks of the table's grid.
 
 // Hashed index of cell c (coordinates on the table's grid).
-MS_D uint32_t blocked_index(const int64_t c[4], const uint64_t bs[4], uint64_t cb, int lg)
+MS_D uint32_t blocked_index(const int64_t c[4], const uint32_t bs[4], uint64_t cb, int lg)
 {
     uint32_t lin = (uint32_t)cb;
 #pragma unroll
@@ -308,7 +308,7 @@ struct BlockWalk {
     uint32_t par0;
 };
 
-MS_D void walk_init(BlockWalk &w, const Range32 &u, const uint64_t bs[4], const uint32_t bh[4], uint64_t cb)
+MS_D void walk_init(BlockWalk &w, const Range32 &u, const uint32_t bs[4], const uint32_t bh[4], uint64_t cb)
 {
     uint32_t lin = (uint32_t)cb;
     w.par0 = 0;
@@ -390,7 +390,7 @@ MS_D uint32_t range_positions(const Range32 &r)
 }
 
 // Marks every cell of range r (any size).
-MS_D void mark_range(const TabRef &t, const Range32 &r, const uint64_t bs[4], const uint32_t bh[4], uint64_t cb,
+MS_D void mark_range(const TabRef &t, const Range32 &r, const uint32_t bs[4], const uint32_t bh[4], uint64_t cb,
                      uint8_t v)
 {
     if (range_small(r)) {
@@ -403,7 +403,7 @@ MS_D void mark_range(const TabRef &t, const Range32 &r, const uint64_t bs[4], co
 }
 
 // Number of cells of range r whose both-occupied bit is set (any range).
-MS_D uint32_t count_both(const BitRef &t, const Range32 &r, const uint64_t bs[4], const uint32_t bh[4], uint64_t cb)
+MS_D uint32_t count_both(const BitRef &t, const Range32 &r, const uint32_t bs[4], const uint32_t bh[4], uint64_t cb)
 {
     if (range_small(r)) {
         BlockWalk w;
@@ -717,7 +717,7 @@ MS_D Range32 range_union(const Range32 &a, const Range32 &b)
 // quad's finite triangles (ok1, ok2); a union wider than two cells on some
 // axis marks each triangle on its own.
 MS_D void mark_quad(const TabRef &t, const Range32 &r1, bool ok1, const Range32 &r2, bool ok2,
-                    const uint64_t bs[4], const uint32_t bh[4], uint64_t cb, uint8_t v)
+                    const uint32_t bs[4], const uint32_t bh[4], uint64_t cb, uint8_t v)
 {
     if (!ok1 && !ok2) return;
     const Range32 u = ok1 && ok2 ? range_union(r1, r2) : (ok1 ? r1 : r2);
@@ -1466,7 +1466,10 @@ MS_D void emit_hit(bool hit, const hit_t &h, uint64_t key, hit_t *hits, uint64_t
 // overlapping pair has, by monotonicity of the cell map), and only if the
 // closed boxes overlap (Sec. 6.2.2).
 //
-// Each block takes a chunk of S::slots consecutive slots.  Of every group the
+// Each block takes a chunk of consecutive slots: ITEMS per thread, or up to
+// ITEMS_MAX when that is enough for every chunk to have a block in the first
+// round of resident blocks (otherwise a few chunks past a full round would
+// wait for a second round, doubling the kernel's time).  Of every group the
 // chunk touches it needs only the A entries of the rows it covers (all of
 // them once it spans more than one row) and the B entries of those rows; when
 // these are at most S::stage in all, the block stages their cells, triangle
@@ -1475,21 +1478,22 @@ MS_D void emit_hit(bool hit, const hit_t &h, uint64_t key, hit_t *hits, uint64_t
 // narrow phase on the chunk's candidates.  Last, the exact cell statistics
 // (Alg. 1's boxes and slots) of the groups that start in the chunk.
 //
-// The work-tile shape: NT threads per block, ITEMS slots per thread (a chunk
-// is NT * ITEMS slots), STAGE staged entries, CELLS groups per chunk held in
-// LDS, PSTART slot offsets held in LDS, GRID blocks.  The narrow phase needs
+// The work-tile shape: NT threads per block, ITEMS (up to ITEMS_MAX) slots
+// per thread (a chunk is NT * ITEMS slots), STAGE staged entries (their LDS
+// also holds a chunk's candidates), CELLS groups per chunk held in LDS,
+// PSTART slot offsets held in LDS, GRID blocks.  The narrow phase needs
 // about 200 registers, so a SIMD holds two waves: one 512-thread block per
 // CU, or two 256-thread blocks when their LDS fits twice.  Results do not
 // depend on the shape, only the time.
-template <int NT, int ITEMS, int STAGE, int CELLS, int PSTART, int GRID>
+template <int NT, int ITEMS, int ITEMS_MAX, int STAGE, int CELLS, int PSTART, int GRID>
 struct EnumShape {
-    static constexpr int block = NT, items = ITEMS, slots = NT * ITEMS, stage = STAGE, cells = CELLS,
-                         pstart = PSTART, grid = GRID;
-    static_assert(ITEMS <= 32 && CELLS <= NT, "keep bits per thread; one group per thread");
+    static constexpr int block = NT, items = ITEMS, items_max = ITEMS_MAX, slots_max = NT * ITEMS_MAX, stage = STAGE,
+                         cells = CELLS, pstart = PSTART, grid = GRID;
+    static_assert(ITEMS <= ITEMS_MAX && ITEMS_MAX <= 32 && CELLS <= NT, "keep bits per thread; one group per thread");
 };
-using EnumWide = EnumShape<512, 8, 768, 256, 4096, 512>;     // one block per CU, two rounds
-using EnumHalf = EnumShape<256, 8, 384, 128, 2048, 1024>;    // two blocks per CU, two rounds
-using EnumQuarter = EnumShape<128, 8, 192, 64, 1024, 2048>;  // four blocks per CU, two rounds
+using EnumWide = EnumShape<512, 8, 10, 960, 256, 4096, 512>;     // one block per CU, two rounds
+using EnumHalf = EnumShape<256, 8, 10, 480, 128, 2048, 1024>;    // two blocks per CU, two rounds
+using EnumQuarter = EnumShape<128, 8, 10, 240, 64, 1024, 2048>;  // four blocks per CU, two rounds
 
 template <bool ONE>
 MS_D bool enum_pair(const PairDesc &Pd, uint64_t cell, const double alo[4], const double ahi[4], const double blo[4],
@@ -1719,10 +1723,11 @@ __global__ void __launch_bounds__(S::block) k_enum(BatchView bv, const uint64_t 
                                                 const uint32_t *mix,
                                                 search_stats_t *stats, uint64_t *cand, int32_t *cand_pair,
                                                 int64_t cand_cap, hit_t *hits, uint64_t *hkeys, int64_t hits_cap,
-                                                unsigned long long *epart)
+                                                unsigned long long *epart, int resident)
 {
-    constexpr int ENUM_BLOCK = S::block, ENUM_ITEMS = S::items, ENUM_SLOTS = S::slots, ENUM_STAGE = S::stage,
-                  ENUM_CELLS = S::cells, ENUM_PSTART = S::pstart;
+    constexpr int ENUM_BLOCK = S::block, ENUM_ITEMS = S::items, ENUM_ITEMS_MAX = S::items_max,
+                  ENUM_SLOTS_MAX = S::slots_max, ENUM_STAGE = S::stage, ENUM_CELLS = S::cells,
+                  ENUM_PSTART = S::pstart;
     static_assert(ENUM_STAGE > 2 * GS_SLOTS, "the staged cells hold a group's statistics table");
     __shared__ int64_t s_pstart[ENUM_PSTART + 1];
     // the staged boxes during enumeration (component-major, so that lanes
@@ -1731,11 +1736,11 @@ __global__ void __launch_bounds__(S::block) k_enum(BatchView bv, const uint64_t 
     __shared__ union {
         double box[8][ENUM_STAGE];
         struct {
-            uint64_t tt[ENUM_SLOTS];
-            int32_t pair[ENUM_SLOTS];
+            uint64_t tt[ENUM_SLOTS_MAX];
+            int32_t pair[ENUM_SLOTS_MAX];
         } c;
     } s_u;
-    static_assert(sizeof(double) * ENUM_STAGE * 8 >= 12 * ENUM_SLOTS, "candidate list overlays the staged boxes");
+    static_assert(sizeof(double) * ENUM_STAGE * 8 >= 12 * ENUM_SLOTS_MAX, "candidate list overlays the staged boxes");
     double (*s_box)[ENUM_STAGE] = s_u.box;
     __shared__ int32_t s_t[ENUM_STAGE];
     __shared__ uint64_t s_ec[ENUM_STAGE];
@@ -1760,18 +1765,27 @@ __global__ void __launch_bounds__(S::block) k_enum(BatchView bv, const uint64_t 
     unsigned long long b_cand = 0, b_moller = 0, b_degen = 0, b_outside = 0, b_unstaged = 0;
     const int64_t ncells = kept[0];
     const int64_t P = kept[1];
-    const int64_t nchunks = ceil_div(P, ENUM_SLOTS);
+    // slots per thread: ENUM_ITEMS, or more (up to ENUM_ITEMS_MAX) when that
+    // gives every chunk a block among the `resident` ones of the first round
+    int items = ENUM_ITEMS;
+    if (resident > 0) {
+        const int64_t per = ceil_div(P, (int64_t)resident * ENUM_BLOCK);
+        if (per > ENUM_ITEMS && per <= ENUM_ITEMS_MAX) items = (int)per;
+    }
+    const int64_t chunk_slots = (int64_t)items * ENUM_BLOCK;
+    const int64_t nchunks = ceil_div(P, chunk_slots);
+    if ((int64_t)blockIdx.x >= nchunks) return;     // no chunk, nothing to count (the whole block)
     const int sh = bv.kl.cell_shift;
     const bool lds_pre = ncells <= ENUM_PSTART;
-    if ((int64_t)blockIdx.x < nchunks) {
+    {
     if (lds_pre) {
         for (int64_t i = threadIdx.x; i <= ncells; i += ENUM_BLOCK) s_pstart[i] = pstart_g[i];
         __syncthreads();
     }
     const int64_t *pstart = lds_pre ? s_pstart : pstart_g;
     for (int64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
-        const int64_t S0 = chunk * ENUM_SLOTS;
-        const int64_t S1 = S0 + ENUM_SLOTS < P ? S0 + ENUM_SLOTS : P;
+        const int64_t S0 = chunk * chunk_slots;
+        const int64_t S1 = S0 + chunk_slots < P ? S0 + chunk_slots : P;
         if (lds_pre) {
             // the one i with pstart[i] <= x < pstart[i + 1], for x = S0, S1 - 1
             for (int64_t i = threadIdx.x; i < ncells; i += ENUM_BLOCK) {
@@ -1879,7 +1893,7 @@ __global__ void __launch_bounds__(S::block) k_enum(BatchView bv, const uint64_t 
         int64_t pend = 0;
         uint32_t nAc = 1, iA = 0, qa = 0, ra = 0;
 #pragma unroll 1
-        for (int j = 0; j < ENUM_ITEMS; ++j) {
+        for (int j = 0; j < items; ++j) {
             const int64_t slot = S0 + (int64_t)j * ENUM_BLOCK + threadIdx.x;
             bool keep = false;
             if (slot < S1) {
@@ -2410,17 +2424,17 @@ PairDesc make_desc(const ms_mesh *A, const ms_mesh *B, const search_params_t *p,
     // blocks of the fine table: (n + 1) / 2 per axis; of the coarse table: (n + 3) / 4
     const uint64_t f1 = (n1 + 1) >> 1, f2 = (n2 + 1) >> 1, f3 = (n3 + 1) >> 1;
     const uint64_t c1 = (n1 + 3) >> 2, c2 = (n2 + 3) >> 2, c3 = (n3 + 3) >> 2;
-    d.fbs[0] = f1 * f2 * f3;
-    d.fbs[1] = f2 * f3;
-    d.fbs[2] = f3;
+    d.fbs[0] = (uint32_t)(f1 * f2 * f3);
+    d.fbs[1] = (uint32_t)(f2 * f3);
+    d.fbs[2] = (uint32_t)f3;
     d.fbs[3] = 1;
-    d.cbs[0] = c1 * c2 * c3;
-    d.cbs[1] = c2 * c3;
-    d.cbs[2] = c3;
+    d.cbs[0] = (uint32_t)(c1 * c2 * c3);
+    d.cbs[1] = (uint32_t)(c2 * c3);
+    d.cbs[2] = (uint32_t)c3;
     d.cbs[3] = 1;
     for (int k = 0; k < 4; ++k) {
-        d.fbh[k] = (uint32_t)d.fbs[k] * HASH_MUL;
-        d.cbh[k] = (uint32_t)d.cbs[k] * HASH_MUL;
+        d.fbh[k] = d.fbs[k] * HASH_MUL;
+        d.cbh[k] = d.cbs[k] * HASH_MUL;
         d.nm1[k] = (double)(p->n_cells[k] - 1);
     }
     return d;
@@ -2447,6 +2461,33 @@ BatchView make_view(const Geometry &G, const PairDesc &p0, char *ws, const Layou
     bv.kl.cell_shift = G.tb + 1;
     bv.kl.tmask = (1ull << G.tb) - 1;
     return bv;
+}
+
+// Blocks of k_enum<ONE, S> resident at once on the current device (0 when
+// the runtime cannot say: the chunks then keep their base size), asked once
+// per device.
+template <bool ONE, class S>
+int enum_resident()
+{
+    static std::mutex mu;
+    static int known[64];           // per device: resident blocks + 1 (0: not asked yet)
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (known[dev] == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_enum<ONE, S>),
+                                                         S::block, 0) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            per_cu = cus = 0;
+        }
+        known[dev] = per_cu * cus + 1;
+    }
+    return known[dev] - 1;
 }
 
 // Queue the whole pipeline (no host synchronisation).
@@ -2540,15 +2581,15 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
     if (G.enum_shape == MS_ENUM_QUARTER)
         MS_LAUNCH("k_enum", (k_enum<ONE, EnumQuarter>), dim3(EnumQuarter::grid), dim3(EnumQuarter::block), 0, st, bv,
                   sorted, spair, sbox, cells, pstart, misc + 1, mix, stats, cand_user, (int32_t *)nullptr,
-                  cand_user ? cand_cap : (int64_t)0, htmp, hkeys, hits_cap, epart);
+                  cand_user ? cand_cap : (int64_t)0, htmp, hkeys, hits_cap, epart, enum_resident<ONE, EnumQuarter>());
     else if (G.enum_shape == MS_ENUM_HALF)
         MS_LAUNCH("k_enum", (k_enum<ONE, EnumHalf>), dim3(EnumHalf::grid), dim3(EnumHalf::block), 0, st, bv, sorted,
                   spair, sbox, cells, pstart, misc + 1, mix, stats, cand_user, (int32_t *)nullptr,
-                  cand_user ? cand_cap : (int64_t)0, htmp, hkeys, hits_cap, epart);
+                  cand_user ? cand_cap : (int64_t)0, htmp, hkeys, hits_cap, epart, enum_resident<ONE, EnumHalf>());
     else
         MS_LAUNCH("k_enum", (k_enum<ONE, EnumWide>), dim3(EnumWide::grid), dim3(EnumWide::block), 0, st, bv, sorted,
                   spair, sbox, cells, pstart, misc + 1, mix, stats, cand_user, (int32_t *)nullptr,
-                  cand_user ? cand_cap : (int64_t)0, htmp, hkeys, hits_cap, epart);
+                  cand_user ? cand_cap : (int64_t)0, htmp, hkeys, hits_cap, epart, enum_resident<ONE, EnumWide>());
     MS_HIP(hipGetLastError());
     const bool tiny = hits_cap > 0 && hits_cap <= HITS_TINY;
     if (hits_cap > HITS_TINY) {
