@@ -212,13 +212,14 @@ MS_D uint32_t occ_bit(const uint32_t *bits, uint32_t h) { return (bits[h >> 5] >
 // ------------------------------------------- 32-bit cell ranges (the usual grids)
 
 // Cell of coordinate x on an axis of n < 2^31 cells (nm1 = n - 1):
-// clamp(floor((x - wlo) * inv), 0, n - 1) in FP64 with the clamp taken before
-// the conversion, so that one 32-bit conversion remains; equal to cell_of
-// (a negative or NaN floor clamps to 0, anything from n - 1 up to n - 1).
+// clamp(floor((x - wlo) * inv), 0, n - 1), equal to cell_of.  The clamp is
+// taken in FP64 before one 32-bit conversion, and the floor is left to that
+// conversion: it truncates, which is the floor on [0, n - 1], and whatever
+// lies below 0 (or is NaN) clamps to 0 either way.
 MS_D int32_t cell_of32(double x, double wlo, double inv, double nm1)
 {
     const double t = (x - wlo) * inv;
-    return (int32_t)fmin(fmax(floor(t), 0.0), nm1);
+    return (int32_t)fmin(fmax(t, 0.0), nm1);
 }
 
 // A triangle's cell range: lowest cell and extent (hi - lo) per axis.
@@ -262,10 +263,15 @@ MS_D Range32 coarse_range(const Range32 &r)
 // ascending b is the lexicographic order) with b inside the extent mask.
 MS_D bool range_small(const Range32 &r) { return (r.e[0] | r.e[1] | r.e[2] | r.e[3]) <= 1; }
 
-MS_D uint32_t extent_mask(const Range32 &r)
+// Cells of a range: 2^(sum of the extents) when each is 0 or 1 (the usual
+// case, a shift), else the product of the cell counts per axis.
+MS_D unsigned long long range_cells(const Range32 &r)
 {
-    return (uint32_t)(r.e[0] << 3 | r.e[1] << 2 | r.e[2] << 1 | r.e[3]);
+    if (range_small(r)) return 1ull << (r.e[0] + r.e[1] + r.e[2] + r.e[3]);
+    return (unsigned long long)(r.e[0] + 1) * (unsigned long long)(r.e[1] + 1) * (unsigned long long)(r.e[2] + 1) *
+           (unsigned long long)(r.e[3] + 1);
 }
+
 
 // ------------------------------------------------- blocked hashed tables
 //
@@ -379,13 +385,16 @@ MS_D void for_cells32(const Range32 &r, F &&f)
                 for (c[3] = r.lo[3]; c[3] <= r.lo[3] + r.e[3]; ++c[3]) f(c);
 }
 
-// The positions of a small range r inside its own extent.
+// The positions of a small range r inside its own extent: starting from
+// position 0, each axis of extent 1 adds the copy of the set moved one cell
+// along it (bit 3 - d of the position).
 MS_D uint32_t range_positions(const Range32 &r)
 {
-    const uint32_t nem = ~extent_mask(r);
-    uint32_t m = 0;
-#pragma unroll
-    for (int b = 0; b < 16; ++b) m |= (uint32_t)((b & nem) == 0) << b;
+    uint32_t m = 1u;
+    m |= (m << 8) & (0u - (uint32_t)r.e[0]);
+    m |= (m << 4) & (0u - (uint32_t)r.e[1]);
+    m |= (m << 2) & (0u - (uint32_t)r.e[2]);
+    m |= (m << 1) & (0u - (uint32_t)r.e[3]);
     return m;
 }
 
@@ -685,20 +694,13 @@ MS_D uint8_t epoch_value(const uint64_t *epoch) { return (uint8_t)(*epoch % 255u
 // map is monotone, so a triangle's cell range is the min / max of its
 // vertices' cells: each of the four vertices is converted once.
 
-// Positions b of a small range (bit 3 - d of b = offset along axis d) whose
-// offset along axis d is 1.
-MS_D uint32_t axis_one(int d) { return d == 0 ? 0xFF00u : d == 1 ? 0xF0F0u : d == 2 ? 0xCCCCu : 0xAAAAu; }
-
-// The positions of the range u (range_small) that lie in triangle range r.
+// The positions of the range u (range_small) that lie in range r, a range
+// inside u: r's own positions, moved by r's offset from u's lowest cell.
 MS_D uint32_t position_mask(const Range32 &u, const Range32 &r)
 {
-    uint32_t m = 0xFFFFu;
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        if (r.lo[d] != u.lo[d]) m &= axis_one(d);                // offset 0 not covered
-        if (r.lo[d] + r.e[d] == u.lo[d]) m &= ~axis_one(d);     // offset 1 not covered
-    }
-    return m;
+    const uint32_t sh = (uint32_t)(r.lo[0] - u.lo[0]) << 3 | (uint32_t)(r.lo[1] - u.lo[1]) << 2 |
+                        (uint32_t)(r.lo[2] - u.lo[2]) << 1 | (uint32_t)(r.lo[3] - u.lo[3]);
+    return range_positions(r) << sh;
 }
 
 // Smallest range holding both ranges.
@@ -909,8 +911,8 @@ __global__ void __launch_bounds__(BLOCK) k_mark(BatchView bv, uint8_t *flags, co
             rr.y = k2 ? pack_range32(r2, bv.packable != 0) : RNG_NONFINITE;
             *reinterpret_cast<ulonglong2 *>(rng + g) = rr;
             bad += (unsigned long long)(!ok1) + (unsigned long long)(!ok2);
-            if (ok1) all += (unsigned long long)((r1.e[0] + 1) * (r1.e[1] + 1)) * (unsigned long long)((r1.e[2] + 1) * (r1.e[3] + 1));
-            if (ok2) all += (unsigned long long)((r2.e[0] + 1) * (r2.e[1] + 1)) * (unsigned long long)((r2.e[2] + 1) * (r2.e[3] + 1));
+            if (ok1) all += range_cells(r1);
+            if (ok2) all += range_cells(r2);
             mark_quad(TabRef{flags, (uint32_t)L.side << lg, lg}, r1, k1, r2, k2, P.fbs, P.fbh, P.cell_base, v);
             mark_quad(TabRef{flags, ((uint32_t)2 << lg) + ((uint32_t)L.side << lc), lc}, coarse_range(r1), k1,
                       coarse_range(r2), k2, P.cbs, P.cbh, P.cell_base, v);
