@@ -199,11 +199,37 @@ def measured_traffic(kernel: str) -> float | None:
     return rows.get(kernel)
 
 
-def batch_roofline(ms, batch, pairs) -> dict:
+BATCH_COUNTERS_FILE = os.path.join(ROOT, "profiles", "search_batched_counters.txt")
+
+
+def batch_counters(leg: str, kernel: str) -> dict | None:
+    """Executed VALU instructions and HBM bytes per batched dispatch of
+    `kernel` in `leg` ("family" or "layers") from the committed counter
+    summary, or None when it is missing or was taken on other sources."""
+    if not os.path.exists(BATCH_COUNTERS_FILE):
+        return None
+    digest, rows = None, {}
+    for line in open(BATCH_COUNTERS_FILE):
+        f = line.split()
+        if len(f) >= 2 and f[0] == "source_digest":
+            digest = f[1]
+        elif len(f) == 8 and f[1].startswith("k_"):
+            try:
+                rows[(f[0], f[1])] = {"valu": float(f[3]) * float(f[4]), "traffic": float(f[7])}
+            except ValueError:
+                pass
+    if digest != source_digest():
+        return None
+    return rows.get((leg, kernel))
+
+
+def batch_roofline(ms, batch, pairs, leg: str) -> dict:
     """Dominant kernel of one batched search (launched without a graph, so
     that every dispatch carries its own start / stop events): its
     algorithmic bytes (the same table as the plain search, summed over the
-    batch's meshes and counts) over its dispatch duration."""
+    batch's meshes and counts) over its dispatch duration, its measured
+    traffic, and its VALU issue fraction from the committed counters; the
+    bound is the busier of HBM and VALU issue, as for the plain search."""
     import torch
     ms.profile_enable(True)
     batch.run(False)
@@ -218,10 +244,23 @@ def batch_roofline(ms, batch, pairs) -> dict:
     cands = [k for k in per if algorithmic_bytes(k, st, sizes) is not None]
     dom = max(cands, key=per.get)
     b = algorithmic_bytes(dom, st, sizes)
-    gbs = b / (per[dom] * 1e-3) / 1e9
-    return {"kernel": dom, "bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 5), "launch_ms": round(per[dom], 5), "bytes_per_launch": b,
-            "kernels_ms": {k: round(v, 5) for k, v in per.items()}}
+    t = per[dom] * 1e-3
+    gbs = b / t / 1e9
+    cnt = batch_counters(leg, dom)
+    traffic = cnt["traffic"] if cnt else None
+    hbm = {"achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 5),
+           "traffic": traffic, "traffic_frac": round(traffic / t / 1e9 / HBM_PEAK_GBS, 5) if traffic else None}
+    out = {"kernel": dom, "launch_ms": round(per[dom], 5), "bytes_per_launch": b,
+           "kernels_ms": {k: round(v, 5) for k, v in per.items()}}
+    valu_frac = cnt["valu"] * 64 / t / VALU_LANE_OPS_PER_S if cnt else None
+    if valu_frac is not None and valu_frac > max(hbm["frac"], hbm["traffic_frac"] or 0.0):
+        out.update({"bound": "alu", "achieved": round(valu_frac * VALU_LANE_OPS_PER_S / 1e12, 3),
+                    "peak": round(VALU_LANE_OPS_PER_S / 1e12, 2), "unit": "TOP/s", "frac": round(valu_frac, 4),
+                    "basis": "executed VALU lane operations (SQ_INSTS_VALU x 64, committed counters) per launch",
+                    "traffic": traffic, "hbm": hbm})
+    else:
+        out.update({"bound": "hbm", **hbm, "valu_issue_frac": round(valu_frac, 4) if valu_frac is not None else None})
+    return out
 
 
 SQ_FILE = os.path.join(ROOT, "profiles", "search_512x512_sq_counters.txt")
@@ -440,7 +479,7 @@ def main():
         out["family_batched_counts_equal_plain"] = bool(same)
         out["family_tris_total"] = int(sum(ga.n_tris + gb.n_tris for ga, gb in gp))
         out["family_batched_tris_per_s"] = out["family_tris_total"] / t_b
-        leg_roof["family_batched"] = batch_roofline(ms, bt, gp)
+        leg_roof["family_batched"] = batch_roofline(ms, bt, gp, "family")
         log(f"family: 256 plain searches in {t_f * 1e3:.2f} ms, batched graph {t_b * 1e3:.2f} ms, counts equal={same}")
         del bt, srch, gp
 
@@ -499,7 +538,7 @@ def main():
         log(f"layers: without world-bound pruning {t_u * 1e3:.2f} ms (hits {ust['n_hits']}, candidates equal "
             f"{ust['n_cand'] == lst['n_cand']})")
         del lsu
-        leg_roof["layers_batched"] = batch_roofline(ms, ls.batch, ls.meshes)
+        leg_roof["layers_batched"] = batch_roofline(ms, ls.batch, ls.meshes, "layers")
         log(f"layers: {len(ls.meshes)} half-layer pairs ({quads:.3e} quad pairs) batched in {t_l * 1e3:.2f} ms, "
             f"pair by pair {t_p * 1e3:.2f} ms, {lst['n_hits']} hits, counts equal={same}")
         del ls, srch, U, S

@@ -51,6 +51,21 @@ namespace {
 
 constexpr int BLOCK = 256;
 constexpr int MAX_GRID = 2048;
+// k_mark: runs of tiles per block, at most MARK_GRID_CAP blocks.  Many short
+// runs balance the CUs better than few long ones (the 256-pair family's
+// 29,700 tiles: 280 us as one tile per block, 443 us as 2048 runs); the
+// grid is the number of runs (rounded up to whole XCDs), so that no XCD is
+// left with only empty runs.
+constexpr int64_t MARK_GRID_CAP = 32768;
+
+inline unsigned mark_grid(int64_t n_tiles)
+{
+    if (n_tiles <= 0) return 1;
+    const int64_t per = (n_tiles + MARK_GRID_CAP - 1) / MARK_GRID_CAP;
+    int64_t g = (n_tiles + per - 1) / per;
+    if (g > 8) g = (g + 7) / 8 * 8;
+    return (unsigned)g;
+}
 static_assert(MAX_GRID <= MS_COUNT_PARTIALS, "count partials fit the mesh scratch");
 constexpr int TILE_TRIS = 2 * BLOCK;                  // triangles of a tile: one quad per thread
 // Counter lines of the enumeration (cand, moller, degen, outside, cells,
@@ -1053,9 +1068,21 @@ __global__ void __launch_bounds__(KEYS_BLOCK) k_keys(BatchView bv, const uint32_
     if (tile >= bv.n_tiles) {
         if (tile == (bv.n_tiles > 0 ? bv.n_tiles : 1)) {
             unsigned long long all = 0, bad = 0;
-            for (int i = threadIdx.x; i < kt.n_mark_partial; i += KEYS_BLOCK) {
-                all += kt.mark_partial[2 * i];
-                bad += kt.mark_partial[2 * i + 1];
+            for (int i0 = threadIdx.x; i0 < kt.n_mark_partial; i0 += 4 * KEYS_BLOCK) {
+                unsigned long long a[4] = {0, 0, 0, 0}, b[4] = {0, 0, 0, 0};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = i0 + u * KEYS_BLOCK;
+                    if (i < kt.n_mark_partial) {
+                        a[u] = kt.mark_partial[2 * i];
+                        b[u] = kt.mark_partial[2 * i + 1];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    all += a[u];
+                    bad += b[u];
+                }
             }
             all = block_sum<KEYS_BLOCK>(all, (unsigned long long *)s_tmp);
             bad = block_sum<KEYS_BLOCK>(bad, (unsigned long long *)s_tmp);
@@ -2362,7 +2389,7 @@ void layout(const Geometry &G, Layout &L)
     L.o_mix = take((size_t)n_ids * 4);
     L.o_gstat = take((size_t)L.n_gtiles * 16);
     L.o_ctrs = take(64);
-    L.o_part = take((size_t)MAX_GRID * 16);
+    L.o_part = take((size_t)MARK_GRID_CAP * 16);
     L.o_pbox = take((size_t)(G.n_pairs > 0 ? G.n_pairs : 1) * 2 * 8 * sizeof(double));
     L.o_epart = take((size_t)STAT_SHARDS * SHARD_WORDS * 8);
     L.o_rng = take((size_t)(G.n_tiles * TILE_TRIS + 1) * 8);
@@ -2465,31 +2492,40 @@ BatchView make_view(const Geometry &G, const PairDesc &p0, char *ws, const Layou
     return bv;
 }
 
-// Blocks of k_enum<ONE, S> resident at once on the current device (0 when
-// the runtime cannot say: the chunks then keep their base size), asked once
-// per device.
-template <bool ONE, class S>
-int enum_resident()
+// Blocks of kernel fn (nt threads each) resident at once on the current
+// device, 0 when the runtime cannot say; asked once per kernel and device
+// (a fixed table: no allocation on this path).
+inline int resident_blocks(const void *fn, int nt)
 {
+    struct Known {
+        const void *fn;
+        int dev, blocks;
+    };
     static std::mutex mu;
-    static int known[64];           // per device: resident blocks + 1 (0: not asked yet)
+    static Known known[64];
+    static int n_known = 0;
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    if (hipGetDevice(&dev) != hipSuccess) {
         (void)hipGetLastError();
         return 0;
     }
     std::lock_guard<std::mutex> lock(mu);
-    if (known[dev] == 0) {
-        int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_enum<ONE, S>),
-                                                         S::block, 0) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-            (void)hipGetLastError();
-            per_cu = cus = 0;
-        }
-        known[dev] = per_cu * cus + 1;
+    for (int i = 0; i < n_known; ++i)
+        if (known[i].fn == fn && known[i].dev == dev) return known[i].blocks;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nt, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        per_cu = cus = 0;
     }
-    return known[dev] - 1;
+    if (n_known < 64) known[n_known++] = Known{fn, dev, per_cu * cus};
+    return per_cu * cus;
+}
+
+template <bool ONE, class S>
+int enum_resident()
+{
+    return resident_blocks(reinterpret_cast<const void *>(&k_enum<ONE, S>), S::block);
 }
 
 // Queue the whole pipeline (no host synchronisation).
@@ -2534,7 +2570,7 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
     cs.n[0] = 2 * L.n_gtiles;
     cs.w[1] = (uint64_t *)ctrs;
     cs.n[1] = 8;
-    const unsigned g_tri = (unsigned)(G.n_tiles < MAX_GRID ? (G.n_tiles > 0 ? G.n_tiles : 1) : MAX_GRID);
+    const unsigned g_tri = mark_grid(G.n_tiles);
     if (G.prune)
         MS_LAUNCH("k_bounds", k_bounds<ONE>, dim3((unsigned)(2 * (G.n_pairs > 0 ? G.n_pairs : 1))),
                   dim3(BOUNDS_BLOCK), 0, st, bv, pbox);
