@@ -2613,7 +2613,7 @@ int enqueue(const Geometry &G, const Layout &L, const BatchView &bv, char *ws, h
     go.stats = stats;
     MS_LAUNCH("k_groups", k_groups, dim3((unsigned)(L.n_gtiles < 1024 ? L.n_gtiles : 1024)), dim3(BLOCK), 0, st, go);
     static_assert(GROUP_DIRECT_TILES <= 1024, "a direct k_groups launch has one block per tile");
-    MS_LAUNCH("k_scatter", k_scatter<ONE>, dim3(grid_for(L.ent_cap, 1024)), dim3(BLOCK), 0, st, bv, ent, epair, erank,
+    MS_LAUNCH("k_scatter", k_scatter<ONE>, dim3(grid_for(L.ent_cap, 8192)), dim3(BLOCK), 0, st, bv, ent, epair, erank,
               ehash, n_keys, L.ent_cap, (uint32_t *)grp, own, mix, sorted, spair, sbox, epoch, (uint4 *)flags,
               (int64_t)(flag_bytes(G) / 16));
     if (G.enum_shape == MS_ENUM_QUARTER)
