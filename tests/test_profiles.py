@@ -57,3 +57,32 @@ def test_profile_files_exist():
     for f in ("search_512x512_kernel_stats.txt", "search_512x512_sq_counters.txt", "search_512x512_traffic.txt",
               "fp64_valu_counters.txt"):
         assert os.path.exists(os.path.join(bench.ROOT, "profiles", f)), f
+
+
+def test_batched_counters_parse_and_read_back():
+    """The batched searches' summary: its traffic column follows from the
+    scaled FETCH_SIZE / WRITE_SIZE columns, every leg has its dominant
+    kernels, and bench.batch_counters returns the row while the digest
+    matches the sources."""
+    path = bench.BATCH_COUNTERS_FILE
+    digest, fscale, wscale, rows = None, None, None, []
+    for line in open(path):
+        f = line.split()
+        if f and f[0] == "source_digest":
+            digest = f[1]
+        elif line.startswith("#   its FETCH_SIZE"):
+            nums = [float(x.rstrip("),")) for x in line.replace("(", " ").split() if x.rstrip("),").replace(".", "", 1).isdigit()]
+            fscale, wscale = nums[1], nums[3]
+        elif len(f) == 8 and f[1].startswith("k_"):
+            rows.append(f)
+    assert digest is not None and len(digest) == 16 and fscale and wscale
+    legs = {(r[0], r[1]) for r in rows}
+    for leg in ("family", "layers"):
+        assert {(leg, k) for k in ("k_mark", "k_keys", "k_scatter", "k_enum")} <= legs
+    for r in rows:
+        want = (float(r[5]) * fscale + float(r[6]) * wscale) * 1024
+        assert abs(want - float(r[7])) <= 1e-4 * want + 2048, r[:2]
+    if digest == bench.source_digest():
+        got = bench.batch_counters("family", "k_keys")
+        row = next(r for r in rows if r[0] == "family" and r[1] == "k_keys")
+        assert got["traffic"] == float(row[7]) and got["valu"] == float(row[3]) * float(row[4])
