@@ -315,6 +315,16 @@ def search_roofline(kernel: str, launch_ms: float, alg_bytes: float) -> dict:
     return out
 
 
+def per_pair_params(p):
+    """The batch's tuned parameters for one pair searched on its own: the
+    same grid and tile, the hashed tables sized for the pair (table_log2 =
+    0), not for the whole batch (hundreds of batch-sized workspaces would
+    not fit in memory)."""
+    q = type(p).from_buffer_copy(p)
+    q.table_log2 = 0
+    return q
+
+
 def time_search(ms, A, B, searcher, steps, warmup, profile=False):
     """ms per step (mesh_update x 2 + one queued search); with profile, also
     the per-dispatch kernel durations of every step."""
@@ -447,7 +457,8 @@ def main():
         ftuned, fparams, fsweep = ms.autotune_batch_kappa(gp)
         fkappa = ftuned["kappa"]
         log(f"family: tuned ({ftuned['cache']}) {ftuned}" + "".join(f"; {k}: {v:.3f} ms" for k, v in fsweep.items()))
-        srch = [ms.Searcher(ga, gb, p, hits_cap=1 << 12, cand_cap=1 << 18) for (ga, gb), p in zip(gp, fparams)]
+        srch = [ms.Searcher(ga, gb, per_pair_params(p), hits_cap=1 << 12, cand_cap=1 << 18)
+                for (ga, gb), p in zip(gp, fparams)]
         for s in srch:
             s.run()
         torch.cuda.synchronize()
@@ -498,7 +509,8 @@ def main():
         torch.cuda.synchronize()
         t_l = (time.perf_counter() - t0) / reps
         lst = ls.batch.stats_dict()
-        srch = [ms.Searcher(a, b, p, hits_cap=1 << 12, cand_cap=1 << 18) for (a, b), p in zip(ls.meshes, ls.params)]
+        srch = [ms.Searcher(a, b, per_pair_params(p), hits_cap=1 << 12, cand_cap=1 << 18)
+                for (a, b), p in zip(ls.meshes, ls.params)]
         for sr in srch:
             sr.run()
         torch.cuda.synchronize()

@@ -143,7 +143,8 @@ typedef struct {
     int64_t n_cells[4];     /* cells per axis, >= 1 */
     int32_t flags;          /* MS_SEARCH_* */
     int32_t table_log2;     /* 0: automatic; else log2 of the hashed occupancy table per
-                               side, clamped to [8, 25] (smaller: more cells share a group;
+                               side, clamped to [8, 27]; the automatic size is within
+                               [12, 25] (smaller: more cells share a group;
                                results do not change, only the work) */
     int32_t enum_shape;     /* work tile of the pair enumeration (MS_ENUM_*; 0: MS_ENUM_HALF;
                                a batch takes its first pair's); results do not change,

@@ -2357,7 +2357,7 @@ int geometry(int64_t n_pairs, const ms_mesh *const *A, const ms_mesh *const *B, 
     int req = 0;     // a table size asked for by any pair (the largest)
     for (int64_t i = 0; i < n_pairs; ++i)
         if (prm[i].table_log2 > req) req = prm[i].table_log2;
-    if (req > 0) G.bm_log2 = req < 8 ? 8 : (req > 25 ? 25 : req);
+    if (req > 0) G.bm_log2 = req < 8 ? 8 : (req > 27 ? 27 : req);   // the automatic size stays within [12, 25]
     G.bc_log2 = G.bm_log2 - 3;
     G.enum_shape = 0;    // the shape of the first pair that asks for one, else MS_ENUM_HALF
     for (int64_t i = 0; i < n_pairs; ++i) {

@@ -22,6 +22,7 @@ import os
 KAPPAS = (0.25, 0.35, 0.5, 0.75, 1.0, 1.5, 2.0, 3.0, 4.0)
 BATCH_KAPPAS = (1.0, 1.5, 2.0, 3.0)
 SHAPES = (1, 2, 3)          # MS_ENUM_WIDE, MS_ENUM_HALF, MS_ENUM_QUARTER
+MAX_TABLE = 27              # the largest table_log2 the library takes (its automatic choice stops at 25)
 DEFAULT_SHAPE = 2
 CACHE_PATH = os.environ.get("MSEARCH_TUNE_CACHE") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                                    "tune_cache.json")
@@ -108,7 +109,7 @@ def tune(pairs, measure, device: str, batch: bool, use_cache: bool = True, path:
         if hit and all(f in hit for f in ("kappa", "table_log2", "enum_shape")):
             return dict(hit, cache="hit", key=key), {}
     auto = auto_table_log2(sum(a.n_tris + b.n_tris for a, b in pairs))
-    tables = sorted({max(12, auto - 1), auto, min(25, auto + 1)})
+    tables = sorted({max(12, auto - 1), auto, min(MAX_TABLE, auto + 1)})
     choice, times = sweep(measure, BATCH_KAPPAS if batch else KAPPAS, tables, default_table=auto)
     if use_cache:
         store(key, dict(choice), path)

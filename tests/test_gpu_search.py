@@ -116,7 +116,7 @@ def test_grid_cfg1_bench_configuration(ms, hits_cap):
 
 
 @pytest.mark.parametrize("shape", [1, 2, 3])
-@pytest.mark.parametrize("kappa,table_log2", [(2.5, 16), (0.75, 20)])
+@pytest.mark.parametrize("kappa,table_log2", [(2.5, 16), (0.75, 20), (1.5, 26)])
 def test_tuned_tuples_match_grid_oracle(ms, shape, kappa, table_log2):
     """Tuples the autotuner may pick (cell edge, hashed table size,
     enumeration work tile) away from the defaults: each gives the oracle's

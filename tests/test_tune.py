@@ -72,3 +72,17 @@ def test_unreadable_cache_is_empty(tmp_path):
     p = tmp_path / "bad.json"
     p.write_text("{not json")
     assert tune.load_cache(str(p)) == {}
+
+
+def test_tables_reach_one_above_the_largest_automatic_size():
+    """Above the automatic ceiling (2^25) the sweep still tries one size more
+    (the library takes up to 2^27), and keeps it when it is the fastest."""
+    seen = set()
+
+    def measure(k, t, s):
+        seen.add(t)
+        return 1.0 - 0.5 * (t == 26) + 0.1 * abs(k - 1.5)
+
+    choice, _ = tune.tune(_pairs((1 << 24, 1 << 24)), measure, "dev", batch=True, use_cache=False)
+    assert seen == {24, 25, 26}
+    assert choice["table_log2"] == 26 and choice["kappa"] == 1.5
