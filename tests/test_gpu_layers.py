@@ -111,3 +111,28 @@ def test_pruned_layer_search(ms):
         slots += ref.n_slots
     assert (stp["n_cells"], stp["n_slots"]) == (cells, slots)
     assert stp["n_slots"] <= stf["n_slots"]
+
+
+def test_full_size_layer_search_equals_plain_searches(ms):
+    """The layer search at the paper's shape (112 half-layer pairs, 25M
+    triangles: more tiles than k_mark's grid, so each block marks a run of
+    two tiles), at its tuned tuple with world-bound pruning: every pair's
+    hits equal its plain search's (same grid, tile and pruning, its own
+    table size), and the batch's counts equal the plain searches' sums."""
+    lp = synth.layered_pair(1024, 2048, 34, 14, 0)
+    U, S = ms.Mesh.from_synth(lp.U), ms.Mesh.from_synth(lp.S)
+    ls = ms.LayerSearch(U, S, lp.D_u, lp.lam_u, lp.D_s, lp.lam_s, lp.n_layers, hits_cap=1 << 16)
+    assert len(ls.meshes) == 112
+    assert sum(a.n_tris + b.n_tris for a, b in ls.meshes) > 512 * 32768
+    ls.run(True)
+    per_pair, st = ls.results()
+    sums = dict.fromkeys(("n_cand", "n_hits", "n_cells", "n_slots"), 0)
+    for (a, b), p, got in zip(ls.meshes, ls.params, per_pair):
+        q = type(p).from_buffer_copy(p)
+        q.table_log2 = 0
+        hits, pst, _ = ms.search(a, b, q, hits_cap=1 << 12, cand_cap=1 << 18)
+        assert_same_hits(got, hits)
+        for k in sums:
+            sums[k] += pst[k]
+    assert all(st[k] == v for k, v in sums.items()), (st, sums)
+    assert st["n_hits"] > 0
